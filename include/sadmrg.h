@@ -1,0 +1,186 @@
+/*
+ * libsadmrg -- spin-adapted two-site DMRG for ab initio quantum chemistry on
+ * AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * Method: Wouters, Poelmans, Ayers, Van Neck, "CheMPS2: a free open-source
+ * spin-adapted implementation of the density matrix renormalization group for
+ * ab initio quantum chemistry" (arXiv:1312.2415).
+ *   - MPS ansatz, canonical forms, effective Hamiltonian, Davidson, SVD and
+ *     truncation, sweeping: section "DMRG for ab initio quantum chemistry".
+ *   - complementary operators (one-body folding, bare renormalised operators,
+ *     integral-weighted complementary operators, Hermitian-conjugate storage):
+ *     section "Complementary operators".
+ *   - SU(2) x U(1) x P symmetry, reduced tensors (eq. tensordecomp), singlet
+ *     embedding, doublet operators (eqs. creaannih1/2), two-site object and
+ *     its decomposition (eqs. TTtoS, StoTT, kappa): section "Symmetry-adapted
+ *     DMRG".
+ *   - user-facing objects (Hamiltonian, Problem, ConvergenceScheme, Solve):
+ *     section "CheMPS2 library".
+ *
+ * Conventions shared by every call:
+ *   - All pointers are HOST pointers unless a parameter says otherwise.
+ *     Inputs are copied before the call returns; the caller keeps ownership.
+ *   - Spins are passed doubled (twoS = 2S).  Point-group irreps are integers
+ *     0..order-1 whose direct product is XOR (D2h in Cotton order
+ *     Ag,B1g,B2g,B3g,Au,B1u,B2u,B3u; subgroups use the low bits).
+ *   - Two-electron integrals are chemist (ij|kl), dense L^4, row-major,
+ *     eightfold symmetric; the paper's physics-notation V_ijkl equals (ik|jl).
+ *   - Every call returns a status: 0 on success, 1 = converged-with-warning
+ *     (Davidson hit its iteration cap), negative on error:
+ *       SADMRG_EINVAL   bad argument / shape / call order
+ *       SADMRG_ESYMM    N, S, irrep inconsistent, or empty symmetry sector
+ *       SADMRG_EINTEG   integrals not symmetric within tolerance, or NaN/Inf
+ *       SADMRG_ENOMEM   device allocation failed
+ *       SADMRG_EDEVICE  HIP runtime error
+ *     sadmrg_last_error() returns a description of the last failure.
+ *   - All device work is enqueued on the context's stream (default stream
+ *     unless sadmrg_set_stream is called); calls that return host data
+ *     synchronise that stream.  One context is used by one host thread.
+ */
+#ifndef SADMRG_H
+#define SADMRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SADMRG_OK 0
+#define SADMRG_WARN_NOT_CONVERGED 1
+#define SADMRG_EINVAL (-1)
+#define SADMRG_ESYMM (-2)
+#define SADMRG_EINTEG (-3)
+#define SADMRG_ENOMEM (-4)
+#define SADMRG_EDEVICE (-5)
+
+typedef struct sadmrg_ctx sadmrg_ctx;
+
+/* Library version string (static storage). */
+const char* sadmrg_version(void);
+
+/* Create a context for L orbitals on HIP device `device`.
+ * group_order: 1, 2, 4 or 8 (C1 .. D2h); orb_irrep[L]: irrep of each orbital
+ * in lattice order.  The paper's Hamiltonian object (section "The Hamiltonian").
+ * Errors: EINVAL (L < 2, bad order or irreps), EDEVICE. */
+int sadmrg_create(sadmrg_ctx** out, int L, int group_order, const int* orb_irrep, int device);
+
+/* Destroy a context and release all its device memory.  NULL is allowed. */
+void sadmrg_destroy(sadmrg_ctx* ctx);
+
+/* Use `hip_stream` (a hipStream_t, may be NULL for the default stream) for all
+ * subsequent device work of this context. */
+int sadmrg_set_stream(sadmrg_ctx* ctx, void* hip_stream);
+
+/* Set E_const, one-body h[L*L] (row-major) and two-body eri[L^4] (chemist,
+ * row-major).  The eightfold symmetry and point-group selection rules are
+ * checked to within sym_tol (EINTEG on failure). */
+int sadmrg_set_integrals(sadmrg_ctx* ctx, double e_const, const double* h, const double* eri, double sym_tol);
+
+/* Target symmetry sector: N electrons, total spin twoS/2, irrep (the paper's
+ * Problem object).  N >= 2 is required by the one-body folding of the
+ * complementary-operator construction (section "Complementary operators",
+ * trick (a)).  Errors: ESYMM. */
+int sadmrg_set_target(sadmrg_ctx* ctx, int N, int twoS, int irrep);
+
+/* Davidson parameters: residual-norm tolerance, maximum subspace size (2..64)
+ * and maximum iterations per micro-iteration. */
+int sadmrg_set_davidson(sadmrg_ctx* ctx, double tol, int max_sub, int max_iter);
+
+/* Seed of the counter-based generator used for the random initial MPS. */
+int sadmrg_set_seed(sadmrg_ctx* ctx, uint64_t seed);
+
+/* Create the initial MPS (section "DMRG" of the library description): the
+ * bond dimension D is split equally over the symmetry sectors of every bond,
+ * capped by the FCI dimension, and filled with random numbers; the tensors of
+ * sites 1..L-1 are right-normalised and all right renormalised operators are
+ * built.  Errors: ESYMM (empty sector), ENOMEM, EDEVICE. */
+int sadmrg_init_mps(sadmrg_ctx* ctx, int D);
+
+/* Run one macro-iteration (a left-to-right pass over i = 0..L-2 followed by a
+ * right-to-left pass over i = L-2..0; section "Sweeping") keeping at most D
+ * reduced states per bond.  *e_min receives the lowest energy of this
+ * macro-iteration.  Returns 1 if some Davidson solve hit max_iter. */
+int sadmrg_sweep(sadmrg_ctx* ctx, int D, double* e_min);
+
+/* Run a convergence scheme (section "Convergence scheme"): n instructions of
+ * (D[i], e_conv[i], max_sweeps[i], noise[i]).  *e_min receives the lowest
+ * variational energy over all micro-iterations (the paper's Solve).
+ * Noise must be 0 in this version (EINVAL otherwise). */
+int sadmrg_solve(sadmrg_ctx* ctx, int n, const int* D, const double* e_conv, const int* max_sweeps,
+                 const double* noise, double* e_min);
+
+/* Energies: lowest over all micro-iterations so far, last micro-iteration's,
+ * and the largest discarded weight of the last macro-iteration. */
+int sadmrg_get_energy(sadmrg_ctx* ctx, double* e_min, double* e_last, double* wdisc_max);
+
+/* Per-micro-iteration energies recorded so far (size query when out == NULL:
+ * *n receives the count). */
+int sadmrg_get_trace(sadmrg_ctx* ctx, double* out, int* n);
+
+/* ------------------------------------------------------------------------
+ * MPS exchange.  Blob layout (little-endian, all fields int64 unless noted):
+ *   magic 0x3154535053414453 ("SADSPST1"), L, N, twoS, irrep, centre i
+ *   for bonds k = 0..L: nsec, then nsec x (N, twoS_sector, irrep, dim)
+ *   left tensors  U[0..i-1]  as double: for each sector m of bond k+1 in
+ *       order, a (dimX(m) x dim(m)) row-major matrix, rows in the left
+ *       enlarged order (see below)
+ *   right tensors V[i+2..L-1] as double: for each sector m of bond k, a
+ *       (dim(m) x dimY(m)) row-major matrix, columns in the right enlarged order
+ *   two-site object on sites (i, i+1) as double: for each sector m of bond
+ *       i+1 present in both enlarged bases, a (dimX(m) x dimY(m)) matrix.
+ * Sector labels (N, 2j, irrep) count the electrons LEFT of the bond; sectors
+ * are sorted lexicographically.  Left enlarged order at bond k+1: pieces
+ * (a, n) with a over bond-k sectors in order, then local state n in
+ * (empty, single, double), keeping those with N_m = N_a + n_e, irrep
+ * I_m = I_a x I(n), j_m in j_a (x) s_n.  Right enlarged order at bond k:
+ * pieces (n, b), n outer, b over bond-(k+1) sectors, with N_b = N_m + n_e.
+ * The two-site basis is [ |(a n1) j_M> (x) |(n2 b) j_M> ]^0 with the right
+ * boundary's singlet-embedding spin S inside the right states.
+ * ------------------------------------------------------------------------ */
+int sadmrg_mps_import(sadmrg_ctx* ctx, const void* blob, size_t bytes);
+int sadmrg_mps_export(sadmrg_ctx* ctx, void* blob, size_t* bytes); /* blob == NULL: size query */
+
+/* ------------------------------------------------------------------------
+ * Single-step hooks (test and benchmark access to one micro-iteration).
+ * sadmrg_prepare_step builds the enlarged blocks for sites (i, i+1) where i
+ * is the current centre; sadmrg_psi_layout reports nsec sectors, each as six
+ * int64 (N, 2j, irrep, dimX, dimY, offset into the flat vector); and
+ * sadmrg_sigma applies the effective Hamiltonian (section "The effective
+ * Hamiltonian equation") to x[n] giving y[n].  x and y are device pointers
+ * when on_device != 0, else host pointers.
+ * ------------------------------------------------------------------------ */
+int sadmrg_prepare_step(sadmrg_ctx* ctx);
+int sadmrg_psi_layout(sadmrg_ctx* ctx, int* nsec, int64_t* desc, int64_t* n);
+int sadmrg_sigma(sadmrg_ctx* ctx, const double* x, double* y, int on_device);
+/* Diagonal of the effective Hamiltonian at the prepared step (same layout). */
+int sadmrg_heff_diagonal(sadmrg_ctx* ctx, double* d, int on_device);
+
+/* Work counters of the prepared step's sigma: algorithmic flops, operator +
+ * vector bytes, number of block-product tasks.  See the design notes for the
+ * exact definitions. */
+int sadmrg_sigma_counters(sadmrg_ctx* ctx, double* flops, double* bytes, int64_t* tasks);
+
+/* Accumulated timings and counts since the last reset: seconds in sigma
+ * kernels, number of sigma calls, seconds of whole micro-iterations, sigma
+ * flops, and seconds in renormalisation/enlargement kernels. */
+int sadmrg_stats(sadmrg_ctx* ctx, double* t_sigma, int64_t* n_sigma, double* t_micro, double* flops_sigma,
+                 double* t_blocking);
+int sadmrg_stats_reset(sadmrg_ctx* ctx);
+
+/* Description of the last failure (static until the next call on ctx). */
+const char* sadmrg_last_error(const sadmrg_ctx* ctx);
+
+/* Debug/test access to the library's SU(2) recoupling coefficients (spins
+ * doubled).  which = 0: coupled product of operators on two subsystems,
+ * args[9] = (j1, j2, J, k1, k2, K, j1', j2', J') through a Wigner 9j symbol;
+ * which = 1: same-space product, args[6] = (j, j'', j', k1, k2, K) through a
+ * 6j symbol; which = 2: 6j symbol {a b c; d e f}, args[6].  Returns the value
+ * in *out. */
+int sadmrg_debug_coupling(int which, const int* args, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SADMRG_H */

@@ -1191,3 +1191,43 @@ def move_center_left(P: Problem, C: dict, Uprev: dict, c: int, dims_c: dict, dim
             co = Er_new.off[(a, n, b)]
             out[a][:, co:co + blk.shape[1]] += r * blk
     return out
+
+
+# ---------------------------------------------------------------------------
+# MPS blob (the exchange format declared in the C ABI header), written from the
+# oracle's state so that the GPU path can be run on the same tensors.
+# ---------------------------------------------------------------------------
+MPS_MAGIC = 0x3154535053414453
+
+
+def export_blob(dm: DMRG) -> bytes:
+    import struct
+    P = dm.P
+    i, psi = dm.center
+    out = bytearray()
+
+    def put(*vals):
+        for v in vals:
+            out.extend(struct.pack("<q", int(v)))
+
+    def putm(a):
+        out.extend(np.ascontiguousarray(a, dtype="<f8").tobytes())
+
+    put(MPS_MAGIC, P.L, P.N, P.twoS, P.irrep, i)
+    for k in range(P.L + 1):
+        d = dm.dims[k]
+        put(len(d))
+        for q in sorted(d):
+            put(q[0], q[1], q[2], d[q])
+    for k in range(i):
+        for m in sorted(dm.dims[k + 1]):
+            putm(dm.U[k][m])
+    for k in range(i + 2, P.L):
+        for m in sorted(dm.dims[k]):
+            putm(dm.V[k][m])
+    El = LeftEnl(P, i + 1, dm.dims[i])
+    Er = RightEnl(P, i + 1, dm.dims[i + 2])
+    for m in sorted(El.dim):
+        if m in Er.dim:
+            putm(psi.get(m, np.zeros((El.dim[m], Er.dim[m]))))
+    return bytes(out)

@@ -1,0 +1,233 @@
+"""ctypes binding of libsadmrg (argument marshalling only).
+
+Every numerical step runs inside the HIP library; this module converts numpy
+arrays / torch tensors to pointers and status codes to exceptions.  The
+library is required: importing works without it, but constructing a solver
+raises if ``libsadmrg.so`` has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+_LIB_PATH = None
+
+_ERR = {-1: "EINVAL", -2: "ESYMM", -3: "EINTEG", -4: "ENOMEM", -5: "EDEVICE"}
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libsadmrg.so")
+
+
+def load_library(path: str | None = None):
+    """Load (once) and return the ctypes handle of libsadmrg."""
+    global _LIB, _LIB_PATH
+    path = os.path.abspath(path or library_path())
+    if _LIB is not None and _LIB_PATH == path:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"libsadmrg not built: {path} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    c_int, c_dbl, c_vp, c_sz = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "sadmrg_version": (ctypes.c_char_p, []),
+        "sadmrg_create": (c_int, [P(c_vp), c_int, c_int, P(c_int), c_int]),
+        "sadmrg_destroy": (None, [c_vp]),
+        "sadmrg_set_stream": (c_int, [c_vp, c_vp]),
+        "sadmrg_set_integrals": (c_int, [c_vp, c_dbl, P(c_dbl), P(c_dbl), c_dbl]),
+        "sadmrg_set_target": (c_int, [c_vp, c_int, c_int, c_int]),
+        "sadmrg_set_davidson": (c_int, [c_vp, c_dbl, c_int, c_int]),
+        "sadmrg_set_seed": (c_int, [c_vp, ctypes.c_uint64]),
+        "sadmrg_init_mps": (c_int, [c_vp, c_int]),
+        "sadmrg_sweep": (c_int, [c_vp, c_int, P(c_dbl)]),
+        "sadmrg_solve": (c_int, [c_vp, c_int, P(c_int), P(c_dbl), P(c_int), P(c_dbl), P(c_dbl)]),
+        "sadmrg_get_energy": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
+        "sadmrg_get_trace": (c_int, [c_vp, P(c_dbl), P(c_int)]),
+        "sadmrg_mps_import": (c_int, [c_vp, c_vp, c_sz]),
+        "sadmrg_mps_export": (c_int, [c_vp, c_vp, P(c_sz)]),
+        "sadmrg_prepare_step": (c_int, [c_vp]),
+        "sadmrg_psi_layout": (c_int, [c_vp, P(c_int), P(ctypes.c_int64), P(ctypes.c_int64)]),
+        "sadmrg_sigma": (c_int, [c_vp, c_vp, c_vp, c_int]),
+        "sadmrg_heff_diagonal": (c_int, [c_vp, c_vp, c_int]),
+        "sadmrg_sigma_counters": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(ctypes.c_int64)]),
+        "sadmrg_stats": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl), P(c_dbl), P(c_dbl)]),
+        "sadmrg_stats_reset": (c_int, [c_vp]),
+        "sadmrg_last_error": (ctypes.c_char_p, [c_vp]),
+        "sadmrg_debug_coupling": (c_int, [c_int, P(c_int), P(c_dbl)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB, _LIB_PATH = lib, path
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class SadmrgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERR.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SaDMRG:
+    """One solver context (one target sector) on one HIP device."""
+
+    def __init__(self, L: int, group_order: int, orb_irrep, device: int = 0, lib_path: str | None = None):
+        self.lib = load_library(lib_path)
+        irr = np.ascontiguousarray(orb_irrep, dtype=np.int32)
+        self.L = int(L)
+        h = ctypes.c_void_p()
+        rc = self.lib.sadmrg_create(ctypes.byref(h), int(L), int(group_order),
+                                    irr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(device))
+        if rc != 0:
+            raise SadmrgError(rc, "sadmrg_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sadmrg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc < 0:
+            raise SadmrgError(rc, self.lib.sadmrg_last_error(self.h).decode())
+        return rc
+
+    # ---- problem definition
+    def set_stream(self, stream_handle: int):
+        self._chk(self.lib.sadmrg_set_stream(self.h, ctypes.c_void_p(int(stream_handle))))
+
+    def set_integrals(self, h, eri, e_const=0.0, sym_tol=1e-10):
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        eri = np.ascontiguousarray(eri, dtype=np.float64)
+        if h.shape != (self.L, self.L) or eri.shape != (self.L,) * 4:
+            raise ValueError("integral shapes do not match L")
+        self._chk(self.lib.sadmrg_set_integrals(self.h, float(e_const), _dptr(h), _dptr(eri), float(sym_tol)))
+
+    def set_target(self, N, twoS, irrep=0):
+        self._chk(self.lib.sadmrg_set_target(self.h, int(N), int(twoS), int(irrep)))
+
+    def set_davidson(self, tol=1e-9, max_sub=32, max_iter=200):
+        self._chk(self.lib.sadmrg_set_davidson(self.h, float(tol), int(max_sub), int(max_iter)))
+
+    def set_seed(self, seed):
+        self._chk(self.lib.sadmrg_set_seed(self.h, ctypes.c_uint64(int(seed))))
+
+    # ---- sweeping
+    def init_mps(self, D):
+        self._chk(self.lib.sadmrg_init_mps(self.h, int(D)))
+
+    def sweep(self, D):
+        e = ctypes.c_double()
+        rc = self._chk(self.lib.sadmrg_sweep(self.h, int(D), ctypes.byref(e)))
+        return e.value, rc
+
+    def solve(self, schedule):
+        """schedule: list of (D, e_conv, max_sweeps[, noise])."""
+        n = len(schedule)
+        D = (ctypes.c_int * n)(*[int(s[0]) for s in schedule])
+        ec = (ctypes.c_double * n)(*[float(s[1]) for s in schedule])
+        ms = (ctypes.c_int * n)(*[int(s[2]) for s in schedule])
+        nz = (ctypes.c_double * n)(*[float(s[3]) if len(s) > 3 else 0.0 for s in schedule])
+        e = ctypes.c_double()
+        self._chk(self.lib.sadmrg_solve(self.h, n, D, ec, ms, nz, ctypes.byref(e)))
+        return e.value
+
+    def energy(self):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._chk(self.lib.sadmrg_get_energy(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def trace(self):
+        n = ctypes.c_int(0)
+        self._chk(self.lib.sadmrg_get_trace(self.h, None, ctypes.byref(n)))
+        out = np.zeros(n.value)
+        self._chk(self.lib.sadmrg_get_trace(self.h, _dptr(out), ctypes.byref(n)))
+        return out
+
+    # ---- MPS exchange
+    def mps_import(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._chk(self.lib.sadmrg_mps_import(self.h, buf, len(blob)))
+
+    def mps_export(self) -> bytes:
+        n = ctypes.c_size_t(0)
+        self._chk(self.lib.sadmrg_mps_export(self.h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._chk(self.lib.sadmrg_mps_export(self.h, buf, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    # ---- single-step hooks
+    def prepare_step(self):
+        self._chk(self.lib.sadmrg_prepare_step(self.h))
+
+    def psi_layout(self):
+        ns = ctypes.c_int(0)
+        n = ctypes.c_int64(0)
+        self._chk(self.lib.sadmrg_psi_layout(self.h, ctypes.byref(ns), None, ctypes.byref(n)))
+        desc = np.zeros((ns.value, 6), dtype=np.int64)
+        self._chk(self.lib.sadmrg_psi_layout(self.h, ctypes.byref(ns),
+                                             desc.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(n)))
+        return desc, n.value
+
+    def sigma(self, x):
+        """Apply H_eff.  numpy in -> numpy out (host), torch CUDA tensor in -> tensor out."""
+        if hasattr(x, "data_ptr") and getattr(x, "is_cuda", False):
+            import torch
+            xx = x.contiguous().to(torch.float64)
+            y = torch.empty_like(xx)
+            self._chk(self.lib.sadmrg_sigma(self.h, ctypes.c_void_p(xx.data_ptr()), ctypes.c_void_p(y.data_ptr()), 1))
+            return y
+        xx = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros_like(xx)
+        self._chk(self.lib.sadmrg_sigma(self.h, xx.ctypes.data_as(ctypes.c_void_p),
+                                        y.ctypes.data_as(ctypes.c_void_p), 0))
+        return y
+
+    def heff_diagonal(self):
+        _, n = self.psi_layout()
+        d = np.zeros(n)
+        self._chk(self.lib.sadmrg_heff_diagonal(self.h, d.ctypes.data_as(ctypes.c_void_p), 0))
+        return d
+
+    def sigma_counters(self):
+        f, b = ctypes.c_double(), ctypes.c_double()
+        t = ctypes.c_int64()
+        self._chk(self.lib.sadmrg_sigma_counters(self.h, ctypes.byref(f), ctypes.byref(b), ctypes.byref(t)))
+        return f.value, b.value, t.value
+
+    def stats(self):
+        ts, tm, fs, tb = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        ns = ctypes.c_int64()
+        self._chk(self.lib.sadmrg_stats(self.h, ctypes.byref(ts), ctypes.byref(ns), ctypes.byref(tm),
+                                        ctypes.byref(fs), ctypes.byref(tb)))
+        return {"t_sigma": ts.value, "n_sigma": ns.value, "t_micro": tm.value, "flops_sigma": fs.value,
+                "t_blocking": tb.value}
+
+    def stats_reset(self):
+        self._chk(self.lib.sadmrg_stats_reset(self.h))
+
+
+def debug_coupling(which: int, args, lib_path: str | None = None) -> float:
+    lib = load_library(lib_path)
+    a = (ctypes.c_int * len(args))(*[int(v) for v in args])
+    out = ctypes.c_double()
+    rc = lib.sadmrg_debug_coupling(int(which), a, ctypes.byref(out))
+    if rc != 0:
+        raise SadmrgError(rc, "bad coupling request")
+    return out.value

@@ -1,0 +1,2579 @@
+// libsadmrg host engine.
+//
+// Paper: arXiv:1312.2415 (CheMPS2).  Section references below are to that text.
+//
+// Data layout (all FP64, all in HBM):
+//  * A block (left block at bond k = orbitals 0..k-1, or right block at bond k
+//    = orbitals k..L-1 plus the singlet-embedding spin) stores its operators in
+//    one buffer.  Every operator belongs to a quantum-number class (rank 2k,
+//    particle change dN, irrep dG); all operators of a class share one
+//    canonical element layout: every symmetry-allowed (bra, ket) sector pair,
+//    dense row-major, in a fixed order.  Operator i of the class sits at its
+//    own base offset with the same element offsets, so integral-weighted sums
+//    over operators (complementary operators) are plain linear combinations.
+//  * An enlarged block (block (x) one site, before truncation) uses the same
+//    scheme on the enlarged sectors; its dense (m', m) blocks hold every
+//    (sector, local state) piece pair.
+//  * The two-site object psi: per sector m of the middle bond a dense
+//    dimX(m) x dimY(m) row-major matrix; sectors concatenated in order.
+#include "engine.h"
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <set>
+
+namespace sadmrg {
+
+void fail(int code, const std::string& msg) { throw Failure{code, msg}; }
+[[noreturn]] void dev_fail(const char* what) { throw Failure{-5, what}; }
+
+int Basis::find(const Sec& s) const {
+  auto it = std::lower_bound(sec.begin(), sec.end(), s);
+  if (it != sec.end() && *it == s) return int(it - sec.begin());
+  return -1;
+}
+int64_t Basis::total() const {
+  int64_t t = 0;
+  for (int d : dim) t += d;
+  return t;
+}
+
+static const int LOC_N[3] = {0, 1, 2};
+static const int LOC_TJ[3] = {0, 1, 0};
+static inline int loc_irrep(int n, int g) { return n == 1 ? g : 0; }
+
+// ---------------------------------------------------------------------------
+// Site operators: reduced elements <n'||o||n> on the local multiplets
+// (empty, single, double), section "Reduced MPS tensors" local basis and the
+// doublet operators of eqs. creaannih1/2.
+// ---------------------------------------------------------------------------
+struct SiteOp {
+  int tk = 0, dN = 0;
+  bool odd = false;
+  double el[3][3] = {{0}};
+};
+
+static SiteOp site_product(const SiteOp& U, const SiteOp& V, int tK) {
+  SiteOp r;
+  r.tk = tK;
+  r.dN = U.dN + V.dN;
+  r.odd = U.odd ^ V.odd;
+  for (int n1 = 0; n1 < 3; ++n1)
+    for (int n2 = 0; n2 < 3; ++n2)
+      for (int n3 = 0; n3 < 3; ++n3) {
+        if (V.el[n2][n1] == 0.0 || U.el[n3][n2] == 0.0) continue;
+        r.el[n3][n1] += coupling_same(LOC_TJ[n1], LOC_TJ[n2], LOC_TJ[n3], U.tk, V.tk, tK) * U.el[n3][n2] * V.el[n2][n1];
+      }
+  return r;
+}
+
+struct SiteOps {
+  SiteOp I, CD, C, A0, B0, B1, AA0, E, CDE, EC;
+  SiteOps() {
+    const double s2 = std::sqrt(2.0);
+    I.el[0][0] = I.el[1][1] = I.el[2][2] = 1.0;
+    CD.tk = 1, CD.dN = 1, CD.odd = true, CD.el[1][0] = 1.0, CD.el[2][1] = -s2;  // b+
+    C.tk = 1, C.dN = -1, C.odd = true, C.el[0][1] = -s2, C.el[1][2] = -1.0;     // b
+    A0 = site_product(CD, CD, 0);                                              // [b+ b+]^0
+    B0 = site_product(CD, C, 0);                                               // [b+ b]^0
+    B1 = site_product(CD, C, 2);                                               // [b+ b]^1
+    AA0 = site_product(C, C, 0);                                               // [b b]^0
+    E = B0;                                                                    // E_kk = -sqrt2 [b+ b]^0
+    for (auto& row : E.el)
+      for (double& v : row) v *= -s2;
+    CDE = site_product(CD, E, 1);  // b+ E_kk
+    EC = site_product(E, C, 1);    // E_kk b
+  }
+  const SiteOp& B(int tj) const { return tj == 0 ? B0 : B1; }
+};
+static const SiteOps& SO() {
+  static const SiteOps s;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Problem (the paper's Hamiltonian + Problem objects)
+// ---------------------------------------------------------------------------
+struct Problem {
+  int L = 0, order = 1;
+  std::vector<int> orb;
+  double e_const = 0.0;
+  std::vector<double> h, eri, W;
+  bool have_ints = false;
+  int N = -1, twoS = 0, irrep = 0;
+  double w(int p, int q, int r, int s) const { return W[(((size_t)p * L + q) * L + r) * L + s]; }
+  // q^j_ab(r,s): 2 W_abrs - W_rbas (j = 0), W_rbas (j = 1)
+  double qc(int tj, int a, int b, int r, int s) const { return tj == 0 ? 2.0 * w(a, b, r, s) - w(r, b, a, s) : w(r, b, a, s); }
+  bool bare_left(int k) const { return k <= L - k; }
+  bool bare_right(int k) const { return L - k < k; }
+  // section "Complementary operators", trick (a): one-body integrals folded
+  // into the two-body ones, W_pqrs = (pq|rs) + [h_pq d_rs + h_rs d_pq]/(N-1)
+  void fold() {
+    W.assign((size_t)L * L * L * L, 0.0);
+    for (int p = 0; p < L; ++p)
+      for (int q = 0; q < L; ++q)
+        for (int r = 0; r < L; ++r)
+          for (int s = 0; s < L; ++s) {
+            double v = eri[(((size_t)p * L + q) * L + r) * L + s];
+            if (r == s) v += h[p * L + q] / (N - 1);
+            if (p == q) v += h[r * L + s] / (N - 1);
+            W[(((size_t)p * L + q) * L + r) * L + s] = v;
+          }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Symmetry-sector tables (section "Reduced MPS tensors"; singlet embedding:
+// left boundary (0,0,I0), right boundary (S,N,I)).
+// ---------------------------------------------------------------------------
+using SecCount = std::map<Sec, long long>;
+
+static std::vector<SecCount> left_mult(const Problem& P) {
+  std::vector<SecCount> out(P.L + 1);
+  out[0][{0, 0, 0}] = 1;
+  for (int k = 0; k < P.L; ++k)
+    for (auto& [s, c] : out[k])
+      for (int n = 0; n < 3; ++n)
+        for (int tj = std::abs(s.tj - LOC_TJ[n]); tj <= s.tj + LOC_TJ[n]; tj += 2) {
+          long long& v = out[k + 1][{s.N + LOC_N[n], tj, s.G ^ loc_irrep(n, P.orb[k])}];
+          v = std::min<long long>(LLONG_MAX / 4, v + c);
+        }
+  return out;
+}
+
+static std::vector<SecCount> right_mult(const Problem& P) {
+  std::vector<SecCount> out(P.L + 1);
+  out[P.L][{P.N, P.twoS, P.irrep}] = 1;
+  for (int k = P.L - 1; k >= 0; --k)
+    for (auto& [b, c] : out[k + 1])
+      for (int n = 0; n < 3; ++n) {
+        const int N = b.N - LOC_N[n];
+        if (N < 0) continue;
+        for (int tj = std::abs(b.tj - LOC_TJ[n]); tj <= b.tj + LOC_TJ[n]; tj += 2) {
+          long long& v = out[k][{N, tj, b.G ^ loc_irrep(n, P.orb[k])}];
+          v = std::min<long long>(LLONG_MAX / 4, v + c);
+        }
+      }
+  return out;
+}
+
+// D split equally over the sectors, capped by the FCI dimension (section "DMRG"
+// of the library description): visit sectors by ascending cap, give each
+// min(cap, floor(rest / sectors left)), then the remainder one by one in
+// sector order to sectors below their cap.
+static std::map<Sec, int> distribute(int D, const std::map<Sec, long long>& caps) {
+  std::map<Sec, int> dims;
+  long long sum = 0;
+  for (auto& [s, c] : caps) sum += c;
+  if (sum <= D) {
+    for (auto& [s, c] : caps) dims[s] = (int)c;
+    return dims;
+  }
+  std::vector<Sec> order;
+  for (auto& [s, c] : caps) order.push_back(s);
+  std::stable_sort(order.begin(), order.end(), [&](const Sec& a, const Sec& b) {
+    if (caps.at(a) != caps.at(b)) return caps.at(a) < caps.at(b);
+    return a < b;
+  });
+  long long rest = D;
+  long long left = (long long)order.size();
+  for (const Sec& s : order) {
+    const long long d = std::min<long long>(caps.at(s), rest / left);
+    dims[s] = (int)d;
+    rest -= d;
+    --left;
+  }
+  while (rest > 0) {
+    bool moved = false;
+    for (auto& [s, c] : caps) {
+      if (rest == 0) break;
+      if (dims[s] < c) {
+        ++dims[s];
+        --rest;
+        moved = true;
+      }
+    }
+    if (!moved) break;
+  }
+  std::map<Sec, int> out;
+  for (auto& [s, d] : dims)
+    if (d > 0) out[s] = d;
+  return out;
+}
+
+static Basis to_basis(const std::map<Sec, int>& m) {
+  Basis b;
+  for (auto& [s, d] : m) {
+    b.sec.push_back(s);
+    b.dim.push_back(d);
+  }
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// Enlarged bases
+// ---------------------------------------------------------------------------
+struct Piece {
+  int sub, n, off;
+};
+struct Enl : Basis {
+  std::vector<std::vector<Piece>> pieces;
+  std::vector<std::vector<std::pair<int, int>>> where;  // [sub*3+n] -> (sector, offset)
+};
+
+static void finish_enl(Enl& E, const std::map<Sec, std::vector<std::pair<int, int>>>& tmp, const Basis& sub) {
+  for (auto& [m, pcs] : tmp) {
+    E.sec.push_back(m);
+    std::vector<Piece> pv;
+    int off = 0;
+    for (auto& [a, n] : pcs) {
+      pv.push_back({a, n, off});
+      off += sub.dim[a];
+    }
+    E.dim.push_back(off);
+    E.pieces.push_back(pv);
+  }
+  E.where.assign(sub.sec.size() * 3, {});
+  for (int m = 0; m < (int)E.sec.size(); ++m)
+    for (auto& p : E.pieces[m]) E.where[p.sub * 3 + p.n].push_back({m, p.off});
+}
+
+// left block at bond c-1 (x) site c-1 -> bond c ; pieces (a, n): a outer, n inner
+static Enl left_enl(const Problem& P, int c, const Basis& sub, const std::set<Sec>* keep) {
+  const int g = P.orb[c - 1];
+  std::map<Sec, std::vector<std::pair<int, int>>> tmp;
+  for (int a = 0; a < (int)sub.sec.size(); ++a)
+    for (int n = 0; n < 3; ++n) {
+      const Sec& s = sub.sec[a];
+      for (int tj = std::abs(s.tj - LOC_TJ[n]); tj <= s.tj + LOC_TJ[n]; tj += 2) {
+        Sec m{s.N + LOC_N[n], tj, s.G ^ loc_irrep(n, g)};
+        if (keep && !keep->count(m)) continue;
+        tmp[m].push_back({a, n});
+      }
+    }
+  Enl E;
+  finish_enl(E, tmp, sub);
+  return E;
+}
+
+// site c (x) right block at bond c+1 -> bond c ; pieces (n, b): n outer, b inner
+static Enl right_enl(const Problem& P, int c, const Basis& sub, const std::set<Sec>* keep) {
+  const int g = P.orb[c];
+  std::map<Sec, std::vector<std::pair<int, int>>> tmp;
+  for (int n = 0; n < 3; ++n)
+    for (int b = 0; b < (int)sub.sec.size(); ++b) {
+      const Sec& s = sub.sec[b];
+      const int N = s.N - LOC_N[n];
+      if (N < 0) continue;
+      for (int tj = std::abs(s.tj - LOC_TJ[n]); tj <= s.tj + LOC_TJ[n]; tj += 2) {
+        Sec m{N, tj, s.G ^ loc_irrep(n, g)};
+        if (keep && !keep->count(m)) continue;
+        tmp[m].push_back({b, n});
+      }
+    }
+  Enl E;
+  finish_enl(E, tmp, sub);
+  // the piece record keeps (sub = b, n)
+  return E;
+}
+
+// ---------------------------------------------------------------------------
+// Operator stores with canonical class layouts
+// ---------------------------------------------------------------------------
+enum Fam : int { F_H = 1, F_C = 2, F_S = 3, F_A = 4, F_B = 5, F_P = 6, F_Q = 7 };
+static inline uint64_t K(int fam, int tj = 0, int i = 0, int j = 0) {
+  return ((uint64_t)fam << 56) | ((uint64_t)tj << 48) | ((uint64_t)i << 24) | (uint64_t)j;
+}
+
+struct Layout {
+  int tk = 0, dN = 0, dG = 0;
+  std::vector<int> bra, ket;
+  std::vector<int64_t> eoff;
+  int64_t nnz = 0;
+  std::unordered_map<int64_t, int> idx;
+  int find(int b, int k) const {
+    auto it = idx.find((int64_t)b * 65536 + k);
+    return it == idx.end() ? -1 : it->second;
+  }
+  // adjoint element map (for dN == 0 classes), built on demand
+  DArr<int> perm;
+  DArr<double> fac;
+  bool adj_ready = false;
+};
+
+struct OpInfo {
+  uint64_t key;
+  int lay;
+  bool odd;
+  int64_t off;
+};
+
+struct Store {
+  char side = 'L';
+  int bond = 0;
+  std::vector<int> orbs;
+  Basis basis;
+  std::vector<std::unique_ptr<Layout>> lays;
+  std::map<std::tuple<int, int, int>, int> lay_of;
+  std::vector<OpInfo> ops;
+  std::unordered_map<uint64_t, int> by_key;
+  DBuf data;
+  int64_t total = 0;
+
+  int layout(int tk, int dN, int dG) {
+    auto key = std::make_tuple(tk, dN, dG);
+    auto it = lay_of.find(key);
+    if (it != lay_of.end()) return it->second;
+    auto L = std::make_unique<Layout>();
+    L->tk = tk, L->dN = dN, L->dG = dG;
+    const int ns = (int)basis.sec.size();
+    // sector labels count the electrons left of the bond: an operator adding
+    // dN electrons to a right block lowers the label by dN
+    const int dl = side == 'R' ? -dN : dN;
+    for (int b = 0; b < ns; ++b)
+      for (int k = 0; k < ns; ++k) {
+        const Sec &sb = basis.sec[b], &sk = basis.sec[k];
+        if (sb.N != sk.N + dl || sb.G != (sk.G ^ dG) || !triangle(sk.tj, tk, sb.tj)) continue;
+        L->idx[(int64_t)b * 65536 + k] = (int)L->bra.size();
+        L->bra.push_back(b);
+        L->ket.push_back(k);
+        L->eoff.push_back(L->nnz);
+        L->nnz += (int64_t)basis.dim[b] * basis.dim[k];
+      }
+    lays.push_back(std::move(L));
+    lay_of[key] = (int)lays.size() - 1;
+    return (int)lays.size() - 1;
+  }
+  int add(uint64_t key, int tk, int dN, int dG, bool odd) {
+    const int l = layout(tk, dN, dG);
+    ops.push_back({key, l, odd, total});
+    total += lays[l]->nnz;
+    by_key[key] = (int)ops.size() - 1;
+    return (int)ops.size() - 1;
+  }
+  int op(uint64_t key) const {
+    auto it = by_key.find(key);
+    return it == by_key.end() ? -1 : it->second;
+  }
+  int need(uint64_t key) const {
+    const int o = op(key);
+    if (o < 0) fail(-1, "internal: missing operator family in block");
+    return o;
+  }
+  const Layout& lay(int o) const { return *lays[ops[o].lay]; }
+  double* ptr(int o, int blk) const { return data.p + ops[o].off + lays[ops[o].lay]->eoff[blk]; }
+  void allocate(Stream st) {
+    data.alloc((size_t)std::max<int64_t>(total, 1));
+    dev_zero(data.p, (size_t)std::max<int64_t>(total, 1) * 8, st);
+  }
+  void ensure_adjoint_map(int l, Stream st) {
+    Layout& L = *lays[l];
+    if (L.adj_ready) return;
+    std::vector<int> perm(L.nnz);
+    std::vector<double> fac(L.nnz);
+    for (size_t b = 0; b < L.bra.size(); ++b) {
+      const int B = L.bra[b], Kk = L.ket[b];
+      const int src = L.find(Kk, B);  // original block (Kk <- B)
+      if (src < 0) fail(-1, "internal: class not closed under adjoint");
+      const double f = adjoint_factor(basis.sec[Kk].tj, basis.sec[B].tj, L.tk);
+      const int rows = basis.dim[B], cols = basis.dim[Kk];
+      for (int r = 0; r < rows; ++r)
+        for (int c = 0; c < cols; ++c) {
+          const int64_t e = L.eoff[b] + (int64_t)r * cols + c;
+          perm[e] = (int)(L.eoff[src] + (int64_t)c * rows + r);
+          fac[e] = f;
+        }
+    }
+    L.perm.put(perm, st);
+    L.fac.put(fac, st);
+    L.adj_ready = true;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Expressions: linear combinations of stored operators (optionally the
+// conjugate tensor Tbar), used as the block factor of a coupled product.
+// ---------------------------------------------------------------------------
+struct Ref {
+  int store;  // 0: the block, 1: combination scratch, -1: identity
+  int op;
+  double c;
+  bool adj;
+};
+using Expr = std::vector<Ref>;
+struct Term {
+  Expr x;
+  SiteOp s;
+  double coef;
+};
+struct Def {
+  uint64_t key;
+  int tk, dN, dG;
+  bool odd;
+  std::vector<Term> terms, sym;  // sym terms are added together with their transpose
+};
+
+static Expr adjoint_expr(const Expr& e, const Store& X, const Store& T) {
+  Expr out;
+  for (const Ref& r : e) {
+    Ref q = r;
+    if (r.store >= 0 && r.adj) {  // Tbar(Tbar(T)) = (-1)^(2k) T
+      const Store& S = r.store == 0 ? X : T;
+      if (S.lay(r.op).tk & 1) q.c = -q.c;
+    }
+    q.adj = !r.adj;
+    out.push_back(q);
+  }
+  return out;
+}
+
+// Combination scratch: integral-weighted sums of a block's operators
+// (complementary operators assembled on the fly), computed before blocking.
+struct Combos {
+  Store T;  // same basis as the block
+  struct In {
+    int op;
+    double c;
+    bool adj;
+  };
+  std::vector<std::vector<In>> inputs;  // per scratch op
+  std::vector<uint64_t> sig;            // dedup signature
+  std::map<std::vector<std::tuple<int, double, bool>>, int> memo;
+
+  // sum_i c_i op_i over block operators of one class; returns a Ref (store 1)
+  // or an empty expression when all coefficients vanish.
+  Expr make(const Store& X, const std::vector<In>& in, int tk, int dN, int dG, bool odd) {
+    std::vector<In> nz;
+    for (auto& i : in)
+      if (i.c != 0.0 && i.op >= 0) nz.push_back(i);
+    if (nz.empty()) return {};
+    if (nz.size() == 1 && !nz[0].adj) return {Ref{0, nz[0].op, nz[0].c, false}};
+    std::vector<std::tuple<int, double, bool>> key;
+    for (auto& i : nz) key.emplace_back(i.op, i.c, i.adj);
+    auto it = memo.find(key);
+    if (it != memo.end()) return {Ref{1, it->second, 1.0, false}};
+    const int o = T.add(K(0, 0, (int)inputs.size(), 0), tk, dN, dG, odd);
+    inputs.push_back(nz);
+    memo[key] = o;
+    return {Ref{1, o, 1.0, false}};
+  }
+
+  void run(Store& X, Stream st) {
+    if (T.ops.empty()) return;
+    T.allocate(st);
+    std::vector<ComboOut> outs;
+    std::vector<ComboIn> ins;
+    int64_t maxn = 0;
+    for (size_t o = 0; o < T.ops.size(); ++o) {
+      const int l = T.ops[o].lay;
+      const Layout& L = *T.lays[l];
+      const int xl = X.layout(L.tk, L.dN, L.dG);
+      bool any_adj = false;
+      for (auto& i : inputs[o]) any_adj |= i.adj;
+      if (any_adj) X.ensure_adjoint_map(xl, st);
+      ComboOut co;
+      co.out = T.data.p + T.ops[o].off;
+      co.nnz = L.nnz;
+      co.i0 = (int)ins.size();
+      for (auto& i : inputs[o]) {
+        if (X.ops[i.op].lay != xl) fail(-1, "internal: combination over mismatched classes");
+        ins.push_back({X.data.p + X.ops[i.op].off, i.c, i.adj ? 1 : 0});
+      }
+      co.i1 = (int)ins.size();
+      co.perm = any_adj ? X.lays[xl]->perm.p : nullptr;
+      co.fac = any_adj ? X.lays[xl]->fac.p : nullptr;
+      outs.push_back(co);
+      maxn = std::max(maxn, L.nnz);
+    }
+    d_outs.put(outs, st);
+    d_ins.put(ins, st);
+    launch_combo(d_outs.p, (int)outs.size(), d_ins.p, maxn, st);
+  }
+  DArr<ComboOut> d_outs;
+  DArr<ComboIn> d_ins;
+};
+
+// ---------------------------------------------------------------------------
+// Materialisation of enlarged-block operators from coupled products
+//   out += coef * [X-expression (x) site operator]^K    (left: block first)
+//   out += coef * [site operator (x) Y-expression]^K    (right: site first)
+// Reduced elements via coupling_product (9j) and the fermion sign of the
+// factor that is moved past the other one's electrons.
+// ---------------------------------------------------------------------------
+struct Entry {
+  int64_t dst;  // element offset in the enlarged store
+  int rows, cols, ld;
+  GatherSrc src;
+};
+
+struct Materializer {
+  std::vector<Entry> entries;
+
+  void emit_op(const Problem& P, const Store& X, const Store& T, const Enl& E, Store& Out, int outop,
+               const Term& term, bool left, bool mirror) {
+    const Layout& OL = Out.lay(outop);
+    const int tK = OL.tk;
+    for (const Ref& r : term.x) {
+      if (r.store == -1) {  // identity on the block
+        for (int a = 0; a < (int)X.basis.sec.size(); ++a)
+          emit_block(P, E, Out, outop, OL, tK, term, r.c, a, a, 0, false, nullptr, 0, GS_IDENT, X.basis, left,
+                     mirror);
+        continue;
+      }
+      const Store& S = r.store == 0 ? X : T;
+      const Layout& L = S.lay(r.op);
+      const bool odd = S.ops[r.op].odd;
+      for (size_t b = 0; b < L.bra.size(); ++b) {
+        int bra = L.bra[b], ket = L.ket[b];
+        double f = r.c;
+        int kind = GS_NORMAL;
+        const int ld = S.basis.dim[ket];
+        if (r.adj) {
+          f *= adjoint_factor(S.basis.sec[bra].tj, S.basis.sec[ket].tj, L.tk);
+          std::swap(bra, ket);
+          kind = GS_TRANS;
+        }
+        emit_block(P, E, Out, outop, OL, tK, term, f, bra, ket, L.tk, odd, S.ptr(r.op, (int)b), ld, kind, S.basis,
+                   left, mirror);
+      }
+    }
+  }
+
+  void emit_block(const Problem& P, const Enl& E, Store& Out, int outop, const Layout& OL, int tK, const Term& term,
+                  double f, int abra, int aket, int tkX, bool oddX, const double* src, int ld, int kind,
+                  const Basis& sub, bool left, bool mirror) {
+    const SiteOp& s = term.s;
+    const Sec &sb = sub.sec[abra], &sk = sub.sec[aket];
+    for (int nb = 0; nb < 3; ++nb)
+      for (int nk = 0; nk < 3; ++nk) {
+        const double sv = s.el[nb][nk];
+        if (sv == 0.0) continue;
+        for (auto& [mk, offk] : E.where[aket * 3 + nk])
+          for (auto& [mb, offb] : E.where[abra * 3 + nb]) {
+            const int tjk = E.sec[mk].tj, tjb = E.sec[mb].tj;
+            if (!triangle(tjk, tK, tjb)) continue;
+            double c9, sign;
+            if (left) {
+              c9 = coupling_product(sk.tj, LOC_TJ[nk], tjk, tkX, s.tk, tK, sb.tj, LOC_TJ[nb], tjb);
+              sign = (s.odd && (sk.N & 1)) ? -1.0 : 1.0;
+            } else {
+              c9 = coupling_product(LOC_TJ[nk], sk.tj, tjk, s.tk, tkX, tK, LOC_TJ[nb], sb.tj, tjb);
+              sign = (oddX && (LOC_N[nk] & 1)) ? -1.0 : 1.0;
+            }
+            if (c9 == 0.0) continue;
+            const double scale = term.coef * f * c9 * sign * sv;
+            const int blk = OL.find(mb, mk);
+            if (blk < 0)
+              fail(-1, "internal: enlarged block outside the class layout (op key " +
+                           std::to_string(Out.ops[outop].key >> 56) + "/" +
+                           std::to_string((Out.ops[outop].key >> 48) & 255) + " tk " + std::to_string(OL.tk) +
+                           " dN " + std::to_string(OL.dN) + " dG " + std::to_string(OL.dG) + "; bra N" +
+                           std::to_string(E.sec[mb].N) + " j" + std::to_string(E.sec[mb].tj) + " G" +
+                           std::to_string(E.sec[mb].G) + ", ket N" + std::to_string(E.sec[mk].N) + " j" +
+                           std::to_string(E.sec[mk].tj) + " G" + std::to_string(E.sec[mk].G) + ", X tk " +
+                           std::to_string(tkX) + " site tk " + std::to_string(s.tk) + ")");
+            const int cols_mk = E.dim[mk];
+            Entry e;
+            e.dst = Out.ops[outop].off + OL.eoff[blk] + (int64_t)offb * cols_mk + offk;
+            e.rows = sub.dim[abra];
+            e.cols = sub.dim[aket];
+            e.ld = cols_mk;
+            e.src = {src, ld, kind, scale};
+            entries.push_back(e);
+            if (mirror) {  // transpose partner: block (mk <- mb) at (offk, offb)
+              const int blk2 = OL.find(mk, mb);
+              if (blk2 < 0) fail(-1, "internal: transpose block missing");
+              Entry m;
+              m.dst = Out.ops[outop].off + OL.eoff[blk2] + (int64_t)offk * E.dim[mb] + offb;
+              m.rows = sub.dim[aket];
+              m.cols = sub.dim[abra];
+              m.ld = E.dim[mb];
+              m.src = {src, ld, kind == GS_NORMAL ? GS_TRANS : (kind == GS_TRANS ? GS_NORMAL : GS_IDENT), scale};
+              entries.push_back(m);
+            }
+          }
+      }
+  }
+
+  void run(Store& Out, Stream st) {
+    std::vector<size_t> idx(entries.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return entries[a].dst < entries[b].dst; });
+    std::vector<GatherDst> dsts;
+    std::vector<GatherSrc> srcs;
+    srcs.reserve(entries.size());
+    for (size_t i = 0; i < idx.size();) {
+      const Entry& e0 = entries[idx[i]];
+      GatherDst d{Out.data.p + e0.dst, e0.rows, e0.cols, e0.ld, (int)srcs.size(), 0};
+      size_t j = i;
+      while (j < idx.size() && entries[idx[j]].dst == e0.dst) {
+        const Entry& e = entries[idx[j]];
+        if (e.rows != e0.rows || e.cols != e0.cols) fail(-1, "internal: overlapping sub-blocks of different shape");
+        srcs.push_back(e.src);
+        ++j;
+      }
+      d.s1 = (int)srcs.size();
+      dsts.push_back(d);
+      i = j;
+    }
+    d_dst.put(dsts, st);
+    d_src.put(srcs, st);
+    launch_gather(d_dst.p, (int)dsts.size(), d_src.p, st);
+    n_entries = (int64_t)entries.size();
+    entries.clear();
+  }
+  DArr<GatherDst> d_dst;
+  DArr<GatherSrc> d_src;
+  int64_t n_entries = 0;
+};
+
+// ---------------------------------------------------------------------------
+// Blocking formulas: the operator families of an enlarged block in terms of
+// the block's families and site operators (complementary operators, section
+// "Complementary operators").  Families:
+//   H          block Hamiltonian
+//   C z        b+_z, z in the block
+//   S w        sum_{p,r,s in block} W_{w p r s} b+_p E_rs, w outside
+//   A j z z'   [b+_z b+_z']^j, B j z z' [b+_z b_z']^j   (z <= z', bare mode)
+//   P j w w'   sum_{zz'} W_{z w z' w'} A^j_zz'           (w <= w' outside)
+//   Q j a b    sum_{rs} q^j_ab(r,s) B^j_rs               (a <= b outside)
+// ---------------------------------------------------------------------------
+struct Blocker {
+  const Problem& P;
+  Store& X;    // block (at bond k)
+  Combos& cb;  // scratch combinations of X
+  bool bare;   // pair mode of X
+  Blocker(const Problem& p, Store& x, Combos& c, bool b) : P(p), X(x), cb(c), bare(b) {}
+
+  Expr C(int z) const { return {Ref{0, X.need(K(F_C, 0, z, 0)), 1.0, false}}; }
+  static Expr scale(Expr e, double f) {
+    for (auto& r : e) r.c *= f;
+    return e;
+  }
+  int gz(int z) const { return P.orb[z]; }
+
+  // sum_z c_z b+_z  (all z in the block share no constraint: grouped by irrep)
+  Expr cdag(const std::vector<double>& coef) {
+    // coefficients of orbitals with different irreps cannot mix; the caller's
+    // integrals respect the point group, so at most one irrep is nonzero.
+    std::vector<Combos::In> in;
+    int g = -1;
+    for (int z : X.orbs) {
+      const double c = coef[z];
+      if (c == 0.0) continue;
+      if (g >= 0 && gz(z) != g) fail(-3, "integrals break the point-group symmetry");
+      g = gz(z);
+      in.push_back({X.need(K(F_C, 0, z, 0)), c, false});
+    }
+    if (in.empty()) return {};
+    return cb.make(X, in, 1, 1, g, true);
+  }
+
+  Expr getP(int tj, int w, int wp) {
+    const int g = gz(w) ^ gz(wp);
+    const double sg = (tj == 2) ? -1.0 : 1.0;
+    if (!bare) {
+      if (tj == 2 && w == wp) return {};
+      if (w <= wp) return {Ref{0, X.need(K(F_P, tj, w, wp)), 1.0, false}};
+      return {Ref{0, X.need(K(F_P, tj, wp, w)), sg, false}};
+    }
+    std::vector<Combos::In> in;
+    for (int z : X.orbs)
+      for (int zp : X.orbs) {
+        const double c = P.w(z, w, zp, wp);
+        if (c == 0.0) continue;
+        if (tj == 2 && z == zp) continue;
+        const int a = std::min(z, zp), b = std::max(z, zp);
+        const double f = (z <= zp) ? 1.0 : sg;
+        in.push_back({X.need(K(F_A, tj, a, b)), c * f, false});
+      }
+    return cb.make(X, in, tj, 2, g, false);
+  }
+
+  Expr getQ(int tj, int a, int b) {
+    const int g = gz(a) ^ gz(b);
+    const double sg = (tj == 2) ? -1.0 : 1.0;
+    if (!bare) {
+      if (a <= b) return {Ref{0, X.need(K(F_Q, tj, a, b)), 1.0, false}};
+      return {Ref{0, X.need(K(F_Q, tj, b, a)), sg, true}};
+    }
+    std::vector<Combos::In> in;
+    for (int r : X.orbs)
+      for (int s : X.orbs) {
+        const double c = P.qc(tj, a, b, r, s);
+        if (c == 0.0) continue;
+        if (r <= s)
+          in.push_back({X.need(K(F_B, tj, r, s)), c, false});
+        else
+          in.push_back({X.need(K(F_B, tj, s, r)), c * sg, true});
+      }
+    return cb.make(X, in, tj, 0, g, false);
+  }
+};
+
+static void add_term(Def& d, Expr x, const SiteOp& s, double coef) {
+  if (x.empty() || coef == 0.0) return;
+  d.terms.push_back({std::move(x), s, coef});
+}
+static void add_sym(Def& d, Expr x, const SiteOp& s, double coef) {
+  if (x.empty() || coef == 0.0) return;
+  d.sym.push_back({std::move(x), s, coef});
+}
+static const Expr IDX = {Ref{-1, -1, 1.0, false}};
+
+// Left: block at bond k (x) site k -> enlarged block at bond k+1
+static std::vector<Def> defs_left(const Problem& P, Store& X, Combos& cb) {
+  const int k = X.bond, L = P.L;
+  const SiteOps& so = SO();
+  const double s2 = std::sqrt(2.0), s3 = std::sqrt(3.0), s32 = std::sqrt(1.5);
+  Blocker bk(P, X, cb, P.bare_left(k));
+  std::vector<Def> defs;
+  std::vector<double> coef(L, 0.0);
+  auto reset = [&] { std::fill(coef.begin(), coef.end(), 0.0); };
+
+  for (int x : X.orbs) {
+    Def d{K(F_C, 0, x, 0), 1, 1, P.orb[x], true, {}, {}};
+    add_term(d, bk.C(x), so.I, 1.0);
+    defs.push_back(d);
+  }
+  {
+    Def d{K(F_C, 0, k, 0), 1, 1, P.orb[k], true, {}, {}};
+    add_term(d, IDX, so.CD, 1.0);
+    defs.push_back(d);
+  }
+  {  // H
+    Def d{K(F_H), 0, 0, 0, false, {}, {}};
+    add_term(d, {Ref{0, X.need(K(F_H)), 1.0, false}}, so.I, 1.0);
+    SiteOp hk;  // site Hamiltonian: W_kkkk n_up n_down
+    hk.el[2][2] = P.w(k, k, k, k);
+    add_term(d, IDX, hk, 1.0);
+    add_sym(d, {Ref{0, X.need(K(F_S, 0, k, 0)), 1.0, false}}, so.C, -s2);
+    reset();
+    for (int x : X.orbs) coef[x] = P.w(x, k, k, k);
+    add_sym(d, bk.cdag(coef), so.EC, -s2);
+    add_sym(d, bk.getP(0, k, k), so.AA0, -0.5);
+    add_term(d, bk.getQ(0, k, k), so.B0, 1.0);
+    add_term(d, bk.getQ(2, k, k), so.B1, s3);
+    defs.push_back(d);
+  }
+  for (int y = k + 1; y < L; ++y) {  // S_y
+    Def d{K(F_S, 0, y, 0), 1, 1, P.orb[y], true, {}, {}};
+    add_term(d, {Ref{0, X.need(K(F_S, 0, y, 0)), 1.0, false}}, so.I, 1.0);
+    add_term(d, bk.getQ(0, k, y), so.CD, -1.0 / s2);
+    add_term(d, bk.getQ(2, k, y), so.CD, -s32);
+    add_term(d, bk.getP(0, y, k), so.C, 1.0 / s2);
+    add_term(d, bk.getP(2, y, k), so.C, -s32);
+    reset();
+    for (int s : X.orbs) coef[s] = P.w(k, y, k, s);
+    add_term(d, adjoint_expr(bk.cdag(coef), X, cb.T), so.A0, 1.0 / s2);
+    reset();
+    for (int r : X.orbs) coef[r] = P.w(k, y, r, k) / s2 - s2 * P.w(r, y, k, k);
+    add_term(d, bk.cdag(coef), so.B0, 1.0);
+    reset();
+    for (int r : X.orbs) coef[r] = P.w(k, y, r, k);
+    add_term(d, bk.cdag(coef), so.B1, s32);
+    add_term(d, IDX, so.CDE, P.w(k, y, k, k));
+    defs.push_back(d);
+  }
+  std::vector<int> orbs = X.orbs;
+  orbs.push_back(k);
+  if (P.bare_left(k + 1)) {
+    for (int x : orbs)
+      for (int xp : orbs) {
+        if (xp < x) continue;
+        const int g = P.orb[x] ^ P.orb[xp];
+        for (int tj : {0, 2}) {
+          if (!(x == xp && tj == 2)) {
+            Def d{K(F_A, tj, x, xp), tj, 2, g, false, {}, {}};
+            if (xp < k)
+              add_term(d, {Ref{0, X.need(K(F_A, tj, x, xp)), 1.0, false}}, so.I, 1.0);
+            else if (x < k)
+              add_term(d, bk.C(x), so.CD, 1.0);
+            else
+              add_term(d, IDX, so.A0, 1.0);
+            defs.push_back(d);
+          }
+          Def d{K(F_B, tj, x, xp), tj, 0, g, false, {}, {}};
+          if (xp < k)
+            add_term(d, {Ref{0, X.need(K(F_B, tj, x, xp)), 1.0, false}}, so.I, 1.0);
+          else if (x < k)
+            add_term(d, bk.C(x), so.C, 1.0);
+          else
+            add_term(d, IDX, so.B(tj), 1.0);
+          defs.push_back(d);
+        }
+      }
+  } else {
+    for (int w = k + 1; w < L; ++w)
+      for (int wp = w; wp < L; ++wp) {
+        const int g = P.orb[w] ^ P.orb[wp];
+        for (int tj : {0, 2}) {
+          const double sg = tj == 2 ? -1.0 : 1.0;
+          if (!(w == wp && tj == 2)) {
+            Def d{K(F_P, tj, w, wp), tj, 2, g, false, {}, {}};
+            add_term(d, bk.getP(tj, w, wp), so.I, 1.0);
+            reset();
+            for (int z : X.orbs) coef[z] = P.w(z, w, k, wp) + sg * P.w(k, w, z, wp);
+            add_term(d, bk.cdag(coef), so.CD, 1.0);
+            if (tj == 0) add_term(d, IDX, so.A0, P.w(k, w, k, wp));
+            defs.push_back(d);
+          }
+          Def d{K(F_Q, tj, w, wp), tj, 0, g, false, {}, {}};
+          add_term(d, bk.getQ(tj, w, wp), so.I, 1.0);
+          reset();
+          for (int r : X.orbs) coef[r] = P.qc(tj, w, wp, r, k);
+          add_term(d, bk.cdag(coef), so.C, 1.0);
+          reset();
+          for (int s : X.orbs) coef[s] = P.qc(tj, w, wp, k, s);
+          add_term(d, adjoint_expr(bk.cdag(coef), X, cb.T), so.CD, sg);
+          add_term(d, IDX, so.B(tj), P.qc(tj, w, wp, k, k));
+          defs.push_back(d);
+        }
+      }
+  }
+  return defs;
+}
+
+// Right: site k (x) block at bond k+1 -> enlarged block at bond k
+static std::vector<Def> defs_right(const Problem& P, Store& Y, Combos& cb) {
+  const int k = Y.bond - 1;
+  const SiteOps& so = SO();
+  const double s2 = std::sqrt(2.0), s3 = std::sqrt(3.0), s32 = std::sqrt(1.5);
+  Blocker bk(P, Y, cb, P.bare_right(k + 1));
+  std::vector<Def> defs;
+  std::vector<double> coef(P.L, 0.0);
+  auto reset = [&] { std::fill(coef.begin(), coef.end(), 0.0); };
+
+  for (int y : Y.orbs) {
+    Def d{K(F_C, 0, y, 0), 1, 1, P.orb[y], true, {}, {}};
+    add_term(d, bk.C(y), so.I, 1.0);
+    defs.push_back(d);
+  }
+  {
+    Def d{K(F_C, 0, k, 0), 1, 1, P.orb[k], true, {}, {}};
+    add_term(d, IDX, so.CD, 1.0);
+    defs.push_back(d);
+  }
+  {  // H
+    Def d{K(F_H), 0, 0, 0, false, {}, {}};
+    add_term(d, {Ref{0, Y.need(K(F_H)), 1.0, false}}, so.I, 1.0);
+    SiteOp hk;
+    hk.el[2][2] = P.w(k, k, k, k);
+    add_term(d, IDX, hk, 1.0);
+    reset();
+    for (int y : Y.orbs) coef[y] = P.w(k, y, k, k);
+    add_sym(d, adjoint_expr(bk.cdag(coef), Y, cb.T), so.CDE, -s2);
+    add_sym(d, adjoint_expr({Ref{0, Y.need(K(F_S, 0, k, 0)), 1.0, false}}, Y, cb.T), so.CD, -s2);
+    add_sym(d, adjoint_expr(bk.getP(0, k, k), Y, cb.T), so.A0, 0.5);
+    add_term(d, bk.getQ(0, k, k), so.B0, 1.0);
+    add_term(d, bk.getQ(2, k, k), so.B1, s3);
+    defs.push_back(d);
+  }
+  for (int x = 0; x < k; ++x) {  // S_x
+    Def d{K(F_S, 0, x, 0), 1, 1, P.orb[x], true, {}, {}};
+    add_term(d, {Ref{0, Y.need(K(F_S, 0, x, 0)), 1.0, false}}, so.I, 1.0);
+    add_term(d, bk.getQ(0, k, x), so.CD, -1.0 / s2);
+    add_term(d, bk.getQ(2, k, x), so.CD, s32);
+    add_term(d, bk.getP(0, x, k), so.C, 1.0 / s2);
+    add_term(d, bk.getP(2, x, k), so.C, s32);
+    reset();
+    for (int s : Y.orbs) coef[s] = P.w(x, k, k, s);
+    add_term(d, adjoint_expr(bk.cdag(coef), Y, cb.T), so.A0, 1.0 / s2);
+    reset();
+    for (int r : Y.orbs) coef[r] = P.w(x, k, r, k) / s2 - s2 * P.w(x, r, k, k);
+    add_term(d, bk.cdag(coef), so.B0, 1.0);
+    reset();
+    for (int r : Y.orbs) coef[r] = P.w(x, k, r, k);
+    add_term(d, bk.cdag(coef), so.B1, -s32);
+    add_term(d, IDX, so.CDE, P.w(x, k, k, k));
+    defs.push_back(d);
+  }
+  std::vector<int> orbs;
+  orbs.push_back(k);
+  for (int y : Y.orbs) orbs.push_back(y);
+  if (P.bare_right(k)) {
+    for (int y : orbs)
+      for (int yp : orbs) {
+        if (yp < y) continue;
+        const int g = P.orb[y] ^ P.orb[yp];
+        for (int tj : {0, 2}) {
+          if (!(y == yp && tj == 2)) {
+            Def d{K(F_A, tj, y, yp), tj, 2, g, false, {}, {}};
+            if (y > k)
+              add_term(d, {Ref{0, Y.need(K(F_A, tj, y, yp)), 1.0, false}}, so.I, 1.0);
+            else if (yp > k)
+              add_term(d, bk.C(yp), so.CD, 1.0);
+            else
+              add_term(d, IDX, so.A0, 1.0);
+            defs.push_back(d);
+          }
+          Def d{K(F_B, tj, y, yp), tj, 0, g, false, {}, {}};
+          if (y > k)
+            add_term(d, {Ref{0, Y.need(K(F_B, tj, y, yp)), 1.0, false}}, so.I, 1.0);
+          else if (yp > k)
+            add_term(d, adjoint_expr(bk.C(yp), Y, cb.T), so.CD, 1.0);
+          else
+            add_term(d, IDX, so.B(tj), 1.0);
+          defs.push_back(d);
+        }
+      }
+  } else {
+    for (int w = 0; w < k; ++w)
+      for (int wp = w; wp < k; ++wp) {
+        const int g = P.orb[w] ^ P.orb[wp];
+        for (int tj : {0, 2}) {
+          const double sg = tj == 2 ? -1.0 : 1.0;
+          if (!(w == wp && tj == 2)) {
+            Def d{K(F_P, tj, w, wp), tj, 2, g, false, {}, {}};
+            add_term(d, bk.getP(tj, w, wp), so.I, 1.0);
+            reset();
+            for (int z : Y.orbs) coef[z] = P.w(k, w, z, wp) + sg * P.w(z, w, k, wp);
+            add_term(d, bk.cdag(coef), so.CD, 1.0);
+            if (tj == 0) add_term(d, IDX, so.A0, P.w(k, w, k, wp));
+            defs.push_back(d);
+          }
+          Def d{K(F_Q, tj, w, wp), tj, 0, g, false, {}, {}};
+          add_term(d, bk.getQ(tj, w, wp), so.I, 1.0);
+          reset();
+          for (int s : Y.orbs) coef[s] = P.qc(tj, w, wp, k, s);
+          add_term(d, adjoint_expr(bk.cdag(coef), Y, cb.T), so.CD, 1.0);
+          reset();
+          for (int r : Y.orbs) coef[r] = P.qc(tj, w, wp, r, k);
+          add_term(d, bk.cdag(coef), so.C, sg);
+          add_term(d, IDX, so.B(tj), P.qc(tj, w, wp, k, k));
+          defs.push_back(d);
+        }
+      }
+  }
+  return defs;
+}
+
+// Enlarge a block by one site: combinations, then materialisation.
+static std::unique_ptr<Store> enlarge(const Problem& P, Store& X, const Enl& E, bool left, Stream st,
+                                      int64_t* n_entries) {
+  Combos cb;
+  cb.T.side = X.side;
+  cb.T.bond = X.bond;
+  cb.T.basis = X.basis;
+  std::vector<Def> defs = left ? defs_left(P, X, cb) : defs_right(P, X, cb);
+  cb.run(X, st);
+  auto out = std::make_unique<Store>();
+  out->side = left ? 'L' : 'R';
+  out->bond = left ? X.bond + 1 : X.bond - 1;
+  out->orbs = X.orbs;
+  if (left)
+    out->orbs.push_back(X.bond);
+  else
+    out->orbs.insert(out->orbs.begin(), X.bond - 1);
+  out->basis.sec = E.sec;
+  out->basis.dim = E.dim;
+  std::vector<int> opidx;
+  for (auto& d : defs) opidx.push_back(out->add(d.key, d.tk, d.dN, d.dG, d.odd));
+  out->allocate(st);
+  Materializer mat;
+  for (size_t i = 0; i < defs.size(); ++i) {
+    for (auto& t : defs[i].terms) mat.emit_op(P, X, cb.T, E, *out, opidx[i], t, left, false);
+    for (auto& t : defs[i].sym) mat.emit_op(P, X, cb.T, E, *out, opidx[i], t, left, true);
+  }
+  mat.run(*out, st);
+  if (n_entries) *n_entries += mat.n_entries;
+  dev_sync(st);  // scratch combinations are released on return
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// Triple-product task lists (tiles of at most 64 x 64 output elements)
+// ---------------------------------------------------------------------------
+struct TripleList {
+  struct T {
+    int tile;
+    TTask t;
+  };
+  std::vector<TTile> tiles;
+  std::vector<T> tasks;
+  double flops = 0.0;
+  // register an output block; returns the first tile index and count per dim
+  int add_block(double* out, int rows, int cols, int ld) {
+    const int first = (int)tiles.size();
+    for (int r0 = 0; r0 < rows; r0 += 64)
+      for (int c0 = 0; c0 < cols; c0 += 64)
+        tiles.push_back({out + (int64_t)r0 * ld + c0, ld, std::min(64, rows - r0), std::min(64, cols - c0), 0, 0});
+    return first;
+  }
+  // out block (registered at `first` with `cols` columns) += coef*opA(A)*B*opC(C)
+  void add(int first, int rows, int cols, const TTask& base) {
+    const int ntc = (cols + 63) / 64;
+    const int K1 = base.K1, K2 = base.K2;
+    if (base.flags & TT_IDENT_C)
+      flops += 2.0 * rows * K1 * cols;
+    else if (base.flags & TT_IDENT_A)
+      flops += 2.0 * rows * K2 * cols;
+    else
+      flops += 2.0 * rows * K1 * K2 + 2.0 * rows * K2 * cols;
+    for (int r0 = 0, tr = 0; r0 < rows; r0 += 64, ++tr)
+      for (int c0 = 0, tc = 0; c0 < cols; c0 += 64, ++tc) {
+        TTask t = base;
+        if (t.flags & TT_IDENT_A)
+          t.b += (int64_t)r0 * t.ldb;
+        else if (t.flags & TT_TRANS_A)
+          t.a += r0;
+        else
+          t.a += (int64_t)r0 * t.lda;
+        if (t.flags & TT_IDENT_C)
+          t.b += c0;
+        else if (t.flags & TT_TRANS_C)
+          t.c += (int64_t)c0 * t.ldc;
+        else
+          t.c += c0;
+        tasks.push_back({first + tr * ntc + tc, t});
+      }
+  }
+  // group by tile and upload
+  void upload(DArr<TTile>& dt, DArr<TTask>& dk, Stream st) {
+    std::vector<int> cnt(tiles.size() + 1, 0);
+    for (auto& t : tasks) cnt[t.tile + 1]++;
+    for (size_t i = 0; i < tiles.size(); ++i) cnt[i + 1] += cnt[i];
+    std::vector<TTask> flat(tasks.size());
+    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+    for (auto& t : tasks) flat[pos[t.tile]++] = t.t;
+    for (size_t i = 0; i < tiles.size(); ++i) {
+      tiles[i].t0 = cnt[i];
+      tiles[i].t1 = cnt[i + 1];
+    }
+    dt.put(tiles, st);
+    dk.put(flat, st);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct Tensor {  // per-sector dense matrices of one MPS site
+  Basis rowsec;  // sectors (labels)
+  std::vector<int> rows, cols;
+  std::vector<int64_t> off;
+  DBuf data;
+  int find(const Sec& s) const { return rowsec.find(s); }
+  double* at(int i) const { return data.p + off[i]; }
+};
+
+enum CenterKind { C_NONE, C_TWO, C_BOND_R, C_BOND_L, C_T0 };
+
+struct Center {
+  CenterKind kind = C_NONE;
+  int pos = -1;         // two-site step i (C_TWO, C_T0) or bond c (C_BOND_*)
+  Tensor t;             // matrices: TWO: psi per sector (dimX x dimY); BOND_R: (k_a x dimY(a));
+                        // BOND_L: (dimX(b) x k_b); T0: (dimX(m) x d_m)
+};
+
+struct Step {
+  int i = -1;
+  std::unique_ptr<Store> X, Y;
+  Enl EX, EY;
+  Basis psi;  // sectors with dims as (dimX) ; dimY separately
+  std::vector<int> dx, dy;
+  std::vector<int64_t> off;
+  int64_t n = 0;
+  DBuf in, out, diag;
+  DArr<TTile> tiles;
+  DArr<TTask> tasks;
+  int ntiles = 0;
+  double flops = 0.0, bytes = 0.0;
+  int64_t ntasks = 0;
+};
+
+struct Engine {
+  Problem P;
+  Stream st = nullptr;
+  int device = 0;
+  uint64_t seed = 7;
+  double dav_tol = 1e-9;
+  int dav_max_sub = 32, dav_max_iter = 200;
+  std::string err;
+  std::vector<std::map<Sec, long long>> caps;
+  std::vector<Basis> dims;  // bond dimensions (kept)
+  std::vector<std::unique_ptr<Store>> Lb, Rb;
+  std::vector<Tensor> U, V;  // left tensors U[i]: bond i+1 sectors (dimX x k); right V[i]: bond i (k x dimY)
+  Center cen;
+  Step step;
+  bool mps_ready = false;
+  double emin = INFINITY, elast = NAN, wdisc = 0.0, wdisc_sweep = 0.0;
+  std::vector<double> trace;
+  bool warned = false;
+  // statistics
+  double t_sigma = 0, t_micro = 0, f_sigma = 0, t_block = 0;
+  int64_t n_sigma = 0;
+  // Davidson work buffers
+  DBuf dV, dW, dHs, dsmall, dpartial, dx_, dax, dr, dt;
+
+  void check_target() const {
+    if (P.N < 0) fail(-1, "target not set");
+    if (!P.have_ints) fail(-1, "integrals not set");
+  }
+
+  // ---- tables
+  void build_caps() {
+    auto lm = left_mult(P), rm = right_mult(P);
+    caps.assign(P.L + 1, {});
+    for (int k = 0; k <= P.L; ++k) {
+      for (auto& [s, c] : lm[k]) {
+        auto it = rm[k].find(s);
+        if (it != rm[k].end()) caps[k][s] = std::min(c, it->second);
+      }
+      if (caps[k].empty()) fail(-2, "the target symmetry sector is empty");
+    }
+  }
+
+  // ---- boundary blocks
+  std::unique_ptr<Store> left_boundary() {
+    auto s = std::make_unique<Store>();
+    s->side = 'L';
+    s->bond = 0;
+    s->basis.sec = {{0, 0, 0}};
+    s->basis.dim = {1};
+    s->add(K(F_H), 0, 0, 0, false);
+    for (int y = 0; y < P.L; ++y) s->add(K(F_S, 0, y, 0), 1, 1, P.orb[y], true);
+    s->allocate(st);
+    return s;
+  }
+  std::unique_ptr<Store> right_boundary() {
+    auto s = std::make_unique<Store>();
+    s->side = 'R';
+    s->bond = P.L;
+    s->basis.sec = {{P.N, P.twoS, P.irrep}};
+    s->basis.dim = {1};
+    s->add(K(F_H), 0, 0, 0, false);
+    for (int x = 0; x < P.L; ++x) s->add(K(F_S, 0, x, 0), 1, 1, P.orb[x], true);
+    s->allocate(st);
+    return s;
+  }
+
+  // ---- renormalisation: left O' = U^T O U, right O' = V O V^T
+  std::unique_ptr<Store> renormalize(const Store& E, const Tensor& T, const Basis& nb, bool left) {
+    auto out = std::make_unique<Store>();
+    out->side = E.side;
+    out->bond = E.bond;
+    out->orbs = E.orbs;
+    out->basis = nb;
+    for (auto& o : E.ops) {
+      const Layout& L = *E.lays[o.lay];
+      out->add(o.key, L.tk, L.dN, L.dG, o.odd);
+    }
+    out->allocate(st);
+    TripleList tl;
+    for (size_t i = 0; i < out->ops.size(); ++i) {
+      const Layout& NL = out->lay((int)i);
+      const Layout& EL = E.lay((int)i);
+      for (size_t b = 0; b < NL.bra.size(); ++b) {
+        const Sec &sb = nb.sec[NL.bra[b]], &sk = nb.sec[NL.ket[b]];
+        const int eb = E.basis.find(sb), ek = E.basis.find(sk);
+        const int tb = T.find(sb), tkk = T.find(sk);
+        if (eb < 0 || ek < 0 || tb < 0 || tkk < 0) fail(-1, "internal: renormalisation sector missing");
+        const int eblk = EL.find(eb, ek);
+        if (eblk < 0) continue;
+        const int rows = nb.dim[NL.bra[b]], cols = nb.dim[NL.ket[b]];
+        double* o = out->ptr((int)i, (int)b);
+        const int first = tl.add_block(o, rows, cols, cols);
+        TTask t{};
+        t.b = E.ptr((int)i, eblk);
+        t.ldb = E.basis.dim[ek];
+        t.coef = 1.0;
+        if (left) {  // U[b]^T (dimX(b) x k_b)^T * O * U[k]
+          t.a = T.at(tb);
+          t.lda = T.cols[tb];
+          t.K1 = E.basis.dim[eb];
+          t.c = T.at(tkk);
+          t.ldc = T.cols[tkk];
+          t.K2 = E.basis.dim[ek];
+          t.flags = TT_TRANS_A;
+        } else {  // V[b] (k_b x dimY(b)) * O * V[k]^T
+          t.a = T.at(tb);
+          t.lda = T.cols[tb];
+          t.K1 = E.basis.dim[eb];
+          t.c = T.at(tkk);
+          t.ldc = T.cols[tkk];
+          t.K2 = E.basis.dim[ek];
+          t.flags = TT_TRANS_C;
+        }
+        tl.add(first, rows, cols, t);
+      }
+    }
+    DArr<TTile> dt;
+    DArr<TTask> dk;
+    tl.upload(dt, dk, st);
+    launch_triple(dt.p, (int)tl.tiles.size(), dk.p, st);
+    dev_sync(st);
+    return out;
+  }
+
+  // ---- random initial MPS (section "DMRG" of the library description)
+  void init_mps(int D) {
+    check_target();
+    if (D < 1) fail(-1, "D must be positive");
+    build_caps();
+    dims.assign(P.L + 1, {});
+    for (int k = 0; k <= P.L; ++k) dims[k] = to_basis(distribute(D, caps[k]));
+    U.clear();
+    U.resize(P.L);
+    V.clear();
+    V.resize(P.L);
+    DBuf work, tmp;
+    for (int k = P.L - 1; k >= 1; --k) {
+      std::set<Sec> keep(dims[k].sec.begin(), dims[k].sec.end());
+      Enl E = right_enl(P, k, dims[k + 1], &keep);
+      std::vector<int> ids;
+      int64_t need = 0, wneed = 0;
+      std::map<Sec, int> newd;
+      for (int qi = 0; qi < (int)dims[k].sec.size(); ++qi) {
+        const int e = E.find(dims[k].sec[qi]);
+        if (e < 0) continue;
+        ids.push_back(qi);
+        const int d = dims[k].dim[qi], n = E.dim[e];
+        need += (int64_t)d * n;
+        const int r = std::min(d, n);
+        wneed += (int64_t)d * n + (int64_t)r * r + r;
+      }
+      // random (d x n) per sector, SVD, keep the orthonormal rows
+      tmp.alloc((size_t)std::max<int64_t>(need, 1));
+      int64_t o = 0;
+      std::vector<int64_t> offs;
+      for (int qi : ids) {
+        const int e = E.find(dims[k].sec[qi]);
+        const int d = dims[k].dim[qi], n = E.dim[e];
+        launch_fill_uniform(tmp.p + o, (int64_t)d * n, seed, ((uint64_t)k << 20) | (uint64_t)qi, st);
+        offs.push_back(o);
+        o += (int64_t)d * n;
+      }
+      Tensor t;
+      int64_t toff = 0, uoff = 0;
+      std::vector<SvdJob> jobs;
+      std::vector<int> rr;
+      for (size_t j = 0; j < ids.size(); ++j) {
+        const int e = E.find(dims[k].sec[ids[j]]);
+        const int d = dims[k].dim[ids[j]], n = E.dim[e];
+        const int r = std::min(d, n);
+        t.rowsec.sec.push_back(dims[k].sec[ids[j]]);
+        t.rowsec.dim.push_back(r);
+        t.rows.push_back(r);
+        t.cols.push_back(n);
+        t.off.push_back(toff);
+        toff += (int64_t)r * n;
+        uoff += (int64_t)d * r + r;
+        rr.push_back(r);
+        newd[dims[k].sec[ids[j]]] = r;
+      }
+      t.data.alloc((size_t)std::max<int64_t>(toff, 1));
+      DBuf ubuf;
+      ubuf.alloc((size_t)std::max<int64_t>(uoff, 1));
+      work.alloc((size_t)std::max<int64_t>(wneed, 1));
+      int64_t wo = 0, uo = 0;
+      int maxs = 1;
+      for (size_t j = 0; j < ids.size(); ++j) {
+        const int e = E.find(dims[k].sec[ids[j]]);
+        const int d = dims[k].dim[ids[j]], n = E.dim[e], r = rr[j];
+        SvdJob jb{tmp.p + offs[j], d, n, n, ubuf.p + uo, ubuf.p + uo + (int64_t)d * r, t.at((int)j), work.p + wo};
+        jobs.push_back(jb);
+        uo += (int64_t)d * r + r;
+        wo += (int64_t)d * n + (int64_t)r * r + r;
+        maxs = std::max(maxs, r);
+      }
+      DArr<SvdJob> dj;
+      dj.put(jobs, st);
+      launch_svd(dj.p, (int)jobs.size(), maxs, st);
+      dev_sync(st);
+      V[k] = std::move(t);
+      dims[k] = to_basis(newd);
+    }
+    // T0: random left tensor of site 0 (enlarged-left at bond 1 x bond 1)
+    {
+      std::set<Sec> keep(dims[1].sec.begin(), dims[1].sec.end());
+      Enl E0 = left_enl(P, 1, dims[0], &keep);
+      Tensor t;
+      int64_t o = 0;
+      std::vector<int> qis;
+      for (int qi = 0; qi < (int)dims[1].sec.size(); ++qi) {
+        const int e = E0.find(dims[1].sec[qi]);
+        if (e < 0) continue;
+        t.rowsec.sec.push_back(dims[1].sec[qi]);
+        t.rowsec.dim.push_back(E0.dim[e]);
+        t.rows.push_back(E0.dim[e]);
+        t.cols.push_back(dims[1].dim[qi]);
+        t.off.push_back(o);
+        o += (int64_t)E0.dim[e] * dims[1].dim[qi];
+        qis.push_back(qi);
+      }
+      t.data.alloc((size_t)std::max<int64_t>(o, 1));
+      for (size_t j = 0; j < qis.size(); ++j)
+        launch_fill_uniform(t.at((int)j), (int64_t)t.rows[j] * t.cols[j], seed, (uint64_t)qis[j], st);
+      cen.kind = C_T0;
+      cen.pos = 0;
+      cen.t = std::move(t);
+    }
+    build_blocks_from_tensors(0);
+    mps_ready = true;
+  }
+
+  // Build left blocks 0..i and right blocks L..i+2 from the stored tensors.
+  void build_blocks_from_tensors(int i) {
+    Lb.clear();
+    Rb.clear();
+    Lb.resize(P.L + 1);
+    Rb.resize(P.L + 1);
+    Lb[0] = left_boundary();
+    for (int k = 0; k < i; ++k) {
+      std::set<Sec> keep(dims[k + 1].sec.begin(), dims[k + 1].sec.end());
+      Enl E = left_enl(P, k + 1, Lb[k]->basis, &keep);
+      auto Xe = enlarge(P, *Lb[k], E, true, st, nullptr);
+      Lb[k + 1] = renormalize(*Xe, U[k], dims[k + 1], true);
+    }
+    Rb[P.L] = right_boundary();
+    for (int k = P.L - 1; k >= i + 2; --k) {
+      std::set<Sec> keep(dims[k].sec.begin(), dims[k].sec.end());
+      Enl E = right_enl(P, k, Rb[k + 1]->basis, &keep);
+      auto Ye = enlarge(P, *Rb[k + 1], E, false, st, nullptr);
+      Rb[k] = renormalize(*Ye, V[k], dims[k], false);
+    }
+    step.i = -1;
+  }
+
+  // ---- prepare the two-site step at sites (i, i+1)
+  void prepare(int i) {
+    if (step.i == i && step.X && step.Y) {
+      build_guess();
+      return;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    const int c = i + 1;
+    Store& Lk = *Lb[i];
+    Store& Rk = *Rb[i + 2];
+    Enl el0 = left_enl(P, c, Lk.basis, nullptr), er0 = right_enl(P, c, Rk.basis, nullptr);
+    std::set<Sec> keep;
+    for (auto& s : el0.sec)
+      if (er0.find(s) >= 0) keep.insert(s);
+    step = Step();
+    step.i = i;
+    step.EX = left_enl(P, c, Lk.basis, &keep);
+    step.EY = right_enl(P, c, Rk.basis, &keep);
+    int64_t ne = 0;
+    step.X = enlarge(P, Lk, step.EX, true, st, &ne);
+    step.Y = enlarge(P, Rk, step.EY, false, st, &ne);
+    // psi layout
+    step.psi.sec = step.EX.sec;
+    step.n = 0;
+    for (size_t m = 0; m < step.EX.sec.size(); ++m) {
+      step.dx.push_back(step.EX.dim[m]);
+      step.dy.push_back(step.EY.dim[m]);
+      step.off.push_back(step.n);
+      step.n += (int64_t)step.EX.dim[m] * step.EY.dim[m];
+    }
+    step.psi.dim = step.dx;
+    step.in.alloc((size_t)std::max<int64_t>(step.n, 1));
+    step.out.alloc((size_t)std::max<int64_t>(step.n, 1));
+    step.diag.alloc((size_t)std::max<int64_t>(step.n, 1));
+    build_sigma_tasks();
+    build_diag();
+    build_guess();
+    dev_sync(st);
+    t_block += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  struct HTerm {
+    double coef;
+    int x, y;  // op index in step.X / step.Y, -1 identity
+    bool yadj, hc;
+  };
+
+  std::vector<HTerm> heff_terms() {
+    std::vector<HTerm> ts;
+    Store &X = *step.X, &Y = *step.Y;
+    const double s2 = std::sqrt(2.0), s3 = std::sqrt(3.0);
+    ts.push_back({1.0, X.need(K(F_H)), -1, false, false});
+    ts.push_back({1.0, -1, Y.need(K(F_H)), false, false});
+    for (int y : Y.orbs) ts.push_back({-s2, X.need(K(F_S, 0, y, 0)), Y.need(K(F_C, 0, y, 0)), true, true});
+    for (int x : X.orbs) ts.push_back({-s2, X.need(K(F_C, 0, x, 0)), Y.need(K(F_S, 0, x, 0)), true, true});
+    const int c = step.i + 1;
+    const std::vector<int>& pr = P.bare_left(c) ? X.orbs : Y.orbs;
+    const bool pairs_on_x = P.bare_left(c);
+    for (int a : pr)
+      for (int b : pr) {
+        if (b < a) continue;
+        for (int tj : {0, 2}) {
+          const double cb = tj == 0 ? 1.0 : s3;
+          if (pairs_on_x) {
+            if (a < b) {
+              ts.push_back({std::sqrt(tj + 1.0), X.need(K(F_A, tj, a, b)), Y.need(K(F_P, tj, a, b)), true, true});
+              ts.push_back({cb, X.need(K(F_B, tj, a, b)), Y.need(K(F_Q, tj, a, b)), false, true});
+            } else {
+              if (tj == 0) ts.push_back({0.5, X.need(K(F_A, 0, a, a)), Y.need(K(F_P, 0, a, a)), true, true});
+              ts.push_back({cb, X.need(K(F_B, tj, a, a)), Y.need(K(F_Q, tj, a, a)), false, false});
+            }
+          } else {
+            if (a < b) {
+              ts.push_back({std::sqrt(tj + 1.0), X.need(K(F_P, tj, a, b)), Y.need(K(F_A, tj, a, b)), true, true});
+              ts.push_back({cb, X.need(K(F_Q, tj, a, b)), Y.need(K(F_B, tj, a, b)), false, true});
+            } else {
+              if (tj == 0) ts.push_back({0.5, X.need(K(F_P, 0, a, a)), Y.need(K(F_A, 0, a, a)), true, true});
+              ts.push_back({cb, X.need(K(F_Q, tj, a, a)), Y.need(K(F_B, tj, a, a)), false, false});
+            }
+          }
+        }
+      }
+    return ts;
+  }
+
+  void build_sigma_tasks() {
+    Store &X = *step.X, &Y = *step.Y;
+    TripleList tl;
+    const int ns = (int)step.psi.sec.size();
+    std::vector<int> first(ns);
+    for (int m = 0; m < ns; ++m) first[m] = tl.add_block(step.out.p + step.off[m], step.dx[m], step.dy[m], step.dy[m]);
+    double bytes = 0.0;
+    std::set<std::pair<int, int>> touched;  // (store, op) operands read
+    for (const HTerm& h : heff_terms()) {
+      if (h.y < 0) {  // H_X (x) 1
+        const Layout& L = X.lay(h.x);
+        for (size_t b = 0; b < L.bra.size(); ++b) {
+          const int m = L.bra[b];
+          if (L.ket[b] != m) continue;
+          TTask t{};
+          t.a = X.ptr(h.x, (int)b);
+          t.lda = step.dx[m];
+          t.K1 = step.dx[m];
+          t.b = step.in.p + step.off[m];
+          t.ldb = step.dy[m];
+          t.flags = TT_IDENT_C;
+          t.coef = h.coef;
+          tl.add(first[m], step.dx[m], step.dy[m], t);
+        }
+        touched.insert({0, h.x});
+        continue;
+      }
+      if (h.x < 0) {  // 1 (x) H_Y : psi H^T
+        const Layout& L = Y.lay(h.y);
+        for (size_t b = 0; b < L.bra.size(); ++b) {
+          const int m = L.bra[b];
+          if (L.ket[b] != m) continue;
+          TTask t{};
+          t.b = step.in.p + step.off[m];
+          t.ldb = step.dy[m];
+          t.c = Y.ptr(h.y, (int)b);
+          t.ldc = step.dy[m];
+          t.K2 = step.dy[m];
+          t.flags = TT_IDENT_A | TT_TRANS_C;
+          t.coef = h.coef;
+          tl.add(first[m], step.dx[m], step.dy[m], t);
+        }
+        touched.insert({1, h.y});
+        continue;
+      }
+      const Layout& XL = X.lay(h.x);
+      const Layout& YL = Y.lay(h.y);
+      const int tk = XL.tk;
+      const bool yodd = Y.ops[h.y].odd;
+      touched.insert({0, h.x});
+      touched.insert({1, h.y});
+      for (size_t b = 0; b < XL.bra.size(); ++b) {
+        const int mb = XL.bra[b], mk = XL.ket[b];
+        int yb;
+        double fy = 1.0;
+        if (h.yadj) {
+          yb = YL.find(mk, mb);
+          if (yb < 0) continue;
+          fy = adjoint_factor(step.psi.sec[mk].tj, step.psi.sec[mb].tj, tk);
+        } else {
+          yb = YL.find(mb, mk);
+          if (yb < 0) continue;
+        }
+        const double cs = coupling_singlet(step.psi.sec[mk].tj, step.psi.sec[mb].tj, tk);
+        const double sign = (yodd && (step.psi.sec[mk].N & 1)) ? -1.0 : 1.0;
+        const double f = h.coef * cs * sign * fy;
+        if (f == 0.0) continue;
+        const double* xa = X.ptr(h.x, (int)b);
+        const double* yc = Y.ptr(h.y, yb);
+        {  // sigma[mb] += f X[mb,mk] psi[mk] Yeff[mb,mk]^T
+          TTask t{};
+          t.a = xa;
+          t.lda = step.dx[mk];
+          t.K1 = step.dx[mk];
+          t.b = step.in.p + step.off[mk];
+          t.ldb = step.dy[mk];
+          t.c = yc;
+          t.K2 = step.dy[mk];
+          if (h.yadj) {
+            t.ldc = step.dy[mb];  // stored (mk <- mb): dy[mk] x dy[mb]
+            t.flags = 0;
+          } else {
+            t.ldc = step.dy[mk];  // stored (mb <- mk): dy[mb] x dy[mk]
+            t.flags = TT_TRANS_C;
+          }
+          t.coef = f;
+          tl.add(first[mb], step.dx[mb], step.dy[mb], t);
+        }
+        if (h.hc) {  // sigma[mk] += f X[mb,mk]^T psi[mb] Yeff[mb,mk]
+          TTask t{};
+          t.a = xa;
+          t.lda = step.dx[mk];
+          t.K1 = step.dx[mb];
+          t.b = step.in.p + step.off[mb];
+          t.ldb = step.dy[mb];
+          t.c = yc;
+          t.K2 = step.dy[mb];
+          if (h.yadj) {
+            t.ldc = step.dy[mb];
+            t.flags = TT_TRANS_A | TT_TRANS_C;
+          } else {
+            t.ldc = step.dy[mk];
+            t.flags = TT_TRANS_A;
+          }
+          t.coef = f;
+          tl.add(first[mk], step.dx[mk], step.dy[mk], t);
+        }
+      }
+    }
+    for (auto& [s, o] : touched) bytes += 8.0 * (s == 0 ? X.lay(o).nnz : Y.lay(o).nnz);
+    bytes += 16.0 * step.n;
+    step.flops = tl.flops;
+    step.bytes = bytes;
+    step.ntasks = (int64_t)tl.tasks.size();
+    step.ntiles = (int)tl.tiles.size();
+    tl.upload(step.tiles, step.tasks, st);
+  }
+
+  void build_diag() {
+    Store &X = *step.X, &Y = *step.Y;
+    const int ns = (int)step.psi.sec.size();
+    std::vector<std::vector<DiagTask>> per(ns);
+    for (const HTerm& h : heff_terms()) {
+      if (h.y < 0 || h.x < 0) {
+        const bool xs = h.y < 0;
+        const Store& S = xs ? X : Y;
+        const int o = xs ? h.x : h.y;
+        const Layout& L = S.lay(o);
+        for (size_t b = 0; b < L.bra.size(); ++b) {
+          const int m = L.bra[b];
+          if (L.ket[b] != m) continue;
+          DiagTask d{};
+          if (xs) {
+            d.x = S.ptr(o, (int)b);
+            d.sx = step.dx[m] + 1;
+          } else {
+            d.y = S.ptr(o, (int)b);
+            d.sy = step.dy[m] + 1;
+          }
+          d.coef = h.coef;
+          per[m].push_back(d);
+        }
+        continue;
+      }
+      const Layout& XL = X.lay(h.x);
+      const Layout& YL = Y.lay(h.y);
+      const int tk = XL.tk;
+      for (size_t b = 0; b < XL.bra.size(); ++b) {
+        const int m = XL.bra[b];
+        if (XL.ket[b] != m) continue;
+        const int yb = YL.find(m, m);
+        if (yb < 0) continue;
+        double fy = h.yadj ? adjoint_factor(step.psi.sec[m].tj, step.psi.sec[m].tj, tk) : 1.0;
+        const double cs = coupling_singlet(step.psi.sec[m].tj, step.psi.sec[m].tj, tk);
+        const double sign = (Y.ops[h.y].odd && (step.psi.sec[m].N & 1)) ? -1.0 : 1.0;
+        DiagTask d{X.ptr(h.x, (int)b), Y.ptr(h.y, yb), step.dx[m] + 1, step.dy[m] + 1,
+                   h.coef * cs * sign * fy * (h.hc ? 2.0 : 1.0)};
+        if (d.coef != 0.0) per[m].push_back(d);
+      }
+    }
+    std::vector<DiagSec> secs;
+    std::vector<DiagTask> tasks;
+    for (int m = 0; m < ns; ++m) {
+      DiagSec s{step.diag.p + step.off[m], step.dx[m], step.dy[m], (int)tasks.size(), 0};
+      for (auto& d : per[m]) tasks.push_back(d);
+      s.t1 = (int)tasks.size();
+      secs.push_back(s);
+    }
+    DArr<DiagSec> ds;
+    DArr<DiagTask> dt;
+    ds.put(secs, st);
+    dt.put(tasks, st);
+    launch_diag(ds.p, (int)secs.size(), dt.p, st);
+    dev_sync(st);
+  }
+
+  // initial guess of the micro-iteration in step.in (section "The effective
+  // Hamiltonian equation": the current two-site object)
+  void build_guess() {
+    dev_zero(step.in.p, (size_t)std::max<int64_t>(step.n, 1) * 8, st);
+    const int i = step.i;
+    TripleList tl;
+    const int ns = (int)step.psi.sec.size();
+    std::vector<int> first(ns, -1);
+    if (cen.kind == C_TWO && cen.pos == i) {
+      std::vector<GatherDst> dsts;
+      std::vector<GatherSrc> srcs;
+      for (int m = 0; m < ns; ++m) {
+        const int j = cen.t.find(step.psi.sec[m]);
+        if (j < 0) continue;
+        if (cen.t.rows[j] != step.dx[m] || cen.t.cols[j] != step.dy[m]) fail(-1, "internal: centre shape mismatch");
+        srcs.push_back({cen.t.at(j), cen.t.cols[j], GS_NORMAL, 1.0});
+        dsts.push_back({step.in.p + step.off[m], step.dx[m], step.dy[m], step.dy[m], (int)srcs.size() - 1,
+                        (int)srcs.size()});
+      }
+      DArr<GatherDst> dd;
+      DArr<GatherSrc> ds;
+      dd.put(dsts, st);
+      ds.put(srcs, st);
+      launch_gather(dd.p, (int)dsts.size(), ds.p, st);
+      dev_sync(st);
+      return;
+    }
+    if (cen.kind == C_T0 && i == 0) {  // psi = T0 V[1]
+      for (int m = 0; m < ns; ++m) {
+        const int j = cen.t.find(step.psi.sec[m]);
+        const int v = V[1].find(step.psi.sec[m]);
+        if (j < 0 || v < 0) continue;
+        const int f = tl.add_block(step.in.p + step.off[m], step.dx[m], step.dy[m], step.dy[m]);
+        TTask t{};
+        t.a = cen.t.at(j);
+        t.lda = cen.t.cols[j];
+        t.K1 = cen.t.cols[j];
+        t.b = V[1].at(v);
+        t.ldb = V[1].cols[v];
+        t.flags = TT_IDENT_C;
+        t.coef = 1.0;
+        tl.add(f, step.dx[m], step.dy[m], t);
+      }
+    } else if (cen.kind == C_BOND_R && cen.pos == i) {
+      // C[a] rows of bond i, columns (n, b) of the right-enlarged basis at bond i
+      Enl Er = right_enl(P, i, dims[i + 1], nullptr);
+      for (size_t ja = 0; ja < cen.t.rowsec.sec.size(); ++ja) {
+        const Sec& a = cen.t.rowsec.sec[ja];
+        const int ea = Er.find(a);
+        if (ea < 0) continue;
+        const int ai = Lb[i]->basis.find(a);
+        for (auto& pc : Er.pieces[ea]) {
+          const Sec& b = dims[i + 1].sec[pc.sub];
+          const int m = step.psi.find(b);
+          const int v = V[i + 1].find(b);
+          if (m < 0 || v < 0 || ai < 0) continue;
+          int roff = -1;
+          for (auto& q : step.EX.pieces[m])
+            if (q.sub == ai && q.n == pc.n) roff = q.off;
+          if (roff < 0) continue;
+          if (first[m] < 0) first[m] = 0;
+          const double r = recouple_singlet(a.tj, LOC_TJ[pc.n], b.tj);
+          const int rows = cen.t.rows[ja];
+          const int f = tl.add_block(step.in.p + step.off[m] + (int64_t)roff * step.dy[m], rows, step.dy[m],
+                                     step.dy[m]);
+          TTask t{};
+          t.b = cen.t.at((int)ja) + pc.off;
+          t.ldb = cen.t.cols[ja];
+          t.K2 = dims[i + 1].dim[pc.sub];
+          t.c = V[i + 1].at(v);
+          t.ldc = V[i + 1].cols[v];
+          t.flags = TT_IDENT_A;
+          t.coef = r;
+          tl.add(f, rows, step.dy[m], t);
+        }
+      }
+    } else if (cen.kind == C_BOND_L && cen.pos == i + 2) {
+      // C[b] rows (a, n) of the left-enlarged basis at bond i+2, columns bond i+2
+      Enl El = left_enl(P, i + 2, dims[i + 1], nullptr);
+      for (size_t jb = 0; jb < cen.t.rowsec.sec.size(); ++jb) {
+        const Sec& b = cen.t.rowsec.sec[jb];
+        const int eb = El.find(b);
+        if (eb < 0) continue;
+        const int bi = Rb[i + 2]->basis.find(b);
+        for (auto& pc : El.pieces[eb]) {
+          const Sec& a = dims[i + 1].sec[pc.sub];
+          const int m = step.psi.find(a);
+          const int u = U[i].find(a);
+          if (m < 0 || u < 0 || bi < 0) continue;
+          int coff = -1;
+          for (auto& q : step.EY.pieces[m])
+            if (q.sub == bi && q.n == pc.n) coff = q.off;
+          if (coff < 0) continue;
+          const double r = recouple_singlet(a.tj, LOC_TJ[pc.n], b.tj);
+          const int cols = cen.t.cols[jb];
+          const int f = tl.add_block(step.in.p + step.off[m] + coff, step.dx[m], cols, step.dy[m]);
+          TTask t{};
+          t.a = U[i].at(u);
+          t.lda = U[i].cols[u];
+          t.K1 = U[i].cols[u];
+          t.b = cen.t.at((int)jb) + (int64_t)pc.off * cen.t.cols[jb];
+          t.ldb = cen.t.cols[jb];
+          t.flags = TT_IDENT_C;
+          t.coef = r;
+          tl.add(f, step.dx[m], cols, t);
+        }
+      }
+    } else {
+      fail(-1, "internal: no centre for this step");
+    }
+    DArr<TTile> dt;
+    DArr<TTask> dk;
+    tl.upload(dt, dk, st);
+    launch_triple(dt.p, (int)tl.tiles.size(), dk.p, st);
+    dev_sync(st);
+  }
+
+  // ---- sigma on the prepared step: step.out = H_eff step.in
+  void sigma_fixed() {
+    dev_zero(step.out.p, (size_t)std::max<int64_t>(step.n, 1) * 8, st);
+    void* e0 = dev_event_record(st);
+    launch_triple(step.tiles.p, step.ntiles, step.tasks.p, st);
+    void* e1 = dev_event_record(st);
+    t_sigma += dev_event_elapsed(e0, e1);
+    dev_event_free(e0);
+    dev_event_free(e1);
+    ++n_sigma;
+    f_sigma += step.flops;
+  }
+  void sigma_vec(const double* x, double* y) {
+    dev_d2d(step.in.p, x, (size_t)step.n * 8, st);
+    sigma_fixed();
+    dev_d2d(y, step.out.p, (size_t)step.n * 8, st);
+  }
+
+  // ---- Davidson (Davidson 1975; section "The effective Hamiltonian equation")
+  double davidson(double* xres, int* iters, bool* conv) {
+    const int64_t n = step.n;
+    const int ms = std::max(2, std::min(dav_max_sub, 64));
+    dV.ensure((size_t)ms * n);
+    dW.ensure((size_t)ms * n);
+    dHs.ensure((size_t)ms * ms);
+    dsmall.ensure(8 * 64 + 64 * 64);
+    dpartial.ensure(256 * 64);
+    dx_.ensure(n);
+    dax.ensure(n);
+    dr.ensure(n);
+    dt.ensure(n);
+    double* evals = dsmall.p;
+    double* evecs = dsmall.p + 64;
+    double* coef = dsmall.p + 64 + 64 * 64;
+    double* nrm = coef + 64;
+    double* nrm2 = nrm + 1;
+    // V0 = guess / |guess|
+    dev_d2d(dV.p, step.in.p, (size_t)n * 8, st);
+    launch_dots(dV.p, n, 1, dV.p, n, nrm, dpartial.p, st);
+    double h0;
+    dev_d2h(&h0, nrm, 8, st);
+    if (!(h0 > 0)) {  // zero guess: use a constant vector
+      std::vector<double> one(n, 1.0);
+      dev_h2d(dV.p, one.data(), (size_t)n * 8, st);
+      launch_dots(dV.p, n, 1, dV.p, n, nrm, dpartial.p, st);
+    }
+    launch_normalize(dV.p, nrm, n, st);
+    sigma_vec(dV.p, dW.p);
+    launch_dots(dV.p, n, 1, dW.p, n, dHs.p, dpartial.p, st);
+    int k = 1;  // vectors in the subspace
+    double theta = 0.0;
+    *conv = false;
+    int it = 0;
+    if (n == 1) {
+      dev_d2h(&theta, dHs.p, 8, st);
+      dev_d2d(xres, dV.p, 8, st);
+      *iters = 1;
+      *conv = true;
+      return theta;
+    }
+    for (it = 1; it <= dav_max_iter; ++it) {
+      launch_syev_small(dHs.p, k, ms, evals, evecs, st);
+      launch_combo_vec(dV.p, n, k, evecs, 1.0, n, dx_.p, 0.0, st);  // x = V s
+      launch_combo_vec(dW.p, n, k, evecs, 1.0, n, dax.p, 0.0, st);  // ax = W s
+      launch_residual(dax.p, dx_.p, evals, n, dr.p, st);
+      launch_dots(dr.p, n, 1, dr.p, n, nrm, dpartial.p, st);
+      double hv[2];
+      dev_d2h(hv, evals, 8, st);
+      dev_d2h(hv + 1, nrm, 8, st);
+      theta = hv[0];
+      if (std::sqrt(std::max(0.0, hv[1])) <= dav_tol) {
+        *conv = true;
+        break;
+      }
+      launch_precond(dr.p, step.diag.p, evals, n, dt.p, st);
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_dots(dV.p, n, k, dt.p, n, coef, dpartial.p, st);
+        launch_combo_vec(dV.p, n, k, coef, -1.0, n, dt.p, 1.0, st);
+      }
+      launch_dots(dt.p, n, 1, dt.p, n, nrm2, dpartial.p, st);
+      double tn;
+      dev_d2h(&tn, nrm2, 8, st);
+      if (!(tn > 1e-28)) {  // preconditioned residual collapsed: use the residual itself
+        dev_d2d(dt.p, dr.p, (size_t)n * 8, st);
+        for (int pass = 0; pass < 2; ++pass) {
+          launch_dots(dV.p, n, k, dt.p, n, coef, dpartial.p, st);
+          launch_combo_vec(dV.p, n, k, coef, -1.0, n, dt.p, 1.0, st);
+        }
+        launch_dots(dt.p, n, 1, dt.p, n, nrm2, dpartial.p, st);
+        dev_d2h(&tn, nrm2, 8, st);
+        if (!(tn > 1e-28)) {
+          *conv = true;
+          break;
+        }
+      }
+      launch_normalize(dt.p, nrm2, n, st);
+      if (k >= ms) {  // restart with the current Ritz vector
+        dev_d2d(dV.p, dx_.p, (size_t)n * 8, st);
+        dev_d2d(dW.p, dax.p, (size_t)n * 8, st);
+        launch_dots(dV.p, n, 1, dV.p, n, nrm, dpartial.p, st);
+        // x is unit (orthonormal basis, unit Ritz coefficients); W follows x
+        launch_dots(dV.p, n, 1, dW.p, n, dHs.p, dpartial.p, st);
+        k = 1;
+        launch_dots(dV.p, n, 1, dt.p, n, coef, dpartial.p, st);
+        launch_combo_vec(dV.p, n, 1, coef, -1.0, n, dt.p, 1.0, st);
+        launch_dots(dt.p, n, 1, dt.p, n, nrm2, dpartial.p, st);
+        launch_normalize(dt.p, nrm2, n, st);
+      }
+      dev_d2d(dV.p + (int64_t)k * n, dt.p, (size_t)n * 8, st);
+      sigma_vec(dV.p + (int64_t)k * n, dW.p + (int64_t)k * n);
+      // row k of Hs: V_j . W_k for j <= k (lower triangle)
+      launch_dots(dV.p, n, k + 1, dW.p + (int64_t)k * n, n, dHs.p + (int64_t)k * ms, dpartial.p, st);
+      ++k;
+    }
+    if (it > dav_max_iter) it = dav_max_iter;
+    // normalise the Ritz vector into xres
+    launch_dots(dx_.p, n, 1, dx_.p, n, nrm, dpartial.p, st);
+    dev_d2d(xres, dx_.p, (size_t)n * 8, st);
+    launch_normalize(xres, nrm, n, st);
+    dev_sync(st);
+    *iters = it;
+    return theta;
+  }
+
+  // ---- SVD and truncation (section "The reduced two-site object"): SVD per
+  // (j_M, N_M, I_M) sector, keep the D largest kappa = s / sqrt(2 j_M + 1).
+  struct Split {
+    Basis kept;
+    std::vector<int> ms;  // psi sector index of each kept sector
+    DBuf ubuf, sbuf, vbuf;
+    std::vector<int64_t> uo, so, vo;
+    std::vector<int> r;
+    double wd = 0.0;
+  };
+
+  void svd_truncate(const double* psi, int D, Split& sp) {
+    const int ns = (int)step.psi.sec.size();
+    sp.uo.resize(ns);
+    sp.so.resize(ns);
+    sp.vo.resize(ns);
+    sp.r.resize(ns);
+    int64_t nu = 0, nsv = 0, nv = 0, nw = 0;
+    int maxs = 1;
+    for (int m = 0; m < ns; ++m) {
+      const int r = std::min(step.dx[m], step.dy[m]);
+      sp.r[m] = r;
+      sp.uo[m] = nu;
+      nu += (int64_t)step.dx[m] * r;
+      sp.so[m] = nsv;
+      nsv += r;
+      sp.vo[m] = nv;
+      nv += (int64_t)r * step.dy[m];
+      nw += (int64_t)step.dx[m] * step.dy[m] + (int64_t)r * r + r;
+      maxs = std::max(maxs, r);
+    }
+    sp.ubuf.alloc((size_t)std::max<int64_t>(nu, 1));
+    sp.sbuf.alloc((size_t)std::max<int64_t>(nsv, 1));
+    sp.vbuf.alloc((size_t)std::max<int64_t>(nv, 1));
+    DBuf work;
+    work.alloc((size_t)std::max<int64_t>(nw, 1));
+    std::vector<SvdJob> jobs;
+    int64_t wo = 0;
+    for (int m = 0; m < ns; ++m) {
+      jobs.push_back({psi + step.off[m], step.dx[m], step.dy[m], step.dy[m], sp.ubuf.p + sp.uo[m],
+                      sp.sbuf.p + sp.so[m], sp.vbuf.p + sp.vo[m], work.p + wo});
+      wo += (int64_t)step.dx[m] * step.dy[m] + (int64_t)sp.r[m] * sp.r[m] + sp.r[m];
+    }
+    DArr<SvdJob> dj;
+    dj.put(jobs, st);
+    launch_svd(dj.p, (int)jobs.size(), maxs, st);
+    std::vector<double> s(nsv);
+    dev_d2h(s.data(), sp.sbuf.p, (size_t)nsv * 8, st);
+    struct Cand {
+      double kappa;
+      int m, a;
+    };
+    std::vector<Cand> cand;
+    double norm2 = 0.0;
+    for (int m = 0; m < ns; ++m)
+      for (int a = 0; a < sp.r[m]; ++a) {
+        const double v = s[sp.so[m] + a];
+        cand.push_back({v / std::sqrt(step.psi.sec[m].tj + 1.0), m, a});
+        norm2 += v * v;
+      }
+    std::stable_sort(cand.begin(), cand.end(), [](const Cand& x, const Cand& y) {
+      if (x.kappa != y.kappa) return x.kappa > y.kappa;
+      if (x.m != y.m) return x.m < y.m;
+      return x.a < y.a;
+    });
+    std::vector<int> kept(ns, 0);
+    double disc = 0.0;
+    for (size_t c = 0; c < cand.size(); ++c) {
+      if ((int)c < D)
+        kept[cand[c].m]++;
+      else
+        disc += s[sp.so[cand[c].m] + cand[c].a] * s[sp.so[cand[c].m] + cand[c].a];
+    }
+    sp.wd = disc / std::max(norm2, 1e-300);
+    sp.kept = Basis();
+    sp.ms.clear();
+    for (int m = 0; m < ns; ++m)
+      if (kept[m] > 0) {
+        sp.kept.sec.push_back(step.psi.sec[m]);
+        sp.kept.dim.push_back(kept[m]);
+        sp.ms.push_back(m);
+      }
+  }
+
+  // copy the leading (rows x cols) part of row-major matrices (ld) into a
+  // compact tensor, optionally scaling rows/cols by singular values
+  void compact(Tensor& t, const std::vector<const double*>& src, const std::vector<int>& ld) {
+    std::vector<GatherDst> dsts;
+    std::vector<GatherSrc> srcs;
+    for (size_t j = 0; j < src.size(); ++j) {
+      srcs.push_back({src[j], ld[j], GS_NORMAL, 1.0});
+      dsts.push_back({t.at((int)j), t.rows[j], t.cols[j], t.cols[j], (int)j, (int)j + 1});
+    }
+    DArr<GatherDst> dd;
+    DArr<GatherSrc> ds;
+    dd.put(dsts, st);
+    ds.put(srcs, st);
+    launch_gather(dd.p, (int)dsts.size(), ds.p, st);
+    dev_sync(st);
+  }
+
+  void alloc_tensor(Tensor& t) {
+    int64_t o = 0;
+    t.off.clear();
+    for (size_t j = 0; j < t.rows.size(); ++j) {
+      t.off.push_back(o);
+      o += (int64_t)t.rows[j] * t.cols[j];
+    }
+    t.data.alloc((size_t)std::max<int64_t>(o, 1));
+  }
+
+  // ---- one micro-iteration
+  double micro(int i, int D, bool right, bool do_svd) {
+    auto t0 = std::chrono::steady_clock::now();
+    prepare(i);
+    DBuf x;
+    x.alloc((size_t)std::max<int64_t>(step.n, 1));
+    int its = 0;
+    bool conv = false;
+    const double th = davidson(x.p, &its, &conv);
+    if (!conv) warned = true;
+    const double e = th + P.e_const;
+    emin = std::min(emin, e);
+    elast = e;
+    trace.push_back(e);
+    const int ns = (int)step.psi.sec.size();
+    if (!do_svd) {  // keep the optimised object as the guess of the next step
+      Tensor t;
+      t.rowsec = step.psi;
+      for (int m = 0; m < ns; ++m) {
+        t.rows.push_back(step.dx[m]);
+        t.cols.push_back(step.dy[m]);
+      }
+      alloc_tensor(t);
+      dev_d2d(t.data.p, x.p, (size_t)step.n * 8, st);
+      cen.kind = C_TWO;
+      cen.pos = i;
+      cen.t = std::move(t);
+      t_micro += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      return e;
+    }
+    Split sp;
+    svd_truncate(x.p, D, sp);
+    wdisc_sweep = std::max(wdisc_sweep, sp.wd);
+    const int c = i + 1;
+    const int nk = (int)sp.kept.sec.size();
+    if (right) {
+      Tensor u;  // U[i]: (dimX(m) x k_m)
+      u.rowsec = sp.kept;
+      std::vector<const double*> src;
+      std::vector<int> ld;
+      for (int j = 0; j < nk; ++j) {
+        const int m = sp.ms[j];
+        u.rows.push_back(step.dx[m]);
+        u.cols.push_back(sp.kept.dim[j]);
+        src.push_back(sp.ubuf.p + sp.uo[m]);
+        ld.push_back(sp.r[m]);
+      }
+      alloc_tensor(u);
+      compact(u, src, ld);
+      Tensor cc;  // centre on bond c: s Vt  (k_m x dimY(m))
+      cc.rowsec = sp.kept;
+      src.clear();
+      ld.clear();
+      for (int j = 0; j < nk; ++j) {
+        const int m = sp.ms[j];
+        cc.rows.push_back(sp.kept.dim[j]);
+        cc.cols.push_back(step.dy[m]);
+        src.push_back(sp.vbuf.p + sp.vo[m]);
+        ld.push_back(step.dy[m]);
+      }
+      alloc_tensor(cc);
+      compact(cc, src, ld);
+      for (int j = 0; j < nk; ++j)
+        launch_scale_rows(cc.at(j), cc.rows[j], cc.cols[j], cc.cols[j], sp.sbuf.p + sp.so[sp.ms[j]], st);
+      dims[c] = sp.kept;
+      U[i] = std::move(u);
+      Lb[c] = renormalize(*step.X, U[i], dims[c], true);
+      cen.kind = C_BOND_R;
+      cen.pos = c;
+      cen.t = std::move(cc);
+    } else {
+      Tensor v;  // V[i+1]: (k_m x dimY(m))
+      v.rowsec = sp.kept;
+      std::vector<const double*> src;
+      std::vector<int> ld;
+      for (int j = 0; j < nk; ++j) {
+        const int m = sp.ms[j];
+        v.rows.push_back(sp.kept.dim[j]);
+        v.cols.push_back(step.dy[m]);
+        src.push_back(sp.vbuf.p + sp.vo[m]);
+        ld.push_back(step.dy[m]);
+      }
+      alloc_tensor(v);
+      compact(v, src, ld);
+      Tensor cc;  // centre: U s (dimX(m) x k_m)
+      cc.rowsec = sp.kept;
+      src.clear();
+      ld.clear();
+      for (int j = 0; j < nk; ++j) {
+        const int m = sp.ms[j];
+        cc.rows.push_back(step.dx[m]);
+        cc.cols.push_back(sp.kept.dim[j]);
+        src.push_back(sp.ubuf.p + sp.uo[m]);
+        ld.push_back(sp.r[m]);
+      }
+      alloc_tensor(cc);
+      compact(cc, src, ld);
+      for (int j = 0; j < nk; ++j)
+        launch_scale_cols(cc.at(j), cc.rows[j], cc.cols[j], cc.cols[j], sp.sbuf.p + sp.so[sp.ms[j]], st);
+      dims[c] = sp.kept;
+      V[i + 1] = std::move(v);
+      Rb[c] = renormalize(*step.Y, V[i + 1], dims[c], false);
+      cen.kind = C_BOND_L;
+      cen.pos = c;
+      cen.t = std::move(cc);
+    }
+    dev_sync(st);
+    step.i = -1;  // blocks changed
+    t_micro += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return e;
+  }
+
+  double sweep(int D) {
+    if (!mps_ready) fail(-1, "call sadmrg_init_mps or sadmrg_mps_import first");
+    const int L = P.L;
+    double e = INFINITY;
+    wdisc_sweep = 0.0;
+    // a left-to-right pass needs the centre at step 0
+    if (!((cen.kind == C_T0 && cen.pos == 0) || (cen.kind == C_TWO && cen.pos == 0)))
+      fail(-1, "internal: sweep must start with the centre at the left end");
+    for (int i = 0; i <= L - 2; ++i) e = std::min(e, micro(i, D, true, i < L - 2));
+    for (int i = L - 2; i >= 0; --i) e = std::min(e, micro(i, D, false, i > 0));
+    wdisc = wdisc_sweep;
+    return e;
+  }
+};
+
+}  // namespace sadmrg
+
+// ===========================================================================
+// MPS exchange and the C ABI
+// ===========================================================================
+namespace sadmrg {
+
+static const int64_t MPS_MAGIC = 0x3154535053414453LL;
+
+struct Reader {
+  const char* p;
+  size_t n, o = 0;
+  int64_t i64() {
+    if (o + 8 > n) fail(-1, "MPS blob truncated");
+    int64_t v;
+    std::memcpy(&v, p + o, 8);
+    o += 8;
+    return v;
+  }
+  void dbl(double* d, size_t cnt) {
+    if (o + 8 * cnt > n) fail(-1, "MPS blob truncated");
+    std::memcpy(d, p + o, 8 * cnt);
+    o += 8 * cnt;
+  }
+};
+
+static void import_mps(Engine& E, const void* blob, size_t bytes) {
+  Problem& P = E.P;
+  E.check_target();
+  Reader r{(const char*)blob, bytes};
+  if (r.i64() != MPS_MAGIC) fail(-1, "MPS blob: bad magic");
+  const int64_t L = r.i64(), N = r.i64(), twoS = r.i64(), irrep = r.i64(), ci = r.i64();
+  if (L != P.L || N != P.N || twoS != P.twoS || irrep != P.irrep) fail(-1, "MPS blob does not match the problem");
+  if (ci < 0 || ci > L - 2) fail(-1, "MPS blob: bad centre");
+  E.build_caps();
+  E.dims.assign(P.L + 1, {});
+  for (int k = 0; k <= P.L; ++k) {
+    const int64_t ns = r.i64();
+    for (int64_t j = 0; j < ns; ++j) {
+      Sec s{(int)r.i64(), (int)r.i64(), (int)r.i64()};
+      const int64_t d = r.i64();
+      if (!E.dims[k].sec.empty() && !(E.dims[k].sec.back() < s)) fail(-1, "MPS blob: sectors not sorted");
+      E.dims[k].sec.push_back(s);
+      E.dims[k].dim.push_back((int)d);
+    }
+  }
+  E.U.clear();
+  E.U.resize(P.L);
+  E.V.clear();
+  E.V.resize(P.L);
+  std::vector<double> buf;
+  auto read_tensor = [&](Tensor& t) {
+    E.alloc_tensor(t);
+    int64_t tot = 0;
+    for (size_t j = 0; j < t.rows.size(); ++j) tot += (int64_t)t.rows[j] * t.cols[j];
+    buf.resize(tot);
+    r.dbl(buf.data(), tot);
+    dev_h2d(t.data.p, buf.data(), tot * 8, E.st);
+  };
+  for (int k = 0; k < ci; ++k) {
+    Enl El = left_enl(P, k + 1, E.dims[k], nullptr);
+    Tensor t;
+    t.rowsec = E.dims[k + 1];
+    for (size_t j = 0; j < E.dims[k + 1].sec.size(); ++j) {
+      const int e = El.find(E.dims[k + 1].sec[j]);
+      if (e < 0) fail(-1, "MPS blob: sector unreachable from the left");
+      t.rows.push_back(El.dim[e]);
+      t.cols.push_back(E.dims[k + 1].dim[j]);
+    }
+    read_tensor(t);
+    E.U[k] = std::move(t);
+  }
+  for (int k = (int)ci + 2; k < P.L; ++k) {
+    Enl Er = right_enl(P, k, E.dims[k + 1], nullptr);
+    Tensor t;
+    t.rowsec = E.dims[k];
+    for (size_t j = 0; j < E.dims[k].sec.size(); ++j) {
+      const int e = Er.find(E.dims[k].sec[j]);
+      if (e < 0) fail(-1, "MPS blob: sector unreachable from the right");
+      t.rows.push_back(E.dims[k].dim[j]);
+      t.cols.push_back(Er.dim[e]);
+    }
+    read_tensor(t);
+    E.V[k] = std::move(t);
+  }
+  {
+    Enl El = left_enl(P, (int)ci + 1, E.dims[ci], nullptr), Er = right_enl(P, (int)ci + 1, E.dims[ci + 2], nullptr);
+    Tensor t;
+    for (size_t m = 0; m < El.sec.size(); ++m) {
+      const int e = Er.find(El.sec[m]);
+      if (e < 0) continue;
+      t.rowsec.sec.push_back(El.sec[m]);
+      t.rowsec.dim.push_back(El.dim[m]);
+      t.rows.push_back(El.dim[m]);
+      t.cols.push_back(Er.dim[e]);
+    }
+    read_tensor(t);
+    E.cen.kind = C_TWO;
+    E.cen.pos = (int)ci;
+    E.cen.t = std::move(t);
+  }
+  if (r.o != r.n) fail(-1, "MPS blob: trailing bytes");
+  E.build_blocks_from_tensors((int)ci);
+  E.mps_ready = true;
+}
+
+static void export_mps(Engine& E, std::vector<char>& out) {
+  if (E.cen.kind != C_TWO) fail(-1, "export needs a two-site centre (call after a micro-iteration or import)");
+  const int ci = E.cen.pos;
+  auto put = [&](int64_t v) {
+    const char* b = (const char*)&v;
+    out.insert(out.end(), b, b + 8);
+  };
+  auto putT = [&](const Tensor& t) {
+    int64_t tot = 0;
+    for (size_t j = 0; j < t.rows.size(); ++j) tot += (int64_t)t.rows[j] * t.cols[j];
+    std::vector<double> h(tot);
+    dev_d2h(h.data(), t.data.p, tot * 8, E.st);
+    const char* b = (const char*)h.data();
+    out.insert(out.end(), b, b + tot * 8);
+  };
+  put(MPS_MAGIC);
+  put(E.P.L), put(E.P.N), put(E.P.twoS), put(E.P.irrep), put(ci);
+  for (int k = 0; k <= E.P.L; ++k) {
+    put((int64_t)E.dims[k].sec.size());
+    for (size_t j = 0; j < E.dims[k].sec.size(); ++j) {
+      put(E.dims[k].sec[j].N), put(E.dims[k].sec[j].tj), put(E.dims[k].sec[j].G), put(E.dims[k].dim[j]);
+    }
+  }
+  for (int k = 0; k < ci; ++k) putT(E.U[k]);
+  for (int k = ci + 2; k < E.P.L; ++k) putT(E.V[k]);
+  putT(E.cen.t);
+}
+
+}  // namespace sadmrg
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+#include "../../include/sadmrg.h"
+
+struct sadmrg_ctx {
+  sadmrg::Engine e;
+  std::string err;
+};
+
+using sadmrg::Failure;
+
+template <class F>
+static int guard(sadmrg_ctx* c, F&& f) {
+  if (!c) return SADMRG_EINVAL;
+  try {
+    c->err.clear();
+    return f();
+  } catch (const Failure& x) {
+    c->err = x.msg;
+    return x.code;
+  } catch (const std::bad_alloc&) {
+    c->err = "host allocation failed";
+    return SADMRG_ENOMEM;
+  } catch (const std::exception& x) {
+    c->err = x.what();
+    return SADMRG_EINVAL;
+  }
+}
+
+extern "C" {
+
+const char* sadmrg_version(void) { return "sadmrg 0.1 (gfx950, FP64)"; }
+
+int sadmrg_create(sadmrg_ctx** out, int L, int group_order, const int* orb_irrep, int device) {
+  if (!out) return SADMRG_EINVAL;
+  *out = nullptr;
+  if (L < 2 || L > 4096 || !orb_irrep) return SADMRG_EINVAL;
+  if (group_order != 1 && group_order != 2 && group_order != 4 && group_order != 8) return SADMRG_EINVAL;
+  for (int i = 0; i < L; ++i)
+    if (orb_irrep[i] < 0 || orb_irrep[i] >= group_order) return SADMRG_EINVAL;
+  auto* c = new (std::nothrow) sadmrg_ctx();
+  if (!c) return SADMRG_ENOMEM;
+  int rc = guard(c, [&] {
+    const int nd = sadmrg::dev_count();
+    if (nd <= 0) sadmrg::fail(SADMRG_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= nd) sadmrg::fail(SADMRG_EINVAL, "device index out of range");
+    sadmrg::dev_set_device(device);
+    c->e.device = device;
+    c->e.P.L = L;
+    c->e.P.order = group_order;
+    c->e.P.orb.assign(orb_irrep, orb_irrep + L);
+    return 0;
+  });
+  if (rc != 0) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return 0;
+}
+
+void sadmrg_destroy(sadmrg_ctx* ctx) {
+  if (!ctx) return;
+  try {
+    sadmrg::dev_sync(ctx->e.st);
+  } catch (...) {
+  }
+  delete ctx;
+}
+
+int sadmrg_set_stream(sadmrg_ctx* ctx, void* hip_stream) {
+  return guard(ctx, [&] {
+    ctx->e.st = hip_stream;
+    return 0;
+  });
+}
+
+int sadmrg_set_integrals(sadmrg_ctx* ctx, double e_const, const double* h, const double* eri, double sym_tol) {
+  return guard(ctx, [&] {
+    auto& P = ctx->e.P;
+    if (!h || !eri) sadmrg::fail(SADMRG_EINVAL, "null integrals");
+    const int L = P.L;
+    const size_t n4 = (size_t)L * L * L * L;
+    for (size_t i = 0; i < (size_t)L * L; ++i)
+      if (!std::isfinite(h[i])) sadmrg::fail(SADMRG_EINTEG, "h contains NaN/Inf");
+    for (size_t i = 0; i < n4; ++i)
+      if (!std::isfinite(eri[i])) sadmrg::fail(SADMRG_EINTEG, "eri contains NaN/Inf");
+    if (!std::isfinite(e_const)) sadmrg::fail(SADMRG_EINTEG, "E_const is not finite");
+    auto E4 = [&](int p, int q, int r, int s) { return eri[(((size_t)p * L + q) * L + r) * L + s]; };
+    for (int p = 0; p < L; ++p)
+      for (int q = 0; q < L; ++q) {
+        if (std::abs(h[p * L + q] - h[q * L + p]) > sym_tol) sadmrg::fail(SADMRG_EINTEG, "h is not symmetric");
+        if (P.orb[p] != P.orb[q] && std::abs(h[p * L + q]) > sym_tol)
+          sadmrg::fail(SADMRG_EINTEG, "h breaks the point-group symmetry");
+      }
+    for (int p = 0; p < L; ++p)
+      for (int q = 0; q < L; ++q)
+        for (int r = 0; r < L; ++r)
+          for (int s = 0; s < L; ++s) {
+            const double v = E4(p, q, r, s);
+            if (std::abs(v - E4(q, p, r, s)) > sym_tol || std::abs(v - E4(p, q, s, r)) > sym_tol ||
+                std::abs(v - E4(r, s, p, q)) > sym_tol)
+              sadmrg::fail(SADMRG_EINTEG, "eri lacks eightfold symmetry");
+            if ((P.orb[p] ^ P.orb[q] ^ P.orb[r] ^ P.orb[s]) != 0 && std::abs(v) > sym_tol)
+              sadmrg::fail(SADMRG_EINTEG, "eri breaks the point-group symmetry");
+          }
+    P.e_const = e_const;
+    P.h.assign(h, h + (size_t)L * L);
+    P.eri.assign(eri, eri + n4);
+    // symmetry-forbidden elements within tolerance are set to exact zeros
+    for (int p = 0; p < L; ++p)
+      for (int q = 0; q < L; ++q)
+        if (P.orb[p] != P.orb[q]) P.h[p * L + q] = 0.0;
+    for (int p = 0; p < L; ++p)
+      for (int q = 0; q < L; ++q)
+        for (int r = 0; r < L; ++r)
+          for (int s = 0; s < L; ++s)
+            if ((P.orb[p] ^ P.orb[q] ^ P.orb[r] ^ P.orb[s]) != 0) P.eri[(((size_t)p * L + q) * L + r) * L + s] = 0.0;
+    P.have_ints = true;
+    if (P.N >= 2) P.fold();
+    ctx->e.mps_ready = false;
+    return 0;
+  });
+}
+
+int sadmrg_set_target(sadmrg_ctx* ctx, int N, int twoS, int irrep) {
+  return guard(ctx, [&] {
+    auto& P = ctx->e.P;
+    if (N < 2 || N > 2 * P.L || twoS < 0 || twoS > N || ((N - twoS) & 1) || irrep < 0 || irrep >= P.order ||
+        twoS > 2 * P.L - N)
+      sadmrg::fail(SADMRG_ESYMM, "inconsistent (N, 2S, irrep)");
+    P.N = N;
+    P.twoS = twoS;
+    P.irrep = irrep;
+    if (P.have_ints) P.fold();
+    ctx->e.mps_ready = false;
+    return 0;
+  });
+}
+
+int sadmrg_set_davidson(sadmrg_ctx* ctx, double tol, int max_sub, int max_iter) {
+  return guard(ctx, [&] {
+    if (!(tol > 0) || max_sub < 2 || max_sub > 64 || max_iter < 1) sadmrg::fail(SADMRG_EINVAL, "bad Davidson settings");
+    ctx->e.dav_tol = tol;
+    ctx->e.dav_max_sub = max_sub;
+    ctx->e.dav_max_iter = max_iter;
+    return 0;
+  });
+}
+
+int sadmrg_set_seed(sadmrg_ctx* ctx, uint64_t seed) {
+  return guard(ctx, [&] {
+    ctx->e.seed = seed;
+    return 0;
+  });
+}
+
+int sadmrg_init_mps(sadmrg_ctx* ctx, int D) {
+  return guard(ctx, [&] {
+    ctx->e.init_mps(D);
+    return 0;
+  });
+}
+
+int sadmrg_sweep(sadmrg_ctx* ctx, int D, double* e_min) {
+  return guard(ctx, [&] {
+    if (D < 1) sadmrg::fail(SADMRG_EINVAL, "D must be positive");
+    ctx->e.warned = false;
+    const double e = ctx->e.sweep(D);
+    if (e_min) *e_min = e;
+    return ctx->e.warned ? SADMRG_WARN_NOT_CONVERGED : 0;
+  });
+}
+
+int sadmrg_solve(sadmrg_ctx* ctx, int n, const int* D, const double* e_conv, const int* max_sweeps,
+                 const double* noise, double* e_min) {
+  return guard(ctx, [&] {
+    if (n < 1 || !D || !e_conv || !max_sweeps) sadmrg::fail(SADMRG_EINVAL, "bad schedule");
+    for (int i = 0; i < n; ++i) {
+      if (D[i] < 1 || max_sweeps[i] < 1 || !(e_conv[i] >= 0)) sadmrg::fail(SADMRG_EINVAL, "bad schedule entry");
+      if (noise && noise[i] != 0.0) sadmrg::fail(SADMRG_EINVAL, "noise is not supported in this version");
+    }
+    auto& E = ctx->e;
+    if (!E.mps_ready) E.init_mps(D[0]);
+    E.warned = false;
+    double prev = INFINITY;
+    for (int i = 0; i < n; ++i)
+      for (int s = 0; s < max_sweeps[i]; ++s) {
+        const double e = E.sweep(D[i]);
+        const bool done = std::abs(e - prev) < e_conv[i];
+        prev = e;
+        if (done) break;
+      }
+    if (e_min) *e_min = E.emin;
+    return E.warned ? SADMRG_WARN_NOT_CONVERGED : 0;
+  });
+}
+
+int sadmrg_get_energy(sadmrg_ctx* ctx, double* e_min, double* e_last, double* wdisc_max) {
+  return guard(ctx, [&] {
+    if (e_min) *e_min = ctx->e.emin;
+    if (e_last) *e_last = ctx->e.elast;
+    if (wdisc_max) *wdisc_max = ctx->e.wdisc;
+    return 0;
+  });
+}
+
+int sadmrg_get_trace(sadmrg_ctx* ctx, double* out, int* n) {
+  return guard(ctx, [&] {
+    if (!n) sadmrg::fail(SADMRG_EINVAL, "null count");
+    const int have = (int)ctx->e.trace.size();
+    if (out) std::copy(ctx->e.trace.begin(), ctx->e.trace.begin() + std::min(have, *n), out);
+    *n = have;
+    return 0;
+  });
+}
+
+int sadmrg_mps_import(sadmrg_ctx* ctx, const void* blob, size_t bytes) {
+  return guard(ctx, [&] {
+    if (!blob) sadmrg::fail(SADMRG_EINVAL, "null blob");
+    sadmrg::import_mps(ctx->e, blob, bytes);
+    return 0;
+  });
+}
+
+int sadmrg_mps_export(sadmrg_ctx* ctx, void* blob, size_t* bytes) {
+  return guard(ctx, [&] {
+    if (!bytes) sadmrg::fail(SADMRG_EINVAL, "null size");
+    std::vector<char> out;
+    sadmrg::export_mps(ctx->e, out);
+    if (blob) {
+      if (*bytes < out.size()) sadmrg::fail(SADMRG_EINVAL, "export buffer too small");
+      std::memcpy(blob, out.data(), out.size());
+    }
+    *bytes = out.size();
+    return 0;
+  });
+}
+
+int sadmrg_prepare_step(sadmrg_ctx* ctx) {
+  return guard(ctx, [&] {
+    auto& E = ctx->e;
+    if (!E.mps_ready) sadmrg::fail(SADMRG_EINVAL, "no MPS");
+    int i;
+    switch (E.cen.kind) {
+      case sadmrg::C_TWO:
+      case sadmrg::C_T0:
+        i = E.cen.pos;
+        break;
+      case sadmrg::C_BOND_R:
+        i = E.cen.pos;
+        break;
+      case sadmrg::C_BOND_L:
+        i = E.cen.pos - 2;
+        break;
+      default:
+        sadmrg::fail(SADMRG_EINVAL, "no centre");
+    }
+    E.prepare(i);
+    return 0;
+  });
+}
+
+int sadmrg_psi_layout(sadmrg_ctx* ctx, int* nsec, int64_t* desc, int64_t* n) {
+  return guard(ctx, [&] {
+    auto& S = ctx->e.step;
+    if (S.i < 0 || !S.X) sadmrg::fail(SADMRG_EINVAL, "no prepared step");
+    if (nsec) *nsec = (int)S.psi.sec.size();
+    if (n) *n = S.n;
+    if (desc)
+      for (size_t m = 0; m < S.psi.sec.size(); ++m) {
+        int64_t* d = desc + 6 * m;
+        d[0] = S.psi.sec[m].N, d[1] = S.psi.sec[m].tj, d[2] = S.psi.sec[m].G;
+        d[3] = S.dx[m], d[4] = S.dy[m], d[5] = S.off[m];
+      }
+    return 0;
+  });
+}
+
+int sadmrg_sigma(sadmrg_ctx* ctx, const double* x, double* y, int on_device) {
+  return guard(ctx, [&] {
+    auto& E = ctx->e;
+    auto& S = E.step;
+    if (S.i < 0 || !S.X) sadmrg::fail(SADMRG_EINVAL, "no prepared step");
+    if (!x || !y) sadmrg::fail(SADMRG_EINVAL, "null vector");
+    if (on_device) {
+      E.sigma_vec(x, y);
+      sadmrg::dev_sync(E.st);
+    } else {
+      sadmrg::dev_h2d(S.in.p, x, (size_t)S.n * 8, E.st);
+      E.sigma_fixed();
+      sadmrg::dev_d2h(y, S.out.p, (size_t)S.n * 8, E.st);
+    }
+    return 0;
+  });
+}
+
+int sadmrg_heff_diagonal(sadmrg_ctx* ctx, double* d, int on_device) {
+  return guard(ctx, [&] {
+    auto& E = ctx->e;
+    auto& S = E.step;
+    if (S.i < 0 || !S.X) sadmrg::fail(SADMRG_EINVAL, "no prepared step");
+    if (on_device)
+      sadmrg::dev_d2d(d, S.diag.p, (size_t)S.n * 8, E.st);
+    else
+      sadmrg::dev_d2h(d, S.diag.p, (size_t)S.n * 8, E.st);
+    sadmrg::dev_sync(E.st);
+    return 0;
+  });
+}
+
+int sadmrg_sigma_counters(sadmrg_ctx* ctx, double* flops, double* bytes, int64_t* tasks) {
+  return guard(ctx, [&] {
+    auto& S = ctx->e.step;
+    if (S.i < 0 || !S.X) sadmrg::fail(SADMRG_EINVAL, "no prepared step");
+    if (flops) *flops = S.flops;
+    if (bytes) *bytes = S.bytes;
+    if (tasks) *tasks = S.ntasks;
+    return 0;
+  });
+}
+
+int sadmrg_stats(sadmrg_ctx* ctx, double* t_sigma, int64_t* n_sigma, double* t_micro, double* flops_sigma,
+                 double* t_blocking) {
+  return guard(ctx, [&] {
+    auto& E = ctx->e;
+    if (t_sigma) *t_sigma = E.t_sigma;
+    if (n_sigma) *n_sigma = E.n_sigma;
+    if (t_micro) *t_micro = E.t_micro;
+    if (flops_sigma) *flops_sigma = E.f_sigma;
+    if (t_blocking) *t_blocking = E.t_block;
+    return 0;
+  });
+}
+
+int sadmrg_stats_reset(sadmrg_ctx* ctx) {
+  return guard(ctx, [&] {
+    auto& E = ctx->e;
+    E.t_sigma = E.t_micro = E.f_sigma = E.t_block = 0;
+    E.n_sigma = 0;
+    return 0;
+  });
+}
+
+const char* sadmrg_last_error(const sadmrg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int sadmrg_debug_coupling(int which, const int* a, double* out) {
+  if (!a || !out) return SADMRG_EINVAL;
+  if (which == 0)
+    *out = sadmrg::coupling_product(a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7], a[8]);
+  else if (which == 1)
+    *out = sadmrg::coupling_same(a[0], a[1], a[2], a[3], a[4], a[5]);
+  else if (which == 2)
+    *out = sadmrg::sixj(a[0], a[1], a[2], a[3], a[4], a[5]);
+  else
+    return SADMRG_EINVAL;
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Device interface of libsadmrg: kernel launchers, the task records they
+// consume, and the device-memory calls.  The host engine talks to the GPU only
+// through this header.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+
+namespace sadmrg {
+
+using Stream = void*;  // hipStream_t
+
+// ---------------------------------------------------------------------------
+// Device memory (HIP runtime); failures throw through dev_fail().
+// ---------------------------------------------------------------------------
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+void dev_h2d(void* dst, const void* src, size_t bytes, Stream st);
+void dev_d2h(void* dst, const void* src, size_t bytes, Stream st);
+void dev_d2d(void* dst, const void* src, size_t bytes, Stream st);
+void dev_zero(void* p, size_t bytes, Stream st);  // fill kernel (no memset node)
+void dev_sync(Stream st);
+void dev_set_device(int device);
+int dev_count();
+// event timing: returns an opaque event handle recorded on st
+void* dev_event_record(Stream st);
+double dev_event_elapsed(void* a, void* b);  // seconds, synchronises b
+void dev_event_free(void* e);
+
+// ---------------------------------------------------------------------------
+// Block triple products:
+//   out[rows x cols] += coef * opA(A)[rows x K1] * B[K1 x K2] * opC(C)[K2 x cols]
+// opA / opC transpose when flagged; an identity A (or C) drops that factor.
+// `a` / `c` already point at the tile's first row / column; `out` at the
+// tile's (0,0) element.  Output tiles of one launch must not overlap.
+// ---------------------------------------------------------------------------
+enum : int { TT_TRANS_A = 1, TT_TRANS_C = 2, TT_IDENT_A = 4, TT_IDENT_C = 8 };
+
+struct TTile {
+  double* out;
+  int ld, rows, cols;
+  int t0, t1;  // task range
+};
+
+struct TTask {
+  const double* a;
+  const double* b;
+  const double* c;
+  int lda, ldb, ldc;
+  int K1, K2;
+  int flags;
+  double coef;
+};
+
+// dst[rows x cols] (leading dim ld) = sum_s scale_s * src_s, where src_s is a
+// (rows x cols) block, the transpose of a (cols x rows) block, or the identity.
+enum : int { GS_NORMAL = 0, GS_TRANS = 1, GS_IDENT = 2 };
+
+struct GatherDst {
+  double* dst;
+  int rows, cols, ld;
+  int s0, s1;
+};
+
+struct GatherSrc {
+  const double* src;
+  int ld;
+  int kind;
+  double scale;
+};
+
+// Linear combinations of operators sharing one element layout:
+//   out[e] = sum_entries coef * (adj ? fac[e] * in[perm[e]] : in[e]),  e < nnz
+struct ComboOut {
+  double* out;
+  int64_t nnz;
+  int i0, i1;         // input-entry range
+  const int* perm;    // adjoint element map of the layout (may be null)
+  const double* fac;  // adjoint factors of the layout (may be null)
+};
+struct ComboIn {
+  const double* in;
+  double coef;
+  int adj;
+};
+
+// Diagonal of the effective Hamiltonian: out[r*cols + c] = sum coef * x[r*sx] * y[c*sy]
+struct DiagTask {
+  const double* x;  // null = identity (value 1)
+  const double* y;
+  int sx, sy;
+  double coef;
+};
+struct DiagSec {
+  double* out;
+  int rows, cols;
+  int t0, t1;
+};
+
+// One-sided Jacobi SVD of a (rows x cols, leading dim lda) matrix:
+//   A = U diag(s) Vt,  r = min(rows, cols), s descending,
+//   U (rows x r, ld r) and Vt (r x cols, ld cols) orthonormal; columns of the
+//   long-side factor whose singular value vanishes are completed by
+//   Gram-Schmidt.  work needs rows*cols + r*r + r doubles.
+struct SvdJob {
+  const double* a;
+  int rows, cols, lda;
+  double* u;
+  double* s;
+  double* vt;
+  double* work;
+};
+
+void launch_triple(const TTile* tiles, int ntiles, const TTask* tasks, Stream st);
+void launch_gather(const GatherDst* dsts, int ndst, const GatherSrc* srcs, Stream st);
+void launch_combo(const ComboOut* outs, int nout, const ComboIn* ins, int64_t max_nnz, Stream st);
+void launch_diag(const DiagSec* secs, int nsec, const DiagTask* tasks, Stream st);
+void launch_svd(const SvdJob* jobs, int njobs, int max_short, Stream st);
+
+// Davidson helpers (device pointers; k <= 64)
+// out[j] = dot(V + j*ldv, x) for j < k; deterministic two-stage reduction (partial: 256*k doubles)
+void launch_dots(const double* V, int64_t ldv, int k, const double* x, int64_t n, double* out, double* partial,
+                 Stream st);
+// y = beta*y + alpha * sum_j coef[j] * V_j   (coef on device)
+void launch_combo_vec(const double* V, int64_t ldv, int k, const double* coef, double alpha, int64_t n, double* y,
+                      double beta, Stream st);
+// r = ax - theta[0] * x
+void launch_residual(const double* ax, const double* x, const double* theta, int64_t n, double* r, Stream st);
+// t = r / (theta[0] - diag), denominator guarded away from zero
+void launch_precond(const double* r, const double* diag, const double* theta, int64_t n, double* t, Stream st);
+// y *= 1 / sqrt(nrm2[0])
+void launch_normalize(double* y, const double* nrm2, int64_t n, Stream st);
+// eigen-decomposition of a symmetric k x k matrix given by its lower triangle
+// (leading dim ld), k <= 64: evals ascending, eigenvector j at evecs + j*k
+void launch_syev_small(const double* H, int k, int ld, double* evals, double* evecs, Stream st);
+// uniform [-1,1) numbers from the SplitMix64 counter generator
+void launch_fill_uniform(double* p, int64_t n, uint64_t seed, uint64_t stream, Stream st);
+// a[r][c] *= s[r]  /  a[r][c] *= s[c]
+void launch_scale_rows(double* a, int rows, int cols, int ld, const double* s, Stream st);
+void launch_scale_cols(double* a, int rows, int cols, int ld, const double* s, Stream st);
+
+}  // namespace sadmrg

@@ -1,0 +1,749 @@
+// HIP kernels for gfx950 (CDNA4, wave64).
+//
+// The hot contraction of the method -- the action of the effective two-site
+// Hamiltonian and the renormalisation of block operators (paper, section
+// "CheMPS2 library": the two OpenMP hot spots) -- is a sum of small
+// block triple products  coef * op(A) * B * op(C)  over symmetry-sector pairs.
+// triple_kernel evaluates a list of such products per output tile, staging
+// operands through LDS and accumulating in registers, so each output element
+// is written exactly once (no atomics; bitwise reproducible).
+#include "kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+
+namespace sadmrg {
+
+[[noreturn]] void dev_fail(const char* what);  // defined by the engine (throws)
+
+static void hip_ok(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    static thread_local char buf[512];
+    snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString(e));
+    dev_fail(buf);
+  }
+}
+
+static void check_launch(const char* what) { hip_ok(hipGetLastError(), what); }
+
+void* dev_alloc(size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    dev_fail("hipMalloc: out of device memory");
+  }
+  return p;
+}
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+void dev_h2d(void* dst, const void* src, size_t bytes, Stream st) {
+  // uploads happen between kernels, never inside the sigma loop: synchronise so
+  // that the host source may be released as soon as this returns
+  if (bytes) hip_ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, (hipStream_t)st), "hipMemcpyAsync H2D");
+  hip_ok(hipStreamSynchronize((hipStream_t)st), "hipStreamSynchronize");
+}
+void dev_d2h(void* dst, const void* src, size_t bytes, Stream st) {
+  if (bytes) hip_ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, (hipStream_t)st), "hipMemcpyAsync D2H");
+  hip_ok(hipStreamSynchronize((hipStream_t)st), "hipStreamSynchronize");
+}
+void dev_d2d(void* dst, const void* src, size_t bytes, Stream st) {
+  if (bytes) hip_ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)st), "hipMemcpyAsync D2D");
+}
+__global__ void zero_kernel(double* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+void dev_zero(void* p, size_t bytes, Stream st) {
+  const int64_t n = (int64_t)(bytes / 8);
+  if (n <= 0) return;
+  const int nb = (int)std::min<int64_t>(8192, (n + 255) / 256);
+  hipLaunchKernelGGL(zero_kernel, dim3(nb), dim3(256), 0, (hipStream_t)st, (double*)p, n);
+  check_launch("zero");
+}
+void dev_sync(Stream st) { hip_ok(hipStreamSynchronize((hipStream_t)st), "hipStreamSynchronize"); }
+void dev_set_device(int device) { hip_ok(hipSetDevice(device), "hipSetDevice"); }
+int dev_count() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+void* dev_event_record(Stream st) {
+  hipEvent_t e;
+  hip_ok(hipEventCreate(&e), "hipEventCreate");
+  hip_ok(hipEventRecord(e, (hipStream_t)st), "hipEventRecord");
+  return (void*)e;
+}
+double dev_event_elapsed(void* a, void* b) {
+  hip_ok(hipEventSynchronize((hipEvent_t)b), "hipEventSynchronize");
+  float ms = 0;
+  hip_ok(hipEventElapsedTime(&ms, (hipEvent_t)a, (hipEvent_t)b), "hipEventElapsedTime");
+  return ms * 1e-3;
+}
+void dev_event_free(void* e) {
+  if (e) (void)hipEventDestroy((hipEvent_t)e);
+}
+
+namespace {
+
+constexpr int TM = 64;   // output tile rows
+constexpr int TN = 64;   // output tile cols
+constexpr int TK = 32;   // inner chunk
+constexpr int NT = 256;  // threads per workgroup (16 x 16 grid, 4 x 4 outputs each)
+
+__device__ inline double ldA(const double* A, int lda, bool tr, int r, int k) {
+  return tr ? A[(int64_t)k * lda + r] : A[(int64_t)r * lda + k];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Block triple products.  One workgroup per output tile (<= 64 x 64).
+// For each task: T = opA(A)[rows x K1] * B[K1 x K2] is formed in 64 x 32
+// chunks of K2 in LDS, then acc += T_chunk * opC(C)[chunk x cols].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void triple_kernel(const TTile* __restrict__ tiles, const TTask* __restrict__ tasks) {
+  __shared__ double sA[TM][TK + 1];
+  __shared__ double sB[TK][TK + 1];
+  __shared__ double sT[TM][TK + 1];
+  __shared__ double sC[TK][TN + 1];
+
+  const TTile tile = tiles[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int ty = tid / 16, tx = tid % 16;  // output: rows ty*4..+3, cols tx*4..+3
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+
+  for (int t = tile.t0; t < tile.t1; ++t) {
+    const TTask tk = tasks[t];
+    const bool trA = tk.flags & TT_TRANS_A, trC = tk.flags & TT_TRANS_C;
+    const bool idA = tk.flags & TT_IDENT_A, idC = tk.flags & TT_IDENT_C;
+    const double* A = tk.a;
+    const double* B = tk.b;
+    const double* C = tk.c;
+    const double coef = tk.coef;
+
+    if (idC) {
+      // acc += coef * opA(A)[rows x K1] * B[K1 x cols]
+      for (int k0 = 0; k0 < tk.K1; k0 += TK) {
+        const int kc = min(TK, tk.K1 - k0);
+        for (int e = tid; e < TM * TK; e += NT) {
+          int r = e / TK, k = e % TK;
+          sA[r][k] = (r < tile.rows && k < kc) ? ldA(A, tk.lda, trA, r, k0 + k) : 0.0;
+        }
+        for (int e = tid; e < TK * TN; e += NT) {
+          int k = e / TN, c = e % TN;
+          sC[k][c] = (k < kc && c < tile.cols) ? B[(int64_t)(k0 + k) * tk.ldb + c] : 0.0;
+        }
+        __syncthreads();
+        for (int k = 0; k < kc; ++k) {
+          double a[4], b[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a[i] = coef * sA[ty * 4 + i][k];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[j] = sC[k][tx * 4 + j];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        }
+        __syncthreads();
+      }
+      continue;
+    }
+
+    for (int j0 = 0; j0 < tk.K2; j0 += TK) {
+      const int jc = min(TK, tk.K2 - j0);
+      // ---- T chunk = opA(A)[rows x K1] * B[K1 x jc]  (or B rows directly if A is identity)
+      if (idA) {
+        for (int e = tid; e < TM * TK; e += NT) {
+          int r = e / TK, j = e % TK;
+          sT[r][j] = (r < tile.rows && j < jc) ? B[(int64_t)r * tk.ldb + j0 + j] : 0.0;
+        }
+        __syncthreads();
+      } else {
+        // each thread owns 4 rows x 2 cols of the 64 x 32 chunk
+        const int r0 = (tid / 16) * 4, c0 = (tid % 16) * 2;
+        double tacc[4][2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tacc[i][0] = tacc[i][1] = 0.0;
+        for (int k0 = 0; k0 < tk.K1; k0 += TK) {
+          const int kc = min(TK, tk.K1 - k0);
+          for (int e = tid; e < TM * TK; e += NT) {
+            int r = e / TK, k = e % TK;
+            sA[r][k] = (r < tile.rows && k < kc) ? ldA(A, tk.lda, trA, r, k0 + k) : 0.0;
+          }
+          for (int e = tid; e < TK * TK; e += NT) {
+            int k = e / TK, j = e % TK;
+            sB[k][j] = (k < kc && j < jc) ? B[(int64_t)(k0 + k) * tk.ldb + j0 + j] : 0.0;
+          }
+          __syncthreads();
+          for (int k = 0; k < kc; ++k) {
+            double a[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = sA[r0 + i][k];
+            const double b0 = sB[k][c0], b1 = sB[k][c0 + 1];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              tacc[i][0] += a[i] * b0;
+              tacc[i][1] += a[i] * b1;
+            }
+          }
+          __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          sT[r0 + i][c0] = tacc[i][0];
+          sT[r0 + i][c0 + 1] = tacc[i][1];
+        }
+      }
+      // ---- C chunk = opC(C)[j0:j0+jc, 0:cols]
+      for (int e = tid; e < TK * TN; e += NT) {
+        int j = e / TN, c = e % TN;
+        double v = 0.0;
+        if (j < jc && c < tile.cols)
+          v = trC ? C[(int64_t)c * tk.ldc + j0 + j] : C[(int64_t)(j0 + j) * tk.ldc + c];
+        sC[j][c] = v;
+      }
+      __syncthreads();
+      for (int j = 0; j < jc; ++j) {
+        double a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = coef * sT[ty * 4 + i][j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[q] = sC[j][tx * 4 + q];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[i][q] += a[i] * b[q];
+      }
+      __syncthreads();
+    }
+  }
+  // write-back (each element owned by exactly one thread of one workgroup)
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = ty * 4 + i;
+    if (r >= tile.rows) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = tx * 4 + j;
+      if (c < tile.cols) tile.out[(int64_t)r * tile.ld + c] += acc[i][j];
+    }
+  }
+}
+
+void launch_triple(const TTile* tiles, int ntiles, const TTask* tasks, Stream st) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(triple_kernel, dim3(ntiles), dim3(NT), 0, (hipStream_t)st, tiles, tasks);
+  check_launch("triple");
+}
+
+// ---------------------------------------------------------------------------
+// Gather-accumulate of scaled (possibly transposed / identity) blocks.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gather_kernel(const GatherDst* __restrict__ dsts,
+                                                     const GatherSrc* __restrict__ srcs) {
+  const GatherDst d = dsts[blockIdx.x];
+  const int n = d.rows * d.cols;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int r = e / d.cols, c = e % d.cols;
+    double v = 0.0;
+    for (int s = d.s0; s < d.s1; ++s) {
+      const GatherSrc g = srcs[s];
+      if (g.kind == GS_NORMAL)
+        v += g.scale * g.src[(int64_t)r * g.ld + c];
+      else if (g.kind == GS_TRANS)
+        v += g.scale * g.src[(int64_t)c * g.ld + r];
+      else if (r == c)
+        v += g.scale;
+    }
+    d.dst[(int64_t)r * d.ld + c] = v;
+  }
+}
+
+void launch_gather(const GatherDst* dsts, int ndst, const GatherSrc* srcs, Stream st) {
+  if (ndst <= 0) return;
+  hipLaunchKernelGGL(gather_kernel, dim3(ndst), dim3(256), 0, (hipStream_t)st, dsts, srcs);
+  check_launch("gather");
+}
+
+// ---------------------------------------------------------------------------
+// Linear combinations of operators that share one element layout (the
+// integral-weighted complementary-operator sums).  Grid: (element chunks, outputs).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void combo_ops_kernel(const ComboOut* __restrict__ outs,
+                                                        const ComboIn* __restrict__ ins) {
+  const ComboOut o = outs[blockIdx.y];
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < o.nnz; e += (int64_t)gridDim.x * 256) {
+    double v = 0.0;
+    for (int i = o.i0; i < o.i1; ++i) {
+      const ComboIn c = ins[i];
+      v += c.adj ? c.coef * o.fac[e] * c.in[o.perm[e]] : c.coef * c.in[e];
+    }
+    o.out[e] = v;
+  }
+}
+
+void launch_combo(const ComboOut* outs, int nout, const ComboIn* ins, int64_t max_nnz, Stream st) {
+  if (nout <= 0 || max_nnz <= 0) return;
+  const int nb = (int)std::min<int64_t>(1024, (max_nnz + 255) / 256);
+  for (int o0 = 0; o0 < nout; o0 += 65535) {
+    const int cnt = std::min(65535, nout - o0);
+    hipLaunchKernelGGL(combo_ops_kernel, dim3(nb, cnt), dim3(256), 0, (hipStream_t)st, outs + o0, ins);
+  }
+  check_launch("combo");
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal of H_eff.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void diag_kernel(const DiagSec* __restrict__ secs,
+                                                   const DiagTask* __restrict__ tasks) {
+  const DiagSec s = secs[blockIdx.x];
+  const int n = s.rows * s.cols;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int r = e / s.cols, c = e % s.cols;
+    double v = 0.0;
+    for (int t = s.t0; t < s.t1; ++t) {
+      const DiagTask d = tasks[t];
+      const double xv = d.x ? d.x[(int64_t)r * d.sx] : 1.0;
+      const double yv = d.y ? d.y[(int64_t)c * d.sy] : 1.0;
+      v += d.coef * xv * yv;
+    }
+    s.out[e] = v;
+  }
+}
+
+void launch_diag(const DiagSec* secs, int nsec, const DiagTask* tasks, Stream st) {
+  if (nsec <= 0) return;
+  hipLaunchKernelGGL(diag_kernel, dim3(nsec), dim3(256), 0, (hipStream_t)st, secs, tasks);
+  check_launch("diag");
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level helpers
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi SVD, one workgroup per sector matrix.
+// Works on the tall orientation M (m x n, m >= n): columns are rotated until
+// mutually orthogonal; M V = U S.  Column pairs are visited in round-robin
+// (tournament) order, so n/2 disjoint pairs are processed concurrently, one
+// pair per wavefront at a time.
+// ---------------------------------------------------------------------------
+constexpr int SVD_WAVES = 8;
+
+__global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __restrict__ jobs) {
+  const SvdJob jb = jobs[blockIdx.x];
+  const bool tall = jb.rows >= jb.cols;
+  const int m = tall ? jb.rows : jb.cols;  // long side
+  const int n = tall ? jb.cols : jb.rows;  // short side (number of singular values)
+  double* M = jb.work;                     // m x n, column j contiguous: M[j*m + i]
+  double* V = M + (int64_t)m * n;          // n x n, column j contiguous
+  double* nrm = V + (int64_t)n * n;        // n
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int nth = blockDim.x;
+  const double* A = jb.a;
+  // load (column-major working copy of the tall orientation)
+  for (int e = tid; e < m * n; e += nth) {
+    const int j = e / m, i = e % m;  // column j, row i of the tall matrix
+    M[e] = tall ? A[(int64_t)i * jb.lda + j] : A[(int64_t)j * jb.lda + i];
+  }
+  for (int e = tid; e < n * n; e += nth) V[e] = (e / n == e % n) ? 1.0 : 0.0;
+  __syncthreads();
+
+  __shared__ int s_rot;
+  const int np = (n % 2) ? n + 1 : n;  // tournament with a dummy when n is odd
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int round = 0; round < np - 1; ++round) {
+      // pairs (p, q) of the round-robin schedule: position 0 fixed, others rotate
+      for (int pr = wv; pr < np / 2; pr += SVD_WAVES) {
+        // circle method: slot 0 fixed, slots 1..np-1 rotate; pair (slot pr, slot np-1-pr)
+        const int a = (pr == 0) ? 0 : ((pr - 1 + round) % (np - 1)) + 1;
+        const int b = ((np - 2 - pr + round) % (np - 1)) + 1;
+        const int p = min(a, b), q = max(a, b);
+        if (q >= n || p == q) continue;
+        double* mp = M + (int64_t)p * m;
+        double* mq = M + (int64_t)q * m;
+        double al = 0, be = 0, ga = 0;
+        for (int i = lane; i < m; i += 64) {
+          const double x = mp[i], y = mq[i];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (fabs(ga) <= 1e-15 * sqrt(al * be) || ga == 0.0) continue;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+        for (int i = lane; i < m; i += 64) {
+          const double x = mp[i], y = mq[i];
+          mp[i] = cs * x - sn * y;
+          mq[i] = sn * x + cs * y;
+        }
+        double* vp = V + (int64_t)p * n;
+        double* vq = V + (int64_t)q * n;
+        for (int i = lane; i < n; i += 64) {
+          const double x = vp[i], y = vq[i];
+          vp[i] = cs * x - sn * y;
+          vq[i] = sn * x + cs * y;
+        }
+        if (lane == 0) s_rot = 1;
+      }
+      __syncthreads();
+    }
+    if (s_rot == 0) break;
+    __syncthreads();
+  }
+  // column norms
+  for (int j = wv; j < n; j += SVD_WAVES) {
+    double s = 0;
+    for (int i = lane; i < m; i += 64) s += M[(int64_t)j * m + i] * M[(int64_t)j * m + i];
+    s = wave_sum(s);
+    if (lane == 0) nrm[j] = sqrt(s);
+  }
+  __syncthreads();
+  // sort order (descending), stable: rank of column j
+  __shared__ int s_ord[1024];
+  for (int j = tid; j < n; j += nth) {
+    int rank = 0;
+    for (int i = 0; i < n; ++i) rank += (nrm[i] > nrm[j]) || (nrm[i] == nrm[j] && i < j);
+    s_ord[rank] = j;
+  }
+  __syncthreads();
+  // outputs: long-side factor columns L_k = M_col / s (m x n), short-side V (n x n)
+  // tall:  A = L S V^T  -> U = L (rows x r), Vt = V^T (r x cols)
+  // wide:  A^T = L S V^T -> A = V S L^T -> U = V (rows x r), Vt = L^T (r x cols)
+  double* U = jb.u;
+  double* S = jb.s;
+  double* VT = jb.vt;
+  const double smax = nrm[s_ord[0]];
+  for (int k = tid; k < n; k += nth) S[k] = nrm[s_ord[k]];
+  // long-side factor, with Gram-Schmidt completion of vanishing columns (serial, rare)
+  for (int k = 0; k < n; ++k) {
+    const int j = s_ord[k];
+    const double s = nrm[j];
+    const bool tiny = !(s > 1e-13 * smax) || s == 0.0;
+    // destination column k of the long-side factor
+    auto put = [&](int i, double v) {
+      if (tall)
+        U[(int64_t)i * n + k] = v;
+      else
+        VT[(int64_t)k * jb.cols + i] = v;
+    };
+    auto get = [&](int i, int kk) -> double { return tall ? U[(int64_t)i * n + kk] : VT[(int64_t)kk * jb.cols + i]; };
+    if (!tiny) {
+      for (int i = tid; i < m; i += nth) put(i, M[(int64_t)j * m + i] / s);
+      __syncthreads();
+      continue;
+    }
+    // completion: try unit vectors e_t until one survives orthogonalisation
+    for (int tt = 0; tt < m; ++tt) {
+      for (int i = tid; i < m; i += nth) put(i, i == tt ? 1.0 : 0.0);
+      __syncthreads();
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int kk = 0; kk < k; ++kk) {
+          __shared__ double s_red[SVD_WAVES];
+          double d = 0;
+          for (int i = tid; i < m; i += nth) d += get(i, kk) * get(i, k);
+          d = wave_sum(d);
+          if (lane == 0) s_red[wv] = d;
+          __syncthreads();
+          double dd = 0;
+          for (int w = 0; w < SVD_WAVES; ++w) dd += s_red[w];
+          for (int i = tid; i < m; i += nth) put(i, get(i, k) - dd * get(i, kk));
+          __syncthreads();
+        }
+      }
+      __shared__ double s_red2[SVD_WAVES];
+      double d = 0;
+      for (int i = tid; i < m; i += nth) d += get(i, k) * get(i, k);
+      d = wave_sum(d);
+      if (lane == 0) s_red2[wv] = d;
+      __syncthreads();
+      double nn = 0;
+      for (int w = 0; w < SVD_WAVES; ++w) nn += s_red2[w];
+      __syncthreads();
+      if (nn > 0.25) {
+        const double inv = 1.0 / sqrt(nn);
+        for (int i = tid; i < m; i += nth) put(i, get(i, k) * inv);
+        __syncthreads();
+        break;
+      }
+    }
+  }
+  // short-side factor
+  for (int e = tid; e < n * n; e += nth) {
+    const int k = e / n, i = e % n;  // column k (sorted) of V, row i
+    const double v = V[(int64_t)s_ord[k] * n + i];
+    if (tall)
+      VT[(int64_t)k * jb.cols + i] = v;  // Vt[k][i]
+    else
+      U[(int64_t)i * n + k] = v;  // U[i][k]
+  }
+}
+
+void launch_svd(const SvdJob* jobs, int njobs, int max_short, Stream st) {
+  if (njobs <= 0) return;
+  if (max_short > 1024) dev_fail("svd: sector matrix too large (short side > 1024)");
+  hipLaunchKernelGGL(svd_kernel, dim3(njobs), dim3(64 * SVD_WAVES), 0, (hipStream_t)st, jobs);
+  check_launch("svd");
+}
+
+// ---------------------------------------------------------------------------
+// Davidson vector kernels
+// ---------------------------------------------------------------------------
+constexpr int RB = 256;
+constexpr int RCH = 256;  // partial-sum chunks per vector
+
+__global__ __launch_bounds__(RB) void dots_stage1(const double* __restrict__ V, int64_t ldv,
+                                                  const double* __restrict__ x, int64_t n,
+                                                  double* __restrict__ partial) {
+  const int j = blockIdx.y;
+  const int64_t chunk = (n + RCH - 1) / RCH;
+  const int64_t b = blockIdx.x * chunk, e = min(n, b + chunk);
+  const double* v = V + j * ldv;
+  double s = 0;
+  for (int64_t i = b + threadIdx.x; i < e; i += RB) s += v[i] * x[i];
+  __shared__ double red[RB / 64];
+  s = wave_sum(s);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < RB / 64; ++w) t += red[w];
+    partial[(int64_t)j * RCH + blockIdx.x] = t;
+  }
+}
+
+__global__ void dots_stage2(const double* __restrict__ partial, int k, double* __restrict__ out) {
+  const int j = blockIdx.x;
+  double s = 0;
+  for (int i = threadIdx.x; i < RCH; i += 64) s += partial[(int64_t)j * RCH + i];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+void launch_dots(const double* V, int64_t ldv, int k, const double* x, int64_t n, double* out, double* partial,
+                 Stream st) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(dots_stage1, dim3(RCH, k), dim3(RB), 0, (hipStream_t)st, V, ldv, x, n, partial);
+  hipLaunchKernelGGL(dots_stage2, dim3(k), dim3(64), 0, (hipStream_t)st, partial, k, out);
+}
+
+__global__ void combo_kernel(const double* __restrict__ V, int64_t ldv, int k, const double* __restrict__ coef,
+                             double alpha, int64_t n, double* __restrict__ y, double beta) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0;
+    for (int j = 0; j < k; ++j) s += coef[j] * V[j * ldv + i];
+    y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + alpha * s;
+  }
+}
+
+void launch_combo_vec(const double* V, int64_t ldv, int k, const double* coef, double alpha, int64_t n, double* y,
+                      double beta, Stream st) {
+  int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(combo_kernel, dim3(nb), dim3(256), 0, (hipStream_t)st, V, ldv, k, coef, alpha, n, y, beta);
+}
+
+__global__ void residual_kernel(const double* ax, const double* x, const double* theta, int64_t n, double* r) {
+  const double th = theta[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = ax[i] - th * x[i];
+}
+
+void launch_residual(const double* ax, const double* x, const double* theta, int64_t n, double* r, Stream st) {
+  int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(256), 0, (hipStream_t)st, ax, x, theta, n, r);
+}
+
+__global__ void precond_kernel(const double* r, const double* diag, const double* theta, int64_t n, double* t) {
+  const double th = theta[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double d = th - diag[i];
+    if (fabs(d) < 1e-12) d = d < 0 ? -1e-12 : 1e-12;
+    t[i] = r[i] / d;
+  }
+}
+
+void launch_precond(const double* r, const double* diag, const double* theta, int64_t n, double* t, Stream st) {
+  int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(precond_kernel, dim3(nb), dim3(256), 0, (hipStream_t)st, r, diag, theta, n, t);
+}
+
+__global__ void normalize_kernel(double* y, const double* nrm2, int64_t n) {
+  const double f = 1.0 / sqrt(nrm2[0]);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] *= f;
+}
+
+void launch_normalize(double* y, const double* nrm2, int64_t n, Stream st) {
+  int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(normalize_kernel, dim3(nb), dim3(256), 0, (hipStream_t)st, y, nrm2, n);
+}
+
+// Cyclic Jacobi eigen-decomposition of a small symmetric matrix, one wavefront.
+// Round-robin ordering: k/2 disjoint rotations per round.
+constexpr int SYEV_MAX = 64;
+
+__global__ __launch_bounds__(64) void syev_kernel(const double* __restrict__ H, int k, int ld,
+                                                  double* __restrict__ evals, double* __restrict__ evecs) {
+  __shared__ double a[SYEV_MAX][SYEV_MAX + 1];
+  __shared__ double v[SYEV_MAX][SYEV_MAX + 1];
+  __shared__ double rc[SYEV_MAX / 2], rs[SYEV_MAX / 2];
+  __shared__ int rp[SYEV_MAX / 2], rq[SYEV_MAX / 2];
+  __shared__ int s_any;
+  const int lane = threadIdx.x;
+  for (int e = lane; e < k * k; e += 64) {
+    const int i = e / k, j = e % k;
+    a[i][j] = (i >= j) ? H[i * ld + j] : H[j * ld + i];  // lower triangle is authoritative
+    v[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int np = (k % 2) ? k + 1 : k;
+  for (int sweep = 0; sweep < 100 && k > 1; ++sweep) {
+    if (lane == 0) s_any = 0;
+    __syncthreads();
+    for (int round = 0; round < np - 1; ++round) {
+      if (lane < np / 2) {
+        const int pr = lane;
+        const int x = (pr == 0) ? 0 : ((pr - 1 + round) % (np - 1)) + 1;
+        const int y = ((np - 2 - pr + round) % (np - 1)) + 1;
+        int p = min(x, y), q = max(x, y);
+        double c = 1.0, s = 0.0;
+        if (q < k && p != q) {
+          const double apq = a[p][q];
+          if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * sqrt(fabs(a[p][p] * a[q][q]) + 1e-300)) {
+            const double th = (a[q][q] - a[p][p]) / (2.0 * apq);
+            const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+            s_any = 1;
+          }
+        } else {
+          p = q = -1;
+        }
+        rp[pr] = p;
+        rq[pr] = q;
+        rc[pr] = c;
+        rs[pr] = s;
+      }
+      __syncthreads();
+      // rows: a <- J^T a
+      for (int e = lane; e < (np / 2) * k; e += 64) {
+        const int pr = e / k, j = e % k;
+        const int p = rp[pr], q = rq[pr];
+        if (p < 0) continue;
+        const double c = rc[pr], s = rs[pr];
+        const double x = a[p][j], y = a[q][j];
+        a[p][j] = c * x - s * y;
+        a[q][j] = s * x + c * y;
+      }
+      __syncthreads();
+      // cols: a <- a J ; v <- v J
+      for (int e = lane; e < (np / 2) * k; e += 64) {
+        const int pr = e / k, i = e % k;
+        const int p = rp[pr], q = rq[pr];
+        if (p < 0) continue;
+        const double c = rc[pr], s = rs[pr];
+        const double x = a[i][p], y = a[i][q];
+        a[i][p] = c * x - s * y;
+        a[i][q] = s * x + c * y;
+        const double vx = v[i][p], vy = v[i][q];
+        v[i][p] = c * vx - s * vy;
+        v[i][q] = s * vx + c * vy;
+      }
+      __syncthreads();
+    }
+    if (s_any == 0) break;
+    __syncthreads();
+  }
+  // sort ascending (selection by rank)
+  __shared__ int ord[SYEV_MAX];
+  for (int j = lane; j < k; j += 64) {
+    int rank = 0;
+    for (int i = 0; i < k; ++i) rank += (a[i][i] < a[j][j]) || (a[i][i] == a[j][j] && i < j);
+    ord[rank] = j;
+  }
+  __syncthreads();
+  for (int j = lane; j < k; j += 64) evals[j] = a[ord[j]][ord[j]];
+  for (int e = lane; e < k * k; e += 64) {
+    const int j = e / k, i = e % k;
+    evecs[j * k + i] = v[i][ord[j]];  // eigenvector j contiguous
+  }
+}
+
+void launch_syev_small(const double* H, int k, int ld, double* evals, double* evecs, Stream st) {
+  hipLaunchKernelGGL(syev_kernel, dim3(1), dim3(64), 0, (hipStream_t)st, H, k, ld, evals, evecs);
+}
+
+// SplitMix64 finaliser (Steele, Lea & Flood, OOPSLA 2014).
+__device__ inline uint64_t sm64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void fill_uniform_kernel(double* p, int64_t n, uint64_t seed, uint64_t stream) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = sm64(seed ^ sm64(stream * 0x100000001B3ull + (uint64_t)i));
+    p[i] = (double)(k >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+  }
+}
+
+void launch_fill_uniform(double* p, int64_t n, uint64_t seed, uint64_t stream, Stream st) {
+  if (n <= 0) return;
+  int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  hipLaunchKernelGGL(fill_uniform_kernel, dim3(nb), dim3(256), 0, (hipStream_t)st, p, n, seed, stream);
+}
+
+__global__ void scale_rows_kernel(double* a, int rows, int cols, int ld, const double* s) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rows * cols; e += gridDim.x * blockDim.x) {
+    const int r = e / cols, c = e % cols;
+    a[(int64_t)r * ld + c] *= s[r];
+  }
+}
+__global__ void scale_cols_kernel(double* a, int rows, int cols, int ld, const double* s) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rows * cols; e += gridDim.x * blockDim.x) {
+    const int r = e / cols, c = e % cols;
+    a[(int64_t)r * ld + c] *= s[c];
+  }
+}
+
+void launch_scale_rows(double* a, int rows, int cols, int ld, const double* s, Stream st) {
+  if (rows * cols <= 0) return;
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(std::min(1024, (rows * cols + 255) / 256)), dim3(256), 0, (hipStream_t)st, a, rows,
+                     cols, ld, s);
+}
+void launch_scale_cols(double* a, int rows, int cols, int ld, const double* s, Stream st) {
+  if (rows * cols <= 0) return;
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(std::min(1024, (rows * cols + 255) / 256)), dim3(256), 0, (hipStream_t)st, a, rows,
+                     cols, ld, s);
+}
+
+}  // namespace sadmrg
