@@ -992,6 +992,7 @@ struct TripleList {
   struct T {
     int tile;
     TTask t;
+    double w;  // flops of this tile task
   };
   std::vector<TTile> tiles;
   std::vector<T> tasks;
@@ -1001,7 +1002,7 @@ struct TripleList {
     const int first = (int)tiles.size();
     for (int r0 = 0; r0 < rows; r0 += 64)
       for (int c0 = 0; c0 < cols; c0 += 64)
-        tiles.push_back({out + (int64_t)r0 * ld + c0, ld, std::min(64, rows - r0), std::min(64, cols - c0), 0, 0});
+        tiles.push_back({out + (int64_t)r0 * ld + c0, nullptr, ld, std::min(64, rows - r0), std::min(64, cols - c0), 0, 0});
     return first;
   }
   // out block (registered at `first` with `cols` columns) += coef*opA(A)*B*opC(C)
@@ -1017,6 +1018,14 @@ struct TripleList {
     for (int r0 = 0, tr = 0; r0 < rows; r0 += 64, ++tr)
       for (int c0 = 0, tc = 0; c0 < cols; c0 += 64, ++tc) {
         TTask t = base;
+        const int tr_ = std::min(64, rows - r0), tc_ = std::min(64, cols - c0);
+        double w;
+        if (t.flags & TT_IDENT_C)
+          w = 2.0 * tr_ * K1 * tc_;
+        else if (t.flags & TT_IDENT_A)
+          w = 2.0 * tr_ * K2 * tc_;
+        else
+          w = 2.0 * tr_ * K1 * K2 + 2.0 * tr_ * K2 * tc_;
         if (t.flags & TT_IDENT_A)
           t.b += (int64_t)r0 * t.ldb;
         else if (t.flags & TT_TRANS_A)
@@ -1029,23 +1038,90 @@ struct TripleList {
           t.c += (int64_t)c0 * t.ldc;
         else
           t.c += c0;
-        tasks.push_back({first + tr * ntc + tc, t});
+        tasks.push_back({first + tr * ntc + tc, t, w});
       }
   }
-  // group by tile and upload
-  void upload(DArr<TTile>& dt, DArr<TTask>& dk, Stream st) {
+  // Group tasks by tile and split every tile's list into chunks of about
+  // `target` flops that run on separate workgroups; chunks of a tile write
+  // partial tiles that a second kernel adds in chunk order (deterministic).
+  struct Plan {
+    DArr<TTile> chunks;
+    DArr<TTask> tasks;
+    DArr<RTile> reds;
+    DBuf part;
+    int nchunks = 0, nreds = 0;
+    void run(Stream st) const {
+      launch_triple(chunks.p, nchunks, tasks.p, st);
+      launch_reduce(reds.p, nreds, st);
+    }
+  };
+  void plan(Plan& pl, Stream st, double target = 0.0) {
     std::vector<int> cnt(tiles.size() + 1, 0);
     for (auto& t : tasks) cnt[t.tile + 1]++;
     for (size_t i = 0; i < tiles.size(); ++i) cnt[i + 1] += cnt[i];
     std::vector<TTask> flat(tasks.size());
+    std::vector<double> wt(tasks.size());
     std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-    for (auto& t : tasks) flat[pos[t.tile]++] = t.t;
-    for (size_t i = 0; i < tiles.size(); ++i) {
-      tiles[i].t0 = cnt[i];
-      tiles[i].t1 = cnt[i + 1];
+    for (auto& t : tasks) {
+      wt[pos[t.tile]] = t.w;
+      flat[pos[t.tile]++] = t.t;
     }
-    dt.put(tiles, st);
-    dk.put(flat, st);
+    double total = 0.0;
+    for (double w : wt) total += w;
+    if (target <= 0.0) target = std::max(2.0e4, total / 16384.0);
+    std::vector<TTile> chunks;
+    std::vector<int64_t> poff;  // partial-buffer offset per chunk (-1: direct write)
+    struct PR {
+      size_t tile;
+      int first, n;
+    };
+    std::vector<PR> pr;
+    int64_t npart = 0;
+    for (size_t i = 0; i < tiles.size(); ++i) {
+      const int a = cnt[i], b = cnt[i + 1];
+      if (a == b) continue;
+      std::vector<std::pair<int, int>> rng;
+      double w = 0.0;
+      int s = a;
+      for (int t = a; t < b; ++t) {
+        w += wt[t];
+        if (w >= target && t + 1 < b) {
+          rng.push_back({s, t + 1});
+          s = t + 1;
+          w = 0.0;
+        }
+      }
+      rng.push_back({s, b});
+      if (rng.size() == 1) {
+        TTile c = tiles[i];
+        c.t0 = a;
+        c.t1 = b;
+        chunks.push_back(c);
+        poff.push_back(-1);
+        continue;
+      }
+      pr.push_back({i, (int)chunks.size(), (int)rng.size()});
+      for (auto& [x, y] : rng) {
+        TTile c = tiles[i];
+        c.t0 = x;
+        c.t1 = y;
+        chunks.push_back(c);
+        poff.push_back(npart);
+        npart += (int64_t)c.rows * c.cols;
+      }
+    }
+    pl.part.alloc((size_t)std::max<int64_t>(npart, 1));
+    std::vector<RTile> reds;
+    for (size_t j = 0; j < chunks.size(); ++j) chunks[j].part = poff[j] >= 0 ? pl.part.p + poff[j] : nullptr;
+    for (auto& p : pr) {
+      const TTile& t = tiles[p.tile];
+      reds.push_back({t.out, chunks[p.first].part, t.ld, t.rows, t.cols, p.n});
+    }
+    pl.chunks.put(chunks, st);
+    pl.tasks.put(flat, st);
+    pl.reds.put(reds, st);
+    pl.nchunks = (int)chunks.size();
+    pl.nreds = (int)reds.size();
   }
 };
 
@@ -1079,8 +1155,7 @@ struct Step {
   std::vector<int64_t> off;
   int64_t n = 0;
   DBuf in, out, diag;
-  DArr<TTile> tiles;
-  DArr<TTask> tasks;
+  TripleList::Plan plan;
   int ntiles = 0;
   double flops = 0.0, bytes = 0.0;
   int64_t ntasks = 0;
@@ -1202,10 +1277,9 @@ struct Engine {
         tl.add(first, rows, cols, t);
       }
     }
-    DArr<TTile> dt;
-    DArr<TTask> dk;
-    tl.upload(dt, dk, st);
-    launch_triple(dt.p, (int)tl.tiles.size(), dk.p, st);
+    TripleList::Plan pl;
+    tl.plan(pl, st);
+    pl.run(st);
     dev_sync(st);
     return out;
   }
@@ -1540,7 +1614,7 @@ struct Engine {
     step.bytes = bytes;
     step.ntasks = (int64_t)tl.tasks.size();
     step.ntiles = (int)tl.tiles.size();
-    tl.upload(step.tiles, step.tasks, st);
+    tl.plan(step.plan, st);
   }
 
   void build_diag() {
@@ -1711,10 +1785,9 @@ struct Engine {
     } else {
       fail(-1, "internal: no centre for this step");
     }
-    DArr<TTile> dt;
-    DArr<TTask> dk;
-    tl.upload(dt, dk, st);
-    launch_triple(dt.p, (int)tl.tiles.size(), dk.p, st);
+    TripleList::Plan pl;
+    tl.plan(pl, st);
+    pl.run(st);
     dev_sync(st);
   }
 
@@ -1722,7 +1795,7 @@ struct Engine {
   void sigma_fixed() {
     dev_zero(step.out.p, (size_t)std::max<int64_t>(step.n, 1) * 8, st);
     void* e0 = dev_event_record(st);
-    launch_triple(step.tiles.p, step.ntiles, step.tasks.p, st);
+    step.plan.run(st);
     void* e1 = dev_event_record(st);
     t_sigma += dev_event_elapsed(e0, e1);
     dev_event_free(e0);

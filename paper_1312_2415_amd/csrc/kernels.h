@@ -36,9 +36,17 @@ void dev_event_free(void* e);
 enum : int { TT_TRANS_A = 1, TT_TRANS_C = 2, TT_IDENT_A = 4, TT_IDENT_C = 8 };
 
 struct TTile {
-  double* out;
+  double* out;   // out[r*ld + c] += result   (when part == nullptr)
+  double* part;  // else part[r*cols + c] = result (a partial sum, reduced later)
   int ld, rows, cols;
   int t0, t1;  // task range
+};
+
+// out[r*ld + c] += sum_{p < nparts} part[p*rows*cols + r*cols + c]  (fixed order)
+struct RTile {
+  double* out;
+  const double* part;
+  int ld, rows, cols, nparts;
 };
 
 struct TTask {
@@ -111,6 +119,7 @@ struct SvdJob {
 };
 
 void launch_triple(const TTile* tiles, int ntiles, const TTask* tasks, Stream st);
+void launch_reduce(const RTile* reds, int nred, Stream st);
 void launch_gather(const GatherDst* dsts, int ndst, const GatherSrc* srcs, Stream st);
 void launch_combo(const ComboOut* outs, int nout, const ComboIn* ins, int64_t max_nnz, Stream st);
 void launch_diag(const DiagSec* secs, int nsec, const DiagTask* tasks, Stream st);

@@ -238,9 +238,29 @@ __global__ __launch_bounds__(NT) void triple_kernel(const TTile* __restrict__ ti
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = tx * 4 + j;
-      if (c < tile.cols) tile.out[(int64_t)r * tile.ld + c] += acc[i][j];
+      if (c >= tile.cols) continue;
+      if (tile.part)
+        tile.part[r * tile.cols + c] = acc[i][j];
+      else
+        tile.out[(int64_t)r * tile.ld + c] += acc[i][j];
     }
   }
+}
+
+__global__ __launch_bounds__(256) void reduce_kernel(const RTile* __restrict__ reds) {
+  const RTile t = reds[blockIdx.x];
+  const int n = t.rows * t.cols;
+  for (int e = threadIdx.x; e < n; e += 256) {
+    double v = 0.0;
+    for (int p = 0; p < t.nparts; ++p) v += t.part[(int64_t)p * n + e];
+    t.out[(int64_t)(e / t.cols) * t.ld + e % t.cols] += v;
+  }
+}
+
+void launch_reduce(const RTile* reds, int nred, Stream st) {
+  if (nred <= 0) return;
+  hipLaunchKernelGGL(reduce_kernel, dim3(nred), dim3(256), 0, (hipStream_t)st, reds);
+  check_launch("reduce");
 }
 
 void launch_triple(const TTile* tiles, int ntiles, const TTask* tasks, Stream st) {
