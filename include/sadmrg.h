@@ -152,6 +152,12 @@ int sadmrg_mps_export(sadmrg_ctx* ctx, void* blob, size_t* bytes); /* blob == NU
  * when on_device != 0, else host pointers.
  * ------------------------------------------------------------------------ */
 int sadmrg_prepare_step(sadmrg_ctx* ctx);
+/* Run n left-to-right micro-iterations (bond dimension D) from the current
+ * centre, moving it right; *e_min receives their lowest energy. */
+int sadmrg_advance(sadmrg_ctx* ctx, int D, int n, double* e_min);
+/* Shapes of the prepared step's sigma tile tasks, five ints each (rows, K1,
+ * K2, cols, flags of the triple-product record); size query when out == NULL. */
+int sadmrg_debug_task_shapes(sadmrg_ctx* ctx, int* out, int64_t* n);
 int sadmrg_psi_layout(sadmrg_ctx* ctx, int* nsec, int64_t* desc, int64_t* n);
 int sadmrg_sigma(sadmrg_ctx* ctx, const double* x, double* y, int on_device);
 /* Diagonal of the effective Hamiltonian at the prepared step (same layout). */
@@ -168,6 +174,10 @@ int sadmrg_sigma_counters(sadmrg_ctx* ctx, double* flops, double* bytes, int64_t
 int sadmrg_stats(sadmrg_ctx* ctx, double* t_sigma, int64_t* n_sigma, double* t_micro, double* flops_sigma,
                  double* t_blocking);
 int sadmrg_stats_reset(sadmrg_ctx* ctx);
+/* Operator bytes touched by the sigma calls since the last reset (operator
+ * stacks read + vector in/out, per call) and the largest enlarged-operator
+ * footprint of one micro-iteration (both enlarged blocks). */
+int sadmrg_stats_bytes(sadmrg_ctx* ctx, double* bytes_sigma, double* max_enlarged_bytes);
 
 /* Description of the last failure (static until the next call on ctx). */
 const char* sadmrg_last_error(const sadmrg_ctx* ctx);

@@ -51,12 +51,15 @@ def load_library(path: str | None = None):
         "sadmrg_mps_import": (c_int, [c_vp, c_vp, c_sz]),
         "sadmrg_mps_export": (c_int, [c_vp, c_vp, P(c_sz)]),
         "sadmrg_prepare_step": (c_int, [c_vp]),
+        "sadmrg_advance": (c_int, [c_vp, c_int, c_int, P(c_dbl)]),
+        "sadmrg_debug_task_shapes": (c_int, [c_vp, P(c_int), P(ctypes.c_int64)]),
         "sadmrg_psi_layout": (c_int, [c_vp, P(c_int), P(ctypes.c_int64), P(ctypes.c_int64)]),
         "sadmrg_sigma": (c_int, [c_vp, c_vp, c_vp, c_int]),
         "sadmrg_heff_diagonal": (c_int, [c_vp, c_vp, c_int]),
         "sadmrg_sigma_counters": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(ctypes.c_int64)]),
         "sadmrg_stats": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl), P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_reset": (c_int, [c_vp]),
+        "sadmrg_stats_bytes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_last_error": (ctypes.c_char_p, [c_vp]),
         "sadmrg_debug_coupling": (c_int, [c_int, P(c_int), P(c_dbl)]),
     }
@@ -176,6 +179,19 @@ class SaDMRG:
     def prepare_step(self):
         self._chk(self.lib.sadmrg_prepare_step(self.h))
 
+    def advance(self, D, n):
+        e = ctypes.c_double()
+        self._chk(self.lib.sadmrg_advance(self.h, int(D), int(n), ctypes.byref(e)))
+        return e.value
+
+    def task_shapes(self):
+        n = ctypes.c_int64(0)
+        self._chk(self.lib.sadmrg_debug_task_shapes(self.h, None, ctypes.byref(n)))
+        out = np.zeros((n.value, 5), dtype=np.int32)
+        self._chk(self.lib.sadmrg_debug_task_shapes(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                                    ctypes.byref(n)))
+        return out
+
     def psi_layout(self):
         ns = ctypes.c_int(0)
         n = ctypes.c_int64(0)
@@ -216,8 +232,10 @@ class SaDMRG:
         ns = ctypes.c_int64()
         self._chk(self.lib.sadmrg_stats(self.h, ctypes.byref(ts), ctypes.byref(ns), ctypes.byref(tm),
                                         ctypes.byref(fs), ctypes.byref(tb)))
+        bs, me = ctypes.c_double(), ctypes.c_double()
+        self._chk(self.lib.sadmrg_stats_bytes(self.h, ctypes.byref(bs), ctypes.byref(me)))
         return {"t_sigma": ts.value, "n_sigma": ns.value, "t_micro": tm.value, "flops_sigma": fs.value,
-                "t_blocking": tb.value}
+                "t_blocking": tb.value, "bytes_sigma": bs.value, "max_enlarged_bytes": me.value}
 
     def stats_reset(self):
         self._chk(self.lib.sadmrg_stats_reset(self.h))

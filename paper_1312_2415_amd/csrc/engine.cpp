@@ -19,6 +19,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -986,91 +987,74 @@ static std::unique_ptr<Store> enlarge(const Problem& P, Store& X, const Enl& E, 
 }
 
 // ---------------------------------------------------------------------------
-// Triple-product task lists (tiles of at most 64 x 64 output elements)
+// Grouped-GEMM task lists (output tiles of at most 64 x 64) and the two-pass
+// evaluation of block triple products  out += coef * opA(A) * B * opC(C):
+//   pass 1: T = opA(A) * B   written once into a workspace slot,
+//   pass 2: out += coef * T * opC(C), all products of one output block
+//           accumulated by the same tiles (long K), split into flop-balanced
+//           chunks whose partial tiles are added in a fixed order.
 // ---------------------------------------------------------------------------
-struct TripleList {
-  struct T {
+struct GemmList {
+  static constexpr int TS = 64;
+  struct Item {
     int tile;
-    TTask t;
-    double w;  // flops of this tile task
+    GTask t;
+    double w;
   };
-  std::vector<TTile> tiles;
-  std::vector<T> tasks;
-  double flops = 0.0;
-  // register an output block; returns the first tile index and count per dim
-  int add_block(double* out, int rows, int cols, int ld) {
+  std::vector<GTile> tiles;
+  std::vector<Item> items;
+
+  int add_block(double* out, int rows, int cols, int ld, int mode) {
     const int first = (int)tiles.size();
-    for (int r0 = 0; r0 < rows; r0 += 64)
-      for (int c0 = 0; c0 < cols; c0 += 64)
-        tiles.push_back({out + (int64_t)r0 * ld + c0, nullptr, ld, std::min(64, rows - r0), std::min(64, cols - c0), 0, 0});
+    for (int r0 = 0; r0 < rows; r0 += TS)
+      for (int c0 = 0; c0 < cols; c0 += TS)
+        tiles.push_back(
+            {out + (int64_t)r0 * ld + c0, nullptr, ld, std::min(TS, rows - r0), std::min(TS, cols - c0), mode, 0, 0});
     return first;
   }
-  // out block (registered at `first` with `cols` columns) += coef*opA(A)*B*opC(C)
-  void add(int first, int rows, int cols, const TTask& base) {
-    const int ntc = (cols + 63) / 64;
-    const int K1 = base.K1, K2 = base.K2;
-    if (base.flags & TT_IDENT_C)
-      flops += 2.0 * rows * K1 * cols;
-    else if (base.flags & TT_IDENT_A)
-      flops += 2.0 * rows * K2 * cols;
-    else
-      flops += 2.0 * rows * K1 * K2 + 2.0 * rows * K2 * cols;
-    for (int r0 = 0, tr = 0; r0 < rows; r0 += 64, ++tr)
-      for (int c0 = 0, tc = 0; c0 < cols; c0 += 64, ++tc) {
-        TTask t = base;
-        const int tr_ = std::min(64, rows - r0), tc_ = std::min(64, cols - c0);
-        double w;
-        if (t.flags & TT_IDENT_C)
-          w = 2.0 * tr_ * K1 * tc_;
-        else if (t.flags & TT_IDENT_A)
-          w = 2.0 * tr_ * K2 * tc_;
-        else
-          w = 2.0 * tr_ * K1 * K2 + 2.0 * tr_ * K2 * tc_;
-        if (t.flags & TT_IDENT_A)
-          t.b += (int64_t)r0 * t.ldb;
-        else if (t.flags & TT_TRANS_A)
-          t.a += r0;
-        else
-          t.a += (int64_t)r0 * t.lda;
-        if (t.flags & TT_IDENT_C)
-          t.b += c0;
-        else if (t.flags & TT_TRANS_C)
-          t.c += (int64_t)c0 * t.ldc;
-        else
-          t.c += c0;
-        tasks.push_back({first + tr * ntc + tc, t, w});
+  // block registered at `first` (rows x cols) += coef * opA(A)[rows x K] * opB(B)[K x cols]
+  void add(int first, int rows, int cols, const GTask& base) {
+    const int ntc = (cols + TS - 1) / TS;
+    for (int r0 = 0, tr = 0; r0 < rows; r0 += TS, ++tr)
+      for (int c0 = 0, tc = 0; c0 < cols; c0 += TS, ++tc) {
+        GTask t = base;
+        t.a += (t.flags & GT_TRANS_A) ? (int64_t)r0 : (int64_t)r0 * t.lda;
+        t.b += (t.flags & GT_TRANS_B) ? (int64_t)c0 * t.ldb : (int64_t)c0;
+        const double w = 2.0 * std::min(TS, rows - r0) * std::min(TS, cols - c0) * t.K;
+        items.push_back({first + tr * ntc + tc, t, w});
       }
   }
-  // Group tasks by tile and split every tile's list into chunks of about
-  // `target` flops that run on separate workgroups; chunks of a tile write
-  // partial tiles that a second kernel adds in chunk order (deterministic).
+
   struct Plan {
-    DArr<TTile> chunks;
-    DArr<TTask> tasks;
+    DArr<GTile> tiles;
+    DArr<GTask> tasks;
     DArr<RTile> reds;
     DBuf part;
-    int nchunks = 0, nreds = 0;
+    int ntiles = 0, nreds = 0;
     void run(Stream st) const {
-      launch_triple(chunks.p, nchunks, tasks.p, st);
+      launch_gemm(tiles.p, ntiles, tasks.p, st);
       launch_reduce(reds.p, nreds, st);
     }
   };
+
   void plan(Plan& pl, Stream st, double target = 0.0) {
     std::vector<int> cnt(tiles.size() + 1, 0);
-    for (auto& t : tasks) cnt[t.tile + 1]++;
+    for (auto& t : items) cnt[t.tile + 1]++;
     for (size_t i = 0; i < tiles.size(); ++i) cnt[i + 1] += cnt[i];
-    std::vector<TTask> flat(tasks.size());
-    std::vector<double> wt(tasks.size());
+    std::vector<GTask> flat(items.size());
+    std::vector<double> wt(items.size());
     std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-    for (auto& t : tasks) {
+    for (auto& t : items) {
       wt[pos[t.tile]] = t.w;
       flat[pos[t.tile]++] = t.t;
     }
     double total = 0.0;
     for (double w : wt) total += w;
-    if (target <= 0.0) target = std::max(2.0e4, total / 16384.0);
-    std::vector<TTile> chunks;
-    std::vector<int64_t> poff;  // partial-buffer offset per chunk (-1: direct write)
+    // enough chunks to fill 256 CUs a few workgroups deep without multiplying
+    // the partial tiles to reduce
+    if (target <= 0.0) target = std::max(2.0e5, total / 2048.0);
+    std::vector<GTile> chunks;
+    std::vector<int64_t> poff;
     struct PR {
       size_t tile;
       int first, n;
@@ -1083,17 +1067,18 @@ struct TripleList {
       std::vector<std::pair<int, int>> rng;
       double w = 0.0;
       int s = a;
-      for (int t = a; t < b; ++t) {
-        w += wt[t];
-        if (w >= target && t + 1 < b) {
-          rng.push_back({s, t + 1});
-          s = t + 1;
-          w = 0.0;
+      if (tiles[i].mode == 0)
+        for (int t = a; t < b; ++t) {
+          w += wt[t];
+          if (w >= target && t + 1 < b) {
+            rng.push_back({s, t + 1});
+            s = t + 1;
+            w = 0.0;
+          }
         }
-      }
       rng.push_back({s, b});
       if (rng.size() == 1) {
-        TTile c = tiles[i];
+        GTile c = tiles[i];
         c.t0 = a;
         c.t1 = b;
         chunks.push_back(c);
@@ -1102,7 +1087,7 @@ struct TripleList {
       }
       pr.push_back({i, (int)chunks.size(), (int)rng.size()});
       for (auto& [x, y] : rng) {
-        TTile c = tiles[i];
+        GTile c = tiles[i];
         c.t0 = x;
         c.t1 = y;
         chunks.push_back(c);
@@ -1111,19 +1096,82 @@ struct TripleList {
       }
     }
     pl.part.alloc((size_t)std::max<int64_t>(npart, 1));
-    std::vector<RTile> reds;
     for (size_t j = 0; j < chunks.size(); ++j) chunks[j].part = poff[j] >= 0 ? pl.part.p + poff[j] : nullptr;
+    std::vector<RTile> reds;
     for (auto& p : pr) {
-      const TTile& t = tiles[p.tile];
+      const GTile& t = tiles[p.tile];
       reds.push_back({t.out, chunks[p.first].part, t.ld, t.rows, t.cols, p.n});
     }
-    pl.chunks.put(chunks, st);
+    pl.tiles.put(chunks, st);
     pl.tasks.put(flat, st);
     pl.reds.put(reds, st);
-    pl.nchunks = (int)chunks.size();
+    pl.ntiles = (int)chunks.size();
     pl.nreds = (int)reds.size();
   }
 };
+
+// one product out[blk] += coef * opA(A)[rows x K1] * B[K1 x K2] * opC(C)[K2 x cols]
+struct Triple {
+  int blk;
+  const double* a;
+  const double* b;
+  const double* c;
+  int lda, ldb, ldc, K1, K2, flags;  // TT_* flags
+  double coef;
+};
+struct OutBlk {
+  double* out;
+  int rows, cols, ld;
+};
+
+struct TwoPass {
+  GemmList::Plan p1, p2;
+  DBuf ws;
+  double flops = 0.0;  // algorithmic: sum of the two GEMMs of every product
+  int64_t nprod = 0;
+  void run(Stream st) const {
+    p1.run(st);
+    p2.run(st);
+  }
+};
+
+static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Triple>& tr, TwoPass& tp, Stream st) {
+  std::vector<int64_t> slot(tr.size(), -1);
+  int64_t ws = 0;
+  for (size_t i = 0; i < tr.size(); ++i)
+    if (!(tr[i].flags & (TT_IDENT_A | TT_IDENT_C))) {
+      slot[i] = ws;
+      ws += (int64_t)outs[tr[i].blk].rows * tr[i].K2;
+    }
+  tp.ws.alloc((size_t)std::max<int64_t>(ws, 1));
+  GemmList g1, g2;
+  std::vector<int> first(outs.size());
+  for (size_t b = 0; b < outs.size(); ++b) first[b] = g2.add_block(outs[b].out, outs[b].rows, outs[b].cols, outs[b].ld, 0);
+  double fl = 0.0;
+  for (size_t i = 0; i < tr.size(); ++i) {
+    const Triple& x = tr[i];
+    const int R = outs[x.blk].rows, Cc = outs[x.blk].cols;
+    const int trA = (x.flags & TT_TRANS_A) ? GT_TRANS_A : 0;
+    const int trC = (x.flags & TT_TRANS_C) ? GT_TRANS_B : 0;
+    if (x.flags & TT_IDENT_C) {
+      g2.add(first[x.blk], R, Cc, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA, x.coef});
+      fl += 2.0 * R * x.K1 * Cc;
+    } else if (x.flags & TT_IDENT_A) {
+      g2.add(first[x.blk], R, Cc, GTask{x.b, x.c, x.ldb, x.ldc, x.K2, trC, x.coef});
+      fl += 2.0 * R * x.K2 * Cc;
+    } else {
+      double* T = tp.ws.p + slot[i];
+      const int f1 = g1.add_block(T, R, x.K2, x.K2, 1);
+      g1.add(f1, R, x.K2, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA, 1.0});
+      g2.add(first[x.blk], R, Cc, GTask{T, x.c, x.K2, x.ldc, x.K2, trC, x.coef});
+      fl += 2.0 * R * x.K1 * x.K2 + 2.0 * R * x.K2 * Cc;
+    }
+  }
+  tp.flops = fl;
+  tp.nprod = (int64_t)tr.size();
+  g1.plan(tp.p1, st);
+  g2.plan(tp.p2, st);
+}
 
 // ---------------------------------------------------------------------------
 // Context
@@ -1155,10 +1203,10 @@ struct Step {
   std::vector<int64_t> off;
   int64_t n = 0;
   DBuf in, out, diag;
-  TripleList::Plan plan;
-  int ntiles = 0;
+  TwoPass plan;
   double flops = 0.0, bytes = 0.0;
   int64_t ntasks = 0;
+  std::vector<std::array<int, 5>> shapes;  // per tile task: rows, K1, K2, cols, flags
 };
 
 struct Engine {
@@ -1180,7 +1228,7 @@ struct Engine {
   std::vector<double> trace;
   bool warned = false;
   // statistics
-  double t_sigma = 0, t_micro = 0, f_sigma = 0, t_block = 0;
+  double t_sigma = 0, t_micro = 0, f_sigma = 0, t_block = 0, b_sigma = 0, max_enl_bytes = 0;
   int64_t n_sigma = 0;
   // Davidson work buffers
   DBuf dV, dW, dHs, dsmall, dpartial, dx_, dax, dr, dt;
@@ -1239,7 +1287,8 @@ struct Engine {
       out->add(o.key, L.tk, L.dN, L.dG, o.odd);
     }
     out->allocate(st);
-    TripleList tl;
+    std::vector<OutBlk> outs;
+    std::vector<Triple> trs;
     for (size_t i = 0; i < out->ops.size(); ++i) {
       const Layout& NL = out->lay((int)i);
       const Layout& EL = E.lay((int)i);
@@ -1251,35 +1300,25 @@ struct Engine {
         const int eblk = EL.find(eb, ek);
         if (eblk < 0) continue;
         const int rows = nb.dim[NL.bra[b]], cols = nb.dim[NL.ket[b]];
-        double* o = out->ptr((int)i, (int)b);
-        const int first = tl.add_block(o, rows, cols, cols);
-        TTask t{};
+        outs.push_back({out->ptr((int)i, (int)b), rows, cols, cols});
+        Triple t{};
+        t.blk = (int)outs.size() - 1;
         t.b = E.ptr((int)i, eblk);
         t.ldb = E.basis.dim[ek];
         t.coef = 1.0;
-        if (left) {  // U[b]^T (dimX(b) x k_b)^T * O * U[k]
-          t.a = T.at(tb);
-          t.lda = T.cols[tb];
-          t.K1 = E.basis.dim[eb];
-          t.c = T.at(tkk);
-          t.ldc = T.cols[tkk];
-          t.K2 = E.basis.dim[ek];
-          t.flags = TT_TRANS_A;
-        } else {  // V[b] (k_b x dimY(b)) * O * V[k]^T
-          t.a = T.at(tb);
-          t.lda = T.cols[tb];
-          t.K1 = E.basis.dim[eb];
-          t.c = T.at(tkk);
-          t.ldc = T.cols[tkk];
-          t.K2 = E.basis.dim[ek];
-          t.flags = TT_TRANS_C;
-        }
-        tl.add(first, rows, cols, t);
+        t.a = T.at(tb);
+        t.lda = T.cols[tb];
+        t.K1 = E.basis.dim[eb];
+        t.c = T.at(tkk);
+        t.ldc = T.cols[tkk];
+        t.K2 = E.basis.dim[ek];
+        t.flags = left ? TT_TRANS_A : TT_TRANS_C;  // left: U^T O U ; right: V O V^T
+        trs.push_back(t);
       }
     }
-    TripleList::Plan pl;
-    tl.plan(pl, st);
-    pl.run(st);
+    TwoPass tp;
+    build_two_pass(outs, trs, tp, st);
+    tp.run(st);
     dev_sync(st);
     return out;
   }
@@ -1449,6 +1488,7 @@ struct Engine {
     step.out.alloc((size_t)std::max<int64_t>(step.n, 1));
     step.diag.alloc((size_t)std::max<int64_t>(step.n, 1));
     build_sigma_tasks();
+    max_enl_bytes = std::max(max_enl_bytes, 8.0 * (double)(step.X->total + step.Y->total));
     build_diag();
     build_guess();
     dev_sync(st);
@@ -1501,10 +1541,10 @@ struct Engine {
 
   void build_sigma_tasks() {
     Store &X = *step.X, &Y = *step.Y;
-    TripleList tl;
     const int ns = (int)step.psi.sec.size();
-    std::vector<int> first(ns);
-    for (int m = 0; m < ns; ++m) first[m] = tl.add_block(step.out.p + step.off[m], step.dx[m], step.dy[m], step.dy[m]);
+    std::vector<OutBlk> outs(ns);
+    for (int m = 0; m < ns; ++m) outs[m] = {step.out.p + step.off[m], step.dx[m], step.dy[m], step.dy[m]};
+    std::vector<Triple> trs;
     double bytes = 0.0;
     std::set<std::pair<int, int>> touched;  // (store, op) operands read
     for (const HTerm& h : heff_terms()) {
@@ -1513,7 +1553,8 @@ struct Engine {
         for (size_t b = 0; b < L.bra.size(); ++b) {
           const int m = L.bra[b];
           if (L.ket[b] != m) continue;
-          TTask t{};
+          Triple t{};
+          t.blk = m;
           t.a = X.ptr(h.x, (int)b);
           t.lda = step.dx[m];
           t.K1 = step.dx[m];
@@ -1521,7 +1562,7 @@ struct Engine {
           t.ldb = step.dy[m];
           t.flags = TT_IDENT_C;
           t.coef = h.coef;
-          tl.add(first[m], step.dx[m], step.dy[m], t);
+          trs.push_back(t);
         }
         touched.insert({0, h.x});
         continue;
@@ -1531,7 +1572,8 @@ struct Engine {
         for (size_t b = 0; b < L.bra.size(); ++b) {
           const int m = L.bra[b];
           if (L.ket[b] != m) continue;
-          TTask t{};
+          Triple t{};
+          t.blk = m;
           t.b = step.in.p + step.off[m];
           t.ldb = step.dy[m];
           t.c = Y.ptr(h.y, (int)b);
@@ -1539,7 +1581,7 @@ struct Engine {
           t.K2 = step.dy[m];
           t.flags = TT_IDENT_A | TT_TRANS_C;
           t.coef = h.coef;
-          tl.add(first[m], step.dx[m], step.dy[m], t);
+          trs.push_back(t);
         }
         touched.insert({1, h.y});
         continue;
@@ -1569,7 +1611,8 @@ struct Engine {
         const double* xa = X.ptr(h.x, (int)b);
         const double* yc = Y.ptr(h.y, yb);
         {  // sigma[mb] += f X[mb,mk] psi[mk] Yeff[mb,mk]^T
-          TTask t{};
+          Triple t{};
+          t.blk = mb;
           t.a = xa;
           t.lda = step.dx[mk];
           t.K1 = step.dx[mk];
@@ -1585,10 +1628,11 @@ struct Engine {
             t.flags = TT_TRANS_C;
           }
           t.coef = f;
-          tl.add(first[mb], step.dx[mb], step.dy[mb], t);
+          trs.push_back(t);
         }
         if (h.hc) {  // sigma[mk] += f X[mb,mk]^T psi[mb] Yeff[mb,mk]
-          TTask t{};
+          Triple t{};
+          t.blk = mk;
           t.a = xa;
           t.lda = step.dx[mk];
           t.K1 = step.dx[mb];
@@ -1604,17 +1648,18 @@ struct Engine {
             t.flags = TT_TRANS_A;
           }
           t.coef = f;
-          tl.add(first[mk], step.dx[mk], step.dy[mk], t);
+          trs.push_back(t);
         }
       }
     }
     for (auto& [s, o] : touched) bytes += 8.0 * (s == 0 ? X.lay(o).nnz : Y.lay(o).nnz);
     bytes += 16.0 * step.n;
-    step.flops = tl.flops;
+    build_two_pass(outs, trs, step.plan, st);
+    step.flops = step.plan.flops;
     step.bytes = bytes;
-    step.ntasks = (int64_t)tl.tasks.size();
-    step.ntiles = (int)tl.tiles.size();
-    tl.plan(step.plan, st);
+    step.ntasks = (int64_t)trs.size();
+    step.shapes.clear();
+    for (auto& t : trs) step.shapes.push_back({outs[t.blk].rows, t.K1, t.K2, outs[t.blk].cols, t.flags});
   }
 
   void build_diag() {
@@ -1680,9 +1725,9 @@ struct Engine {
   void build_guess() {
     dev_zero(step.in.p, (size_t)std::max<int64_t>(step.n, 1) * 8, st);
     const int i = step.i;
-    TripleList tl;
     const int ns = (int)step.psi.sec.size();
-    std::vector<int> first(ns, -1);
+    std::vector<OutBlk> outs;
+    std::vector<Triple> trs;
     if (cen.kind == C_TWO && cen.pos == i) {
       std::vector<GatherDst> dsts;
       std::vector<GatherSrc> srcs;
@@ -1707,8 +1752,10 @@ struct Engine {
         const int j = cen.t.find(step.psi.sec[m]);
         const int v = V[1].find(step.psi.sec[m]);
         if (j < 0 || v < 0) continue;
-        const int f = tl.add_block(step.in.p + step.off[m], step.dx[m], step.dy[m], step.dy[m]);
-        TTask t{};
+        if (V[1].cols[v] != step.dy[m]) fail(-1, "internal: right tensor shape mismatch");
+        outs.push_back({step.in.p + step.off[m], step.dx[m], step.dy[m], step.dy[m]});
+        Triple t{};
+        t.blk = (int)outs.size() - 1;
         t.a = cen.t.at(j);
         t.lda = cen.t.cols[j];
         t.K1 = cen.t.cols[j];
@@ -1716,7 +1763,7 @@ struct Engine {
         t.ldb = V[1].cols[v];
         t.flags = TT_IDENT_C;
         t.coef = 1.0;
-        tl.add(f, step.dx[m], step.dy[m], t);
+        trs.push_back(t);
       }
     } else if (cen.kind == C_BOND_R && cen.pos == i) {
       // C[a] rows of bond i, columns (n, b) of the right-enlarged basis at bond i
@@ -1735,12 +1782,12 @@ struct Engine {
           for (auto& q : step.EX.pieces[m])
             if (q.sub == ai && q.n == pc.n) roff = q.off;
           if (roff < 0) continue;
-          if (first[m] < 0) first[m] = 0;
+          if (V[i + 1].cols[v] != step.dy[m]) fail(-1, "internal: right tensor shape mismatch");
           const double r = recouple_singlet(a.tj, LOC_TJ[pc.n], b.tj);
           const int rows = cen.t.rows[ja];
-          const int f = tl.add_block(step.in.p + step.off[m] + (int64_t)roff * step.dy[m], rows, step.dy[m],
-                                     step.dy[m]);
-          TTask t{};
+          outs.push_back({step.in.p + step.off[m] + (int64_t)roff * step.dy[m], rows, step.dy[m], step.dy[m]});
+          Triple t{};
+          t.blk = (int)outs.size() - 1;
           t.b = cen.t.at((int)ja) + pc.off;
           t.ldb = cen.t.cols[ja];
           t.K2 = dims[i + 1].dim[pc.sub];
@@ -1748,7 +1795,7 @@ struct Engine {
           t.ldc = V[i + 1].cols[v];
           t.flags = TT_IDENT_A;
           t.coef = r;
-          tl.add(f, rows, step.dy[m], t);
+          trs.push_back(t);
         }
       }
     } else if (cen.kind == C_BOND_L && cen.pos == i + 2) {
@@ -1768,10 +1815,12 @@ struct Engine {
           for (auto& q : step.EY.pieces[m])
             if (q.sub == bi && q.n == pc.n) coff = q.off;
           if (coff < 0) continue;
+          if (U[i].rows[u] != step.dx[m]) fail(-1, "internal: left tensor shape mismatch");
           const double r = recouple_singlet(a.tj, LOC_TJ[pc.n], b.tj);
           const int cols = cen.t.cols[jb];
-          const int f = tl.add_block(step.in.p + step.off[m] + coff, step.dx[m], cols, step.dy[m]);
-          TTask t{};
+          outs.push_back({step.in.p + step.off[m] + coff, step.dx[m], cols, step.dy[m]});
+          Triple t{};
+          t.blk = (int)outs.size() - 1;
           t.a = U[i].at(u);
           t.lda = U[i].cols[u];
           t.K1 = U[i].cols[u];
@@ -1779,15 +1828,15 @@ struct Engine {
           t.ldb = cen.t.cols[jb];
           t.flags = TT_IDENT_C;
           t.coef = r;
-          tl.add(f, step.dx[m], cols, t);
+          trs.push_back(t);
         }
       }
     } else {
       fail(-1, "internal: no centre for this step");
     }
-    TripleList::Plan pl;
-    tl.plan(pl, st);
-    pl.run(st);
+    TwoPass tp;
+    build_two_pass(outs, trs, tp, st);
+    tp.run(st);
     dev_sync(st);
   }
 
@@ -1802,6 +1851,7 @@ struct Engine {
     dev_event_free(e1);
     ++n_sigma;
     f_sigma += step.flops;
+    b_sigma += step.bytes;
   }
   void sigma_vec(const double* x, double* y) {
     dev_d2d(step.in.p, x, (size_t)step.n * 8, st);
@@ -2135,6 +2185,17 @@ struct Engine {
     dev_sync(st);
     step.i = -1;  // blocks changed
     t_micro += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return e;
+  }
+
+  // left-to-right micro-iterations from the current centre (test / benchmark hook)
+  double advance(int D, int n) {
+    if (!mps_ready) fail(-1, "no MPS");
+    if (!((cen.kind == C_T0 && cen.pos == 0) || (cen.kind == C_TWO) || cen.kind == C_BOND_R))
+      fail(-1, "advance needs a centre reached by a left-to-right move");
+    int i = cen.pos;
+    double e = INFINITY;
+    for (int s = 0; s < n && i <= P.L - 3; ++s, ++i) e = std::min(e, micro(i, D, true, true));
     return e;
   }
 
@@ -2625,10 +2686,42 @@ int sadmrg_stats(sadmrg_ctx* ctx, double* t_sigma, int64_t* n_sigma, double* t_m
   });
 }
 
+int sadmrg_stats_bytes(sadmrg_ctx* ctx, double* bytes_sigma, double* max_enlarged_bytes) {
+  return guard(ctx, [&] {
+    if (bytes_sigma) *bytes_sigma = ctx->e.b_sigma;
+    if (max_enlarged_bytes) *max_enlarged_bytes = ctx->e.max_enl_bytes;
+    return 0;
+  });
+}
+
+int sadmrg_advance(sadmrg_ctx* ctx, int D, int n, double* e_min) {
+  return guard(ctx, [&] {
+    if (D < 1 || n < 0) sadmrg::fail(SADMRG_EINVAL, "bad arguments");
+    const double e = ctx->e.advance(D, n);
+    if (e_min) *e_min = e;
+    return 0;
+  });
+}
+
+int sadmrg_debug_task_shapes(sadmrg_ctx* ctx, int* out, int64_t* n) {
+  return guard(ctx, [&] {
+    auto& S = ctx->e.step;
+    if (S.i < 0 || !S.X) sadmrg::fail(SADMRG_EINVAL, "no prepared step");
+    if (!n) sadmrg::fail(SADMRG_EINVAL, "null count");
+    if (out) {
+      const int64_t m = std::min<int64_t>(*n, (int64_t)S.shapes.size());
+      for (int64_t i = 0; i < m; ++i)
+        for (int q = 0; q < 5; ++q) out[5 * i + q] = S.shapes[i][q];
+    }
+    *n = (int64_t)S.shapes.size();
+    return 0;
+  });
+}
+
 int sadmrg_stats_reset(sadmrg_ctx* ctx) {
   return guard(ctx, [&] {
     auto& E = ctx->e;
-    E.t_sigma = E.t_micro = E.f_sigma = E.t_block = 0;
+    E.t_sigma = E.t_micro = E.f_sigma = E.t_block = E.b_sigma = E.max_enl_bytes = 0;
     E.n_sigma = 0;
     return 0;
   });

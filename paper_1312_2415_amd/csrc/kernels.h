@@ -26,37 +26,15 @@ void* dev_event_record(Stream st);
 double dev_event_elapsed(void* a, void* b);  // seconds, synchronises b
 void dev_event_free(void* e);
 
-// ---------------------------------------------------------------------------
-// Block triple products:
-//   out[rows x cols] += coef * opA(A)[rows x K1] * B[K1 x K2] * opC(C)[K2 x cols]
-// opA / opC transpose when flagged; an identity A (or C) drops that factor.
-// `a` / `c` already point at the tile's first row / column; `out` at the
-// tile's (0,0) element.  Output tiles of one launch must not overlap.
-// ---------------------------------------------------------------------------
+// Flags of a block triple product  out += coef * opA(A) * B * opC(C)  (the
+// host evaluates it as two grouped GEMMs): transpose A / C, identity A / C.
 enum : int { TT_TRANS_A = 1, TT_TRANS_C = 2, TT_IDENT_A = 4, TT_IDENT_C = 8 };
-
-struct TTile {
-  double* out;   // out[r*ld + c] += result   (when part == nullptr)
-  double* part;  // else part[r*cols + c] = result (a partial sum, reduced later)
-  int ld, rows, cols;
-  int t0, t1;  // task range
-};
 
 // out[r*ld + c] += sum_{p < nparts} part[p*rows*cols + r*cols + c]  (fixed order)
 struct RTile {
   double* out;
   const double* part;
   int ld, rows, cols, nparts;
-};
-
-struct TTask {
-  const double* a;
-  const double* b;
-  const double* c;
-  int lda, ldb, ldc;
-  int K1, K2;
-  int flags;
-  double coef;
 };
 
 // dst[rows x cols] (leading dim ld) = sum_s scale_s * src_s, where src_s is a
@@ -118,7 +96,26 @@ struct SvdJob {
   double* work;
 };
 
-void launch_triple(const TTile* tiles, int ntiles, const TTask* tasks, Stream st);
+
+// Grouped GEMM: each output tile (<= 64 x 64) gets
+//   mode 0: out += sum_t coef_t * opA(A_t)[rows x K_t] * opB(B_t)[K_t x cols]
+//   mode 1: out  = (same sum)        (when part == nullptr)
+// or writes the sum to `part` (a partial of a split tile, reduced later).
+// `a` / `b` point at the tile's first row / column.
+enum : int { GT_TRANS_A = 1, GT_TRANS_B = 2 };
+struct GTile {
+  double* out;
+  double* part;
+  int ld, rows, cols, mode;
+  int t0, t1;
+};
+struct GTask {
+  const double* a;
+  const double* b;
+  int lda, ldb, K, flags;
+  double coef;
+};
+void launch_gemm(const GTile* tiles, int ntiles, const GTask* tasks, Stream st);
 void launch_reduce(const RTile* reds, int nred, Stream st);
 void launch_gather(const GatherDst* dsts, int ndst, const GatherSrc* srcs, Stream st);
 void launch_combo(const ComboOut* outs, int nout, const ComboIn* ins, int64_t max_nnz, Stream st);

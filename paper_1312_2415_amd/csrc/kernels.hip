@@ -2,11 +2,11 @@
 //
 // The hot contraction of the method -- the action of the effective two-site
 // Hamiltonian and the renormalisation of block operators (paper, section
-// "CheMPS2 library": the two OpenMP hot spots) -- is a sum of small
-// block triple products  coef * op(A) * B * op(C)  over symmetry-sector pairs.
-// triple_kernel evaluates a list of such products per output tile, staging
-// operands through LDS and accumulating in registers, so each output element
-// is written exactly once (no atomics; bitwise reproducible).
+// "CheMPS2 library": the two OpenMP hot spots) -- is a sum of block triple
+// products  coef * op(A) * B * op(C)  over symmetry-sector pairs.  The host
+// evaluates them as two grouped GEMMs (gemm_kernel, FP64 matrix cores); split
+// output tiles are combined by reduce_kernel in a fixed order, so every output
+// element is written deterministically (no floating-point atomics).
 #include "kernels.h"
 
 #include <hip/hip_runtime.h>
@@ -93,167 +93,181 @@ void dev_event_free(void* e) {
 
 namespace {
 
-constexpr int TM = 64;   // output tile rows
-constexpr int TN = 64;   // output tile cols
-constexpr int TK = 32;   // inner chunk
-constexpr int NT = 256;  // threads per workgroup (16 x 16 grid, 4 x 4 outputs each)
-
-__device__ inline double ldA(const double* A, int lda, bool tr, int r, int k) {
-  return tr ? A[(int64_t)k * lda + r] : A[(int64_t)r * lda + k];
-}
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Block triple products.  One workgroup per output tile (<= 64 x 64).
-// For each task: T = opA(A)[rows x K1] * B[K1 x K2] is formed in 64 x 32
-// chunks of K2 in LDS, then acc += T_chunk * opC(C)[chunk x cols].
+// FP64 matrix-core helper.  Lane layout of v_mfma_f64_16x16x4f64 (checked on
+// gfx950): A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane
+// j + 16 (i % 4), register i / 4.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void triple_kernel(const TTile* __restrict__ tiles, const TTask* __restrict__ tasks) {
-  __shared__ double sA[TM][TK + 1];
-  __shared__ double sB[TK][TK + 1];
-  __shared__ double sT[TM][TK + 1];
-  __shared__ double sC[TK][TN + 1];
+typedef double d4_t __attribute__((ext_vector_type(4)));
 
-  const TTile tile = tiles[blockIdx.x];
-  const int tid = threadIdx.x;
-  const int ty = tid / 16, tx = tid % 16;  // output: rows ty*4..+3, cols tx*4..+3
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+__device__ inline d4_t mfma16(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
-  for (int t = tile.t0; t < tile.t1; ++t) {
-    const TTask tk = tasks[t];
-    const bool trA = tk.flags & TT_TRANS_A, trC = tk.flags & TT_TRANS_C;
-    const bool idA = tk.flags & TT_IDENT_A, idC = tk.flags & TT_IDENT_C;
-    const double* A = tk.a;
-    const double* B = tk.b;
-    const double* C = tk.c;
-    const double coef = tk.coef;
 
-    if (idC) {
-      // acc += coef * opA(A)[rows x K1] * B[K1 x cols]
-      for (int k0 = 0; k0 < tk.K1; k0 += TK) {
-        const int kc = min(TK, tk.K1 - k0);
-        for (int e = tid; e < TM * TK; e += NT) {
-          int r = e / TK, k = e % TK;
-          sA[r][k] = (r < tile.rows && k < kc) ? ldA(A, tk.lda, trA, r, k0 + k) : 0.0;
-        }
-        for (int e = tid; e < TK * TN; e += NT) {
-          int k = e / TN, c = e % TN;
-          sC[k][c] = (k < kc && c < tile.cols) ? B[(int64_t)(k0 + k) * tk.ldb + c] : 0.0;
-        }
-        __syncthreads();
-        for (int k = 0; k < kc; ++k) {
-          double a[4], b[4];
+// ---------------------------------------------------------------------------
+// Grouped GEMM on the FP64 matrix cores.  One workgroup (4 wavefronts) per
+// output tile of at most 64 x 64; wave w owns rows [16w, 16w+16) as four
+// 16 x 16 accumulator blocks.  K is streamed in chunks of 32 through LDS
+// (opA chunk 64 x 32, opB chunk 32 x 64, zero padded), double buffered: the
+// next chunk is loaded into registers while the current one is multiplied.
+// ---------------------------------------------------------------------------
+constexpr int GK = 32;
+
+struct GChunk {  // one thread's share of a staged chunk: 8 + 8 elements
+  double a[8], b[8];
+};
+
+__device__ inline void gemm_fetch(GChunk& r, const GTask& t, int k0, int rows, int cols, int tid) {
+  const bool trA = t.flags & GT_TRANS_A, trB = t.flags & GT_TRANS_B;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) a[i] = coef * sA[ty * 4 + i][k];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) b[j] = sC[k][tx * 4 + j];
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
-        }
-        __syncthreads();
-      }
-      continue;
+  for (int q = 0; q < 8; ++q) {
+    const int e = tid + q * 256;  // 0 .. 2047
+    // opA chunk element (row, k): contiguous direction of A first
+    int row, k;
+    if (trA) {
+      k = e / 64;
+      row = e % 64;
+    } else {
+      row = e / GK;
+      k = e % GK;
     }
+    const int kk = k0 + k;
+    double v = 0.0;
+    if (row < rows && kk < t.K) v = trA ? t.a[(int64_t)kk * t.lda + row] : t.a[(int64_t)row * t.lda + kk];
+    r.a[q] = v;
+    // opB chunk element (k, col)
+    int c;
+    if (trB) {
+      c = e / GK;
+      k = e % GK;
+    } else {
+      k = e / 64;
+      c = e % 64;
+    }
+    const int kb = k0 + k;
+    double u = 0.0;
+    if (c < cols && kb < t.K) u = trB ? t.b[(int64_t)c * t.ldb + kb] : t.b[(int64_t)kb * t.ldb + c];
+    r.b[q] = u;
+  }
+}
 
-    for (int j0 = 0; j0 < tk.K2; j0 += TK) {
-      const int jc = min(TK, tk.K2 - j0);
-      // ---- T chunk = opA(A)[rows x K1] * B[K1 x jc]  (or B rows directly if A is identity)
-      if (idA) {
-        for (int e = tid; e < TM * TK; e += NT) {
-          int r = e / TK, j = e % TK;
-          sT[r][j] = (r < tile.rows && j < jc) ? B[(int64_t)r * tk.ldb + j0 + j] : 0.0;
-        }
-        __syncthreads();
-      } else {
-        // each thread owns 4 rows x 2 cols of the 64 x 32 chunk
-        const int r0 = (tid / 16) * 4, c0 = (tid % 16) * 2;
-        double tacc[4][2];
+__device__ inline void gemm_store(const GChunk& r, const GTask& t, double (*sA)[GK + 1], double (*sB)[65], int tid) {
+  const bool trA = t.flags & GT_TRANS_A, trB = t.flags & GT_TRANS_B;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) tacc[i][0] = tacc[i][1] = 0.0;
-        for (int k0 = 0; k0 < tk.K1; k0 += TK) {
-          const int kc = min(TK, tk.K1 - k0);
-          for (int e = tid; e < TM * TK; e += NT) {
-            int r = e / TK, k = e % TK;
-            sA[r][k] = (r < tile.rows && k < kc) ? ldA(A, tk.lda, trA, r, k0 + k) : 0.0;
-          }
-          for (int e = tid; e < TK * TK; e += NT) {
-            int k = e / TK, j = e % TK;
-            sB[k][j] = (k < kc && j < jc) ? B[(int64_t)(k0 + k) * tk.ldb + j0 + j] : 0.0;
-          }
-          __syncthreads();
-          for (int k = 0; k < kc; ++k) {
-            double a[4];
+  for (int q = 0; q < 8; ++q) {
+    const int e = tid + q * 256;
+    if (trA)
+      sA[e % 64][e / 64] = r.a[q];
+    else
+      sA[e / GK][e % GK] = r.a[q];
+    if (trB)
+      sB[e % GK][e / GK] = r.b[q];
+    else
+      sB[e / 64][e % 64] = r.b[q];
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void gemm_kernel(const GTile* __restrict__ tiles, const GTask* __restrict__ tasks) {
+  __shared__ double sA[2][64][GK + 1];
+  __shared__ double sB[2][GK][65];
+  const GTile tile = tiles[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int w = tid / 64, l = tid % 64;
+  const int li = l % 16, lk = l / 16;
+  const int r0 = 16 * w;
+  const bool active = r0 < tile.rows;
+  const int ncb = (tile.cols + 15) / 16;
+  d4_t acc[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = sA[r0 + i][k];
-            const double b0 = sB[k][c0], b1 = sB[k][c0 + 1];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              tacc[i][0] += a[i] * b0;
-              tacc[i][1] += a[i] * b1;
-            }
-          }
-          __syncthreads();
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          sT[r0 + i][c0] = tacc[i][0];
-          sT[r0 + i][c0 + 1] = tacc[i][1];
-        }
-      }
-      // ---- C chunk = opC(C)[j0:j0+jc, 0:cols]
-      for (int e = tid; e < TK * TN; e += NT) {
-        int j = e / TN, c = e % TN;
-        double v = 0.0;
-        if (j < jc && c < tile.cols)
-          v = trC ? C[(int64_t)c * tk.ldc + j0 + j] : C[(int64_t)(j0 + j) * tk.ldc + c];
-        sC[j][c] = v;
-      }
+  for (int b = 0; b < 4; ++b) acc[b] = (d4_t){0.0, 0.0, 0.0, 0.0};
+
+  // flatten (task, k-chunk) into one stream so the prefetch crosses task borders
+  int t = tile.t0, k0 = 0;
+  if (t >= tile.t1) goto write;
+  {
+    GTask cur = tasks[t];
+    GChunk reg;
+    gemm_fetch(reg, cur, 0, tile.rows, tile.cols, tid);
+    int buf = 0;
+    while (true) {
+      gemm_store(reg, cur, sA[buf], sB[buf], tid);
       __syncthreads();
-      for (int j = 0; j < jc; ++j) {
-        double a[4], b[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = coef * sT[ty * 4 + i][j];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) b[q] = sC[j][tx * 4 + q];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc[i][q] += a[i] * b[q];
+      // advance the stream and prefetch the next chunk
+      const GTask now = cur;
+      const int kc = min(GK, now.K - k0);
+      int tn = t, kn = k0 + GK;
+      if (kn >= now.K) {
+        ++tn;
+        kn = 0;
       }
-      __syncthreads();
+      const bool more = tn < tile.t1;
+      if (more) {
+        if (tn != t) cur = tasks[tn];
+        gemm_fetch(reg, cur, kn, tile.rows, tile.cols, tid);
+      }
+      if (active) {
+        const double cf = now.coef;
+        for (int kk = 0; kk < kc; kk += 4) {
+          const double a = cf * sA[buf][r0 + li][kk + lk];
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if (b < ncb) acc[b] = mfma16(a, sB[buf][kk + lk][16 * b + li], acc[b]);
+        }
+      }
+      if (!more) break;
+      t = tn;
+      k0 = kn;
+      buf ^= 1;
     }
   }
-  // write-back (each element owned by exactly one thread of one workgroup)
+write:
+  if (active) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = ty * 4 + i;
-    if (r >= tile.rows) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = tx * 4 + j;
+    for (int b = 0; b < 4; ++b) {
+      const int c = 16 * b + li;
       if (c >= tile.cols) continue;
-      if (tile.part)
-        tile.part[r * tile.cols + c] = acc[i][j];
-      else
-        tile.out[(int64_t)r * tile.ld + c] += acc[i][j];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int orow = r0 + lk + 4 * r;
+        if (orow >= tile.rows) continue;
+        if (tile.part)
+          tile.part[orow * tile.cols + c] = acc[b][r];
+        else if (tile.mode == 1)
+          tile.out[(int64_t)orow * tile.ld + c] = acc[b][r];
+        else
+          tile.out[(int64_t)orow * tile.ld + c] += acc[b][r];
+      }
     }
   }
 }
 
+void launch_gemm(const GTile* tiles, int ntiles, const GTask* tasks, Stream st) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(gemm_kernel, dim3(ntiles), dim3(256), 0, (hipStream_t)st, tiles, tasks);
+  check_launch("gemm");
+}
+
+// Ordered sum of a tile's partial results: eight interleaved accumulators
+// keep loads in flight; the combination order is fixed, so results are
+// reproducible run to run.
 __global__ __launch_bounds__(256) void reduce_kernel(const RTile* __restrict__ reds) {
   const RTile t = reds[blockIdx.x];
   const int n = t.rows * t.cols;
   for (int e = threadIdx.x; e < n; e += 256) {
-    double v = 0.0;
-    for (int p = 0; p < t.nparts; ++p) v += t.part[(int64_t)p * n + e];
-    t.out[(int64_t)(e / t.cols) * t.ld + e % t.cols] += v;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const double* p = t.part + e;
+    int q = 0;
+    for (; q + 8 <= t.nparts; q += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] += p[(int64_t)(q + u) * n];
+    }
+    for (int u = 0; q < t.nparts; ++q, ++u) v[u] += p[(int64_t)q * n];
+    const double s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    t.out[(int64_t)(e / t.cols) * t.ld + e % t.cols] += s;
   }
 }
 
@@ -263,11 +277,6 @@ void launch_reduce(const RTile* reds, int nred, Stream st) {
   check_launch("reduce");
 }
 
-void launch_triple(const TTile* tiles, int ntiles, const TTask* tasks, Stream st) {
-  if (ntiles <= 0) return;
-  hipLaunchKernelGGL(triple_kernel, dim3(ntiles), dim3(NT), 0, (hipStream_t)st, tiles, tasks);
-  check_launch("triple");
-}
 
 // ---------------------------------------------------------------------------
 // Gather-accumulate of scaled (possibly transposed / identity) blocks.
