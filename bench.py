@@ -8,16 +8,22 @@ carbon-dimer cc-pVDZ integrals, which are not available).
 
 A "step" is one macro-iteration (a left-to-right plus a right-to-left pass;
 every micro-iteration: enlargement and complementary operators, Davidson with
-the H_eff sigma product, SVD truncation, renormalisation).  Warm-up sweeps ramp
-the bond dimension (default 500 -> 1000 -> 2500); the K timed sweeps run at D.
+the H_eff sigma product, SVD truncation, renormalisation).  The MPS starts
+random at bond dimension D and every sweep (warm-up and timed) runs at D, so
+every kernel launch of the run has the shapes of the headline workload.
 
 Reported `value` is the sigma-product rate: algorithmic FP64 flops of all
 H_eff*psi calls in the timed sweeps divided by their kernel time (HIP events on
-the library stream).  `ms_per_step` is the wall time per sweep.
+the library stream).  `ms_per_step` is the wall time per sweep.  `roofline`
+describes the dominant sigma kernel (the grouped-GEMM pass with the larger
+share of sigma time): its algorithmic flops per launch over its mean launch
+duration, against the FP64 MFMA peak.  `traffic` is filled from the committed
+HBM-counter summary when that summary was taken on the current kernel source.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,8 +33,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "H_eff·ψ TFLOP/s + s/sweep, FP64 vs mixed at |ΔE|≤1e-6 Eh, L=28 D=2500"
-FP64_VECTOR_PEAK = 78.6  # TFLOP/s, MI355X (256 CUs x 2.4 GHz x 128 FP64 flop/clk)
+FP64_MFMA_PEAK = 78.6  # TFLOP/s, MI355X dense FP64 matrix peak
 HBM_PEAK = 8000.0  # GB/s
+KERNEL_SRC = os.path.join(ROOT, "paper_1312_2415_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_kernel_sigma_L28_N12_D2500_traffic.json")
+PASS_KERNEL = {"pass1": "gemm_kernel<0> (sigma pass 1: T = X psi)",
+               "pass2": "gemm_kernel<1> (sigma pass 2: sigma += T Y^T)"}
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def stored_traffic(pass_name: str):
+    """HBM bytes per launch of a sigma pass from the committed counter summary,
+    or None when it is missing or was taken on other kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_hip_sha256") != kernel_source_hash():
+        return None
+    ent = rec.get("per_launch", {}).get(pass_name)
+    if not ent:
+        return None
+    return ent.get("fetch_bytes", 0.0) + ent.get("write_bytes", 0.0)
 
 
 def cpu_baseline(seconds: float, L: int, N: int, twoS: int, irrep: int, seed: int, D: int):
@@ -116,7 +147,8 @@ def main():
     ap.add_argument("--twoS", type=int, default=0)
     ap.add_argument("--irrep", type=int, default=0)
     ap.add_argument("--D", type=int, default=2500)
-    ap.add_argument("--ramp", type=str, default="500,1000")
+    ap.add_argument("--copy-probe-mib", type=int, default=1024,
+                    help="size of the reference streaming copy (HBM counter scale); 0 = skip")
     ap.add_argument("--seed", type=int, default=1003)
     ap.add_argument("--dav-tol", type=float, default=1e-7)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -139,13 +171,18 @@ def main():
     g.set_integrals(I.h, I.eri)
     g.set_target(N, args.twoS, args.irrep)
     g.set_davidson(args.dav_tol, 32, 100)
-    ramp = [int(x) for x in args.ramp.split(",") if x.strip()]
-    g.init_mps(ramp[0] if ramp else args.D)
+    copy_gbps = None
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        sec = g.copy_probe(n, 5)
+        copy_gbps = 16.0 * n / sec / 1e9
+        print(f"copy probe {args.copy_probe_mib} MiB: {1e3 * sec:.3f} ms/launch, {copy_gbps:.0f} GB/s", file=sys.stderr,
+              flush=True)
+    g.init_mps(args.D)
     for w in range(args.warmup):
-        D = ramp[w] if w < len(ramp) else args.D
         t = time.time()
-        e, _ = g.sweep(D)
-        print(f"warmup sweep {w + 1}/{args.warmup} D={D} E={e:.10f} {time.time() - t:.1f}s", file=sys.stderr,
+        e, _ = g.sweep(args.D)
+        print(f"warmup sweep {w + 1}/{args.warmup} D={args.D} E={e:.10f} {time.time() - t:.1f}s", file=sys.stderr,
               flush=True)
     g.stats_reset()
     t0 = time.perf_counter()
@@ -161,8 +198,14 @@ def main():
     sec_per_sweep = (t1 - t0) / args.steps
     sigma_tflops = st["flops_sigma"] / max(st["t_sigma"], 1e-12) / 1e12
     avg_sigma_ms = 1e3 * st["t_sigma"] / max(st["n_sigma"], 1)
-    flops_per_sigma = st["flops_sigma"] / max(st["n_sigma"], 1)
     e_min, e_last, wd = g.energy()
+    dom = max(("pass1", "pass2"), key=lambda k: st[k]["t"])
+    ps = st[dom]
+    nl = max(ps["launches"], 1)
+    flops_per_launch = ps["flops"] / nl
+    bytes_per_launch = ps["bytes"] / nl
+    launch_ms = 1e3 * ps["t"] / nl
+    achieved = flops_per_launch / max(launch_ms, 1e-12) / 1e9
     line = {
         "metric": METRIC,
         "value": sigma_tflops,
@@ -179,18 +222,23 @@ def main():
         "config": {"workload": f"spin-adapted two-site DMRG sweep, L={L} N={N} 2S={args.twoS} D2h irrep {args.irrep}, "
                                f"D_SU(2)={args.D}, seeded synthetic integrals (seed {args.seed})",
                    "L": L, "N": N, "twoS": args.twoS, "D": args.D, "point_group": "D2h",
-                   "ramp": ramp, "davidson_tol": args.dav_tol},
+                   "davidson_tol": args.dav_tol},
         "s_per_sweep": sec_per_sweep,
         "sigma_calls": st["n_sigma"],
         "sigma_ms_avg": avg_sigma_ms,
         "energy_min": e_min,
         "energy_last_sweep": energies[-1],
         "wdisc_max": wd,
-        "roofline": {"bound": "alu", "achieved": flops_per_sigma / max(avg_sigma_ms, 1e-9) / 1e9,
-                     "peak": FP64_VECTOR_PEAK, "unit": "TFLOP/s",
-                     "frac": (flops_per_sigma / max(avg_sigma_ms, 1e-9) / 1e9) / FP64_VECTOR_PEAK,
-                     "traffic": None, "kernel": "triple_kernel (H_eff sigma tasks)",
-                     "flops_per_launch": flops_per_sigma},
+        "sigma_passes": {k: {"ms_per_launch": 1e3 * st[k]["t"] / max(st[k]["launches"], 1),
+                             "tflops": st[k]["flops"] / max(st[k]["t"], 1e-12) / 1e12,
+                             "share_of_sigma_time": st[k]["t"] / max(st["t_sigma"], 1e-12)}
+                         for k in ("pass1", "pass2")},
+        "copy_probe_GBps": copy_gbps,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_MFMA_PEAK, "traffic": stored_traffic(dom),
+                     "kernel": PASS_KERNEL[dom], "flops_per_launch": flops_per_launch,
+                     "algorithmic_bytes_per_launch": bytes_per_launch, "launch_ms_avg": launch_ms,
+                     "launches": ps["launches"]},
     }
     g.close()
     if not args.no_cpu_baseline:

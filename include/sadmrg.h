@@ -178,6 +178,20 @@ int sadmrg_stats_reset(sadmrg_ctx* ctx);
  * stacks read + vector in/out, per call) and the largest enlarged-operator
  * footprint of one micro-iteration (both enlarged blocks). */
 int sadmrg_stats_bytes(sadmrg_ctx* ctx, double* bytes_sigma, double* max_enlarged_bytes);
+/* Sigma is evaluated by two grouped-GEMM launches (pass 1: T = X psi, pass 2:
+ * sigma += T Y^T) plus an ordered reduction.  pass1[4] and pass2[4] receive,
+ * since the last reset: kernel seconds (HIP events on the context stream
+ * around each launch), algorithmic flops, algorithmic bytes (each GEMM
+ * operand read once, each workspace/output block written once) and the number
+ * of launches.  Either pointer may be NULL. */
+int sadmrg_stats_passes(sadmrg_ctx* ctx, double* pass1, double* pass2);
+
+/* Reference copy for HBM byte counters and bandwidth: allocates two device
+ * arrays of n doubles, runs a plain streaming-copy kernel `reps` times on the
+ * context stream (8n bytes read + 8n bytes written per launch) and returns
+ * the mean kernel seconds per launch.  Frees both arrays.  Errors: EINVAL
+ * (n or reps not positive), ENOMEM, EDEVICE. */
+int sadmrg_debug_copy_probe(sadmrg_ctx* ctx, int64_t n, int reps, double* seconds);
 
 /* Description of the last failure (static until the next call on ctx). */
 const char* sadmrg_last_error(const sadmrg_ctx* ctx);

@@ -60,6 +60,8 @@ def load_library(path: str | None = None):
         "sadmrg_stats": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl), P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_reset": (c_int, [c_vp]),
         "sadmrg_stats_bytes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
+        "sadmrg_stats_passes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
+        "sadmrg_debug_copy_probe": (c_int, [c_vp, ctypes.c_int64, c_int, P(c_dbl)]),
         "sadmrg_last_error": (ctypes.c_char_p, [c_vp]),
         "sadmrg_debug_coupling": (c_int, [c_int, P(c_int), P(c_dbl)]),
     }
@@ -234,8 +236,20 @@ class SaDMRG:
                                         ctypes.byref(fs), ctypes.byref(tb)))
         bs, me = ctypes.c_double(), ctypes.c_double()
         self._chk(self.lib.sadmrg_stats_bytes(self.h, ctypes.byref(bs), ctypes.byref(me)))
-        return {"t_sigma": ts.value, "n_sigma": ns.value, "t_micro": tm.value, "flops_sigma": fs.value,
-                "t_blocking": tb.value, "bytes_sigma": bs.value, "max_enlarged_bytes": me.value}
+        p1 = (ctypes.c_double * 4)()
+        p2 = (ctypes.c_double * 4)()
+        self._chk(self.lib.sadmrg_stats_passes(self.h, p1, p2))
+        out = {"t_sigma": ts.value, "n_sigma": ns.value, "t_micro": tm.value, "flops_sigma": fs.value,
+               "t_blocking": tb.value, "bytes_sigma": bs.value, "max_enlarged_bytes": me.value}
+        for name, arr in (("pass1", p1), ("pass2", p2)):
+            out[name] = {"t": arr[0], "flops": arr[1], "bytes": arr[2], "launches": int(arr[3])}
+        return out
+
+    def copy_probe(self, n: int, reps: int = 5) -> float:
+        """Mean seconds of the library's plain streaming-copy kernel over n doubles."""
+        s = ctypes.c_double()
+        self._chk(self.lib.sadmrg_debug_copy_probe(self.h, int(n), int(reps), ctypes.byref(s)))
+        return s.value
 
     def stats_reset(self):
         self._chk(self.lib.sadmrg_stats_reset(self.h))

@@ -1014,6 +1014,12 @@ struct GemmList {
   }
   // block registered at `first` (rows x cols) += coef * opA(A)[rows x K] * opB(B)[K x cols]
   void add(int first, int rows, int cols, const GTask& base) {
+    if (base.K <= 0 || rows <= 0 || cols <= 0) return;
+    // the kernel addresses each operand of a tile with 32-bit byte offsets
+    // (element offsets up to (K + 64) * ld must stay below 2^28)
+    const int64_t lim = (int64_t)1 << 28;
+    if ((int64_t)(base.K + 64) * std::max(base.lda, TS) >= lim || (int64_t)(base.K + 64) * std::max(base.ldb, TS) >= lim)
+      fail(-4, "block product too large for the grouped GEMM kernel");
     const int ntc = (cols + TS - 1) / TS;
     for (int r0 = 0, tr = 0; r0 < rows; r0 += TS, ++tr)
       for (int c0 = 0, tc = 0; c0 < cols; c0 += TS, ++tc) {
@@ -1031,8 +1037,9 @@ struct GemmList {
     DArr<RTile> reds;
     DBuf part;
     int ntiles = 0, nreds = 0;
+    int tag = 2;
     void run(Stream st) const {
-      launch_gemm(tiles.p, ntiles, tasks.p, st);
+      launch_gemm(tiles.p, ntiles, tasks.p, tag, st);
       launch_reduce(reds.p, nreds, st);
     }
   };
@@ -1128,6 +1135,10 @@ struct TwoPass {
   GemmList::Plan p1, p2;
   DBuf ws;
   double flops = 0.0;  // algorithmic: sum of the two GEMMs of every product
+  double flops1 = 0.0, flops2 = 0.0;  // pass 1 / pass 2 shares
+  // Algorithmic bytes of each pass: every GEMM reads its two operands once and
+  // pass 1 writes its workspace tile once; pass 2 adds the output blocks once.
+  double bytes1 = 0.0, bytes2 = 0.0;
   int64_t nprod = 0;
   void run(Stream st) const {
     p1.run(st);
@@ -1135,7 +1146,8 @@ struct TwoPass {
   }
 };
 
-static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Triple>& tr, TwoPass& tp, Stream st) {
+static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Triple>& tr, TwoPass& tp, Stream st,
+                           bool sigma = false) {
   std::vector<int64_t> slot(tr.size(), -1);
   int64_t ws = 0;
   for (size_t i = 0; i < tr.size(); ++i)
@@ -1147,7 +1159,8 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
   GemmList g1, g2;
   std::vector<int> first(outs.size());
   for (size_t b = 0; b < outs.size(); ++b) first[b] = g2.add_block(outs[b].out, outs[b].rows, outs[b].cols, outs[b].ld, 0);
-  double fl = 0.0;
+  double fl = 0.0, f1 = 0.0, by1 = 0.0, by2 = 0.0;
+  for (const OutBlk& o : outs) by2 += 8.0 * (double)o.rows * o.cols;
   for (size_t i = 0; i < tr.size(); ++i) {
     const Triple& x = tr[i];
     const int R = outs[x.blk].rows, Cc = outs[x.blk].cols;
@@ -1156,21 +1169,35 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
     if (x.flags & TT_IDENT_C) {
       g2.add(first[x.blk], R, Cc, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA, x.coef});
       fl += 2.0 * R * x.K1 * Cc;
+      by2 += 8.0 * ((double)R * x.K1 + (double)x.K1 * Cc);
     } else if (x.flags & TT_IDENT_A) {
       g2.add(first[x.blk], R, Cc, GTask{x.b, x.c, x.ldb, x.ldc, x.K2, trC, x.coef});
       fl += 2.0 * R * x.K2 * Cc;
+      by2 += 8.0 * ((double)R * x.K2 + (double)x.K2 * Cc);
     } else {
       double* T = tp.ws.p + slot[i];
-      const int f1 = g1.add_block(T, R, x.K2, x.K2, 1);
-      g1.add(f1, R, x.K2, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA, 1.0});
+      const int b1 = g1.add_block(T, R, x.K2, x.K2, 1);
+      g1.add(b1, R, x.K2, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA, 1.0});
       g2.add(first[x.blk], R, Cc, GTask{T, x.c, x.K2, x.ldc, x.K2, trC, x.coef});
       fl += 2.0 * R * x.K1 * x.K2 + 2.0 * R * x.K2 * Cc;
+      f1 += 2.0 * R * x.K1 * x.K2;
+      by1 += 8.0 * ((double)R * x.K1 + (double)x.K1 * x.K2 + (double)R * x.K2);
+      by2 += 8.0 * ((double)R * x.K2 + (double)x.K2 * Cc);
     }
   }
+  tp.bytes1 = by1;
+  tp.bytes2 = by2;
   tp.flops = fl;
+  tp.flops1 = f1;
+  tp.flops2 = fl - f1;
+  tp.p1.tag = sigma ? 0 : 2;
+  tp.p2.tag = sigma ? 1 : 2;
   tp.nprod = (int64_t)tr.size();
+  const int tag1 = tp.p1.tag, tag2 = tp.p2.tag;
   g1.plan(tp.p1, st);
   g2.plan(tp.p2, st);
+  tp.p1.tag = tag1;
+  tp.p2.tag = tag2;
 }
 
 // ---------------------------------------------------------------------------
@@ -1229,6 +1256,8 @@ struct Engine {
   bool warned = false;
   // statistics
   double t_sigma = 0, t_micro = 0, f_sigma = 0, t_block = 0, b_sigma = 0, max_enl_bytes = 0;
+  double t_pass1 = 0, t_pass2 = 0, f_pass1 = 0, f_pass2 = 0, b_pass1 = 0, b_pass2 = 0;
+  int64_t n_pass1 = 0, n_pass2 = 0;
   int64_t n_sigma = 0;
   // Davidson work buffers
   DBuf dV, dW, dHs, dsmall, dpartial, dx_, dax, dr, dt;
@@ -1654,7 +1683,7 @@ struct Engine {
     }
     for (auto& [s, o] : touched) bytes += 8.0 * (s == 0 ? X.lay(o).nnz : Y.lay(o).nnz);
     bytes += 16.0 * step.n;
-    build_two_pass(outs, trs, step.plan, st);
+    build_two_pass(outs, trs, step.plan, st, true);
     step.flops = step.plan.flops;
     step.bytes = bytes;
     step.ntasks = (int64_t)trs.size();
@@ -1844,13 +1873,25 @@ struct Engine {
   void sigma_fixed() {
     dev_zero(step.out.p, (size_t)std::max<int64_t>(step.n, 1) * 8, st);
     void* e0 = dev_event_record(st);
-    step.plan.run(st);
+    step.plan.p1.run(st);
     void* e1 = dev_event_record(st);
-    t_sigma += dev_event_elapsed(e0, e1);
-    dev_event_free(e0);
-    dev_event_free(e1);
+    launch_gemm(step.plan.p2.tiles.p, step.plan.p2.ntiles, step.plan.p2.tasks.p, step.plan.p2.tag, st);
+    void* e2 = dev_event_record(st);
+    launch_reduce(step.plan.p2.reds.p, step.plan.p2.nreds, st);
+    void* e3 = dev_event_record(st);
+    const double t1 = dev_event_elapsed(e0, e1), t2 = dev_event_elapsed(e1, e2), t3 = dev_event_elapsed(e2, e3);
+    t_sigma += t1 + t2 + t3;
+    t_pass1 += t1;
+    t_pass2 += t2;
+    for (void* ev : {e0, e1, e2, e3}) dev_event_free(ev);
     ++n_sigma;
     f_sigma += step.flops;
+    f_pass1 += step.plan.flops1;
+    f_pass2 += step.plan.flops2;
+    b_pass1 += step.plan.bytes1;
+    b_pass2 += step.plan.bytes2;
+    ++n_pass1;
+    if (step.plan.p2.ntiles > 0) ++n_pass2;
     b_sigma += step.bytes;
   }
   void sigma_vec(const double* x, double* y) {
@@ -2718,10 +2759,53 @@ int sadmrg_debug_task_shapes(sadmrg_ctx* ctx, int* out, int64_t* n) {
   });
 }
 
+int sadmrg_stats_passes(sadmrg_ctx* ctx, double* pass1, double* pass2) {
+  return guard(ctx, [&] {
+    auto& E = ctx->e;
+    if (pass1) {
+      pass1[0] = E.t_pass1;
+      pass1[1] = E.f_pass1;
+      pass1[2] = E.b_pass1;
+      pass1[3] = (double)E.n_pass1;
+    }
+    if (pass2) {
+      pass2[0] = E.t_pass2;
+      pass2[1] = E.f_pass2;
+      pass2[2] = E.b_pass2;
+      pass2[3] = (double)E.n_pass2;
+    }
+    return 0;
+  });
+}
+
+int sadmrg_debug_copy_probe(sadmrg_ctx* ctx, int64_t n, int reps, double* seconds) {
+  return guard(ctx, [&] {
+    if (n <= 0 || reps <= 0) sadmrg::fail(SADMRG_EINVAL, "copy probe: n and reps must be positive");
+    sadmrg::DBuf a, b;
+    a.alloc((size_t)n);
+    b.alloc((size_t)n);
+    sadmrg::launch_fill_uniform(a.p, n, 1, 2, ctx->e.st);
+    double t = 0.0;
+    for (int r = 0; r < reps; ++r) {
+      void* e0 = sadmrg::dev_event_record(ctx->e.st);
+      sadmrg::launch_copy(b.p, a.p, n, ctx->e.st);
+      void* e1 = sadmrg::dev_event_record(ctx->e.st);
+      t += sadmrg::dev_event_elapsed(e0, e1);
+      sadmrg::dev_event_free(e0);
+      sadmrg::dev_event_free(e1);
+    }
+    sadmrg::dev_sync(ctx->e.st);
+    if (seconds) *seconds = t / reps;
+    return 0;
+  });
+}
+
 int sadmrg_stats_reset(sadmrg_ctx* ctx) {
   return guard(ctx, [&] {
     auto& E = ctx->e;
     E.t_sigma = E.t_micro = E.f_sigma = E.t_block = E.b_sigma = E.max_enl_bytes = 0;
+    E.t_pass1 = E.t_pass2 = E.f_pass1 = E.f_pass2 = E.b_pass1 = E.b_pass2 = 0;
+    E.n_pass1 = E.n_pass2 = 0;
     E.n_sigma = 0;
     return 0;
   });

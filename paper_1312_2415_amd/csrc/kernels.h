@@ -115,7 +115,8 @@ struct GTask {
   int lda, ldb, K, flags;
   double coef;
 };
-void launch_gemm(const GTile* tiles, int ntiles, const GTask* tasks, Stream st);
+// tag: 0 = sigma pass 1, 1 = sigma pass 2, 2 = other (separate kernel symbols for profiling)
+void launch_gemm(const GTile* tiles, int ntiles, const GTask* tasks, int tag, Stream st);
 void launch_reduce(const RTile* reds, int nred, Stream st);
 void launch_gather(const GatherDst* dsts, int ndst, const GatherSrc* srcs, Stream st);
 void launch_combo(const ComboOut* outs, int nout, const ComboIn* ins, int64_t max_nnz, Stream st);
@@ -140,6 +141,8 @@ void launch_normalize(double* y, const double* nrm2, int64_t n, Stream st);
 void launch_syev_small(const double* H, int k, int ld, double* evals, double* evecs, Stream st);
 // uniform [-1,1) numbers from the SplitMix64 counter generator
 void launch_fill_uniform(double* p, int64_t n, uint64_t seed, uint64_t stream, Stream st);
+// Plain streaming copy dst[i] = src[i] (reference kernel for HBM byte counters).
+void launch_copy(double* dst, const double* src, int64_t n, Stream st);
 // a[r][c] *= s[r]  /  a[r][c] *= s[c]
 void launch_scale_rows(double* a, int rows, int cols, int ld, const double* s, Stream st);
 void launch_scale_cols(double* a, int rows, int cols, int ld, const double* s, Stream st);
