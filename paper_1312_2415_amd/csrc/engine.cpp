@@ -1034,85 +1034,127 @@ struct GemmList {
   struct Plan {
     DArr<GTile> tiles;
     DArr<GTask> tasks;
+    DArr<int> wstart;
     DArr<RTile> reds;
     DBuf part;
-    int ntiles = 0, nreds = 0;
+    int ntiles = 0, nwg = 0, nreds = 0;
+    bool stream = false;
     int tag = 2;
     void run(Stream st) const {
-      launch_gemm(tiles.p, ntiles, tasks.p, tag, st);
+      launch_gemm(tiles.p, tasks.p, wstart.p, nwg, stream, tag, st);
       launch_reduce(reds.p, nreds, st);
     }
   };
 
-  void plan(Plan& pl, Stream st, double target = 0.0) {
+  // Estimated workgroup cycles of one task in a tile with `cols` columns:
+  // MFMA time of a wave (two 64-cycle MFMAs per k-step pair and 16-column
+  // block) plus a fixed cost per staged chunk and per task.
+  static double task_cost(int K, int cols) {
+    const int ncb = (cols + 15) / 16;
+    const int pairs = 4 * (K / GK_HOST) + (K % GK_HOST + 7) / 8;
+    return 128.0 * ncb * pairs + 400.0 * ((K + GK_HOST - 1) / GK_HOST) + 200.0;
+  }
+  static constexpr int GK_HOST = 32;
+  static constexpr double TILE_COST = 1500.0;
+
+  // Assign the tiles, in order, to contiguous per-workgroup ranges of about
+  // equal estimated cost, `gpc` workgroups per CU; gpc = 0 gives every tile
+  // its own workgroup (the hardware then balances the load).  An
+  // accumulating tile (mode 0) may be cut between two workgroups: its pieces
+  // write partial tiles that a second kernel adds in a fixed order.
+  void plan(Plan& pl, Stream st, int gpc) {
     std::vector<int> cnt(tiles.size() + 1, 0);
     for (auto& t : items) cnt[t.tile + 1]++;
     for (size_t i = 0; i < tiles.size(); ++i) cnt[i + 1] += cnt[i];
     std::vector<GTask> flat(items.size());
-    std::vector<double> wt(items.size());
     std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-    for (auto& t : items) {
-      wt[pos[t.tile]] = t.w;
-      flat[pos[t.tile]++] = t.t;
-    }
+    for (auto& t : items) flat[pos[t.tile]++] = t.t;
+    std::vector<double> cost(flat.size());
     double total = 0.0;
-    for (double w : wt) total += w;
-    // enough chunks to fill 256 CUs a few workgroups deep without multiplying
-    // the partial tiles to reduce
-    if (target <= 0.0) target = std::max(2.0e5, total / 2048.0);
+    for (size_t i = 0; i < tiles.size(); ++i) {
+      if (cnt[i] == cnt[i + 1] && tiles[i].mode == 0) continue;
+      total += TILE_COST;
+      for (int t = cnt[i]; t < cnt[i + 1]; ++t) total += (cost[t] = task_cost(flat[t].K, tiles[i].cols));
+    }
+    static int cus = 0;
+    if (cus <= 0) cus = std::max(1, dev_cu_count());
+    const int G = gpc > 0 ? gpc * cus : INT32_MAX;
+    const double target = gpc > 0 ? total / G : 0.0;
+
     std::vector<GTile> chunks;
-    std::vector<int64_t> poff;
-    struct PR {
-      size_t tile;
-      int first, n;
+    std::vector<int> owner;  // source tile of every chunk
+    std::vector<int> ws{0};
+    double acc = 0.0;
+    auto emit = [&](size_t i, int t0, int t1) {
+      GTile c = tiles[i];
+      c.t0 = t0;
+      c.t1 = t1;
+      chunks.push_back(c);
+      owner.push_back((int)i);
     };
-    std::vector<PR> pr;
-    int64_t npart = 0;
+    auto cut = [&]() {
+      if ((int)ws.size() < G && ws.back() < (int)chunks.size()) {
+        ws.push_back((int)chunks.size());
+        acc = 0.0;
+      }
+    };
     for (size_t i = 0; i < tiles.size(); ++i) {
       const int a = cnt[i], b = cnt[i + 1];
-      if (a == b) continue;
-      std::vector<std::pair<int, int>> rng;
-      double w = 0.0;
-      int s = a;
-      if (tiles[i].mode == 0)
-        for (int t = a; t < b; ++t) {
-          w += wt[t];
-          if (w >= target && t + 1 < b) {
-            rng.push_back({s, t + 1});
-            s = t + 1;
-            w = 0.0;
-          }
+      if (gpc <= 0) {
+        if (a < b || tiles[i].mode != 0) {
+          emit(i, a, b);
+          cut();
         }
-      rng.push_back({s, b});
-      if (rng.size() == 1) {
-        GTile c = tiles[i];
-        c.t0 = a;
-        c.t1 = b;
-        chunks.push_back(c);
-        poff.push_back(-1);
         continue;
       }
-      pr.push_back({i, (int)chunks.size(), (int)rng.size()});
-      for (auto& [x, y] : rng) {
-        GTile c = tiles[i];
-        c.t0 = x;
-        c.t1 = y;
-        chunks.push_back(c);
-        poff.push_back(npart);
-        npart += (int64_t)c.rows * c.cols;
+      if (a == b) {
+        if (tiles[i].mode == 0) continue;  // nothing to add
+        emit(i, a, a);                     // overwrite with zeros
+        if ((acc += TILE_COST) >= target) cut();
+        continue;
       }
+      acc += TILE_COST;
+      int s = a;
+      for (int t = a; t < b; ++t) {
+        acc += cost[t];
+        if (acc >= target && (tiles[i].mode == 0 || t + 1 == b) && (int)ws.size() < G) {
+          emit(i, s, t + 1);
+          s = t + 1;
+          cut();
+        }
+      }
+      if (s < b) emit(i, s, b);
+    }
+    if (ws.back() < (int)chunks.size()) ws.push_back((int)chunks.size());
+
+    // partial tiles for the tiles that were cut (their pieces are adjacent)
+    int64_t npart = 0;
+    std::vector<RTile> reds;
+    std::vector<int64_t> poff(chunks.size(), -1);
+    for (size_t j = 0; j < chunks.size();) {
+      size_t e = j + 1;
+      while (e < chunks.size() && owner[e] == owner[j]) ++e;
+      if (e - j > 1) {
+        const GTile& t = tiles[owner[j]];
+        reds.push_back({t.out, nullptr, t.ld, t.rows, t.cols, (int)(e - j)});
+        for (size_t q = j; q < e; ++q) {
+          poff[q] = npart;
+          npart += (int64_t)t.rows * t.cols;
+        }
+      }
+      j = e;
     }
     pl.part.alloc((size_t)std::max<int64_t>(npart, 1));
     for (size_t j = 0; j < chunks.size(); ++j) chunks[j].part = poff[j] >= 0 ? pl.part.p + poff[j] : nullptr;
-    std::vector<RTile> reds;
-    for (auto& p : pr) {
-      const GTile& t = tiles[p.tile];
-      reds.push_back({t.out, chunks[p.first].part, t.ld, t.rows, t.cols, p.n});
-    }
+    for (size_t j = 0, r = 0; j < chunks.size(); ++j)
+      if (poff[j] >= 0 && (j == 0 || owner[j - 1] != owner[j])) reds[r++].part = chunks[j].part;
     pl.tiles.put(chunks, st);
     pl.tasks.put(flat, st);
+    pl.wstart.put(ws, st);
     pl.reds.put(reds, st);
     pl.ntiles = (int)chunks.size();
+    pl.nwg = (int)ws.size() - 1;
+    pl.stream = gpc > 0;
     pl.nreds = (int)reds.size();
   }
 };
@@ -1130,6 +1172,16 @@ struct OutBlk {
   double* out;
   int rows, cols, ld;
 };
+
+// Workgroups per CU of the grouped-GEMM plans (0 = one tile per workgroup):
+// the first pass (one product per tile, short K) is best balanced by the
+// hardware; the second (long accumulations) by cost-balanced ranges.
+#ifndef GEMM_GPC_PASS1
+#define GEMM_GPC_PASS1 0
+#endif
+#ifndef GEMM_GPC_PASS2
+#define GEMM_GPC_PASS2 12
+#endif
 
 struct TwoPass {
   GemmList::Plan p1, p2;
@@ -1194,8 +1246,8 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
   tp.p2.tag = sigma ? 1 : 2;
   tp.nprod = (int64_t)tr.size();
   const int tag1 = tp.p1.tag, tag2 = tp.p2.tag;
-  g1.plan(tp.p1, st);
-  g2.plan(tp.p2, st);
+  g1.plan(tp.p1, st, GEMM_GPC_PASS1);
+  g2.plan(tp.p2, st, GEMM_GPC_PASS2);
   tp.p1.tag = tag1;
   tp.p2.tag = tag2;
 }
@@ -1875,7 +1927,8 @@ struct Engine {
     void* e0 = dev_event_record(st);
     step.plan.p1.run(st);
     void* e1 = dev_event_record(st);
-    launch_gemm(step.plan.p2.tiles.p, step.plan.p2.ntiles, step.plan.p2.tasks.p, step.plan.p2.tag, st);
+    launch_gemm(step.plan.p2.tiles.p, step.plan.p2.tasks.p, step.plan.p2.wstart.p, step.plan.p2.nwg, step.plan.p2.stream,
+                step.plan.p2.tag, st);
     void* e2 = dev_event_record(st);
     launch_reduce(step.plan.p2.reds.p, step.plan.p2.nreds, st);
     void* e3 = dev_event_record(st);

@@ -115,8 +115,13 @@ struct GTask {
   int lda, ldb, K, flags;
   double coef;
 };
+// stream: workgroup g processes the tiles [wstart[g], wstart[g+1]) in order
+// (nwg groups); otherwise workgroup g processes tile g (nwg = tile count,
+// wstart unused).
 // tag: 0 = sigma pass 1, 1 = sigma pass 2, 2 = other (separate kernel symbols for profiling)
-void launch_gemm(const GTile* tiles, int ntiles, const GTask* tasks, int tag, Stream st);
+void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag, Stream st);
+// Number of compute units of the current device.
+int dev_cu_count();
 void launch_reduce(const RTile* reds, int nred, Stream st);
 void launch_gather(const GatherDst* dsts, int ndst, const GatherSrc* srcs, Stream st);
 void launch_combo(const ComboOut* outs, int nout, const ComboIn* ins, int64_t max_nnz, Stream st);

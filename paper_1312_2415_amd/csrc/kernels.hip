@@ -111,10 +111,13 @@ __device__ inline d4_t mfma16(double a, double b, d4_t c) {
 // ---------------------------------------------------------------------------
 // Grouped GEMM on the FP64 matrix cores.
 //
-// One workgroup (4 wavefronts) per output tile of at most 64 x 64; wave w
-// owns rows [16w, 16w+16) as four 16 x 16 accumulator blocks.  A tile sums the
-// products of its task range [t0, t1): the (task, k-chunk) pairs form one
-// stream, staged through LDS in chunks of GK = 32 along K.  opA is kept in
+// Output tiles of at most 64 x 64; a tile sums the products of its task range
+// [t0, t1).  Workgroup g (4 wavefronts) processes the tiles
+// [wstart[g], wstart[g+1]) in order, as one stream of (tile, task, k-chunk)
+// items, so the loads of the next tile start while the current one is still
+// being multiplied; the host balances the ranges by estimated cost.  Wave w
+// owns rows [16w, 16w+16) of a tile as four 16 x 16 accumulator blocks.
+// Items are staged through LDS in chunks of GK = 32 along K.  opA is kept in
 // LDS as [row][k] and opB as [col][k] (row stride SLD doubles), so that every
 // lane reads its MFMA operands for two k-steps with one 16-byte LDS read.
 // The k index of the product is permuted inside a chunk (k-step pair p, lane
@@ -130,7 +133,7 @@ __device__ inline d4_t mfma16(double a, double b, d4_t c) {
 // the extent are real data of the operand; they only reach output rows
 // (cols) that are never written.  The next chunk is loaded into registers
 // while the current one is multiplied out of LDS (one LDS buffer of 34 KB:
-// four workgroups per CU).  Task records are read one task ahead.
+// four workgroups per CU).  Task and tile records are read one ahead.
 // ---------------------------------------------------------------------------
 constexpr int GK = 32;
 constexpr int SLD = 34;                 // LDS row stride (doubles): 16-byte rows, conflict-free 16-byte reads
@@ -160,6 +163,20 @@ __device__ inline GTask g_task(const GTask* __restrict__ tasks, int i) {
   u.K = g_u(t.K);
   u.flags = g_u(t.flags);
   u.coef = __builtin_bit_cast(double, g_u64(__builtin_bit_cast(uint64_t, t.coef)));
+  return u;
+}
+
+__device__ inline GTile g_tile(const GTile* __restrict__ tiles, int i) {
+  const GTile t = tiles[i];
+  GTile u;
+  u.out = (double*)g_u64((uint64_t)t.out);
+  u.part = (double*)g_u64((uint64_t)t.part);
+  u.ld = g_u(t.ld);
+  u.rows = g_u(t.rows);
+  u.cols = g_u(t.cols);
+  u.mode = g_u(t.mode);
+  u.t0 = g_u(t.t0);
+  u.t1 = g_u(t.t1);
   return u;
 }
 
@@ -234,10 +251,39 @@ __device__ inline void g_mac(d4_t (&acc)[4], const double* sA, const double* sB,
   }
 }
 
+struct GOut {  // what the epilogue of a tile needs
+  double* out;
+  double* part;
+  int ld, rows, cols, mode;
+};
+__device__ inline GOut g_out(const GTile& t) { return GOut{t.out, t.part, t.ld, t.rows, t.cols, t.mode}; }
+
+__device__ inline void g_write(const GOut& tile, const d4_t (&acc)[4], int r0, int li, int lk) {
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int col = 16 * b + li;
+    if (col >= tile.cols) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int orow = r0 + lk + 4 * r;
+      if (orow >= tile.rows) continue;
+      if (tile.part)
+        tile.part[orow * tile.cols + col] = acc[b][r];
+      else if (tile.mode == 1)
+        tile.out[(int64_t)orow * tile.ld + col] = acc[b][r];
+      else
+        tile.out[(int64_t)orow * tile.ld + col] += acc[b][r];
+    }
+  }
+}
+
+// One tile per workgroup (blockIdx.x = tile), no state carried between tiles:
+// the hardware dispatcher balances short, independent tiles best.
 // TAG only separates the symbols of the launch sites for profiling:
 // 0 = sigma pass 1, 1 = sigma pass 2, 2 = renormalisation / other products.
 template <int TAG>
-__global__ __launch_bounds__(256, 4) void gemm_kernel(const GTile* __restrict__ tiles, const GTask* __restrict__ tasks) {
+__global__ __launch_bounds__(256, 4) void gemm_tile_kernel(const GTile* __restrict__ tiles,
+                                                           const GTask* __restrict__ tasks) {
   __shared__ __attribute__((aligned(16))) double sA[64 * SLD];
   __shared__ __attribute__((aligned(16))) double sB[64 * SLD];
   const GTile tile = tiles[blockIdx.x];
@@ -300,35 +346,149 @@ __global__ __launch_bounds__(256, 4) void gemm_kernel(const GTile* __restrict__ 
       __syncthreads();
     }
   }
-  if (active) {
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int col = 16 * b + li;
-      if (col >= tile.cols) continue;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int orow = r0 + lk + 4 * r;
-        if (orow >= tile.rows) continue;
-        if (tile.part)
-          tile.part[orow * tile.cols + col] = acc[b][r];
-        else if (tile.mode == 1)
-          tile.out[(int64_t)orow * tile.ld + col] = acc[b][r];
-        else
-          tile.out[(int64_t)orow * tile.ld + col] += acc[b][r];
+  if (active) g_write(g_out(tile), acc, r0, li, lk);
+}
+
+// Workgroup g streams the tiles [wstart[g], wstart[g+1]).
+// TAG only separates the symbols of the launch sites for profiling:
+// 0 = sigma pass 1, 1 = sigma pass 2, 2 = renormalisation / other products.
+template <int TAG>
+__global__ __launch_bounds__(256, 3) void gemm_stream_kernel(const GTile* __restrict__ tiles,
+                                                             const GTask* __restrict__ tasks,
+                                                             const int* __restrict__ wstart) {
+  __shared__ __attribute__((aligned(16))) double sA[64 * SLD];
+  __shared__ __attribute__((aligned(16))) double sB[64 * SLD];
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid / 64);  // wave index, scalar
+  const int l = tid % 64;
+  const int li = l % 16, lk = l / 16;
+  const int r0 = 16 * w;
+  int ft = wstart[blockIdx.x];
+  const int fe = wstart[blockIdx.x + 1];
+  if (ft >= fe) return;
+
+  // fetch side: tile ft (record FT), task t (record cur) at chunk k0; the
+  // next task of the tile (nxt), the next tile (NT) and its first task (ncur)
+  GTile FT = g_tile(tiles, ft);
+  GTile NT = ft + 1 < fe ? g_tile(tiles, ft + 1) : FT;
+  int t = FT.t0, k0 = 0;
+  GTask cur{}, nxt{}, ncur{};
+  GOp A, B;
+  if (FT.t0 < FT.t1) {
+    cur = g_task(tasks, t);
+    nxt = t + 1 < FT.t1 ? g_task(tasks, t + 1) : cur;
+    g_op(A, cur.a, cur.lda, !(cur.flags & GT_TRANS_A), FT.rows, cur.K, tid);
+    g_op(B, cur.b, cur.ldb, (cur.flags & GT_TRANS_B) != 0, FT.cols, cur.K, tid);
+  }
+  if (ft + 1 < fe && NT.t0 < NT.t1) ncur = g_task(tasks, NT.t0);
+
+  // the staged item: registers + description
+  double ra[8], rb[8];
+  GOut MT;  // tile of the staged item
+  int kc, flags;
+  bool last;
+  double coef;
+  auto issue = [&]() {
+    MT = g_out(FT);
+    if (t < FT.t1) {
+      g_fetch(ra, A, k0, cur.K, tid);
+      g_fetch(rb, B, k0, cur.K, tid);
+      kc = min(GK, cur.K - k0);
+      coef = cur.coef;
+      flags = cur.flags;
+      k0 += GK;
+      if (k0 >= cur.K) {
+        k0 = 0;
+        if (++t < FT.t1) {
+          cur = nxt;
+          if (t + 1 < FT.t1) nxt = g_task(tasks, t + 1);
+          g_op(A, cur.a, cur.lda, !(cur.flags & GT_TRANS_A), FT.rows, cur.K, tid);
+          g_op(B, cur.b, cur.ldb, (cur.flags & GT_TRANS_B) != 0, FT.cols, cur.K, tid);
+        }
+      }
+    } else {  // a tile without products: its output is written as zero
+      kc = 0;
+      coef = 0.0;
+      flags = 0;
+    }
+    last = t >= FT.t1;
+    if (last && ++ft < fe) {
+      FT = NT;
+      t = FT.t0;
+      k0 = 0;
+      if (t < FT.t1) {
+        cur = ncur;
+        nxt = t + 1 < FT.t1 ? g_task(tasks, t + 1) : cur;
+        g_op(A, cur.a, cur.lda, !(cur.flags & GT_TRANS_A), FT.rows, cur.K, tid);
+        g_op(B, cur.b, cur.ldb, (cur.flags & GT_TRANS_B) != 0, FT.cols, cur.K, tid);
+      }
+      if (ft + 1 < fe) {
+        NT = g_tile(tiles, ft + 1);
+        if (NT.t0 < NT.t1) ncur = g_task(tasks, NT.t0);
       }
     }
+  };
+
+  d4_t acc[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = (d4_t){0.0, 0.0, 0.0, 0.0};
+  issue();
+  while (true) {
+    if (kc > 0) g_store(ra, rb, coef, flags, sA, sB, tid);
+    const GOut mt = MT;
+    const int np = (kc + 7) / 8;
+    const bool mlast = last;
+    __syncthreads();
+    const bool more = ft < fe;
+    if (more) issue();
+    const bool active = r0 < mt.rows;
+    if (active && np > 0) {
+      const int ncb = (mt.cols + 15) / 16;
+      if (ncb == 4)
+        g_mac<4>(acc, sA, sB, np, r0, li, lk);
+      else if (ncb == 3)
+        g_mac<3>(acc, sA, sB, np, r0, li, lk);
+      else if (ncb == 2)
+        g_mac<2>(acc, sA, sB, np, r0, li, lk);
+      else
+        g_mac<1>(acc, sA, sB, np, r0, li, lk);
+    }
+    if (mlast) {
+      if (active) g_write(mt, acc, r0, li, lk);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = (d4_t){0.0, 0.0, 0.0, 0.0};
+    }
+    if (!more) break;
+    __syncthreads();
   }
 }
 
-void launch_gemm(const GTile* tiles, int ntiles, const GTask* tasks, int tag, Stream st) {
-  if (ntiles <= 0) return;
-  if (tag == 0)
-    hipLaunchKernelGGL(gemm_kernel<0>, dim3(ntiles), dim3(256), 0, (hipStream_t)st, tiles, tasks);
-  else if (tag == 1)
-    hipLaunchKernelGGL(gemm_kernel<1>, dim3(ntiles), dim3(256), 0, (hipStream_t)st, tiles, tasks);
-  else
-    hipLaunchKernelGGL(gemm_kernel<2>, dim3(ntiles), dim3(256), 0, (hipStream_t)st, tiles, tasks);
+void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag, Stream st) {
+  if (nwg <= 0) return;
+  const hipStream_t hs = (hipStream_t)st;
+  if (stream) {
+    if (tag == 0)
+      hipLaunchKernelGGL(gemm_stream_kernel<0>, dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+    else if (tag == 1)
+      hipLaunchKernelGGL(gemm_stream_kernel<1>, dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+    else
+      hipLaunchKernelGGL(gemm_stream_kernel<2>, dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+  } else {
+    if (tag == 0)
+      hipLaunchKernelGGL(gemm_tile_kernel<0>, dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+    else if (tag == 1)
+      hipLaunchKernelGGL(gemm_tile_kernel<1>, dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+    else
+      hipLaunchKernelGGL(gemm_tile_kernel<2>, dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+  }
   check_launch("gemm");
+}
+
+int dev_cu_count() {
+  int dev = 0, n = 0;
+  hip_ok(hipGetDevice(&dev), "hipGetDevice");
+  hip_ok(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+  return n;
 }
 
 // Ordered sum of a tile's partial results: eight interleaved accumulators
