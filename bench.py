@@ -37,8 +37,8 @@ FP64_MFMA_PEAK = 78.6  # TFLOP/s, MI355X dense FP64 matrix peak
 HBM_PEAK = 8000.0  # GB/s
 KERNEL_SRC = os.path.join(ROOT, "paper_1312_2415_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_kernel_sigma_L28_N12_D2500_traffic.json")
-PASS_KERNEL = {"pass1": "gemm_kernel<0> (sigma pass 1: T = X psi)",
-               "pass2": "gemm_kernel<1> (sigma pass 2: sigma += T Y^T)"}
+PASS_KERNEL = {"pass1": "gemm_tile_kernel<0> (sigma pass 1: T = X psi)",
+               "pass2": "gemm_stream_kernel<1> (sigma pass 2: sigma += T Y^T)"}
 
 
 def kernel_source_hash() -> str:
