@@ -88,6 +88,19 @@ int sadmrg_set_target(sadmrg_ctx* ctx, int N, int twoS, int irrep);
  * and maximum iterations per micro-iteration. */
 int sadmrg_set_davidson(sadmrg_ctx* ctx, double tol, int max_sub, int max_iter);
 
+/* Precision of the sigma product (spec precision variant of the
+ * effective-Hamiltonian step, section "The effective Hamiltonian equation").
+ * mode 0: FP64 everywhere (default).  mode 1: every sigma product of the
+ * Davidson iterations uses FP32 copies of the operators and of psi with FP32
+ * accumulation, Davidson runs to the residual tolerance max(tol, mixed_tol)
+ * or, once below 6e-6 |theta|, until the residual stops improving (10 % over
+ * four iterations: the FP32 rounding floor), with orthogonalisation, Ritz
+ * problem and residuals in FP64, and the reported
+ * energy of each micro-iteration is the FP64 Rayleigh quotient <x|H|x>/<x|x>
+ * of the final vector (one FP64 sigma).  sadmrg_sigma follows the mode.
+ * SVD, truncation and renormalisation stay FP64.  Errors: EINVAL. */
+int sadmrg_set_precision(sadmrg_ctx* ctx, int mode, double mixed_tol);
+
 /* Seed of the counter-based generator used for the random initial MPS. */
 int sadmrg_set_seed(sadmrg_ctx* ctx, uint64_t seed);
 
@@ -185,6 +198,10 @@ int sadmrg_stats_bytes(sadmrg_ctx* ctx, double* bytes_sigma, double* max_enlarge
  * operand read once, each workspace/output block written once) and the number
  * of launches.  Either pointer may be NULL. */
 int sadmrg_stats_passes(sadmrg_ctx* ctx, double* pass1, double* pass2);
+
+/* FP32 sigma calls since the last reset: kernel seconds (conversions
+ * included), count and algorithmic flops (same definition as FP64). */
+int sadmrg_stats_mixed(sadmrg_ctx* ctx, double* t_sigma32, int64_t* n_sigma32, double* flops_sigma32);
 
 /* Reference copy for HBM byte counters and bandwidth: allocates two device
  * arrays of n doubles, runs a plain streaming-copy kernel `reps` times on the

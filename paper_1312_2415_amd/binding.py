@@ -61,6 +61,8 @@ def load_library(path: str | None = None):
         "sadmrg_stats_reset": (c_int, [c_vp]),
         "sadmrg_stats_bytes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_passes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
+        "sadmrg_stats_mixed": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl)]),
+        "sadmrg_set_precision": (c_int, [c_vp, c_int, c_dbl]),
         "sadmrg_debug_copy_probe": (c_int, [c_vp, ctypes.c_int64, c_int, P(c_dbl)]),
         "sadmrg_last_error": (ctypes.c_char_p, [c_vp]),
         "sadmrg_debug_coupling": (c_int, [c_int, P(c_int), P(c_dbl)]),
@@ -243,7 +245,14 @@ class SaDMRG:
                "t_blocking": tb.value, "bytes_sigma": bs.value, "max_enlarged_bytes": me.value}
         for name, arr in (("pass1", p1), ("pass2", p2)):
             out[name] = {"t": arr[0], "flops": arr[1], "bytes": arr[2], "launches": int(arr[3])}
+        t32, n32, f32 = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        self._chk(self.lib.sadmrg_stats_mixed(self.h, ctypes.byref(t32), ctypes.byref(n32), ctypes.byref(f32)))
+        out["fp32"] = {"t": t32.value, "calls": n32.value, "flops": f32.value}
         return out
+
+    def set_precision(self, mode: int, mixed_tol: float = 3e-5):
+        """0: FP64 sigma; 1: FP32 sigma in Davidson + FP64 Rayleigh-quotient energy."""
+        self._chk(self.lib.sadmrg_set_precision(self.h, int(mode), float(mixed_tol)))
 
     def copy_probe(self, n: int, reps: int = 5) -> float:
         """Mean seconds of the library's plain streaming-copy kernel over n doubles."""

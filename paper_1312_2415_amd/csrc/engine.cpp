@@ -1038,11 +1038,11 @@ struct GemmList {
     DArr<RTile> reds;
     DBuf part;
     int ntiles = 0, nwg = 0, nreds = 0;
-    bool stream = false;
+    bool stream = false, f32 = false;
     int tag = 2;
     void run(Stream st) const {
-      launch_gemm(tiles.p, tasks.p, wstart.p, nwg, stream, tag, st);
-      launch_reduce(reds.p, nreds, st);
+      launch_gemm(tiles.p, tasks.p, wstart.p, nwg, stream, tag, f32, st);
+      launch_reduce(reds.p, nreds, f32, st);
     }
   };
 
@@ -1283,6 +1283,12 @@ struct Step {
   int64_t n = 0;
   DBuf in, out, diag;
   TwoPass plan;
+  // FP32 mirror of the sigma evaluation (built on first use): operator
+  // stores, vectors, workspace and partial tiles as float arrays, and the
+  // same plan with every record pointer moved to the mirror.
+  bool f32_ready = false;
+  DBuf x32, y32, in32, out32, ws32, p1part32, p2part32;
+  GemmList::Plan q1, q2;
   double flops = 0.0, bytes = 0.0;
   int64_t ntasks = 0;
   std::vector<std::array<int, 5>> shapes;  // per tile task: rows, K1, K2, cols, flags
@@ -1310,6 +1316,10 @@ struct Engine {
   double t_sigma = 0, t_micro = 0, f_sigma = 0, t_block = 0, b_sigma = 0, max_enl_bytes = 0;
   double t_pass1 = 0, t_pass2 = 0, f_pass1 = 0, f_pass2 = 0, b_pass1 = 0, b_pass2 = 0;
   int64_t n_pass1 = 0, n_pass2 = 0;
+  double t_sigma32 = 0, f_sigma32 = 0;
+  int64_t n_sigma32 = 0;
+  int prec = 0;             // 0: FP64 sigma; 1: FP32 sigma + FP64 Rayleigh quotient
+  double mixed_tol = 3e-5;  // Davidson tolerance of the FP32 phase
   int64_t n_sigma = 0;
   // Davidson work buffers
   DBuf dV, dW, dHs, dsmall, dpartial, dx_, dax, dr, dt;
@@ -1921,22 +1931,105 @@ struct Engine {
     dev_sync(st);
   }
 
-  // ---- sigma on the prepared step: step.out = H_eff step.in
-  void sigma_fixed() {
-    dev_zero(step.out.p, (size_t)std::max<int64_t>(step.n, 1) * 8, st);
+  // ---- FP32 mirror of the prepared step's sigma
+  static void alloc_f32(DBuf& b, int64_t count) { b.alloc((size_t)std::max<int64_t>((count + 1) / 2, 1)); }
+
+  void ensure_f32() {
+    Step& S = step;
+    if (S.f32_ready) return;
+    Store &X = *S.X, &Y = *S.Y;
+    alloc_f32(S.x32, X.total);
+    alloc_f32(S.y32, Y.total);
+    alloc_f32(S.in32, S.n);
+    alloc_f32(S.out32, S.n);
+    alloc_f32(S.ws32, (int64_t)S.plan.ws.n);
+    alloc_f32(S.p1part32, (int64_t)S.plan.p1.part.n);
+    alloc_f32(S.p2part32, (int64_t)S.plan.p2.part.n);
+    launch_cvt_d2f((float*)S.x32.p, X.data.p, X.total, st);
+    launch_cvt_d2f((float*)S.y32.p, Y.data.p, Y.total, st);
+    struct Region {
+      const double* b64;
+      size_t n;
+      float* b32;
+    };
+    const Region reg[] = {{X.data.p, (size_t)X.total, (float*)S.x32.p},
+                          {Y.data.p, (size_t)Y.total, (float*)S.y32.p},
+                          {S.in.p, (size_t)S.n, (float*)S.in32.p},
+                          {S.out.p, (size_t)S.n, (float*)S.out32.p},
+                          {S.plan.ws.p, S.plan.ws.n, (float*)S.ws32.p},
+                          {S.plan.p1.part.p, S.plan.p1.part.n, (float*)S.p1part32.p},
+                          {S.plan.p2.part.p, S.plan.p2.part.n, (float*)S.p2part32.p}};
+    auto remap = [&](const double* p) -> double* {
+      if (!p) return nullptr;
+      for (const Region& r : reg)
+        if (r.b64 && p >= r.b64 && p < r.b64 + r.n) return (double*)(r.b32 + (p - r.b64));
+      fail(-5, "internal: sigma operand outside the known buffers");
+    };
+    auto mirror = [&](const GemmList::Plan& a, GemmList::Plan& b) {
+      std::vector<GTile> tl = a.tiles.host;
+      for (GTile& t : tl) {
+        t.out = remap(t.out);
+        t.part = remap(t.part);
+      }
+      std::vector<GTask> tk = a.tasks.host;
+      for (GTask& t : tk) {
+        t.a = remap(t.a);
+        t.b = remap(t.b);
+      }
+      std::vector<RTile> rd = a.reds.host;
+      for (RTile& r : rd) {
+        r.out = remap(r.out);
+        r.part = remap(r.part);
+      }
+      b.tiles.put(tl, st);
+      b.tasks.put(tk, st);
+      b.wstart.put(a.wstart.host, st);
+      b.reds.put(rd, st);
+      b.ntiles = a.ntiles;
+      b.nwg = a.nwg;
+      b.nreds = a.nreds;
+      b.stream = a.stream;
+      b.tag = a.tag;
+      b.f32 = true;
+    };
+    mirror(S.plan.p1, S.q1);
+    mirror(S.plan.p2, S.q2);
+    S.f32_ready = true;
+  }
+
+  // ---- sigma on the prepared step: step.out = H_eff step.in (FP64, or with
+  // FP32 operands and FP32 accumulation when f32)
+  void sigma_fixed(bool f32 = false) {
+    if (f32) ensure_f32();
+    const GemmList::Plan& p1 = f32 ? step.q1 : step.plan.p1;
+    const GemmList::Plan& p2 = f32 ? step.q2 : step.plan.p2;
     void* e0 = dev_event_record(st);
-    step.plan.p1.run(st);
+    if (f32) {
+      launch_cvt_d2f((float*)step.in32.p, step.in.p, step.n, st);
+      dev_zero(step.out32.p, step.out32.n * 8, st);  // whole mirror (n floats, rounded up)
+    } else {
+      dev_zero(step.out.p, (size_t)std::max<int64_t>(step.n, 1) * 8, st);
+    }
     void* e1 = dev_event_record(st);
-    launch_gemm(step.plan.p2.tiles.p, step.plan.p2.tasks.p, step.plan.p2.wstart.p, step.plan.p2.nwg, step.plan.p2.stream,
-                step.plan.p2.tag, st);
+    p1.run(st);
     void* e2 = dev_event_record(st);
-    launch_reduce(step.plan.p2.reds.p, step.plan.p2.nreds, st);
+    launch_gemm(p2.tiles.p, p2.tasks.p, p2.wstart.p, p2.nwg, p2.stream, p2.tag, p2.f32, st);
     void* e3 = dev_event_record(st);
-    const double t1 = dev_event_elapsed(e0, e1), t2 = dev_event_elapsed(e1, e2), t3 = dev_event_elapsed(e2, e3);
+    launch_reduce(p2.reds.p, p2.nreds, p2.f32, st);
+    if (f32) launch_cvt_f2d(step.out.p, (const float*)step.out32.p, step.n, st);
+    void* e4 = dev_event_record(st);
+    const double t0 = dev_event_elapsed(e0, e1), t1 = dev_event_elapsed(e1, e2), t2 = dev_event_elapsed(e2, e3),
+                 t3 = dev_event_elapsed(e3, e4);
+    for (void* ev : {e0, e1, e2, e3, e4}) dev_event_free(ev);
+    if (f32) {
+      t_sigma32 += t0 + t1 + t2 + t3;
+      f_sigma32 += step.flops;
+      ++n_sigma32;
+      return;
+    }
     t_sigma += t1 + t2 + t3;
     t_pass1 += t1;
     t_pass2 += t2;
-    for (void* ev : {e0, e1, e2, e3}) dev_event_free(ev);
     ++n_sigma;
     f_sigma += step.flops;
     f_pass1 += step.plan.flops1;
@@ -1947,14 +2040,15 @@ struct Engine {
     if (step.plan.p2.ntiles > 0) ++n_pass2;
     b_sigma += step.bytes;
   }
-  void sigma_vec(const double* x, double* y) {
+  void sigma_vec(const double* x, double* y, bool f32 = false) {
     dev_d2d(step.in.p, x, (size_t)step.n * 8, st);
-    sigma_fixed();
+    sigma_fixed(f32);
     dev_d2d(y, step.out.p, (size_t)step.n * 8, st);
   }
 
   // ---- Davidson (Davidson 1975; section "The effective Hamiltonian equation")
-  double davidson(double* xres, int* iters, bool* conv) {
+  // tol: residual-norm tolerance; f32: sigma with FP32 operands.
+  double davidson(double* xres, int* iters, bool* conv, double tol, bool f32) {
     const int64_t n = step.n;
     const int ms = std::max(2, std::min(dav_max_sub, 64));
     dV.ensure((size_t)ms * n);
@@ -1982,12 +2076,17 @@ struct Engine {
       launch_dots(dV.p, n, 1, dV.p, n, nrm, dpartial.p, st);
     }
     launch_normalize(dV.p, nrm, n, st);
-    sigma_vec(dV.p, dW.p);
+    sigma_vec(dV.p, dW.p, f32);
     launch_dots(dV.p, n, 1, dW.p, n, dHs.p, dpartial.p, st);
     int k = 1;  // vectors in the subspace
     double theta = 0.0;
     *conv = false;
     int it = 0;
+    // FP32 sigma has a residual floor set by its rounding (observed near
+    // 10 eps_32 |theta|): close to it, stop when the residual has not
+    // improved by 10 % for four iterations
+    double rbest = INFINITY;
+    int stall = 0;
     if (n == 1) {
       dev_d2h(&theta, dHs.p, 8, st);
       dev_d2d(xres, dV.p, 8, st);
@@ -2005,9 +2104,19 @@ struct Engine {
       dev_d2h(hv, evals, 8, st);
       dev_d2h(hv + 1, nrm, 8, st);
       theta = hv[0];
-      if (std::sqrt(std::max(0.0, hv[1])) <= dav_tol) {
+      const double rn = std::sqrt(std::max(0.0, hv[1]));
+      if (rn <= tol) {
         *conv = true;
         break;
+      }
+      if (f32 && rn < 100.0 * 6e-8 * std::max(1.0, std::fabs(theta))) {
+        if (rn < 0.9 * rbest) {
+          rbest = rn;
+          stall = 0;
+        } else if (++stall >= 4) {
+          *conv = true;
+          break;
+        }
       }
       launch_precond(dr.p, step.diag.p, evals, n, dt.p, st);
       for (int pass = 0; pass < 2; ++pass) {
@@ -2044,7 +2153,7 @@ struct Engine {
         launch_normalize(dt.p, nrm2, n, st);
       }
       dev_d2d(dV.p + (int64_t)k * n, dt.p, (size_t)n * 8, st);
-      sigma_vec(dV.p + (int64_t)k * n, dW.p + (int64_t)k * n);
+      sigma_vec(dV.p + (int64_t)k * n, dW.p + (int64_t)k * n, f32);
       // row k of Hs: V_j . W_k for j <= k (lower triangle)
       launch_dots(dV.p, n, k + 1, dW.p + (int64_t)k * n, n, dHs.p + (int64_t)k * ms, dpartial.p, st);
       ++k;
@@ -2171,6 +2280,20 @@ struct Engine {
   }
 
   // ---- one micro-iteration
+  // <x|H|x> / <x|x> with the FP64 sigma
+  double rayleigh(const double* x) {
+    const int64_t n = step.n;
+    dsmall.ensure(8 * 64 + 64 * 64);
+    dpartial.ensure(256 * 64);
+    dr.ensure(n);
+    sigma_vec(x, dr.p, false);
+    launch_dots(x, n, 1, dr.p, n, dsmall.p, dpartial.p, st);
+    launch_dots(x, n, 1, x, n, dsmall.p + 1, dpartial.p, st);
+    double h[2];
+    dev_d2h(h, dsmall.p, 16, st);
+    return h[0] / h[1];
+  }
+
   double micro(int i, int D, bool right, bool do_svd) {
     auto t0 = std::chrono::steady_clock::now();
     prepare(i);
@@ -2178,7 +2301,15 @@ struct Engine {
     x.alloc((size_t)std::max<int64_t>(step.n, 1));
     int its = 0;
     bool conv = false;
-    const double th = davidson(x.p, &its, &conv);
+    double th;
+    if (prec == 1) {
+      // FP32 sigma until the residual reaches mixed_tol, then one FP64 sigma:
+      // the reported energy is the FP64 Rayleigh quotient of that vector
+      th = davidson(x.p, &its, &conv, std::max(dav_tol, mixed_tol), true);
+      th = rayleigh(x.p);
+    } else {
+      th = davidson(x.p, &its, &conv, dav_tol, false);
+    }
     if (!conv) warned = true;
     const double e = th + P.e_const;
     emin = std::min(emin, e);
@@ -2450,15 +2581,25 @@ static void export_mps(Engine& E, std::vector<char>& out) {
 #include "../../include/sadmrg.h"
 
 struct sadmrg_ctx {
+  sadmrg::DevPool* pool = nullptr;  // outlives e: released by sadmrg_destroy
   sadmrg::Engine e;
   std::string err;
 };
+
+namespace {
+struct PoolScope {  // binds a context's device-memory pool for one call
+  sadmrg::DevPool* prev;
+  explicit PoolScope(sadmrg::DevPool* p) : prev(sadmrg::dev_pool_bind(p)) {}
+  ~PoolScope() { sadmrg::dev_pool_bind(prev); }
+};
+}  // namespace
 
 using sadmrg::Failure;
 
 template <class F>
 static int guard(sadmrg_ctx* c, F&& f) {
   if (!c) return SADMRG_EINVAL;
+  PoolScope scope(c->pool);
   try {
     c->err.clear();
     return f();
@@ -2487,6 +2628,7 @@ int sadmrg_create(sadmrg_ctx** out, int L, int group_order, const int* orb_irrep
     if (orb_irrep[i] < 0 || orb_irrep[i] >= group_order) return SADMRG_EINVAL;
   auto* c = new (std::nothrow) sadmrg_ctx();
   if (!c) return SADMRG_ENOMEM;
+  c->pool = sadmrg::dev_pool_create();
   int rc = guard(c, [&] {
     const int nd = sadmrg::dev_count();
     if (nd <= 0) sadmrg::fail(SADMRG_EDEVICE, "no HIP device available");
@@ -2499,7 +2641,7 @@ int sadmrg_create(sadmrg_ctx** out, int L, int group_order, const int* orb_irrep
     return 0;
   });
   if (rc != 0) {
-    delete c;
+    sadmrg_destroy(c);
     return rc;
   }
   *out = c;
@@ -2508,15 +2650,21 @@ int sadmrg_create(sadmrg_ctx** out, int L, int group_order, const int* orb_irrep
 
 void sadmrg_destroy(sadmrg_ctx* ctx) {
   if (!ctx) return;
-  try {
-    sadmrg::dev_sync(ctx->e.st);
-  } catch (...) {
+  sadmrg::DevPool* pool = ctx->pool;
+  {
+    PoolScope scope(pool);
+    try {
+      sadmrg::dev_sync(ctx->e.st);
+    } catch (...) {
+    }
+    delete ctx;  // device blocks return to the pool
   }
-  delete ctx;
+  sadmrg::dev_pool_destroy(pool);
 }
 
 int sadmrg_set_stream(sadmrg_ctx* ctx, void* hip_stream) {
   return guard(ctx, [&] {
+    sadmrg::dev_sync(ctx->e.st);  // cached blocks are idle before the stream changes
     ctx->e.st = hip_stream;
     return 0;
   });
@@ -2730,12 +2878,13 @@ int sadmrg_sigma(sadmrg_ctx* ctx, const double* x, double* y, int on_device) {
     auto& S = E.step;
     if (S.i < 0 || !S.X) sadmrg::fail(SADMRG_EINVAL, "no prepared step");
     if (!x || !y) sadmrg::fail(SADMRG_EINVAL, "null vector");
+    const bool f32 = E.prec == 1;
     if (on_device) {
-      E.sigma_vec(x, y);
+      E.sigma_vec(x, y, f32);
       sadmrg::dev_sync(E.st);
     } else {
       sadmrg::dev_h2d(S.in.p, x, (size_t)S.n * 8, E.st);
-      E.sigma_fixed();
+      E.sigma_fixed(f32);
       sadmrg::dev_d2h(y, S.out.p, (size_t)S.n * 8, E.st);
     }
     return 0;
@@ -2831,6 +2980,25 @@ int sadmrg_stats_passes(sadmrg_ctx* ctx, double* pass1, double* pass2) {
   });
 }
 
+int sadmrg_set_precision(sadmrg_ctx* ctx, int mode, double mixed_tol) {
+  return guard(ctx, [&] {
+    if (mode != 0 && mode != 1) sadmrg::fail(SADMRG_EINVAL, "precision mode must be 0 (FP64) or 1 (FP32 mixed)");
+    if (mode == 1 && !(mixed_tol > 0.0)) sadmrg::fail(SADMRG_EINVAL, "mixed_tol must be positive");
+    ctx->e.prec = mode;
+    if (mode == 1) ctx->e.mixed_tol = mixed_tol;
+    return 0;
+  });
+}
+
+int sadmrg_stats_mixed(sadmrg_ctx* ctx, double* t_sigma32, int64_t* n_sigma32, double* flops_sigma32) {
+  return guard(ctx, [&] {
+    if (t_sigma32) *t_sigma32 = ctx->e.t_sigma32;
+    if (n_sigma32) *n_sigma32 = ctx->e.n_sigma32;
+    if (flops_sigma32) *flops_sigma32 = ctx->e.f_sigma32;
+    return 0;
+  });
+}
+
 int sadmrg_debug_copy_probe(sadmrg_ctx* ctx, int64_t n, int reps, double* seconds) {
   return guard(ctx, [&] {
     if (n <= 0 || reps <= 0) sadmrg::fail(SADMRG_EINVAL, "copy probe: n and reps must be positive");
@@ -2859,6 +3027,8 @@ int sadmrg_stats_reset(sadmrg_ctx* ctx) {
     E.t_sigma = E.t_micro = E.f_sigma = E.t_block = E.b_sigma = E.max_enl_bytes = 0;
     E.t_pass1 = E.t_pass2 = E.f_pass1 = E.f_pass2 = E.b_pass1 = E.b_pass2 = 0;
     E.n_pass1 = E.n_pass2 = 0;
+    E.t_sigma32 = E.f_sigma32 = 0;
+    E.n_sigma32 = 0;
     E.n_sigma = 0;
     return 0;
   });

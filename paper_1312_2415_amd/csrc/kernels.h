@@ -14,6 +14,12 @@ using Stream = void*;  // hipStream_t
 // ---------------------------------------------------------------------------
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
+// Per-context cache of device blocks (see kernels.hip); bind returns the
+// previously bound pool.  Destroy only after the context's stream is idle.
+struct DevPool;
+DevPool* dev_pool_create();
+void dev_pool_destroy(DevPool* pool);
+DevPool* dev_pool_bind(DevPool* pool);
 void dev_h2d(void* dst, const void* src, size_t bytes, Stream st);
 void dev_d2h(void* dst, const void* src, size_t bytes, Stream st);
 void dev_d2d(void* dst, const void* src, size_t bytes, Stream st);
@@ -119,10 +125,16 @@ struct GTask {
 // (nwg groups); otherwise workgroup g processes tile g (nwg = tile count,
 // wstart unused).
 // tag: 0 = sigma pass 1, 1 = sigma pass 2, 2 = other (separate kernel symbols for profiling)
-void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag, Stream st);
+// f32: operands, outputs and partial tiles are float arrays (the record
+// pointers keep their double* type and are reinterpreted).
+void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag, bool f32,
+                 Stream st);
 // Number of compute units of the current device.
 int dev_cu_count();
-void launch_reduce(const RTile* reds, int nred, Stream st);
+void launch_reduce(const RTile* reds, int nred, bool f32, Stream st);
+// dst[i] = (float)src[i] / (double)src[i], i < n
+void launch_cvt_d2f(float* dst, const double* src, int64_t n, Stream st);
+void launch_cvt_f2d(double* dst, const float* src, int64_t n, Stream st);
 void launch_gather(const GatherDst* dsts, int ndst, const GatherSrc* srcs, Stream st);
 void launch_combo(const ComboOut* outs, int nout, const ComboIn* ins, int64_t max_nnz, Stream st);
 void launch_diag(const DiagSec* secs, int nsec, const DiagTask* tasks, Stream st);

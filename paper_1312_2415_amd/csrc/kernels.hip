@@ -13,6 +13,9 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <iterator>
+#include <map>
+#include <unordered_map>
 
 namespace sadmrg {
 
@@ -28,18 +31,94 @@ static void hip_ok(hipError_t e, const char* what) {
 
 static void check_launch(const char* what) { hip_ok(hipGetLastError(), what); }
 
+// ---------------------------------------------------------------------------
+// Device memory.  Without a bound pool, dev_alloc/dev_free are hipMalloc /
+// hipFree.  A context binds its own pool for the duration of every call: freed
+// blocks are kept (keyed by a size class) and handed out again, so the
+// per-micro-iteration stores and plans do not pay hipMalloc/hipFree (which
+// synchronises the device) every step.  A context uses one stream at a time,
+// so a block reused on it is ordered after every earlier use.
+// ---------------------------------------------------------------------------
+struct DevPool {
+  std::multimap<size_t, void*> cached;     // size class -> block
+  std::unordered_map<void*, size_t> owned;  // every block of this pool -> size class
+  size_t cached_bytes = 0;
+};
+static thread_local DevPool* tl_pool = nullptr;
+static constexpr size_t POOL_CACHE_MAX = (size_t)96 << 30;
+
+DevPool* dev_pool_create() { return new DevPool(); }
+void dev_pool_destroy(DevPool* pool) {
+  if (!pool) return;
+  for (auto& [p, sz] : pool->owned) (void)hipFree(p);
+  delete pool;
+}
+DevPool* dev_pool_bind(DevPool* pool) {
+  DevPool* prev = tl_pool;
+  tl_pool = pool;
+  return prev;
+}
+
+// size classes: multiples of 256 B up to 64 KiB, then 2^k * {1, 5/4, 3/2, 7/4}
+static size_t size_class(size_t b) {
+  if (b <= 65536) return (b + 255) & ~(size_t)255;
+  size_t p = 65536;
+  while (p * 2 < b) p *= 2;
+  for (size_t q = 4; q <= 8; ++q)
+    if (p / 4 * q >= b) return p / 4 * q;
+  return p * 2;
+}
+
+static void pool_trim(DevPool* pool, size_t keep) {
+  while (pool->cached_bytes > keep && !pool->cached.empty()) {
+    auto it = std::prev(pool->cached.end());  // largest first
+    pool->cached_bytes -= it->first;
+    pool->owned.erase(it->second);
+    (void)hipFree(it->second);
+    pool->cached.erase(it);
+  }
+}
+
 void* dev_alloc(size_t bytes) {
   if (bytes == 0) bytes = 8;
+  DevPool* pool = tl_pool;
+  if (pool) {
+    bytes = size_class(bytes);
+    auto it = pool->cached.find(bytes);
+    if (it != pool->cached.end()) {
+      void* p = it->second;
+      pool->cached.erase(it);
+      pool->cached_bytes -= bytes;
+      return p;
+    }
+  }
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess && pool && pool->cached_bytes) {  // give the cache back and retry
+    (void)hipGetLastError();
+    pool_trim(pool, 0);
+    e = hipMalloc(&p, bytes);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     dev_fail("hipMalloc: out of device memory");
   }
+  if (pool) pool->owned[p] = bytes;
   return p;
 }
 void dev_free(void* p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  DevPool* pool = tl_pool;
+  if (pool) {
+    auto it = pool->owned.find(p);
+    if (it != pool->owned.end()) {
+      pool->cached.emplace(it->second, p);
+      pool->cached_bytes += it->second;
+      if (pool->cached_bytes > POOL_CACHE_MAX) pool_trim(pool, POOL_CACHE_MAX / 2);
+      return;
+    }
+  }
+  (void)hipFree(p);
 }
 void dev_h2d(void* dst, const void* src, size_t bytes, Stream st) {
   // uploads happen between kernels, never inside the sigma loop: synchronise so
@@ -136,12 +215,42 @@ __device__ inline d4_t mfma16(double a, double b, d4_t c) {
 // four workgroups per CU).  Task and tile records are read one ahead.
 // ---------------------------------------------------------------------------
 constexpr int GK = 32;
-constexpr int SLD = 34;                 // LDS row stride (doubles): 16-byte rows, conflict-free 16-byte reads
 constexpr unsigned G_OOB = 0x80000000u;  // offset past every record count
 constexpr int G_RSRC_W3 = 0x00020000;   // raw buffer, 32-bit data format
 
 typedef unsigned int u2_t __attribute__((ext_vector_type(2)));
 typedef double d2_t __attribute__((ext_vector_type(2)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// Element-type traits of the grouped GEMM.  SLD: LDS row stride in elements
+// (16-byte aligned rows; 68 / 36 dwords = 4 mod 32 banks, so 16-byte reads of
+// 8 consecutive lanes are conflict-free).  VEC: elements per 16-byte read =
+// MFMA k-steps served by one read.  Accumulator row of (lane group lk,
+// register r) in a 16 x 16 block: FP64 lk + 4r, FP32 4lk + r.
+template <typename T>
+struct GT;
+template <>
+struct GT<double> {
+  static constexpr int SLD = 34, VEC = 2;
+  typedef d2_t V;
+  typedef d4_t Acc;
+  __device__ static double load(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+  }
+  __device__ static Acc mfma(double a, double b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lk, int r) { return lk + 4 * r; }
+};
+template <>
+struct GT<float> {
+  static constexpr int SLD = 36, VEC = 4;
+  typedef f4_t V;
+  typedef f4_t Acc;
+  __device__ static float load(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+  }
+  __device__ static Acc mfma(float a, float b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lk, int r) { return 4 * lk + r; }
+};
 
 // Task records are read with a uniform index; the compiler cannot prove the
 // loaded values uniform once LDS stores intervene, so every word is moved to
@@ -182,7 +291,9 @@ __device__ inline GTile g_tile(const GTile* __restrict__ tiles, int i) {
 
 // One operand of the current task.  k-fast storage (contiguous along k: opA
 // not transposed, opB transposed): thread element q is (mn, k) =
-// (tid/32 + 8q, tid%32); mn-fast storage: (tid%64, tid/64 + 4q).
+// (tid/32 + 8q, tid%32); mn-fast storage: (tid%64, tid/64 + 4q).  Record
+// pointers are typed double* on the host; the element type T of the launch
+// decides how they are read.
 struct GOp {
   __amdgpu_buffer_rsrc_t rs;
   unsigned base;   // byte offset of element q = 0 at k0 = 0 (per thread)
@@ -191,64 +302,87 @@ struct GOp {
   bool kfast;
 };
 
+template <typename T>
 __device__ inline void g_op(GOp& o, const double* ptr, int ld, bool kfast, int ext, int K, int tid) {
-  const int nrec = kfast ? ((ext - 1) * ld + K) * 8 : ((K - 1) * ld + ext) * 8;
+  constexpr unsigned ES = sizeof(T);
+  const int nrec = (kfast ? (ext - 1) * ld + K : (K - 1) * ld + ext) * (int)ES;
   o.rs = __builtin_amdgcn_make_buffer_rsrc((void*)ptr, (short)0, nrec, G_RSRC_W3);
   o.kfast = kfast;
-  o.base = kfast ? (unsigned)((tid / 32) * ld + tid % 32) * 8u : (unsigned)((tid / 64) * ld + tid % 64) * 8u;
-  o.qstep = kfast ? (unsigned)ld * 64u : (unsigned)ld * 32u;
-  o.kstep = kfast ? 8u : (unsigned)ld * 8u;
+  o.base = kfast ? (unsigned)((tid / 32) * ld + tid % 32) * ES : (unsigned)((tid / 64) * ld + tid % 64) * ES;
+  o.qstep = kfast ? (unsigned)ld * 8u * ES : (unsigned)ld * 4u * ES;
+  o.kstep = kfast ? ES : (unsigned)ld * ES;
 }
 
-__device__ inline void g_fetch(double (&r)[8], const GOp& o, int k0, int K, int tid) {
+template <typename T>
+__device__ inline void g_fetch(T (&r)[8], const GOp& o, int k0, int K, int tid) {
   unsigned b = o.base;
   if (o.kfast && k0 + GK > K && k0 + tid % 32 >= K) b = G_OOB;
   const unsigned adv = (unsigned)k0 * o.kstep;
 #pragma unroll
-  for (int q = 0; q < 8; ++q)
-    r[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(o.rs, (int)(b + (q * o.qstep + adv)), 0, 0));
+  for (int q = 0; q < 8; ++q) r[q] = GT<T>::load(o.rs, b + (q * o.qstep + adv));
 }
 
 // LDS position of element q: [mn][k] with row stride SLD.
+template <typename T>
 __device__ inline int g_lds(bool kfast, int tid, int q) {
+  constexpr int SLD = GT<T>::SLD;
   return kfast ? (tid / 32 + 8 * q) * SLD + tid % 32 : (tid % 64) * SLD + tid / 64 + 4 * q;
 }
 
-__device__ inline void g_store(const double (&ra)[8], const double (&rb)[8], double coef, int flags, double* sA,
-                               double* sB, int tid) {
+template <typename T>
+__device__ inline void g_store(const T (&ra)[8], const T (&rb)[8], double coef, int flags, T* sA, T* sB, int tid) {
   const bool kfa = !(flags & GT_TRANS_A), kfb = (flags & GT_TRANS_B) != 0;
+  const T c = (T)coef;
   if (kfa) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sA[g_lds(true, tid, q)] = coef * ra[q];
+    for (int q = 0; q < 8; ++q) sA[g_lds<T>(true, tid, q)] = c * ra[q];
   } else {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sA[g_lds(false, tid, q)] = coef * ra[q];
+    for (int q = 0; q < 8; ++q) sA[g_lds<T>(false, tid, q)] = c * ra[q];
   }
   if (kfb) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sB[g_lds(true, tid, q)] = rb[q];
+    for (int q = 0; q < 8; ++q) sB[g_lds<T>(true, tid, q)] = rb[q];
   } else {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sB[g_lds(false, tid, q)] = rb[q];
+    for (int q = 0; q < 8; ++q) sB[g_lds<T>(false, tid, q)] = rb[q];
   }
 }
 
 // acc[b] += A[16 rows][k] * B[k][16b .. 16b+15], b < NCB, over the first np
-// k-step pairs (8 values of k each) of the staged chunk.
-template <int NCB>
-__device__ inline void g_mac(d4_t (&acc)[4], const double* sA, const double* sB, int np, int r0, int li, int lk) {
-  const double* pa = sA + (r0 + li) * SLD + 2 * lk;
-  const double* pb = sB + li * SLD + 2 * lk;
+// groups of 4*VEC values of k of the staged chunk.  Inside a group, lane
+// group lk reads VEC consecutive k with one 16-byte read and feeds them to
+// VEC successive MFMA k-steps (k = 4*VEC*p + VEC*lk + e), for both operands.
+template <typename T, int NCB>
+__device__ inline void g_mac(typename GT<T>::Acc (&acc)[4], const T* sA, const T* sB, int np, int r0, int li, int lk) {
+  typedef typename GT<T>::V V;
+  constexpr int SLD = GT<T>::SLD, VEC = GT<T>::VEC;
+  const T* pa = sA + (r0 + li) * SLD + VEC * lk;
+  const T* pb = sB + li * SLD + VEC * lk;
   for (int p = 0; p < np; ++p) {
-    const d2_t a2 = *(const d2_t*)(pa + 8 * p);
-    d2_t b2[NCB];
+    const V av = *(const V*)(pa + 4 * VEC * p);
+    V bv[NCB];
 #pragma unroll
-    for (int b = 0; b < NCB; ++b) b2[b] = *(const d2_t*)(pb + 16 * b * SLD + 8 * p);
+    for (int b = 0; b < NCB; ++b) bv[b] = *(const V*)(pb + 16 * b * SLD + 4 * VEC * p);
 #pragma unroll
-    for (int b = 0; b < NCB; ++b) acc[b] = mfma16(a2.x, b2[b].x, acc[b]);
+    for (int e = 0; e < VEC; ++e)
 #pragma unroll
-    for (int b = 0; b < NCB; ++b) acc[b] = mfma16(a2.y, b2[b].y, acc[b]);
+      for (int b = 0; b < NCB; ++b) acc[b] = GT<T>::mfma(av[e], bv[b][e], acc[b]);
   }
+}
+
+template <typename T>
+__device__ inline void g_mac_any(typename GT<T>::Acc (&acc)[4], const T* sA, const T* sB, int kc, int ncb, int r0,
+                                 int li, int lk) {
+  const int np = (kc + 4 * GT<T>::VEC - 1) / (4 * GT<T>::VEC);
+  if (ncb == 4)
+    g_mac<T, 4>(acc, sA, sB, np, r0, li, lk);
+  else if (ncb == 3)
+    g_mac<T, 3>(acc, sA, sB, np, r0, li, lk);
+  else if (ncb == 2)
+    g_mac<T, 2>(acc, sA, sB, np, r0, li, lk);
+  else
+    g_mac<T, 1>(acc, sA, sB, np, r0, li, lk);
 }
 
 struct GOut {  // what the epilogue of a tile needs
@@ -258,21 +392,24 @@ struct GOut {  // what the epilogue of a tile needs
 };
 __device__ inline GOut g_out(const GTile& t) { return GOut{t.out, t.part, t.ld, t.rows, t.cols, t.mode}; }
 
-__device__ inline void g_write(const GOut& tile, const d4_t (&acc)[4], int r0, int li, int lk) {
+template <typename T>
+__device__ inline void g_write(const GOut& tile, const typename GT<T>::Acc (&acc)[4], int r0, int li, int lk) {
+  T* const out = (T*)tile.out;
+  T* const part = (T*)tile.part;
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     const int col = 16 * b + li;
     if (col >= tile.cols) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int orow = r0 + lk + 4 * r;
+      const int orow = r0 + GT<T>::row(lk, r);
       if (orow >= tile.rows) continue;
-      if (tile.part)
-        tile.part[orow * tile.cols + col] = acc[b][r];
+      if (part)
+        part[orow * tile.cols + col] = acc[b][r];
       else if (tile.mode == 1)
-        tile.out[(int64_t)orow * tile.ld + col] = acc[b][r];
+        out[(int64_t)orow * tile.ld + col] = acc[b][r];
       else
-        tile.out[(int64_t)orow * tile.ld + col] += acc[b][r];
+        out[(int64_t)orow * tile.ld + col] += acc[b][r];
     }
   }
 }
@@ -281,11 +418,12 @@ __device__ inline void g_write(const GOut& tile, const d4_t (&acc)[4], int r0, i
 // the hardware dispatcher balances short, independent tiles best.
 // TAG only separates the symbols of the launch sites for profiling:
 // 0 = sigma pass 1, 1 = sigma pass 2, 2 = renormalisation / other products.
-template <int TAG>
+template <typename T, int TAG>
 __global__ __launch_bounds__(256, 4) void gemm_tile_kernel(const GTile* __restrict__ tiles,
                                                            const GTask* __restrict__ tasks) {
-  __shared__ __attribute__((aligned(16))) double sA[64 * SLD];
-  __shared__ __attribute__((aligned(16))) double sB[64 * SLD];
+  typedef typename GT<T>::Acc Acc;
+  __shared__ __attribute__((aligned(16))) T sA[64 * GT<T>::SLD];
+  __shared__ __attribute__((aligned(16))) T sB[64 * GT<T>::SLD];
   const GTile tile = tiles[blockIdx.x];
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid / 64);  // wave index, scalar
@@ -294,23 +432,23 @@ __global__ __launch_bounds__(256, 4) void gemm_tile_kernel(const GTile* __restri
   const int r0 = 16 * w;
   const bool active = r0 < tile.rows;
   const int ncb = (tile.cols + 15) / 16;
-  d4_t acc[4];
+  Acc acc[4];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) acc[b] = (d4_t){0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < 4; ++b) acc[b] = (Acc){0, 0, 0, 0};
 
   if (tile.t0 < tile.t1) {
     int t = tile.t0, k0 = 0;  // stream position of the next fetch
     GTask cur = g_task(tasks, t);
     GTask nxt = t + 1 < tile.t1 ? g_task(tasks, t + 1) : cur;
     GOp A, B;
-    g_op(A, cur.a, cur.lda, !(cur.flags & GT_TRANS_A), tile.rows, cur.K, tid);
-    g_op(B, cur.b, cur.ldb, (cur.flags & GT_TRANS_B) != 0, tile.cols, cur.K, tid);
-    double ra[8], rb[8];
+    g_op<T>(A, cur.a, cur.lda, !(cur.flags & GT_TRANS_A), tile.rows, cur.K, tid);
+    g_op<T>(B, cur.b, cur.ldb, (cur.flags & GT_TRANS_B) != 0, tile.cols, cur.K, tid);
+    T ra[8], rb[8];
     int kc, flags;
     double coef;
     auto next = [&]() {
-      g_fetch(ra, A, k0, cur.K, tid);
-      g_fetch(rb, B, k0, cur.K, tid);
+      g_fetch<T>(ra, A, k0, cur.K, tid);
+      g_fetch<T>(rb, B, k0, cur.K, tid);
       kc = min(GK, cur.K - k0);
       coef = cur.coef;
       flags = cur.flags;
@@ -320,44 +458,36 @@ __global__ __launch_bounds__(256, 4) void gemm_tile_kernel(const GTile* __restri
         if (++t < tile.t1) {
           cur = nxt;
           if (t + 1 < tile.t1) nxt = g_task(tasks, t + 1);
-          g_op(A, cur.a, cur.lda, !(cur.flags & GT_TRANS_A), tile.rows, cur.K, tid);
-          g_op(B, cur.b, cur.ldb, (cur.flags & GT_TRANS_B) != 0, tile.cols, cur.K, tid);
+          g_op<T>(A, cur.a, cur.lda, !(cur.flags & GT_TRANS_A), tile.rows, cur.K, tid);
+          g_op<T>(B, cur.b, cur.ldb, (cur.flags & GT_TRANS_B) != 0, tile.cols, cur.K, tid);
         }
       }
     };
     next();
     while (true) {
-      g_store(ra, rb, coef, flags, sA, sB, tid);
-      const int np = (kc + 7) / 8;
+      g_store<T>(ra, rb, coef, flags, sA, sB, tid);
+      const int kcc = kc;
       __syncthreads();
       const bool more = t < tile.t1;
       if (more) next();
-      if (active) {
-        if (ncb == 4)
-          g_mac<4>(acc, sA, sB, np, r0, li, lk);
-        else if (ncb == 3)
-          g_mac<3>(acc, sA, sB, np, r0, li, lk);
-        else if (ncb == 2)
-          g_mac<2>(acc, sA, sB, np, r0, li, lk);
-        else
-          g_mac<1>(acc, sA, sB, np, r0, li, lk);
-      }
+      if (active) g_mac_any<T>(acc, sA, sB, kcc, ncb, r0, li, lk);
       if (!more) break;
       __syncthreads();
     }
   }
-  if (active) g_write(g_out(tile), acc, r0, li, lk);
+  if (active) g_write<T>(g_out(tile), acc, r0, li, lk);
 }
 
 // Workgroup g streams the tiles [wstart[g], wstart[g+1]).
 // TAG only separates the symbols of the launch sites for profiling:
 // 0 = sigma pass 1, 1 = sigma pass 2, 2 = renormalisation / other products.
-template <int TAG>
+template <typename T, int TAG>
 __global__ __launch_bounds__(256, 3) void gemm_stream_kernel(const GTile* __restrict__ tiles,
                                                              const GTask* __restrict__ tasks,
                                                              const int* __restrict__ wstart) {
-  __shared__ __attribute__((aligned(16))) double sA[64 * SLD];
-  __shared__ __attribute__((aligned(16))) double sB[64 * SLD];
+  typedef typename GT<T>::Acc Acc;
+  __shared__ __attribute__((aligned(16))) T sA[64 * GT<T>::SLD];
+  __shared__ __attribute__((aligned(16))) T sB[64 * GT<T>::SLD];
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid / 64);  // wave index, scalar
   const int l = tid % 64;
@@ -377,13 +507,13 @@ __global__ __launch_bounds__(256, 3) void gemm_stream_kernel(const GTile* __rest
   if (FT.t0 < FT.t1) {
     cur = g_task(tasks, t);
     nxt = t + 1 < FT.t1 ? g_task(tasks, t + 1) : cur;
-    g_op(A, cur.a, cur.lda, !(cur.flags & GT_TRANS_A), FT.rows, cur.K, tid);
-    g_op(B, cur.b, cur.ldb, (cur.flags & GT_TRANS_B) != 0, FT.cols, cur.K, tid);
+    g_op<T>(A, cur.a, cur.lda, !(cur.flags & GT_TRANS_A), FT.rows, cur.K, tid);
+    g_op<T>(B, cur.b, cur.ldb, (cur.flags & GT_TRANS_B) != 0, FT.cols, cur.K, tid);
   }
   if (ft + 1 < fe && NT.t0 < NT.t1) ncur = g_task(tasks, NT.t0);
 
   // the staged item: registers + description
-  double ra[8], rb[8];
+  T ra[8], rb[8];
   GOut MT;  // tile of the staged item
   int kc, flags;
   bool last;
@@ -391,8 +521,8 @@ __global__ __launch_bounds__(256, 3) void gemm_stream_kernel(const GTile* __rest
   auto issue = [&]() {
     MT = g_out(FT);
     if (t < FT.t1) {
-      g_fetch(ra, A, k0, cur.K, tid);
-      g_fetch(rb, B, k0, cur.K, tid);
+      g_fetch<T>(ra, A, k0, cur.K, tid);
+      g_fetch<T>(rb, B, k0, cur.K, tid);
       kc = min(GK, cur.K - k0);
       coef = cur.coef;
       flags = cur.flags;
@@ -402,8 +532,8 @@ __global__ __launch_bounds__(256, 3) void gemm_stream_kernel(const GTile* __rest
         if (++t < FT.t1) {
           cur = nxt;
           if (t + 1 < FT.t1) nxt = g_task(tasks, t + 1);
-          g_op(A, cur.a, cur.lda, !(cur.flags & GT_TRANS_A), FT.rows, cur.K, tid);
-          g_op(B, cur.b, cur.ldb, (cur.flags & GT_TRANS_B) != 0, FT.cols, cur.K, tid);
+          g_op<T>(A, cur.a, cur.lda, !(cur.flags & GT_TRANS_A), FT.rows, cur.K, tid);
+          g_op<T>(B, cur.b, cur.ldb, (cur.flags & GT_TRANS_B) != 0, FT.cols, cur.K, tid);
         }
       }
     } else {  // a tile without products: its output is written as zero
@@ -419,8 +549,8 @@ __global__ __launch_bounds__(256, 3) void gemm_stream_kernel(const GTile* __rest
       if (t < FT.t1) {
         cur = ncur;
         nxt = t + 1 < FT.t1 ? g_task(tasks, t + 1) : cur;
-        g_op(A, cur.a, cur.lda, !(cur.flags & GT_TRANS_A), FT.rows, cur.K, tid);
-        g_op(B, cur.b, cur.ldb, (cur.flags & GT_TRANS_B) != 0, FT.cols, cur.K, tid);
+        g_op<T>(A, cur.a, cur.lda, !(cur.flags & GT_TRANS_A), FT.rows, cur.K, tid);
+        g_op<T>(B, cur.b, cur.ldb, (cur.flags & GT_TRANS_B) != 0, FT.cols, cur.K, tid);
       }
       if (ft + 1 < fe) {
         NT = g_tile(tiles, ft + 1);
@@ -429,58 +559,57 @@ __global__ __launch_bounds__(256, 3) void gemm_stream_kernel(const GTile* __rest
     }
   };
 
-  d4_t acc[4];
+  Acc acc[4];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) acc[b] = (d4_t){0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < 4; ++b) acc[b] = (Acc){0, 0, 0, 0};
   issue();
   while (true) {
-    if (kc > 0) g_store(ra, rb, coef, flags, sA, sB, tid);
+    if (kc > 0) g_store<T>(ra, rb, coef, flags, sA, sB, tid);
     const GOut mt = MT;
-    const int np = (kc + 7) / 8;
+    const int kcc = kc;
     const bool mlast = last;
     __syncthreads();
     const bool more = ft < fe;
     if (more) issue();
     const bool active = r0 < mt.rows;
-    if (active && np > 0) {
-      const int ncb = (mt.cols + 15) / 16;
-      if (ncb == 4)
-        g_mac<4>(acc, sA, sB, np, r0, li, lk);
-      else if (ncb == 3)
-        g_mac<3>(acc, sA, sB, np, r0, li, lk);
-      else if (ncb == 2)
-        g_mac<2>(acc, sA, sB, np, r0, li, lk);
-      else
-        g_mac<1>(acc, sA, sB, np, r0, li, lk);
-    }
+    if (active && kcc > 0) g_mac_any<T>(acc, sA, sB, kcc, (mt.cols + 15) / 16, r0, li, lk);
     if (mlast) {
-      if (active) g_write(mt, acc, r0, li, lk);
+      if (active) g_write<T>(mt, acc, r0, li, lk);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[b] = (d4_t){0.0, 0.0, 0.0, 0.0};
+      for (int b = 0; b < 4; ++b) acc[b] = (Acc){0, 0, 0, 0};
     }
     if (!more) break;
     __syncthreads();
   }
 }
 
-void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag, Stream st) {
-  if (nwg <= 0) return;
-  const hipStream_t hs = (hipStream_t)st;
+template <typename T>
+static void launch_gemm_t(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag,
+                          hipStream_t hs) {
   if (stream) {
     if (tag == 0)
-      hipLaunchKernelGGL(gemm_stream_kernel<0>, dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+      hipLaunchKernelGGL((gemm_stream_kernel<T, 0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
     else if (tag == 1)
-      hipLaunchKernelGGL(gemm_stream_kernel<1>, dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+      hipLaunchKernelGGL((gemm_stream_kernel<T, 1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
     else
-      hipLaunchKernelGGL(gemm_stream_kernel<2>, dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+      hipLaunchKernelGGL((gemm_stream_kernel<T, 2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
   } else {
     if (tag == 0)
-      hipLaunchKernelGGL(gemm_tile_kernel<0>, dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+      hipLaunchKernelGGL((gemm_tile_kernel<T, 0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks);
     else if (tag == 1)
-      hipLaunchKernelGGL(gemm_tile_kernel<1>, dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+      hipLaunchKernelGGL((gemm_tile_kernel<T, 1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks);
     else
-      hipLaunchKernelGGL(gemm_tile_kernel<2>, dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+      hipLaunchKernelGGL((gemm_tile_kernel<T, 2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks);
   }
+}
+
+void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag, bool f32,
+                 Stream st) {
+  if (nwg <= 0) return;
+  if (f32)
+    launch_gemm_t<float>(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st);
+  else
+    launch_gemm_t<double>(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st);
   check_launch("gemm");
 }
 
@@ -494,29 +623,58 @@ int dev_cu_count() {
 // Ordered sum of a tile's partial results: eight interleaved accumulators
 // keep loads in flight; the combination order is fixed, so results are
 // reproducible run to run.
+template <typename T>
 __global__ __launch_bounds__(256) void reduce_kernel(const RTile* __restrict__ reds) {
   const RTile t = reds[blockIdx.x];
+  const T* const part = (const T*)t.part;
+  T* const out = (T*)t.out;
   const int n = t.rows * t.cols;
   for (int e = threadIdx.x; e < n; e += 256) {
-    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const double* p = t.part + e;
+    T v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const T* p = part + e;
     int q = 0;
     for (; q + 8 <= t.nparts; q += 8) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) v[u] += p[(int64_t)(q + u) * n];
     }
     for (int u = 0; q < t.nparts; ++q, ++u) v[u] += p[(int64_t)q * n];
-    const double s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
-    t.out[(int64_t)(e / t.cols) * t.ld + e % t.cols] += s;
+    const T s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    out[(int64_t)(e / t.cols) * t.ld + e % t.cols] += s;
   }
 }
 
-void launch_reduce(const RTile* reds, int nred, Stream st) {
+void launch_reduce(const RTile* reds, int nred, bool f32, Stream st) {
   if (nred <= 0) return;
-  hipLaunchKernelGGL(reduce_kernel, dim3(nred), dim3(256), 0, (hipStream_t)st, reds);
+  if (f32)
+    hipLaunchKernelGGL(reduce_kernel<float>, dim3(nred), dim3(256), 0, (hipStream_t)st, reds);
+  else
+    hipLaunchKernelGGL(reduce_kernel<double>, dim3(nred), dim3(256), 0, (hipStream_t)st, reds);
   check_launch("reduce");
 }
 
+// ---------------------------------------------------------------------------
+// Precision conversions (FP64 <-> FP32 copies of operands and vectors).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void cvt_d2f_kernel(float* __restrict__ dst, const double* __restrict__ src, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = (float)src[i];
+}
+__global__ __launch_bounds__(256) void cvt_f2d_kernel(double* __restrict__ dst, const float* __restrict__ src, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = (double)src[i];
+}
+void launch_cvt_d2f(float* dst, const double* src, int64_t n, Stream st) {
+  if (n <= 0) return;
+  const int nb = (int)std::min<int64_t>((n + 255) / 256, 256 * 32);
+  hipLaunchKernelGGL(cvt_d2f_kernel, dim3(nb), dim3(256), 0, (hipStream_t)st, dst, src, n);
+  check_launch("cvt_d2f");
+}
+void launch_cvt_f2d(double* dst, const float* src, int64_t n, Stream st) {
+  if (n <= 0) return;
+  const int nb = (int)std::min<int64_t>((n + 255) / 256, 256 * 32);
+  hipLaunchKernelGGL(cvt_f2d_kernel, dim3(nb), dim3(256), 0, (hipStream_t)st, dst, src, n);
+  check_launch("cvt_f2d");
+}
 
 // ---------------------------------------------------------------------------
 // Gather-accumulate of scaled (possibly transposed / identity) blocks.

@@ -1,0 +1,104 @@
+"""GPU precision variant: FP32 sigma (FP32 operators, FP32 accumulation) with
+FP64 Davidson algebra and an FP64 Rayleigh-quotient energy per micro-iteration.
+
+Checked against the FP64 oracle: the FP32 sigma stays within FP32 rounding of
+the oracle's sigma at every step, and mixed-precision sweep energies match
+the oracle's FP64 sweep to 1e-6 E_h (the precision target), including an
+FCI-exact case.
+"""
+import numpy as np
+import pytest
+
+from oracle import sadmrg as sd
+from oracle.fci import fci_solve
+from synth.integrals import make_integrals
+
+pytestmark = pytest.mark.gpu
+
+ORDER = {"C1": 1, "C2": 2, "C2v": 4, "D2h": 8}
+
+
+def _gpu(L, group, I):
+    from paper_1312_2415_amd import SaDMRG
+    g = SaDMRG(L, ORDER[group], I.orb_irrep, device=0)
+    g.set_integrals(I.h, I.eri)
+    return g
+
+
+@pytest.mark.parametrize("case", [(6, 6, 2, "D2h", 0, 10), (10, 10, 0, "D2h", 0, 30)])
+def test_fp32_sigma_within_fp32_rounding_of_oracle(case):
+    L, N, twoS, group, irrep, D = case
+    I = make_integrals(L, group, 11)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    g = _gpu(L, group, I)
+    g.set_target(N, twoS, irrep)
+    for i in range(L - 1):
+        print(f"case {case} step {i}", flush=True)
+        g.mps_import(sd.export_blob(dm))
+        g.prepare_step()
+        desc, n = g.psi_layout()
+        El, Er, Xe, Ye, secs = dm.enlarged(i)
+        He = sd.Heff(P, Xe, Ye, secs)
+        shapes = {m: (El.dim[m], Er.dim[m]) for m in secs}
+        x = np.random.default_rng(100 + i).normal(size=n)
+        ref = sd.flatten(He.apply(sd.unflatten(x, shapes, secs)), secs)
+        g.set_precision(1)
+        got32 = g.sigma(x)
+        g.set_precision(0)
+        got64 = g.sigma(x)
+        scale = np.abs(ref).max()
+        err32 = np.abs(got32 - ref).max() / scale
+        assert err32 <= 2e-5
+        if n > 8:  # the FP32 path really ran in FP32
+            assert err32 > 1e-12
+        assert np.abs(got64 - ref).max() <= 1e-10 * scale
+        if i < L - 2:
+            dm.micro(i, D, "right")
+    st = g.stats()
+    assert st["fp32"]["calls"] >= L - 1
+    g.close()
+
+
+@pytest.mark.parametrize("case", [(8, 8, 0, "C1", 0, 64, 3, 1001), (10, 6, 2, "D2h", 0, 24, 2, 5),
+                                  (12, 12, 0, "D2h", 0, 40, 2, 7)])
+def test_mixed_sweep_energies_match_fp64_oracle(case):
+    L, N, twoS, group, irrep, D, nsw, seed = case
+    I = make_integrals(L, group, seed)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    blob = sd.export_blob(dm)
+    for _ in range(nsw):
+        dm.sweep(D)
+    g = _gpu(L, group, I)
+    g.set_target(N, twoS, irrep)
+    g.set_davidson(1e-9, 32, 200)
+    g.set_precision(1, 1e-5)
+    g.mps_import(blob)
+    for s in range(nsw):
+        print(f"case {case} sweep {s}", flush=True)
+        g.sweep(D)
+    got, ref = g.trace(), np.array(dm.stats.energies)
+    assert len(got) == len(ref)
+    assert np.abs(got[-(L - 1):] - ref[-(L - 1):]).max() <= 1e-6  # the final sweep
+    assert abs(g.energy()[0] - dm.emin) <= 1e-6
+    assert g.stats()["fp32"]["calls"] > 0
+    if case[0] == 8:  # D = 64 at L = 8 is complete: FCI-exact
+        e_fci = fci_solve(I.h, I.eri, N, twoS, irrep, I.orb_irrep, I.e_const, nroots=1)[0][0]
+        assert abs(g.energy()[0] - e_fci) <= 1e-6
+    g.close()
+
+
+def test_precision_mode_is_validated():
+    I = make_integrals(4, "C1", 3)
+    g = _gpu(4, "C1", I)
+    from paper_1312_2415_amd.binding import SadmrgError
+    with pytest.raises(SadmrgError):
+        g.set_precision(2)
+    with pytest.raises(SadmrgError):
+        g.set_precision(1, 0.0)
+    g.set_precision(1, 1e-6)
+    g.set_precision(0)
+    g.close()
