@@ -12,9 +12,12 @@ the H_eff sigma product, SVD truncation, renormalisation).  The MPS starts
 random at bond dimension D and every sweep (warm-up and timed) runs at D, so
 every kernel launch of the run has the shapes of the headline workload.
 
-Reported `value` is the sigma-product rate: algorithmic FP64 flops of all
-H_eff*psi calls in the timed sweeps divided by their kernel time (HIP events on
-the library stream).  `ms_per_step` is the wall time per sweep.  `roofline`
+Reported `value` is the sigma-product rate of the plain FP64 path: algorithmic
+FP64 flops of all H_eff*psi calls in the timed sweeps divided by their kernel
+time (HIP events on the library stream).  `ms_per_step` is the wall time per
+FP64 sweep.  `mixed` repeats the timed sweeps from the same state with FP32
+sigma products in Davidson (FP64 Rayleigh-quotient energies) and reports its
+s/sweep, speedup, FP32 sigma rate and |dE| against the FP64 sweeps.  `roofline`
 describes the dominant sigma kernel (the grouped-GEMM pass with the larger
 share of sigma time): its algorithmic flops per launch over its mean launch
 duration, against the FP64 MFMA peak.  `traffic` is filled from the committed
@@ -37,8 +40,8 @@ FP64_MFMA_PEAK = 78.6  # TFLOP/s, MI355X dense FP64 matrix peak
 HBM_PEAK = 8000.0  # GB/s
 KERNEL_SRC = os.path.join(ROOT, "paper_1312_2415_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_kernel_sigma_L28_N12_D2500_traffic.json")
-PASS_KERNEL = {"pass1": "gemm_tile_kernel<0> (sigma pass 1: T = X psi)",
-               "pass2": "gemm_stream_kernel<1> (sigma pass 2: sigma += T Y^T)"}
+PASS_KERNEL = {"pass1": "gemm_tile_kernel<double, 0> (sigma pass 1: T = X psi)",
+               "pass2": "gemm_stream_kernel<double, 1> (sigma pass 2: sigma += T Y^T)"}
 
 
 def kernel_source_hash() -> str:
@@ -154,6 +157,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-D", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed-tol", type=float, default=3e-5)
+    ap.add_argument("--no-mixed", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -184,6 +189,7 @@ def main():
         e, _ = g.sweep(args.D)
         print(f"warmup sweep {w + 1}/{args.warmup} D={args.D} E={e:.10f} {time.time() - t:.1f}s", file=sys.stderr,
               flush=True)
+    start = g.mps_export()  # the mixed sweeps restart from here
     g.stats_reset()
     t0 = time.perf_counter()
     energies = []
@@ -195,6 +201,7 @@ def main():
               file=sys.stderr, flush=True)
     t1 = time.perf_counter()
     st = g.stats()
+    trace64 = g.trace()
     sec_per_sweep = (t1 - t0) / args.steps
     sigma_tflops = st["flops_sigma"] / max(st["t_sigma"], 1e-12) / 1e12
     avg_sigma_ms = 1e3 * st["t_sigma"] / max(st["n_sigma"], 1)
@@ -240,6 +247,42 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch, "launch_ms_avg": launch_ms,
                      "launches": ps["launches"]},
     }
+    if not args.no_mixed:
+        # the same timed sweeps from the same state with FP32 sigma in Davidson
+        # and FP64 Rayleigh-quotient energies
+        n64 = len(trace64)
+        g.set_precision(1, args.mixed_tol)
+        g.mps_import(start)
+        g.stats_reset()
+        tm0 = time.perf_counter()
+        emix = []
+        for k in range(args.steps):
+            ts = time.perf_counter()
+            e, _ = g.sweep(args.D)
+            emix.append(e)
+            print(f"mixed sweep {k + 1}/{args.steps} D={args.D} E={e:.10f} {time.perf_counter() - ts:.1f}s",
+                  file=sys.stderr, flush=True)
+        tm1 = time.perf_counter()
+        sm = g.stats()
+        tracem = g.trace()
+        nt = len(tracem) - n64  # micro-iterations of the mixed sweeps
+        d_micro = float(max(abs(a - b) for a, b in zip(trace64[n64 - nt:], tracem[n64:]))) if nt > 0 else None
+        sec_mixed = (tm1 - tm0) / args.steps
+        line["mixed"] = {
+            "precision": "FP32 sigma (FP32 operators, FP32 accumulation) in Davidson; FP64 Davidson algebra, "
+                         "SVD, renormalisation; FP64 Rayleigh-quotient energy per micro-iteration",
+            "mixed_tol": args.mixed_tol,
+            "s_per_sweep": sec_mixed,
+            "speedup_s_per_sweep": sec_per_sweep / sec_mixed,
+            "sigma_fp32_tflops": sm["fp32"]["flops"] / max(sm["fp32"]["t"], 1e-12) / 1e12,
+            "sigma_fp32_calls": sm["fp32"]["calls"],
+            "sigma_fp64_polish_calls": sm["n_sigma"],
+            "sigma_seconds_per_sweep": (sm["fp32"]["t"] + sm["t_sigma"]) / args.steps,
+            "sigma_seconds_per_sweep_fp64_path": st["t_sigma"] / args.steps,
+            "energy_last_sweep": emix[-1],
+            "abs_dE_last_sweep_vs_fp64": abs(emix[-1] - energies[-1]),
+            "max_abs_dE_per_micro_iteration_vs_fp64": d_micro,
+        }
     g.close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, L, N, args.twoS, args.irrep, args.seed, args.cpu_D)

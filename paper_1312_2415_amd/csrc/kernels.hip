@@ -466,11 +466,20 @@ __global__ __launch_bounds__(256, 4) void gemm_tile_kernel(const GTile* __restri
     next();
     while (true) {
       g_store<T>(ra, rb, coef, flags, sA, sB, tid);
-      const int kcc = kc;
+      const int np = (kc + 4 * GT<T>::VEC - 1) / (4 * GT<T>::VEC);
       __syncthreads();
       const bool more = t < tile.t1;
       if (more) next();
-      if (active) g_mac_any<T>(acc, sA, sB, kcc, ncb, r0, li, lk);
+      if (active) {
+        if (ncb == 4)
+          g_mac<T, 4>(acc, sA, sB, np, r0, li, lk);
+        else if (ncb == 3)
+          g_mac<T, 3>(acc, sA, sB, np, r0, li, lk);
+        else if (ncb == 2)
+          g_mac<T, 2>(acc, sA, sB, np, r0, li, lk);
+        else
+          g_mac<T, 1>(acc, sA, sB, np, r0, li, lk);
+      }
       if (!more) break;
       __syncthreads();
     }
