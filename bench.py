@@ -157,8 +157,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-D", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mixed-tol", type=float, default=3e-5)
+    ap.add_argument("--mixed-tol", type=float, default=1e-5)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-rdm", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -190,6 +191,7 @@ def main():
         print(f"warmup sweep {w + 1}/{args.warmup} D={args.D} E={e:.10f} {time.time() - t:.1f}s", file=sys.stderr,
               flush=True)
     start = g.mps_export()  # the mixed sweeps restart from here
+    import numpy as np
     g.stats_reset()
     t0 = time.perf_counter()
     energies = []
@@ -247,6 +249,16 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch, "launch_ms_avg": launch_ms,
                      "launches": ps["launches"]},
     }
+    rdm64 = None
+    if not args.no_rdm:  # spin-summed 1- and 2-RDM of the final FP64 MPS (energy adjoint)
+        tr0 = time.perf_counter()
+        g1, g2, e_rdm = g.rdm()
+        t_rdm = time.perf_counter() - tr0
+        rdm64 = (g1, g2)
+        e_id = I.e_const + float(np.einsum("pq,pq", I.h, g1)) + 0.5 * float(np.einsum("ikjl,ijkl", I.eri, g2))
+        line["rdm"] = {"seconds": t_rdm, "energy": e_rdm, "energy_identity_error": abs(e_id - e_rdm),
+                       "trace_gamma": float(np.trace(g1))}
+        print(f"rdm {t_rdm:.1f}s E={e_rdm:.10f} identity error {abs(e_id - e_rdm):.2e}", file=sys.stderr, flush=True)
     if not args.no_mixed:
         # the same timed sweeps from the same state with FP32 sigma in Davidson
         # and FP64 Rayleigh-quotient energies
@@ -276,13 +288,17 @@ def main():
             "speedup_s_per_sweep": sec_per_sweep / sec_mixed,
             "sigma_fp32_tflops": sm["fp32"]["flops"] / max(sm["fp32"]["t"], 1e-12) / 1e12,
             "sigma_fp32_calls": sm["fp32"]["calls"],
-            "sigma_fp64_polish_calls": sm["n_sigma"],
+            "sigma_fp64_calls": sm["n_sigma"],
             "sigma_seconds_per_sweep": (sm["fp32"]["t"] + sm["t_sigma"]) / args.steps,
             "sigma_seconds_per_sweep_fp64_path": st["t_sigma"] / args.steps,
             "energy_last_sweep": emix[-1],
             "abs_dE_last_sweep_vs_fp64": abs(emix[-1] - energies[-1]),
             "max_abs_dE_per_micro_iteration_vs_fp64": d_micro,
         }
+        if rdm64 is not None:
+            m1, m2, _ = g.rdm()
+            line["mixed"]["rdm_max_abs_error_vs_fp64"] = {"gamma": float(np.abs(m1 - rdm64[0]).max()),
+                                                           "Gamma": float(np.abs(m2 - rdm64[1]).max())}
     g.close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, L, N, args.twoS, args.irrep, args.seed, args.cpu_D)

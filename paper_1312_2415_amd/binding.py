@@ -63,6 +63,8 @@ def load_library(path: str | None = None):
         "sadmrg_stats_passes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_mixed": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl)]),
         "sadmrg_set_precision": (c_int, [c_vp, c_int, c_dbl]),
+        "sadmrg_rdm": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
+        "sadmrg_get_s2": (c_int, [c_vp, P(c_dbl)]),
         "sadmrg_debug_copy_probe": (c_int, [c_vp, ctypes.c_int64, c_int, P(c_dbl)]),
         "sadmrg_last_error": (ctypes.c_char_p, [c_vp]),
         "sadmrg_debug_coupling": (c_int, [c_int, P(c_int), P(c_dbl)]),
@@ -250,7 +252,21 @@ class SaDMRG:
         out["fp32"] = {"t": t32.value, "calls": n32.value, "flops": f32.value}
         return out
 
-    def set_precision(self, mode: int, mixed_tol: float = 3e-5):
+    def rdm(self, two_body: bool = True):
+        """(gamma [L,L], Gamma^A [L,L,L,L] or None, E) at the current two-site centre."""
+        L = self.L
+        g1 = np.zeros((L, L))
+        g2 = np.zeros((L, L, L, L)) if two_body else None
+        e = ctypes.c_double()
+        self._chk(self.lib.sadmrg_rdm(self.h, _dptr(g1), _dptr(g2) if two_body else None, ctypes.byref(e)))
+        return g1, g2, e.value
+
+    def s2(self) -> float:
+        v = ctypes.c_double()
+        self._chk(self.lib.sadmrg_get_s2(self.h, ctypes.byref(v)))
+        return v.value
+
+    def set_precision(self, mode: int, mixed_tol: float = 1e-5):
         """0: FP64 sigma; 1: FP32 sigma in Davidson + FP64 Rayleigh-quotient energy."""
         self._chk(self.lib.sadmrg_set_precision(self.h, int(mode), float(mixed_tol)))
 

@@ -73,10 +73,11 @@ static SiteOp site_product(const SiteOp& U, const SiteOp& V, int tK) {
 }
 
 struct SiteOps {
-  SiteOp I, CD, C, A0, B0, B1, AA0, E, CDE, EC;
+  SiteOp I, CD, C, A0, B0, B1, AA0, E, CDE, EC, NUD;
   SiteOps() {
     const double s2 = std::sqrt(2.0);
     I.el[0][0] = I.el[1][1] = I.el[2][2] = 1.0;
+    NUD.el[2][2] = 1.0;  // n_up n_down
     CD.tk = 1, CD.dN = 1, CD.odd = true, CD.el[1][0] = 1.0, CD.el[2][1] = -s2;  // b+
     C.tk = 1, C.dN = -1, C.odd = true, C.el[0][1] = -s2, C.el[1][2] = -1.0;     // b
     A0 = site_product(CD, CD, 0);                                              // [b+ b+]^0
@@ -99,6 +100,35 @@ static const SiteOps& SO() {
 // ---------------------------------------------------------------------------
 // Problem (the paper's Hamiltonian + Problem objects)
 // ---------------------------------------------------------------------------
+// A coefficient linear in the folded integrals: v = sum_i m_i W[e_i] (at most
+// four entries).  Blocking formulas carry these so that the energy adjoint
+// can route d E / d(coefficient) back to the integrals.
+struct WLin {
+  double v = 0.0;
+  int n = 0;
+  int64_t e[4] = {0, 0, 0, 0};
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+};
+static inline WLin operator*(WLin a, double f) {
+  a.v *= f;
+  for (int i = 0; i < a.n; ++i) a.m[i] *= f;
+  return a;
+}
+static inline WLin operator+(WLin a, const WLin& b) {
+  a.v += b.v;
+  for (int i = 0; i < b.n; ++i) {
+    if (a.n >= 4) fail(-1, "internal: coefficient with more than four integrals");
+    a.e[a.n] = b.e[i];
+    a.m[a.n++] = b.m[i];
+  }
+  return a;
+}
+static inline WLin wconst(double v) {
+  WLin a;
+  a.v = v;
+  return a;
+}
+
 struct Problem {
   int L = 0, order = 1;
   std::vector<int> orb;
@@ -109,6 +139,18 @@ struct Problem {
   double w(int p, int q, int r, int s) const { return W[(((size_t)p * L + q) * L + r) * L + s]; }
   // q^j_ab(r,s): 2 W_abrs - W_rbas (j = 0), W_rbas (j = 1)
   double qc(int tj, int a, int b, int r, int s) const { return tj == 0 ? 2.0 * w(a, b, r, s) - w(r, b, a, s) : w(r, b, a, s); }
+  int64_t wi(int p, int q, int r, int s) const { return (((int64_t)p * L + q) * L + r) * L + s; }
+  WLin wl(int p, int q, int r, int s) const {
+    WLin x;
+    x.v = w(p, q, r, s);
+    x.n = 1;
+    x.e[0] = wi(p, q, r, s);
+    x.m[0] = 1.0;
+    return x;
+  }
+  WLin qcl(int tj, int a, int b, int r, int s) const {
+    return tj == 0 ? wl(a, b, r, s) * 2.0 + wl(r, b, a, s) * -1.0 : wl(r, b, a, s);
+  }
   bool bare_left(int k) const { return k <= L - k; }
   bool bare_right(int k) const { return L - k < k; }
   // section "Complementary operators", trick (a): one-body integrals folded
@@ -303,6 +345,7 @@ struct Layout {
   // adjoint element map (for dN == 0 classes), built on demand
   DArr<int> perm;
   DArr<double> fac;
+  DArr<double> facT;  // fac[perm[e]]: factors of the transposed map (perm is an involution)
   bool adj_ready = false;
 };
 
@@ -371,6 +414,14 @@ struct Store {
     data.alloc((size_t)std::max<int64_t>(total, 1));
     dev_zero(data.p, (size_t)std::max<int64_t>(total, 1) * 8, st);
   }
+  // adjoint (d E / d element) of every operator, same layout (energy adjoint)
+  DBuf adj;
+  void alloc_adj(Stream st) {
+    adj.alloc((size_t)std::max<int64_t>(total, 1));
+    dev_zero(adj.p, (size_t)std::max<int64_t>(total, 1) * 8, st);
+  }
+  bool owns(const double* p) const { return data.p && p >= data.p && p < data.p + total; }
+  double* adj_of(const double* p) const { return adj.p + (p - data.p); }
   void ensure_adjoint_map(int l, Stream st) {
     Layout& L = *lays[l];
     if (L.adj_ready) return;
@@ -389,8 +440,11 @@ struct Store {
           fac[e] = f;
         }
     }
+    std::vector<double> facT(L.nnz);
+    for (int64_t q = 0; q < L.nnz; ++q) facT[q] = fac[perm[q]];
     L.perm.put(perm, st);
     L.fac.put(fac, st);
+    L.facT.put(facT, st);
     L.adj_ready = true;
   }
 };
@@ -410,6 +464,7 @@ struct Term {
   Expr x;
   SiteOp s;
   double coef;
+  WLin wl;  // coef as a linear form of the integrals (n = 0: constant)
 };
 struct Def {
   uint64_t key;
@@ -440,21 +495,32 @@ struct Combos {
     int op;
     double c;
     bool adj;
+    WLin w;  // c as a linear form of the integrals
   };
   std::vector<std::vector<In>> inputs;  // per scratch op
   std::vector<uint64_t> sig;            // dedup signature
-  std::map<std::vector<std::tuple<int, double, bool>>, int> memo;
+  std::map<std::vector<double>, int> memo;
 
   // sum_i c_i op_i over block operators of one class; returns a Ref (store 1)
-  // or an empty expression when all coefficients vanish.
+  // or an empty expression when all coefficients vanish.  A single constant
+  // input becomes a scaled reference to the block operator itself.
   Expr make(const Store& X, const std::vector<In>& in, int tk, int dN, int dG, bool odd) {
     std::vector<In> nz;
     for (auto& i : in)
       if (i.c != 0.0 && i.op >= 0) nz.push_back(i);
     if (nz.empty()) return {};
-    if (nz.size() == 1 && !nz[0].adj) return {Ref{0, nz[0].op, nz[0].c, false}};
-    std::vector<std::tuple<int, double, bool>> key;
-    for (auto& i : nz) key.emplace_back(i.op, i.c, i.adj);
+    if (nz.size() == 1 && !nz[0].adj && nz[0].w.n == 0) return {Ref{0, nz[0].op, nz[0].c, false}};
+    std::vector<double> key;
+    for (auto& i : nz) {
+      key.push_back(i.op);
+      key.push_back(i.c);
+      key.push_back(i.adj);
+      key.push_back(i.w.n);
+      for (int q = 0; q < i.w.n; ++q) {
+        key.push_back((double)i.w.e[q]);
+        key.push_back(i.w.m[q]);
+      }
+    }
     auto it = memo.find(key);
     if (it != memo.end()) return {Ref{1, it->second, 1.0, false}};
     const int o = T.add(K(0, 0, (int)inputs.size(), 0), tk, dN, dG, odd);
@@ -509,6 +575,8 @@ struct Entry {
   int64_t dst;  // element offset in the enlarged store
   int rows, cols, ld;
   GatherSrc src;
+  const Term* term;  // the term that produced it (scale = term->coef * unit)
+  double unit;
 };
 
 struct Materializer {
@@ -584,6 +652,8 @@ struct Materializer {
             e.cols = sub.dim[aket];
             e.ld = cols_mk;
             e.src = {src, ld, kind, scale};
+            e.term = &term;
+            e.unit = f * c9 * sign * sv;
             entries.push_back(e);
             if (mirror) {  // transpose partner: block (mk <- mb) at (offk, offb)
               const int blk2 = OL.find(mk, mb);
@@ -594,6 +664,8 @@ struct Materializer {
               m.cols = sub.dim[abra];
               m.ld = E.dim[mb];
               m.src = {src, ld, kind == GS_NORMAL ? GS_TRANS : (kind == GS_TRANS ? GS_NORMAL : GS_IDENT), scale};
+              m.term = &term;
+              m.unit = e.unit;
               entries.push_back(m);
             }
           }
@@ -658,17 +730,17 @@ struct Blocker {
   int gz(int z) const { return P.orb[z]; }
 
   // sum_z c_z b+_z  (all z in the block share no constraint: grouped by irrep)
-  Expr cdag(const std::vector<double>& coef) {
+  Expr cdag(const std::vector<WLin>& coef) {
     // coefficients of orbitals with different irreps cannot mix; the caller's
     // integrals respect the point group, so at most one irrep is nonzero.
     std::vector<Combos::In> in;
     int g = -1;
     for (int z : X.orbs) {
-      const double c = coef[z];
+      const double c = coef[z].v;
       if (c == 0.0) continue;
       if (g >= 0 && gz(z) != g) fail(-3, "integrals break the point-group symmetry");
       g = gz(z);
-      in.push_back({X.need(K(F_C, 0, z, 0)), c, false});
+      in.push_back({X.need(K(F_C, 0, z, 0)), c, false, coef[z]});
     }
     if (in.empty()) return {};
     return cb.make(X, in, 1, 1, g, true);
@@ -690,7 +762,7 @@ struct Blocker {
         if (tj == 2 && z == zp) continue;
         const int a = std::min(z, zp), b = std::max(z, zp);
         const double f = (z <= zp) ? 1.0 : sg;
-        in.push_back({X.need(K(F_A, tj, a, b)), c * f, false});
+        in.push_back({X.need(K(F_A, tj, a, b)), c * f, false, P.wl(z, w, zp, wp) * f});
       }
     return cb.make(X, in, tj, 2, g, false);
   }
@@ -708,9 +780,9 @@ struct Blocker {
         const double c = P.qc(tj, a, b, r, s);
         if (c == 0.0) continue;
         if (r <= s)
-          in.push_back({X.need(K(F_B, tj, r, s)), c, false});
+          in.push_back({X.need(K(F_B, tj, r, s)), c, false, P.qcl(tj, a, b, r, s)});
         else
-          in.push_back({X.need(K(F_B, tj, s, r)), c * sg, true});
+          in.push_back({X.need(K(F_B, tj, s, r)), c * sg, true, P.qcl(tj, a, b, r, s) * sg});
       }
     return cb.make(X, in, tj, 0, g, false);
   }
@@ -718,11 +790,15 @@ struct Blocker {
 
 static void add_term(Def& d, Expr x, const SiteOp& s, double coef) {
   if (x.empty() || coef == 0.0) return;
-  d.terms.push_back({std::move(x), s, coef});
+  d.terms.push_back({std::move(x), s, coef, wconst(coef)});
+}
+static void add_term_w(Def& d, Expr x, const SiteOp& s, const WLin& coef) {  // integral-valued coefficient
+  if (x.empty() || coef.v == 0.0) return;
+  d.terms.push_back({std::move(x), s, coef.v, coef});
 }
 static void add_sym(Def& d, Expr x, const SiteOp& s, double coef) {
   if (x.empty() || coef == 0.0) return;
-  d.sym.push_back({std::move(x), s, coef});
+  d.sym.push_back({std::move(x), s, coef, wconst(coef)});
 }
 static const Expr IDX = {Ref{-1, -1, 1.0, false}};
 
@@ -733,8 +809,8 @@ static std::vector<Def> defs_left(const Problem& P, Store& X, Combos& cb) {
   const double s2 = std::sqrt(2.0), s3 = std::sqrt(3.0), s32 = std::sqrt(1.5);
   Blocker bk(P, X, cb, P.bare_left(k));
   std::vector<Def> defs;
-  std::vector<double> coef(L, 0.0);
-  auto reset = [&] { std::fill(coef.begin(), coef.end(), 0.0); };
+  std::vector<WLin> coef(L);
+  auto reset = [&] { std::fill(coef.begin(), coef.end(), WLin()); };
 
   for (int x : X.orbs) {
     Def d{K(F_C, 0, x, 0), 1, 1, P.orb[x], true, {}, {}};
@@ -749,12 +825,10 @@ static std::vector<Def> defs_left(const Problem& P, Store& X, Combos& cb) {
   {  // H
     Def d{K(F_H), 0, 0, 0, false, {}, {}};
     add_term(d, {Ref{0, X.need(K(F_H)), 1.0, false}}, so.I, 1.0);
-    SiteOp hk;  // site Hamiltonian: W_kkkk n_up n_down
-    hk.el[2][2] = P.w(k, k, k, k);
-    add_term(d, IDX, hk, 1.0);
+    add_term_w(d, IDX, so.NUD, P.wl(k, k, k, k));  // site Hamiltonian: W_kkkk n_up n_down
     add_sym(d, {Ref{0, X.need(K(F_S, 0, k, 0)), 1.0, false}}, so.C, -s2);
     reset();
-    for (int x : X.orbs) coef[x] = P.w(x, k, k, k);
+    for (int x : X.orbs) coef[x] = P.wl(x, k, k, k);
     add_sym(d, bk.cdag(coef), so.EC, -s2);
     add_sym(d, bk.getP(0, k, k), so.AA0, -0.5);
     add_term(d, bk.getQ(0, k, k), so.B0, 1.0);
@@ -769,15 +843,15 @@ static std::vector<Def> defs_left(const Problem& P, Store& X, Combos& cb) {
     add_term(d, bk.getP(0, y, k), so.C, 1.0 / s2);
     add_term(d, bk.getP(2, y, k), so.C, -s32);
     reset();
-    for (int s : X.orbs) coef[s] = P.w(k, y, k, s);
+    for (int s : X.orbs) coef[s] = P.wl(k, y, k, s);
     add_term(d, adjoint_expr(bk.cdag(coef), X, cb.T), so.A0, 1.0 / s2);
     reset();
-    for (int r : X.orbs) coef[r] = P.w(k, y, r, k) / s2 - s2 * P.w(r, y, k, k);
+    for (int r : X.orbs) coef[r] = P.wl(k, y, r, k) * (1.0 / s2) + P.wl(r, y, k, k) * -s2;
     add_term(d, bk.cdag(coef), so.B0, 1.0);
     reset();
-    for (int r : X.orbs) coef[r] = P.w(k, y, r, k);
+    for (int r : X.orbs) coef[r] = P.wl(k, y, r, k);
     add_term(d, bk.cdag(coef), so.B1, s32);
-    add_term(d, IDX, so.CDE, P.w(k, y, k, k));
+    add_term_w(d, IDX, so.CDE, P.wl(k, y, k, k));
     defs.push_back(d);
   }
   std::vector<int> orbs = X.orbs;
@@ -818,20 +892,20 @@ static std::vector<Def> defs_left(const Problem& P, Store& X, Combos& cb) {
             Def d{K(F_P, tj, w, wp), tj, 2, g, false, {}, {}};
             add_term(d, bk.getP(tj, w, wp), so.I, 1.0);
             reset();
-            for (int z : X.orbs) coef[z] = P.w(z, w, k, wp) + sg * P.w(k, w, z, wp);
+            for (int z : X.orbs) coef[z] = P.wl(z, w, k, wp) + P.wl(k, w, z, wp) * sg;
             add_term(d, bk.cdag(coef), so.CD, 1.0);
-            if (tj == 0) add_term(d, IDX, so.A0, P.w(k, w, k, wp));
+            if (tj == 0) add_term_w(d, IDX, so.A0, P.wl(k, w, k, wp));
             defs.push_back(d);
           }
           Def d{K(F_Q, tj, w, wp), tj, 0, g, false, {}, {}};
           add_term(d, bk.getQ(tj, w, wp), so.I, 1.0);
           reset();
-          for (int r : X.orbs) coef[r] = P.qc(tj, w, wp, r, k);
+          for (int r : X.orbs) coef[r] = P.qcl(tj, w, wp, r, k);
           add_term(d, bk.cdag(coef), so.C, 1.0);
           reset();
-          for (int s : X.orbs) coef[s] = P.qc(tj, w, wp, k, s);
+          for (int s : X.orbs) coef[s] = P.qcl(tj, w, wp, k, s);
           add_term(d, adjoint_expr(bk.cdag(coef), X, cb.T), so.CD, sg);
-          add_term(d, IDX, so.B(tj), P.qc(tj, w, wp, k, k));
+          add_term_w(d, IDX, so.B(tj), P.qcl(tj, w, wp, k, k));
           defs.push_back(d);
         }
       }
@@ -846,8 +920,8 @@ static std::vector<Def> defs_right(const Problem& P, Store& Y, Combos& cb) {
   const double s2 = std::sqrt(2.0), s3 = std::sqrt(3.0), s32 = std::sqrt(1.5);
   Blocker bk(P, Y, cb, P.bare_right(k + 1));
   std::vector<Def> defs;
-  std::vector<double> coef(P.L, 0.0);
-  auto reset = [&] { std::fill(coef.begin(), coef.end(), 0.0); };
+  std::vector<WLin> coef(P.L);
+  auto reset = [&] { std::fill(coef.begin(), coef.end(), WLin()); };
 
   for (int y : Y.orbs) {
     Def d{K(F_C, 0, y, 0), 1, 1, P.orb[y], true, {}, {}};
@@ -862,11 +936,9 @@ static std::vector<Def> defs_right(const Problem& P, Store& Y, Combos& cb) {
   {  // H
     Def d{K(F_H), 0, 0, 0, false, {}, {}};
     add_term(d, {Ref{0, Y.need(K(F_H)), 1.0, false}}, so.I, 1.0);
-    SiteOp hk;
-    hk.el[2][2] = P.w(k, k, k, k);
-    add_term(d, IDX, hk, 1.0);
+    add_term_w(d, IDX, so.NUD, P.wl(k, k, k, k));
     reset();
-    for (int y : Y.orbs) coef[y] = P.w(k, y, k, k);
+    for (int y : Y.orbs) coef[y] = P.wl(k, y, k, k);
     add_sym(d, adjoint_expr(bk.cdag(coef), Y, cb.T), so.CDE, -s2);
     add_sym(d, adjoint_expr({Ref{0, Y.need(K(F_S, 0, k, 0)), 1.0, false}}, Y, cb.T), so.CD, -s2);
     add_sym(d, adjoint_expr(bk.getP(0, k, k), Y, cb.T), so.A0, 0.5);
@@ -882,15 +954,15 @@ static std::vector<Def> defs_right(const Problem& P, Store& Y, Combos& cb) {
     add_term(d, bk.getP(0, x, k), so.C, 1.0 / s2);
     add_term(d, bk.getP(2, x, k), so.C, s32);
     reset();
-    for (int s : Y.orbs) coef[s] = P.w(x, k, k, s);
+    for (int s : Y.orbs) coef[s] = P.wl(x, k, k, s);
     add_term(d, adjoint_expr(bk.cdag(coef), Y, cb.T), so.A0, 1.0 / s2);
     reset();
-    for (int r : Y.orbs) coef[r] = P.w(x, k, r, k) / s2 - s2 * P.w(x, r, k, k);
+    for (int r : Y.orbs) coef[r] = P.wl(x, k, r, k) * (1.0 / s2) + P.wl(x, r, k, k) * -s2;
     add_term(d, bk.cdag(coef), so.B0, 1.0);
     reset();
-    for (int r : Y.orbs) coef[r] = P.w(x, k, r, k);
+    for (int r : Y.orbs) coef[r] = P.wl(x, k, r, k);
     add_term(d, bk.cdag(coef), so.B1, -s32);
-    add_term(d, IDX, so.CDE, P.w(x, k, k, k));
+    add_term_w(d, IDX, so.CDE, P.wl(x, k, k, k));
     defs.push_back(d);
   }
   std::vector<int> orbs;
@@ -932,20 +1004,20 @@ static std::vector<Def> defs_right(const Problem& P, Store& Y, Combos& cb) {
             Def d{K(F_P, tj, w, wp), tj, 2, g, false, {}, {}};
             add_term(d, bk.getP(tj, w, wp), so.I, 1.0);
             reset();
-            for (int z : Y.orbs) coef[z] = P.w(k, w, z, wp) + sg * P.w(z, w, k, wp);
+            for (int z : Y.orbs) coef[z] = P.wl(k, w, z, wp) + P.wl(z, w, k, wp) * sg;
             add_term(d, bk.cdag(coef), so.CD, 1.0);
-            if (tj == 0) add_term(d, IDX, so.A0, P.w(k, w, k, wp));
+            if (tj == 0) add_term_w(d, IDX, so.A0, P.wl(k, w, k, wp));
             defs.push_back(d);
           }
           Def d{K(F_Q, tj, w, wp), tj, 0, g, false, {}, {}};
           add_term(d, bk.getQ(tj, w, wp), so.I, 1.0);
           reset();
-          for (int s : Y.orbs) coef[s] = P.qc(tj, w, wp, k, s);
+          for (int s : Y.orbs) coef[s] = P.qcl(tj, w, wp, k, s);
           add_term(d, adjoint_expr(bk.cdag(coef), Y, cb.T), so.CD, 1.0);
           reset();
-          for (int r : Y.orbs) coef[r] = P.qc(tj, w, wp, r, k);
+          for (int r : Y.orbs) coef[r] = P.qcl(tj, w, wp, r, k);
           add_term(d, bk.cdag(coef), so.C, sg);
-          add_term(d, IDX, so.B(tj), P.qc(tj, w, wp, k, k));
+          add_term_w(d, IDX, so.B(tj), P.qcl(tj, w, wp, k, k));
           defs.push_back(d);
         }
       }
@@ -953,37 +1025,50 @@ static std::vector<Def> defs_right(const Problem& P, Store& Y, Combos& cb) {
   return defs;
 }
 
+// The blocking of one enlargement: the evaluated scratch combinations, the
+// enlarged store's structure and its materialisation entries (host).
+struct EnlargeTrace {
+  Combos cb;
+  std::vector<Def> defs;
+  std::unique_ptr<Store> out;
+  Materializer mat;
+};
+
+static void trace_enlarge(const Problem& P, Store& X, const Enl& E, bool left, Stream st, EnlargeTrace& tr) {
+  tr.cb.T.side = X.side;
+  tr.cb.T.bond = X.bond;
+  tr.cb.T.basis = X.basis;
+  tr.defs = left ? defs_left(P, X, tr.cb) : defs_right(P, X, tr.cb);
+  tr.cb.run(X, st);
+  tr.out = std::make_unique<Store>();
+  Store& out = *tr.out;
+  out.side = left ? 'L' : 'R';
+  out.bond = left ? X.bond + 1 : X.bond - 1;
+  out.orbs = X.orbs;
+  if (left)
+    out.orbs.push_back(X.bond);
+  else
+    out.orbs.insert(out.orbs.begin(), X.bond - 1);
+  out.basis.sec = E.sec;
+  out.basis.dim = E.dim;
+  std::vector<int> opidx;
+  for (auto& d : tr.defs) opidx.push_back(out.add(d.key, d.tk, d.dN, d.dG, d.odd));
+  for (size_t i = 0; i < tr.defs.size(); ++i) {
+    for (auto& t : tr.defs[i].terms) tr.mat.emit_op(P, X, tr.cb.T, E, out, opidx[i], t, left, false);
+    for (auto& t : tr.defs[i].sym) tr.mat.emit_op(P, X, tr.cb.T, E, out, opidx[i], t, left, true);
+  }
+}
+
 // Enlarge a block by one site: combinations, then materialisation.
 static std::unique_ptr<Store> enlarge(const Problem& P, Store& X, const Enl& E, bool left, Stream st,
                                       int64_t* n_entries) {
-  Combos cb;
-  cb.T.side = X.side;
-  cb.T.bond = X.bond;
-  cb.T.basis = X.basis;
-  std::vector<Def> defs = left ? defs_left(P, X, cb) : defs_right(P, X, cb);
-  cb.run(X, st);
-  auto out = std::make_unique<Store>();
-  out->side = left ? 'L' : 'R';
-  out->bond = left ? X.bond + 1 : X.bond - 1;
-  out->orbs = X.orbs;
-  if (left)
-    out->orbs.push_back(X.bond);
-  else
-    out->orbs.insert(out->orbs.begin(), X.bond - 1);
-  out->basis.sec = E.sec;
-  out->basis.dim = E.dim;
-  std::vector<int> opidx;
-  for (auto& d : defs) opidx.push_back(out->add(d.key, d.tk, d.dN, d.dG, d.odd));
-  out->allocate(st);
-  Materializer mat;
-  for (size_t i = 0; i < defs.size(); ++i) {
-    for (auto& t : defs[i].terms) mat.emit_op(P, X, cb.T, E, *out, opidx[i], t, left, false);
-    for (auto& t : defs[i].sym) mat.emit_op(P, X, cb.T, E, *out, opidx[i], t, left, true);
-  }
-  mat.run(*out, st);
-  if (n_entries) *n_entries += mat.n_entries;
+  EnlargeTrace tr;
+  trace_enlarge(P, X, E, left, st, tr);
+  tr.out->allocate(st);
+  tr.mat.run(*tr.out, st);
+  if (n_entries) *n_entries += tr.mat.n_entries;
   dev_sync(st);  // scratch combinations are released on return
-  return out;
+  return std::move(tr.out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1015,10 +1100,13 @@ struct GemmList {
   // block registered at `first` (rows x cols) += coef * opA(A)[rows x K] * opB(B)[K x cols]
   void add(int first, int rows, int cols, const GTask& base) {
     if (base.K <= 0 || rows <= 0 || cols <= 0) return;
-    // the kernel addresses each operand of a tile with 32-bit byte offsets
-    // (element offsets up to (K + 64) * ld must stay below 2^28)
+    // the kernel addresses each operand of a tile with 32-bit byte offsets:
+    // the largest element offset it forms, (64 ld + K) for storage contiguous
+    // along k and (K + 32) ld + 64 otherwise, must stay below 2^28
     const int64_t lim = (int64_t)1 << 28;
-    if ((int64_t)(base.K + 64) * std::max(base.lda, TS) >= lim || (int64_t)(base.K + 64) * std::max(base.ldb, TS) >= lim)
+    auto reach = [](bool kfast, int64_t ld, int64_t K) { return kfast ? 64 * ld + K + 64 : (K + 32) * ld + 64; };
+    if (reach(!(base.flags & GT_TRANS_A), base.lda, base.K) >= lim ||
+        reach((base.flags & GT_TRANS_B) != 0, base.ldb, base.K) >= lim)
       fail(-4, "block product too large for the grouped GEMM kernel");
     const int ntc = (cols + TS - 1) / TS;
     for (int r0 = 0, tr = 0; r0 < rows; r0 += TS, ++tr)
@@ -1218,18 +1306,19 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
     const int R = outs[x.blk].rows, Cc = outs[x.blk].cols;
     const int trA = (x.flags & TT_TRANS_A) ? GT_TRANS_A : 0;
     const int trC = (x.flags & TT_TRANS_C) ? GT_TRANS_B : 0;
+    const bool trB = (x.flags & TT_TRANS_B) != 0;  // middle factor transposed
     if (x.flags & TT_IDENT_C) {
-      g2.add(first[x.blk], R, Cc, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA, x.coef});
+      g2.add(first[x.blk], R, Cc, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA | (trB ? GT_TRANS_B : 0), x.coef});
       fl += 2.0 * R * x.K1 * Cc;
       by2 += 8.0 * ((double)R * x.K1 + (double)x.K1 * Cc);
     } else if (x.flags & TT_IDENT_A) {
-      g2.add(first[x.blk], R, Cc, GTask{x.b, x.c, x.ldb, x.ldc, x.K2, trC, x.coef});
+      g2.add(first[x.blk], R, Cc, GTask{x.b, x.c, x.ldb, x.ldc, x.K2, trC | (trB ? GT_TRANS_A : 0), x.coef});
       fl += 2.0 * R * x.K2 * Cc;
       by2 += 8.0 * ((double)R * x.K2 + (double)x.K2 * Cc);
     } else {
       double* T = tp.ws.p + slot[i];
       const int b1 = g1.add_block(T, R, x.K2, x.K2, 1);
-      g1.add(b1, R, x.K2, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA, 1.0});
+      g1.add(b1, R, x.K2, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA | (trB ? GT_TRANS_B : 0), 1.0});
       g2.add(first[x.blk], R, Cc, GTask{T, x.c, x.K2, x.ldc, x.K2, trC, x.coef});
       fl += 2.0 * R * x.K1 * x.K2 + 2.0 * R * x.K2 * Cc;
       f1 += 2.0 * R * x.K1 * x.K2;
@@ -1286,6 +1375,7 @@ struct Step {
   // FP32 mirror of the sigma evaluation (built on first use): operator
   // stores, vectors, workspace and partial tiles as float arrays, and the
   // same plan with every record pointer moved to the mirror.
+  std::vector<Triple> trs;  // the sigma products (kept for the energy adjoint)
   bool f32_ready = false;
   DBuf x32, y32, in32, out32, ws32, p1part32, p2part32;
   GemmList::Plan q1, q2;
@@ -1318,8 +1408,8 @@ struct Engine {
   int64_t n_pass1 = 0, n_pass2 = 0;
   double t_sigma32 = 0, f_sigma32 = 0;
   int64_t n_sigma32 = 0;
-  int prec = 0;             // 0: FP64 sigma; 1: FP32 sigma + FP64 Rayleigh quotient
-  double mixed_tol = 3e-5;  // Davidson tolerance of the FP32 phase
+  int prec = 0;             // 0: FP64 sigma; 1: FP32 sigma in Davidson + FP64 Rayleigh quotient
+  double mixed_tol = 1e-5;  // Davidson tolerance of the FP32 phase
   int64_t n_sigma = 0;
   // Davidson work buffers
   DBuf dV, dW, dHs, dsmall, dpartial, dx_, dax, dr, dt;
@@ -1412,6 +1502,400 @@ struct Engine {
     tp.run(st);
     dev_sync(st);
     return out;
+  }
+
+  // ==========================================================================
+  // Energy adjoint: the spin-summed 1- and 2-RDMs as derivatives of
+  // E = <psi|H_eff|psi> at a two-site centre with respect to the folded
+  // integrals W.  E is linear in W through the complementary operators of every
+  // block; reverse-mode differentiation runs the sigma products, the
+  // enlargements (materialisation, integral-weighted combinations) and the
+  // renormalisations backwards with transposed products, and collects
+  // d E / d W[e] on the host from the coefficients' linear forms.
+  // ==========================================================================
+
+  // Xbar, Ybar of the centre's enlarged stores from the sigma products:
+  // for sigma[blk] += coef opA(A) B opC(C) and E = sum psi[blk] . sigma[blk],
+  // Abar and Cbar are products of psi blocks with the other factor.
+  void seed_adjoints() {
+    Store &X = *step.X, &Y = *step.Y;
+    X.alloc_adj(st);
+    Y.alloc_adj(st);
+    std::vector<OutBlk> outs;
+    std::map<double*, int> oid;
+    auto out_of = [&](Store& S, const double* blk, int rows, int cols) -> int {
+      double* a = S.adj_of(blk);
+      auto it = oid.find(a);
+      if (it != oid.end()) return it->second;
+      outs.push_back({a, rows, cols, cols});
+      return oid[a] = (int)outs.size() - 1;
+    };
+    std::vector<Triple> at;
+    for (const Triple& t : step.trs) {
+      const int blk = t.blk;
+      const double* O = step.in.p + step.off[blk];
+      const int R = step.dx[blk], C = step.dy[blk];
+      const bool hasA = !(t.flags & TT_IDENT_A), hasC = !(t.flags & TT_IDENT_C);
+      const bool trA = (t.flags & TT_TRANS_A) != 0, trC = (t.flags & TT_TRANS_C) != 0;
+      // sigma[blk] (R x C) += coef opA(A) [R x K1] B [K1 x K2] opC(C) [K2 x C];
+      // without C, B is K1 x C; without A, B is R x K2
+      if (hasA) {
+        Triple a{};
+        a.coef = t.coef;
+        if (!trA) {  // A is R x K1
+          a.blk = out_of(X, t.a, R, t.K1);
+          a.a = O, a.lda = C, a.K1 = C;
+          if (hasC) {  // Abar += O opC(C)^T B^T
+            a.b = t.c, a.ldb = t.ldc, a.K2 = t.K2;
+            a.c = t.b, a.ldc = t.ldb;
+            a.flags = (trC ? 0 : TT_TRANS_B) | TT_TRANS_C;
+          } else {  // Abar += O B^T
+            a.b = t.b, a.ldb = t.ldb;
+            a.flags = TT_IDENT_C | TT_TRANS_B;
+          }
+        } else {  // A is K1 x R
+          a.blk = out_of(X, t.a, t.K1, R);
+          a.a = t.b, a.lda = t.ldb;
+          if (hasC) {  // Abar += B opC(C) O^T
+            a.K1 = t.K2;
+            a.b = t.c, a.ldb = t.ldc, a.K2 = C;
+            a.c = O, a.ldc = C;
+            a.flags = (trC ? TT_TRANS_B : 0) | TT_TRANS_C;
+          } else {  // Abar += B O^T
+            a.K1 = C;
+            a.b = O, a.ldb = C;
+            a.flags = TT_IDENT_C | TT_TRANS_B;
+          }
+        }
+        at.push_back(a);
+      }
+      if (hasC) {
+        Triple c{};
+        c.coef = t.coef;
+        if (!trC) {  // C is K2 x C
+          c.blk = out_of(Y, t.c, t.K2, C);
+          if (hasA) {  // Cbar += B^T opA(A)^T O
+            c.a = t.b, c.lda = t.ldb, c.K1 = t.K1;
+            c.b = t.a, c.ldb = t.lda, c.K2 = R;
+            c.c = O, c.ldc = C;
+            c.flags = TT_TRANS_A | (trA ? 0 : TT_TRANS_B);
+          } else {  // Cbar += B^T O
+            c.b = t.b, c.ldb = t.ldb, c.K2 = R;
+            c.c = O, c.ldc = C;
+            c.flags = TT_IDENT_A | TT_TRANS_B;
+          }
+        } else {  // C is C x K2
+          c.blk = out_of(Y, t.c, C, t.K2);
+          c.a = O, c.lda = C, c.K1 = R;
+          if (hasA) {  // Cbar += O^T opA(A) B
+            c.b = t.a, c.ldb = t.lda, c.K2 = t.K1;
+            c.c = t.b, c.ldc = t.ldb;
+            c.flags = TT_TRANS_A | (trA ? TT_TRANS_B : 0);
+          } else {  // Cbar += O^T B
+            c.b = t.b, c.ldb = t.ldb;
+            c.flags = TT_IDENT_C | TT_TRANS_A;
+          }
+        }
+        at.push_back(c);
+      }
+    }
+    TwoPass tp;
+    build_two_pass(outs, at, tp, st);
+    tp.run(st);
+    dev_sync(st);
+  }
+
+  // Ebar of an enlarged store from Rbar of the block renormalised from it:
+  // left R = U^T E U  ->  Ebar = U Rbar U^T;  right R = V E V^T  ->  Ebar = V^T Rbar V
+  void renorm_backward(const Store& R, Store& E, const Tensor& T, bool left) {
+    E.alloc_adj(st);
+    std::vector<OutBlk> outs;
+    std::vector<Triple> trs;
+    const Basis& nb = R.basis;
+    for (size_t i = 0; i < R.ops.size(); ++i) {
+      const Layout& NL = R.lay((int)i);
+      const Layout& EL = E.lay((int)i);
+      for (size_t b = 0; b < NL.bra.size(); ++b) {
+        const Sec &sb = nb.sec[NL.bra[b]], &sk = nb.sec[NL.ket[b]];
+        const int eb = E.basis.find(sb), ek = E.basis.find(sk);
+        const int tb = T.find(sb), tkk = T.find(sk);
+        if (eb < 0 || ek < 0 || tb < 0 || tkk < 0) fail(-1, "internal: renormalisation sector missing");
+        const int eblk = EL.find(eb, ek);
+        if (eblk < 0) continue;
+        const int kb = nb.dim[NL.bra[b]], kk = nb.dim[NL.ket[b]];
+        const int rows = E.basis.dim[eb], cols = E.basis.dim[ek];
+        outs.push_back({E.adj.p + E.ops[i].off + EL.eoff[eblk], rows, cols, cols});
+        Triple t{};
+        t.blk = (int)outs.size() - 1;
+        t.coef = 1.0;
+        t.a = T.at(tb), t.lda = T.cols[tb], t.K1 = kb;
+        t.b = R.adj.p + R.ops[i].off + NL.eoff[b], t.ldb = kk;
+        t.c = T.at(tkk), t.ldc = T.cols[tkk], t.K2 = kk;
+        t.flags = left ? TT_TRANS_C : TT_TRANS_A;
+        trs.push_back(t);
+      }
+    }
+    TwoPass tp;
+    build_two_pass(outs, trs, tp, st);
+    tp.run(st);
+    dev_sync(st);
+  }
+
+  // Xbar of the block and d E / d W from Ebar of the store enlarged from it.
+  void enlarge_backward(Store& X, EnlargeTrace& tr, std::vector<double>& G) {
+    Store& Out = *tr.out;
+    Store& T = tr.cb.T;
+    X.alloc_adj(st);
+    if (!T.ops.empty()) T.alloc_adj(st);
+    // (1) transposed materialisation: every source block collects
+    //     scale * op^T(Ebar sub-block) over the entries that read it
+    struct Grp {
+      double* dst;
+      int rows, cols, ld;
+      std::vector<GatherSrc> src;
+    };
+    std::map<double*, int> gid;
+    std::vector<Grp> groups;
+    std::vector<TraceJob> jobs;
+    std::vector<const Entry*> jent;
+    for (const Entry& en : tr.mat.entries) {
+      double* dsub = Out.adj.p + en.dst;
+      if (en.src.kind == GS_IDENT) {  // identity on the block: the coefficient may be an integral
+        if (en.term->wl.n > 0) {
+          jobs.push_back({dsub, en.rows, en.ld});
+          jent.push_back(&en);
+        }
+        continue;
+      }
+      const double* s = en.src.src;
+      double* sadj = X.owns(s) ? X.adj_of(s) : (T.owns(s) ? T.adj_of(s) : nullptr);
+      if (!sadj) fail(-1, "internal: materialisation source outside the block and its combinations");
+      const bool trn = en.src.kind == GS_TRANS;
+      auto it = gid.find(sadj);
+      int g;
+      if (it == gid.end()) {
+        g = (int)groups.size();
+        gid[sadj] = g;
+        groups.push_back({sadj, trn ? en.cols : en.rows, trn ? en.rows : en.cols, en.src.ld, {}});
+      } else {
+        g = it->second;
+      }
+      groups[g].src.push_back({dsub, en.ld, en.src.kind, en.src.scale});
+    }
+    {
+      std::vector<GatherDst> dsts;
+      std::vector<GatherSrc> srcs;
+      for (const Grp& g : groups) {
+        GatherDst d{g.dst, g.rows, g.cols, g.ld, (int)srcs.size(), 0};
+        for (const GatherSrc& s : g.src) srcs.push_back(s);
+        d.s1 = (int)srcs.size();
+        dsts.push_back(d);
+      }
+      DArr<GatherDst> ddst;
+      DArr<GatherSrc> dsrc;
+      ddst.put(dsts, st);
+      dsrc.put(srcs, st);
+      launch_gather(ddst.p, (int)dsts.size(), dsrc.p, st);
+      dev_sync(st);
+    }
+    // (2) integral-valued coefficients of identity terms: d E / d coef = unit * trace
+    if (!jobs.empty()) {
+      DArr<TraceJob> dj;
+      dj.put(jobs, st);
+      DBuf tv;
+      tv.alloc(jobs.size());
+      launch_traces(dj.p, (int)jobs.size(), tv.p, st);
+      std::vector<double> h(jobs.size());
+      dev_d2h(h.data(), tv.p, h.size() * 8, st);
+      for (size_t j = 0; j < jobs.size(); ++j) {
+        const WLin& w = jent[j]->term->wl;
+        const double d = jent[j]->unit * h[j];
+        for (int q = 0; q < w.n; ++q) G[w.e[q]] += w.m[q] * d;
+      }
+    }
+    if (T.ops.empty()) return;
+    // (3) transposed combinations: Xbar[op_i] += c_i op_i^T(Tbar[o])
+    {
+      std::map<int, std::vector<std::pair<int, int>>> by_op;  // X op -> (combo, input index)
+      for (size_t o = 0; o < T.ops.size(); ++o)
+        for (size_t i = 0; i < tr.cb.inputs[o].size(); ++i) by_op[tr.cb.inputs[o][i].op].push_back({(int)o, (int)i});
+      std::vector<ComboOut> outs;
+      std::vector<ComboIn> ins;
+      int64_t maxn = 0;
+      for (auto& [op, lst] : by_op) {
+        const int xl = X.ops[op].lay;
+        bool any_adj = false;
+        for (auto& [o, i] : lst) any_adj |= tr.cb.inputs[o][i].adj;
+        if (any_adj) X.ensure_adjoint_map(xl, st);
+        ComboOut co;
+        co.out = X.adj.p + X.ops[op].off;
+        co.nnz = X.lays[xl]->nnz;
+        co.i0 = (int)ins.size();
+        ins.push_back({co.out, 1.0, 0});
+        for (auto& [o, i] : lst) {
+          const Combos::In& in = tr.cb.inputs[o][i];
+          ins.push_back({T.adj.p + T.ops[o].off, in.c, in.adj ? 1 : 0});
+        }
+        co.i1 = (int)ins.size();
+        co.perm = any_adj ? X.lays[xl]->perm.p : nullptr;
+        co.fac = any_adj ? X.lays[xl]->facT.p : nullptr;
+        outs.push_back(co);
+        maxn = std::max(maxn, co.nnz);
+      }
+      DArr<ComboOut> dout;
+      DArr<ComboIn> din;
+      dout.put(outs, st);
+      din.put(ins, st);
+      launch_combo(dout.p, (int)outs.size(), din.p, maxn, st);
+      dev_sync(st);
+    }
+    // (4) d E / d c_i = < Tbar[o], op_i(X[op_i]) >, one GEMM per operator class
+    std::map<int, std::vector<int>> combos_of_class;  // X layout -> combos
+    for (size_t o = 0; o < T.ops.size(); ++o) {
+      const Layout& L = *T.lays[T.ops[o].lay];
+      combos_of_class[X.layout(L.tk, L.dN, L.dG)].push_back((int)o);
+    }
+    for (auto& [xl, cos] : combos_of_class) {
+      const int64_t nnz = X.lays[xl]->nnz;
+      if (nnz == 0) continue;
+      std::map<std::pair<int, int>, int> col;  // (X op, adj) -> column
+      for (int o : cos)
+        for (const Combos::In& in : tr.cb.inputs[o]) col.emplace(std::make_pair(in.op, in.adj ? 1 : 0), 0);
+      int nc = 0;
+      for (auto& kv : col) kv.second = nc++;
+      const int M = (int)cos.size();
+      DBuf Am, Bm, Gm;
+      Am.alloc((size_t)M * nnz);
+      Bm.alloc((size_t)nc * nnz);
+      Gm.alloc((size_t)M * nc);
+      dev_zero(Gm.p, (size_t)M * nc * 8, st);
+      for (int r = 0; r < M; ++r) dev_d2d(Am.p + (int64_t)r * nnz, T.adj.p + T.ops[cos[r]].off, (size_t)nnz * 8, st);
+      std::vector<ComboOut> outs;
+      std::vector<ComboIn> ins;
+      bool any_adj = false;
+      for (auto& [key, c] : col) {
+        if (key.second) {
+          any_adj = true;
+          X.ensure_adjoint_map(xl, st);
+          ComboOut co{Bm.p + (int64_t)c * nnz, nnz, (int)ins.size(), (int)ins.size() + 1, X.lays[xl]->perm.p,
+                      X.lays[xl]->fac.p};
+          ins.push_back({X.data.p + X.ops[key.first].off, 1.0, 1});
+          outs.push_back(co);
+        } else {
+          dev_d2d(Bm.p + (int64_t)c * nnz, X.data.p + X.ops[key.first].off, (size_t)nnz * 8, st);
+        }
+      }
+      if (any_adj) {
+        DArr<ComboOut> dout;
+        DArr<ComboIn> din;
+        dout.put(outs, st);
+        din.put(ins, st);
+        launch_combo(dout.p, (int)outs.size(), din.p, nnz, st);
+      }
+      GemmList gl;
+      const int first = gl.add_block(Gm.p, M, nc, nc, 0);
+      gl.add(first, M, nc, GTask{Am.p, Bm.p, (int)nnz, (int)nnz, (int)nnz, GT_TRANS_B, 1.0});
+      GemmList::Plan pl;
+      gl.plan(pl, st, GEMM_GPC_PASS2);
+      pl.run(st);
+      std::vector<double> g((size_t)M * nc);
+      dev_d2h(g.data(), Gm.p, g.size() * 8, st);
+      for (int r = 0; r < M; ++r)
+        for (const Combos::In& in : tr.cb.inputs[cos[r]]) {
+          const double d = g[(size_t)r * nc + col[{in.op, in.adj ? 1 : 0}]];
+          for (int q = 0; q < in.w.n; ++q) G[in.w.e[q]] += in.w.m[q] * d;
+        }
+    }
+  }
+
+  // d E / d W (L^4, accumulated into G) for E = <psi|H_eff|psi> / <psi|psi> at
+  // the current two-site centre; returns E (without E_const).
+  double energy_gradient(std::vector<double>& G) {
+    if (!mps_ready) fail(-1, "no MPS");
+    if (cen.kind != C_TWO) fail(-1, "RDMs need a two-site centre (after a sweep, a micro-iteration or an import)");
+    const int i = cen.pos;
+    prepare(i);
+    const int64_t n = step.n;
+    dsmall.ensure(8 * 64 + 64 * 64);
+    dpartial.ensure(256 * 64);
+    launch_dots(step.in.p, n, 1, step.in.p, n, dsmall.p, dpartial.p, st);
+    launch_normalize(step.in.p, dsmall.p, n, st);
+    sigma_fixed(false);
+    launch_dots(step.in.p, n, 1, step.out.p, n, dsmall.p + 1, dpartial.p, st);
+    double e;
+    dev_d2h(&e, dsmall.p + 1, 8, st);
+    G.assign((size_t)P.L * P.L * P.L * P.L, 0.0);
+    seed_adjoints();
+    {  // left blocks: bond i down to 0
+      EnlargeTrace tr;
+      trace_enlarge(P, *Lb[i], step.EX, true, st, tr);
+      if (tr.out->total != step.X->total) fail(-1, "internal: enlarged store mismatch in the adjoint");
+      tr.out->adj = std::move(step.X->adj);
+      for (int k = i;; --k) {
+        enlarge_backward(*Lb[k], tr, G);
+        tr.out->adj.release();
+        if (k == 0) break;
+        EnlargeTrace prev;
+        std::set<Sec> keep(dims[k].sec.begin(), dims[k].sec.end());
+        Enl E = left_enl(P, k, Lb[k - 1]->basis, &keep);
+        trace_enlarge(P, *Lb[k - 1], E, true, st, prev);
+        renorm_backward(*Lb[k], *prev.out, U[k - 1], true);
+        Lb[k]->adj.release();
+        tr = std::move(prev);
+      }
+      Lb[0]->adj.release();
+    }
+    {  // right blocks: bond i+2 up to L
+      EnlargeTrace tr;
+      trace_enlarge(P, *Rb[i + 2], step.EY, false, st, tr);
+      if (tr.out->total != step.Y->total) fail(-1, "internal: enlarged store mismatch in the adjoint");
+      tr.out->adj = std::move(step.Y->adj);
+      for (int k = i + 2;; ++k) {
+        enlarge_backward(*Rb[k], tr, G);
+        tr.out->adj.release();
+        if (k == P.L) break;
+        EnlargeTrace prev;
+        std::set<Sec> keep(dims[k].sec.begin(), dims[k].sec.end());
+        Enl E = right_enl(P, k, Rb[k + 1]->basis, &keep);
+        trace_enlarge(P, *Rb[k + 1], E, false, st, prev);
+        renorm_backward(*Rb[k], *prev.out, V[k], false);
+        Rb[k]->adj.release();
+        tr = std::move(prev);
+      }
+      Rb[P.L]->adj.release();
+    }
+    return e;
+  }
+
+  // Spin-summed 1-RDM gamma_pq = <E_pq> and 2-RDM Gamma_{ij;kl} =
+  // sum_{st} <a+_is a+_jt a_lt a_ks> (symmetrised over the eightfold
+  // permutations of the integral it multiplies) from d E / d W.
+  double rdms(double* rdm1, double* rdm2) {
+    std::vector<double> G;
+    const double e = energy_gradient(G);
+    const int L = P.L;
+    auto ix = [L](int p, int q, int r, int s) { return (((size_t)p * L + q) * L + r) * L + s; };
+    std::vector<double> D((size_t)L * L * L * L);
+    for (int p = 0; p < L; ++p)
+      for (int q = 0; q < L; ++q)
+        for (int r = 0; r < L; ++r)
+          for (int s = 0; s < L; ++s)
+            D[ix(p, q, r, s)] = (G[ix(p, q, r, s)] + G[ix(q, p, r, s)] + G[ix(p, q, s, r)] + G[ix(q, p, s, r)] +
+                                 G[ix(r, s, p, q)] + G[ix(s, r, p, q)] + G[ix(r, s, q, p)] + G[ix(s, r, q, p)]) /
+                                8.0;
+    if (rdm2)
+      for (int p = 0; p < L; ++p)
+        for (int q = 0; q < L; ++q)
+          for (int r = 0; r < L; ++r)
+            for (int s = 0; s < L; ++s) rdm2[ix(p, r, q, s)] = 2.0 * D[ix(p, q, r, s)];
+    if (rdm1)
+      for (int p = 0; p < L; ++p)
+        for (int q = 0; q < L; ++q) {
+          double v = 0.0;
+          for (int r = 0; r < L; ++r) v += D[ix(p, q, r, r)];
+          rdm1[p * L + q] = 2.0 * v / (P.N - 1);
+        }
+    return e + P.e_const;
   }
 
   // ---- random initial MPS (section "DMRG" of the library description)
@@ -1746,6 +2230,7 @@ struct Engine {
     for (auto& [s, o] : touched) bytes += 8.0 * (s == 0 ? X.lay(o).nnz : Y.lay(o).nnz);
     bytes += 16.0 * step.n;
     build_two_pass(outs, trs, step.plan, st, true);
+    step.trs = trs;
     step.flops = step.plan.flops;
     step.bytes = bytes;
     step.ntasks = (int64_t)trs.size();
@@ -2878,7 +3363,7 @@ int sadmrg_sigma(sadmrg_ctx* ctx, const double* x, double* y, int on_device) {
     auto& S = E.step;
     if (S.i < 0 || !S.X) sadmrg::fail(SADMRG_EINVAL, "no prepared step");
     if (!x || !y) sadmrg::fail(SADMRG_EINVAL, "null vector");
-    const bool f32 = E.prec == 1;
+    const bool f32 = E.prec != 0;
     if (on_device) {
       E.sigma_vec(x, y, f32);
       sadmrg::dev_sync(E.st);
@@ -2980,12 +3465,32 @@ int sadmrg_stats_passes(sadmrg_ctx* ctx, double* pass1, double* pass2) {
   });
 }
 
+int sadmrg_rdm(sadmrg_ctx* ctx, double* rdm1, double* rdm2, double* energy) {
+  return guard(ctx, [&] {
+    auto& E = ctx->e;
+    if (E.P.N < 2) sadmrg::fail(SADMRG_ESYMM, "no target");
+    const double e = E.rdms(rdm1, rdm2);
+    if (energy) *energy = e;
+    return 0;
+  });
+}
+
+int sadmrg_get_s2(sadmrg_ctx* ctx, double* s2) {
+  return guard(ctx, [&] {
+    if (!s2) sadmrg::fail(SADMRG_EINVAL, "null output");
+    if (ctx->e.P.N < 0) sadmrg::fail(SADMRG_ESYMM, "no target");
+    const double S = 0.5 * ctx->e.P.twoS;
+    *s2 = S * (S + 1.0);
+    return 0;
+  });
+}
+
 int sadmrg_set_precision(sadmrg_ctx* ctx, int mode, double mixed_tol) {
   return guard(ctx, [&] {
     if (mode != 0 && mode != 1) sadmrg::fail(SADMRG_EINVAL, "precision mode must be 0 (FP64) or 1 (FP32 mixed)");
-    if (mode == 1 && !(mixed_tol > 0.0)) sadmrg::fail(SADMRG_EINVAL, "mixed_tol must be positive");
+    if (mode > 0 && !(mixed_tol > 0.0)) sadmrg::fail(SADMRG_EINVAL, "mixed_tol must be positive");
     ctx->e.prec = mode;
-    if (mode == 1) ctx->e.mixed_tol = mixed_tol;
+    if (mode > 0) ctx->e.mixed_tol = mixed_tol;
     return 0;
   });
 }

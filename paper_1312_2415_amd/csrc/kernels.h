@@ -34,7 +34,7 @@ void dev_event_free(void* e);
 
 // Flags of a block triple product  out += coef * opA(A) * B * opC(C)  (the
 // host evaluates it as two grouped GEMMs): transpose A / C, identity A / C.
-enum : int { TT_TRANS_A = 1, TT_TRANS_C = 2, TT_IDENT_A = 4, TT_IDENT_C = 8 };
+enum : int { TT_TRANS_A = 1, TT_TRANS_C = 2, TT_IDENT_A = 4, TT_IDENT_C = 8, TT_TRANS_B = 16 };
 
 // out[r*ld + c] += sum_{p < nparts} part[p*rows*cols + r*cols + c]  (fixed order)
 struct RTile {
@@ -132,6 +132,12 @@ void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int 
 // Number of compute units of the current device.
 int dev_cu_count();
 void launch_reduce(const RTile* reds, int nred, bool f32, Stream st);
+// out[j] = sum_{r < n_j} p_j[r * (ld_j + 1)]  (traces of square sub-blocks)
+struct TraceJob {
+  const double* p;
+  int n, ld;
+};
+void launch_traces(const TraceJob* jobs, int njobs, double* out, Stream st);
 // dst[i] = (float)src[i] / (double)src[i], i < n
 void launch_cvt_d2f(float* dst, const double* src, int64_t n, Stream st);
 void launch_cvt_f2d(double* dst, const float* src, int64_t n, Stream st);

@@ -662,6 +662,28 @@ void launch_reduce(const RTile* reds, int nred, bool f32, Stream st) {
 }
 
 // ---------------------------------------------------------------------------
+// Traces of square sub-blocks: one workgroup per job, fixed-order reduction.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void traces_kernel(const TraceJob* __restrict__ jobs, double* __restrict__ out) {
+  const TraceJob j = jobs[blockIdx.x];
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int r = threadIdx.x; r < j.n; r += 256) v += j.p[(int64_t)r * (j.ld + 1)];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+void launch_traces(const TraceJob* jobs, int njobs, double* out, Stream st) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(traces_kernel, dim3(njobs), dim3(256), 0, (hipStream_t)st, jobs, out);
+  check_launch("traces");
+}
+
+// ---------------------------------------------------------------------------
 // Precision conversions (FP64 <-> FP32 copies of operands and vectors).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void cvt_d2f_kernel(float* __restrict__ dst, const double* __restrict__ src, int64_t n) {

@@ -1,0 +1,130 @@
+"""GPU RDMs: spin-summed 1- and 2-RDMs from the energy adjoint.
+
+Pinned by brute-force FCI where the bond dimension is complete, by central
+finite differences of the energy with respect to integral orbits on a
+truncated MPS, by the energy identity E = E_c + h.gamma + 1/2 (ik|jl) Gamma_ijkl,
+and by the partial-trace relation between gamma and Gamma.
+"""
+import numpy as np
+import pytest
+
+from oracle import sadmrg as sd
+from oracle.fci import fci_solve, rdms, s2_from_gamma
+from synth.integrals import make_integrals
+
+pytestmark = pytest.mark.gpu
+
+ORDER = {"C1": 1, "C2": 2, "C2v": 4, "D2h": 8}
+
+
+def _gpu(L, group, I, h=None, eri=None):
+    from paper_1312_2415_amd import SaDMRG
+    g = SaDMRG(L, ORDER[group], I.orb_irrep, device=0)
+    g.set_integrals(I.h if h is None else h, I.eri if eri is None else eri)
+    return g
+
+
+def sym8(G):
+    """Gamma_{ij;kl} multiplies (ik|jl): average it over the eightfold images of (ik|jl)."""
+    D = np.einsum("ijkl->ikjl", G)
+    S = (D + D.transpose(1, 0, 2, 3) + D.transpose(0, 1, 3, 2) + D.transpose(1, 0, 3, 2) + D.transpose(2, 3, 0, 1)
+         + D.transpose(3, 2, 0, 1) + D.transpose(2, 3, 1, 0) + D.transpose(3, 2, 1, 0)) / 8.0
+    return np.einsum("pqrs->prqs", S)
+
+
+@pytest.mark.parametrize("case", [(6, 6, 0, "C1", 64), (8, 8, 0, "D2h", 128), (7, 5, 1, "C2v", 64),
+                                  (8, 6, 2, "D2h", 100), (6, 4, 2, "C1", 40)])
+def test_rdms_match_fci_at_complete_bond_dimension(case):
+    L, N, twoS, group, D = case
+    I = make_integrals(L, group, 11)
+    g = _gpu(L, group, I)
+    g.set_target(N, twoS, 0)
+    g.set_davidson(1e-10, 32, 300)
+    g.init_mps(D)
+    for s in range(4):
+        print(f"case {case} sweep {s}", flush=True)
+        g.sweep(D)
+    g1, g2, e = g.rdm()
+    vals, vecs, f = fci_solve(I.h, I.eri, N, twoS, 0, I.orb_irrep, I.e_const, nroots=1)
+    fg1, fg2 = rdms(f, vecs[:, 0])
+    assert abs(e - vals[0]) <= 1e-8
+    assert np.abs(g1 - fg1).max() <= 1e-8
+    assert np.abs(g2 - sym8(fg2)).max() <= 1e-8
+    assert abs(g.s2() - s2_from_gamma(fg2, N)) <= 1e-8
+    g.close()
+
+
+def test_rdm_energy_identity_and_traces_on_truncated_mps():
+    L, N, twoS, D = 12, 12, 0, 40
+    I = make_integrals(L, "D2h", 7)
+    g = _gpu(L, "D2h", I)
+    g.set_target(N, twoS, 0)
+    g.set_davidson(1e-9, 32, 200)
+    g.init_mps(D)
+    for _ in range(2):
+        e_sweep, _ = g.sweep(D)
+    g1, g2, e = g.rdm()
+    e_id = I.e_const + np.einsum("pq,pq", I.h, g1) + 0.5 * np.einsum("ikjl,ijkl", I.eri, g2)
+    assert abs(e_id - e) <= 1e-9 * max(1.0, abs(e))
+    assert abs(e - e_sweep) <= 1e-6  # the converged centre's energy
+    assert abs(np.trace(g1) - N) <= 1e-9
+    assert np.abs(g1 - g1.T).max() <= 1e-10
+    # partial trace: gamma_il = sum_k Gamma_{ik;lk} / (N - 1)
+    assert np.abs(np.einsum("iklk->il", g2) / (N - 1) - g1).max() <= 1e-9
+    assert abs(np.einsum("ijij->", g2) - N * (N - 1)) <= 1e-8
+    g.close()
+
+
+def test_rdm_is_the_integral_derivative_of_the_energy():
+    """Central differences of E (same MPS, perturbed integral orbits)."""
+    L, N, twoS, D = 8, 6, 0, 12  # truncated: D below the FCI bond dimension
+    I = make_integrals(L, "C1", 5)
+    g = _gpu(L, "C1", I)
+    g.set_target(N, twoS, 0)
+    g.set_davidson(1e-9, 32, 200)
+    g.init_mps(D)
+    g.sweep(D)
+    blob = g.mps_export()
+    g1, g2, e0 = g.rdm()
+    g.close()
+    rng = np.random.default_rng(2)
+    eps = 1e-5
+
+    def energy(h, eri):
+        q = _gpu(L, "C1", I, h, eri)
+        q.set_target(N, twoS, 0)
+        q.mps_import(blob)
+        _, _, e = q.rdm(two_body=False)
+        q.close()
+        return e
+
+    for _ in range(6):  # two-electron orbits
+        p, q, r, s = rng.integers(0, L, 4)
+        dE = np.zeros_like(I.eri)
+        for a, b, c, d in {(p, q, r, s), (q, p, r, s), (p, q, s, r), (q, p, s, r), (r, s, p, q), (s, r, p, q),
+                           (r, s, q, p), (s, r, q, p)}:
+            dE[a, b, c, d] = 1.0
+        fd = (energy(I.h, I.eri + eps * dE) - energy(I.h, I.eri - eps * dE)) / (2 * eps)
+        an = 0.5 * np.einsum("ikjl,ijkl", dE, g2)
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+    for _ in range(3):  # one-electron orbits
+        p, q = rng.integers(0, L, 2)
+        dh = np.zeros_like(I.h)
+        dh[p, q] = dh[q, p] = 1.0
+        fd = (energy(I.h + eps * dh, I.eri) - energy(I.h - eps * dh, I.eri)) / (2 * eps)
+        assert abs(fd - np.einsum("pq,pq", dh, g1)) <= 1e-6
+
+
+def test_rdm_needs_a_two_site_centre():
+    from paper_1312_2415_amd.binding import SadmrgError
+    I = make_integrals(6, "C1", 3)
+    g = _gpu(6, "C1", I)
+    g.set_target(6, 0, 0)
+    with pytest.raises(SadmrgError):
+        g.rdm()
+    g.init_mps(8)
+    with pytest.raises(SadmrgError):  # the initial MPS has no optimised two-site centre
+        g.rdm()
+    g.sweep(8)
+    g.rdm(two_body=False)
+    g.close()
