@@ -121,8 +121,14 @@ int sadmrg_sweep(sadmrg_ctx* ctx, int D, double* e_min);
 
 /* Run a convergence scheme (section "Convergence scheme"): n instructions of
  * (D[i], e_conv[i], max_sweeps[i], noise[i]).  *e_min receives the lowest
- * variational energy over all micro-iterations (the paper's Solve).
- * Noise must be 0 in this version (EINVAL otherwise). */
+ * variational energy over all micro-iterations (the paper's Solve).  With
+ * noise[i] = gamma > 0, every decomposition adds gamma/2 * w * u_e to the
+ * two-site object, w the largest discarded weight of the previous left- or
+ * right-pass and u_e uniform in [-1, 1) from the counter generator keyed by
+ * (seed, 0x4E4F << 40 | pass << 16 | step, element), passes counted from the
+ * MPS's creation or import; the object's sign is first chosen so that its
+ * inner product with u is non-negative.  noise may be NULL (no noise); negative noise is
+ * EINVAL. */
 int sadmrg_solve(sadmrg_ctx* ctx, int n, const int* D, const double* e_conv, const int* max_sweeps,
                  const double* noise, double* e_min);
 

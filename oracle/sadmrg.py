@@ -953,6 +953,11 @@ class DMRG:
         self.center = None  # (i, psi dict) for the two-site object on sites i,i+1
         self.emin = math.inf
         self.stats = SweepStats()
+        # noise (section "Convergence scheme"): bounded by 0.5 gamma w_disc of
+        # the previous left- or right-sweep; passes counted from here
+        self.n_pass = 0
+        self.wd_prev = 0.0
+        self.wd_pass = 0.0
         self._init_mps()
 
     # ----- initial state: random right-canonical tensors (paper: random noise)
@@ -1021,7 +1026,7 @@ class DMRG:
         Ye = enlarge_right(P, Rk, Er)
         return El, Er, Xe, Ye, sorted(keep)
 
-    def micro(self, i, D, direction, do_svd=True):
+    def micro(self, i, D, direction, do_svd=True, noise=0.0):
         P = self.P
         El, Er, Xe, Ye, secs = self.enlarged(i)
         H = Heff(P, Xe, Ye, secs)
@@ -1038,12 +1043,22 @@ class DMRG:
         self.emin = min(self.emin, e)
         self.stats.energies.append(e)
         self.stats.dav_iters.append(its)
-        psi = unflatten(x, shapes, secs)
         if not do_svd:
-            self.center = (i, psi)
+            self.center = (i, unflatten(x, shapes, secs))
             return e
+        if noise > 0.0 and self.wd_prev > 0.0:
+            # uniform noise of magnitude <= 0.5 gamma w_disc(previous pass),
+            # added just before the decomposition (section "Convergence scheme");
+            # the eigenvector's arbitrary sign is fixed first (<x, u> >= 0) so
+            # that the noisy object does not depend on it
+            u = noise_values(self.seed, self.n_pass, i, len(x))
+            if x @ u < 0:
+                x = -x
+            x = x + 0.5 * noise * self.wd_prev * u
+        psi = unflatten(x, shapes, secs)
         U, s, Vt, kept, wd = svd_truncate(psi, D)
         self.stats.wdisc.append(wd)
+        self.wd_pass = max(self.wd_pass, wd)
         c = i + 1
         if direction == "right":
             self.U[i] = U
@@ -1059,7 +1074,7 @@ class DMRG:
             self.center = (i - 1, move_center_left(P, C, self.U[i - 1], c, kept, self.dims[c - 1]))
         return e
 
-    def sweep(self, D):
+    def sweep(self, D, noise=0.0):
         """One macro-iteration: right pass i = 0..L-2, left pass i = L-2..0.
 
         The turning steps are not split: at i = L-2 of the right pass and at
@@ -1069,19 +1084,27 @@ class DMRG:
         L = self.P.L
         e0 = len(self.stats.energies)
         for i in range(0, L - 1):
-            self.micro(i, D, "right", do_svd=(i < L - 2))
+            self.micro(i, D, "right", do_svd=(i < L - 2), noise=noise)
+        self._end_pass()
         for i in range(L - 2, -1, -1):
-            self.micro(i, D, "left", do_svd=(i > 0))
+            self.micro(i, D, "left", do_svd=(i > 0), noise=noise)
+        self._end_pass()
         return min(self.stats.energies[e0:])
 
+    def _end_pass(self):
+        self.wd_prev, self.wd_pass = self.wd_pass, 0.0
+        self.n_pass += 1
+
     def solve(self, schedule):
-        """schedule: list of (D, e_conv, max_sweeps)."""
+        """schedule: list of (D, e_conv, max_sweeps[, noise])."""
         if self.Rblk[2] is None:
             self.build_boundaries()
         e_prev = math.inf
-        for D, e_conv, nmax in schedule:
+        for ins in schedule:
+            D, e_conv, nmax = ins[:3]
+            noise = ins[3] if len(ins) > 3 else 0.0
             for _ in range(nmax):
-                e = self.sweep(D)
+                e = self.sweep(D, noise)
                 if abs(e - e_prev) < e_conv:
                     e_prev = e
                     break
@@ -1091,6 +1114,15 @@ class DMRG:
     # two-site wavefunction as (sectors, shapes, flat vector) at the current centre
     def current_psi(self):
         return self.center
+
+
+NOISE_STREAM = 0x4E4F << 40
+
+
+def noise_values(seed, n_pass, i, n):
+    """The noise draws of step i of pass n_pass: uniform in [-1, 1), counter-based."""
+    from synth.integrals import uniform_pm1_array
+    return uniform_pm1_array(seed, NOISE_STREAM | (n_pass << 16) | i, n)
 
 
 def _mps_random(seed, site, sector_index, n):
@@ -1108,6 +1140,12 @@ def svd_truncate(psi: dict, D: int):
     cand = []
     for qi, m in enumerate(sorted(psi)):
         u, s, vt = np.linalg.svd(psi[m], full_matrices=False)
+        # sign convention: the largest-magnitude entry of each left singular
+        # vector (lowest row among ties) is positive; the right vector follows
+        for a in range(u.shape[1]):
+            if u[np.argmax(np.abs(u[:, a])), a] < 0:
+                u[:, a] = -u[:, a]
+                vt[a, :] = -vt[a, :]
         Us[m], Ss[m], Vs[m] = u, s, vt
         for a, sv in enumerate(s):
             cand.append((-sv / math.sqrt(m[1] + 1), qi, a, m))

@@ -1384,6 +1384,9 @@ struct Step {
   std::vector<std::array<int, 5>> shapes;  // per tile task: rows, K1, K2, cols, flags
 };
 
+// stream of the noise draws of step i in pass p: NOISE_STREAM | p << 16 | i
+static const uint64_t NOISE_STREAM = (uint64_t)0x4E4F << 40;
+
 struct Engine {
   Problem P;
   Stream st = nullptr;
@@ -1408,6 +1411,11 @@ struct Engine {
   int64_t n_pass1 = 0, n_pass2 = 0;
   double t_sigma32 = 0, f_sigma32 = 0;
   int64_t n_sigma32 = 0;
+  // noise (section "Convergence scheme"): uniform, magnitude <= 0.5 gamma
+  // w_disc of the previous left- or right-sweep, added before each decomposition
+  double noise = 0.0;
+  double wd_prev = 0.0, wd_pass = 0.0;
+  int64_t n_pass = 0;  // passes since the MPS was created or imported
   int prec = 0;             // 0: FP64 sigma; 1: FP32 sigma in Davidson + FP64 Rayleigh quotient
   double mixed_tol = 1e-5;  // Davidson tolerance of the FP32 phase
   int64_t n_sigma = 0;
@@ -2003,6 +2011,8 @@ struct Engine {
     }
     build_blocks_from_tensors(0);
     mps_ready = true;
+    n_pass = 0;
+    wd_prev = wd_pass = 0.0;
   }
 
   // Build left blocks 0..i and right blocks L..i+2 from the stored tensors.
@@ -2699,6 +2709,7 @@ struct Engine {
     DArr<SvdJob> dj;
     dj.put(jobs, st);
     launch_svd(dj.p, (int)jobs.size(), maxs, st);
+    launch_svd_signs(dj.p, (int)jobs.size(), st);
     std::vector<double> s(nsv);
     dev_d2h(s.data(), sp.sbuf.p, (size_t)nsv * 8, st);
     struct Cand {
@@ -2816,9 +2827,25 @@ struct Engine {
       t_micro += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       return e;
     }
+    if (noise > 0.0 && wd_prev > 0.0) {
+      // the eigenvector's arbitrary sign is fixed first (<x, u> >= 0) so that
+      // the noisy object does not depend on it
+      DBuf u;
+      u.alloc((size_t)std::max<int64_t>(step.n, 1));
+      launch_fill_uniform(u.p, step.n, seed, NOISE_STREAM | ((uint64_t)n_pass << 16) | (uint64_t)i, st);
+      dsmall.ensure(8 * 64 + 64 * 64);
+      dpartial.ensure(256 * 64);
+      launch_dots(x.p, step.n, 1, u.p, step.n, dsmall.p, dpartial.p, st);
+      double xu;
+      dev_d2h(&xu, dsmall.p, 8, st);
+      if (xu < 0.0) launch_axpy(x.p, x.p, -2.0, step.n, st);
+      launch_axpy(x.p, u.p, 0.5 * noise * wd_prev, step.n, st);
+      dev_sync(st);
+    }
     Split sp;
     svd_truncate(x.p, D, sp);
     wdisc_sweep = std::max(wdisc_sweep, sp.wd);
+    wd_pass = std::max(wd_pass, sp.wd);
     const int c = i + 1;
     const int nk = (int)sp.kept.sec.size();
     if (right) {
@@ -2909,6 +2936,12 @@ struct Engine {
     return e;
   }
 
+  void end_pass() {
+    wd_prev = wd_pass;
+    wd_pass = 0.0;
+    ++n_pass;
+  }
+
   double sweep(int D) {
     if (!mps_ready) fail(-1, "call sadmrg_init_mps or sadmrg_mps_import first");
     const int L = P.L;
@@ -2918,7 +2951,9 @@ struct Engine {
     if (!((cen.kind == C_T0 && cen.pos == 0) || (cen.kind == C_TWO && cen.pos == 0)))
       fail(-1, "internal: sweep must start with the centre at the left end");
     for (int i = 0; i <= L - 2; ++i) e = std::min(e, micro(i, D, true, i < L - 2));
+    end_pass();
     for (int i = L - 2; i >= 0; --i) e = std::min(e, micro(i, D, false, i > 0));
+    end_pass();
     wdisc = wdisc_sweep;
     return e;
   }
@@ -3028,6 +3063,8 @@ static void import_mps(Engine& E, const void* blob, size_t bytes) {
   if (r.o != r.n) fail(-1, "MPS blob: trailing bytes");
   E.build_blocks_from_tensors((int)ci);
   E.mps_ready = true;
+  E.n_pass = 0;
+  E.wd_prev = E.wd_pass = 0.0;
 }
 
 static void export_mps(Engine& E, std::vector<char>& out) {
@@ -3258,19 +3295,25 @@ int sadmrg_solve(sadmrg_ctx* ctx, int n, const int* D, const double* e_conv, con
     if (n < 1 || !D || !e_conv || !max_sweeps) sadmrg::fail(SADMRG_EINVAL, "bad schedule");
     for (int i = 0; i < n; ++i) {
       if (D[i] < 1 || max_sweeps[i] < 1 || !(e_conv[i] >= 0)) sadmrg::fail(SADMRG_EINVAL, "bad schedule entry");
-      if (noise && noise[i] != 0.0) sadmrg::fail(SADMRG_EINVAL, "noise is not supported in this version");
+      if (noise && !(noise[i] >= 0.0)) sadmrg::fail(SADMRG_EINVAL, "noise must be non-negative");
     }
     auto& E = ctx->e;
     if (!E.mps_ready) E.init_mps(D[0]);
     E.warned = false;
     double prev = INFINITY;
-    for (int i = 0; i < n; ++i)
+    struct NoiseReset {  // the noise applies to this schedule only
+      sadmrg::Engine& e;
+      ~NoiseReset() { e.noise = 0.0; }
+    } reset{E};
+    for (int i = 0; i < n; ++i) {
+      E.noise = noise ? noise[i] : 0.0;
       for (int s = 0; s < max_sweeps[i]; ++s) {
         const double e = E.sweep(D[i]);
         const bool done = std::abs(e - prev) < e_conv[i];
         prev = e;
         if (done) break;
       }
+    }
     if (e_min) *e_min = E.emin;
     return E.warned ? SADMRG_WARN_NOT_CONVERGED : 0;
   });

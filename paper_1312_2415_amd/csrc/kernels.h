@@ -145,6 +145,10 @@ void launch_gather(const GatherDst* dsts, int ndst, const GatherSrc* srcs, Strea
 void launch_combo(const ComboOut* outs, int nout, const ComboIn* ins, int64_t max_nnz, Stream st);
 void launch_diag(const DiagSec* secs, int nsec, const DiagTask* tasks, Stream st);
 void launch_svd(const SvdJob* jobs, int njobs, int max_short, Stream st);
+// Sign convention of singular vectors: for every column a of U (rows x r,
+// leading dimension r) the entry of largest magnitude (lowest row among ties)
+// is made positive; row a of Vt (r x cols, leading dimension cols) follows.
+void launch_svd_signs(const SvdJob* jobs, int njobs, Stream st);
 
 // Davidson helpers (device pointers; k <= 64)
 // out[j] = dot(V + j*ldv, x) for j < k; deterministic two-stage reduction (partial: 256*k doubles)
@@ -164,6 +168,8 @@ void launch_normalize(double* y, const double* nrm2, int64_t n, Stream st);
 void launch_syev_small(const double* H, int k, int ld, double* evals, double* evecs, Stream st);
 // uniform [-1,1) numbers from the SplitMix64 counter generator
 void launch_fill_uniform(double* p, int64_t n, uint64_t seed, uint64_t stream, Stream st);
+// y[i] += a * x[i], i < n
+void launch_axpy(double* y, const double* x, double a, int64_t n, Stream st);
 // Plain streaming copy dst[i] = src[i] (reference kernel for HBM byte counters).
 void launch_copy(double* dst, const double* src, int64_t n, Stream st);
 // a[r][c] *= s[r]  /  a[r][c] *= s[c]

@@ -968,6 +968,51 @@ void launch_svd(const SvdJob* jobs, int njobs, int max_short, Stream st) {
   check_launch("svd");
 }
 
+__global__ __launch_bounds__(256) void svd_signs_kernel(const SvdJob* __restrict__ jobs) {
+  const SvdJob j = jobs[blockIdx.x];
+  const int r = min(j.rows, j.cols);
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  for (int a = 0; a < r; ++a) {
+    double best = -1.0;
+    int idx = 0x7fffffff;
+    for (int row = threadIdx.x; row < j.rows; row += 256) {
+      const double v = fabs(j.u[(int64_t)row * r + a]);
+      if (v > best) {  // rows visited in increasing order: ties keep the lowest
+        best = v;
+        idx = row;
+      }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = idx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        const double ov = bv[threadIdx.x + w];
+        const int oi = bi[threadIdx.x + w];
+        if (ov > bv[threadIdx.x] || (ov == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+          bv[threadIdx.x] = ov;
+          bi[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const bool flip = bi[0] < j.rows && j.u[(int64_t)bi[0] * r + a] < 0.0;
+    __syncthreads();
+    if (flip) {
+      for (int row = threadIdx.x; row < j.rows; row += 256) j.u[(int64_t)row * r + a] = -j.u[(int64_t)row * r + a];
+      for (int c = threadIdx.x; c < j.cols; c += 256) j.vt[(int64_t)a * j.cols + c] = -j.vt[(int64_t)a * j.cols + c];
+    }
+    __syncthreads();
+  }
+}
+
+void launch_svd_signs(const SvdJob* jobs, int njobs, Stream st) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(svd_signs_kernel, dim3(njobs), dim3(256), 0, (hipStream_t)st, jobs);
+  check_launch("svd_signs");
+}
+
 // ---------------------------------------------------------------------------
 // Davidson vector kernels
 // ---------------------------------------------------------------------------
@@ -1178,6 +1223,17 @@ void launch_fill_uniform(double* p, int64_t n, uint64_t seed, uint64_t stream, S
   if (n <= 0) return;
   int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
   hipLaunchKernelGGL(fill_uniform_kernel, dim3(nb), dim3(256), 0, (hipStream_t)st, p, n, seed, stream);
+}
+
+__global__ void axpy_kernel(double* y, const double* x, double a, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+void launch_axpy(double* y, const double* x, double a, int64_t n, Stream st) {
+  if (n <= 0) return;
+  const int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, (hipStream_t)st, y, x, a, n);
+  check_launch("axpy");
 }
 
 __global__ void scale_rows_kernel(double* a, int rows, int cols, int ld, const double* s) {

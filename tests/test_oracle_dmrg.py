@@ -240,3 +240,26 @@ def test_dmrg_variational_and_monotone_in_D():
     assert all(e >= efci - 1e-10 for e in es)
     assert es[0] >= es[1] - 1e-9 >= es[2] - 2e-9
     assert es[0] > efci + 1e-6
+
+
+def test_noise_enters_after_the_first_pass_and_is_bounded():
+    """Noise is 0.5 gamma w_disc(previous pass) times uniform draws: the first
+    pass (no previous pass) equals the noiseless run; later passes differ but
+    stay variational above FCI."""
+    L, N, D = 8, 8, 12
+    I = make_integrals(L, "C1", 1001)
+    P = sd.Problem(I.h, I.eri, N, 0, 0, I.orb_irrep)
+    e_fci = fci_solve(I.h, I.eri, N, 0)[0][0]
+    runs = []
+    for gamma in (0.0, 0.5):
+        dm = sd.DMRG(P, D, seed=3)
+        dm.build_boundaries()
+        dm.sweep(D, noise=gamma)
+        dm.sweep(D, noise=gamma)
+        runs.append(np.array(dm.stats.energies))
+    n1 = L - 1  # micro-iterations of the first (right) pass
+    assert np.allclose(runs[0][:n1], runs[1][:n1], atol=0, rtol=0)
+    assert np.abs(runs[0][n1:] - runs[1][n1:]).max() > 0
+    assert runs[1].min() >= e_fci - 1e-10
+    u = sd.noise_values(3, 1, 2, 1000)
+    assert u.min() >= -1.0 and u.max() < 1.0 and abs(u.mean()) < 0.1
