@@ -119,6 +119,30 @@ int sadmrg_init_mps(sadmrg_ctx* ctx, int D);
  * macro-iteration.  Returns 1 if some Davidson solve hit max_iter. */
 int sadmrg_sweep(sadmrg_ctx* ctx, int D, double* e_min);
 
+/* One macro-iteration (as sadmrg_sweep) of each of n independent problems,
+ * run in lockstep: micro-iteration r of every context still sweeping, then
+ * r + 1.  The paper treats each state of its carbon-dimer study as its own
+ * calculation in its own symmetry sector (section "Bond dissociation
+ * curves") and parallelises within a calculation over the sparse blocks
+ * (section "DMRG" of the library description); here the sigma products of
+ * all contexts in one Davidson iteration go out as one launch per GEMM pass,
+ * the accumulating pass balanced over the whole batch.
+ *   ctxs[n]: distinct contexts with an MPS, every centre at the left end
+ *            (as after sadmrg_init_mps, sadmrg_mps_import or a sweep), all on
+ *            one device and one stream (sadmrg_set_stream) and in one
+ *            precision mode.  Sizes, sectors and schedules may differ.
+ *   D[n]:    bond dimension of each context (host array).
+ *   e_min[n] (may be NULL): lowest energy of each context's macro-iteration.
+ *   stats[6] (may be NULL): seconds, algorithmic flops and number of the
+ *            shared FP64 sigma launches, then the same for FP32 (zero for a
+ *            batch of one, which runs as sadmrg_sweep).
+ * Each context's result equals its own sadmrg_sweep up to the summation
+ * order of the shared launches.  Returns 1 if some Davidson solve hit
+ * max_iter; on an error every context gets the message, and the contexts
+ * are left mid-sweep (re-import or re-initialise them).  Errors: EINVAL,
+ * ENOMEM, EDEVICE. */
+int sadmrg_batch_sweep(sadmrg_ctx* const* ctxs, int n, const int* D, double* e_min, double* stats);
+
 /* Run a convergence scheme (section "Convergence scheme"): n instructions of
  * (D[i], e_conv[i], max_sweeps[i], noise[i]).  *e_min receives the lowest
  * variational energy over all micro-iterations (the paper's Solve).  With

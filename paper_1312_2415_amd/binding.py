@@ -45,6 +45,7 @@ def load_library(path: str | None = None):
         "sadmrg_set_seed": (c_int, [c_vp, ctypes.c_uint64]),
         "sadmrg_init_mps": (c_int, [c_vp, c_int]),
         "sadmrg_sweep": (c_int, [c_vp, c_int, P(c_dbl)]),
+        "sadmrg_batch_sweep": (c_int, [P(c_vp), c_int, P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_solve": (c_int, [c_vp, c_int, P(c_int), P(c_dbl), P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_get_energy": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
         "sadmrg_get_trace": (c_int, [c_vp, P(c_dbl), P(c_int)]),
@@ -278,6 +279,35 @@ class SaDMRG:
 
     def stats_reset(self):
         self._chk(self.lib.sadmrg_stats_reset(self.h))
+
+
+def batch_sweep(solvers, D):
+    """One lockstep macro-iteration of several solvers (sadmrg_batch_sweep).
+
+    solvers: SaDMRG objects sharing one library, device, stream and precision;
+    D: one bond dimension per solver (or a single int for all).
+    Returns (e_min list, stats dict, rc)."""
+    solvers = list(solvers)
+    n = len(solvers)
+    if n == 0:
+        raise ValueError("empty batch")
+    lib = solvers[0].lib
+    if any(s.lib is not lib for s in solvers):
+        raise ValueError("solvers of different libraries")
+    Ds = [int(D)] * n if np.isscalar(D) else [int(d) for d in D]
+    if len(Ds) != n:
+        raise ValueError("one D per solver")
+    hs = (ctypes.c_void_p * n)(*[s.h for s in solvers])
+    dd = (ctypes.c_int * n)(*Ds)
+    em = (ctypes.c_double * n)()
+    st = (ctypes.c_double * 6)()
+    rc = lib.sadmrg_batch_sweep(hs, n, dd, em, st)
+    if rc < 0:
+        msg = lib.sadmrg_last_error(solvers[0].h)
+        raise SadmrgError(rc, msg.decode() if msg else "")
+    stats = {"t_sigma": st[0], "flops_sigma": st[1], "n_sigma": int(st[2]),
+             "t_sigma32": st[3], "flops_sigma32": st[4], "n_sigma32": int(st[5])}
+    return list(em), stats, rc
 
 
 def debug_coupling(which: int, args, lib_path: str | None = None) -> float:

@@ -1144,13 +1144,37 @@ struct GemmList {
   }
   static constexpr int GK_HOST = 32;
   static constexpr double TILE_COST = 1500.0;
+  // smallest estimated cost worth a workgroup of its own (about ten products):
+  // below it a small problem would be cut into slivers that each pay the
+  // workgroup start and a partial tile
+  static constexpr double MIN_WG_COST = 30000.0;
+  static int cus() {
+    static int n = 0;
+    if (n <= 0) n = std::max(1, dev_cu_count());
+    return n;
+  }
+  // estimated cost of all tiles (the quantity the ranges of plan() divide)
+  double total_cost() const {
+    std::vector<int> cnt(tiles.size(), 0);
+    std::vector<double> tc(tiles.size(), 0.0);
+    for (auto& t : items) {
+      cnt[t.tile]++;
+      tc[t.tile] += task_cost(t.t.K, tiles[t.tile].cols);
+    }
+    double total = 0.0;
+    for (size_t i = 0; i < tiles.size(); ++i)
+      if (cnt[i] > 0 || tiles[i].mode != 0) total += TILE_COST + tc[i];
+    return total;
+  }
 
   // Assign the tiles, in order, to contiguous per-workgroup ranges of about
-  // equal estimated cost, `gpc` workgroups per CU; gpc = 0 gives every tile
-  // its own workgroup (the hardware then balances the load).  An
+  // equal estimated cost, at most `gpc` workgroups per CU; gpc = 0 gives
+  // every tile its own workgroup (the hardware then balances the load).  The
+  // cost of a range is total / (gpc * CUs), or `target` when given (a batch
+  // of problems sharing the launch), and never below MIN_WG_COST.  An
   // accumulating tile (mode 0) may be cut between two workgroups: its pieces
   // write partial tiles that a second kernel adds in a fixed order.
-  void plan(Plan& pl, Stream st, int gpc) {
+  void plan(Plan& pl, Stream st, int gpc, double target_cost = 0.0) {
     std::vector<int> cnt(tiles.size() + 1, 0);
     for (auto& t : items) cnt[t.tile + 1]++;
     for (size_t i = 0; i < tiles.size(); ++i) cnt[i + 1] += cnt[i];
@@ -1164,10 +1188,8 @@ struct GemmList {
       total += TILE_COST;
       for (int t = cnt[i]; t < cnt[i + 1]; ++t) total += (cost[t] = task_cost(flat[t].K, tiles[i].cols));
     }
-    static int cus = 0;
-    if (cus <= 0) cus = std::max(1, dev_cu_count());
-    const int G = gpc > 0 ? gpc * cus : INT32_MAX;
-    const double target = gpc > 0 ? total / G : 0.0;
+    const int G = gpc > 0 ? gpc * cus() : INT32_MAX;
+    const double target = gpc > 0 ? std::max(target_cost > 0.0 ? target_cost : total / G, MIN_WG_COST) : 0.0;
 
     std::vector<GTile> chunks;
     std::vector<int> owner;  // source tile of every chunk
@@ -1286,8 +1308,10 @@ struct TwoPass {
   }
 };
 
+// keep2: hand the accumulating pass's product list to the caller instead of
+// planning it (a batch plans it with the cost target of the whole batch).
 static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Triple>& tr, TwoPass& tp, Stream st,
-                           bool sigma = false) {
+                           bool sigma = false, GemmList* keep2 = nullptr) {
   std::vector<int64_t> slot(tr.size(), -1);
   int64_t ws = 0;
   for (size_t i = 0; i < tr.size(); ++i)
@@ -1336,7 +1360,10 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
   tp.nprod = (int64_t)tr.size();
   const int tag1 = tp.p1.tag, tag2 = tp.p2.tag;
   g1.plan(tp.p1, st, GEMM_GPC_PASS1);
-  g2.plan(tp.p2, st, GEMM_GPC_PASS2);
+  if (keep2)
+    *keep2 = std::move(g2);
+  else
+    g2.plan(tp.p2, st, GEMM_GPC_PASS2);
   tp.p1.tag = tag1;
   tp.p2.tag = tag2;
 }
@@ -1379,6 +1406,10 @@ struct Step {
   bool f32_ready = false;
   DBuf x32, y32, in32, out32, ws32, p1part32, p2part32;
   GemmList::Plan q1, q2;
+  // the accumulating pass's products while its plan waits for the batch's
+  // cost target
+  GemmList g2;
+  bool p2_pending = false;
   double flops = 0.0, bytes = 0.0;
   int64_t ntasks = 0;
   std::vector<std::array<int, 5>> shapes;  // per tile task: rows, K1, K2, cols, flags
@@ -1386,6 +1417,32 @@ struct Step {
 
 // stream of the noise draws of step i in pass p: NOISE_STREAM | p << 16 | i
 static const uint64_t NOISE_STREAM = (uint64_t)0x4E4F << 40;
+
+// binds a device-memory pool to the calling thread for one scope
+struct PoolBind {
+  DevPool* prev;
+  explicit PoolBind(DevPool* p) : prev(p ? dev_pool_bind(p) : nullptr), set(p != nullptr) {}
+  ~PoolBind() {
+    if (set) dev_pool_bind(prev);
+  }
+  bool set;
+};
+
+// State of one Davidson solve (Davidson 1975; section "The effective
+// Hamiltonian equation"), advanced phase by phase so that the solves of
+// several engines on one stream can run in lockstep.
+struct DavState {
+  double* xres = nullptr;  // normalised Ritz vector on exit
+  double tol = 0.0;        // residual-norm tolerance
+  bool f32 = false;        // sigma with FP32 operands
+  int ms = 2, k = 0, it = 1;
+  double theta = 0.0, rbest = INFINITY;
+  int stall = 0;
+  bool conv = false, done = false;
+};
+struct Engine;
+struct BatchLaunch;
+static void davidson_lockstep(const std::vector<Engine*>& E, std::vector<DavState>& D, BatchLaunch* bl);
 
 struct Engine {
   Problem P;
@@ -1421,6 +1478,14 @@ struct Engine {
   int64_t n_sigma = 0;
   // Davidson work buffers
   DBuf dV, dW, dHs, dsmall, dpartial, dx_, dax, dr, dt;
+  double* hpin = nullptr;   // page-locked scalars read back after a stream sync
+  DevPool* pool = nullptr;  // the context's device-memory pool
+  bool defer_p2 = false;    // prepare() leaves the accumulating pass unplanned
+
+  Engine() = default;
+  Engine(const Engine&) = delete;
+  Engine& operator=(const Engine&) = delete;
+  ~Engine() { host_free_pinned(hpin); }
 
   void check_target() const {
     if (P.N < 0) fail(-1, "target not set");
@@ -2239,7 +2304,8 @@ struct Engine {
     }
     for (auto& [s, o] : touched) bytes += 8.0 * (s == 0 ? X.lay(o).nnz : Y.lay(o).nnz);
     bytes += 16.0 * step.n;
-    build_two_pass(outs, trs, step.plan, st, true);
+    build_two_pass(outs, trs, step.plan, st, true, defer_p2 ? &step.g2 : nullptr);
+    step.p2_pending = defer_p2;
     step.trs = trs;
     step.flops = step.plan.flops;
     step.bytes = bytes;
@@ -2495,6 +2561,7 @@ struct Engine {
   // ---- sigma on the prepared step: step.out = H_eff step.in (FP64, or with
   // FP32 operands and FP32 accumulation when f32)
   void sigma_fixed(bool f32 = false) {
+    if (step.p2_pending) fail(-1, "internal: sigma plan incomplete");
     if (f32) ensure_f32();
     const GemmList::Plan& p1 = f32 ? step.q1 : step.plan.p1;
     const GemmList::Plan& p2 = f32 ? step.q2 : step.plan.p2;
@@ -2540,127 +2607,194 @@ struct Engine {
     sigma_fixed(f32);
     dev_d2d(y, step.out.p, (size_t)step.n * 8, st);
   }
+  // the parts of sigma_vec around the two GEMM passes, for a launch shared
+  // with other engines (same operations in the same order)
+  void sigma_in(const double* x, bool f32) {
+    if (step.p2_pending) fail(-1, "internal: sigma plan incomplete");
+    if (f32) ensure_f32();
+    dev_d2d(step.in.p, x, (size_t)step.n * 8, st);
+    if (f32) {
+      launch_cvt_d2f((float*)step.in32.p, step.in.p, step.n, st);
+      dev_zero(step.out32.p, step.out32.n * 8, st);
+    } else {
+      dev_zero(step.out.p, (size_t)std::max<int64_t>(step.n, 1) * 8, st);
+    }
+  }
+  void sigma_out(double* y, bool f32) {
+    if (f32) launch_cvt_f2d(step.out.p, (const float*)step.out32.p, step.n, st);
+    dev_d2d(y, step.out.p, (size_t)step.n * 8, st);
+  }
+  // plan the accumulating pass left open by prepare() (target: cost per
+  // workgroup range; 0 = this problem alone)
+  void plan_pass2(double target) {
+    if (!step.p2_pending) return;
+    const int tag = step.plan.p2.tag;
+    step.g2.plan(step.plan.p2, st, GEMM_GPC_PASS2, target);
+    step.plan.p2.tag = tag;
+    step.g2 = GemmList();
+    step.p2_pending = false;
+  }
 
   // ---- Davidson (Davidson 1975; section "The effective Hamiltonian equation")
   // tol: residual-norm tolerance; f32: sigma with FP32 operands.
   double davidson(double* xres, int* iters, bool* conv, double tol, bool f32) {
+    std::vector<Engine*> E{this};
+    std::vector<DavState> D(1);
+    D[0].xres = xres;
+    D[0].tol = tol;
+    D[0].f32 = f32;
+    davidson_lockstep(E, D, nullptr);
+    *iters = D[0].it;
+    *conv = D[0].conv;
+    return D[0].theta;
+  }
+
+  // The phases of one solve.  Each only enqueues work on the stream; the
+  // scalars the host decides on arrive in hpin after the stream sync that
+  // follows dav_start, dav_iter_a and dav_iter_b.  Small-matrix layout in
+  // dsmall: eigenvalues, eigenvectors (64 x 64), coefficients, norms.
+  double* dav_evals() { return dsmall.p; }
+  double* dav_evecs() { return dsmall.p + 64; }
+  double* dav_coef() { return dsmall.p + 64 + 64 * 64; }
+  double* dav_nrm() { return dav_coef() + 64; }
+  double* dav_nrm2() { return dav_coef() + 65; }
+
+  // |guess|^2 of the guess in step.in
+  void dav_start(DavState& d) {
     const int64_t n = step.n;
-    const int ms = std::max(2, std::min(dav_max_sub, 64));
-    dV.ensure((size_t)ms * n);
-    dW.ensure((size_t)ms * n);
-    dHs.ensure((size_t)ms * ms);
+    d.ms = std::max(2, std::min(dav_max_sub, 64));
+    d.k = 0;
+    d.it = 1;
+    d.theta = 0.0;
+    d.rbest = INFINITY;
+    d.stall = 0;
+    d.conv = d.done = false;
+    dV.ensure((size_t)d.ms * n);
+    dW.ensure((size_t)d.ms * n);
+    dHs.ensure((size_t)d.ms * d.ms);
     dsmall.ensure(8 * 64 + 64 * 64);
     dpartial.ensure(256 * 64);
     dx_.ensure(n);
     dax.ensure(n);
     dr.ensure(n);
     dt.ensure(n);
-    double* evals = dsmall.p;
-    double* evecs = dsmall.p + 64;
-    double* coef = dsmall.p + 64 + 64 * 64;
-    double* nrm = coef + 64;
-    double* nrm2 = nrm + 1;
-    // V0 = guess / |guess|
+    if (!hpin) hpin = (double*)host_alloc_pinned(8 * sizeof(double));
     dev_d2d(dV.p, step.in.p, (size_t)n * 8, st);
-    launch_dots(dV.p, n, 1, dV.p, n, nrm, dpartial.p, st);
-    double h0;
-    dev_d2h(&h0, nrm, 8, st);
-    if (!(h0 > 0)) {  // zero guess: use a constant vector
+    launch_dots(dV.p, n, 1, dV.p, n, dav_nrm(), dpartial.p, st);
+    dev_d2h_async(hpin, dav_nrm(), 8, st);
+  }
+  // V_0 = guess / |guess| (a zero guess becomes the constant vector); the
+  // sigma of V_0 follows
+  void dav_guess(DavState&) {
+    const int64_t n = step.n;
+    if (!(hpin[0] > 0)) {
       std::vector<double> one(n, 1.0);
       dev_h2d(dV.p, one.data(), (size_t)n * 8, st);
-      launch_dots(dV.p, n, 1, dV.p, n, nrm, dpartial.p, st);
+      launch_dots(dV.p, n, 1, dV.p, n, dav_nrm(), dpartial.p, st);
     }
-    launch_normalize(dV.p, nrm, n, st);
-    sigma_vec(dV.p, dW.p, f32);
-    launch_dots(dV.p, n, 1, dW.p, n, dHs.p, dpartial.p, st);
-    int k = 1;  // vectors in the subspace
-    double theta = 0.0;
-    *conv = false;
-    int it = 0;
+    launch_normalize(dV.p, dav_nrm(), n, st);
+  }
+  // vector whose sigma is due, and where it goes
+  double* dav_x(const DavState& d) { return dV.p + (int64_t)d.k * step.n; }
+  double* dav_y(const DavState& d) { return dW.p + (int64_t)d.k * step.n; }
+  // after the sigma of V_k: row k of the projected matrix, V_j . W_k (j <= k)
+  void dav_absorb(DavState& d) {
+    const int64_t n = step.n;
+    launch_dots(dV.p, n, d.k + 1, dW.p + (int64_t)d.k * n, n, dHs.p + (int64_t)d.k * d.ms, dpartial.p, st);
+    ++d.k;
+  }
+  // Ritz pair of the subspace and its residual norm
+  void dav_iter_a(DavState& d) {
+    const int64_t n = step.n;
+    if (n == 1) {
+      dev_d2h_async(hpin, dHs.p, 8, st);
+      return;
+    }
+    launch_syev_small(dHs.p, d.k, d.ms, dav_evals(), dav_evecs(), st);
+    launch_combo_vec(dV.p, n, d.k, dav_evecs(), 1.0, n, dx_.p, 0.0, st);  // x = V s
+    launch_combo_vec(dW.p, n, d.k, dav_evecs(), 1.0, n, dax.p, 0.0, st);  // ax = W s
+    launch_residual(dax.p, dx_.p, dav_evals(), n, dr.p, st);
+    launch_dots(dr.p, n, 1, dr.p, n, dav_nrm(), dpartial.p, st);
+    dev_d2h_async(hpin, dav_evals(), 8, st);
+    dev_d2h_async(hpin + 1, dav_nrm(), 8, st);
+  }
+  // convergence test; otherwise the preconditioned, orthogonalised residual
+  void dav_iter_b(DavState& d) {
+    const int64_t n = step.n;
+    d.theta = hpin[0];
+    if (n == 1) {
+      dev_d2d(d.xres, dV.p, 8, st);
+      d.it = 1;
+      d.conv = d.done = true;
+      return;
+    }
+    const double rn = std::sqrt(std::max(0.0, hpin[1]));
+    if (rn <= d.tol) {
+      d.conv = true;
+      dav_finish(d);
+      return;
+    }
     // FP32 sigma has a residual floor set by its rounding (observed near
     // 10 eps_32 |theta|): close to it, stop when the residual has not
     // improved by 10 % for four iterations
-    double rbest = INFINITY;
-    int stall = 0;
-    if (n == 1) {
-      dev_d2h(&theta, dHs.p, 8, st);
-      dev_d2d(xres, dV.p, 8, st);
-      *iters = 1;
-      *conv = true;
-      return theta;
+    if (d.f32 && rn < 100.0 * 6e-8 * std::max(1.0, std::fabs(d.theta))) {
+      if (rn < 0.9 * d.rbest) {
+        d.rbest = rn;
+        d.stall = 0;
+      } else if (++d.stall >= 4) {
+        d.conv = true;
+        dav_finish(d);
+        return;
+      }
     }
-    for (it = 1; it <= dav_max_iter; ++it) {
-      launch_syev_small(dHs.p, k, ms, evals, evecs, st);
-      launch_combo_vec(dV.p, n, k, evecs, 1.0, n, dx_.p, 0.0, st);  // x = V s
-      launch_combo_vec(dW.p, n, k, evecs, 1.0, n, dax.p, 0.0, st);  // ax = W s
-      launch_residual(dax.p, dx_.p, evals, n, dr.p, st);
-      launch_dots(dr.p, n, 1, dr.p, n, nrm, dpartial.p, st);
-      double hv[2];
-      dev_d2h(hv, evals, 8, st);
-      dev_d2h(hv + 1, nrm, 8, st);
-      theta = hv[0];
-      const double rn = std::sqrt(std::max(0.0, hv[1]));
-      if (rn <= tol) {
-        *conv = true;
-        break;
-      }
-      if (f32 && rn < 100.0 * 6e-8 * std::max(1.0, std::fabs(theta))) {
-        if (rn < 0.9 * rbest) {
-          rbest = rn;
-          stall = 0;
-        } else if (++stall >= 4) {
-          *conv = true;
-          break;
-        }
-      }
-      launch_precond(dr.p, step.diag.p, evals, n, dt.p, st);
+    launch_precond(dr.p, step.diag.p, dav_evals(), n, dt.p, st);
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_dots(dV.p, n, d.k, dt.p, n, dav_coef(), dpartial.p, st);
+      launch_combo_vec(dV.p, n, d.k, dav_coef(), -1.0, n, dt.p, 1.0, st);
+    }
+    launch_dots(dt.p, n, 1, dt.p, n, dav_nrm2(), dpartial.p, st);
+    dev_d2h_async(hpin + 2, dav_nrm2(), 8, st);
+  }
+  // the new direction into V_k (restarting from the Ritz vector when full)
+  void dav_iter_c(DavState& d) {
+    const int64_t n = step.n;
+    double tn = hpin[2];
+    if (!(tn > 1e-28)) {  // preconditioned residual collapsed: use the residual itself
+      dev_d2d(dt.p, dr.p, (size_t)n * 8, st);
       for (int pass = 0; pass < 2; ++pass) {
-        launch_dots(dV.p, n, k, dt.p, n, coef, dpartial.p, st);
-        launch_combo_vec(dV.p, n, k, coef, -1.0, n, dt.p, 1.0, st);
+        launch_dots(dV.p, n, d.k, dt.p, n, dav_coef(), dpartial.p, st);
+        launch_combo_vec(dV.p, n, d.k, dav_coef(), -1.0, n, dt.p, 1.0, st);
       }
-      launch_dots(dt.p, n, 1, dt.p, n, nrm2, dpartial.p, st);
-      double tn;
-      dev_d2h(&tn, nrm2, 8, st);
-      if (!(tn > 1e-28)) {  // preconditioned residual collapsed: use the residual itself
-        dev_d2d(dt.p, dr.p, (size_t)n * 8, st);
-        for (int pass = 0; pass < 2; ++pass) {
-          launch_dots(dV.p, n, k, dt.p, n, coef, dpartial.p, st);
-          launch_combo_vec(dV.p, n, k, coef, -1.0, n, dt.p, 1.0, st);
-        }
-        launch_dots(dt.p, n, 1, dt.p, n, nrm2, dpartial.p, st);
-        dev_d2h(&tn, nrm2, 8, st);
-        if (!(tn > 1e-28)) {
-          *conv = true;
-          break;
-        }
+      launch_dots(dt.p, n, 1, dt.p, n, dav_nrm2(), dpartial.p, st);
+      dev_d2h(&tn, dav_nrm2(), 8, st);
+      if (!(tn > 1e-28)) {
+        d.conv = true;
+        dav_finish(d);
+        return;
       }
-      launch_normalize(dt.p, nrm2, n, st);
-      if (k >= ms) {  // restart with the current Ritz vector
-        dev_d2d(dV.p, dx_.p, (size_t)n * 8, st);
-        dev_d2d(dW.p, dax.p, (size_t)n * 8, st);
-        launch_dots(dV.p, n, 1, dV.p, n, nrm, dpartial.p, st);
-        // x is unit (orthonormal basis, unit Ritz coefficients); W follows x
-        launch_dots(dV.p, n, 1, dW.p, n, dHs.p, dpartial.p, st);
-        k = 1;
-        launch_dots(dV.p, n, 1, dt.p, n, coef, dpartial.p, st);
-        launch_combo_vec(dV.p, n, 1, coef, -1.0, n, dt.p, 1.0, st);
-        launch_dots(dt.p, n, 1, dt.p, n, nrm2, dpartial.p, st);
-        launch_normalize(dt.p, nrm2, n, st);
-      }
-      dev_d2d(dV.p + (int64_t)k * n, dt.p, (size_t)n * 8, st);
-      sigma_vec(dV.p + (int64_t)k * n, dW.p + (int64_t)k * n, f32);
-      // row k of Hs: V_j . W_k for j <= k (lower triangle)
-      launch_dots(dV.p, n, k + 1, dW.p + (int64_t)k * n, n, dHs.p + (int64_t)k * ms, dpartial.p, st);
-      ++k;
     }
-    if (it > dav_max_iter) it = dav_max_iter;
-    // normalise the Ritz vector into xres
-    launch_dots(dx_.p, n, 1, dx_.p, n, nrm, dpartial.p, st);
-    dev_d2d(xres, dx_.p, (size_t)n * 8, st);
-    launch_normalize(xres, nrm, n, st);
-    dev_sync(st);
-    *iters = it;
-    return theta;
+    launch_normalize(dt.p, dav_nrm2(), n, st);
+    if (d.k >= d.ms) {  // restart with the current Ritz vector
+      dev_d2d(dV.p, dx_.p, (size_t)n * 8, st);
+      dev_d2d(dW.p, dax.p, (size_t)n * 8, st);
+      launch_dots(dV.p, n, 1, dV.p, n, dav_nrm(), dpartial.p, st);
+      // x is unit (orthonormal basis, unit Ritz coefficients); W follows x
+      launch_dots(dV.p, n, 1, dW.p, n, dHs.p, dpartial.p, st);
+      d.k = 1;
+      launch_dots(dV.p, n, 1, dt.p, n, dav_coef(), dpartial.p, st);
+      launch_combo_vec(dV.p, n, 1, dav_coef(), -1.0, n, dt.p, 1.0, st);
+      launch_dots(dt.p, n, 1, dt.p, n, dav_nrm2(), dpartial.p, st);
+      launch_normalize(dt.p, dav_nrm2(), n, st);
+    }
+    dev_d2d(dV.p + (int64_t)d.k * n, dt.p, (size_t)n * 8, st);
+  }
+  // normalised Ritz vector into xres
+  void dav_finish(DavState& d) {
+    const int64_t n = step.n;
+    launch_dots(dx_.p, n, 1, dx_.p, n, dav_nrm(), dpartial.p, st);
+    dev_d2d(d.xres, dx_.p, (size_t)n * 8, st);
+    launch_normalize(d.xres, dav_nrm(), n, st);
+    d.done = true;
   }
 
   // ---- SVD and truncation (section "The reduced two-site object"): SVD per
@@ -2778,16 +2912,25 @@ struct Engine {
   // ---- one micro-iteration
   // <x|H|x> / <x|x> with the FP64 sigma
   double rayleigh(const double* x) {
+    ray_enqueue(x, nullptr);
+    dev_sync(st);
+    return hpin[4] / hpin[5];
+  }
+  // the two inner products of the quotient, read back into hpin[4..5];
+  // y = null: sigma here, else y already holds H x
+  void ray_enqueue(const double* x, const double* y) {
     const int64_t n = step.n;
     dsmall.ensure(8 * 64 + 64 * 64);
     dpartial.ensure(256 * 64);
     dr.ensure(n);
-    sigma_vec(x, dr.p, false);
-    launch_dots(x, n, 1, dr.p, n, dsmall.p, dpartial.p, st);
+    if (!hpin) hpin = (double*)host_alloc_pinned(8 * sizeof(double));
+    if (!y) {
+      sigma_vec(x, dr.p, false);
+      y = dr.p;
+    }
+    launch_dots(x, n, 1, y, n, dsmall.p, dpartial.p, st);
     launch_dots(x, n, 1, x, n, dsmall.p + 1, dpartial.p, st);
-    double h[2];
-    dev_d2h(h, dsmall.p, 16, st);
-    return h[0] / h[1];
+    dev_d2h_async(hpin + 4, dsmall.p, 16, st);
   }
 
   double micro(int i, int D, bool right, bool do_svd) {
@@ -2806,6 +2949,14 @@ struct Engine {
     } else {
       th = davidson(x.p, &its, &conv, dav_tol, false);
     }
+    const double e = micro_finish(i, D, right, do_svd, x.p, th, conv);
+    t_micro += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return e;
+  }
+
+  // everything after the centre solve: energy bookkeeping, noise, SVD and
+  // truncation, the new site tensor, renormalisation, the centre move
+  double micro_finish(int i, int D, bool right, bool do_svd, double* x, double th, bool conv) {
     if (!conv) warned = true;
     const double e = th + P.e_const;
     emin = std::min(emin, e);
@@ -2820,11 +2971,10 @@ struct Engine {
         t.cols.push_back(step.dy[m]);
       }
       alloc_tensor(t);
-      dev_d2d(t.data.p, x.p, (size_t)step.n * 8, st);
+      dev_d2d(t.data.p, x, (size_t)step.n * 8, st);
       cen.kind = C_TWO;
       cen.pos = i;
       cen.t = std::move(t);
-      t_micro += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       return e;
     }
     if (noise > 0.0 && wd_prev > 0.0) {
@@ -2835,15 +2985,15 @@ struct Engine {
       launch_fill_uniform(u.p, step.n, seed, NOISE_STREAM | ((uint64_t)n_pass << 16) | (uint64_t)i, st);
       dsmall.ensure(8 * 64 + 64 * 64);
       dpartial.ensure(256 * 64);
-      launch_dots(x.p, step.n, 1, u.p, step.n, dsmall.p, dpartial.p, st);
+      launch_dots(x, step.n, 1, u.p, step.n, dsmall.p, dpartial.p, st);
       double xu;
       dev_d2h(&xu, dsmall.p, 8, st);
-      if (xu < 0.0) launch_axpy(x.p, x.p, -2.0, step.n, st);
-      launch_axpy(x.p, u.p, 0.5 * noise * wd_prev, step.n, st);
+      if (xu < 0.0) launch_axpy(x, x, -2.0, step.n, st);
+      launch_axpy(x, u.p, 0.5 * noise * wd_prev, step.n, st);
       dev_sync(st);
     }
     Split sp;
-    svd_truncate(x.p, D, sp);
+    svd_truncate(x, D, sp);
     wdisc_sweep = std::max(wdisc_sweep, sp.wd);
     wd_pass = std::max(wd_pass, sp.wd);
     const int c = i + 1;
@@ -2921,7 +3071,6 @@ struct Engine {
     }
     dev_sync(st);
     step.i = -1;  // blocks changed
-    t_micro += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return e;
   }
 
@@ -2958,6 +3107,321 @@ struct Engine {
     return e;
   }
 };
+
+// ---------------------------------------------------------------------------
+// Independent problems in lockstep.  The paper computes each state of its
+// carbon-dimer study (section "Bond dissociation curves") as a separate
+// calculation in its own symmetry sector, and parallelises within one
+// calculation over the sparse blocks (section "DMRG" of the library
+// description).  Small calculations cannot fill the GPU alone, so several
+// engines that share one stream advance step by step together: their sigma
+// products go out as one launch per GEMM pass, with the accumulating pass
+// balanced over the whole batch, and the host waits for the stream once per
+// Davidson phase for all of them.
+// ---------------------------------------------------------------------------
+struct BatchLaunch {
+  Stream st = nullptr;
+  DevPool* pool = nullptr;  // holds the descriptor buffer
+  void* host = nullptr;     // page-locked staging of the descriptors
+  void* dev = nullptr;
+  size_t cap = 0;
+  void* uploaded = nullptr;  // event after the last upload from `host`
+  // timing: event pairs around the shared launches, read at the end
+  std::vector<std::pair<void*, void*>> ev64, ev32;
+  double f64 = 0.0, f32 = 0.0;  // algorithmic flops of the shared launches
+  int64_t n64 = 0, n32 = 0;     // shared launches (one per pass pair)
+
+  BatchLaunch(Stream s, DevPool* p) : st(s), pool(p) {}
+  BatchLaunch(const BatchLaunch&) = delete;
+  BatchLaunch& operator=(const BatchLaunch&) = delete;
+  ~BatchLaunch() {
+    if (uploaded) dev_event_free(uploaded);
+    for (auto& e : ev64) dev_event_free(e.first), dev_event_free(e.second);
+    for (auto& e : ev32) dev_event_free(e.first), dev_event_free(e.second);
+    host_free_pinned(host);
+    PoolBind b(pool);
+    if (dev) dev_free(dev);
+  }
+  // seconds in the shared launches (synchronises)
+  void times(double& t64, double& t32) {
+    t64 = t32 = 0.0;
+    for (auto& e : ev64) t64 += dev_event_elapsed(e.first, e.second);
+    for (auto& e : ev32) t32 += dev_event_elapsed(e.first, e.second);
+  }
+
+  // y_e = H_eff(e) x_e for every engine e, the GEMM passes shared
+  void sigma(const std::vector<Engine*>& E, const std::vector<const double*>& x, const std::vector<double*>& y,
+             bool use32) {
+    const size_t n = E.size();
+    for (size_t k = 0; k < n; ++k) {
+      PoolBind b(E[k]->pool);
+      E[k]->sigma_in(x[k], use32);
+    }
+    // descriptors: pass-1 tiles, pass-2 ranges, reductions of cut tiles
+    std::vector<GSeg> s1, s2, sr;
+    std::vector<int> b1, b2, br;
+    int nw1 = 0, nw2 = 0, nr = 0;
+    bool stream2 = true;
+    double fl = 0.0;
+    for (size_t k = 0; k < n; ++k) {
+      const Step& S = E[k]->step;
+      const GemmList::Plan& p1 = use32 ? S.q1 : S.plan.p1;
+      const GemmList::Plan& p2 = use32 ? S.q2 : S.plan.p2;
+      if (p1.stream || p1.nreds != 0) fail(-1, "internal: first pass must be one tile per workgroup");
+      stream2 = p2.stream;
+      if (p1.nwg > 0) {
+        s1.push_back({p1.tiles.p, p1.tasks.p, nullptr, nullptr});
+        b1.push_back(nw1);
+        nw1 += p1.nwg;
+      }
+      if (p2.nwg > 0) {
+        s2.push_back({p2.tiles.p, p2.tasks.p, p2.wstart.p, nullptr});
+        b2.push_back(nw2);
+        nw2 += p2.nwg;
+      }
+      if (p2.nreds > 0) {
+        sr.push_back({nullptr, nullptr, nullptr, p2.reds.p});
+        br.push_back(nr);
+        nr += p2.nreds;
+      }
+      fl += S.flops;
+    }
+    const size_t nseg = s1.size() + s2.size() + sr.size();
+    const size_t bytes = nseg * sizeof(GSeg) + nseg * sizeof(int);
+    if (bytes > cap) {
+      if (uploaded) dev_event_wait(uploaded);
+      host_free_pinned(host);
+      host = nullptr;
+      {
+        PoolBind b(pool);
+        if (dev) dev_free(dev);
+        dev = nullptr;
+        cap = std::max<size_t>(bytes, 4096);
+        dev = dev_alloc(cap);
+      }
+      host = host_alloc_pinned(cap);
+    } else if (uploaded) {
+      dev_event_wait(uploaded);  // the previous upload has left the staging buffer
+    }
+    char* h = (char*)host;
+    GSeg* hs = (GSeg*)h;
+    int* hb = (int*)(h + nseg * sizeof(GSeg));
+    size_t o = 0;
+    for (auto* v : {&s1, &s2, &sr})
+      for (const GSeg& g : *v) hs[o++] = g;
+    o = 0;
+    for (auto* v : {&b1, &b2, &br})
+      for (int q : *v) hb[o++] = q;
+    dev_h2d_async(dev, host, bytes, st);
+    if (uploaded) dev_event_free(uploaded);
+    uploaded = dev_event_record(st);
+    const GSeg* d = (const GSeg*)dev;
+    const int* db = (const int*)((char*)dev + nseg * sizeof(GSeg));
+    void* e0 = dev_event_record(st);
+    launch_gemm_seg(d, db, (int)s1.size(), nw1, false, use32, st);
+    launch_gemm_seg(d + s1.size(), db + s1.size(), (int)s2.size(), nw2, stream2, use32, st);
+    launch_reduce_seg(d + s1.size() + s2.size(), db + s1.size() + s2.size(), (int)sr.size(), nr, use32, st);
+    void* e1 = dev_event_record(st);
+    (use32 ? ev32 : ev64).push_back({e0, e1});
+    (use32 ? f32 : f64) += fl;
+    ++(use32 ? n32 : n64);
+    for (size_t k = 0; k < n; ++k) {
+      PoolBind b(E[k]->pool);
+      E[k]->sigma_out(y[k], use32);
+    }
+  }
+};
+
+// sigma of the due vector of every listed solve, then its row of the
+// projected matrix
+static void dav_sigma(const std::vector<Engine*>& E, std::vector<DavState>& D, const std::vector<size_t>& idx,
+                      BatchLaunch* bl) {
+  if (idx.empty()) return;
+  if (!bl || idx.size() == 1) {
+    for (size_t k : idx) {
+      PoolBind b(E[k]->pool);
+      E[k]->sigma_vec(E[k]->dav_x(D[k]), E[k]->dav_y(D[k]), D[k].f32);
+    }
+  } else {
+    std::vector<Engine*> e;
+    std::vector<const double*> x;
+    std::vector<double*> y;
+    bool use32 = D[idx[0]].f32;
+    for (size_t k : idx) {
+      if (D[k].f32 != use32) fail(-1, "internal: one shared launch has one precision");
+      e.push_back(E[k]);
+      x.push_back(E[k]->dav_x(D[k]));
+      y.push_back(E[k]->dav_y(D[k]));
+    }
+    bl->sigma(e, x, y, use32);
+  }
+  for (size_t k : idx) {
+    PoolBind b(E[k]->pool);
+    E[k]->dav_absorb(D[k]);
+  }
+}
+
+// Davidson solves of engines that share one stream, phase by phase; with
+// bl the sigma products of each iteration share their launches.
+static void davidson_lockstep(const std::vector<Engine*>& E, std::vector<DavState>& D, BatchLaunch* bl) {
+  const size_t n = E.size();
+  if (n == 0) return;
+  const Stream st = E[0]->st;
+  std::vector<size_t> all(n), act, act2;
+  for (size_t k = 0; k < n; ++k) {
+    all[k] = k;
+    PoolBind b(E[k]->pool);
+    E[k]->dav_start(D[k]);
+  }
+  dev_sync(st);
+  for (size_t k = 0; k < n; ++k) {
+    PoolBind b(E[k]->pool);
+    E[k]->dav_guess(D[k]);
+  }
+  dav_sigma(E, D, all, bl);
+  while (true) {
+    act.clear();
+    for (size_t k = 0; k < n; ++k) {
+      if (D[k].done) continue;
+      if (D[k].it > E[k]->dav_max_iter) {  // out of iterations
+        D[k].it = E[k]->dav_max_iter;
+        PoolBind b(E[k]->pool);
+        E[k]->dav_finish(D[k]);
+        continue;
+      }
+      act.push_back(k);
+    }
+    if (act.empty()) break;
+    for (size_t k : act) {
+      PoolBind b(E[k]->pool);
+      E[k]->dav_iter_a(D[k]);
+    }
+    dev_sync(st);
+    act2.clear();
+    for (size_t k : act) {
+      PoolBind b(E[k]->pool);
+      E[k]->dav_iter_b(D[k]);
+      if (!D[k].done) act2.push_back(k);
+    }
+    if (act2.empty()) continue;
+    dev_sync(st);
+    act.clear();
+    for (size_t k : act2) {
+      PoolBind b(E[k]->pool);
+      E[k]->dav_iter_c(D[k]);
+      if (!D[k].done) act.push_back(k);
+    }
+    dav_sigma(E, D, act, bl);
+    for (size_t k : act) ++D[k].it;
+  }
+  dev_sync(st);
+}
+
+// One sweep (left-to-right then right-to-left pass; section "Sweeping") of
+// every engine, the micro-iterations of all engines in lockstep: step r of
+// each engine still sweeping, then step r + 1.  Engines keep their own
+// schedule position, noise and statistics; only the launches are shared.
+static bool batch_sweep(const std::vector<Engine*>& E, const std::vector<int>& Dk, std::vector<double>& emin,
+                        BatchLaunch& bl) {
+  const size_t n = E.size();
+  std::vector<int> nsteps(n);
+  int maxs = 0;
+  for (size_t k = 0; k < n; ++k) {
+    Engine& e = *E[k];
+    if (!e.mps_ready) fail(-1, "call sadmrg_init_mps or sadmrg_mps_import first");
+    if (!((e.cen.kind == C_T0 && e.cen.pos == 0) || (e.cen.kind == C_TWO && e.cen.pos == 0)))
+      fail(-1, "a batched sweep starts with every centre at the left end");
+    e.wdisc_sweep = 0.0;
+    e.warned = false;
+    nsteps[k] = 2 * (e.P.L - 1);
+    maxs = std::max(maxs, nsteps[k]);
+  }
+  emin.assign(n, INFINITY);
+  const int prec = E[0]->prec;
+  const bool use32 = prec == 1;
+  for (int r = 0; r < maxs; ++r) {
+    std::vector<Engine*> ea;
+    std::vector<size_t> ka;
+    std::vector<int> si;
+    std::vector<char> sright, ssvd;
+    for (size_t k = 0; k < n; ++k) {
+      if (r >= nsteps[k]) continue;
+      const int L = E[k]->P.L;
+      const bool right = r <= L - 2;
+      const int i = right ? r : 2 * L - 3 - r;
+      ea.push_back(E[k]);
+      ka.push_back(k);
+      si.push_back(i);
+      sright.push_back(right);
+      ssvd.push_back(right ? i < L - 2 : i > 0);
+    }
+    const size_t na = ea.size();
+    std::vector<DBuf> xb(na);
+    for (size_t j = 0; j < na; ++j) {
+      Engine& e = *ea[j];
+      PoolBind b(e.pool);
+      struct Defer {
+        Engine& e;
+        ~Defer() { e.defer_p2 = false; }
+      } df{e};
+      e.defer_p2 = true;
+      e.prepare(si[j]);
+      xb[j].alloc((size_t)std::max<int64_t>(e.step.n, 1));
+    }
+    // the accumulating pass balanced over the whole batch
+    double tot = 0.0;
+    for (Engine* e : ea)
+      if (e->step.p2_pending) tot += e->step.g2.total_cost();
+    const double target = GEMM_GPC_PASS2 > 0 ? tot / ((double)GEMM_GPC_PASS2 * GemmList::cus()) : 0.0;
+    for (Engine* e : ea) {
+      PoolBind b(e->pool);
+      e->plan_pass2(target);
+    }
+    std::vector<DavState> ds(na);
+    for (size_t j = 0; j < na; ++j) {
+      ds[j].xres = xb[j].p;
+      ds[j].tol = use32 ? std::max(ea[j]->dav_tol, ea[j]->mixed_tol) : ea[j]->dav_tol;
+      ds[j].f32 = use32;
+    }
+    davidson_lockstep(ea, ds, &bl);
+    std::vector<double> th(na);
+    for (size_t j = 0; j < na; ++j) th[j] = ds[j].theta;
+    if (use32) {  // FP64 Rayleigh quotients of the FP32 solutions, sigma shared
+      std::vector<const double*> xs;
+      std::vector<double*> ys;
+      for (size_t j = 0; j < na; ++j) {
+        PoolBind b(ea[j]->pool);
+        ea[j]->dr.ensure(ea[j]->step.n);
+        xs.push_back(xb[j].p);
+        ys.push_back(ea[j]->dr.p);
+      }
+      if (na == 1) {
+        PoolBind b(ea[0]->pool);
+        ea[0]->sigma_vec(xs[0], ys[0], false);
+      } else {
+        bl.sigma(ea, xs, ys, false);
+      }
+      for (size_t j = 0; j < na; ++j) {
+        PoolBind b(ea[j]->pool);
+        ea[j]->ray_enqueue(xs[j], ys[j]);
+      }
+      dev_sync(bl.st);
+      for (size_t j = 0; j < na; ++j) th[j] = ea[j]->hpin[4] / ea[j]->hpin[5];
+    }
+    for (size_t j = 0; j < na; ++j) {
+      Engine& e = *ea[j];
+      PoolBind b(e.pool);
+      const double en = e.micro_finish(si[j], Dk[ka[j]], sright[j], ssvd[j], xb[j].p, th[j], ds[j].conv);
+      emin[ka[j]] = std::min(emin[ka[j]], en);
+      if ((sright[j] && si[j] == e.P.L - 2) || (!sright[j] && si[j] == 0)) e.end_pass();
+      if (!sright[j] && si[j] == 0) e.wdisc = e.wdisc_sweep;
+      xb[j].release();
+    }
+  }
+  bool warned = false;
+  for (Engine* e : E) warned = warned || e->warned;
+  return warned;
+}
 
 }  // namespace sadmrg
 
@@ -3157,6 +3621,7 @@ int sadmrg_create(sadmrg_ctx** out, int L, int group_order, const int* orb_irrep
     if (device < 0 || device >= nd) sadmrg::fail(SADMRG_EINVAL, "device index out of range");
     sadmrg::dev_set_device(device);
     c->e.device = device;
+    c->e.pool = c->pool;
     c->e.P.L = L;
     c->e.P.order = group_order;
     c->e.P.orb.assign(orb_irrep, orb_irrep + L);
@@ -3287,6 +3752,58 @@ int sadmrg_sweep(sadmrg_ctx* ctx, int D, double* e_min) {
     if (e_min) *e_min = e;
     return ctx->e.warned ? SADMRG_WARN_NOT_CONVERGED : 0;
   });
+}
+
+int sadmrg_batch_sweep(sadmrg_ctx* const* ctxs, int n, const int* D, double* e_min, double* stats) {
+  if (!ctxs || n < 1 || !D) return SADMRG_EINVAL;
+  for (int k = 0; k < n; ++k) {
+    if (!ctxs[k]) return SADMRG_EINVAL;
+    ctxs[k]->err.clear();
+    for (int j = 0; j < k; ++j)
+      if (ctxs[j] == ctxs[k]) {
+        ctxs[k]->err = "a context appears twice in the batch";
+        return SADMRG_EINVAL;
+      }
+  }
+  auto fail_all = [&](int code, const std::string& msg) {
+    for (int k = 0; k < n; ++k) ctxs[k]->err = msg;
+    return code;
+  };
+  sadmrg::Engine& e0 = ctxs[0]->e;
+  for (int k = 0; k < n; ++k) {
+    const sadmrg::Engine& e = ctxs[k]->e;
+    if (D[k] < 1) return fail_all(SADMRG_EINVAL, "D must be positive");
+    if (e.device != e0.device || e.st != e0.st)
+      return fail_all(SADMRG_EINVAL, "batched contexts must share one device and one stream");
+    if (e.prec != e0.prec) return fail_all(SADMRG_EINVAL, "batched contexts must share one precision mode");
+  }
+  try {
+    std::vector<sadmrg::Engine*> E;
+    for (int k = 0; k < n; ++k) E.push_back(&ctxs[k]->e);
+    std::vector<double> em;
+    bool warned;
+    double t64 = 0.0, t32 = 0.0;
+    sadmrg::BatchLaunch bl(e0.st, ctxs[0]->pool);
+    warned = sadmrg::batch_sweep(E, std::vector<int>(D, D + n), em, bl);
+    bl.times(t64, t32);
+    if (e_min)
+      for (int k = 0; k < n; ++k) e_min[k] = em[k];
+    if (stats) {
+      stats[0] = t64;
+      stats[1] = bl.f64;
+      stats[2] = (double)bl.n64;
+      stats[3] = t32;
+      stats[4] = bl.f32;
+      stats[5] = (double)bl.n32;
+    }
+    return warned ? SADMRG_WARN_NOT_CONVERGED : 0;
+  } catch (const sadmrg::Failure& x) {
+    return fail_all(x.code, x.msg);
+  } catch (const std::bad_alloc&) {
+    return fail_all(SADMRG_ENOMEM, "host allocation failed");
+  } catch (const std::exception& x) {
+    return fail_all(SADMRG_EINVAL, x.what());
+  }
 }
 
 int sadmrg_solve(sadmrg_ctx* ctx, int n, const int* D, const double* e_conv, const int* max_sweeps,

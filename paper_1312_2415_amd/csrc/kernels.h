@@ -25,12 +25,19 @@ void dev_d2h(void* dst, const void* src, size_t bytes, Stream st);
 void dev_d2d(void* dst, const void* src, size_t bytes, Stream st);
 void dev_zero(void* p, size_t bytes, Stream st);  // fill kernel (no memset node)
 void dev_sync(Stream st);
+// Page-locked host memory and copies that do not wait for the stream: the
+// host side must stay untouched until the stream has passed the copy.
+void* host_alloc_pinned(size_t bytes);
+void host_free_pinned(void* p);
+void dev_h2d_async(void* dst, const void* pinned_src, size_t bytes, Stream st);
+void dev_d2h_async(void* pinned_dst, const void* src, size_t bytes, Stream st);
 void dev_set_device(int device);
 int dev_count();
 // event timing: returns an opaque event handle recorded on st
 void* dev_event_record(Stream st);
 double dev_event_elapsed(void* a, void* b);  // seconds, synchronises b
 void dev_event_free(void* e);
+void dev_event_wait(void* e);  // the host waits until the stream has passed e
 
 // Flags of a block triple product  out += coef * opA(A) * B * opC(C)  (the
 // host evaluates it as two grouped GEMMs): transpose A / C, identity A / C.
@@ -132,6 +139,18 @@ void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int 
 // Number of compute units of the current device.
 int dev_cu_count();
 void launch_reduce(const RTile* reds, int nred, bool f32, Stream st);
+// Several independent plans in one launch: plan s owns the workgroups
+// [base[s], base[s+1]) of the grid (base ascending from 0, nwg in total) and
+// reads its own records: tiles + tasks (+ wstart when stream) for the GEMM,
+// reds for the reduction.  Both arrays live in device memory.
+struct GSeg {
+  const GTile* tiles;
+  const GTask* tasks;
+  const int* wstart;
+  const RTile* reds;
+};
+void launch_gemm_seg(const GSeg* segs, const int* base, int nseg, int nwg, bool stream, bool f32, Stream st);
+void launch_reduce_seg(const GSeg* segs, const int* base, int nseg, int nred, bool f32, Stream st);
 // out[j] = sum_{r < n_j} p_j[r * (ld_j + 1)]  (traces of square sub-blocks)
 struct TraceJob {
   const double* p;

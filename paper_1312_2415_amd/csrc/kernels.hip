@@ -145,6 +145,23 @@ void dev_zero(void* p, size_t bytes, Stream st) {
   check_launch("zero");
 }
 void dev_sync(Stream st) { hip_ok(hipStreamSynchronize((hipStream_t)st), "hipStreamSynchronize"); }
+void* host_alloc_pinned(size_t bytes) {
+  void* p = nullptr;
+  if (hipHostMalloc(&p, bytes ? bytes : 8, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    dev_fail("hipHostMalloc failed");
+  }
+  return p;
+}
+void host_free_pinned(void* p) {
+  if (p) (void)hipHostFree(p);
+}
+void dev_h2d_async(void* dst, const void* src, size_t bytes, Stream st) {
+  if (bytes) hip_ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, (hipStream_t)st), "hipMemcpyAsync H2D");
+}
+void dev_d2h_async(void* dst, const void* src, size_t bytes, Stream st) {
+  if (bytes) hip_ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, (hipStream_t)st), "hipMemcpyAsync D2H");
+}
 void dev_set_device(int device) { hip_ok(hipSetDevice(device), "hipSetDevice"); }
 int dev_count() {
   int n = 0;
@@ -169,6 +186,7 @@ double dev_event_elapsed(void* a, void* b) {
 void dev_event_free(void* e) {
   if (e) (void)hipEventDestroy((hipEvent_t)e);
 }
+void dev_event_wait(void* e) { hip_ok(hipEventSynchronize((hipEvent_t)e), "hipEventSynchronize"); }
 
 namespace {
 
@@ -418,13 +436,13 @@ __device__ inline void g_write(const GOut& tile, const typename GT<T>::Acc (&acc
 // the hardware dispatcher balances short, independent tiles best.
 // TAG only separates the symbols of the launch sites for profiling:
 // 0 = sigma pass 1, 1 = sigma pass 2, 2 = renormalisation / other products.
-template <typename T, int TAG>
-__global__ __launch_bounds__(256, 4) void gemm_tile_kernel(const GTile* __restrict__ tiles,
-                                                           const GTask* __restrict__ tasks) {
+template <typename T>
+__device__ __forceinline__ void gemm_tile_body(const GTile* __restrict__ tiles, const GTask* __restrict__ tasks,
+                                               const unsigned bid) {
   typedef typename GT<T>::Acc Acc;
   __shared__ __attribute__((aligned(16))) T sA[64 * GT<T>::SLD];
   __shared__ __attribute__((aligned(16))) T sB[64 * GT<T>::SLD];
-  const GTile tile = tiles[blockIdx.x];
+  const GTile tile = tiles[bid];
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid / 64);  // wave index, scalar
   const int l = tid % 64;
@@ -487,13 +505,18 @@ __global__ __launch_bounds__(256, 4) void gemm_tile_kernel(const GTile* __restri
   if (active) g_write<T>(g_out(tile), acc, r0, li, lk);
 }
 
+template <typename T, int TAG>
+__global__ __launch_bounds__(256, 4) void gemm_tile_kernel(const GTile* __restrict__ tiles,
+                                                           const GTask* __restrict__ tasks) {
+  gemm_tile_body<T>(tiles, tasks, blockIdx.x);
+}
+
 // Workgroup g streams the tiles [wstart[g], wstart[g+1]).
 // TAG only separates the symbols of the launch sites for profiling:
 // 0 = sigma pass 1, 1 = sigma pass 2, 2 = renormalisation / other products.
-template <typename T, int TAG>
-__global__ __launch_bounds__(256, 3) void gemm_stream_kernel(const GTile* __restrict__ tiles,
-                                                             const GTask* __restrict__ tasks,
-                                                             const int* __restrict__ wstart) {
+template <typename T>
+__device__ __forceinline__ void gemm_stream_body(const GTile* __restrict__ tiles, const GTask* __restrict__ tasks,
+                                                 const int* __restrict__ wstart, const unsigned bid) {
   typedef typename GT<T>::Acc Acc;
   __shared__ __attribute__((aligned(16))) T sA[64 * GT<T>::SLD];
   __shared__ __attribute__((aligned(16))) T sB[64 * GT<T>::SLD];
@@ -502,8 +525,8 @@ __global__ __launch_bounds__(256, 3) void gemm_stream_kernel(const GTile* __rest
   const int l = tid % 64;
   const int li = l % 16, lk = l / 16;
   const int r0 = 16 * w;
-  int ft = wstart[blockIdx.x];
-  const int fe = wstart[blockIdx.x + 1];
+  int ft = wstart[bid];
+  const int fe = wstart[bid + 1];
   if (ft >= fe) return;
 
   // fetch side: tile ft (record FT), task t (record cur) at chunk k0; the
@@ -592,6 +615,57 @@ __global__ __launch_bounds__(256, 3) void gemm_stream_kernel(const GTile* __rest
   }
 }
 
+template <typename T, int TAG>
+__global__ __launch_bounds__(256, 3) void gemm_stream_kernel(const GTile* __restrict__ tiles,
+                                                             const GTask* __restrict__ tasks,
+                                                             const int* __restrict__ wstart) {
+  gemm_stream_body<T>(tiles, tasks, wstart, blockIdx.x);
+}
+
+// Several plans in one launch (independent problems batched together): plan s
+// owns the workgroups [base[s], base[s+1]), base ascending from 0.  Every
+// wavefront finds its plan with one vector load and a ballot per 64 plans.
+__device__ __forceinline__ int seg_find(const int* __restrict__ base, const int nseg, const int bid) {
+  const int lane = threadIdx.x % 64;
+  int s = 0;
+  for (int c = 0; c < nseg; c += 64) {
+    const int j = c + lane;
+    const bool le = j < nseg && base[j] <= bid;
+    const unsigned long long m = __ballot(le);
+    s += __popcll(m);
+    if (m != ~0ull) break;
+  }
+  return __builtin_amdgcn_readfirstlane(s - 1);
+}
+
+// The descriptor as the kernels read it: record pointers typed as global
+// memory, so that their loads stay scalar as for kernel-argument pointers.
+#define G_GLOBAL __attribute__((address_space(1)))
+struct GSegDev {
+  const G_GLOBAL GTile* tiles;
+  const G_GLOBAL GTask* tasks;
+  const G_GLOBAL int* wstart;
+  const G_GLOBAL RTile* reds;
+};
+static_assert(sizeof(GSegDev) == sizeof(GSeg), "descriptor layout");
+
+template <typename T>
+__global__ __launch_bounds__(256, 4) void gemm_tile_seg_kernel(const GSeg* __restrict__ segs,
+                                                               const int* __restrict__ base, int nseg) {
+  const int s = seg_find(base, nseg, blockIdx.x);
+  const GSegDev* const d = (const GSegDev*)segs;
+  gemm_tile_body<T>((const GTile*)d[s].tiles, (const GTask*)d[s].tasks, blockIdx.x - base[s]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 3) void gemm_stream_seg_kernel(const GSeg* __restrict__ segs,
+                                                                 const int* __restrict__ base, int nseg) {
+  const int s = seg_find(base, nseg, blockIdx.x);
+  const GSegDev* const d = (const GSegDev*)segs;
+  gemm_stream_body<T>((const GTile*)d[s].tiles, (const GTask*)d[s].tasks, (const int*)d[s].wstart,
+                      blockIdx.x - base[s]);
+}
+
 template <typename T>
 static void launch_gemm_t(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag,
                           hipStream_t hs) {
@@ -622,6 +696,23 @@ void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int 
   check_launch("gemm");
 }
 
+void launch_gemm_seg(const GSeg* segs, const int* base, int nseg, int nwg, bool stream, bool f32, Stream st) {
+  if (nwg <= 0 || nseg <= 0) return;
+  const hipStream_t hs = (hipStream_t)st;
+  if (stream) {
+    if (f32)
+      hipLaunchKernelGGL(gemm_stream_seg_kernel<float>, dim3(nwg), dim3(256), 0, hs, segs, base, nseg);
+    else
+      hipLaunchKernelGGL(gemm_stream_seg_kernel<double>, dim3(nwg), dim3(256), 0, hs, segs, base, nseg);
+  } else {
+    if (f32)
+      hipLaunchKernelGGL(gemm_tile_seg_kernel<float>, dim3(nwg), dim3(256), 0, hs, segs, base, nseg);
+    else
+      hipLaunchKernelGGL(gemm_tile_seg_kernel<double>, dim3(nwg), dim3(256), 0, hs, segs, base, nseg);
+  }
+  check_launch("gemm_seg");
+}
+
 int dev_cu_count() {
   int dev = 0, n = 0;
   hip_ok(hipGetDevice(&dev), "hipGetDevice");
@@ -633,8 +724,8 @@ int dev_cu_count() {
 // keep loads in flight; the combination order is fixed, so results are
 // reproducible run to run.
 template <typename T>
-__global__ __launch_bounds__(256) void reduce_kernel(const RTile* __restrict__ reds) {
-  const RTile t = reds[blockIdx.x];
+__device__ __forceinline__ void reduce_body(const RTile* __restrict__ reds, const unsigned bid) {
+  const RTile t = reds[bid];
   const T* const part = (const T*)t.part;
   T* const out = (T*)t.out;
   const int n = t.rows * t.cols;
@@ -651,6 +742,16 @@ __global__ __launch_bounds__(256) void reduce_kernel(const RTile* __restrict__ r
     out[(int64_t)(e / t.cols) * t.ld + e % t.cols] += s;
   }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_kernel(const RTile* __restrict__ reds) {
+  reduce_body<T>(reds, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_seg_kernel(const GSeg* __restrict__ segs, const int* __restrict__ base,
+                                                         int nseg) {
+  const int s = seg_find(base, nseg, blockIdx.x);
+  reduce_body<T>((const RTile*)((const GSegDev*)segs)[s].reds, blockIdx.x - base[s]);
+}
 
 void launch_reduce(const RTile* reds, int nred, bool f32, Stream st) {
   if (nred <= 0) return;
@@ -659,6 +760,15 @@ void launch_reduce(const RTile* reds, int nred, bool f32, Stream st) {
   else
     hipLaunchKernelGGL(reduce_kernel<double>, dim3(nred), dim3(256), 0, (hipStream_t)st, reds);
   check_launch("reduce");
+}
+
+void launch_reduce_seg(const GSeg* segs, const int* base, int nseg, int nred, bool f32, Stream st) {
+  if (nred <= 0 || nseg <= 0) return;
+  if (f32)
+    hipLaunchKernelGGL(reduce_seg_kernel<float>, dim3(nred), dim3(256), 0, (hipStream_t)st, segs, base, nseg);
+  else
+    hipLaunchKernelGGL(reduce_seg_kernel<double>, dim3(nred), dim3(256), 0, (hipStream_t)st, segs, base, nseg);
+  check_launch("reduce_seg");
 }
 
 // ---------------------------------------------------------------------------
