@@ -243,6 +243,9 @@ def main():
                              "share_of_sigma_time": st[k]["t"] / max(st["t_sigma"], 1e-12)}
                          for k in ("pass1", "pass2")},
         "copy_probe_GBps": copy_gbps,
+        "host_phase_seconds_per_sweep": {k: v / args.steps for k, v in st["phases"].items()},
+        "davidson_sigma_seconds_per_sweep": st["t_sigma"] / args.steps,
+        "max_enlarged_bytes": st["max_enlarged_bytes"],
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK, "unit": "TFLOP/s",
                      "frac": achieved / FP64_MFMA_PEAK, "traffic": stored_traffic(dom),
                      "kernel": PASS_KERNEL[dom], "flops_per_launch": flops_per_launch,

@@ -133,15 +133,26 @@ int sadmrg_sweep(sadmrg_ctx* ctx, int D, double* e_min);
  *            precision mode.  Sizes, sectors and schedules may differ.
  *   D[n]:    bond dimension of each context (host array).
  *   e_min[n] (may be NULL): lowest energy of each context's macro-iteration.
- *   stats[6] (may be NULL): seconds, algorithmic flops and number of the
+ *   stats[10] (may be NULL): seconds, algorithmic flops and number of the
  *            shared FP64 sigma launches, then the same for FP32 (zero for a
- *            batch of one, which runs as sadmrg_sweep).
+ *            batch of one, which runs as sadmrg_sweep); then the host wall
+ *            seconds of the phases: step preparation, Davidson, Rayleigh
+ *            quotients (mixed precision), decomposition and update.
  * Each context's result equals its own sadmrg_sweep up to the summation
  * order of the shared launches.  Returns 1 if some Davidson solve hit
  * max_iter; on an error every context gets the message, and the contexts
  * are left mid-sweep (re-import or re-initialise them).  Errors: EINVAL,
  * ENOMEM, EDEVICE. */
 int sadmrg_batch_sweep(sadmrg_ctx* const* ctxs, int n, const int* D, double* e_min, double* stats);
+
+/* Keep enlarged blocks for the next pass (on = 1, the default) or build
+ * every enlargement afresh (on = 0, which also releases the kept ones).  In a
+ * left-to-right pass the right blocks are the ones the previous
+ * right-to-left pass built (section "Sweeping"), so the enlargement of the
+ * unchanged side at step i equals the one made there; results are identical
+ * either way.  Kept blocks of all contexts of the process share a ceiling
+ * of a quarter of the device memory; the oldest go first.  Errors: EINVAL. */
+int sadmrg_set_enlarge_cache(sadmrg_ctx* ctx, int on);
 
 /* Run a convergence scheme (section "Convergence scheme"): n instructions of
  * (D[i], e_conv[i], max_sweeps[i], noise[i]).  *e_min receives the lowest
@@ -241,6 +252,14 @@ int sadmrg_sigma_counters(sadmrg_ctx* ctx, double* flops, double* bytes, int64_t
 int sadmrg_stats(sadmrg_ctx* ctx, double* t_sigma, int64_t* n_sigma, double* t_micro, double* flops_sigma,
                  double* t_blocking);
 int sadmrg_stats_reset(sadmrg_ctx* ctx);
+
+/* Host wall seconds since the last reset of the parts of the micro-iterations
+ * outside Davidson (section "Sweeping"), out[7]: enlargement of the two
+ * blocks, sigma task lists, GEMM planning, effective-Hamiltonian diagonal,
+ * initial guess, SVD and truncation, new site tensor and renormalisation.
+ * Device work that these parts wait for is included.  Errors: EINVAL. */
+int sadmrg_stats_phases(sadmrg_ctx* ctx, double* out);
+
 /* Operator bytes touched by the sigma calls since the last reset (operator
  * stacks read + vector in/out, per call) and the largest enlarged-operator
  * footprint of one micro-iteration (both enlarged blocks). */

@@ -60,6 +60,8 @@ def load_library(path: str | None = None):
         "sadmrg_sigma_counters": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(ctypes.c_int64)]),
         "sadmrg_stats": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl), P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_reset": (c_int, [c_vp]),
+        "sadmrg_stats_phases": (c_int, [c_vp, P(c_dbl)]),
+        "sadmrg_set_enlarge_cache": (c_int, [c_vp, c_int]),
         "sadmrg_stats_bytes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_passes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_mixed": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl)]),
@@ -251,6 +253,9 @@ class SaDMRG:
         t32, n32, f32 = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         self._chk(self.lib.sadmrg_stats_mixed(self.h, ctypes.byref(t32), ctypes.byref(n32), ctypes.byref(f32)))
         out["fp32"] = {"t": t32.value, "calls": n32.value, "flops": f32.value}
+        ph = (ctypes.c_double * 7)()
+        self._chk(self.lib.sadmrg_stats_phases(self.h, ph))
+        out["phases"] = dict(zip(("enlarge", "tasks", "plan", "diag", "guess", "svd", "renorm"), list(ph)))
         return out
 
     def rdm(self, two_body: bool = True):
@@ -266,6 +271,9 @@ class SaDMRG:
         v = ctypes.c_double()
         self._chk(self.lib.sadmrg_get_s2(self.h, ctypes.byref(v)))
         return v.value
+
+    def set_enlarge_cache(self, on: bool):
+        self._chk(self.lib.sadmrg_set_enlarge_cache(self.h, int(bool(on))))
 
     def set_precision(self, mode: int, mixed_tol: float = 1e-5):
         """0: FP64 sigma; 1: FP32 sigma in Davidson + FP64 Rayleigh-quotient energy."""
@@ -300,13 +308,14 @@ def batch_sweep(solvers, D):
     hs = (ctypes.c_void_p * n)(*[s.h for s in solvers])
     dd = (ctypes.c_int * n)(*Ds)
     em = (ctypes.c_double * n)()
-    st = (ctypes.c_double * 6)()
+    st = (ctypes.c_double * 10)()
     rc = lib.sadmrg_batch_sweep(hs, n, dd, em, st)
     if rc < 0:
         msg = lib.sadmrg_last_error(solvers[0].h)
         raise SadmrgError(rc, msg.decode() if msg else "")
     stats = {"t_sigma": st[0], "flops_sigma": st[1], "n_sigma": int(st[2]),
-             "t_sigma32": st[3], "flops_sigma32": st[4], "n_sigma32": int(st[5])}
+             "t_sigma32": st[3], "flops_sigma32": st[4], "n_sigma32": int(st[5]),
+             "wall": {"prepare": st[6], "davidson": st[7], "rayleigh": st[8], "finish": st[9]}}
     return list(em), stats, rc
 
 

@@ -20,7 +20,11 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
+#include <exception>
+#include <mutex>
+#include <thread>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -356,7 +360,16 @@ struct OpInfo {
   int64_t off;
 };
 
+// every Store gets a distinct generation number: a cached result derived
+// from a store is valid while that store (not a later one at the same
+// address) is the current block
+static uint64_t next_store_gen() {
+  static std::atomic<uint64_t> g{0};
+  return ++g;
+}
+
 struct Store {
+  uint64_t gen = next_store_gen();
   char side = 'L';
   int bond = 0;
   std::vector<int> orbs;
@@ -1149,21 +1162,30 @@ struct GemmList {
   // workgroup start and a partial tile
   static constexpr double MIN_WG_COST = 30000.0;
   static int cus() {
-    static int n = 0;
-    if (n <= 0) n = std::max(1, dev_cu_count());
+    static const int n = std::max(1, dev_cu_count());
     return n;
   }
-  // estimated cost of all tiles (the quantity the ranges of plan() divide)
+  // the tasks grouped by tile (tile order, insertion order within a tile):
+  // tile i owns flat[cnt[i], cnt[i+1])
+  void grouped(std::vector<int>& cnt, std::vector<GTask>& flat) const {
+    cnt.assign(tiles.size() + 1, 0);
+    for (auto& t : items) cnt[t.tile + 1]++;
+    for (size_t i = 0; i < tiles.size(); ++i) cnt[i + 1] += cnt[i];
+    flat.resize(items.size());
+    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+    for (auto& t : items) flat[pos[t.tile]++] = t.t;
+  }
+  // estimated cost of all tiles, summed in the order plan() sums it
   double total_cost() const {
-    std::vector<int> cnt(tiles.size(), 0);
-    std::vector<double> tc(tiles.size(), 0.0);
-    for (auto& t : items) {
-      cnt[t.tile]++;
-      tc[t.tile] += task_cost(t.t.K, tiles[t.tile].cols);
-    }
+    std::vector<int> cnt;
+    std::vector<GTask> flat;
+    grouped(cnt, flat);
     double total = 0.0;
-    for (size_t i = 0; i < tiles.size(); ++i)
-      if (cnt[i] > 0 || tiles[i].mode != 0) total += TILE_COST + tc[i];
+    for (size_t i = 0; i < tiles.size(); ++i) {
+      if (cnt[i] == cnt[i + 1] && tiles[i].mode == 0) continue;
+      total += TILE_COST;
+      for (int t = cnt[i]; t < cnt[i + 1]; ++t) total += task_cost(flat[t].K, tiles[i].cols);
+    }
     return total;
   }
 
@@ -1175,12 +1197,9 @@ struct GemmList {
   // accumulating tile (mode 0) may be cut between two workgroups: its pieces
   // write partial tiles that a second kernel adds in a fixed order.
   void plan(Plan& pl, Stream st, int gpc, double target_cost = 0.0) {
-    std::vector<int> cnt(tiles.size() + 1, 0);
-    for (auto& t : items) cnt[t.tile + 1]++;
-    for (size_t i = 0; i < tiles.size(); ++i) cnt[i + 1] += cnt[i];
-    std::vector<GTask> flat(items.size());
-    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-    for (auto& t : items) flat[pos[t.tile]++] = t.t;
+    std::vector<int> cnt;
+    std::vector<GTask> flat;
+    grouped(cnt, flat);
     std::vector<double> cost(flat.size());
     double total = 0.0;
     for (size_t i = 0; i < tiles.size(); ++i) {
@@ -1413,7 +1432,17 @@ struct Step {
   double flops = 0.0, bytes = 0.0;
   int64_t ntasks = 0;
   std::vector<std::array<int, 5>> shapes;  // per tile task: rows, K1, K2, cols, flags
+  int site = -1;                 // i of the sites (i, i+1), kept when i is reset
+  uint64_t genX = 0, genY = 0;   // generations of the blocks X and Y were built from
 };
+
+// Device bytes of enlarged blocks kept for reuse, over all engines of the
+// process, and their ceiling (a quarter of the device memory).
+static std::atomic<int64_t> g_enl_cache_bytes{0};
+static int64_t enl_cache_budget() {
+  static const int64_t b = (int64_t)(dev_total_memory() / 4);
+  return b;
+}
 
 // stream of the noise draws of step i in pass p: NOISE_STREAM | p << 16 | i
 static const uint64_t NOISE_STREAM = (uint64_t)0x4E4F << 40;
@@ -1440,9 +1469,94 @@ struct DavState {
   int stall = 0;
   bool conv = false, done = false;
 };
+// Small job arrays for the kernels, staged through page-locked memory: each
+// upload is appended and copied asynchronously.  Space is reused only after
+// reset(), which the caller issues right after a stream sync (when every
+// copy and every kernel reading the arrays has finished); when the space
+// runs out, a larger pair takes over and the old one is released at the
+// next reset, so pointers handed out before stay valid until then.  Scalars
+// the host needs come back through fetch(): one gather kernel and one copy.
+struct Staging {
+  Stream st = nullptr;
+  DevPool* pool = nullptr;
+  char* host = nullptr;
+  char* dev = nullptr;
+  size_t cap = 0, used = 0;
+  double* sdev = nullptr;   // gathered scalars (device)
+  double* shost = nullptr;  // gathered scalars (page-locked host)
+  size_t scap = 0;
+  std::vector<std::pair<void*, void*>> retired;  // (page-locked, device) to release at reset
+
+  Staging(Stream s, DevPool* p) : st(s), pool(p) {}
+  Staging(const Staging&) = delete;
+  Staging& operator=(const Staging&) = delete;
+  ~Staging() {
+    try {
+      dev_sync(st);
+    } catch (...) {
+    }
+    release_retired();
+    host_free_pinned(host);
+    host_free_pinned(shost);
+    PoolBind b(pool);
+    if (dev) dev_free(dev);
+    if (sdev) dev_free(sdev);
+  }
+  void release_retired() {
+    PoolBind b(pool);
+    for (auto& r : retired) {
+      host_free_pinned(r.first);
+      if (r.second) dev_free(r.second);
+    }
+    retired.clear();
+  }
+  void reset() {
+    used = 0;
+    release_retired();
+  }
+  template <class T>
+  const T* up(const std::vector<T>& v) {
+    const size_t b = std::max<size_t>(v.size() * sizeof(T), 8);
+    size_t off = (used + 255) & ~(size_t)255;
+    if (off + b > cap) {
+      if (host || dev) retired.push_back({host, dev});
+      cap = std::max<size_t>({2 * cap, b, (size_t)1 << 20});
+      {
+        PoolBind pb(pool);
+        dev = (char*)dev_alloc(cap);
+      }
+      host = (char*)host_alloc_pinned(cap);
+      off = 0;
+    }
+    if (!v.empty()) {
+      std::memcpy(host + off, v.data(), v.size() * sizeof(T));
+      dev_h2d_async(dev + off, host + off, v.size() * sizeof(T), st);
+    }
+    used = off + b;
+    return (const T*)(dev + off);
+  }
+  // shost[i] = *src[i] once the stream has been synchronised
+  void fetch(const std::vector<const double*>& src) {
+    if (src.empty()) return;
+    if (src.size() > scap) {
+      if (shost || sdev) retired.push_back({shost, sdev});
+      scap = std::max<size_t>(2 * src.size(), 64);
+      {
+        PoolBind pb(pool);
+        sdev = (double*)dev_alloc(scap * sizeof(double));
+      }
+      shost = (double*)host_alloc_pinned(scap * sizeof(double));
+    }
+    const double* const* d = up(src);
+    launch_scalars(d, (int)src.size(), sdev, st);
+    dev_d2h_async(shost, sdev, src.size() * sizeof(double), st);
+  }
+};
+
 struct Engine;
 struct BatchLaunch;
-static void davidson_lockstep(const std::vector<Engine*>& E, std::vector<DavState>& D, BatchLaunch* bl);
+static void davidson_lockstep(const std::vector<Engine*>& E, std::vector<DavState>& D, BatchLaunch* bl,
+                              Staging& sg);
 
 struct Engine {
   Problem P;
@@ -1468,6 +1582,15 @@ struct Engine {
   int64_t n_pass1 = 0, n_pass2 = 0;
   double t_sigma32 = 0, f_sigma32 = 0;
   int64_t n_sigma32 = 0;
+  // host wall seconds of the parts of a micro-iteration outside Davidson
+  enum { PH_ENLARGE, PH_TASKS, PH_PLAN, PH_DIAG, PH_GUESS, PH_SVD, PH_RENORM, PH_N };
+  double t_phase[PH_N] = {};
+  struct PhaseTimer {
+    double& acc;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    explicit PhaseTimer(double& a) : acc(a) {}
+    ~PhaseTimer() { acc += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+  };
   // noise (section "Convergence scheme"): uniform, magnitude <= 0.5 gamma
   // w_disc of the previous left- or right-sweep, added before each decomposition
   double noise = 0.0;
@@ -1479,13 +1602,100 @@ struct Engine {
   // Davidson work buffers
   DBuf dV, dW, dHs, dsmall, dpartial, dx_, dax, dr, dt;
   double* hpin = nullptr;   // page-locked scalars read back after a stream sync
+  std::unique_ptr<Staging> stage;  // job arrays of this engine's own Davidson
   DevPool* pool = nullptr;  // the context's device-memory pool
   bool defer_p2 = false;    // prepare() leaves the accumulating pass unplanned
+  // Enlarged blocks kept from the previous pass (section "Sweeping"): while
+  // a left-to-right pass renews the left blocks, the right blocks are the
+  // ones the previous right-to-left pass built, so the enlargement of the
+  // right block at step i is the one that pass made at step i (and the
+  // other way round).  Entry i of each side holds the enlarged store, the
+  // generation of the block it came from and its enlarged basis.
+  struct EnlCache {
+    uint64_t src = 0;
+    Basis E;
+    std::unique_ptr<Store> st;
+    int64_t bytes = 0;
+  };
+  std::vector<EnlCache> cacheX, cacheY;
+  std::vector<std::pair<int, int>> cache_fifo;  // (side 0 = X / 1 = Y, site), oldest first
+  bool enl_cache_on = true;
 
   Engine() = default;
   Engine(const Engine&) = delete;
   Engine& operator=(const Engine&) = delete;
-  ~Engine() { host_free_pinned(hpin); }
+  ~Engine() {
+    clear_enl_cache();
+    stage.reset();
+    host_free_pinned(hpin);
+  }
+
+  void drop_cache_entry(EnlCache& c) {
+    if (c.st) g_enl_cache_bytes -= c.bytes;
+    c.st.reset();
+    c.bytes = 0;
+    c.src = 0;
+  }
+  void clear_enl_cache() {
+    for (auto& c : cacheX) drop_cache_entry(c);
+    for (auto& c : cacheY) drop_cache_entry(c);
+    cache_fifo.clear();
+  }
+  // keep an enlarged store for the next pass if the byte ceiling allows,
+  // giving up this engine's oldest entries first
+  void cache_put(int side, int site, uint64_t src, const Basis& E, std::unique_ptr<Store> st) {
+    if (!enl_cache_on || !st || site < 0) return;
+    auto& vec = side == 0 ? cacheX : cacheY;
+    if ((int)vec.size() < P.L) vec.resize(P.L);
+    drop_cache_entry(vec[site]);
+    const int64_t bytes = 8 * st->total;
+    const int64_t cap = enl_cache_budget();
+    size_t q = 0;
+    while (true) {
+      int64_t cur = g_enl_cache_bytes.load();
+      if (cur + bytes <= cap) {
+        if (g_enl_cache_bytes.compare_exchange_weak(cur, cur + bytes)) break;
+        continue;
+      }
+      // evict the oldest of this engine's entries
+      while (q < cache_fifo.size()) {
+        auto [sd, k] = cache_fifo[q++];
+        auto& v2 = sd == 0 ? cacheX : cacheY;
+        if (k < (int)v2.size() && v2[k].st) {
+          drop_cache_entry(v2[k]);
+          break;
+        }
+      }
+      if (q >= cache_fifo.size() && g_enl_cache_bytes.load() + bytes > cap) {
+        cache_fifo.erase(cache_fifo.begin(), cache_fifo.begin() + q);
+        return;  // does not fit
+      }
+    }
+    cache_fifo.erase(cache_fifo.begin(), cache_fifo.begin() + q);
+    EnlCache& c = vec[site];
+    c.src = src;
+    c.E.sec = E.sec;
+    c.E.dim = E.dim;
+    c.st = std::move(st);
+    c.bytes = bytes;
+    cache_fifo.push_back({side, site});
+  }
+  // the kept enlargement of block src for basis E, if there is one
+  std::unique_ptr<Store> cache_take(int side, int site, const Store& src, const Basis& E) {
+    auto& vec = side == 0 ? cacheX : cacheY;
+    if (site < 0 || site >= (int)vec.size() || !vec[site].st) return nullptr;
+    EnlCache& c = vec[site];
+    std::unique_ptr<Store> out;
+    if (c.src == src.gen && c.E.sec == E.sec && c.E.dim == E.dim) {
+      g_enl_cache_bytes -= c.bytes;
+      out = std::move(c.st);
+      c.bytes = 0;
+      c.src = 0;
+    } else {
+      drop_cache_entry(c);
+    }
+    return out;
+  }
 
   void check_target() const {
     if (P.N < 0) fail(-1, "target not set");
@@ -2082,6 +2292,8 @@ struct Engine {
 
   // Build left blocks 0..i and right blocks L..i+2 from the stored tensors.
   void build_blocks_from_tensors(int i) {
+    clear_enl_cache();
+    step = Step();
     Lb.clear();
     Rb.clear();
     Lb.resize(P.L + 1);
@@ -2117,13 +2329,24 @@ struct Engine {
     std::set<Sec> keep;
     for (auto& s : el0.sec)
       if (er0.find(s) >= 0) keep.insert(s);
+    // the finished step's enlarged blocks may serve the next pass
+    cache_put(0, step.site, step.genX, step.EX, std::move(step.X));
+    cache_put(1, step.site, step.genY, step.EY, std::move(step.Y));
     step = Step();
     step.i = i;
+    step.site = i;
     step.EX = left_enl(P, c, Lk.basis, &keep);
     step.EY = right_enl(P, c, Rk.basis, &keep);
+    step.genX = Lk.gen;
+    step.genY = Rk.gen;
     int64_t ne = 0;
-    step.X = enlarge(P, Lk, step.EX, true, st, &ne);
-    step.Y = enlarge(P, Rk, step.EY, false, st, &ne);
+    {
+      PhaseTimer pt(t_phase[PH_ENLARGE]);
+      step.X = cache_take(0, i, Lk, step.EX);
+      if (!step.X) step.X = enlarge(P, Lk, step.EX, true, st, &ne);
+      step.Y = cache_take(1, i, Rk, step.EY);
+      if (!step.Y) step.Y = enlarge(P, Rk, step.EY, false, st, &ne);
+    }
     // psi layout
     step.psi.sec = step.EX.sec;
     step.n = 0;
@@ -2139,9 +2362,15 @@ struct Engine {
     step.diag.alloc((size_t)std::max<int64_t>(step.n, 1));
     build_sigma_tasks();
     max_enl_bytes = std::max(max_enl_bytes, 8.0 * (double)(step.X->total + step.Y->total));
-    build_diag();
-    build_guess();
-    dev_sync(st);
+    {
+      PhaseTimer pt(t_phase[PH_DIAG]);
+      build_diag();
+    }
+    {
+      PhaseTimer pt(t_phase[PH_GUESS]);
+      build_guess();
+      dev_sync(st);
+    }
     t_block += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
 
@@ -2190,6 +2419,7 @@ struct Engine {
   }
 
   void build_sigma_tasks() {
+    auto tt0 = std::chrono::steady_clock::now();
     Store &X = *step.X, &Y = *step.Y;
     const int ns = (int)step.psi.sec.size();
     std::vector<OutBlk> outs(ns);
@@ -2304,6 +2534,8 @@ struct Engine {
     }
     for (auto& [s, o] : touched) bytes += 8.0 * (s == 0 ? X.lay(o).nnz : Y.lay(o).nnz);
     bytes += 16.0 * step.n;
+    t_phase[PH_TASKS] += std::chrono::duration<double>(std::chrono::steady_clock::now() - tt0).count();
+    PhaseTimer pt(t_phase[PH_PLAN]);
     build_two_pass(outs, trs, step.plan, st, true, defer_p2 ? &step.g2 : nullptr);
     step.p2_pending = defer_p2;
     step.trs = trs;
@@ -2638,29 +2870,27 @@ struct Engine {
   // ---- Davidson (Davidson 1975; section "The effective Hamiltonian equation")
   // tol: residual-norm tolerance; f32: sigma with FP32 operands.
   double davidson(double* xres, int* iters, bool* conv, double tol, bool f32) {
+    if (!stage) stage = std::make_unique<Staging>(st, pool);
+    stage->st = st;
     std::vector<Engine*> E{this};
     std::vector<DavState> D(1);
     D[0].xres = xres;
     D[0].tol = tol;
     D[0].f32 = f32;
-    davidson_lockstep(E, D, nullptr);
+    davidson_lockstep(E, D, nullptr, *stage);
     *iters = D[0].it;
     *conv = D[0].conv;
     return D[0].theta;
   }
 
-  // The phases of one solve.  Each only enqueues work on the stream; the
-  // scalars the host decides on arrive in hpin after the stream sync that
-  // follows dav_start, dav_iter_a and dav_iter_b.  Small-matrix layout in
-  // dsmall: eigenvalues, eigenvectors (64 x 64), coefficients, norms.
+  // Work buffers of one solve.  Small-matrix layout in dsmall: eigenvalues,
+  // eigenvectors (64 x 64), coefficients, norms.
   double* dav_evals() { return dsmall.p; }
   double* dav_evecs() { return dsmall.p + 64; }
   double* dav_coef() { return dsmall.p + 64 + 64 * 64; }
   double* dav_nrm() { return dav_coef() + 64; }
   double* dav_nrm2() { return dav_coef() + 65; }
-
-  // |guess|^2 of the guess in step.in
-  void dav_start(DavState& d) {
+  void dav_alloc(DavState& d) {
     const int64_t n = step.n;
     d.ms = std::max(2, std::min(dav_max_sub, 64));
     d.k = 0;
@@ -2678,123 +2908,45 @@ struct Engine {
     dax.ensure(n);
     dr.ensure(n);
     dt.ensure(n);
-    if (!hpin) hpin = (double*)host_alloc_pinned(8 * sizeof(double));
-    dev_d2d(dV.p, step.in.p, (size_t)n * 8, st);
-    launch_dots(dV.p, n, 1, dV.p, n, dav_nrm(), dpartial.p, st);
-    dev_d2h_async(hpin, dav_nrm(), 8, st);
-  }
-  // V_0 = guess / |guess| (a zero guess becomes the constant vector); the
-  // sigma of V_0 follows
-  void dav_guess(DavState&) {
-    const int64_t n = step.n;
-    if (!(hpin[0] > 0)) {
-      std::vector<double> one(n, 1.0);
-      dev_h2d(dV.p, one.data(), (size_t)n * 8, st);
-      launch_dots(dV.p, n, 1, dV.p, n, dav_nrm(), dpartial.p, st);
-    }
-    launch_normalize(dV.p, dav_nrm(), n, st);
   }
   // vector whose sigma is due, and where it goes
   double* dav_x(const DavState& d) { return dV.p + (int64_t)d.k * step.n; }
   double* dav_y(const DavState& d) { return dW.p + (int64_t)d.k * step.n; }
-  // after the sigma of V_k: row k of the projected matrix, V_j . W_k (j <= k)
-  void dav_absorb(DavState& d) {
+  // a zero guess becomes the constant vector (rare; synchronous)
+  void dav_zero_guess() {
     const int64_t n = step.n;
-    launch_dots(dV.p, n, d.k + 1, dW.p + (int64_t)d.k * n, n, dHs.p + (int64_t)d.k * d.ms, dpartial.p, st);
-    ++d.k;
+    std::vector<double> one(n, 1.0);
+    dev_h2d(dV.p, one.data(), (size_t)n * 8, st);
+    launch_dots(dV.p, n, 1, dV.p, n, dav_nrm(), dpartial.p, st);
   }
-  // Ritz pair of the subspace and its residual norm
-  void dav_iter_a(DavState& d) {
+  // the preconditioned residual collapsed: orthogonalise the residual itself;
+  // false if that vanishes too (rare; synchronous)
+  bool dav_residual_direction(DavState& d) {
     const int64_t n = step.n;
-    if (n == 1) {
-      dev_d2h_async(hpin, dHs.p, 8, st);
-      return;
-    }
-    launch_syev_small(dHs.p, d.k, d.ms, dav_evals(), dav_evecs(), st);
-    launch_combo_vec(dV.p, n, d.k, dav_evecs(), 1.0, n, dx_.p, 0.0, st);  // x = V s
-    launch_combo_vec(dW.p, n, d.k, dav_evecs(), 1.0, n, dax.p, 0.0, st);  // ax = W s
-    launch_residual(dax.p, dx_.p, dav_evals(), n, dr.p, st);
-    launch_dots(dr.p, n, 1, dr.p, n, dav_nrm(), dpartial.p, st);
-    dev_d2h_async(hpin, dav_evals(), 8, st);
-    dev_d2h_async(hpin + 1, dav_nrm(), 8, st);
-  }
-  // convergence test; otherwise the preconditioned, orthogonalised residual
-  void dav_iter_b(DavState& d) {
-    const int64_t n = step.n;
-    d.theta = hpin[0];
-    if (n == 1) {
-      dev_d2d(d.xres, dV.p, 8, st);
-      d.it = 1;
-      d.conv = d.done = true;
-      return;
-    }
-    const double rn = std::sqrt(std::max(0.0, hpin[1]));
-    if (rn <= d.tol) {
-      d.conv = true;
-      dav_finish(d);
-      return;
-    }
-    // FP32 sigma has a residual floor set by its rounding (observed near
-    // 10 eps_32 |theta|): close to it, stop when the residual has not
-    // improved by 10 % for four iterations
-    if (d.f32 && rn < 100.0 * 6e-8 * std::max(1.0, std::fabs(d.theta))) {
-      if (rn < 0.9 * d.rbest) {
-        d.rbest = rn;
-        d.stall = 0;
-      } else if (++d.stall >= 4) {
-        d.conv = true;
-        dav_finish(d);
-        return;
-      }
-    }
-    launch_precond(dr.p, step.diag.p, dav_evals(), n, dt.p, st);
+    dev_d2d(dt.p, dr.p, (size_t)n * 8, st);
     for (int pass = 0; pass < 2; ++pass) {
       launch_dots(dV.p, n, d.k, dt.p, n, dav_coef(), dpartial.p, st);
       launch_combo_vec(dV.p, n, d.k, dav_coef(), -1.0, n, dt.p, 1.0, st);
     }
     launch_dots(dt.p, n, 1, dt.p, n, dav_nrm2(), dpartial.p, st);
-    dev_d2h_async(hpin + 2, dav_nrm2(), 8, st);
+    double tn;
+    dev_d2h(&tn, dav_nrm2(), 8, st);
+    return tn > 1e-28;
   }
-  // the new direction into V_k (restarting from the Ritz vector when full)
-  void dav_iter_c(DavState& d) {
+  // subspace full: restart from the current Ritz vector, then the new
+  // direction (already normalised) is orthogonalised against it
+  void dav_restart(DavState& d) {
     const int64_t n = step.n;
-    double tn = hpin[2];
-    if (!(tn > 1e-28)) {  // preconditioned residual collapsed: use the residual itself
-      dev_d2d(dt.p, dr.p, (size_t)n * 8, st);
-      for (int pass = 0; pass < 2; ++pass) {
-        launch_dots(dV.p, n, d.k, dt.p, n, dav_coef(), dpartial.p, st);
-        launch_combo_vec(dV.p, n, d.k, dav_coef(), -1.0, n, dt.p, 1.0, st);
-      }
-      launch_dots(dt.p, n, 1, dt.p, n, dav_nrm2(), dpartial.p, st);
-      dev_d2h(&tn, dav_nrm2(), 8, st);
-      if (!(tn > 1e-28)) {
-        d.conv = true;
-        dav_finish(d);
-        return;
-      }
-    }
+    dev_d2d(dV.p, dx_.p, (size_t)n * 8, st);
+    dev_d2d(dW.p, dax.p, (size_t)n * 8, st);
+    launch_dots(dV.p, n, 1, dV.p, n, dav_nrm(), dpartial.p, st);
+    // x is unit (orthonormal basis, unit Ritz coefficients); W follows x
+    launch_dots(dV.p, n, 1, dW.p, n, dHs.p, dpartial.p, st);
+    d.k = 1;
+    launch_dots(dV.p, n, 1, dt.p, n, dav_coef(), dpartial.p, st);
+    launch_combo_vec(dV.p, n, 1, dav_coef(), -1.0, n, dt.p, 1.0, st);
+    launch_dots(dt.p, n, 1, dt.p, n, dav_nrm2(), dpartial.p, st);
     launch_normalize(dt.p, dav_nrm2(), n, st);
-    if (d.k >= d.ms) {  // restart with the current Ritz vector
-      dev_d2d(dV.p, dx_.p, (size_t)n * 8, st);
-      dev_d2d(dW.p, dax.p, (size_t)n * 8, st);
-      launch_dots(dV.p, n, 1, dV.p, n, dav_nrm(), dpartial.p, st);
-      // x is unit (orthonormal basis, unit Ritz coefficients); W follows x
-      launch_dots(dV.p, n, 1, dW.p, n, dHs.p, dpartial.p, st);
-      d.k = 1;
-      launch_dots(dV.p, n, 1, dt.p, n, dav_coef(), dpartial.p, st);
-      launch_combo_vec(dV.p, n, 1, dav_coef(), -1.0, n, dt.p, 1.0, st);
-      launch_dots(dt.p, n, 1, dt.p, n, dav_nrm2(), dpartial.p, st);
-      launch_normalize(dt.p, dav_nrm2(), n, st);
-    }
-    dev_d2d(dV.p + (int64_t)d.k * n, dt.p, (size_t)n * 8, st);
-  }
-  // normalised Ritz vector into xres
-  void dav_finish(DavState& d) {
-    const int64_t n = step.n;
-    launch_dots(dx_.p, n, 1, dx_.p, n, dav_nrm(), dpartial.p, st);
-    dev_d2d(d.xres, dx_.p, (size_t)n * 8, st);
-    launch_normalize(d.xres, dav_nrm(), n, st);
-    d.done = true;
   }
 
   // ---- SVD and truncation (section "The reduced two-site object"): SVD per
@@ -2993,7 +3145,11 @@ struct Engine {
       dev_sync(st);
     }
     Split sp;
-    svd_truncate(x, D, sp);
+    {
+      PhaseTimer pt(t_phase[PH_SVD]);
+      svd_truncate(x, D, sp);
+    }
+    PhaseTimer pt(t_phase[PH_RENORM]);
     wdisc_sweep = std::max(wdisc_sweep, sp.wd);
     wd_pass = std::max(wd_pass, sp.wd);
     const int c = i + 1;
@@ -3121,26 +3277,29 @@ struct Engine {
 // ---------------------------------------------------------------------------
 struct BatchLaunch {
   Stream st = nullptr;
-  DevPool* pool = nullptr;  // holds the descriptor buffer
-  void* host = nullptr;     // page-locked staging of the descriptors
-  void* dev = nullptr;
-  size_t cap = 0;
-  void* uploaded = nullptr;  // event after the last upload from `host`
+  Staging stage;             // job arrays and descriptors of the shared launches
+  std::vector<Stream> priv;  // one stream per engine for its own phases
   // timing: event pairs around the shared launches, read at the end
   std::vector<std::pair<void*, void*>> ev64, ev32;
   double f64 = 0.0, f32 = 0.0;  // algorithmic flops of the shared launches
   int64_t n64 = 0, n32 = 0;     // shared launches (one per pass pair)
+  // host wall time of the phases of the batched micro-iterations: step
+  // preparation, Davidson, Rayleigh quotients, decomposition and update
+  double w_prepare = 0.0, w_davidson = 0.0, w_rayleigh = 0.0, w_finish = 0.0;
 
-  BatchLaunch(Stream s, DevPool* p) : st(s), pool(p) {}
+  BatchLaunch(Stream s, DevPool* p, size_t n) : st(s), stage(s, p) {
+    for (size_t k = 0; k < n; ++k) priv.push_back(dev_stream_create());
+  }
   BatchLaunch(const BatchLaunch&) = delete;
   BatchLaunch& operator=(const BatchLaunch&) = delete;
   ~BatchLaunch() {
-    if (uploaded) dev_event_free(uploaded);
+    try {
+      dev_sync(st);
+    } catch (...) {
+    }
+    for (Stream s : priv) dev_stream_destroy(s);
     for (auto& e : ev64) dev_event_free(e.first), dev_event_free(e.second);
     for (auto& e : ev32) dev_event_free(e.first), dev_event_free(e.second);
-    host_free_pinned(host);
-    PoolBind b(pool);
-    if (dev) dev_free(dev);
   }
   // seconds in the shared launches (synchronises)
   void times(double& t64, double& t32) {
@@ -3149,22 +3308,16 @@ struct BatchLaunch {
     for (auto& e : ev32) t32 += dev_event_elapsed(e.first, e.second);
   }
 
-  // y_e = H_eff(e) x_e for every engine e, the GEMM passes shared
-  void sigma(const std::vector<Engine*>& E, const std::vector<const double*>& x, const std::vector<double*>& y,
-             bool use32) {
-    const size_t n = E.size();
-    for (size_t k = 0; k < n; ++k) {
-      PoolBind b(E[k]->pool);
-      E[k]->sigma_in(x[k], use32);
-    }
-    // descriptors: pass-1 tiles, pass-2 ranges, reductions of cut tiles
+  // The GEMM passes of the sigma of every engine, shared: each engine's
+  // step.in (FP64 or its FP32 mirror) must be in place and its output zeroed.
+  void gemm_passes(const std::vector<Engine*>& E, bool use32) {
     std::vector<GSeg> s1, s2, sr;
     std::vector<int> b1, b2, br;
     int nw1 = 0, nw2 = 0, nr = 0;
     bool stream2 = true;
     double fl = 0.0;
-    for (size_t k = 0; k < n; ++k) {
-      const Step& S = E[k]->step;
+    for (Engine* e : E) {
+      const Step& S = e->step;
       const GemmList::Plan& p1 = use32 ? S.q1 : S.plan.p1;
       const GemmList::Plan& p2 = use32 ? S.q2 : S.plan.p2;
       if (p1.stream || p1.nreds != 0) fail(-1, "internal: first pass must be one tile per workgroup");
@@ -3186,135 +3339,387 @@ struct BatchLaunch {
       }
       fl += S.flops;
     }
-    const size_t nseg = s1.size() + s2.size() + sr.size();
-    const size_t bytes = nseg * sizeof(GSeg) + nseg * sizeof(int);
-    if (bytes > cap) {
-      if (uploaded) dev_event_wait(uploaded);
-      host_free_pinned(host);
-      host = nullptr;
-      {
-        PoolBind b(pool);
-        if (dev) dev_free(dev);
-        dev = nullptr;
-        cap = std::max<size_t>(bytes, 4096);
-        dev = dev_alloc(cap);
-      }
-      host = host_alloc_pinned(cap);
-    } else if (uploaded) {
-      dev_event_wait(uploaded);  // the previous upload has left the staging buffer
-    }
-    char* h = (char*)host;
-    GSeg* hs = (GSeg*)h;
-    int* hb = (int*)(h + nseg * sizeof(GSeg));
-    size_t o = 0;
-    for (auto* v : {&s1, &s2, &sr})
-      for (const GSeg& g : *v) hs[o++] = g;
-    o = 0;
-    for (auto* v : {&b1, &b2, &br})
-      for (int q : *v) hb[o++] = q;
-    dev_h2d_async(dev, host, bytes, st);
-    if (uploaded) dev_event_free(uploaded);
-    uploaded = dev_event_record(st);
-    const GSeg* d = (const GSeg*)dev;
-    const int* db = (const int*)((char*)dev + nseg * sizeof(GSeg));
-    void* e0 = dev_event_record(st);
-    launch_gemm_seg(d, db, (int)s1.size(), nw1, false, use32, st);
-    launch_gemm_seg(d + s1.size(), db + s1.size(), (int)s2.size(), nw2, stream2, use32, st);
-    launch_reduce_seg(d + s1.size() + s2.size(), db + s1.size() + s2.size(), (int)sr.size(), nr, use32, st);
-    void* e1 = dev_event_record(st);
-    (use32 ? ev32 : ev64).push_back({e0, e1});
+    const GSeg* d1 = stage.up(s1);
+    const GSeg* d2 = stage.up(s2);
+    const GSeg* dr = stage.up(sr);
+    const int* e1 = stage.up(b1);
+    const int* e2 = stage.up(b2);
+    const int* er = stage.up(br);
+    void* t0 = dev_event_record(st);
+    launch_gemm_seg(d1, e1, (int)s1.size(), nw1, false, use32, st);
+    launch_gemm_seg(d2, e2, (int)s2.size(), nw2, stream2, use32, st);
+    launch_reduce_seg(dr, er, (int)sr.size(), nr, use32, st);
+    void* t1 = dev_event_record(st);
+    (use32 ? ev32 : ev64).push_back({t0, t1});
     (use32 ? f32 : f64) += fl;
     ++(use32 ? n32 : n64);
-    for (size_t k = 0; k < n; ++k) {
-      PoolBind b(E[k]->pool);
-      E[k]->sigma_out(y[k], use32);
+  }
+
+  // y_e = H_eff(e) x_e for every engine e (the single-engine operations
+  // around the GEMM passes as job lists)
+  void sigma(const std::vector<Engine*>& E, const std::vector<const double*>& x, const std::vector<double*>& y,
+             bool use32);
+};
+
+// fn(j) for j < n on up to `threads` host threads (the calling one
+// included); the first exception is rethrown after all have stopped
+template <class F>
+static void parallel_for(size_t n, int threads, F&& fn) {
+  const int nt = (int)std::min<size_t>(n, (size_t)std::max(1, threads));
+  if (nt <= 1) {
+    for (size_t j = 0; j < n; ++j) fn(j);
+    return;
+  }
+  std::atomic<size_t> next{0};
+  std::atomic<bool> stop{false};
+  std::exception_ptr first;
+  std::mutex mu;
+  auto work = [&]() {
+    for (size_t j; !stop.load() && (j = next.fetch_add(1)) < n;) {
+      try {
+        fn(j);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!first) first = std::current_exception();
+        stop = true;
+      }
     }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (auto& t : pool) t.join();
+  if (first) std::rethrow_exception(first);
+}
+
+// host threads for the per-engine parts of a batched micro-iteration
+// (preparation, decomposition and update); the engines touch disjoint
+// memory and keep their own stream order
+static const int BATCH_HOST_THREADS = 16;
+
+// For one per-engine phase the engine works on a stream of its own, so that
+// its waits do not include the other engines' work: the private stream
+// first follows the shared one, and the shared one follows the private
+// stream at the end; the engine's work thus stays in one total order.
+struct OwnStream {
+  Engine& e;
+  Stream shared;
+  OwnStream(Engine& en, Stream priv) : e(en), shared(en.st) {
+    dev_stream_order(priv, shared);
+    e.st = priv;
+  }
+  ~OwnStream() {
+    try {
+      dev_stream_order(shared, e.st);
+    } catch (...) {
+    }
+    e.st = shared;
   }
 };
 
-// sigma of the due vector of every listed solve, then its row of the
-// projected matrix
-static void dav_sigma(const std::vector<Engine*>& E, std::vector<DavState>& D, const std::vector<size_t>& idx,
-                      BatchLaunch* bl) {
-  if (idx.empty()) return;
-  if (!bl || idx.size() == 1) {
-    for (size_t k : idx) {
-      PoolBind b(E[k]->pool);
-      E[k]->sigma_vec(E[k]->dav_x(D[k]), E[k]->dav_y(D[k]), D[k].f32);
-    }
-  } else {
-    std::vector<Engine*> e;
-    std::vector<const double*> x;
-    std::vector<double*> y;
-    bool use32 = D[idx[0]].f32;
-    for (size_t k : idx) {
-      if (D[k].f32 != use32) fail(-1, "internal: one shared launch has one precision");
-      e.push_back(E[k]);
-      x.push_back(E[k]->dav_x(D[k]));
-      y.push_back(E[k]->dav_y(D[k]));
-    }
-    bl->sigma(e, x, y, use32);
+// Job lists of one launch of the batched Davidson helpers
+struct EwList {
+  std::vector<EwJob> v;
+  int64_t maxn = 0;
+  void add(int kind, const double* a, const double* b, const double* sc, double* y, int64_t n) {
+    v.push_back({a, b, sc, y, n, kind});
+    maxn = std::max(maxn, n);
   }
-  for (size_t k : idx) {
-    PoolBind b(E[k]->pool);
-    E[k]->dav_absorb(D[k]);
+  void run(Staging& sg, Stream st) {
+    if (!v.empty()) launch_ew_batch(sg.up(v), (int)v.size(), maxn, st);
+    v.clear();
+    maxn = 0;
   }
+};
+struct DotList {
+  std::vector<DotJob> v;
+  int maxk = 0;
+  void add(const double* V, int64_t ldv, int k, const double* x, int64_t n, double* out, double* part) {
+    v.push_back({V, x, out, part, ldv, n, k});
+    maxk = std::max(maxk, k);
+  }
+  void run(Staging& sg, Stream st) {
+    if (!v.empty()) launch_dots_batch(sg.up(v), (int)v.size(), maxk, st);
+    v.clear();
+    maxk = 0;
+  }
+};
+struct ComboList {
+  std::vector<ComboJob> v;
+  int64_t maxn = 0;
+  void add(const double* V, int64_t ldv, int k, const double* coef, double alpha, int64_t n, double* y, double beta) {
+    v.push_back({V, coef, y, ldv, n, k, alpha, beta});
+    maxn = std::max(maxn, n);
+  }
+  void run(Staging& sg, Stream st) {
+    if (!v.empty()) launch_combo_batch(sg.up(v), (int)v.size(), maxn, st);
+    v.clear();
+    maxn = 0;
+  }
+};
+
+void BatchLaunch::sigma(const std::vector<Engine*>& E, const std::vector<const double*>& x,
+                        const std::vector<double*>& y, bool use32) {
+  EwList ew;
+  for (size_t k = 0; k < E.size(); ++k) {
+    Engine& e = *E[k];
+    if (e.step.p2_pending) fail(-1, "internal: sigma plan incomplete");
+    const int64_t n = e.step.n;
+    if (use32) {
+      {
+        PoolBind b(e.pool);
+        e.ensure_f32();
+      }
+      ew.add(EW_D2F, x[k], nullptr, nullptr, e.step.in32.p, n);
+      ew.add(EW_ZERO, nullptr, nullptr, nullptr, e.step.out32.p, (int64_t)e.step.out32.n);
+    } else {
+      ew.add(EW_COPY, x[k], nullptr, nullptr, e.step.in.p, n);
+      ew.add(EW_ZERO, nullptr, nullptr, nullptr, e.step.out.p, std::max<int64_t>(n, 1));
+    }
+  }
+  ew.run(stage, st);
+  gemm_passes(E, use32);
+  for (size_t k = 0; k < E.size(); ++k) {
+    Engine& e = *E[k];
+    if (use32)
+      ew.add(EW_F2D, e.step.out32.p, nullptr, nullptr, y[k], e.step.n);
+    else
+      ew.add(EW_COPY, e.step.out.p, nullptr, nullptr, y[k], e.step.n);
+  }
+  ew.run(stage, st);
 }
 
-// Davidson solves of engines that share one stream, phase by phase; with
-// bl the sigma products of each iteration share their launches.
-static void davidson_lockstep(const std::vector<Engine*>& E, std::vector<DavState>& D, BatchLaunch* bl) {
-  const size_t n = E.size();
-  if (n == 0) return;
+// Davidson solves of engines that share one stream, in lockstep.  Every
+// stage is one launch over all solves that take part in it (the helpers'
+// job-list forms, each job with the arithmetic of the single-solve kernel),
+// and the host waits for the stream twice per iteration, once for all
+// solves.  With bl, the sigma products of an iteration share their GEMM
+// launches; without it (one engine) each engine runs its own sigma.
+static void davidson_lockstep(const std::vector<Engine*>& E, std::vector<DavState>& D, BatchLaunch* bl,
+                              Staging& sg) {
+  const size_t ne = E.size();
+  if (ne == 0) return;
   const Stream st = E[0]->st;
-  std::vector<size_t> all(n), act, act2;
-  for (size_t k = 0; k < n; ++k) {
+  sg.st = st;
+  sg.reset();
+  EwList ew;
+  DotList dots;
+  ComboList cb;
+  std::vector<SyevJob> sy;
+  std::vector<const double*> sc;
+  auto N = [&](size_t k) { return E[k]->step.n; };
+  auto sync = [&]() {
+    dev_sync(st);
+    sg.reset();
+  };
+  // sigma of V_k into W_k, then row k of the projected matrix
+  auto sigma_round = [&](const std::vector<size_t>& idx) {
+    if (idx.empty()) return;
+    if (!bl || idx.size() == 1) {
+      for (size_t k : idx) {
+        PoolBind b(E[k]->pool);
+        E[k]->sigma_vec(E[k]->dav_x(D[k]), E[k]->dav_y(D[k]), D[k].f32);
+      }
+    } else {
+      std::vector<Engine*> e;
+      std::vector<const double*> x;
+      std::vector<double*> y;
+      const bool use32 = D[idx[0]].f32;
+      for (size_t k : idx) {
+        if (D[k].f32 != use32) fail(-1, "internal: one shared launch has one precision");
+        e.push_back(E[k]);
+        x.push_back(E[k]->dav_x(D[k]));
+        y.push_back(E[k]->dav_y(D[k]));
+      }
+      bl->sigma(e, x, y, use32);
+    }
+    for (size_t k : idx) {
+      Engine& g = *E[k];
+      const int64_t n = N(k);
+      dots.add(g.dV.p, n, D[k].k + 1, g.dW.p + (int64_t)D[k].k * n, n, g.dHs.p + (int64_t)D[k].k * D[k].ms,
+               g.dpartial.p);
+    }
+    dots.run(sg, st);
+    for (size_t k : idx) ++D[k].k;
+  };
+  // normalised Ritz vector into xres
+  auto finish = [&](const std::vector<size_t>& idx) {
+    if (idx.empty()) return;
+    for (size_t k : idx) {
+      Engine& g = *E[k];
+      dots.add(g.dx_.p, N(k), 1, g.dx_.p, N(k), g.dav_nrm(), g.dpartial.p);
+      ew.add(EW_COPY, g.dx_.p, nullptr, nullptr, D[k].xres, N(k));
+    }
+    dots.run(sg, st);
+    ew.run(sg, st);
+    for (size_t k : idx) {
+      ew.add(EW_NORMALIZE, nullptr, nullptr, E[k]->dav_nrm(), D[k].xres, N(k));
+      D[k].done = true;
+    }
+    ew.run(sg, st);
+  };
+
+  std::vector<size_t> all(ne);
+  for (size_t k = 0; k < ne; ++k) {
     all[k] = k;
     PoolBind b(E[k]->pool);
-    E[k]->dav_start(D[k]);
+    E[k]->dav_alloc(D[k]);
   }
-  dev_sync(st);
-  for (size_t k = 0; k < n; ++k) {
-    PoolBind b(E[k]->pool);
-    E[k]->dav_guess(D[k]);
+  // V_0 = guess / |guess| (the guess is in step.in)
+  for (size_t k : all) ew.add(EW_COPY, E[k]->step.in.p, nullptr, nullptr, E[k]->dV.p, N(k));
+  ew.run(sg, st);
+  for (size_t k : all) dots.add(E[k]->dV.p, N(k), 1, E[k]->dV.p, N(k), E[k]->dav_nrm(), E[k]->dpartial.p);
+  dots.run(sg, st);
+  sc.clear();
+  for (size_t k : all) sc.push_back(E[k]->dav_nrm());
+  sg.fetch(sc);
+  sync();
+  {
+    std::vector<double> h0(sg.shost, sg.shost + ne);
+    for (size_t k : all)
+      if (!(h0[k] > 0)) {
+        PoolBind b(E[k]->pool);
+        E[k]->dav_zero_guess();
+      }
   }
-  dav_sigma(E, D, all, bl);
+  for (size_t k : all) ew.add(EW_NORMALIZE, nullptr, nullptr, E[k]->dav_nrm(), E[k]->dV.p, N(k));
+  ew.run(sg, st);
+  sigma_round(all);
+
+  std::vector<size_t> act, cont, fin, next;
   while (true) {
     act.clear();
-    for (size_t k = 0; k < n; ++k) {
+    fin.clear();
+    for (size_t k = 0; k < ne; ++k) {
       if (D[k].done) continue;
       if (D[k].it > E[k]->dav_max_iter) {  // out of iterations
         D[k].it = E[k]->dav_max_iter;
-        PoolBind b(E[k]->pool);
-        E[k]->dav_finish(D[k]);
+        fin.push_back(k);
         continue;
       }
       act.push_back(k);
     }
+    finish(fin);
     if (act.empty()) break;
+    // Ritz pair of the subspace and its residual norm
+    sy.clear();
+    sc.clear();
     for (size_t k : act) {
-      PoolBind b(E[k]->pool);
-      E[k]->dav_iter_a(D[k]);
+      Engine& g = *E[k];
+      if (N(k) == 1) continue;
+      sy.push_back({g.dHs.p, g.dav_evals(), g.dav_evecs(), D[k].k, D[k].ms});
+      cb.add(g.dV.p, N(k), D[k].k, g.dav_evecs(), 1.0, N(k), g.dx_.p, 0.0);  // x = V s
+      cb.add(g.dW.p, N(k), D[k].k, g.dav_evecs(), 1.0, N(k), g.dax.p, 0.0);  // ax = W s
+      ew.add(EW_RESIDUAL, g.dax.p, g.dx_.p, g.dav_evals(), g.dr.p, N(k));
+      dots.add(g.dr.p, N(k), 1, g.dr.p, N(k), g.dav_nrm(), g.dpartial.p);
     }
-    dev_sync(st);
-    act2.clear();
+    if (!sy.empty()) launch_syev_batch(sg.up(sy), (int)sy.size(), st);
+    cb.run(sg, st);
+    ew.run(sg, st);
+    dots.run(sg, st);
     for (size_t k : act) {
-      PoolBind b(E[k]->pool);
-      E[k]->dav_iter_b(D[k]);
-      if (!D[k].done) act2.push_back(k);
+      if (N(k) == 1) {
+        sc.push_back(E[k]->dHs.p);
+        sc.push_back(E[k]->dHs.p);
+      } else {
+        sc.push_back(E[k]->dav_evals());
+        sc.push_back(E[k]->dav_nrm());
+      }
     }
-    if (act2.empty()) continue;
-    dev_sync(st);
-    act.clear();
-    for (size_t k : act2) {
-      PoolBind b(E[k]->pool);
-      E[k]->dav_iter_c(D[k]);
-      if (!D[k].done) act.push_back(k);
+    sg.fetch(sc);
+    sync();
+    // convergence test; otherwise the preconditioned, orthogonalised residual
+    cont.clear();
+    fin.clear();
+    for (size_t j = 0; j < act.size(); ++j) {
+      const size_t k = act[j];
+      DavState& d = D[k];
+      d.theta = sg.shost[2 * j];
+      if (N(k) == 1) {
+        ew.add(EW_COPY, E[k]->dV.p, nullptr, nullptr, d.xres, 1);
+        d.it = 1;
+        d.conv = d.done = true;
+        continue;
+      }
+      const double rn = std::sqrt(std::max(0.0, sg.shost[2 * j + 1]));
+      if (rn <= d.tol) {
+        d.conv = true;
+        fin.push_back(k);
+        continue;
+      }
+      // FP32 sigma has a residual floor set by its rounding (observed near
+      // 10 eps_32 |theta|): close to it, stop when the residual has not
+      // improved by 10 % for four iterations
+      if (d.f32 && rn < 100.0 * 6e-8 * std::max(1.0, std::fabs(d.theta))) {
+        if (rn < 0.9 * d.rbest) {
+          d.rbest = rn;
+          d.stall = 0;
+        } else if (++d.stall >= 4) {
+          d.conv = true;
+          fin.push_back(k);
+          continue;
+        }
+      }
+      cont.push_back(k);
     }
-    dav_sigma(E, D, act, bl);
-    for (size_t k : act) ++D[k].it;
+    ew.run(sg, st);  // the one-element copies
+    finish(fin);
+    if (cont.empty()) continue;
+    for (size_t k : cont) {
+      Engine& g = *E[k];
+      ew.add(EW_PRECOND, g.dr.p, g.step.diag.p, g.dav_evals(), g.dt.p, N(k));
+    }
+    ew.run(sg, st);
+    for (int pass = 0; pass < 2; ++pass) {
+      for (size_t k : cont) {
+        Engine& g = *E[k];
+        dots.add(g.dV.p, N(k), D[k].k, g.dt.p, N(k), g.dav_coef(), g.dpartial.p);
+        cb.add(g.dV.p, N(k), D[k].k, g.dav_coef(), -1.0, N(k), g.dt.p, 1.0);
+      }
+      dots.run(sg, st);
+      cb.run(sg, st);
+    }
+    sc.clear();
+    for (size_t k : cont) {
+      Engine& g = *E[k];
+      dots.add(g.dt.p, N(k), 1, g.dt.p, N(k), g.dav_nrm2(), g.dpartial.p);
+      sc.push_back(g.dav_nrm2());
+    }
+    dots.run(sg, st);
+    sg.fetch(sc);
+    sync();
+    // the new direction into V_k (restarting from the Ritz vector when full)
+    next.clear();
+    fin.clear();
+    {
+      std::vector<double> tn(sg.shost, sg.shost + cont.size());
+      for (size_t j = 0; j < cont.size(); ++j) {
+        const size_t k = cont[j];
+        if (!(tn[j] > 1e-28)) {  // preconditioned residual collapsed
+          PoolBind b(E[k]->pool);
+          if (!E[k]->dav_residual_direction(D[k])) {
+            D[k].conv = true;
+            fin.push_back(k);
+            continue;
+          }
+        }
+        next.push_back(k);
+      }
+    }
+    finish(fin);
+    for (size_t k : next) ew.add(EW_NORMALIZE, nullptr, nullptr, E[k]->dav_nrm2(), E[k]->dt.p, N(k));
+    ew.run(sg, st);
+    for (size_t k : next)
+      if (D[k].k >= D[k].ms) {
+        PoolBind b(E[k]->pool);
+        E[k]->dav_restart(D[k]);
+      }
+    for (size_t k : next) ew.add(EW_COPY, E[k]->dt.p, nullptr, nullptr, E[k]->dav_x(D[k]), N(k));
+    ew.run(sg, st);
+    sigma_round(next);
+    for (size_t k : next) ++D[k].it;
   }
-  dev_sync(st);
+  sync();
 }
 
 // One sweep (left-to-right then right-to-left pass; section "Sweeping") of
@@ -3357,9 +3762,17 @@ static bool batch_sweep(const std::vector<Engine*>& E, const std::vector<int>& D
     }
     const size_t na = ea.size();
     std::vector<DBuf> xb(na);
-    for (size_t j = 0; j < na; ++j) {
+    auto clock = std::chrono::steady_clock::now();
+    auto lap = [&clock]() {
+      const auto t = std::chrono::steady_clock::now();
+      const double d = std::chrono::duration<double>(t - clock).count();
+      clock = t;
+      return d;
+    };
+    parallel_for(na, BATCH_HOST_THREADS, [&](size_t j) {
       Engine& e = *ea[j];
       PoolBind b(e.pool);
+      OwnStream os(e, bl.priv[ka[j]]);
       struct Defer {
         Engine& e;
         ~Defer() { e.defer_p2 = false; }
@@ -3367,7 +3780,7 @@ static bool batch_sweep(const std::vector<Engine*>& E, const std::vector<int>& D
       e.defer_p2 = true;
       e.prepare(si[j]);
       xb[j].alloc((size_t)std::max<int64_t>(e.step.n, 1));
-    }
+    });
     // the accumulating pass balanced over the whole batch
     double tot = 0.0;
     for (Engine* e : ea)
@@ -3377,13 +3790,15 @@ static bool batch_sweep(const std::vector<Engine*>& E, const std::vector<int>& D
       PoolBind b(e->pool);
       e->plan_pass2(target);
     }
+    bl.w_prepare += lap();
     std::vector<DavState> ds(na);
     for (size_t j = 0; j < na; ++j) {
       ds[j].xres = xb[j].p;
       ds[j].tol = use32 ? std::max(ea[j]->dav_tol, ea[j]->mixed_tol) : ea[j]->dav_tol;
       ds[j].f32 = use32;
     }
-    davidson_lockstep(ea, ds, &bl);
+    davidson_lockstep(ea, ds, &bl, bl.stage);
+    bl.w_davidson += lap();
     std::vector<double> th(na);
     for (size_t j = 0; j < na; ++j) th[j] = ds[j].theta;
     if (use32) {  // FP64 Rayleigh quotients of the FP32 solutions, sigma shared
@@ -3408,15 +3823,18 @@ static bool batch_sweep(const std::vector<Engine*>& E, const std::vector<int>& D
       dev_sync(bl.st);
       for (size_t j = 0; j < na; ++j) th[j] = ea[j]->hpin[4] / ea[j]->hpin[5];
     }
-    for (size_t j = 0; j < na; ++j) {
+    bl.w_rayleigh += lap();
+    parallel_for(na, BATCH_HOST_THREADS, [&](size_t j) {
       Engine& e = *ea[j];
       PoolBind b(e.pool);
+      OwnStream os(e, bl.priv[ka[j]]);
       const double en = e.micro_finish(si[j], Dk[ka[j]], sright[j], ssvd[j], xb[j].p, th[j], ds[j].conv);
       emin[ka[j]] = std::min(emin[ka[j]], en);
       if ((sright[j] && si[j] == e.P.L - 2) || (!sright[j] && si[j] == 0)) e.end_pass();
       if (!sright[j] && si[j] == 0) e.wdisc = e.wdisc_sweep;
       xb[j].release();
-    }
+    });
+    bl.w_finish += lap();
   }
   bool warned = false;
   for (Engine* e : E) warned = warned || e->warned;
@@ -3783,7 +4201,7 @@ int sadmrg_batch_sweep(sadmrg_ctx* const* ctxs, int n, const int* D, double* e_m
     std::vector<double> em;
     bool warned;
     double t64 = 0.0, t32 = 0.0;
-    sadmrg::BatchLaunch bl(e0.st, ctxs[0]->pool);
+    sadmrg::BatchLaunch bl(e0.st, ctxs[0]->pool, (size_t)n);
     warned = sadmrg::batch_sweep(E, std::vector<int>(D, D + n), em, bl);
     bl.times(t64, t32);
     if (e_min)
@@ -3795,6 +4213,10 @@ int sadmrg_batch_sweep(sadmrg_ctx* const* ctxs, int n, const int* D, double* e_m
       stats[3] = t32;
       stats[4] = bl.f32;
       stats[5] = (double)bl.n32;
+      stats[6] = bl.w_prepare;
+      stats[7] = bl.w_davidson;
+      stats[8] = bl.w_rayleigh;
+      stats[9] = bl.w_finish;
     }
     return warned ? SADMRG_WARN_NOT_CONVERGED : 0;
   } catch (const sadmrg::Failure& x) {
@@ -4095,6 +4517,24 @@ int sadmrg_stats_reset(sadmrg_ctx* ctx) {
     E.t_sigma32 = E.f_sigma32 = 0;
     E.n_sigma32 = 0;
     E.n_sigma = 0;
+    for (double& t : E.t_phase) t = 0.0;
+    return 0;
+  });
+}
+
+int sadmrg_set_enlarge_cache(sadmrg_ctx* ctx, int on) {
+  return guard(ctx, [&] {
+    if (on != 0 && on != 1) sadmrg::fail(SADMRG_EINVAL, "on must be 0 or 1");
+    ctx->e.enl_cache_on = on != 0;
+    if (!on) ctx->e.clear_enl_cache();
+    return 0;
+  });
+}
+
+int sadmrg_stats_phases(sadmrg_ctx* ctx, double* out) {
+  return guard(ctx, [&] {
+    if (!out) sadmrg::fail(SADMRG_EINVAL, "null output");
+    for (int k = 0; k < sadmrg::Engine::PH_N; ++k) out[k] = ctx->e.t_phase[k];
     return 0;
   });
 }

@@ -32,12 +32,18 @@ void host_free_pinned(void* p);
 void dev_h2d_async(void* dst, const void* pinned_src, size_t bytes, Stream st);
 void dev_d2h_async(void* pinned_dst, const void* src, size_t bytes, Stream st);
 void dev_set_device(int device);
+size_t dev_total_memory();  // bytes of device memory of the current device
 int dev_count();
 // event timing: returns an opaque event handle recorded on st
 void* dev_event_record(Stream st);
 double dev_event_elapsed(void* a, void* b);  // seconds, synchronises b
 void dev_event_free(void* e);
 void dev_event_wait(void* e);  // the host waits until the stream has passed e
+// Streams of default priority; dev_stream_order(a, b): work enqueued on a
+// from now on starts after the work already enqueued on b.
+Stream dev_stream_create();
+void dev_stream_destroy(Stream s);
+void dev_stream_order(Stream a, Stream b);
 
 // Flags of a block triple product  out += coef * opA(A) * B * opC(C)  (the
 // host evaluates it as two grouped GEMMs): transpose A / C, identity A / C.
@@ -185,6 +191,50 @@ void launch_normalize(double* y, const double* nrm2, int64_t n, Stream st);
 // eigen-decomposition of a symmetric k x k matrix given by its lower triangle
 // (leading dim ld), k <= 64: evals ascending, eigenvector j at evecs + j*k
 void launch_syev_small(const double* H, int k, int ld, double* evals, double* evecs, Stream st);
+// The Davidson helpers over job lists: one launch serves many independent
+// solves, each job with the arithmetic of the single-solve call.
+// out[j] = dot(V + j*ldv, x), j < k; part holds 256*k doubles
+struct DotJob {
+  const double* V;
+  const double* x;
+  double* out;
+  double* part;
+  int64_t ldv, n;
+  int k;
+};
+void launch_dots_batch(const DotJob* jobs, int njobs, int max_k, Stream st);
+// y = beta*y + alpha * sum_j coef[j] * V_j
+struct ComboJob {
+  const double* V;
+  const double* coef;
+  double* y;
+  int64_t ldv, n;
+  int k;
+  double alpha, beta;
+};
+void launch_combo_batch(const ComboJob* jobs, int njobs, int64_t max_n, Stream st);
+// element-wise, i < n:  COPY y = a;  ZERO y = 0;  RESIDUAL y = a - s[0] b;
+// PRECOND y = a / (s[0] - b) (guarded as launch_precond);  NORMALIZE
+// y *= 1/sqrt(s[0]);  D2F (float)y = a;  F2D y = (float)a
+enum : int { EW_COPY = 0, EW_ZERO, EW_RESIDUAL, EW_PRECOND, EW_NORMALIZE, EW_D2F, EW_F2D };
+struct EwJob {
+  const double* a;
+  const double* b;
+  const double* s;
+  double* y;
+  int64_t n;
+  int kind;
+};
+void launch_ew_batch(const EwJob* jobs, int njobs, int64_t max_n, Stream st);
+struct SyevJob {
+  const double* H;
+  double* evals;
+  double* evecs;
+  int k, ld;
+};
+void launch_syev_batch(const SyevJob* jobs, int njobs, Stream st);
+// dst[i] = *src[i], i < n (src: device array of device pointers)
+void launch_scalars(const double* const* src, int n, double* dst, Stream st);
 // uniform [-1,1) numbers from the SplitMix64 counter generator
 void launch_fill_uniform(double* p, int64_t n, uint64_t seed, uint64_t stream, Stream st);
 // y[i] += a * x[i], i < n

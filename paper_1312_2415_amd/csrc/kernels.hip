@@ -131,7 +131,14 @@ void dev_d2h(void* dst, const void* src, size_t bytes, Stream st) {
   hip_ok(hipStreamSynchronize((hipStream_t)st), "hipStreamSynchronize");
 }
 void dev_d2d(void* dst, const void* src, size_t bytes, Stream st) {
-  if (bytes) hip_ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)st), "hipMemcpyAsync D2D");
+  if (!bytes) return;
+  // whole doubles: a plain copy kernel (a fraction of the host cost of the
+  // runtime's copy, which matters for the many short vector copies)
+  if (bytes % 8 == 0 && (uintptr_t)dst % 8 == 0 && (uintptr_t)src % 8 == 0) {
+    launch_copy((double*)dst, (const double*)src, (int64_t)(bytes / 8), st);
+    return;
+  }
+  hip_ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)st), "hipMemcpyAsync D2D");
 }
 __global__ void zero_kernel(double* p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -163,6 +170,11 @@ void dev_d2h_async(void* dst, const void* src, size_t bytes, Stream st) {
   if (bytes) hip_ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, (hipStream_t)st), "hipMemcpyAsync D2H");
 }
 void dev_set_device(int device) { hip_ok(hipSetDevice(device), "hipSetDevice"); }
+size_t dev_total_memory() {
+  size_t fr = 0, tot = 0;
+  hip_ok(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+  return tot;
+}
 int dev_count() {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess) {
@@ -187,6 +199,22 @@ void dev_event_free(void* e) {
   if (e) (void)hipEventDestroy((hipEvent_t)e);
 }
 void dev_event_wait(void* e) { hip_ok(hipEventSynchronize((hipEvent_t)e), "hipEventSynchronize"); }
+Stream dev_stream_create() {
+  hipStream_t s = nullptr;
+  hip_ok(hipStreamCreate(&s), "hipStreamCreate");
+  return (Stream)s;
+}
+void dev_stream_destroy(Stream s) {
+  if (s) (void)hipStreamDestroy((hipStream_t)s);
+}
+void dev_stream_order(Stream a, Stream b) {
+  if (a == b) return;
+  hipEvent_t e;
+  hip_ok(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+  hip_ok(hipEventRecord(e, (hipStream_t)b), "hipEventRecord");
+  hip_ok(hipStreamWaitEvent((hipStream_t)a, e, 0), "hipStreamWaitEvent");
+  (void)hipEventDestroy(e);
+}
 
 namespace {
 
@@ -1223,8 +1251,8 @@ void launch_normalize(double* y, const double* nrm2, int64_t n, Stream st) {
 // Round-robin ordering: k/2 disjoint rotations per round.
 constexpr int SYEV_MAX = 64;
 
-__global__ __launch_bounds__(64) void syev_kernel(const double* __restrict__ H, int k, int ld,
-                                                  double* __restrict__ evals, double* __restrict__ evecs) {
+__device__ __forceinline__ void syev_body(const double* __restrict__ H, const int k, const int ld,
+                                          double* __restrict__ evals, double* __restrict__ evecs) {
   __shared__ double a[SYEV_MAX][SYEV_MAX + 1];
   __shared__ double v[SYEV_MAX][SYEV_MAX + 1];
   __shared__ double rc[SYEV_MAX / 2], rs[SYEV_MAX / 2];
@@ -1310,8 +1338,143 @@ __global__ __launch_bounds__(64) void syev_kernel(const double* __restrict__ H, 
   }
 }
 
+__global__ __launch_bounds__(64) void syev_kernel(const double* __restrict__ H, int k, int ld,
+                                                  double* __restrict__ evals, double* __restrict__ evecs) {
+  syev_body(H, k, ld, evals, evecs);
+}
+
 void launch_syev_small(const double* H, int k, int ld, double* evals, double* evecs, Stream st) {
   hipLaunchKernelGGL(syev_kernel, dim3(1), dim3(64), 0, (hipStream_t)st, H, k, ld, evals, evecs);
+}
+
+// ---------------------------------------------------------------------------
+// The same Davidson helpers over job lists (one launch for many solves).  Each
+// job gets the arithmetic of the single-solve kernel above: the same
+// partial-sum chunks and reduction order for the inner products, the same
+// element formulas, the same Jacobi solver.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(RB) void dots_batch_stage1(const DotJob* __restrict__ jobs) {
+  const DotJob jb = jobs[blockIdx.z];
+  const int j = blockIdx.y;
+  if (j >= jb.k) return;
+  const int64_t n = jb.n;
+  const int64_t chunk = (n + RCH - 1) / RCH;
+  const int64_t b = blockIdx.x * chunk, e = min(n, b + chunk);
+  const double* v = jb.V + j * jb.ldv;
+  const double* x = jb.x;
+  double s = 0;
+  for (int64_t i = b + threadIdx.x; i < e; i += RB) s += v[i] * x[i];
+  __shared__ double red[RB / 64];
+  s = wave_sum(s);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < RB / 64; ++w) t += red[w];
+    jb.part[(int64_t)j * RCH + blockIdx.x] = t;
+  }
+}
+
+__global__ void dots_batch_stage2(const DotJob* __restrict__ jobs) {
+  const DotJob jb = jobs[blockIdx.y];
+  const int j = blockIdx.x;
+  if (j >= jb.k) return;
+  double s = 0;
+  for (int i = threadIdx.x; i < RCH; i += 64) s += jb.part[(int64_t)j * RCH + i];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) jb.out[j] = s;
+}
+
+void launch_dots_batch(const DotJob* jobs, int njobs, int max_k, Stream st) {
+  if (njobs <= 0 || max_k <= 0) return;
+  hipLaunchKernelGGL(dots_batch_stage1, dim3(RCH, max_k, njobs), dim3(RB), 0, (hipStream_t)st, jobs);
+  hipLaunchKernelGGL(dots_batch_stage2, dim3(max_k, njobs), dim3(64), 0, (hipStream_t)st, jobs);
+  check_launch("dots_batch");
+}
+
+__global__ void combo_batch_kernel(const ComboJob* __restrict__ jobs) {
+  const ComboJob jb = jobs[blockIdx.y];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < jb.n; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0;
+    for (int j = 0; j < jb.k; ++j) s += jb.coef[j] * jb.V[j * jb.ldv + i];
+    jb.y[i] = (jb.beta == 0.0 ? 0.0 : jb.beta * jb.y[i]) + jb.alpha * s;
+  }
+}
+
+void launch_combo_batch(const ComboJob* jobs, int njobs, int64_t max_n, Stream st) {
+  if (njobs <= 0) return;
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (max_n + 255) / 256));
+  hipLaunchKernelGGL(combo_batch_kernel, dim3(nb, njobs), dim3(256), 0, (hipStream_t)st, jobs);
+  check_launch("combo_batch");
+}
+
+__global__ void ew_batch_kernel(const EwJob* __restrict__ jobs) {
+  const EwJob jb = jobs[blockIdx.y];
+  const int64_t n = jb.n;
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, step = (int64_t)gridDim.x * blockDim.x;
+  switch (jb.kind) {
+    case EW_COPY:
+      for (int64_t i = i0; i < n; i += step) jb.y[i] = jb.a[i];
+      break;
+    case EW_ZERO:
+      for (int64_t i = i0; i < n; i += step) jb.y[i] = 0.0;
+      break;
+    case EW_RESIDUAL: {
+      const double th = jb.s[0];
+      for (int64_t i = i0; i < n; i += step) jb.y[i] = jb.a[i] - th * jb.b[i];
+      break;
+    }
+    case EW_PRECOND: {
+      const double th = jb.s[0];
+      for (int64_t i = i0; i < n; i += step) {
+        double d = th - jb.b[i];
+        if (fabs(d) < 1e-12) d = d < 0 ? -1e-12 : 1e-12;
+        jb.y[i] = jb.a[i] / d;
+      }
+      break;
+    }
+    case EW_NORMALIZE: {
+      const double f = 1.0 / sqrt(jb.s[0]);
+      for (int64_t i = i0; i < n; i += step) jb.y[i] *= f;
+      break;
+    }
+    case EW_D2F:
+      for (int64_t i = i0; i < n; i += step) ((float*)jb.y)[i] = (float)jb.a[i];
+      break;
+    case EW_F2D:
+      for (int64_t i = i0; i < n; i += step) jb.y[i] = (double)((const float*)jb.a)[i];
+      break;
+    default:
+      break;
+  }
+}
+
+void launch_ew_batch(const EwJob* jobs, int njobs, int64_t max_n, Stream st) {
+  if (njobs <= 0) return;
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (max_n + 255) / 256));
+  hipLaunchKernelGGL(ew_batch_kernel, dim3(nb, njobs), dim3(256), 0, (hipStream_t)st, jobs);
+  check_launch("ew_batch");
+}
+
+__global__ __launch_bounds__(64) void syev_batch_kernel(const SyevJob* __restrict__ jobs) {
+  const SyevJob jb = jobs[blockIdx.x];
+  syev_body(jb.H, jb.k, jb.ld, jb.evals, jb.evecs);
+}
+
+void launch_syev_batch(const SyevJob* jobs, int njobs, Stream st) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(syev_batch_kernel, dim3(njobs), dim3(64), 0, (hipStream_t)st, jobs);
+  check_launch("syev_batch");
+}
+
+__global__ void scalars_kernel(const double* const* __restrict__ src, int n, double* __restrict__ dst) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i][0];
+}
+
+void launch_scalars(const double* const* src, int n, double* dst, Stream st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(scalars_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)st, src, n, dst);
+  check_launch("scalars");
 }
 
 // SplitMix64 finaliser (Steele, Lea & Flood, OOPSLA 2014).

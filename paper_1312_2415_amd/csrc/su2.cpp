@@ -74,19 +74,15 @@ double coupling_product(int tj1, int tj2, int tJ, int tk1, int tk2, int tK, int 
   if (!triangle(tj1, tj2, tJ) || !triangle(tj1p, tj2p, tJp) || !triangle(tk1, tk2, tK) || !triangle(tj1, tk1, tj1p) ||
       !triangle(tj2, tk2, tj2p) || !triangle(tJ, tK, tJp))
     return 0.0;
-  static std::mutex mu;
-  static std::unordered_map<uint64_t, double> cache;
+  // memo per host thread: engines of a batch prepare their steps in parallel
+  static thread_local std::unordered_map<uint64_t, double> cache;
   uint64_t key = 0;
   for (int v : {tj1, tj2, tJ, tk1, tk2, tK, tj1p, tj2p, tJp}) key = key * 64 + (uint64_t)v;
-  {
-    std::lock_guard<std::mutex> g(mu);
-    auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
-  }
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
   const double v = std::sqrt((double)(tJ + 1) * (tK + 1) * (tj1p + 1) * (tj2p + 1)) *
                    ninej(tj1p, tj1, tk1, tj2p, tj2, tk2, tJp, tJ, tK);
-  std::lock_guard<std::mutex> g(mu);
-  cache[key] = v;
+  cache.emplace(key, v);
   return v;
 }
 

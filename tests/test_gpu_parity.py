@@ -79,6 +79,35 @@ def test_sweep_energies_match_oracle(case):
     g.close()
 
 
+def test_kept_enlargements_give_identical_sweeps():
+    """Reusing the previous pass's enlarged blocks changes nothing: the
+    traces with and without the cache agree bit for bit, also across a
+    D change and an import that replaces every block."""
+    L, N, twoS, group, irrep, D = 10, 8, 2, "D2h", 0, 30
+    I = make_integrals(L, group, 41)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    blob = sd.export_blob(dm)
+    runs = []
+    for on in (True, False):
+        g = _gpu(L, group, I)
+        g.set_target(N, twoS, irrep)
+        g.set_enlarge_cache(on)
+        g.mps_import(blob)
+        g.sweep(D)
+        g.sweep(D + 10)
+        g.mps_import(blob)
+        g.sweep(D)
+        runs.append(g.trace())
+        g.close()
+    assert np.array_equal(runs[0], runs[1])
+    # the same energies as the oracle's first sweep from that state
+    dm.sweep(D)
+    n = 2 * (L - 1)
+    assert np.abs(runs[0][-n:] - np.array(dm.stats.energies[:n])).max() <= 1e-8
+
+
 def test_config1_exact_at_fci_bond_dimension_with_own_initial_state():
     I = make_integrals(8, "C1", 1001)
     efci = fci_solve(I.h, I.eri, 8, 0)[0][0]
