@@ -32,6 +32,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -140,6 +142,76 @@ def cpu_baseline(seconds: float, L: int, N: int, twoS: int, irrep: int, seed: in
             "sigma_seconds": acc["t"]}
 
 
+def batch_workload(n, seed):
+    """Independent small problems of mixed size: L uniform in 10..20, N = L/2
+    rounded to an even number, S in {0, 1}, D uniform in 128..1024, D2h with
+    orbital irreps round-robin, target Ag, each with its own integral seed."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for k in range(n):
+        L = int(rng.integers(10, 21))
+        specs.append({"L": L, "N": 2 * int(round(L / 4)), "twoS": 2 * int(rng.integers(0, 2)),
+                      "D": int(rng.integers(128, 1025)), "seed": seed * 1000 + k})
+    return specs
+
+
+def batch_bench(n, seed, prec, mixed_tol):
+    """One lockstep sweep of n problems (sadmrg_batch_sweep) against the same
+    problems swept one after another from the same states."""
+    from paper_1312_2415_amd import SaDMRG
+    from paper_1312_2415_amd.binding import batch_sweep
+    from synth.integrals import make_integrals
+    specs = batch_workload(n, seed)
+    t0 = time.perf_counter()
+    gs = []
+    for sp in specs:
+        I = make_integrals(sp["L"], "D2h", sp["seed"])
+        g = SaDMRG(sp["L"], 8, I.orb_irrep, device=0)
+        g.set_integrals(I.h, I.eri)
+        g.set_target(sp["N"], sp["twoS"], 0)
+        g.set_seed(sp["seed"])
+        g.set_davidson(1e-7, 32, 100)
+        g.set_precision(prec, mixed_tol)
+        g.init_mps(sp["D"])
+        gs.append(g)
+    Ds = [sp["D"] for sp in specs]
+    t_init = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batch_sweep(gs, Ds)  # warm-up: pools, kept enlargements, a converging state
+    t_warm = time.perf_counter() - t0
+    print(f"batch of {n}: init {t_init:.1f}s, warm-up lockstep sweep {t_warm:.1f}s", file=sys.stderr, flush=True)
+    blobs = [g.mps_export() for g in gs]
+    t0 = time.perf_counter()
+    eb, st, _ = batch_sweep(gs, Ds)
+    t_batch = time.perf_counter() - t0
+    print(f"batch of {n}: lockstep sweep {t_batch:.2f}s", file=sys.stderr, flush=True)
+    for g, b in zip(gs, blobs):
+        g.mps_import(b)
+    t0 = time.perf_counter()
+    es = [g.sweep(D)[0] for g, D in zip(gs, Ds)]
+    t_sep = time.perf_counter() - t0
+    print(f"batch of {n}: separate sweeps {t_sep:.2f}s", file=sys.stderr, flush=True)
+    for g in gs:
+        g.close()
+    t_sh = st["t_sigma"] + st["t_sigma32"]
+    f_sh = st["flops_sigma"] + st["flops_sigma32"]
+    return {
+        "workload": "independent problems, L uniform 10..20, N = L/2 rounded to even, S in {0,1}, "
+                    "D_SU(2) uniform 128..1024, D2h round-robin orbital irreps, own integral seed each",
+        "instances": n, "seed": seed,
+        "precision": "FP32 sigma in Davidson + FP64 Rayleigh quotients" if prec == 1 else "FP64",
+        "s_per_lockstep_sweep": t_batch,
+        "s_per_separate_sweeps": t_sep,
+        "speedup": t_sep / t_batch,
+        "shared_sigma_launch_seconds": t_sh,
+        "shared_sigma_tflops": f_sh / max(t_sh, 1e-12) / 1e12,
+        "shared_sigma_launches": st["n_sigma"] + st["n_sigma32"],
+        "host_phase_wall_seconds": st["wall"],
+        "max_abs_dE_lockstep_vs_separate": float(max(abs(a - b) for a, b in zip(eb, es))),
+        "L": [sp["L"] for sp in specs], "D": Ds,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +232,8 @@ def main():
     ap.add_argument("--mixed-tol", type=float, default=1e-5)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-rdm", action="store_true")
+    ap.add_argument("--batch-n", type=int, default=64, help="independent problems of the lockstep batch; 0 = skip")
+    ap.add_argument("--batch-seed", type=int, default=4)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -303,6 +377,8 @@ def main():
             line["mixed"]["rdm_max_abs_error_vs_fp64"] = {"gamma": float(np.abs(m1 - rdm64[0]).max()),
                                                            "Gamma": float(np.abs(m2 - rdm64[1]).max())}
     g.close()
+    if args.batch_n > 0:
+        line["batch"] = batch_bench(args.batch_n, args.batch_seed, 1, args.mixed_tol)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, L, N, args.twoS, args.irrep, args.seed, args.cpu_D)
     print(json.dumps(line), flush=True)
