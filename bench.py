@@ -238,7 +238,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the method runs on a single MI355X here "
-              "(multi-GPU sharding of the sigma product is described in the design notes, not run).",
+              "(sharding the sigma product over several GPUs is not run).",
               file=sys.stderr)
         sys.exit(2)
 
@@ -276,6 +276,8 @@ def main():
         print(f"timed sweep {k + 1}/{args.steps} D={args.D} E={e:.10f} {time.perf_counter() - ts:.1f}s",
               file=sys.stderr, flush=True)
     t1 = time.perf_counter()
+    from paper_1312_2415_amd.binding import device_memory
+    mem_free, mem_total = device_memory(0)
     st = g.stats()
     trace64 = g.trace()
     sec_per_sweep = (t1 - t0) / args.steps
@@ -320,6 +322,7 @@ def main():
         "host_phase_seconds_per_sweep": {k: v / args.steps for k, v in st["phases"].items()},
         "davidson_sigma_seconds_per_sweep": st["t_sigma"] / args.steps,
         "max_enlarged_bytes": st["max_enlarged_bytes"],
+        "device_memory_used_GiB_after_timed_sweeps": (mem_total - mem_free) / 2**30,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK, "unit": "TFLOP/s",
                      "frac": achieved / FP64_MFMA_PEAK, "traffic": stored_traffic(dom),
                      "kernel": PASS_KERNEL[dom], "flops_per_launch": flops_per_launch,

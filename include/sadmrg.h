@@ -88,17 +88,17 @@ int sadmrg_set_target(sadmrg_ctx* ctx, int N, int twoS, int irrep);
  * and maximum iterations per micro-iteration. */
 int sadmrg_set_davidson(sadmrg_ctx* ctx, double tol, int max_sub, int max_iter);
 
-/* Precision of the sigma product (spec precision variant of the
- * effective-Hamiltonian step, section "The effective Hamiltonian equation").
+/* Precision of the sigma product (section "The effective Hamiltonian
+ * equation": the eigenproblem solved at every micro-iteration).
  * mode 0: FP64 everywhere (default).
  * mode 1: the Davidson sigma products use FP32 copies of the operators and of
  *   psi with FP32 accumulation until the residual reaches max(tol, mixed_tol)
  *   or, once below 6e-6 |theta|, stops improving (10 % over four iterations:
  *   the FP32 rounding floor); orthogonalisation, Ritz problem and residuals
- *   stay FP64, and one FP64 sigma gives the reported energy of the
- *   micro-iteration as the Rayleigh quotient <x|H|x>/<x|x> of the final
- *   vector.  mixed_tol = 1e-5 keeps energies within ~1e-7 Eh and RDMs within
- *   ~1e-6 of an FP64 run at the L=28, D=2500 headline shape.
+ *   stay FP64.  Then one FP64 Davidson step refines the vector: the subspace
+ *   of the vector and its preconditioned FP64 residual, two FP64 sigma
+ *   products; the reported energy of the micro-iteration is the lower FP64
+ *   Ritz value and the refined vector goes on to the decomposition.
  * sadmrg_sigma uses FP32 in mode 1.  SVD, truncation and renormalisation stay
  * FP64.  Errors: EINVAL. */
 int sadmrg_set_precision(sadmrg_ctx* ctx, int mode, double mixed_tol);
@@ -145,13 +145,17 @@ int sadmrg_sweep(sadmrg_ctx* ctx, int D, double* e_min);
  * ENOMEM, EDEVICE. */
 int sadmrg_batch_sweep(sadmrg_ctx* const* ctxs, int n, const int* D, double* e_min, double* stats);
 
+/* Free and total bytes of device memory on a device (the library's cached
+ * blocks count as used).  Errors: EINVAL, EDEVICE. */
+int sadmrg_device_memory(int device, size_t* free_bytes, size_t* total_bytes);
+
 /* Keep enlarged blocks for the next pass (on = 1, the default) or build
  * every enlargement afresh (on = 0, which also releases the kept ones).  In a
  * left-to-right pass the right blocks are the ones the previous
  * right-to-left pass built (section "Sweeping"), so the enlargement of the
  * unchanged side at step i equals the one made there; results are identical
  * either way.  Kept blocks of all contexts of the process share a ceiling
- * of a quarter of the device memory; the oldest go first.  Errors: EINVAL. */
+ * of two fifths of the device memory; the oldest go first.  Errors: EINVAL. */
 int sadmrg_set_enlarge_cache(sadmrg_ctx* ctx, int on);
 
 /* Run a convergence scheme (section "Convergence scheme"): n instructions of
@@ -241,9 +245,10 @@ int sadmrg_sigma(sadmrg_ctx* ctx, const double* x, double* y, int on_device);
 /* Diagonal of the effective Hamiltonian at the prepared step (same layout). */
 int sadmrg_heff_diagonal(sadmrg_ctx* ctx, double* d, int on_device);
 
-/* Work counters of the prepared step's sigma: algorithmic flops, operator +
- * vector bytes, number of block-product tasks.  See the design notes for the
- * exact definitions. */
+/* Work counters of the prepared step's sigma: algorithmic flops (the sum
+ * over block products c op(A) B op(C) of the two GEMMs' 2mnk, tile padding
+ * excluded), bytes (every operator the products read, all its blocks, once,
+ * plus the input and output vectors) and the number of block products. */
 int sadmrg_sigma_counters(sadmrg_ctx* ctx, double* flops, double* bytes, int64_t* tasks);
 
 /* Accumulated timings and counts since the last reset: seconds in sigma

@@ -19,7 +19,7 @@ What it follows in the paper (arXiv:1312.2415):
     DMRG", eqs. tensordecomp, creaannih1/2.
   * kappa normalisation and discarded weight -- eqs. for kappa and w^disc.
 
-Readings where the paper is silent (all listed in the design notes):
+Readings where the paper is silent:
   * The two-site object is kept in the "TT" coupling of the paper's StoTT
     equation (left block (x) site i coupled to the middle bond spin j_M, site
     i+1 (x) right block coupled to the same j_M, the pair coupled to a singlet

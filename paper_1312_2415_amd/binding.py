@@ -62,6 +62,7 @@ def load_library(path: str | None = None):
         "sadmrg_stats_reset": (c_int, [c_vp]),
         "sadmrg_stats_phases": (c_int, [c_vp, P(c_dbl)]),
         "sadmrg_set_enlarge_cache": (c_int, [c_vp, c_int]),
+        "sadmrg_device_memory": (c_int, [c_int, P(c_sz), P(c_sz)]),
         "sadmrg_stats_bytes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_passes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_mixed": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl)]),
@@ -287,6 +288,16 @@ class SaDMRG:
 
     def stats_reset(self):
         self._chk(self.lib.sadmrg_stats_reset(self.h))
+
+
+def device_memory(device: int = 0, lib_path: str | None = None):
+    """(free, total) bytes of device memory (sadmrg_device_memory)."""
+    lib = load_library(lib_path)
+    f, t = ctypes.c_size_t(), ctypes.c_size_t()
+    rc = lib.sadmrg_device_memory(int(device), ctypes.byref(f), ctypes.byref(t))
+    if rc != 0:
+        raise SadmrgError(rc, "sadmrg_device_memory failed")
+    return f.value, t.value
 
 
 def batch_sweep(solvers, D):

@@ -1437,10 +1437,10 @@ struct Step {
 };
 
 // Device bytes of enlarged blocks kept for reuse, over all engines of the
-// process, and their ceiling (a quarter of the device memory).
+// process, and their ceiling (two fifths of the device memory).
 static std::atomic<int64_t> g_enl_cache_bytes{0};
 static int64_t enl_cache_budget() {
-  static const int64_t b = (int64_t)(dev_total_memory() / 4);
+  static const int64_t b = (int64_t)(dev_total_memory() / 5 * 2);
   return b;
 }
 
@@ -3063,28 +3063,64 @@ struct Engine {
 
   // ---- one micro-iteration
   // <x|H|x> / <x|x> with the FP64 sigma
-  double rayleigh(const double* x) {
-    ray_enqueue(x, nullptr);
-    dev_sync(st);
-    return hpin[4] / hpin[5];
-  }
-  // the two inner products of the quotient, read back into hpin[4..5];
-  // y = null: sigma here, else y already holds H x
-  void ray_enqueue(const double* x, const double* y) {
+  // FP64 refinement of an FP32 Davidson solution x (unit; the solve's last
+  // Ritz value still in dav_evals()): one Davidson step in FP64 on the
+  // subspace {x, t}, t the preconditioned FP64 residual made orthonormal to
+  // x.  The phases: after y = H x is in dr, refine_dir forms t in dt; after
+  // w = H t is in dax, refine_dots enqueues the inner products (read back
+  // into hpin[0..4]); refine_update solves the 2 x 2 problem on the host,
+  // replaces x by the lowest Ritz vector and returns its FP64 Rayleigh
+  // quotient.
+  void refine_dir(const double* x) {
     const int64_t n = step.n;
-    dsmall.ensure(8 * 64 + 64 * 64);
-    dpartial.ensure(256 * 64);
-    dr.ensure(n);
-    if (!hpin) hpin = (double*)host_alloc_pinned(8 * sizeof(double));
-    if (!y) {
-      sigma_vec(x, dr.p, false);
-      y = dr.p;
+    launch_residual(dr.p, x, dav_evals(), n, dt.p, st);
+    launch_precond(dt.p, step.diag.p, dav_evals(), n, dt.p, st);
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_dots(x, n, 1, dt.p, n, dav_coef(), dpartial.p, st);
+      launch_combo_vec(x, n, 1, dav_coef(), -1.0, n, dt.p, 1.0, st);
     }
-    launch_dots(x, n, 1, y, n, dsmall.p, dpartial.p, st);
-    launch_dots(x, n, 1, x, n, dsmall.p + 1, dpartial.p, st);
-    dev_d2h_async(hpin + 4, dsmall.p, 16, st);
+    launch_dots(dt.p, n, 1, dt.p, n, dav_nrm2(), dpartial.p, st);
+    launch_normalize(dt.p, dav_nrm2(), n, st);
   }
-
+  void refine_dots(const double* x) {
+    const int64_t n = step.n;
+    double* c = dav_coef();
+    launch_dots(x, n, 1, dr.p, n, c + 1, dpartial.p, st);   // x.Hx
+    launch_dots(x, n, 1, x, n, c + 2, dpartial.p, st);      // x.x
+    launch_dots(x, n, 1, dax.p, n, c + 3, dpartial.p, st);  // x.Ht
+    launch_dots(dt.p, n, 1, dax.p, n, c + 4, dpartial.p, st);  // t.Ht
+    if (!hpin) hpin = (double*)host_alloc_pinned(8 * sizeof(double));
+    dev_d2h_async(hpin, dav_nrm2(), 8, st);  // |t|^2 before normalisation
+    dev_d2h_async(hpin + 1, c + 1, 32, st);
+  }
+  double refine_update(double* x) {
+    const int64_t n = step.n;
+    const double tt = hpin[0], xy = hpin[1], xx = hpin[2], xw = hpin[3], tw = hpin[4];
+    const double a = xy / xx;
+    if (!(tt > 1e-28) || !(xx > 0) || !std::isfinite(xw) || !std::isfinite(tw)) return a;
+    const double sx = std::sqrt(xx);
+    const double b = xw / sx, c = tw;
+    const double lam = 0.5 * (a + c) - std::sqrt(0.25 * (a - c) * (a - c) + b * b);
+    double p = b, q = lam - a;  // (H - lam) v = 0, two equivalent rows
+    const double p2 = lam - c, q2 = b;
+    if (p2 * p2 + q2 * q2 > p * p + q * q) p = p2, q = q2;
+    const double nv = std::sqrt(p * p + q * q);
+    if (!(nv > 0) || !std::isfinite(lam) || lam > a) return a;
+    p /= nv;
+    q /= nv;
+    if (p < 0) p = -p, q = -q;  // keep the sign of x
+    launch_scal(x, p / sx, n, st);
+    launch_axpy(x, dt.p, q, n, st);
+    return lam;
+  }
+  double refine64(double* x) {
+    sigma_vec(x, dr.p, false);
+    refine_dir(x);
+    sigma_vec(dt.p, dax.p, false);
+    refine_dots(x);
+    dev_sync(st);
+    return refine_update(x);
+  }
   double micro(int i, int D, bool right, bool do_svd) {
     auto t0 = std::chrono::steady_clock::now();
     prepare(i);
@@ -3094,10 +3130,11 @@ struct Engine {
     bool conv = false;
     double th;
     if (prec == 1) {
-      // FP32 sigma until the residual reaches mixed_tol, then one FP64 sigma:
-      // the reported energy is the FP64 Rayleigh quotient of that vector
+      // FP32 sigma until the residual reaches mixed_tol, then one FP64
+      // Davidson step from that vector (two FP64 sigma): the reported energy
+      // is the FP64 Ritz value of the refined vector
       th = davidson(x.p, &its, &conv, std::max(dav_tol, mixed_tol), true);
-      th = rayleigh(x.p);
+      th = refine64(x.p);
     } else {
       th = davidson(x.p, &its, &conv, dav_tol, false);
     }
@@ -3801,27 +3838,39 @@ static bool batch_sweep(const std::vector<Engine*>& E, const std::vector<int>& D
     bl.w_davidson += lap();
     std::vector<double> th(na);
     for (size_t j = 0; j < na; ++j) th[j] = ds[j].theta;
-    if (use32) {  // FP64 Rayleigh quotients of the FP32 solutions, sigma shared
-      std::vector<const double*> xs;
-      std::vector<double*> ys;
+    if (use32) {  // FP64 refinement of the FP32 solutions, sigma shared
+      auto shared_sigma = [&](std::vector<const double*> xs, std::vector<double*> ys) {
+        if (na == 1) {
+          PoolBind b(ea[0]->pool);
+          ea[0]->sigma_vec(xs[0], ys[0], false);
+        } else {
+          bl.sigma(ea, xs, ys, false);
+        }
+      };
+      std::vector<const double*> xs, ts;
+      std::vector<double*> ys, ws;
       for (size_t j = 0; j < na; ++j) {
-        PoolBind b(ea[j]->pool);
-        ea[j]->dr.ensure(ea[j]->step.n);
         xs.push_back(xb[j].p);
         ys.push_back(ea[j]->dr.p);
+        ts.push_back(ea[j]->dt.p);
+        ws.push_back(ea[j]->dax.p);
       }
-      if (na == 1) {
-        PoolBind b(ea[0]->pool);
-        ea[0]->sigma_vec(xs[0], ys[0], false);
-      } else {
-        bl.sigma(ea, xs, ys, false);
-      }
+      shared_sigma(xs, ys);
       for (size_t j = 0; j < na; ++j) {
         PoolBind b(ea[j]->pool);
-        ea[j]->ray_enqueue(xs[j], ys[j]);
+        ea[j]->refine_dir(xb[j].p);
+      }
+      shared_sigma(ts, ws);
+      for (size_t j = 0; j < na; ++j) {
+        PoolBind b(ea[j]->pool);
+        ea[j]->refine_dots(xb[j].p);
       }
       dev_sync(bl.st);
-      for (size_t j = 0; j < na; ++j) th[j] = ea[j]->hpin[4] / ea[j]->hpin[5];
+      bl.stage.reset();
+      for (size_t j = 0; j < na; ++j) {
+        PoolBind b(ea[j]->pool);
+        th[j] = ea[j]->refine_update(xb[j].p);
+      }
     }
     bl.w_rayleigh += lap();
     parallel_for(na, BATCH_HOST_THREADS, [&](size_t j) {
@@ -4520,6 +4569,19 @@ int sadmrg_stats_reset(sadmrg_ctx* ctx) {
     for (double& t : E.t_phase) t = 0.0;
     return 0;
   });
+}
+
+int sadmrg_device_memory(int device, size_t* free_bytes, size_t* total_bytes) {
+  if (!free_bytes || !total_bytes) return SADMRG_EINVAL;
+  try {
+    const int nd = sadmrg::dev_count();
+    if (device < 0 || device >= nd) return SADMRG_EINVAL;
+    sadmrg::dev_set_device(device);
+    sadmrg::dev_memory_info(free_bytes, total_bytes);
+    return 0;
+  } catch (...) {
+    return SADMRG_EDEVICE;
+  }
 }
 
 int sadmrg_set_enlarge_cache(sadmrg_ctx* ctx, int on) {

@@ -33,6 +33,7 @@ void dev_h2d_async(void* dst, const void* pinned_src, size_t bytes, Stream st);
 void dev_d2h_async(void* pinned_dst, const void* src, size_t bytes, Stream st);
 void dev_set_device(int device);
 size_t dev_total_memory();  // bytes of device memory of the current device
+void dev_memory_info(size_t* free_bytes, size_t* total_bytes);  // current device
 int dev_count();
 // event timing: returns an opaque event handle recorded on st
 void* dev_event_record(Stream st);
@@ -239,6 +240,8 @@ void launch_scalars(const double* const* src, int n, double* dst, Stream st);
 void launch_fill_uniform(double* p, int64_t n, uint64_t seed, uint64_t stream, Stream st);
 // y[i] += a * x[i], i < n
 void launch_axpy(double* y, const double* x, double a, int64_t n, Stream st);
+// y[i] *= a, i < n
+void launch_scal(double* y, double a, int64_t n, Stream st);
 // Plain streaming copy dst[i] = src[i] (reference kernel for HBM byte counters).
 void launch_copy(double* dst, const double* src, int64_t n, Stream st);
 // a[r][c] *= s[r]  /  a[r][c] *= s[c]

@@ -170,6 +170,7 @@ void dev_d2h_async(void* dst, const void* src, size_t bytes, Stream st) {
   if (bytes) hip_ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, (hipStream_t)st), "hipMemcpyAsync D2H");
 }
 void dev_set_device(int device) { hip_ok(hipSetDevice(device), "hipSetDevice"); }
+void dev_memory_info(size_t* fr, size_t* tot) { hip_ok(hipMemGetInfo(fr, tot), "hipMemGetInfo"); }
 size_t dev_total_memory() {
   size_t fr = 0, tot = 0;
   hip_ok(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
@@ -1507,6 +1508,18 @@ void launch_axpy(double* y, const double* x, double a, int64_t n, Stream st) {
   const int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
   hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, (hipStream_t)st, y, x, a, n);
   check_launch("axpy");
+}
+
+__global__ void scal_kernel(double* y, double a, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] *= a;
+}
+
+void launch_scal(double* y, double a, int64_t n, Stream st) {
+  if (n <= 0) return;
+  const int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  hipLaunchKernelGGL(scal_kernel, dim3(nb), dim3(256), 0, (hipStream_t)st, y, a, n);
+  check_launch("scal");
 }
 
 __global__ void scale_rows_kernel(double* a, int rows, int cols, int ld, const double* s) {
