@@ -39,6 +39,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "H_eff·ψ TFLOP/s + s/sweep, FP64 vs mixed at |ΔE|≤1e-6 Eh, L=28 D=2500"
 FP64_MFMA_PEAK = 78.6  # TFLOP/s, MI355X dense FP64 matrix peak
+FP32_MFMA_PEAK = 157.3  # TFLOP/s, dense FP32 matrix peak
+BF16_MFMA_PEAK = 2500.0  # TFLOP/s, dense BF16 matrix peak (a BF16x3 product costs three)
 HBM_PEAK = 8000.0  # GB/s
 KERNEL_SRC = os.path.join(ROOT, "paper_1312_2415_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_kernel_sigma_L28_N12_D2500_traffic.json")
@@ -340,45 +342,56 @@ def main():
                        "trace_gamma": float(np.trace(g1))}
         print(f"rdm {t_rdm:.1f}s E={e_rdm:.10f} identity error {abs(e_id - e_rdm):.2e}", file=sys.stderr, flush=True)
     if not args.no_mixed:
-        # the same timed sweeps from the same state with FP32 sigma in Davidson
-        # and FP64 Rayleigh-quotient energies
-        n64 = len(trace64)
-        g.set_precision(1, args.mixed_tol)
-        g.mps_import(start)
-        g.stats_reset()
-        tm0 = time.perf_counter()
-        emix = []
-        for k in range(args.steps):
-            ts = time.perf_counter()
-            e, _ = g.sweep(args.D)
-            emix.append(e)
-            print(f"mixed sweep {k + 1}/{args.steps} D={args.D} E={e:.10f} {time.perf_counter() - ts:.1f}s",
-                  file=sys.stderr, flush=True)
-        tm1 = time.perf_counter()
-        sm = g.stats()
-        tracem = g.trace()
-        nt = len(tracem) - n64  # micro-iterations of the mixed sweeps
-        d_micro = float(max(abs(a - b) for a, b in zip(trace64[n64 - nt:], tracem[n64:]))) if nt > 0 else None
-        sec_mixed = (tm1 - tm0) / args.steps
-        line["mixed"] = {
-            "precision": "FP32 sigma (FP32 operators, FP32 accumulation) in Davidson; FP64 Davidson algebra, "
-                         "SVD, renormalisation; FP64 Rayleigh-quotient energy per micro-iteration",
-            "mixed_tol": args.mixed_tol,
-            "s_per_sweep": sec_mixed,
-            "speedup_s_per_sweep": sec_per_sweep / sec_mixed,
-            "sigma_fp32_tflops": sm["fp32"]["flops"] / max(sm["fp32"]["t"], 1e-12) / 1e12,
-            "sigma_fp32_calls": sm["fp32"]["calls"],
-            "sigma_fp64_calls": sm["n_sigma"],
-            "sigma_seconds_per_sweep": (sm["fp32"]["t"] + sm["t_sigma"]) / args.steps,
-            "sigma_seconds_per_sweep_fp64_path": st["t_sigma"] / args.steps,
-            "energy_last_sweep": emix[-1],
-            "abs_dE_last_sweep_vs_fp64": abs(emix[-1] - energies[-1]),
-            "max_abs_dE_per_micro_iteration_vs_fp64": d_micro,
-        }
-        if rdm64 is not None:
-            m1, m2, _ = g.rdm()
-            line["mixed"]["rdm_max_abs_error_vs_fp64"] = {"gamma": float(np.abs(m1 - rdm64[0]).max()),
-                                                           "Gamma": float(np.abs(m2 - rdm64[1]).max())}
+        # the same timed sweeps from the same state with reduced-precision
+        # sigma in Davidson (FP32, then BF16x3) and an FP64 refinement step
+        n_done = len(trace64)
+        for mode, key, desc in (
+                (1, "mixed", "FP32 sigma (FP32 operators, FP32 accumulation) in Davidson"),
+                (2, "mixed_bf16x3", "BF16x3 sigma (hi*hi + hi*lo + lo*hi of BF16 splits of the FP32 operators, "
+                                    "FP32 accumulation) in Davidson")):
+            g.set_precision(mode, args.mixed_tol)
+            g.mps_import(start)
+            g.stats_reset()
+            tm0 = time.perf_counter()
+            emix = []
+            for k in range(args.steps):
+                ts = time.perf_counter()
+                e, _ = g.sweep(args.D)
+                emix.append(e)
+                print(f"{key} sweep {k + 1}/{args.steps} D={args.D} E={e:.10f} {time.perf_counter() - ts:.1f}s",
+                      file=sys.stderr, flush=True)
+            tm1 = time.perf_counter()
+            sm = g.stats()
+            tracem = g.trace()
+            nt = len(tracem) - n_done  # micro-iterations of these sweeps
+            d_micro = float(max(abs(a - b) for a, b in zip(trace64[len(trace64) - nt:], tracem[n_done:]))) \
+                if nt > 0 else None
+            n_done = len(tracem)
+            sec_mixed = (tm1 - tm0) / args.steps
+            peak = FP32_MFMA_PEAK if mode == 1 else BF16_MFMA_PEAK / 3
+            tf = sm["fp32"]["flops"] / max(sm["fp32"]["t"], 1e-12) / 1e12
+            rec = {
+                "precision": desc + "; FP64 Davidson algebra, SVD, renormalisation; one FP64 Davidson step "
+                                    "(two FP64 sigma) refines each micro-iteration's vector and gives its energy",
+                "mixed_tol": args.mixed_tol,
+                "s_per_sweep": sec_mixed,
+                "speedup_s_per_sweep": sec_per_sweep / sec_mixed,
+                "sigma_reduced_tflops": tf,
+                "sigma_reduced_roofline_frac": tf / peak,
+                "sigma_reduced_peak_tflops": peak,
+                "sigma_reduced_calls": sm["fp32"]["calls"],
+                "sigma_fp64_calls": sm["n_sigma"],
+                "sigma_seconds_per_sweep": (sm["fp32"]["t"] + sm["t_sigma"]) / args.steps,
+                "sigma_seconds_per_sweep_fp64_path": st["t_sigma"] / args.steps,
+                "energy_last_sweep": emix[-1],
+                "abs_dE_last_sweep_vs_fp64": abs(emix[-1] - energies[-1]),
+                "max_abs_dE_per_micro_iteration_vs_fp64": d_micro,
+            }
+            if rdm64 is not None:
+                m1, m2, _ = g.rdm()
+                rec["rdm_max_abs_error_vs_fp64"] = {"gamma": float(np.abs(m1 - rdm64[0]).max()),
+                                                    "Gamma": float(np.abs(m2 - rdm64[1]).max())}
+            line[key] = rec
     g.close()
     if args.batch_n > 0:
         line["batch"] = batch_bench(args.batch_n, args.batch_seed, 1, args.mixed_tol)

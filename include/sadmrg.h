@@ -99,8 +99,13 @@ int sadmrg_set_davidson(sadmrg_ctx* ctx, double tol, int max_sub, int max_iter);
  *   of the vector and its preconditioned FP64 residual, two FP64 sigma
  *   products; the reported energy of the micro-iteration is the lower FP64
  *   Ritz value and the refined vector goes on to the decomposition.
- * sadmrg_sigma uses FP32 in mode 1.  SVD, truncation and renormalisation stay
- * FP64.  Errors: EINVAL. */
+ * mode 2: as mode 1, but the Davidson sigma products are BF16x3 on the FP32
+ *   copies: each value is split into hi = bf16(x) and lo = bf16(x - hi), a
+ *   product is hi*hi + hi*lo + lo*hi on the BF16 matrix cores with FP32
+ *   accumulation (relative error about 2^-16); the stall test uses that
+ *   rounding level.
+ * sadmrg_sigma uses the reduced products in modes 1 and 2.  SVD, truncation
+ * and renormalisation stay FP64.  Errors: EINVAL. */
 int sadmrg_set_precision(sadmrg_ctx* ctx, int mode, double mixed_tol);
 
 /* Seed of the counter-based generator used for the random initial MPS. */

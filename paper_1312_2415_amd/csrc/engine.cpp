@@ -1141,8 +1141,8 @@ struct GemmList {
     int ntiles = 0, nwg = 0, nreds = 0;
     bool stream = false, f32 = false;
     int tag = 2;
-    void run(Stream st) const {
-      launch_gemm(tiles.p, tasks.p, wstart.p, nwg, stream, tag, f32, st);
+    void run(Stream st, bool bf3 = false) const {
+      launch_gemm(tiles.p, tasks.p, wstart.p, nwg, stream, tag, f32, st, f32 && bf3);
       launch_reduce(reds.p, nreds, f32, st);
     }
   };
@@ -1463,7 +1463,8 @@ struct PoolBind {
 struct DavState {
   double* xres = nullptr;  // normalised Ritz vector on exit
   double tol = 0.0;        // residual-norm tolerance
-  bool f32 = false;        // sigma with FP32 operands
+  bool f32 = false;        // sigma with FP32 operands (FP32 or BF16x3 products)
+  double eps = 6e-8;       // relative rounding of those products
   int ms = 2, k = 0, it = 1;
   double theta = 0.0, rbest = INFINITY;
   int stall = 0;
@@ -1596,7 +1597,7 @@ struct Engine {
   double noise = 0.0;
   double wd_prev = 0.0, wd_pass = 0.0;
   int64_t n_pass = 0;  // passes since the MPS was created or imported
-  int prec = 0;             // 0: FP64 sigma; 1: FP32 sigma in Davidson + FP64 Rayleigh quotient
+  int prec = 0;             // 0: FP64 sigma; 1 / 2: FP32 / BF16x3 sigma in Davidson + FP64 refinement
   double mixed_tol = 1e-5;  // Davidson tolerance of the FP32 phase
   int64_t n_sigma = 0;
   // Davidson work buffers
@@ -2805,9 +2806,10 @@ struct Engine {
       dev_zero(step.out.p, (size_t)std::max<int64_t>(step.n, 1) * 8, st);
     }
     void* e1 = dev_event_record(st);
-    p1.run(st);
+    const bool bf3 = f32 && prec == 2;
+    p1.run(st, bf3);
     void* e2 = dev_event_record(st);
-    launch_gemm(p2.tiles.p, p2.tasks.p, p2.wstart.p, p2.nwg, p2.stream, p2.tag, p2.f32, st);
+    launch_gemm(p2.tiles.p, p2.tasks.p, p2.wstart.p, p2.nwg, p2.stream, p2.tag, p2.f32, st, bf3);
     void* e3 = dev_event_record(st);
     launch_reduce(p2.reds.p, p2.nreds, p2.f32, st);
     if (f32) launch_cvt_f2d(step.out.p, (const float*)step.out32.p, step.n, st);
@@ -2856,6 +2858,9 @@ struct Engine {
     if (f32) launch_cvt_f2d(step.out.p, (const float*)step.out32.p, step.n, st);
     dev_d2d(y, step.out.p, (size_t)step.n * 8, st);
   }
+  // relative rounding of the reduced-precision sigma products: FP32 (2^-24),
+  // BF16x3 (the dropped lo*lo term and the split remainder, about 2^-16)
+  double reduced_eps() const { return prec == 2 ? 1.5e-5 : 6e-8; }
   // plan the accumulating pass left open by prepare() (target: cost per
   // workgroup range; 0 = this problem alone)
   void plan_pass2(double target) {
@@ -2877,6 +2882,7 @@ struct Engine {
     D[0].xres = xres;
     D[0].tol = tol;
     D[0].f32 = f32;
+    D[0].eps = reduced_eps();
     davidson_lockstep(E, D, nullptr, *stage);
     *iters = D[0].it;
     *conv = D[0].conv;
@@ -3129,8 +3135,8 @@ struct Engine {
     int its = 0;
     bool conv = false;
     double th;
-    if (prec == 1) {
-      // FP32 sigma until the residual reaches mixed_tol, then one FP64
+    if (prec >= 1) {
+      // FP32 (or BF16x3) sigma until the residual reaches mixed_tol, then one FP64
       // Davidson step from that vector (two FP64 sigma): the reported energy
       // is the FP64 Ritz value of the refined vector
       th = davidson(x.p, &its, &conv, std::max(dav_tol, mixed_tol), true);
@@ -3383,8 +3389,9 @@ struct BatchLaunch {
     const int* e2 = stage.up(b2);
     const int* er = stage.up(br);
     void* t0 = dev_event_record(st);
-    launch_gemm_seg(d1, e1, (int)s1.size(), nw1, false, use32, st);
-    launch_gemm_seg(d2, e2, (int)s2.size(), nw2, stream2, use32, st);
+    const bool bf3 = use32 && !E.empty() && E[0]->prec == 2;
+    launch_gemm_seg(d1, e1, (int)s1.size(), nw1, false, use32, st, bf3);
+    launch_gemm_seg(d2, e2, (int)s2.size(), nw2, stream2, use32, st, bf3);
     launch_reduce_seg(dr, er, (int)sr.size(), nr, use32, st);
     void* t1 = dev_event_record(st);
     (use32 ? ev32 : ev64).push_back({t0, t1});
@@ -3684,10 +3691,10 @@ static void davidson_lockstep(const std::vector<Engine*>& E, std::vector<DavStat
         fin.push_back(k);
         continue;
       }
-      // FP32 sigma has a residual floor set by its rounding (observed near
-      // 10 eps_32 |theta|): close to it, stop when the residual has not
-      // improved by 10 % for four iterations
-      if (d.f32 && rn < 100.0 * 6e-8 * std::max(1.0, std::fabs(d.theta))) {
+      // reduced-precision sigma has a residual floor set by its rounding
+      // (observed near 10 eps |theta| for FP32): close to it, stop when the
+      // residual has not improved by 10 % for four iterations
+      if (d.f32 && rn < 100.0 * d.eps * std::max(1.0, std::fabs(d.theta))) {
         if (rn < 0.9 * d.rbest) {
           d.rbest = rn;
           d.stall = 0;
@@ -3780,7 +3787,7 @@ static bool batch_sweep(const std::vector<Engine*>& E, const std::vector<int>& D
   }
   emin.assign(n, INFINITY);
   const int prec = E[0]->prec;
-  const bool use32 = prec == 1;
+  const bool use32 = prec >= 1;
   for (int r = 0; r < maxs; ++r) {
     std::vector<Engine*> ea;
     std::vector<size_t> ka;
@@ -3833,6 +3840,7 @@ static bool batch_sweep(const std::vector<Engine*>& E, const std::vector<int>& D
       ds[j].xres = xb[j].p;
       ds[j].tol = use32 ? std::max(ea[j]->dav_tol, ea[j]->mixed_tol) : ea[j]->dav_tol;
       ds[j].f32 = use32;
+      ds[j].eps = ea[j]->reduced_eps();
     }
     davidson_lockstep(ea, ds, &bl, bl.stage);
     bl.w_davidson += lap();
@@ -4518,7 +4526,8 @@ int sadmrg_get_s2(sadmrg_ctx* ctx, double* s2) {
 
 int sadmrg_set_precision(sadmrg_ctx* ctx, int mode, double mixed_tol) {
   return guard(ctx, [&] {
-    if (mode != 0 && mode != 1) sadmrg::fail(SADMRG_EINVAL, "precision mode must be 0 (FP64) or 1 (FP32 mixed)");
+    if (mode < 0 || mode > 2)
+      sadmrg::fail(SADMRG_EINVAL, "precision mode must be 0 (FP64), 1 (FP32 mixed) or 2 (BF16x3 mixed)");
     if (mode > 0 && !(mixed_tol > 0.0)) sadmrg::fail(SADMRG_EINVAL, "mixed_tol must be positive");
     ctx->e.prec = mode;
     if (mode > 0) ctx->e.mixed_tol = mixed_tol;

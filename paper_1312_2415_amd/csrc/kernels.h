@@ -141,8 +141,10 @@ struct GTask {
 // tag: 0 = sigma pass 1, 1 = sigma pass 2, 2 = other (separate kernel symbols for profiling)
 // f32: operands, outputs and partial tiles are float arrays (the record
 // pointers keep their double* type and are reinterpreted).
+// bf3 (with f32): BF16x3 products on the FP32 data (hi*hi + hi*lo + lo*hi of
+// the BF16 splits, FP32 accumulation).
 void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag, bool f32,
-                 Stream st);
+                 Stream st, bool bf3 = false);
 // Number of compute units of the current device.
 int dev_cu_count();
 void launch_reduce(const RTile* reds, int nred, bool f32, Stream st);
@@ -156,7 +158,8 @@ struct GSeg {
   const int* wstart;
   const RTile* reds;
 };
-void launch_gemm_seg(const GSeg* segs, const int* base, int nseg, int nwg, bool stream, bool f32, Stream st);
+void launch_gemm_seg(const GSeg* segs, const int* base, int nseg, int nwg, bool stream, bool f32, Stream st,
+                     bool bf3 = false);
 void launch_reduce_seg(const GSeg* segs, const int* base, int nseg, int nred, bool f32, Stream st);
 // out[j] = sum_{r < n_j} p_j[r * (ld_j + 1)]  (traces of square sub-blocks)
 struct TraceJob {

@@ -432,6 +432,58 @@ __device__ inline void g_mac_any(typename GT<T>::Acc (&acc)[4], const T* sA, con
     g_mac<T, 1>(acc, sA, sB, np, r0, li, lk);
 }
 
+// BF16x3 products on FP32 data: every staged value x is split at the LDS
+// store into hi = bf16(x) and lo = bf16(x - hi) (round to nearest; x = hi +
+// lo to about 2^-17 |x|), and a product is hi*hi + hi*lo + lo*hi (the lo*lo
+// term, about 2^-16 of it, is dropped) with FP32 accumulation, on the
+// 16x16x32 BF16 MFMA.  The four LDS planes (A hi, A lo, B hi, B lo) are
+// [mn][k] with row stride SLDB; lane group lk feeds k = 8 lk .. 8 lk + 7 of
+// a chunk to the MFMA, the same k slots for both operands.
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+constexpr int SLDB = 40;                // bf16 row stride (80 B: 16-byte aligned rows)
+constexpr int BF_PLANE = 64 * SLDB;     // elements of one plane
+__device__ inline int g_lds_bf(bool kfast, int tid, int q) {
+  return kfast ? (tid / 32 + 8 * q) * SLDB + tid % 32 : (tid % 64) * SLDB + tid / 64 + 4 * q;
+}
+__device__ inline void g_store_bf3(const float (&ra)[8], const float (&rb)[8], double coef, int flags, __bf16* sH,
+                                   int tid) {
+  const bool kfa = !(flags & GT_TRANS_A), kfb = (flags & GT_TRANS_B) != 0;
+  const float c = (float)coef;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const float a = c * ra[q], b = rb[q];
+    const __bf16 ah = (__bf16)a, bh = (__bf16)b;
+    const int ia = g_lds_bf(kfa, tid, q), ib = g_lds_bf(kfb, tid, q);
+    sH[ia] = ah;
+    sH[BF_PLANE + ia] = (__bf16)(a - (float)ah);
+    sH[2 * BF_PLANE + ib] = bh;
+    sH[3 * BF_PLANE + ib] = (__bf16)(b - (float)bh);
+  }
+}
+template <int NCB>
+__device__ inline void g_mac_bf3(f4_t (&acc)[4], const __bf16* sH, int r0, int li, int lk) {
+  const int oa = (r0 + li) * SLDB + 8 * lk;
+  const bf8_t ah = *(const bf8_t*)(sH + oa), al = *(const bf8_t*)(sH + BF_PLANE + oa);
+#pragma unroll
+  for (int b = 0; b < NCB; ++b) {
+    const int ob = (li + 16 * b) * SLDB + 8 * lk;
+    const bf8_t bh = *(const bf8_t*)(sH + 2 * BF_PLANE + ob), bl = *(const bf8_t*)(sH + 3 * BF_PLANE + ob);
+    acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[b], 0, 0, 0);
+    acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[b], 0, 0, 0);
+    acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[b], 0, 0, 0);
+  }
+}
+__device__ inline void g_mac_bf3_any(f4_t (&acc)[4], const __bf16* sH, int ncb, int r0, int li, int lk) {
+  if (ncb == 4)
+    g_mac_bf3<4>(acc, sH, r0, li, lk);
+  else if (ncb == 3)
+    g_mac_bf3<3>(acc, sH, r0, li, lk);
+  else if (ncb == 2)
+    g_mac_bf3<2>(acc, sH, r0, li, lk);
+  else
+    g_mac_bf3<1>(acc, sH, r0, li, lk);
+}
+
 struct GOut {  // what the epilogue of a tile needs
   double* out;
   double* part;
@@ -465,12 +517,14 @@ __device__ inline void g_write(const GOut& tile, const typename GT<T>::Acc (&acc
 // the hardware dispatcher balances short, independent tiles best.
 // TAG only separates the symbols of the launch sites for profiling:
 // 0 = sigma pass 1, 1 = sigma pass 2, 2 = renormalisation / other products.
-template <typename T>
+template <typename T, bool BF3 = false>
 __device__ __forceinline__ void gemm_tile_body(const GTile* __restrict__ tiles, const GTask* __restrict__ tasks,
                                                const unsigned bid) {
   typedef typename GT<T>::Acc Acc;
-  __shared__ __attribute__((aligned(16))) T sA[64 * GT<T>::SLD];
-  __shared__ __attribute__((aligned(16))) T sB[64 * GT<T>::SLD];
+  static_assert(!BF3 || sizeof(T) == 4, "BF16x3 products take FP32 data");
+  __shared__ __attribute__((aligned(16))) T sA[BF3 ? 4 : 64 * GT<T>::SLD];
+  __shared__ __attribute__((aligned(16))) T sB[BF3 ? 4 : 64 * GT<T>::SLD];
+  __shared__ __attribute__((aligned(16))) __bf16 sH[BF3 ? 4 * BF_PLANE : 8];
   const GTile tile = tiles[bid];
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid / 64);  // wave index, scalar
@@ -512,12 +566,17 @@ __device__ __forceinline__ void gemm_tile_body(const GTile* __restrict__ tiles, 
     };
     next();
     while (true) {
-      g_store<T>(ra, rb, coef, flags, sA, sB, tid);
+      if constexpr (BF3)
+        g_store_bf3(ra, rb, coef, flags, sH, tid);
+      else
+        g_store<T>(ra, rb, coef, flags, sA, sB, tid);
       const int np = (kc + 4 * GT<T>::VEC - 1) / (4 * GT<T>::VEC);
       __syncthreads();
       const bool more = t < tile.t1;
       if (more) next();
-      if (active) {
+      if constexpr (BF3) {
+        if (active) g_mac_bf3_any(acc, sH, ncb, r0, li, lk);
+      } else if (active) {
         if (ncb == 4)
           g_mac<T, 4>(acc, sA, sB, np, r0, li, lk);
         else if (ncb == 3)
@@ -539,16 +598,24 @@ __global__ __launch_bounds__(256, 4) void gemm_tile_kernel(const GTile* __restri
                                                            const GTask* __restrict__ tasks) {
   gemm_tile_body<T>(tiles, tasks, blockIdx.x);
 }
+// the same with BF16x3 products on FP32 data
+template <int TAG>
+__global__ __launch_bounds__(256, 4) void gemm_tile_bf3_kernel(const GTile* __restrict__ tiles,
+                                                               const GTask* __restrict__ tasks) {
+  gemm_tile_body<float, true>(tiles, tasks, blockIdx.x);
+}
 
 // Workgroup g streams the tiles [wstart[g], wstart[g+1]).
 // TAG only separates the symbols of the launch sites for profiling:
 // 0 = sigma pass 1, 1 = sigma pass 2, 2 = renormalisation / other products.
-template <typename T>
+template <typename T, bool BF3 = false>
 __device__ __forceinline__ void gemm_stream_body(const GTile* __restrict__ tiles, const GTask* __restrict__ tasks,
                                                  const int* __restrict__ wstart, const unsigned bid) {
   typedef typename GT<T>::Acc Acc;
-  __shared__ __attribute__((aligned(16))) T sA[64 * GT<T>::SLD];
-  __shared__ __attribute__((aligned(16))) T sB[64 * GT<T>::SLD];
+  static_assert(!BF3 || sizeof(T) == 4, "BF16x3 products take FP32 data");
+  __shared__ __attribute__((aligned(16))) T sA[BF3 ? 4 : 64 * GT<T>::SLD];
+  __shared__ __attribute__((aligned(16))) T sB[BF3 ? 4 : 64 * GT<T>::SLD];
+  __shared__ __attribute__((aligned(16))) __bf16 sH[BF3 ? 4 * BF_PLANE : 8];
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid / 64);  // wave index, scalar
   const int l = tid % 64;
@@ -625,7 +692,12 @@ __device__ __forceinline__ void gemm_stream_body(const GTile* __restrict__ tiles
   for (int b = 0; b < 4; ++b) acc[b] = (Acc){0, 0, 0, 0};
   issue();
   while (true) {
-    if (kc > 0) g_store<T>(ra, rb, coef, flags, sA, sB, tid);
+    if (kc > 0) {
+      if constexpr (BF3)
+        g_store_bf3(ra, rb, coef, flags, sH, tid);
+      else
+        g_store<T>(ra, rb, coef, flags, sA, sB, tid);
+    }
     const GOut mt = MT;
     const int kcc = kc;
     const bool mlast = last;
@@ -633,7 +705,11 @@ __device__ __forceinline__ void gemm_stream_body(const GTile* __restrict__ tiles
     const bool more = ft < fe;
     if (more) issue();
     const bool active = r0 < mt.rows;
-    if (active && kcc > 0) g_mac_any<T>(acc, sA, sB, kcc, (mt.cols + 15) / 16, r0, li, lk);
+    if constexpr (BF3) {
+      if (active && kcc > 0) g_mac_bf3_any(acc, sH, (mt.cols + 15) / 16, r0, li, lk);
+    } else {
+      if (active && kcc > 0) g_mac_any<T>(acc, sA, sB, kcc, (mt.cols + 15) / 16, r0, li, lk);
+    }
     if (mlast) {
       if (active) g_write<T>(mt, acc, r0, li, lk);
 #pragma unroll
@@ -649,6 +725,12 @@ __global__ __launch_bounds__(256, 3) void gemm_stream_kernel(const GTile* __rest
                                                              const GTask* __restrict__ tasks,
                                                              const int* __restrict__ wstart) {
   gemm_stream_body<T>(tiles, tasks, wstart, blockIdx.x);
+}
+template <int TAG>
+__global__ __launch_bounds__(256, 3) void gemm_stream_bf3_kernel(const GTile* __restrict__ tiles,
+                                                                 const GTask* __restrict__ tasks,
+                                                                 const int* __restrict__ wstart) {
+  gemm_stream_body<float, true>(tiles, tasks, wstart, blockIdx.x);
 }
 
 // Several plans in one launch (independent problems batched together): plan s
@@ -678,21 +760,40 @@ struct GSegDev {
 };
 static_assert(sizeof(GSegDev) == sizeof(GSeg), "descriptor layout");
 
-template <typename T>
-__global__ __launch_bounds__(256, 4) void gemm_tile_seg_kernel(const GSeg* __restrict__ segs,
+template <typename T, bool BF3>
+__device__ __forceinline__ void gemm_tile_seg_body(const GSeg* __restrict__ segs,
                                                                const int* __restrict__ base, int nseg) {
   const int s = seg_find(base, nseg, blockIdx.x);
   const GSegDev* const d = (const GSegDev*)segs;
-  gemm_tile_body<T>((const GTile*)d[s].tiles, (const GTask*)d[s].tasks, blockIdx.x - base[s]);
+  gemm_tile_body<T, BF3>((const GTile*)d[s].tiles, (const GTask*)d[s].tasks, blockIdx.x - base[s]);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256, 3) void gemm_stream_seg_kernel(const GSeg* __restrict__ segs,
+template <typename T, bool BF3>
+__device__ __forceinline__ void gemm_stream_seg_body(const GSeg* __restrict__ segs,
                                                                  const int* __restrict__ base, int nseg) {
   const int s = seg_find(base, nseg, blockIdx.x);
   const GSegDev* const d = (const GSegDev*)segs;
-  gemm_stream_body<T>((const GTile*)d[s].tiles, (const GTask*)d[s].tasks, (const int*)d[s].wstart,
+  gemm_stream_body<T, BF3>((const GTile*)d[s].tiles, (const GTask*)d[s].tasks, (const int*)d[s].wstart,
                       blockIdx.x - base[s]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 4) void gemm_tile_seg_kernel(const GSeg* __restrict__ segs,
+                                                               const int* __restrict__ base, int nseg) {
+  gemm_tile_seg_body<T, false>(segs, base, nseg);
+}
+__global__ __launch_bounds__(256, 4) void gemm_tile_seg_bf3_kernel(const GSeg* __restrict__ segs,
+                                                                   const int* __restrict__ base, int nseg) {
+  gemm_tile_seg_body<float, true>(segs, base, nseg);
+}
+template <typename T>
+__global__ __launch_bounds__(256, 3) void gemm_stream_seg_kernel(const GSeg* __restrict__ segs,
+                                                                 const int* __restrict__ base, int nseg) {
+  gemm_stream_seg_body<T, false>(segs, base, nseg);
+}
+__global__ __launch_bounds__(256, 3) void gemm_stream_seg_bf3_kernel(const GSeg* __restrict__ segs,
+                                                                     const int* __restrict__ base, int nseg) {
+  gemm_stream_seg_body<float, true>(segs, base, nseg);
 }
 
 template <typename T>
@@ -714,20 +815,49 @@ static void launch_gemm_t(const GTile* tiles, const GTask* tasks, const int* wst
       hipLaunchKernelGGL((gemm_tile_kernel<T, 2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks);
   }
 }
+static void launch_gemm_bf3(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag,
+                            hipStream_t hs) {
+  if (stream) {
+    if (tag == 0)
+      hipLaunchKernelGGL((gemm_stream_bf3_kernel<0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+    else if (tag == 1)
+      hipLaunchKernelGGL((gemm_stream_bf3_kernel<1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+    else
+      hipLaunchKernelGGL((gemm_stream_bf3_kernel<2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+  } else {
+    if (tag == 0)
+      hipLaunchKernelGGL((gemm_tile_bf3_kernel<0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+    else if (tag == 1)
+      hipLaunchKernelGGL((gemm_tile_bf3_kernel<1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+    else
+      hipLaunchKernelGGL((gemm_tile_bf3_kernel<2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+  }
+}
 
 void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag, bool f32,
-                 Stream st) {
+                 Stream st, bool bf3) {
   if (nwg <= 0) return;
-  if (f32)
+  if (f32 && bf3)
+    launch_gemm_bf3(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st);
+  else if (f32)
     launch_gemm_t<float>(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st);
   else
     launch_gemm_t<double>(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st);
   check_launch("gemm");
 }
 
-void launch_gemm_seg(const GSeg* segs, const int* base, int nseg, int nwg, bool stream, bool f32, Stream st) {
+void launch_gemm_seg(const GSeg* segs, const int* base, int nseg, int nwg, bool stream, bool f32, Stream st,
+                     bool bf3) {
   if (nwg <= 0 || nseg <= 0) return;
   const hipStream_t hs = (hipStream_t)st;
+  if (f32 && bf3) {
+    if (stream)
+      hipLaunchKernelGGL(gemm_stream_seg_bf3_kernel, dim3(nwg), dim3(256), 0, hs, segs, base, nseg);
+    else
+      hipLaunchKernelGGL(gemm_tile_seg_bf3_kernel, dim3(nwg), dim3(256), 0, hs, segs, base, nseg);
+    check_launch("gemm_seg");
+    return;
+  }
   if (stream) {
     if (f32)
       hipLaunchKernelGGL(gemm_stream_seg_kernel<float>, dim3(nwg), dim3(256), 0, hs, segs, base, nseg);

@@ -91,12 +91,76 @@ def test_mixed_sweep_energies_match_fp64_oracle(case):
     g.close()
 
 
+def test_bf16x3_sigma_within_its_rounding_of_oracle():
+    """Mode 2: BF16x3 products (hi*hi + hi*lo + lo*hi of the BF16 splits,
+    FP32 accumulation).  The sigma stays within a few hundred times the
+    products' 2^-16 relative rounding of the FP64 oracle, and is measurably
+    less exact than the FP32 products (so the BF16 path really ran)."""
+    L, N, twoS, group, irrep, D = 10, 10, 0, "D2h", 0, 30
+    I = make_integrals(L, group, 11)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    g = _gpu(L, group, I)
+    g.set_target(N, twoS, irrep)
+    worst32 = worst3 = 0.0
+    for i in range(L - 1):
+        print(f"bf16x3 step {i}", flush=True)
+        g.mps_import(sd.export_blob(dm))
+        g.prepare_step()
+        desc, n = g.psi_layout()
+        El, Er, Xe, Ye, secs = dm.enlarged(i)
+        He = sd.Heff(P, Xe, Ye, secs)
+        shapes = {m: (El.dim[m], Er.dim[m]) for m in secs}
+        x = np.random.default_rng(200 + i).normal(size=n)
+        ref = sd.flatten(He.apply(sd.unflatten(x, shapes, secs)), secs)
+        scale = np.abs(ref).max()
+        g.set_precision(2)
+        e3 = np.abs(g.sigma(x) - ref).max() / scale
+        g.set_precision(1)
+        e32 = np.abs(g.sigma(x) - ref).max() / scale
+        g.set_precision(0)
+        assert e3 <= 5e-3
+        worst3, worst32 = max(worst3, e3), max(worst32, e32)
+        if i < L - 2:
+            dm.micro(i, D, "right")
+    assert worst3 > 10 * worst32 > 0.0
+    g.close()
+
+
+def test_bf16x3_mixed_sweeps_match_fp64_oracle():
+    L, N, twoS, group, irrep, D, nsw, seed = 10, 6, 2, "D2h", 0, 24, 2, 5
+    I = make_integrals(L, group, seed)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    blob = sd.export_blob(dm)
+    for _ in range(nsw):
+        dm.sweep(D)
+    g = _gpu(L, group, I)
+    g.set_target(N, twoS, irrep)
+    g.set_davidson(1e-9, 32, 200)
+    g.set_precision(2, 1e-5)
+    g.mps_import(blob)
+    for s in range(nsw):
+        print(f"bf16x3 sweep {s}", flush=True)
+        g.sweep(D)
+    got, ref = g.trace(), np.array(dm.stats.energies)
+    assert len(got) == len(ref)
+    assert np.abs(got[-(L - 1):] - ref[-(L - 1):]).max() <= 1e-6
+    assert abs(g.energy()[0] - dm.emin) <= 1e-6
+    assert g.stats()["fp32"]["calls"] > 0
+    g.close()
+
+
 def test_precision_mode_is_validated():
     I = make_integrals(4, "C1", 3)
     g = _gpu(4, "C1", I)
     from paper_1312_2415_amd.binding import SadmrgError
     with pytest.raises(SadmrgError):
-        g.set_precision(2)
+        g.set_precision(3)
+    with pytest.raises(SadmrgError):
+        g.set_precision(-1)
     with pytest.raises(SadmrgError):
         g.set_precision(1, 0.0)
     g.set_precision(1, 1e-6)
