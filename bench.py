@@ -236,6 +236,7 @@ def main():
     ap.add_argument("--no-rdm", action="store_true")
     ap.add_argument("--batch-n", type=int, default=64, help="independent problems of the lockstep batch; 0 = skip")
     ap.add_argument("--batch-seed", type=int, default=4)
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -267,6 +268,16 @@ def main():
         print(f"warmup sweep {w + 1}/{args.warmup} D={args.D} E={e:.10f} {time.time() - t:.1f}s", file=sys.stderr,
               flush=True)
     start = g.mps_export()  # the mixed sweeps restart from here
+    # launch-shape autotuning on a middle step of the warmed-up MPS
+    tune = None
+    if not args.no_autotune:
+        g.advance(args.D, L // 2 - 1)
+        g.prepare_step()
+        chosen, table = g.autotune(5)
+        g.mps_import(start)
+        tune = {"step": L // 2 - 1, "chosen_gpc_pass1_pass2": list(chosen),
+                "candidates_ms_per_sigma": {f"{a},{b}": ms for (a, b), ms in table}}
+        print(f"autotune: pass-1/pass-2 workgroups per CU {chosen}", file=sys.stderr, flush=True)
     import numpy as np
     g.stats_reset()
     t0 = time.perf_counter()
@@ -321,6 +332,7 @@ def main():
                              "share_of_sigma_time": st[k]["t"] / max(st["t_sigma"], 1e-12)}
                          for k in ("pass1", "pass2")},
         "copy_probe_GBps": copy_gbps,
+        "autotune": tune,
         "host_phase_seconds_per_sweep": {k: v / args.steps for k, v in st["phases"].items()},
         "davidson_sigma_seconds_per_sweep": st["t_sigma"] / args.steps,
         "max_enlarged_bytes": st["max_enlarged_bytes"],

@@ -150,6 +150,24 @@ int sadmrg_sweep(sadmrg_ctx* ctx, int D, double* e_min);
  * ENOMEM, EDEVICE. */
 int sadmrg_batch_sweep(sadmrg_ctx* const* ctxs, int n, const int* D, double* e_min, double* stats);
 
+/* Tune the launch shape of the sigma product on the prepared step (call
+ * after sadmrg_prepare_step; the paper's parallelisation over sparse blocks,
+ * section "DMRG" of the library description, here as grouped GEMM launches).
+ * Twelve candidate plans are timed, each over `reps` FP64 sigma calls on a
+ * fixed pseudo-random vector: the first GEMM pass with one output tile per
+ * workgroup or 8 cost-balanced ranges per compute unit, times the
+ * accumulating pass with 8, 12, 16, 24, 32 or 48 ranges per compute unit
+ * (defaults: one tile per workgroup, 24 ranges).  The fastest pair is kept
+ * for this context (later steps are planned with it) and the step is
+ * re-planned.  Results do not depend on the choice beyond the summation
+ * order of cut tiles.  *gpc1, *gpc2 (may be NULL): the chosen pair (0 = one
+ * tile per workgroup); table[36] (may be NULL): the candidates' pairs
+ * (table[2c], table[2c+1]) and mean ms per sigma (table[24 + c]).  The
+ * sigma statistics exclude the timing calls; the content of the step's
+ * input vector is overwritten.  Errors: EINVAL (no prepared step, reps < 1),
+ * ENOMEM, EDEVICE. */
+int sadmrg_autotune(sadmrg_ctx* ctx, int reps, int* gpc1, int* gpc2, double* table);
+
 /* Free and total bytes of device memory on a device (the library's cached
  * blocks count as used).  Errors: EINVAL, EDEVICE. */
 int sadmrg_device_memory(int device, size_t* free_bytes, size_t* total_bytes);

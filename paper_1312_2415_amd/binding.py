@@ -63,6 +63,7 @@ def load_library(path: str | None = None):
         "sadmrg_stats_phases": (c_int, [c_vp, P(c_dbl)]),
         "sadmrg_set_enlarge_cache": (c_int, [c_vp, c_int]),
         "sadmrg_device_memory": (c_int, [c_int, P(c_sz), P(c_sz)]),
+        "sadmrg_autotune": (c_int, [c_vp, c_int, P(c_int), P(c_int), P(c_dbl)]),
         "sadmrg_stats_bytes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_passes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_mixed": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl)]),
@@ -272,6 +273,14 @@ class SaDMRG:
         v = ctypes.c_double()
         self._chk(self.lib.sadmrg_get_s2(self.h, ctypes.byref(v)))
         return v.value
+
+    def autotune(self, reps: int = 5):
+        """Tune the sigma launch shape on the prepared step (sadmrg_autotune).
+        Returns ((gpc1, gpc2), [((g1, g2), ms), ...])."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        t = (ctypes.c_double * 36)()
+        self._chk(self.lib.sadmrg_autotune(self.h, int(reps), ctypes.byref(a), ctypes.byref(b), t))
+        return (a.value, b.value), [((int(t[2 * c]), int(t[2 * c + 1])), t[24 + c]) for c in range(12)]
 
     def set_enlarge_cache(self, on: bool):
         self._chk(self.lib.sadmrg_set_enlarge_cache(self.h, int(bool(on))))

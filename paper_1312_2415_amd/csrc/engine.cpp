@@ -1309,7 +1309,7 @@ struct OutBlk {
 #define GEMM_GPC_PASS1 0
 #endif
 #ifndef GEMM_GPC_PASS2
-#define GEMM_GPC_PASS2 12
+#define GEMM_GPC_PASS2 24
 #endif
 
 struct TwoPass {
@@ -1330,7 +1330,8 @@ struct TwoPass {
 // keep2: hand the accumulating pass's product list to the caller instead of
 // planning it (a batch plans it with the cost target of the whole batch).
 static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Triple>& tr, TwoPass& tp, Stream st,
-                           bool sigma = false, GemmList* keep2 = nullptr) {
+                           bool sigma = false, GemmList* keep2 = nullptr, int gpc1 = GEMM_GPC_PASS1,
+                           int gpc2 = GEMM_GPC_PASS2) {
   std::vector<int64_t> slot(tr.size(), -1);
   int64_t ws = 0;
   for (size_t i = 0; i < tr.size(); ++i)
@@ -1378,11 +1379,11 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
   tp.p2.tag = sigma ? 1 : 2;
   tp.nprod = (int64_t)tr.size();
   const int tag1 = tp.p1.tag, tag2 = tp.p2.tag;
-  g1.plan(tp.p1, st, GEMM_GPC_PASS1);
+  g1.plan(tp.p1, st, gpc1);
   if (keep2)
     *keep2 = std::move(g2);
   else
-    g2.plan(tp.p2, st, GEMM_GPC_PASS2);
+    g2.plan(tp.p2, st, gpc2);
   tp.p1.tag = tag1;
   tp.p2.tag = tag2;
 }
@@ -1606,6 +1607,9 @@ struct Engine {
   std::unique_ptr<Staging> stage;  // job arrays of this engine's own Davidson
   DevPool* pool = nullptr;  // the context's device-memory pool
   bool defer_p2 = false;    // prepare() leaves the accumulating pass unplanned
+  // workgroups per CU of the sigma plans (0 = one tile per workgroup), set by
+  // sadmrg_autotune
+  int gpc1 = GEMM_GPC_PASS1, gpc2 = GEMM_GPC_PASS2;
   // Enlarged blocks kept from the previous pass (section "Sweeping"): while
   // a left-to-right pass renews the left blocks, the right blocks are the
   // ones the previous right-to-left pass built, so the enlargement of the
@@ -2537,7 +2541,7 @@ struct Engine {
     bytes += 16.0 * step.n;
     t_phase[PH_TASKS] += std::chrono::duration<double>(std::chrono::steady_clock::now() - tt0).count();
     PhaseTimer pt(t_phase[PH_PLAN]);
-    build_two_pass(outs, trs, step.plan, st, true, defer_p2 ? &step.g2 : nullptr);
+    build_two_pass(outs, trs, step.plan, st, true, defer_p2 ? &step.g2 : nullptr, gpc1, gpc2);
     step.p2_pending = defer_p2;
     step.trs = trs;
     step.flops = step.plan.flops;
@@ -2858,6 +2862,57 @@ struct Engine {
     if (f32) launch_cvt_f2d(step.out.p, (const float*)step.out32.p, step.n, st);
     dev_d2d(y, step.out.p, (size_t)step.n * 8, st);
   }
+  // Pick the sigma plans' workgroups per CU by timing the prepared step:
+  // every candidate pair (first pass: one tile per workgroup or 8 ranges per
+  // CU; accumulating pass: 8..48 ranges per CU) is planned and its FP64 sigma
+  // timed over `reps` calls; the fastest pair is kept for this context and
+  // the step is re-planned with it.  out[2 * c], out[2 * c + 1]: the pair's
+  // gpc values, out[2 * ncand + c]: its mean ms per sigma.
+  static constexpr int TUNE_G1[2] = {0, 8};
+  static constexpr int TUNE_G2[6] = {8, 12, 16, 24, 32, 48};
+  static constexpr int TUNE_N = 12;
+  void autotune(int reps, double* out) {
+    if (step.i < 0 || !step.X || !step.Y) fail(-1, "no prepared step");
+    if (reps < 1) fail(-1, "reps must be positive");
+    const int ns = (int)step.psi.sec.size();
+    std::vector<OutBlk> outs(ns);
+    for (int m = 0; m < ns; ++m) outs[m] = {step.out.p + step.off[m], step.dx[m], step.dy[m], step.dy[m]};
+    launch_fill_uniform(step.in.p, step.n, 99, 0x5455, st);  // timing input
+    const double ts = t_sigma, fs = f_sigma, tp1 = t_pass1, tp2 = t_pass2, fp1 = f_pass1, fp2 = f_pass2,
+                 bp1 = b_pass1, bp2 = b_pass2, bs = b_sigma;
+    const int64_t nsg = n_sigma, np1 = n_pass1, np2 = n_pass2;
+    int best = -1;
+    double best_ms = INFINITY;
+    for (int c = 0; c < TUNE_N; ++c) {
+      const int g1 = TUNE_G1[c / 6], g2 = TUNE_G2[c % 6];
+      TwoPass tp;
+      build_two_pass(outs, step.trs, tp, st, true, nullptr, g1, g2);
+      std::swap(tp, step.plan);
+      sigma_fixed(false);  // warm-up
+      const double t0 = t_sigma;
+      for (int r = 0; r < reps; ++r) sigma_fixed(false);
+      const double ms = 1e3 * (t_sigma - t0) / reps;
+      std::swap(tp, step.plan);
+      if (out) {
+        out[2 * c] = g1;
+        out[2 * c + 1] = g2;
+        out[2 * TUNE_N + c] = ms;
+      }
+      if (ms < best_ms) best_ms = ms, best = c;
+    }
+    // the timing calls do not count in the statistics
+    t_sigma = ts, f_sigma = fs, t_pass1 = tp1, t_pass2 = tp2, f_pass1 = fp1, f_pass2 = fp2;
+    b_pass1 = bp1, b_pass2 = bp2, b_sigma = bs, n_sigma = nsg, n_pass1 = np1, n_pass2 = np2;
+    gpc1 = TUNE_G1[best / 6];
+    gpc2 = TUNE_G2[best % 6];
+    TwoPass tp;
+    build_two_pass(outs, step.trs, tp, st, true, nullptr, gpc1, gpc2);
+    std::swap(tp, step.plan);
+    step.flops = step.plan.flops;
+    step.f32_ready = false;
+    dev_sync(st);
+  }
+
   // relative rounding of the reduced-precision sigma products: FP32 (2^-24),
   // BF16x3 (the dropped lo*lo term and the split remainder, about 2^-16)
   double reduced_eps() const { return prec == 2 ? 1.5e-5 : 6e-8; }
@@ -2866,7 +2921,7 @@ struct Engine {
   void plan_pass2(double target) {
     if (!step.p2_pending) return;
     const int tag = step.plan.p2.tag;
-    step.g2.plan(step.plan.p2, st, GEMM_GPC_PASS2, target);
+    step.g2.plan(step.plan.p2, st, gpc2, target);
     step.plan.p2.tag = tag;
     step.g2 = GemmList();
     step.p2_pending = false;
@@ -3829,7 +3884,8 @@ static bool batch_sweep(const std::vector<Engine*>& E, const std::vector<int>& D
     double tot = 0.0;
     for (Engine* e : ea)
       if (e->step.p2_pending) tot += e->step.g2.total_cost();
-    const double target = GEMM_GPC_PASS2 > 0 ? tot / ((double)GEMM_GPC_PASS2 * GemmList::cus()) : 0.0;
+    const int gpc2 = E[0]->gpc2;
+    const double target = gpc2 > 0 ? tot / ((double)gpc2 * GemmList::cus()) : 0.0;
     for (Engine* e : ea) {
       PoolBind b(e->pool);
       e->plan_pass2(target);
@@ -4576,6 +4632,15 @@ int sadmrg_stats_reset(sadmrg_ctx* ctx) {
     E.n_sigma32 = 0;
     E.n_sigma = 0;
     for (double& t : E.t_phase) t = 0.0;
+    return 0;
+  });
+}
+
+int sadmrg_autotune(sadmrg_ctx* ctx, int reps, int* gpc1, int* gpc2, double* table) {
+  return guard(ctx, [&] {
+    ctx->e.autotune(reps, table);
+    if (gpc1) *gpc1 = ctx->e.gpc1;
+    if (gpc2) *gpc2 = ctx->e.gpc2;
     return 0;
   });
 }

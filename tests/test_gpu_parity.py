@@ -108,6 +108,42 @@ def test_kept_enlargements_give_identical_sweeps():
     assert np.abs(runs[0][-n:] - np.array(dm.stats.energies[:n])).max() <= 1e-8
 
 
+def test_autotuned_launch_shape_keeps_sigma_and_sweeps():
+    """The autotuner only changes how the products are spread over
+    workgroups: sigma stays within rounding of the untuned one and of the
+    oracle, and sweeps planned with the chosen shape match the oracle."""
+    L, N, twoS, group, irrep, D = 10, 8, 0, "D2h", 0, 30
+    I = make_integrals(L, group, 43)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    blob = sd.export_blob(dm)
+    g = _gpu(L, group, I)
+    g.set_target(N, twoS, irrep)
+    g.mps_import(blob)
+    g.prepare_step()
+    desc, n = g.psi_layout()
+    x = np.random.default_rng(5).normal(size=n)
+    y0 = g.sigma(x)
+    (g1, g2), table = g.autotune(3)
+    assert (g1, g2) in [t[0] for t in table]
+    assert g1 in (0, 8) and g2 in (8, 12, 16, 24, 32, 48) and len(table) == 12
+    assert all(ms > 0 for _, ms in table)
+    y1 = g.sigma(x)
+    assert np.abs(y1 - y0).max() <= 1e-12 * np.abs(y0).max()
+    El, Er, Xe, Ye, secs = dm.enlarged(0)
+    He = sd.Heff(P, Xe, Ye, secs)
+    shapes = {m: (El.dim[m], Er.dim[m]) for m in secs}
+    ref = sd.flatten(He.apply(sd.unflatten(x, shapes, secs)), secs)
+    assert np.abs(y1 - ref).max() <= 1e-10 * np.abs(ref).max()
+    g.mps_import(blob)
+    g.sweep(D)
+    dm.sweep(D)
+    got, refe = g.trace(), np.array(dm.stats.energies)
+    assert np.abs(got - refe).max() <= 1e-8
+    g.close()
+
+
 def test_config1_exact_at_fci_bond_dimension_with_own_initial_state():
     I = make_integrals(8, "C1", 1001)
     efci = fci_solve(I.h, I.eri, 8, 0)[0][0]
