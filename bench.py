@@ -237,6 +237,8 @@ def main():
     ap.add_argument("--batch-n", type=int, default=64, help="independent problems of the lockstep batch; 0 = skip")
     ap.add_argument("--batch-seed", type=int, default=4)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--gpc", default="", help="fixed sigma launch shape 'pass1,pass2' (workgroups per CU) "
+                                               "instead of autotuning")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -270,7 +272,12 @@ def main():
     start = g.mps_export()  # the mixed sweeps restart from here
     # launch-shape autotuning on a middle step of the warmed-up MPS
     tune = None
-    if not args.no_autotune:
+    if args.gpc:
+        g1, g2 = (int(v) for v in args.gpc.split(","))
+        g.set_launch_shape(g1, g2)
+        g.mps_import(start)
+        tune = {"fixed_gpc_pass1_pass2": [g1, g2]}
+    elif not args.no_autotune:
         g.advance(args.D, L // 2 - 1)
         g.prepare_step()
         chosen, table = g.autotune(5)

@@ -168,6 +168,12 @@ int sadmrg_batch_sweep(sadmrg_ctx* const* ctxs, int n, const int* D, double* e_m
  * ENOMEM, EDEVICE. */
 int sadmrg_autotune(sadmrg_ctx* ctx, int reps, int* gpc1, int* gpc2, double* table);
 
+/* Set the sigma plans' workgroups per compute unit directly (as
+ * sadmrg_autotune would choose them): gpc1 for the first GEMM pass, gpc2 for
+ * the accumulating pass, 0 = one output tile per workgroup, at most 64.
+ * Takes effect from the next prepared step.  Errors: EINVAL. */
+int sadmrg_set_launch_shape(sadmrg_ctx* ctx, int gpc1, int gpc2);
+
 /* Free and total bytes of device memory on a device (the library's cached
  * blocks count as used).  Errors: EINVAL, EDEVICE. */
 int sadmrg_device_memory(int device, size_t* free_bytes, size_t* total_bytes);

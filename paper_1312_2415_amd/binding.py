@@ -64,6 +64,7 @@ def load_library(path: str | None = None):
         "sadmrg_set_enlarge_cache": (c_int, [c_vp, c_int]),
         "sadmrg_device_memory": (c_int, [c_int, P(c_sz), P(c_sz)]),
         "sadmrg_autotune": (c_int, [c_vp, c_int, P(c_int), P(c_int), P(c_dbl)]),
+        "sadmrg_set_launch_shape": (c_int, [c_vp, c_int, c_int]),
         "sadmrg_stats_bytes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_passes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_mixed": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl)]),
@@ -281,6 +282,9 @@ class SaDMRG:
         t = (ctypes.c_double * 36)()
         self._chk(self.lib.sadmrg_autotune(self.h, int(reps), ctypes.byref(a), ctypes.byref(b), t))
         return (a.value, b.value), [((int(t[2 * c]), int(t[2 * c + 1])), t[24 + c]) for c in range(12)]
+
+    def set_launch_shape(self, gpc1: int, gpc2: int):
+        self._chk(self.lib.sadmrg_set_launch_shape(self.h, int(gpc1), int(gpc2)))
 
     def set_enlarge_cache(self, on: bool):
         self._chk(self.lib.sadmrg_set_enlarge_cache(self.h, int(bool(on))))

@@ -4636,6 +4636,17 @@ int sadmrg_stats_reset(sadmrg_ctx* ctx) {
   });
 }
 
+int sadmrg_set_launch_shape(sadmrg_ctx* ctx, int gpc1, int gpc2) {
+  return guard(ctx, [&] {
+    if (gpc1 < 0 || gpc1 > 64 || gpc2 < 0 || gpc2 > 64)
+      sadmrg::fail(SADMRG_EINVAL, "workgroups per CU must be in 0..64");
+    ctx->e.gpc1 = gpc1;
+    ctx->e.gpc2 = gpc2;
+    ctx->e.step.i = -1;  // the next prepared step is planned with them
+    return 0;
+  });
+}
+
 int sadmrg_autotune(sadmrg_ctx* ctx, int reps, int* gpc1, int* gpc2, double* table) {
   return guard(ctx, [&] {
     ctx->e.autotune(reps, table);
