@@ -584,6 +584,51 @@ struct Combos {
 // Reduced elements via coupling_product (9j) and the fermion sign of the
 // factor that is moved past the other one's electrons.
 // ---------------------------------------------------------------------------
+// fn(j) for j < n on up to `threads` host threads (the calling one
+// included); the first exception is rethrown after all have stopped.  A
+// call from inside a worker runs serially (no nested pools).  Workers use
+// the caller's device-memory pool.
+static thread_local bool tl_in_pool = false;
+template <class F>
+static void parallel_for(size_t n, int threads, F&& fn) {
+  const int nt = tl_in_pool ? 1 : (int)std::min<size_t>(n, (size_t)std::max(1, threads));
+  if (nt <= 1) {
+    for (size_t j = 0; j < n; ++j) fn(j);
+    return;
+  }
+  std::atomic<size_t> next{0};
+  std::atomic<bool> stop{false};
+  std::exception_ptr first;
+  std::mutex mu;
+  auto work = [&]() {
+    const bool was = tl_in_pool;
+    tl_in_pool = true;
+    for (size_t j; !stop.load() && (j = next.fetch_add(1)) < n;) {
+      try {
+        fn(j);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!first) first = std::current_exception();
+        stop = true;
+      }
+    }
+    tl_in_pool = was;
+  };
+  DevPool* const mem = dev_pool_current();
+  auto worker = [&]() {
+    dev_pool_bind(mem);
+    work();
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+  work();
+  for (auto& t : pool) t.join();
+  if (first) std::rethrow_exception(first);
+}
+
+// host threads for the per-operator parts of an enlargement
+static const int ENLARGE_HOST_THREADS = 16;
+
 struct Entry {
   int64_t dst;  // element offset in the enlarged store
   int rows, cols, ld;
@@ -594,6 +639,9 @@ struct Entry {
 
 struct Materializer {
   std::vector<Entry> entries;
+  // entries[seg[i], seg[i+1]) write operator i of the enlarged store (each
+  // operator has its own region, so equal destinations stay in one segment)
+  std::vector<size_t> seg;
 
   void emit_op(const Problem& P, const Store& X, const Store& T, const Enl& E, Store& Out, int outop,
                const Term& term, bool left, bool mirror) {
@@ -688,7 +736,13 @@ struct Materializer {
   void run(Store& Out, Stream st) {
     std::vector<size_t> idx(entries.size());
     std::iota(idx.begin(), idx.end(), 0);
-    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return entries[a].dst < entries[b].dst; });
+    // group equal destinations, keeping the emission order inside a group
+    // (the order of the summands), one operator's segment at a time
+    if (seg.size() < 2) seg = {0, entries.size()};
+    parallel_for(seg.size() - 1, ENLARGE_HOST_THREADS, [&](size_t i) {
+      std::stable_sort(idx.begin() + seg[i], idx.begin() + seg[i + 1],
+                       [&](size_t a, size_t b) { return entries[a].dst < entries[b].dst; });
+    });
     std::vector<GatherDst> dsts;
     std::vector<GatherSrc> srcs;
     srcs.reserve(entries.size());
@@ -711,6 +765,7 @@ struct Materializer {
     launch_gather(d_dst.p, (int)dsts.size(), d_src.p, st);
     n_entries = (int64_t)entries.size();
     entries.clear();
+    seg.clear();
   }
   DArr<GatherDst> d_dst;
   DArr<GatherSrc> d_src;
@@ -1066,9 +1121,23 @@ static void trace_enlarge(const Problem& P, Store& X, const Enl& E, bool left, S
   out.basis.dim = E.dim;
   std::vector<int> opidx;
   for (auto& d : tr.defs) opidx.push_back(out.add(d.key, d.tk, d.dN, d.dG, d.odd));
-  for (size_t i = 0; i < tr.defs.size(); ++i) {
-    for (auto& t : tr.defs[i].terms) tr.mat.emit_op(P, X, tr.cb.T, E, out, opidx[i], t, left, false);
-    for (auto& t : tr.defs[i].sym) tr.mat.emit_op(P, X, tr.cb.T, E, out, opidx[i], t, left, true);
+  // the operators' entries are independent: emitted on host threads, then
+  // concatenated in operator order (the serial emission order)
+  std::vector<std::vector<Entry>> per(tr.defs.size());
+  parallel_for(tr.defs.size(), ENLARGE_HOST_THREADS, [&](size_t i) {
+    Materializer m;
+    for (auto& t : tr.defs[i].terms) m.emit_op(P, X, tr.cb.T, E, out, opidx[i], t, left, false);
+    for (auto& t : tr.defs[i].sym) m.emit_op(P, X, tr.cb.T, E, out, opidx[i], t, left, true);
+    per[i] = std::move(m.entries);
+  });
+  size_t tot = 0;
+  for (auto& v : per) tot += v.size();
+  tr.mat.entries.clear();
+  tr.mat.entries.reserve(tot);
+  tr.mat.seg.assign(1, 0);
+  for (auto& v : per) {
+    tr.mat.entries.insert(tr.mat.entries.end(), v.begin(), v.end());
+    tr.mat.seg.push_back(tr.mat.entries.size());
   }
 }
 
@@ -1340,30 +1409,19 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
       ws += (int64_t)outs[tr[i].blk].rows * tr[i].K2;
     }
   tp.ws.alloc((size_t)std::max<int64_t>(ws, 1));
-  GemmList g1, g2;
-  std::vector<int> first(outs.size());
-  for (size_t b = 0; b < outs.size(); ++b) first[b] = g2.add_block(outs[b].out, outs[b].rows, outs[b].cols, outs[b].ld, 0);
+  // counters
   double fl = 0.0, f1 = 0.0, by1 = 0.0, by2 = 0.0;
   for (const OutBlk& o : outs) by2 += 8.0 * (double)o.rows * o.cols;
   for (size_t i = 0; i < tr.size(); ++i) {
     const Triple& x = tr[i];
     const int R = outs[x.blk].rows, Cc = outs[x.blk].cols;
-    const int trA = (x.flags & TT_TRANS_A) ? GT_TRANS_A : 0;
-    const int trC = (x.flags & TT_TRANS_C) ? GT_TRANS_B : 0;
-    const bool trB = (x.flags & TT_TRANS_B) != 0;  // middle factor transposed
     if (x.flags & TT_IDENT_C) {
-      g2.add(first[x.blk], R, Cc, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA | (trB ? GT_TRANS_B : 0), x.coef});
       fl += 2.0 * R * x.K1 * Cc;
       by2 += 8.0 * ((double)R * x.K1 + (double)x.K1 * Cc);
     } else if (x.flags & TT_IDENT_A) {
-      g2.add(first[x.blk], R, Cc, GTask{x.b, x.c, x.ldb, x.ldc, x.K2, trC | (trB ? GT_TRANS_A : 0), x.coef});
       fl += 2.0 * R * x.K2 * Cc;
       by2 += 8.0 * ((double)R * x.K2 + (double)x.K2 * Cc);
     } else {
-      double* T = tp.ws.p + slot[i];
-      const int b1 = g1.add_block(T, R, x.K2, x.K2, 1);
-      g1.add(b1, R, x.K2, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA | (trB ? GT_TRANS_B : 0), 1.0});
-      g2.add(first[x.blk], R, Cc, GTask{T, x.c, x.K2, x.ldc, x.K2, trC, x.coef});
       fl += 2.0 * R * x.K1 * x.K2 + 2.0 * R * x.K2 * Cc;
       f1 += 2.0 * R * x.K1 * x.K2;
       by1 += 8.0 * ((double)R * x.K1 + (double)x.K1 * x.K2 + (double)R * x.K2);
@@ -1379,11 +1437,46 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
   tp.p2.tag = sigma ? 1 : 2;
   tp.nprod = (int64_t)tr.size();
   const int tag1 = tp.p1.tag, tag2 = tp.p2.tag;
-  g1.plan(tp.p1, st, gpc1);
-  if (keep2)
-    *keep2 = std::move(g2);
-  else
-    g2.plan(tp.p2, st, gpc2);
+  // the two passes' product lists and plans are independent: built on two
+  // host threads (pass 1: the T = op(A) B products into workspace slots;
+  // pass 2: the accumulation into the output blocks)
+  parallel_for(2, 2, [&](size_t which) {
+    if (which == 0) {
+      GemmList g1;
+      for (size_t i = 0; i < tr.size(); ++i) {
+        const Triple& x = tr[i];
+        if (x.flags & (TT_IDENT_A | TT_IDENT_C)) continue;
+        const int R = outs[x.blk].rows;
+        const int trA = (x.flags & TT_TRANS_A) ? GT_TRANS_A : 0;
+        const bool trB = (x.flags & TT_TRANS_B) != 0;  // middle factor transposed
+        const int b1 = g1.add_block(tp.ws.p + slot[i], R, x.K2, x.K2, 1);
+        g1.add(b1, R, x.K2, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA | (trB ? GT_TRANS_B : 0), 1.0});
+      }
+      g1.plan(tp.p1, st, gpc1);
+    } else {
+      GemmList g2;
+      std::vector<int> first(outs.size());
+      for (size_t b = 0; b < outs.size(); ++b)
+        first[b] = g2.add_block(outs[b].out, outs[b].rows, outs[b].cols, outs[b].ld, 0);
+      for (size_t i = 0; i < tr.size(); ++i) {
+        const Triple& x = tr[i];
+        const int R = outs[x.blk].rows, Cc = outs[x.blk].cols;
+        const int trA = (x.flags & TT_TRANS_A) ? GT_TRANS_A : 0;
+        const int trC = (x.flags & TT_TRANS_C) ? GT_TRANS_B : 0;
+        const bool trB = (x.flags & TT_TRANS_B) != 0;
+        if (x.flags & TT_IDENT_C)
+          g2.add(first[x.blk], R, Cc, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA | (trB ? GT_TRANS_B : 0), x.coef});
+        else if (x.flags & TT_IDENT_A)
+          g2.add(first[x.blk], R, Cc, GTask{x.b, x.c, x.ldb, x.ldc, x.K2, trC | (trB ? GT_TRANS_A : 0), x.coef});
+        else
+          g2.add(first[x.blk], R, Cc, GTask{tp.ws.p + slot[i], x.c, x.K2, x.ldc, x.K2, trC, x.coef});
+      }
+      if (keep2)
+        *keep2 = std::move(g2);
+      else
+        g2.plan(tp.p2, st, gpc2);
+    }
+  });
   tp.p1.tag = tag1;
   tp.p2.tag = tag2;
 }
@@ -3459,37 +3552,6 @@ struct BatchLaunch {
   void sigma(const std::vector<Engine*>& E, const std::vector<const double*>& x, const std::vector<double*>& y,
              bool use32);
 };
-
-// fn(j) for j < n on up to `threads` host threads (the calling one
-// included); the first exception is rethrown after all have stopped
-template <class F>
-static void parallel_for(size_t n, int threads, F&& fn) {
-  const int nt = (int)std::min<size_t>(n, (size_t)std::max(1, threads));
-  if (nt <= 1) {
-    for (size_t j = 0; j < n; ++j) fn(j);
-    return;
-  }
-  std::atomic<size_t> next{0};
-  std::atomic<bool> stop{false};
-  std::exception_ptr first;
-  std::mutex mu;
-  auto work = [&]() {
-    for (size_t j; !stop.load() && (j = next.fetch_add(1)) < n;) {
-      try {
-        fn(j);
-      } catch (...) {
-        std::lock_guard<std::mutex> lk(mu);
-        if (!first) first = std::current_exception();
-        stop = true;
-      }
-    }
-  };
-  std::vector<std::thread> pool;
-  for (int t = 1; t < nt; ++t) pool.emplace_back(work);
-  work();
-  for (auto& t : pool) t.join();
-  if (first) std::rethrow_exception(first);
-}
 
 // host threads for the per-engine parts of a batched micro-iteration
 // (preparation, decomposition and update); the engines touch disjoint

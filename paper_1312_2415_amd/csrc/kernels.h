@@ -20,6 +20,7 @@ struct DevPool;
 DevPool* dev_pool_create();
 void dev_pool_destroy(DevPool* pool);
 DevPool* dev_pool_bind(DevPool* pool);
+DevPool* dev_pool_current();  // the pool bound to the calling thread
 void dev_h2d(void* dst, const void* src, size_t bytes, Stream st);
 void dev_d2h(void* dst, const void* src, size_t bytes, Stream st);
 void dev_d2d(void* dst, const void* src, size_t bytes, Stream st);

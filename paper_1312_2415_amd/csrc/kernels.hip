@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <iterator>
 #include <map>
+#include <mutex>
 #include <unordered_map>
 
 namespace sadmrg {
@@ -43,6 +44,7 @@ struct DevPool {
   std::multimap<size_t, void*> cached;     // size class -> block
   std::unordered_map<void*, size_t> owned;  // every block of this pool -> size class
   size_t cached_bytes = 0;
+  std::mutex mu;  // host threads of one context may share the pool
 };
 static thread_local DevPool* tl_pool = nullptr;
 static constexpr size_t POOL_CACHE_MAX = (size_t)96 << 30;
@@ -58,6 +60,7 @@ DevPool* dev_pool_bind(DevPool* pool) {
   tl_pool = pool;
   return prev;
 }
+DevPool* dev_pool_current() { return tl_pool; }
 
 // size classes: multiples of 256 B up to 64 KiB, then 2^k * {1, 5/4, 3/2, 7/4}
 static size_t size_class(size_t b) {
@@ -82,6 +85,8 @@ static void pool_trim(DevPool* pool, size_t keep) {
 void* dev_alloc(size_t bytes) {
   if (bytes == 0) bytes = 8;
   DevPool* pool = tl_pool;
+  std::unique_lock<std::mutex> lk;
+  if (pool) lk = std::unique_lock<std::mutex>(pool->mu);
   if (pool) {
     bytes = size_class(bytes);
     auto it = pool->cached.find(bytes);
@@ -110,6 +115,7 @@ void dev_free(void* p) {
   if (!p) return;
   DevPool* pool = tl_pool;
   if (pool) {
+    std::lock_guard<std::mutex> lk(pool->mu);
     auto it = pool->owned.find(p);
     if (it != pool->owned.end()) {
       pool->cached.emplace(it->second, p);
