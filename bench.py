@@ -15,9 +15,13 @@ every kernel launch of the run has the shapes of the headline workload.
 Reported `value` is the sigma-product rate of the plain FP64 path: algorithmic
 FP64 flops of all H_eff*psi calls in the timed sweeps divided by their kernel
 time (HIP events on the library stream).  `ms_per_step` is the wall time per
-FP64 sweep.  `mixed` repeats the timed sweeps from the same state with FP32
-sigma products in Davidson (FP64 Rayleigh-quotient energies) and reports its
-s/sweep, speedup, FP32 sigma rate and |dE| against the FP64 sweeps.  `roofline`
+FP64 sweep.  `mixed` and `mixed_bf16x3` repeat the timed sweeps from the same
+state with FP32 / BF16x3 sigma products in Davidson (one FP64 Davidson step
+per micro-iteration gives the energy) and report s/sweep, speedup, the reduced
+sigma rate and its roofline fraction, and |dE| and RDM errors against the FP64
+sweeps.  `batch` sweeps 64 independent small problems in lockstep against the
+same sweeps one after another.  `autotune` records the launch-shape choice.
+`roofline`
 describes the dominant sigma kernel (the grouped-GEMM pass with the larger
 share of sigma time): its algorithmic flops per launch over its mean launch
 duration, against the FP64 MFMA peak.  `traffic` is filled from the committed
@@ -201,7 +205,7 @@ def batch_bench(n, seed, prec, mixed_tol):
         "workload": "independent problems, L uniform 10..20, N = L/2 rounded to even, S in {0,1}, "
                     "D_SU(2) uniform 128..1024, D2h round-robin orbital irreps, own integral seed each",
         "instances": n, "seed": seed,
-        "precision": "FP32 sigma in Davidson + FP64 Rayleigh quotients" if prec == 1 else "FP64",
+        "precision": "FP32 sigma in Davidson + one FP64 Davidson step per micro-iteration" if prec == 1 else "FP64",
         "s_per_lockstep_sweep": t_batch,
         "s_per_separate_sweeps": t_sep,
         "speedup": t_sep / t_batch,

@@ -141,8 +141,8 @@ int sadmrg_sweep(sadmrg_ctx* ctx, int D, double* e_min);
  *   stats[10] (may be NULL): seconds, algorithmic flops and number of the
  *            shared FP64 sigma launches, then the same for FP32 (zero for a
  *            batch of one, which runs as sadmrg_sweep); then the host wall
- *            seconds of the phases: step preparation, Davidson, Rayleigh
- *            quotients (mixed precision), decomposition and update.
+ *            seconds of the phases: step preparation, Davidson, FP64
+ *            refinement (mixed precision), decomposition and update.
  * Each context's result equals its own sadmrg_sweep up to the summation
  * order of the shared launches.  Returns 1 if some Davidson solve hit
  * max_iter; on an error every context gets the message, and the contexts

@@ -290,7 +290,8 @@ class SaDMRG:
         self._chk(self.lib.sadmrg_set_enlarge_cache(self.h, int(bool(on))))
 
     def set_precision(self, mode: int, mixed_tol: float = 1e-5):
-        """0: FP64 sigma; 1: FP32 sigma in Davidson + FP64 Rayleigh-quotient energy."""
+        """0: FP64 sigma; 1 / 2: FP32 / BF16x3 sigma in Davidson, then one FP64
+        Davidson step per micro-iteration (sadmrg_set_precision)."""
         self._chk(self.lib.sadmrg_set_precision(self.h, int(mode), float(mixed_tol)))
 
     def copy_probe(self, n: int, reps: int = 5) -> float:
@@ -339,7 +340,7 @@ def batch_sweep(solvers, D):
         raise SadmrgError(rc, msg.decode() if msg else "")
     stats = {"t_sigma": st[0], "flops_sigma": st[1], "n_sigma": int(st[2]),
              "t_sigma32": st[3], "flops_sigma32": st[4], "n_sigma32": int(st[5]),
-             "wall": {"prepare": st[6], "davidson": st[7], "rayleigh": st[8], "finish": st[9]}}
+             "wall": {"prepare": st[6], "davidson": st[7], "refine": st[8], "finish": st[9]}}
     return list(em), stats, rc
 
 

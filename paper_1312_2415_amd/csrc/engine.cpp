@@ -3475,7 +3475,8 @@ struct BatchLaunch {
   double f64 = 0.0, f32 = 0.0;  // algorithmic flops of the shared launches
   int64_t n64 = 0, n32 = 0;     // shared launches (one per pass pair)
   // host wall time of the phases of the batched micro-iterations: step
-  // preparation, Davidson, Rayleigh quotients, decomposition and update
+  // preparation, Davidson, FP64 refinement (mixed precision), decomposition
+  // and update
   double w_prepare = 0.0, w_davidson = 0.0, w_rayleigh = 0.0, w_finish = 0.0;
 
   BatchLaunch(Stream s, DevPool* p, size_t n) : st(s), stage(s, p) {
