@@ -144,6 +144,29 @@ def test_autotuned_launch_shape_keeps_sigma_and_sweeps():
     g.close()
 
 
+def test_fixed_launch_shape_and_device_memory_query():
+    from paper_1312_2415_amd.binding import SadmrgError, device_memory
+    L, N, twoS, group, irrep, D = 8, 6, 2, "C2v", 1, 24
+    I = make_integrals(L, group, 44)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    blob = sd.export_blob(dm)
+    g = _gpu(L, group, I)
+    g.set_target(N, twoS, irrep)
+    g.set_launch_shape(8, 48)
+    for bad in ((-1, 12), (0, 65)):
+        with pytest.raises(SadmrgError):
+            g.set_launch_shape(*bad)
+    g.mps_import(blob)
+    g.sweep(D)
+    dm.sweep(D)
+    assert np.abs(g.trace() - np.array(dm.stats.energies)).max() <= 1e-8
+    free, total = device_memory(0)
+    assert 0 < free <= total
+    g.close()
+
+
 def test_config1_exact_at_fci_bond_dimension_with_own_initial_state():
     I = make_integrals(8, "C1", 1001)
     efci = fci_solve(I.h, I.eri, 8, 0)[0][0]
