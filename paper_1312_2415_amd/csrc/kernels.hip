@@ -1079,7 +1079,10 @@ __device__ inline double wave_sum(double v) {
 // (tournament) order, so n/2 disjoint pairs are processed concurrently, one
 // pair per wavefront at a time.
 // ---------------------------------------------------------------------------
-constexpr int SVD_WAVES = 8;
+#ifndef SVD_WAVES_N
+#define SVD_WAVES_N 16
+#endif
+constexpr int SVD_WAVES = SVD_WAVES_N;
 
 __global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __restrict__ jobs) {
   const SvdJob jb = jobs[blockIdx.x];
