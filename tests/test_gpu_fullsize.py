@@ -1,0 +1,65 @@
+"""The headline shape (L = 28, N = 12, singlet Ag, D2h, D_SU(2) = 2500) in the
+launch configuration the benchmark times, checked through properties that hold
+at any size (the oracle cannot build this problem):
+
+* H_eff is symmetric in the plain inner product of the TT basis:
+  <x|H y> = <y|H x> for random x, y;
+* the effective-Hamiltonian diagonal equals <e_i|H e_i> on sampled unit vectors;
+* the FP32 and BF16x3 products stay within their rounding of the FP64 sigma;
+* the RDMs reproduce the energy: E = e0 + sum h gamma + 1/2 sum (ik|jl) Gamma,
+  trace gamma = N, and gamma is symmetric.
+"""
+import numpy as np
+import pytest
+
+from synth.integrals import make_integrals
+
+pytestmark = pytest.mark.gpu
+
+
+def test_headline_shape_properties():
+    from paper_1312_2415_amd import SaDMRG
+    L, N, D = 28, 12, 2500
+    I = make_integrals(L, "D2h", 1003)
+    g = SaDMRG(L, 8, I.orb_irrep, device=0)
+    g.set_integrals(I.h, I.eri, I.e_const)
+    g.set_target(N, 0, 0)
+    g.set_davidson(1e-7, 32, 100)
+    g.init_mps(D)
+    print("sweep at D=2500", flush=True)
+    e_sweep, _ = g.sweep(D)
+    assert np.isfinite(e_sweep)
+    blob = g.mps_export()
+    g.advance(D, L // 2 - 1)
+    g.prepare_step()
+    desc, n = g.psi_layout()
+    assert n > 100000
+    rng = np.random.default_rng(12)
+    x, y = rng.normal(size=n), rng.normal(size=n)
+    print("sigma symmetry", flush=True)
+    hx, hy = g.sigma(x), g.sigma(y)
+    a, b = float(x @ hy), float(y @ hx)
+    assert abs(a - b) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(hy)
+    print("diagonal samples", flush=True)
+    d = g.heff_diagonal()
+    for i in rng.choice(n, 8, replace=False):
+        e = np.zeros(n)
+        e[i] = 1.0
+        assert abs(g.sigma(e)[i] - d[i]) <= 1e-12 * max(1.0, abs(d[i]))
+    print("reduced-precision products", flush=True)
+    scale = np.abs(hx).max()
+    g.set_precision(1)
+    e32 = np.abs(g.sigma(x) - hx).max() / scale
+    g.set_precision(2)
+    e3 = np.abs(g.sigma(x) - hx).max() / scale
+    g.set_precision(0)
+    assert 0.0 < e32 <= 2e-5
+    assert e32 < e3 <= 5e-3
+    print("RDM identities", flush=True)
+    g.mps_import(blob)
+    g1, g2, e = g.rdm()
+    e_id = I.e_const + float(np.einsum("pq,pq", I.h, g1)) + 0.5 * float(np.einsum("ikjl,ijkl", I.eri, g2))
+    assert abs(e_id - e) <= 1e-9 * max(1.0, abs(e))
+    assert abs(np.trace(g1) - N) <= 1e-9
+    assert np.abs(g1 - g1.T).max() <= 1e-12
+    g.close()
