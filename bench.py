@@ -241,6 +241,7 @@ def main():
     ap.add_argument("--batch-n", type=int, default=64, help="independent problems of the lockstep batch; 0 = skip")
     ap.add_argument("--batch-seed", type=int, default=4)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--only-batch", action="store_true", help="run only the lockstep batch record")
     ap.add_argument("--gpc", default="", help="fixed sigma launch shape 'pass1,pass2' (workgroups per CU) "
                                                "instead of autotuning")
     args = ap.parse_args()
@@ -250,6 +251,11 @@ def main():
               "(sharding the sigma product over several GPUs is not run).",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.only_batch:  # the lockstep batch record alone (for profiling it)
+        print(json.dumps({"batch": batch_bench(max(args.batch_n, 1), args.batch_seed, 1, args.mixed_tol)}),
+              flush=True)
+        return
 
     from paper_1312_2415_amd import SaDMRG
     from synth.integrals import make_integrals

@@ -587,7 +587,7 @@ struct Combos {
 // fn(j) for j < n on up to `threads` host threads (the calling one
 // included); the first exception is rethrown after all have stopped.  A
 // call from inside a worker runs serially (no nested pools).  Workers use
-// the caller's device-memory pool.
+// the caller's device and device-memory pool.
 static thread_local bool tl_in_pool = false;
 template <class F>
 static void parallel_for(size_t n, int threads, F&& fn) {
@@ -615,8 +615,16 @@ static void parallel_for(size_t n, int threads, F&& fn) {
     tl_in_pool = was;
   };
   DevPool* const mem = dev_pool_current();
+  const int device = dev_get_device();
   auto worker = [&]() {
     dev_pool_bind(mem);
+    try {
+      dev_set_device(device);
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(mu);
+      if (!first) first = std::current_exception();
+      stop = true;
+    }
     work();
   };
   std::vector<std::thread> pool;

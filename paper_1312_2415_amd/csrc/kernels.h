@@ -33,6 +33,7 @@ void host_free_pinned(void* p);
 void dev_h2d_async(void* dst, const void* pinned_src, size_t bytes, Stream st);
 void dev_d2h_async(void* pinned_dst, const void* src, size_t bytes, Stream st);
 void dev_set_device(int device);
+int dev_get_device();  // the calling thread's current device
 size_t dev_total_memory();  // bytes of device memory of the current device
 void dev_memory_info(size_t* free_bytes, size_t* total_bytes);  // current device
 int dev_count();

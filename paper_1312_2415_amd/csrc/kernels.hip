@@ -176,6 +176,11 @@ void dev_d2h_async(void* dst, const void* src, size_t bytes, Stream st) {
   if (bytes) hip_ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, (hipStream_t)st), "hipMemcpyAsync D2H");
 }
 void dev_set_device(int device) { hip_ok(hipSetDevice(device), "hipSetDevice"); }
+int dev_get_device() {
+  int d = 0;
+  hip_ok(hipGetDevice(&d), "hipGetDevice");
+  return d;
+}
 void dev_memory_info(size_t* fr, size_t* tot) { hip_ok(hipMemGetInfo(fr, tot), "hipMemGetInfo"); }
 size_t dev_total_memory() {
   size_t fr = 0, tot = 0;
