@@ -186,8 +186,10 @@ def test_config1_exact_at_fci_bond_dimension_with_own_initial_state():
 
 
 @pytest.mark.parametrize("N,twoS,group,irrep", [(6, 2, "C1", 0), (5, 1, "C2v", 1), (6, 0, "D2h", 0), (2, 0, "C1", 0),
-                                                (12, 0, "C1", 0), (6, 6, "C1", 0)])
+                                                (12, 0, "C1", 0), (6, 6, "C1", 0), (11, 1, "C2v", 0)])
 def test_spin_and_symmetry_targets_exact(N, twoS, group, irrep):
+    # includes the one-hole and filled (N = 2L) limits and the fully polarised
+    # sector (N < 2 is rejected: the one-body folding divides by N - 1)
     I = make_integrals(6, group, 21)
     efci = fci_solve(I.h, I.eri, N, twoS, irrep, I.orb_irrep)[0][0]
     g = _gpu(6, group, I)
@@ -238,6 +240,12 @@ def test_rejects_bad_targets_and_integrals():
         g.set_target(3, 0, 0)  # N - 2S odd
     with pytest.raises(SadmrgError):
         g.set_target(1, 1, 0)  # N < 2
+    with pytest.raises(SadmrgError):
+        g.set_target(0, 0, 0)  # empty
+    with pytest.raises(SadmrgError):
+        g.set_target(9, 1, 0)  # N > 2L
+    with pytest.raises(SadmrgError):
+        g.set_target(6, 4, 0)  # 2S beyond the 2L - N holes
     bad = I.eri.copy()
     bad[0, 1, 2, 3] += 1e-3
     with pytest.raises(SadmrgError):
