@@ -2965,12 +2965,12 @@ struct Engine {
   }
   // Pick the sigma plans' workgroups per CU by timing the prepared step:
   // every candidate pair (first pass: one tile per workgroup or 8 ranges per
-  // CU; accumulating pass: 8..48 ranges per CU) is planned and its FP64 sigma
+  // CU; accumulating pass: 12..64 ranges per CU) is planned and its FP64 sigma
   // timed over `reps` calls; the fastest pair is kept for this context and
   // the step is re-planned with it.  out[2 * c], out[2 * c + 1]: the pair's
   // gpc values, out[2 * ncand + c]: its mean ms per sigma.
   static constexpr int TUNE_G1[2] = {0, 8};
-  static constexpr int TUNE_G2[6] = {8, 12, 16, 24, 32, 48};
+  static constexpr int TUNE_G2[6] = {12, 16, 24, 32, 48, 64};
   static constexpr int TUNE_N = 12;
   void autotune(int reps, double* out) {
     if (step.i < 0 || !step.X || !step.Y) fail(-1, "no prepared step");

@@ -127,7 +127,7 @@ def test_autotuned_launch_shape_keeps_sigma_and_sweeps():
     y0 = g.sigma(x)
     (g1, g2), table = g.autotune(3)
     assert (g1, g2) in [t[0] for t in table]
-    assert g1 in (0, 8) and g2 in (8, 12, 16, 24, 32, 48) and len(table) == 12
+    assert g1 in (0, 8) and g2 in (12, 16, 24, 32, 48, 64) and len(table) == 12
     assert all(ms > 0 for _, ms in table)
     y1 = g.sigma(x)
     assert np.abs(y1 - y0).max() <= 1e-12 * np.abs(y0).max()
