@@ -20,8 +20,11 @@ state with FP32 / BF16x3 sigma products in Davidson (one FP64 Davidson step
 per micro-iteration gives the energy) and report s/sweep, speedup, the reduced
 sigma rate and its roofline fraction, and |dE| and RDM errors against the FP64
 sweeps.  `batch` sweeps 64 independent small problems in lockstep against the
-same sweeps one after another.  `autotune` records the launch-shape choice.
-`roofline`
+same sweeps one after another.  `roots` sweeps one GPU's share of twelve roots
+of the headline problem (S in {0, 1, 2} times four irreps, in separate
+symmetry sectors, dealt round-robin to GPUs) in lockstep, in FP64 and in mixed
+precision from the same states, with per-root |dE| and RDM errors.
+`autotune` records the launch-shape choice.  `roofline`
 describes the dominant sigma kernel (the grouped-GEMM pass with the larger
 share of sigma time): its algorithmic flops per launch over its mean launch
 duration, against the FP64 MFMA peak.  `traffic` is filled from the committed
@@ -218,6 +221,98 @@ def batch_bench(n, seed, prec, mixed_tol):
     }
 
 
+ROOT_TARGETS = [(2 * s, ir) for s in (0, 1, 2) for ir in (0, 1, 2, 3)]  # (2S, irrep) of the twelve roots
+
+
+def roots_bench(k, L, N, D, seed, warm, dav_tol, mixed_tol, refine=1):
+    """Roots 0, 12/k, 2*12/k, ... of the twelve (one GPU's share when they are
+    dealt round-robin over 12/k GPUs) swept in lockstep (sadmrg_batch_sweep):
+    `warm` FP64 lockstep sweeps from random MPS, then one timed FP64 lockstep
+    sweep, the same sweep of each root on its own, and one timed mixed
+    lockstep sweep (FP32 sigma + FP64 refinement) from the same states."""
+    from paper_1312_2415_amd import SaDMRG
+    from paper_1312_2415_amd.binding import batch_sweep, device_memory
+    from synth.integrals import make_integrals
+    if k < 1 or 12 % k:
+        raise ValueError("roots: k must divide 12")
+    targets = ROOT_TARGETS[::12 // k]
+    I = make_integrals(L, "D2h", seed)
+    gs = []
+    try:
+        for j, (twoS, irrep) in enumerate(targets):
+            g = SaDMRG(L, 8, I.orb_irrep, device=0)
+            gs.append(g)
+            g.set_integrals(I.h, I.eri)
+            g.set_target(N, twoS, irrep)
+            g.set_seed(seed + 17 * j)
+            g.set_davidson(dav_tol, 32, 100)
+            g.init_mps(D)
+        for w in range(warm):
+            t = time.perf_counter()
+            batch_sweep(gs, D)
+            print(f"roots: warm-up lockstep sweep {w + 1}/{warm} {time.perf_counter() - t:.1f}s", file=sys.stderr,
+                  flush=True)
+        blobs = [g.mps_export() for g in gs]
+        n0 = [len(g.trace()) for g in gs]
+        t = time.perf_counter()
+        e64, st64, _ = batch_sweep(gs, D)
+        t64 = time.perf_counter() - t
+        free, total = device_memory(0)
+        tr64 = [np.array(g.trace()[n:]) for g, n in zip(gs, n0)]
+        print(f"roots: FP64 lockstep sweep {t64:.2f}s", file=sys.stderr, flush=True)
+        r64 = [g.rdm() for g in gs]
+        t = time.perf_counter()
+        for g, b in zip(gs, blobs):
+            g.mps_import(b)
+            g.sweep(D)
+        tsep = time.perf_counter() - t
+        print(f"roots: separate FP64 sweeps {tsep:.2f}s", file=sys.stderr, flush=True)
+        n1 = []
+        for g, b in zip(gs, blobs):
+            g.set_precision(1, mixed_tol)
+            g.set_refinement(refine)
+            g.mps_import(b)
+            n1.append(len(g.trace()))
+        t = time.perf_counter()
+        e32, st32, _ = batch_sweep(gs, D)
+        t32 = time.perf_counter() - t
+        tr32 = [np.array(g.trace()[n:]) for g, n in zip(gs, n1)]
+        print(f"roots: mixed lockstep sweep {t32:.2f}s", file=sys.stderr, flush=True)
+        r32 = [g.rdm() for g in gs]
+        per = []
+        for j, (twoS, irrep) in enumerate(targets):
+            same = len(tr32[j]) == len(tr64[j]) and len(tr64[j]) > 0
+            per.append({"twoS": twoS, "irrep": irrep, "energy_fp64": e64[j], "energy_mixed": e32[j],
+                        "abs_dE": abs(e32[j] - e64[j]),
+                        "max_abs_dE_per_micro_iteration": float(np.abs(tr32[j] - tr64[j]).max()) if same else None,
+                        "rdm_max_abs_error": {"gamma": float(np.abs(r32[j][0] - r64[j][0]).max()),
+                                              "Gamma": float(np.abs(r32[j][1] - r64[j][1]).max())}})
+        f64 = st64["flops_sigma"] / max(st64["t_sigma"], 1e-12) / 1e12
+        f32 = st32["flops_sigma32"] / max(st32["t_sigma32"], 1e-12) / 1e12
+        return {
+            "workload": f"roots of L={L} N={N} D2h D_SU(2)={D} (seed {seed}): (2S, irrep) in "
+                        f"{[list(t) for t in targets]}, the share of one GPU when the twelve roots "
+                        f"(S in {{0,1,2}} x irreps 0..3) are dealt round-robin to {12 // k} GPUs",
+            "roots": k, "warmup_lockstep_sweeps": warm, "fp64_refinement_steps": refine,
+            "s_per_lockstep_sweep_fp64": t64,
+            "s_per_separate_sweeps_fp64": tsep,
+            "s_per_lockstep_sweep_mixed": t32,
+            "speedup_mixed_lockstep_vs_fp64_lockstep": t64 / t32,
+            "speedup_mixed_lockstep_vs_fp64_separate": tsep / t32,
+            "sigma_tflops_fp64_lockstep": f64,
+            "sigma_roofline_frac_fp64": f64 / FP64_MFMA_PEAK,
+            "sigma_tflops_fp32_mixed": f32,
+            "sigma_roofline_frac_fp32": f32 / FP32_MFMA_PEAK,
+            "max_abs_dE": max(r["abs_dE"] for r in per),
+            "max_rdm_abs_error": max(max(r["rdm_max_abs_error"].values()) for r in per),
+            "device_memory_used_GiB": (total - free) / 2**30,
+            "per_root": per,
+        }
+    finally:
+        for g in gs:
+            g.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +337,11 @@ def main():
     ap.add_argument("--batch-seed", type=int, default=4)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--only-batch", action="store_true", help="run only the lockstep batch record")
+    ap.add_argument("--roots", type=int, default=3, help="roots of the headline problem swept in lockstep "
+                                                         "(a divisor of 12; 0 = skip)")
+    ap.add_argument("--roots-warmup", type=int, default=2)
+    ap.add_argument("--refine", type=int, default=1, help="FP64 Davidson steps after the reduced-precision phase")
+    ap.add_argument("--only-roots", action="store_true", help="run only the roots record")
     ap.add_argument("--gpc", default="", help="fixed sigma launch shape 'pass1,pass2' (workgroups per CU) "
                                                "instead of autotuning")
     args = ap.parse_args()
@@ -252,6 +352,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.only_roots:
+        print(json.dumps({"roots": roots_bench(args.roots, args.L, args.N, args.D, args.seed, args.roots_warmup,
+                                               args.dav_tol, args.mixed_tol, args.refine)}), flush=True)
+        return
     if args.only_batch:  # the lockstep batch record alone (for profiling it)
         print(json.dumps({"batch": batch_bench(max(args.batch_n, 1), args.batch_seed, 1, args.mixed_tol)}),
               flush=True)
@@ -379,6 +483,7 @@ def main():
                 (2, "mixed_bf16x3", "BF16x3 sigma (hi*hi + hi*lo + lo*hi of BF16 splits of the FP32 operators, "
                                     "FP32 accumulation) in Davidson")):
             g.set_precision(mode, args.mixed_tol)
+            g.set_refinement(args.refine)
             g.mps_import(start)
             g.stats_reset()
             tm0 = time.perf_counter()
@@ -400,9 +505,11 @@ def main():
             peak = FP32_MFMA_PEAK if mode == 1 else BF16_MFMA_PEAK / 3
             tf = sm["fp32"]["flops"] / max(sm["fp32"]["t"], 1e-12) / 1e12
             rec = {
-                "precision": desc + "; FP64 Davidson algebra, SVD, renormalisation; one FP64 Davidson step "
-                                    "(two FP64 sigma) refines each micro-iteration's vector and gives its energy",
+                "precision": desc + f"; FP64 Davidson algebra, SVD, renormalisation; {args.refine} FP64 Davidson "
+                                    f"step(s) ({args.refine + 1} FP64 sigma) refine each micro-iteration's vector "
+                                    "and give its energy",
                 "mixed_tol": args.mixed_tol,
+                "fp64_refinement_steps": args.refine,
                 "s_per_sweep": sec_mixed,
                 "speedup_s_per_sweep": sec_per_sweep / sec_mixed,
                 "sigma_reduced_tflops": tf,
@@ -424,6 +531,12 @@ def main():
     g.close()
     if args.batch_n > 0:
         line["batch"] = batch_bench(args.batch_n, args.batch_seed, 1, args.mixed_tol)
+    if args.roots > 0:
+        try:
+            line["roots"] = roots_bench(args.roots, L, N, args.D, args.seed, args.roots_warmup, args.dav_tol,
+                                        args.mixed_tol, args.refine)
+        except Exception as ex:  # the headline record stands on its own
+            line["roots"] = {"error": f"{type(ex).__name__}: {ex}"}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, L, N, args.twoS, args.irrep, args.seed, args.cpu_D)
     print(json.dumps(line), flush=True)

@@ -95,10 +95,12 @@ int sadmrg_set_davidson(sadmrg_ctx* ctx, double tol, int max_sub, int max_iter);
  *   psi with FP32 accumulation until the residual reaches max(tol, mixed_tol)
  *   or, once below 6e-6 |theta|, stops improving (10 % over four iterations:
  *   the FP32 rounding floor); orthogonalisation, Ritz problem and residuals
- *   stay FP64.  Then one FP64 Davidson step refines the vector: the subspace
- *   of the vector and its preconditioned FP64 residual, two FP64 sigma
- *   products; the reported energy of the micro-iteration is the lower FP64
- *   Ritz value and the refined vector goes on to the decomposition.
+ *   stay FP64.  Then FP64 Davidson steps refine the vector (one by default,
+ *   sadmrg_set_refinement): the subspace of the vector and its preconditioned
+ *   FP64 residual, two FP64 sigma products for the first step and one for
+ *   each further step; the reported energy of the micro-iteration is the
+ *   lowest FP64 Ritz value and the refined vector goes on to the
+ *   decomposition.
  * mode 2: as mode 1, but the Davidson sigma products are BF16x3 on the FP32
  *   copies: each value is split into hi = bf16(x) and lo = bf16(x - hi), a
  *   product is hi*hi + hi*lo + lo*hi on the BF16 matrix cores with FP32
@@ -107,6 +109,13 @@ int sadmrg_set_davidson(sadmrg_ctx* ctx, double tol, int max_sub, int max_iter);
  * sadmrg_sigma uses the reduced products in modes 1 and 2.  SVD, truncation
  * and renormalisation stay FP64.  Errors: EINVAL. */
 int sadmrg_set_precision(sadmrg_ctx* ctx, int mode, double mixed_tol);
+/* Number of FP64 Davidson steps that refine the reduced-precision solution of
+ * modes 1 and 2 (default 1, allowed 1..8).  Each step works on the subspace
+ * of the current vector and its preconditioned FP64 residual and costs one
+ * FP64 sigma product (plus one for the first step); the refinement stops
+ * early when a step cannot move the vector.  Contexts swept together by
+ * sadmrg_batch_sweep must share it.  Errors: EINVAL. */
+int sadmrg_set_refinement(sadmrg_ctx* ctx, int steps);
 
 /* Seed of the counter-based generator used for the random initial MPS. */
 int sadmrg_set_seed(sadmrg_ctx* ctx, uint64_t seed);

@@ -68,6 +68,7 @@ def load_library(path: str | None = None):
         "sadmrg_stats_bytes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_passes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_mixed": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl)]),
+        "sadmrg_set_refinement": (c_int, [c_vp, c_int]),
         "sadmrg_set_precision": (c_int, [c_vp, c_int, c_dbl]),
         "sadmrg_rdm": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
         "sadmrg_get_s2": (c_int, [c_vp, P(c_dbl)]),
@@ -293,6 +294,10 @@ class SaDMRG:
         """0: FP64 sigma; 1 / 2: FP32 / BF16x3 sigma in Davidson, then one FP64
         Davidson step per micro-iteration (sadmrg_set_precision)."""
         self._chk(self.lib.sadmrg_set_precision(self.h, int(mode), float(mixed_tol)))
+
+    def set_refinement(self, steps: int):
+        """FP64 Davidson steps after the reduced-precision phase (modes 1, 2)."""
+        self._chk(self.lib.sadmrg_set_refinement(self.h, int(steps)))
 
     def copy_probe(self, n: int, reps: int = 5) -> float:
         """Mean seconds of the library's plain streaming-copy kernel over n doubles."""

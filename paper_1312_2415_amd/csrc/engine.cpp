@@ -1701,6 +1701,7 @@ struct Engine {
   int64_t n_pass = 0;  // passes since the MPS was created or imported
   int prec = 0;             // 0: FP64 sigma; 1 / 2: FP32 / BF16x3 sigma in Davidson + FP64 refinement
   double mixed_tol = 1e-5;  // Davidson tolerance of the FP32 phase
+  int refine_steps = 1;     // FP64 Davidson steps after the FP32 phase
   int64_t n_sigma = 0;
   // Davidson work buffers
   DBuf dV, dW, dHs, dsmall, dpartial, dx_, dax, dr, dt;
@@ -3226,13 +3227,15 @@ struct Engine {
   // ---- one micro-iteration
   // <x|H|x> / <x|x> with the FP64 sigma
   // FP64 refinement of an FP32 Davidson solution x (unit; the solve's last
-  // Ritz value still in dav_evals()): one Davidson step in FP64 on the
-  // subspace {x, t}, t the preconditioned FP64 residual made orthonormal to
-  // x.  The phases: after y = H x is in dr, refine_dir forms t in dt; after
+  // Ritz value still in dav_evals()): Davidson steps in FP64 on the subspace
+  // {x, t}, t the preconditioned FP64 residual made orthonormal to x.  The
+  // phases of a step: after y = H x is in dr, refine_dir forms t in dt; after
   // w = H t is in dax, refine_dots enqueues the inner products (read back
   // into hpin[0..4]); refine_update solves the 2 x 2 problem on the host,
   // replaces x by the lowest Ritz vector and returns its FP64 Rayleigh
-  // quotient.
+  // quotient.  With `more`, it also leaves H x of the new vector in dr (as
+  // the same combination of y and w) and its Rayleigh quotient in
+  // dav_evals(), ready for the next step: one more FP64 sigma per step.
   void refine_dir(const double* x) {
     const int64_t n = step.n;
     launch_residual(dr.p, x, dav_evals(), n, dt.p, st);
@@ -3255,10 +3258,11 @@ struct Engine {
     dev_d2h_async(hpin, dav_nrm2(), 8, st);  // |t|^2 before normalisation
     dev_d2h_async(hpin + 1, c + 1, 32, st);
   }
-  double refine_update(double* x) {
+  double refine_update(double* x, bool more = false, bool* moved = nullptr) {
     const int64_t n = step.n;
     const double tt = hpin[0], xy = hpin[1], xx = hpin[2], xw = hpin[3], tw = hpin[4];
     const double a = xy / xx;
+    if (moved) *moved = false;
     if (!(tt > 1e-28) || !(xx > 0) || !std::isfinite(xw) || !std::isfinite(tw)) return a;
     const double sx = std::sqrt(xx);
     const double b = xw / sx, c = tw;
@@ -3273,15 +3277,28 @@ struct Engine {
     if (p < 0) p = -p, q = -q;  // keep the sign of x
     launch_scal(x, p / sx, n, st);
     launch_axpy(x, dt.p, q, n, st);
+    if (more) {
+      launch_scal(dr.p, p / sx, n, st);
+      launch_axpy(dr.p, dax.p, q, n, st);
+      hpin[6] = lam;  // read by the copy before the next step's host update
+      dev_h2d_async(dav_evals(), hpin + 6, sizeof(double), st);
+    }
+    if (moved) *moved = true;
     return lam;
   }
   double refine64(double* x) {
     sigma_vec(x, dr.p, false);
-    refine_dir(x);
-    sigma_vec(dt.p, dax.p, false);
-    refine_dots(x);
-    dev_sync(st);
-    return refine_update(x);
+    double th = 0.0;
+    for (int k = 0; k < refine_steps; ++k) {
+      refine_dir(x);
+      sigma_vec(dt.p, dax.p, false);
+      refine_dots(x);
+      dev_sync(st);
+      bool moved = false;
+      th = refine_update(x, k + 1 < refine_steps, &moved);
+      if (!moved) break;
+    }
+    return th;
   }
   double micro(int i, int D, bool right, bool do_svd) {
     auto t0 = std::chrono::steady_clock::now();
@@ -3991,20 +4008,41 @@ static bool batch_sweep(const std::vector<Engine*>& E, const std::vector<int>& D
         ws.push_back(ea[j]->dax.p);
       }
       shared_sigma(xs, ys);
-      for (size_t j = 0; j < na; ++j) {
-        PoolBind b(ea[j]->pool);
-        ea[j]->refine_dir(xb[j].p);
-      }
-      shared_sigma(ts, ws);
-      for (size_t j = 0; j < na; ++j) {
-        PoolBind b(ea[j]->pool);
-        ea[j]->refine_dots(xb[j].p);
-      }
-      dev_sync(bl.st);
-      bl.stage.reset();
-      for (size_t j = 0; j < na; ++j) {
-        PoolBind b(ea[j]->pool);
-        th[j] = ea[j]->refine_update(xb[j].p);
+      const int steps = E[0]->refine_steps;
+      std::vector<char> live(na, 1);  // still refining (a step that could not move x ends it)
+      for (int k = 0; k < steps; ++k) {
+        std::vector<Engine*> ek;
+        std::vector<const double*> tk;
+        std::vector<double*> wk;
+        for (size_t j = 0; j < na; ++j) {
+          if (!live[j]) continue;
+          PoolBind b(ea[j]->pool);
+          ea[j]->refine_dir(xb[j].p);
+          ek.push_back(ea[j]);
+          tk.push_back(ts[j]);
+          wk.push_back(ws[j]);
+        }
+        if (ek.empty()) break;
+        if (ek.size() == 1) {
+          PoolBind b(ek[0]->pool);
+          ek[0]->sigma_vec(tk[0], wk[0], false);
+        } else {
+          bl.sigma(ek, tk, wk, false);
+        }
+        for (size_t j = 0; j < na; ++j) {
+          if (!live[j]) continue;
+          PoolBind b(ea[j]->pool);
+          ea[j]->refine_dots(xb[j].p);
+        }
+        dev_sync(bl.st);
+        bl.stage.reset();
+        for (size_t j = 0; j < na; ++j) {
+          if (!live[j]) continue;
+          PoolBind b(ea[j]->pool);
+          bool moved = false;
+          th[j] = ea[j]->refine_update(xb[j].p, k + 1 < steps, &moved);
+          live[j] = moved;
+        }
       }
     }
     bl.w_rayleigh += lap();
@@ -4377,7 +4415,8 @@ int sadmrg_batch_sweep(sadmrg_ctx* const* ctxs, int n, const int* D, double* e_m
     if (D[k] < 1) return fail_all(SADMRG_EINVAL, "D must be positive");
     if (e.device != e0.device || e.st != e0.st)
       return fail_all(SADMRG_EINVAL, "batched contexts must share one device and one stream");
-    if (e.prec != e0.prec) return fail_all(SADMRG_EINVAL, "batched contexts must share one precision mode");
+    if (e.prec != e0.prec || e.refine_steps != e0.refine_steps)
+      return fail_all(SADMRG_EINVAL, "batched contexts must share one precision mode and refinement");
   }
   try {
     std::vector<sadmrg::Engine*> E;
@@ -4658,6 +4697,14 @@ int sadmrg_set_precision(sadmrg_ctx* ctx, int mode, double mixed_tol) {
     if (mode > 0 && !(mixed_tol > 0.0)) sadmrg::fail(SADMRG_EINVAL, "mixed_tol must be positive");
     ctx->e.prec = mode;
     if (mode > 0) ctx->e.mixed_tol = mixed_tol;
+    return 0;
+  });
+}
+
+int sadmrg_set_refinement(sadmrg_ctx* ctx, int steps) {
+  return guard(ctx, [&] {
+    if (steps < 1 || steps > 8) sadmrg::fail(SADMRG_EINVAL, "refinement steps must be in 1..8");
+    ctx->e.refine_steps = steps;
     return 0;
   });
 }

@@ -48,10 +48,24 @@ struct DevPool {
 };
 static thread_local DevPool* tl_pool = nullptr;
 static constexpr size_t POOL_CACHE_MAX = (size_t)96 << 30;
+// Every live pool, so that an allocation that fails in one context can take
+// back the blocks the other contexts keep cached.  Lock order: the registry
+// before a pool; no thread waits for the registry while holding a pool.
+static std::mutex g_pools_mu;
+static std::vector<DevPool*> g_pools;
 
-DevPool* dev_pool_create() { return new DevPool(); }
+DevPool* dev_pool_create() {
+  DevPool* pool = new DevPool();
+  std::lock_guard<std::mutex> lk(g_pools_mu);
+  g_pools.push_back(pool);
+  return pool;
+}
 void dev_pool_destroy(DevPool* pool) {
   if (!pool) return;
+  {
+    std::lock_guard<std::mutex> lk(g_pools_mu);
+    g_pools.erase(std::remove(g_pools.begin(), g_pools.end(), pool), g_pools.end());
+  }
   for (auto& [p, sz] : pool->owned) (void)hipFree(p);
   delete pool;
 }
@@ -81,6 +95,19 @@ static void pool_trim(DevPool* pool, size_t keep) {
     pool->cached.erase(it);
   }
 }
+// empty the caches of every pool but `self` (called without holding any
+// pool's lock); returns the bytes given back
+static size_t trim_other_pools(DevPool* self) {
+  size_t freed = 0;
+  std::lock_guard<std::mutex> reg(g_pools_mu);
+  for (DevPool* q : g_pools) {
+    if (q == self) continue;
+    std::lock_guard<std::mutex> lk(q->mu);
+    freed += q->cached_bytes;
+    pool_trim(q, 0);
+  }
+  return freed;
+}
 
 void* dev_alloc(size_t bytes) {
   if (bytes == 0) bytes = 8;
@@ -103,6 +130,12 @@ void* dev_alloc(size_t bytes) {
     (void)hipGetLastError();
     pool_trim(pool, 0);
     e = hipMalloc(&p, bytes);
+  }
+  if (e != hipSuccess) {  // then the caches of the other contexts
+    (void)hipGetLastError();
+    if (lk.owns_lock()) lk.unlock();
+    if (trim_other_pools(pool) > 0) e = hipMalloc(&p, bytes);
+    if (pool) lk.lock();
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -1081,13 +1114,27 @@ __device__ inline double wave_sum(double v) {
 // One-sided (Hestenes) Jacobi SVD, one workgroup per sector matrix.
 // Works on the tall orientation M (m x n, m >= n): columns are rotated until
 // mutually orthogonal; M V = U S.  Column pairs are visited in round-robin
-// (tournament) order, so n/2 disjoint pairs are processed concurrently, one
-// pair per wavefront at a time.
+// (tournament) order, so n/2 disjoint pairs are processed concurrently: a
+// group of SVD_G lanes per pair, 64 / SVD_G pairs per wavefront at a time
+// (their loads in flight together).
 // ---------------------------------------------------------------------------
 #ifndef SVD_WAVES_N
 #define SVD_WAVES_N 16
 #endif
+#ifndef SVD_GROUP_N
+#define SVD_GROUP_N 32
+#endif
 constexpr int SVD_WAVES = SVD_WAVES_N;
+constexpr int SVD_G = SVD_GROUP_N;                   // lanes per column pair
+constexpr int SVD_PAIRS = SVD_WAVES * (64 / SVD_G);  // pairs processed at once
+static_assert(SVD_G == 16 || SVD_G == 32 || SVD_G == 64, "pair group size");
+
+// Sum over the SVD_G lanes of a group (butterfly: every lane of the group
+// ends with the same value, bit for bit).
+__device__ inline double group_sum(double v) {
+  for (int o = SVD_G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, SVD_G);
+  return v;
+}
 
 __global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __restrict__ jobs) {
   const SvdJob jb = jobs[blockIdx.x];
@@ -1098,6 +1145,7 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __res
   double* V = M + (int64_t)m * n;          // n x n, column j contiguous
   double* nrm = V + (int64_t)n * n;        // n
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  const int gl = tid % SVD_G, grp = tid / SVD_G;  // lane within its pair group, group index
   const int nth = blockDim.x;
   const double* A = jb.a;
   // load (column-major working copy of the tall orientation)
@@ -1115,7 +1163,7 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __res
     __syncthreads();
     for (int round = 0; round < np - 1; ++round) {
       // pairs (p, q) of the round-robin schedule: position 0 fixed, others rotate
-      for (int pr = wv; pr < np / 2; pr += SVD_WAVES) {
+      for (int pr = grp; pr < np / 2; pr += SVD_PAIRS) {
         // circle method: slot 0 fixed, slots 1..np-1 rotate; pair (slot pr, slot np-1-pr)
         const int a = (pr == 0) ? 0 : ((pr - 1 + round) % (np - 1)) + 1;
         const int b = ((np - 2 - pr + round) % (np - 1)) + 1;
@@ -1124,32 +1172,32 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __res
         double* mp = M + (int64_t)p * m;
         double* mq = M + (int64_t)q * m;
         double al = 0, be = 0, ga = 0;
-        for (int i = lane; i < m; i += 64) {
+        for (int i = gl; i < m; i += SVD_G) {
           const double x = mp[i], y = mq[i];
           al += x * x;
           be += y * y;
           ga += x * y;
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
+        al = group_sum(al);
+        be = group_sum(be);
+        ga = group_sum(ga);
         if (fabs(ga) <= 1e-15 * sqrt(al * be) || ga == 0.0) continue;
         const double zeta = (be - al) / (2.0 * ga);
         const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-        for (int i = lane; i < m; i += 64) {
+        for (int i = gl; i < m; i += SVD_G) {
           const double x = mp[i], y = mq[i];
           mp[i] = cs * x - sn * y;
           mq[i] = sn * x + cs * y;
         }
         double* vp = V + (int64_t)p * n;
         double* vq = V + (int64_t)q * n;
-        for (int i = lane; i < n; i += 64) {
+        for (int i = gl; i < n; i += SVD_G) {
           const double x = vp[i], y = vq[i];
           vp[i] = cs * x - sn * y;
           vq[i] = sn * x + cs * y;
         }
-        if (lane == 0) s_rot = 1;
+        if (gl == 0) s_rot = 1;
       }
       __syncthreads();
     }

@@ -138,6 +138,34 @@ def test_mixed_precision_batch_matches_fp64_oracle():
         g.close()
 
 
+def test_mixed_batch_with_refinement_steps():
+    """Two FP64 refinement steps in a batch (their sigma shared like the
+    others): energies on the oracle's; contexts with different refinement
+    are not batched together."""
+    from paper_1312_2415_amd.binding import SadmrgError, batch_sweep
+    cases = CASES[1:3]
+    pairs = [_pair(c) for c in cases]
+    for _, g in pairs:
+        g.set_precision(1)
+        g.set_refinement(2)
+    Ds = [c[5] for c in cases]
+    for s in range(2):
+        print(f"refined mixed batch sweep {s}", flush=True)
+        batch_sweep([g for _, g in pairs], Ds)
+        for (dm, _), D in zip(pairs, Ds):
+            dm.sweep(D)
+    for case, (dm, g) in zip(cases, pairs):
+        L = case[0]
+        got, ref = g.trace(), np.array(dm.stats.energies)
+        assert len(got) == len(ref), case
+        assert np.abs(got[-(L - 1):] - ref[-(L - 1):]).max() <= 1e-6, case
+    pairs[1][1].set_refinement(3)
+    with pytest.raises(SadmrgError):
+        batch_sweep([g for _, g in pairs], Ds)
+    for _, g in pairs:
+        g.close()
+
+
 def test_malformed_batches_are_rejected():
     from paper_1312_2415_amd.binding import SadmrgError, batch_sweep
     _, a = _pair(CASES[0])

@@ -91,6 +91,44 @@ def test_mixed_sweep_energies_match_fp64_oracle(case):
     g.close()
 
 
+def test_fp64_refinement_steps():
+    """More FP64 Davidson steps after the FP32 phase: one more FP64 sigma per
+    step and micro-iteration, energies still on the FP64 oracle's sweeps."""
+    from paper_1312_2415_amd.binding import SadmrgError
+    L, N, twoS, group, irrep, D, nsw, seed = 10, 6, 2, "D2h", 0, 24, 2, 5
+    I = make_integrals(L, group, seed)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    blob = sd.export_blob(dm)
+    for _ in range(nsw):
+        dm.sweep(D)
+    ref = np.array(dm.stats.energies)
+    calls = {}
+    for steps in (1, 3):
+        g = _gpu(L, group, I)
+        g.set_target(N, twoS, irrep)
+        g.set_davidson(1e-9, 32, 200)
+        g.set_precision(1, 1e-5)
+        g.set_refinement(steps)
+        g.mps_import(blob)
+        g.stats_reset()
+        for s in range(nsw):
+            print(f"refinement {steps} sweep {s}", flush=True)
+            g.sweep(D)
+        got = g.trace()
+        assert len(got) == len(ref)
+        assert np.abs(got[-(L - 1):] - ref[-(L - 1):]).max() <= 1e-6
+        assert abs(g.energy()[0] - dm.emin) <= 1e-6
+        calls[steps] = g.stats()["n_sigma"] / len(got)  # FP64 sigma per micro-iteration
+        for bad in (0, 9):
+            with pytest.raises(SadmrgError):
+                g.set_refinement(bad)
+        g.close()
+    assert abs(calls[1] - 2.0) <= 1e-12
+    assert 2.0 < calls[3] <= 4.0
+
+
 def test_bf16x3_sigma_within_its_rounding_of_oracle():
     """Mode 2: BF16x3 products (hi*hi + hi*lo + lo*hi of the BF16 splits,
     FP32 accumulation).  The sigma stays within a few hundred times the
