@@ -23,8 +23,10 @@ sweeps.  `batch` sweeps 64 independent small problems in lockstep against the
 same sweeps one after another.  `roots` sweeps one GPU's share of twelve roots
 of the headline problem (S in {0, 1, 2} times four irreps, in separate
 symmetry sectors, dealt round-robin to GPUs) in lockstep, in FP64 and in mixed
-precision from the same states, with per-root |dE| and RDM errors.
-`autotune` records the launch-shape choice.  `roofline`
+precision from the same states, with per-root |dE| and RDM errors.  `grad`
+is the energy adjoint (spin-summed 1- and 2-RDM as dE/dh and dE/d(ij|kl)) at
+L = 36, D = 2500, checked by central differences of the frozen-MPS energy
+along a few integral orbits.  `autotune` records the launch-shape choice.  `roofline`
 describes the dominant sigma kernel (the grouped-GEMM pass with the larger
 share of sigma time): its algorithmic flops per launch over its mean launch
 duration, against the FP64 MFMA peak.  `traffic` is filled from the committed
@@ -313,6 +315,82 @@ def roots_bench(k, L, N, D, seed, warm, dav_tol, mixed_tol, refine=1):
             g.close()
 
 
+def grad_bench(L, N, D, seed, warm, n_orbits, tau):
+    """Energy adjoint at the differentiation configuration (L orbitals, N
+    electrons, singlet Ag, D2h): the spin-summed 1- and 2-RDM of the MPS after
+    `warm` sweeps at D, as dE/dh and dE/d(ij|kl), against central differences
+    of E = <psi|H|psi> for that same frozen MPS along symmetry-allowed integral
+    orbits (every evaluation rebuilds all renormalised operators from the MPS
+    with the shifted integrals).  At fixed psi, E is linear in the integrals,
+    so the difference quotient is exact up to rounding."""
+    from paper_1312_2415_amd import SaDMRG
+    from synth.integrals import make_integrals
+    I = make_integrals(L, "D2h", seed)
+    irr = np.asarray(I.orb_irrep)
+    g = SaDMRG(L, 8, irr, device=0)
+    try:
+        g.set_integrals(I.h, I.eri)
+        g.set_target(N, 0, 0)
+        g.set_davidson(1e-7, 32, 100)
+        t = time.perf_counter()
+        g.init_mps(D)
+        for w in range(warm):
+            ts = time.perf_counter()
+            e, _ = g.sweep(D)
+            print(f"grad: sweep {w + 1}/{warm} L={L} D={D} E={e:.10f} {time.perf_counter() - ts:.1f}s",
+                  file=sys.stderr, flush=True)
+        t_sweeps = time.perf_counter() - t
+        blob = g.mps_export()
+        t = time.perf_counter()
+        g1, g2, e0 = g.rdm()
+        t_rdm = time.perf_counter() - t
+        e_id = I.e_const + float(np.einsum("pq,pq", I.h, g1)) + 0.5 * float(np.einsum("ikjl,ijkl", I.eri, g2))
+        dv_of = g2.transpose(0, 2, 1, 3)  # dE/d(ik|jl) = Gamma[i,j,k,l] / 2 at [i,k,j,l]
+        rng = np.random.default_rng(seed + 5)
+        rows = []
+        t_fd = time.perf_counter()
+        for k in range(n_orbits):
+            dh = np.zeros((L, L))
+            dv = np.zeros((L,) * 4)
+            if k % 2 == 0:  # one-body entry h_pq = h_qp of one irrep
+                while True:
+                    p, q = (int(x) for x in rng.integers(0, L, 2))
+                    if irr[p] == irr[q]:
+                        break
+                dh[p, q] = dh[q, p] = 1.0
+                label = f"h[{p},{q}]"
+            else:  # the eightfold orbit of one allowed (ij|kl)
+                while True:
+                    i, j, kk, l = (int(x) for x in rng.integers(0, L, 4))
+                    if irr[i] ^ irr[j] ^ irr[kk] ^ irr[l] == 0:
+                        break
+                for a, b, c, d in ((i, j, kk, l), (j, i, kk, l), (i, j, l, kk), (j, i, l, kk),
+                                   (kk, l, i, j), (l, kk, i, j), (kk, l, j, i), (l, kk, j, i)):
+                    dv[a, b, c, d] = 1.0
+                label = f"({i}{j}|{kk}{l})"
+            pred = float(np.sum(g1 * dh)) + 0.5 * float(np.sum(dv_of * dv))
+            es = []
+            for sgn in (1.0, -1.0):
+                g.set_integrals(I.h + sgn * tau * dh, I.eri + sgn * tau * dv)
+                g.mps_import(blob)
+                es.append(g.rdm(two_body=False)[2])
+            fd = (es[0] - es[1]) / (2.0 * tau)
+            rows.append({"entry": label, "adjoint": pred, "finite_difference": fd, "abs_diff": abs(fd - pred)})
+            print(f"grad: {label} adjoint {pred:.10f} fd {fd:.10f}", file=sys.stderr, flush=True)
+        t_fd = time.perf_counter() - t_fd
+        return {
+            "workload": f"energy adjoint at L={L} N={N} 2S=0 D2h irrep Ag D_SU(2)={D}, seeded synthetic integrals "
+                        f"(seed {seed}), MPS after {warm} sweeps from random",
+            "seconds_sweeps": t_sweeps, "seconds_rdm": t_rdm, "energy": e0,
+            "energy_identity_error": abs(e_id - e0), "trace_gamma": float(np.trace(g1)),
+            "fd_step": tau, "fd_orbits": n_orbits, "fd_seconds_per_evaluation": t_fd / max(2 * n_orbits, 1),
+            "max_abs_diff": max((r["abs_diff"] for r in rows), default=None),
+            "fd": rows,
+        }
+    finally:
+        g.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -342,6 +420,12 @@ def main():
     ap.add_argument("--roots-warmup", type=int, default=2)
     ap.add_argument("--refine", type=int, default=1, help="FP64 Davidson steps after the reduced-precision phase")
     ap.add_argument("--only-roots", action="store_true", help="run only the roots record")
+    ap.add_argument("--grad", type=int, default=4, help="integral orbits checked by finite differences in the "
+                                                        "energy-adjoint record at --grad-L orbitals (0 = skip)")
+    ap.add_argument("--grad-L", type=int, default=36)
+    ap.add_argument("--grad-warmup", type=int, default=3)
+    ap.add_argument("--grad-tau", type=float, default=1e-5)
+    ap.add_argument("--only-grad", action="store_true", help="run only the energy-adjoint record")
     ap.add_argument("--gpc", default="", help="fixed sigma launch shape 'pass1,pass2' (workgroups per CU) "
                                                "instead of autotuning")
     args = ap.parse_args()
@@ -352,6 +436,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.only_grad:
+        print(json.dumps({"grad": grad_bench(args.grad_L, args.N, args.D, args.seed, args.grad_warmup,
+                                             max(args.grad, 1), args.grad_tau)}), flush=True)
+        return
     if args.only_roots:
         print(json.dumps({"roots": roots_bench(args.roots, args.L, args.N, args.D, args.seed, args.roots_warmup,
                                                args.dav_tol, args.mixed_tol, args.refine)}), flush=True)
@@ -537,6 +625,11 @@ def main():
                                         args.mixed_tol, args.refine)
         except Exception as ex:  # the headline record stands on its own
             line["roots"] = {"error": f"{type(ex).__name__}: {ex}"}
+    if args.grad > 0:
+        try:
+            line["grad"] = grad_bench(args.grad_L, N, args.D, args.seed, args.grad_warmup, args.grad, args.grad_tau)
+        except Exception as ex:
+            line["grad"] = {"error": f"{type(ex).__name__}: {ex}"}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, L, N, args.twoS, args.irrep, args.seed, args.cpu_D)
     print(json.dumps(line), flush=True)
