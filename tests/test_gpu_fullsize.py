@@ -1,6 +1,7 @@
-"""The headline shape (L = 28, N = 12, singlet Ag, D2h, D_SU(2) = 2500) in the
-launch configuration the benchmark times, checked through properties that hold
-at any size (the oracle cannot build this problem):
+"""Full-size configurations, checked through properties that hold at any size
+(the oracle cannot sweep these problems).  The headline shape (L = 28,
+N = 12, singlet Ag, D2h, D_SU(2) = 2500) in the launch configuration the
+benchmark times:
 
 * H_eff is symmetric in the plain inner product of the TT basis:
   <x|H y> = <y|H x> for random x, y;
@@ -8,6 +9,10 @@ at any size (the oracle cannot build this problem):
 * the FP32 and BF16x3 products stay within their rounding of the FP64 sigma;
 * the RDMs reproduce the energy: E = e0 + sum h gamma + 1/2 sum (ik|jl) Gamma,
   trace gamma = N, and gamma is symmetric.
+
+The plain FP64 configuration L = 24, N = 12, singlet Ag, D2h, D_SU(2) = 500,
+six sweeps: sweep minima do not rise, a larger bond dimension does not raise
+the energy, and the same symmetry, diagonal and RDM identities hold.
 """
 import numpy as np
 import pytest
@@ -62,4 +67,49 @@ def test_headline_shape_properties():
     assert abs(e_id - e) <= 1e-9 * max(1.0, abs(e))
     assert abs(np.trace(g1) - N) <= 1e-9
     assert np.abs(g1 - g1.T).max() <= 1e-12
+    g.close()
+
+
+def _symmetry_and_diagonal(g, n, rng, nsamp=6):
+    x, y = rng.normal(size=n), rng.normal(size=n)
+    hx, hy = g.sigma(x), g.sigma(y)
+    assert abs(float(x @ hy) - float(y @ hx)) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(hy)
+    d = g.heff_diagonal()
+    for i in rng.choice(n, nsamp, replace=False):
+        e = np.zeros(n)
+        e[i] = 1.0
+        assert abs(g.sigma(e)[i] - d[i]) <= 1e-12 * max(1.0, abs(d[i]))
+
+
+def test_l24_d500_sweeps_and_identities():
+    from paper_1312_2415_amd import SaDMRG
+    L, N = 24, 12
+    I = make_integrals(L, "D2h", 1002)
+    g = SaDMRG(L, 8, I.orb_irrep, device=0)
+    g.set_integrals(I.h, I.eri, I.e_const)
+    g.set_target(N, 0, 0)
+    g.set_davidson(1e-8, 32, 200)
+    g.init_mps(250)
+    e250 = min(g.sweep(250)[0] for _ in range(3))
+    es = []
+    for s in range(6):
+        e, _ = g.sweep(500)
+        print(f"L=24 D=500 sweep {s}: {e:.10f}", flush=True)
+        es.append(e)
+    assert all(np.isfinite(es))
+    assert all(b <= a + 1e-8 for a, b in zip(es, es[1:]))  # sweep minima do not rise
+    assert es[-1] <= e250 + 1e-8  # more states, no higher energy
+    blob = g.mps_export()
+    g.advance(500, L // 2 - 1)
+    g.prepare_step()
+    desc, n = g.psi_layout()
+    assert n > 10000
+    _symmetry_and_diagonal(g, n, np.random.default_rng(24))
+    g.mps_import(blob)
+    g1, g2, e = g.rdm()
+    e_id = I.e_const + float(np.einsum("pq,pq", I.h, g1)) + 0.5 * float(np.einsum("ikjl,ijkl", I.eri, g2))
+    assert abs(e_id - e) <= 1e-9 * max(1.0, abs(e))
+    assert abs(np.trace(g1) - N) <= 1e-9
+    assert np.abs(g1 - g1.T).max() <= 1e-12
+    assert e >= es[-1] - 1e-6  # the final state's energy is not below the sweep minimum
     g.close()
