@@ -1409,12 +1409,23 @@ struct TwoPass {
 static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Triple>& tr, TwoPass& tp, Stream st,
                            bool sigma = false, GemmList* keep2 = nullptr, int gpc1 = GEMM_GPC_PASS1,
                            int gpc2 = GEMM_GPC_PASS2) {
+  // Contraction order of every full product out[R x C] += c opA(A)[R x K1]
+  // B'[K1 x K2] opC(C)[K2 x C] (B' = B or its transpose): left first (T =
+  // opA(A) B' in the workspace, then out += c T opC(C): 2 R K2 (K1 + C)
+  // flops) or right first (U = B' opC(C), then out += c opA(A) U: 2 K1 C
+  // (K2 + R) flops), whichever does fewer flops; blocks whose sector
+  // dimensions change across an operator make the two differ by up to a
+  // factor of several.
   std::vector<int64_t> slot(tr.size(), -1);
+  std::vector<char> right(tr.size(), 0);
   int64_t ws = 0;
   for (size_t i = 0; i < tr.size(); ++i)
     if (!(tr[i].flags & (TT_IDENT_A | TT_IDENT_C))) {
+      const Triple& x = tr[i];
+      const double R = outs[x.blk].rows, Cc = outs[x.blk].cols;
+      right[i] = (double)x.K1 * Cc * (x.K2 + R) < R * x.K2 * (x.K1 + Cc);
       slot[i] = ws;
-      ws += (int64_t)outs[tr[i].blk].rows * tr[i].K2;
+      ws += right[i] ? (int64_t)x.K1 * outs[x.blk].cols : (int64_t)outs[x.blk].rows * x.K2;
     }
   tp.ws.alloc((size_t)std::max<int64_t>(ws, 1));
   // counters
@@ -1429,6 +1440,11 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
     } else if (x.flags & TT_IDENT_A) {
       fl += 2.0 * R * x.K2 * Cc;
       by2 += 8.0 * ((double)R * x.K2 + (double)x.K2 * Cc);
+    } else if (right[i]) {
+      fl += 2.0 * x.K1 * x.K2 * Cc + 2.0 * R * x.K1 * Cc;
+      f1 += 2.0 * x.K1 * x.K2 * Cc;
+      by1 += 8.0 * ((double)x.K1 * x.K2 + (double)x.K2 * Cc + (double)x.K1 * Cc);
+      by2 += 8.0 * ((double)R * x.K1 + (double)x.K1 * Cc);
     } else {
       fl += 2.0 * R * x.K1 * x.K2 + 2.0 * R * x.K2 * Cc;
       f1 += 2.0 * R * x.K1 * x.K2;
@@ -1446,19 +1462,25 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
   tp.nprod = (int64_t)tr.size();
   const int tag1 = tp.p1.tag, tag2 = tp.p2.tag;
   // the two passes' product lists and plans are independent: built on two
-  // host threads (pass 1: the T = op(A) B products into workspace slots;
-  // pass 2: the accumulation into the output blocks)
+  // host threads (pass 1: the T = op(A) B' or U = B' op(C) products into
+  // workspace slots; pass 2: the accumulation into the output blocks)
   parallel_for(2, 2, [&](size_t which) {
     if (which == 0) {
       GemmList g1;
       for (size_t i = 0; i < tr.size(); ++i) {
         const Triple& x = tr[i];
         if (x.flags & (TT_IDENT_A | TT_IDENT_C)) continue;
-        const int R = outs[x.blk].rows;
+        const int R = outs[x.blk].rows, Cc = outs[x.blk].cols;
         const int trA = (x.flags & TT_TRANS_A) ? GT_TRANS_A : 0;
+        const int trC = (x.flags & TT_TRANS_C) ? GT_TRANS_B : 0;
         const bool trB = (x.flags & TT_TRANS_B) != 0;  // middle factor transposed
-        const int b1 = g1.add_block(tp.ws.p + slot[i], R, x.K2, x.K2, 1);
-        g1.add(b1, R, x.K2, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA | (trB ? GT_TRANS_B : 0), 1.0});
+        if (right[i]) {
+          const int b1 = g1.add_block(tp.ws.p + slot[i], x.K1, Cc, Cc, 1);
+          g1.add(b1, x.K1, Cc, GTask{x.b, x.c, x.ldb, x.ldc, x.K2, (trB ? GT_TRANS_A : 0) | trC, 1.0});
+        } else {
+          const int b1 = g1.add_block(tp.ws.p + slot[i], R, x.K2, x.K2, 1);
+          g1.add(b1, R, x.K2, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA | (trB ? GT_TRANS_B : 0), 1.0});
+        }
       }
       g1.plan(tp.p1, st, gpc1);
     } else {
@@ -1476,6 +1498,8 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
           g2.add(first[x.blk], R, Cc, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA | (trB ? GT_TRANS_B : 0), x.coef});
         else if (x.flags & TT_IDENT_A)
           g2.add(first[x.blk], R, Cc, GTask{x.b, x.c, x.ldb, x.ldc, x.K2, trC | (trB ? GT_TRANS_A : 0), x.coef});
+        else if (right[i])
+          g2.add(first[x.blk], R, Cc, GTask{x.a, tp.ws.p + slot[i], x.lda, Cc, x.K1, trA, x.coef});
         else
           g2.add(first[x.blk], R, Cc, GTask{tp.ws.p + slot[i], x.c, x.K2, x.ldc, x.K2, trC, x.coef});
       }
