@@ -622,17 +622,19 @@ def main():
     g.close()
     if args.batch_n > 0:
         line["batch"] = batch_bench(args.batch_n, args.batch_seed, 1, args.mixed_tol)
-    if args.roots > 0:
-        try:
-            line["roots"] = roots_bench(args.roots, L, N, args.D, args.seed, args.roots_warmup, args.dav_tol,
-                                        args.mixed_tol, args.refine)
-        except Exception as ex:  # the headline record stands on its own
-            line["roots"] = {"error": f"{type(ex).__name__}: {ex}"}
+    # the extra records run last, the one that fills device memory most at the
+    # end; after a failed record no further GPU work is started
     if args.grad > 0:
         try:
             line["grad"] = grad_bench(args.grad_L, N, args.D, args.seed, args.grad_warmup, args.grad, args.grad_tau)
-        except Exception as ex:
+        except Exception as ex:  # the headline record stands on its own
             line["grad"] = {"error": f"{type(ex).__name__}: {ex}"}
+    if args.roots > 0 and "error" not in line.get("grad", {}):
+        try:
+            line["roots"] = roots_bench(args.roots, L, N, args.D, args.seed, args.roots_warmup, args.dav_tol,
+                                        args.mixed_tol, args.refine)
+        except Exception as ex:
+            line["roots"] = {"error": f"{type(ex).__name__}: {ex}"}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, L, N, args.twoS, args.irrep, args.seed, args.cpu_D)
     print(json.dumps(line), flush=True)

@@ -109,6 +109,22 @@ static size_t trim_other_pools(DevPool* self) {
   return freed;
 }
 
+// Device memory the library leaves free for the runtime (kernel scratch,
+// queues, code objects, signals): a new block of 1 MiB or more that would cut
+// into it first takes back cached blocks, its own pool's and then the other
+// contexts', and otherwise fails as out of memory (an error the caller can
+// handle, where a runtime allocation failing later would end the queue).
+static constexpr size_t DEV_RESERVE = (size_t)6 << 30;
+static bool dev_room(size_t bytes) {
+  if (bytes < ((size_t)1 << 20)) return true;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;
+  }
+  return fr >= bytes + DEV_RESERVE;
+}
+
 void* dev_alloc(size_t bytes) {
   if (bytes == 0) bytes = 8;
   DevPool* pool = tl_pool;
@@ -122,6 +138,15 @@ void* dev_alloc(size_t bytes) {
       pool->cached.erase(it);
       pool->cached_bytes -= bytes;
       return p;
+    }
+  }
+  if (!dev_room(bytes)) {
+    if (pool) pool_trim(pool, 0);
+    if (!dev_room(bytes)) {
+      if (lk.owns_lock()) lk.unlock();
+      trim_other_pools(pool);
+      if (pool) lk.lock();
+      if (!dev_room(bytes)) dev_fail("hipMalloc: out of device memory (the runtime's reserve is reached)");
     }
   }
   void* p = nullptr;
