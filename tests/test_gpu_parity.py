@@ -79,6 +79,42 @@ def test_sweep_energies_match_oracle(case):
     g.close()
 
 
+def test_products_take_the_cheaper_contraction_order():
+    """Each full product out[R x C] += c op(A)[R x K1] B[K1 x K2] op(C)[K2 x C]
+    runs left first (2 R K2 (K1 + C) flops) or right first (2 K1 C (K2 + R)),
+    whichever is cheaper: the flop counter equals the sum of the minima over
+    the step's products, some steps do take the right-first order, and sigma
+    stays on the oracle's (the per-step parity test above)."""
+    L, N, twoS, group, irrep, D = 10, 8, 2, "D2h", 0, 30
+    I = make_integrals(L, group, 11)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    g = _gpu(L, group, I)
+    g.set_target(N, twoS, irrep)
+    g.mps_import(sd.export_blob(dm))
+    saved = 0.0
+    for i in range(L - 1):
+        g.prepare_step()
+        sh = g.task_shapes().astype(np.float64)
+        R, K1, K2, C, fl = sh.T
+        fl = fl.astype(int)
+        ident_c, ident_a = (fl & 8) != 0, (fl & 4) != 0
+        full = ~(ident_c | ident_a)
+        left = 2 * R * K2 * (K1 + C)
+        right = 2 * K1 * C * (K2 + R)
+        want = (np.minimum(left, right)[full].sum() + (2 * R * K1 * C)[ident_c].sum()
+                + (2 * R * K2 * C)[ident_a].sum())
+        flops, _, ntasks = g.sigma_counters()
+        assert ntasks == len(sh)
+        assert abs(flops - want) <= 1e-9 * want
+        saved += (left - np.minimum(left, right))[full].sum()
+        if i < L - 2:
+            g.advance(D, 1)
+    assert saved > 0.0
+    g.close()
+
+
 def test_kept_enlargements_give_identical_sweeps():
     """Reusing the previous pass's enlarged blocks changes nothing: the
     traces with and without the cache agree bit for bit, also across a
