@@ -13,8 +13,9 @@ random at bond dimension D and every sweep (warm-up and timed) runs at D, so
 every kernel launch of the run has the shapes of the headline workload.
 
 Reported `value` is the sigma-product rate of the plain FP64 path: algorithmic
-FP64 flops of all H_eff*psi calls in the timed sweeps divided by their kernel
-time (HIP events on the library stream).  `ms_per_step` is the wall time per
+FP64 flops of all H_eff*psi calls in the timed sweeps (every block triple
+product in the cheaper of its two contraction orders, the order the kernels
+run) divided by their kernel time (HIP events on the library stream).  `ms_per_step` is the wall time per
 FP64 sweep.  `mixed` and `mixed_bf16x3` repeat the timed sweeps from the same
 state with FP32 / BF16x3 sigma products in Davidson (one FP64 Davidson step
 per micro-iteration gives the energy) and report s/sweep, speedup, the reduced
@@ -53,8 +54,8 @@ BF16_MFMA_PEAK = 2500.0  # TFLOP/s, dense BF16 matrix peak (a BF16x3 product cos
 HBM_PEAK = 8000.0  # GB/s
 KERNEL_SRC = os.path.join(ROOT, "paper_1312_2415_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_kernel_sigma_L28_N12_D2500_traffic.json")
-PASS_KERNEL = {"pass1": "gemm_tile_kernel<double, 0> (sigma pass 1: T = X psi)",
-               "pass2": "gemm_stream_kernel<double, 1> (sigma pass 2: sigma += T Y^T)"}
+PASS_KERNEL = {"pass1": "gemm_tile_kernel<double, 0> (sigma pass 1: T = X psi or U = psi Y^T per product)",
+               "pass2": "gemm_stream_kernel<double, 1> (sigma pass 2: sigma += T Y^T or X U)"}
 
 
 def kernel_source_hash() -> str:
