@@ -30,7 +30,7 @@ def load_library(path: str | None = None):
     if _LIB is not None and _LIB_PATH == path:
         return _LIB
     if not os.path.exists(path):
-        raise RuntimeError(f"libsadmrg not built: {path} is missing (run __graft_entry__.build())")
+        raise RuntimeError(f"libsadmrg not built: {path} is missing (build it with python -m paper_1312_2415_amd.build)")
     lib = ctypes.CDLL(path)
     c_int, c_dbl, c_vp, c_sz = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
     P = ctypes.POINTER
