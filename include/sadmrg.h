@@ -166,7 +166,7 @@ int sadmrg_batch_sweep(sadmrg_ctx* const* ctxs, int n, const int* D, double* e_m
  * fixed pseudo-random vector: the first GEMM pass with one output tile per
  * workgroup or 8 cost-balanced ranges per compute unit, times the
  * accumulating pass with 12, 16, 24, 32, 48 or 64 ranges per compute unit
- * (defaults: one tile per workgroup, 24 ranges).  The fastest pair is kept
+ * (defaults: one tile per workgroup, 64 ranges).  The fastest pair is kept
  * for this context (later steps are planned with it) and the step is
  * re-planned.  Results do not depend on the choice beyond the summation
  * order of cut tiles.  *gpc1, *gpc2 (may be NULL): the chosen pair (0 = one

@@ -1386,7 +1386,7 @@ struct OutBlk {
 #define GEMM_GPC_PASS1 0
 #endif
 #ifndef GEMM_GPC_PASS2
-#define GEMM_GPC_PASS2 24
+#define GEMM_GPC_PASS2 64
 #endif
 
 struct TwoPass {
