@@ -164,6 +164,22 @@ class SaDMRG:
         self._chk(self.lib.sadmrg_solve(self.h, n, D, ec, ms, nz, ctypes.byref(e)))
         return e.value
 
+    def solve_extrapolated(self, schedule):
+        """The convergence scheme stage by stage with the discarded-weight
+        extrapolation of section "Extrapolation" (eq. extrapolSchemeEq: E(D) =
+        E_exact + C1 w_disc(D)): after each stage, E(D) is the lowest energy of
+        its last sweep and w_disc(D) the largest discarded weight of that sweep.
+        Returns (E0, C1, [(D, w_disc, E(D))]), E0 and C1 from the least-squares
+        line through the stages that truncated (w_disc > 0)."""
+        n_sweep = 2 * (self.L - 1)
+        points = []
+        for stage in schedule:
+            self.solve([stage])
+            w = self.energy()[2]
+            points.append((int(stage[0]), w, float(np.min(self.trace()[-n_sweep:]))))
+        e0, c1 = fit_discarded_weight([(w, e) for _, w, e in points])
+        return e0, c1, points
+
     def energy(self):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         self._chk(self.lib.sadmrg_get_energy(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
@@ -307,6 +323,26 @@ class SaDMRG:
 
     def stats_reset(self):
         self._chk(self.lib.sadmrg_stats_reset(self.h))
+
+
+def fit_discarded_weight(points):
+    """Least-squares line E = E0 + C1 w through (w_disc, E) pairs (section
+    "Extrapolation", eq. extrapolSchemeEq).  Pairs with w_disc = 0 are exact
+    energies at their D: if there is one, E0 is the lowest of them and C1 = 0;
+    a single truncated pair gives C1 = 0 and E0 = its energy.  Returns (E0, C1)."""
+    pts = [(float(w), float(e)) for w, e in points]
+    if not pts:
+        raise ValueError("no (w_disc, E) pairs")
+    exact = [e for w, e in pts if w <= 0.0]
+    if exact:
+        return min(exact), 0.0
+    if len(pts) == 1:
+        return pts[0][1], 0.0
+    w = np.array([p[0] for p in pts])
+    e = np.array([p[1] for p in pts])
+    A = np.stack([np.ones_like(w), w], axis=1)
+    (e0, c1), *_ = np.linalg.lstsq(A, e, rcond=None)
+    return float(e0), float(c1)
 
 
 def device_memory(device: int = 0, lib_path: str | None = None):

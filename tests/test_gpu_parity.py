@@ -234,6 +234,31 @@ def test_spin_and_symmetry_targets_exact(N, twoS, group, irrep):
     g.close()
 
 
+def test_discarded_weight_extrapolation_stages():
+    """solve_extrapolated runs the scheme stage by stage: each stage's E(D)
+    is the lowest energy of its last sweep and stays above FCI, E(D) does not
+    rise with D, E0 is the least-squares intercept of the returned pairs, and
+    a complete bond dimension (w = 0) returns the FCI energy itself."""
+    I = make_integrals(8, "C1", 1001)
+    efci = fci_solve(I.h, I.eri, 8, 0)[0][0]
+    g = _gpu(8, "C1", I)
+    g.set_target(8, 0, 0)
+    g.set_seed(7)
+    Ds = (28, 34, 40, 46)
+    e0, c1, pts = g.solve_extrapolated([(D, 1e-10, 6) for D in Ds])
+    assert [p[0] for p in pts] == list(Ds)
+    es = np.array([p[2] for p in pts])
+    ws = np.array([p[1] for p in pts])
+    assert np.all(es >= efci - 1e-10) and np.all(ws > 0)
+    assert np.all(np.diff(es) <= 1e-9)
+    c1_ref, e0_ref = np.polyfit(ws, es, 1)
+    assert abs(e0 - e0_ref) <= 1e-9 and abs(c1 - c1_ref) <= 1e-6 * max(1.0, abs(c1_ref))
+    e0x, c1x, ptsx = g.solve_extrapolated([(128, 1e-10, 3)])
+    assert ptsx[0][1] == 0.0 and c1x == 0.0
+    assert abs(e0x - efci) <= 1e-9
+    g.close()
+
+
 def test_two_orbitals_single_step():
     # L = 2: the only micro-iteration covers the whole system (Hubbard dimer form)
     h = np.array([[0.0, -1.0], [-1.0, 0.0]])

@@ -73,3 +73,23 @@ def test_create_rejects_bad_arguments():
     assert lib.sadmrg_create(ctypes.byref(h), 1, 1, irr, 0) == -1       # L < 2
     assert lib.sadmrg_create(ctypes.byref(h), 4, 3, irr, 0) == -1       # bad group order
     assert lib.sadmrg_create(ctypes.byref(h), 4, 2, irr, 0) == -1       # irrep out of range
+
+
+def test_discarded_weight_fit():
+    """E(D) = E0 + C1 w(D) (section "Extrapolation"): a line is recovered
+    exactly, noisy pairs give the least-squares line, an exact (w = 0)
+    energy is returned as it is, a single pair carries no slope."""
+    import numpy as np
+    pts = [(w, -1.5 + 3.0 * w) for w in (1e-3, 4e-4, 1e-4)]
+    e0, c1 = binding.fit_discarded_weight(pts)
+    assert abs(e0 + 1.5) <= 1e-12 and abs(c1 - 3.0) <= 1e-9
+    rng = np.random.default_rng(1)
+    w = np.array([2e-3, 1e-3, 5e-4, 2e-4])
+    e = -2.0 + 5.0 * w + rng.normal(scale=1e-5, size=w.size)
+    e0, c1 = binding.fit_discarded_weight(list(zip(w, e)))
+    c1_ref, e0_ref = np.polyfit(w, e, 1)
+    assert abs(e0 - e0_ref) <= 1e-10 and abs(c1 - c1_ref) <= 1e-6
+    assert binding.fit_discarded_weight([(1e-3, -1.0), (0.0, -1.2), (0.0, -1.1)]) == (-1.2, 0.0)
+    assert binding.fit_discarded_weight([(1e-3, -1.0)]) == (-1.0, 0.0)
+    with pytest.raises(ValueError):
+        binding.fit_discarded_weight([])
