@@ -57,3 +57,30 @@ class DMRGEnergy(torch.autograd.Function):
 def dmrg_energy(h, eri, solver, schedule, e_const=0.0, warm=True):
     """Functional form of ``DMRGEnergy.apply``."""
     return DMRGEnergy.apply(h, eri, solver, schedule, e_const, warm)
+
+
+def rotate_integrals(h, eri, kappa):
+    """The integrals in the orbitals rotated by U = exp(kappa - kappa^T):
+    h' = U^T h U and (pq|rs)' = sum_ijkl U_ip U_jq U_kr U_ls (ij|kl), one
+    index at a time; differentiable in kappa (float64 tensors, one device)."""
+    u = torch.matrix_exp(kappa - kappa.transpose(0, 1))
+    L = h.shape[0]
+    h2 = u.transpose(0, 1) @ h @ u
+    v = eri
+    for axis in range(4):
+        w = torch.movedim(v, axis, 0).reshape(L, -1)
+        v = torch.movedim((u.transpose(0, 1) @ w).reshape(L, L, L, L), 0, axis)
+    return h2, v
+
+
+def orbital_gradient(h, eri, solver, schedule, e_const=0.0):
+    """dE/dkappa at kappa = 0 for orbitals rotated by exp(kappa - kappa^T):
+    the orbital gradient that a DMRG-SCF step (section "DMRG-SCF") is built
+    from.  The chain rule runs through ``rotate_integrals`` and the energy's
+    adjoint (the RDMs); the solver is left at its re-converged MPS.  Returns
+    (E, gradient [L, L], antisymmetric)."""
+    kappa = torch.zeros_like(h, requires_grad=True)
+    h2, v2 = rotate_integrals(h, eri, kappa)
+    e = dmrg_energy(h2, v2, solver, schedule, e_const)
+    (g,) = torch.autograd.grad(e, kappa)
+    return e.detach(), g
