@@ -283,6 +283,20 @@ int sadmrg_sigma(sadmrg_ctx* ctx, const double* x, double* y, int on_device);
 /* Diagonal of the effective Hamiltonian at the prepared step (same layout). */
 int sadmrg_heff_diagonal(sadmrg_ctx* ctx, double* d, int on_device);
 
+/* Initial vector of the prepared step's Davidson solve (same layout as
+ * sadmrg_sigma): the current two-site object, moved to the prepared centre
+ * by the decomposition of the previous step and the recoupling with the next
+ * site tensor (section "The reduced two-site object", eqs. StoTT and TTtoS).
+ * Read it before sadmrg_sigma with host vectors, which overwrites it.
+ * out[n] is a device pointer when on_device != 0.  Errors: EINVAL. */
+int sadmrg_debug_guess(sadmrg_ctx* ctx, double* out, int on_device);
+
+/* Launch plan of the prepared step's FP64 sigma, out[6]: for the first and
+ * then the accumulating GEMM pass, the number of tile pieces, of workgroups,
+ * and of output tiles cut between workgroups (added by the ordered reduction).
+ * Errors: EINVAL. */
+int sadmrg_debug_plan_stats(sadmrg_ctx* ctx, int64_t* out);
+
 /* Work counters of the prepared step's sigma: algorithmic flops (the sum
  * over block products c op(A) B op(C) of the two GEMMs' 2mnk, tile padding
  * excluded), bytes (every operator the products read, all its blocks, once,

@@ -210,3 +210,62 @@ class Expansion:
                         basis[:, :, idx:idx + self.ng] += cgv * L_[:, d1][:, None, None] * R_[:, d2, :][None, :, :]
             out[m] = basis.reshape(El.dim[m] * Er.dim[m], F.dim * self.ng)
         return out
+
+
+# ---------------------------------------------------------------------------
+# Reduced density matrices of an MPS, written out in Fock space.  The paper's
+# calc2DM (section "CheMPS2 library", the DMRG object) defines
+#   Gamma_{(i s)(j t);(k s)(l t)} = <a+_{i s} a+_{j t} a_{l t} a_{k s}>,
+#   Gamma^A_{ij;kl} = sum_{s t} Gamma_{(i s)(j t);(k s)(l t)},
+#   Gamma^B_{ij;kl} = sum_{s t} (-1)^(s - t) Gamma_{(i s)(j t);(k s)(l t)}.
+# The singlet-embedded state carries the right-boundary ghost spin; tracing it
+# out leaves the average over the 2S+1 members of the multiplet, so Gamma^B
+# here is that multiplet average (Gamma^A does not depend on the member).
+# ---------------------------------------------------------------------------
+def state_vector(ex: Expansion, dm) -> np.ndarray:
+    """Normalised many-electron state (Fock dim, ghost dim) of dm's MPS at
+    its current two-site centre."""
+    from .sadmrg import LeftEnl, RightEnl
+    P = dm.P
+    i, psi = dm.center
+    El = LeftEnl(P, i + 1, dm.dims[i])
+    Er = RightEnl(P, i + 1, dm.dims[i + 2])
+    secs = sorted(set(El.dim) & set(Er.dim))
+    basis = ex.two_site_basis(i, El, Er, secs, ex.left_states(i), ex.right_states(i + 2))
+    v = np.zeros(ex.F.dim * ex.ng)
+    for m in secs:
+        x = psi.get(m)
+        if x is None:
+            continue
+        v += basis[m].T @ x.ravel()
+    v = v.reshape(ex.F.dim, ex.ng)
+    return v / np.linalg.norm(v)
+
+
+def rdms_of_state(F: Fock, Psi: np.ndarray):
+    """(gamma, Gamma^A, Gamma^B, <S^2>) of a normalised (Fock, ghost) state.
+
+    Every element is an inner product of explicit vectors:
+    <a+_{i s} a+_{j t} a_{l t} a_{k s}> = (a_{j t} a_{i s} Psi) . (a_{l t} a_{k s} Psi).
+    <S^2> comes from the spin operators themselves, S^2 = S_- S_+ + S_z^2 + S_z,
+    not from the density matrices, so that it checks them.
+    """
+    L = F.L
+    ann = {(p, s): F.cdag[p, s].T.tocsr() for p in range(L) for s in (0, 1)}
+    g1 = np.zeros((L, L))
+    for s in (0, 1):
+        A = np.stack([(ann[p, s] @ Psi).ravel() for p in range(L)])  # a_{p s} Psi
+        g1 += A @ A.T  # <a+_{p s} a_{q s}> = (a_p Psi).(a_q Psi)
+    GA = np.zeros((L, L, L, L))
+    GB = np.zeros((L, L, L, L))
+    for s in (0, 1):
+        for t in (0, 1):
+            W = np.stack([(ann[j, t] @ (ann[i, s] @ Psi)).ravel() for i in range(L) for j in range(L)])
+            G = (W @ W.T).reshape(L, L, L, L)  # [i, j, k, l]
+            GA += G
+            GB += G if s == t else -G
+    Sp = sum(F.cdag[p, 0] @ ann[p, 1] for p in range(L))
+    Sz = 0.5 * sum(F.cdag[p, 0] @ ann[p, 0] - F.cdag[p, 1] @ ann[p, 1] for p in range(L))
+    S2 = (Sp.T @ Sp + Sz @ Sz + Sz).tocsr()
+    s2 = float(np.sum(Psi * (S2 @ Psi)))
+    return g1, GA, GB, s2

@@ -198,3 +198,36 @@ def rdms(f: FCI, c: np.ndarray):
 def s2_from_gamma(gA: np.ndarray, N: int) -> float:
     """<S^2> = -N(N-4)/4 - 1/2 sum_ij Gamma^A_{ij;ji}."""
     return -N * (N - 4) / 4.0 - 0.5 * np.einsum("ijji->", gA)
+
+
+def rdm_b_multiplet(f: FCI, c: np.ndarray):
+    """The paper's Gamma^B_{ij;kl} = sum_{s t} (-1)^(s-t) <a+_{i s} a+_{j t}
+    a_{l t} a_{k s}>, averaged over the 2S+1 members M = S .. -S of the
+    multiplet of the FCI vector c (given at M = S).  The lower members are
+    S_- applied to c, normalised; each expectation value is written out with
+    spin-resolved hops:  Gamma^B = 4 <Sz_ik Sz_jl> - d_jk gamma_il with
+    Sz_pq = (E^up_pq - E^down_pq) / 2."""
+    L, N = f.L, f.N
+    space, vec = f.space, c / np.linalg.norm(c)
+    acc = np.zeros((L, L, L, L))
+    for step in range(f.twoS + 1):
+        twoM = f.twoS - 2 * step
+        if step > 0:
+            lower = DetSpace(L, N, twoM)
+            Sm = None
+            for p in range(L):
+                t = hop(space, lower, 2 * p + 1, 2 * p)
+                Sm = t if Sm is None else Sm + t
+            vec = Sm @ vec
+            vec = vec / np.linalg.norm(vec)
+            space = lower
+        Eu = {(p, q): hop(space, space, 2 * p, 2 * q) for p in range(L) for q in range(L)}
+        Ed = {(p, q): hop(space, space, 2 * p + 1, 2 * q + 1) for p in range(L) for q in range(L)}
+        Z = np.stack([0.5 * ((Eu[p, q] - Ed[p, q]) @ vec) for p in range(L) for q in range(L)])
+        g1 = np.array([[vec @ ((Eu[p, q] + Ed[p, q]) @ vec) for q in range(L)] for p in range(L)])
+        M = (Z @ Z.T).reshape(L, L, L, L)  # [k, i, j, l] = <Sz_ik Sz_jl>
+        G = 4.0 * np.einsum("kijl->ijkl", M)
+        for j in range(L):
+            G[:, j, j, :] -= g1
+        acc += G
+    return acc / (f.twoS + 1)

@@ -57,6 +57,8 @@ def load_library(path: str | None = None):
         "sadmrg_psi_layout": (c_int, [c_vp, P(c_int), P(ctypes.c_int64), P(ctypes.c_int64)]),
         "sadmrg_sigma": (c_int, [c_vp, c_vp, c_vp, c_int]),
         "sadmrg_heff_diagonal": (c_int, [c_vp, c_vp, c_int]),
+        "sadmrg_debug_guess": (c_int, [c_vp, c_vp, c_int]),
+        "sadmrg_debug_plan_stats": (c_int, [c_vp, P(ctypes.c_int64)]),
         "sadmrg_sigma_counters": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(ctypes.c_int64)]),
         "sadmrg_stats": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl), P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_reset": (c_int, [c_vp]),
@@ -249,6 +251,19 @@ class SaDMRG:
         d = np.zeros(n)
         self._chk(self.lib.sadmrg_heff_diagonal(self.h, d.ctypes.data_as(ctypes.c_void_p), 0))
         return d
+
+    def guess(self):
+        """Initial Davidson vector of the prepared step (host copy)."""
+        _, n = self.psi_layout()
+        d = np.zeros(n)
+        self._chk(self.lib.sadmrg_debug_guess(self.h, d.ctypes.data_as(ctypes.c_void_p), 0))
+        return d
+
+    def plan_stats(self):
+        """((pieces, workgroups, cut tiles) of pass 1, same of pass 2)."""
+        out = (ctypes.c_int64 * 6)()
+        self._chk(self.lib.sadmrg_debug_plan_stats(self.h, out))
+        return tuple(out[:3]), tuple(out[3:])
 
     def sigma_counters(self):
         f, b = ctypes.c_double(), ctypes.c_double()

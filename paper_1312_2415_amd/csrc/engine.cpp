@@ -4619,6 +4619,36 @@ int sadmrg_heff_diagonal(sadmrg_ctx* ctx, double* d, int on_device) {
   });
 }
 
+int sadmrg_debug_guess(sadmrg_ctx* ctx, double* out, int on_device) {
+  return guard(ctx, [&] {
+    auto& E = ctx->e;
+    auto& S = E.step;
+    if (S.i < 0 || !S.X) sadmrg::fail(SADMRG_EINVAL, "no prepared step");
+    if (!out) sadmrg::fail(SADMRG_EINVAL, "null vector");
+    if (on_device)
+      sadmrg::dev_d2d(out, S.in.p, (size_t)S.n * 8, E.st);
+    else
+      sadmrg::dev_d2h(out, S.in.p, (size_t)S.n * 8, E.st);
+    sadmrg::dev_sync(E.st);
+    return 0;
+  });
+}
+
+int sadmrg_debug_plan_stats(sadmrg_ctx* ctx, int64_t* out) {
+  return guard(ctx, [&] {
+    auto& S = ctx->e.step;
+    if (S.i < 0 || !S.X) sadmrg::fail(SADMRG_EINVAL, "no prepared step");
+    if (!out) sadmrg::fail(SADMRG_EINVAL, "null output");
+    const sadmrg::GemmList::Plan* pl[2] = {&S.plan.p1, &S.plan.p2};
+    for (int q = 0; q < 2; ++q) {
+      out[3 * q + 0] = pl[q]->ntiles;
+      out[3 * q + 1] = pl[q]->nwg;
+      out[3 * q + 2] = pl[q]->nreds;
+    }
+    return 0;
+  });
+}
+
 int sadmrg_sigma_counters(sadmrg_ctx* ctx, double* flops, double* bytes, int64_t* tasks) {
   return guard(ctx, [&] {
     auto& S = ctx->e.step;

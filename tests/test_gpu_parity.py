@@ -312,3 +312,48 @@ def test_rejects_bad_targets_and_integrals():
     with pytest.raises(SadmrgError):
         g.set_integrals(I.h, bad)
     g.close()
+
+
+def test_sigma_matches_oracle_on_wide_blocks():
+    """C1, L = 10, N = 10, D = 256: the enlarged sector blocks reach 144 wide,
+    so products span several 64 x 64 output tiles in both directions, both
+    GEMM passes run K beyond one 32-deep chunk, both contraction orders occur
+    and the accumulating pass cuts tiles between workgroups (ordered partial
+    reduction).  sigma and the diagonal against the oracle at every step."""
+    L, N, twoS, group, irrep, D = 10, 10, 0, "C1", 0, 256
+    I = make_integrals(L, group, 11)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    g = _gpu(L, group, I)
+    g.set_target(N, twoS, irrep)
+    widest, orders, cuts = 0, set(), 0
+    for i in range(L - 1):
+        print(f"wide step {i}", flush=True)
+        g.mps_import(sd.export_blob(dm))
+        g.prepare_step()
+        desc, n = g.psi_layout()
+        El, Er, Xe, Ye, secs = dm.enlarged(i)
+        assert [tuple(d[:3]) for d in desc] == list(secs)
+        sh = g.task_shapes().astype(np.float64)
+        R, K1, K2, C, fl = sh.T
+        widest = max(widest, int(max(R.max(), K1.max(), K2.max(), C.max())))
+        full = (fl.astype(int) & 12) == 0
+        left, right = 2 * R * K2 * (K1 + C), 2 * K1 * C * (K2 + R)
+        orders |= {"left"} if (left <= right)[full].any() else set()
+        orders |= {"right"} if (right < left)[full].any() else set()
+        cuts += g.plan_stats()[1][2]
+        He = sd.Heff(P, Xe, Ye, secs)
+        shapes = {m: (El.dim[m], Er.dim[m]) for m in secs}
+        x = np.random.default_rng(300 + i).normal(size=n)
+        ref = sd.flatten(He.apply(sd.unflatten(x, shapes, secs)), secs)
+        got = g.sigma(x)
+        assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+        dref = sd.flatten(He.diagonal(shapes), secs)
+        assert np.abs(g.heff_diagonal() - dref).max() <= 1e-10 * max(1.0, np.abs(dref).max())
+        if i < L - 2:
+            dm.micro(i, D, "right")
+    g.close()
+    assert widest > 128
+    assert orders == {"left", "right"}
+    assert cuts > 0
