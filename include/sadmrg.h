@@ -280,6 +280,25 @@ int sadmrg_advance(sadmrg_ctx* ctx, int D, int n, double* e_min);
 int sadmrg_debug_task_shapes(sadmrg_ctx* ctx, int* out, int64_t* n);
 int sadmrg_psi_layout(sadmrg_ctx* ctx, int* nsec, int64_t* desc, int64_t* n);
 int sadmrg_sigma(sadmrg_ctx* ctx, const double* x, double* y, int on_device);
+/* sadmrg_sigma for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same FP64 sigma of the prepared step, y = H_eff x, with x[n] and y[n]
+ * DEVICE pointers (may alias), enqueued on the context stream and finished
+ * before return.  Every intermediate (the copies of x and y, the first GEMM
+ * pass's workspace, the partial tiles of cut output tiles, and the launch
+ * records) lives in one static device array of 32 MiB per device, allocated
+ * when the library is loaded and held until the process ends; no device
+ * memory is allocated or freed by this call.  The array keeps the last
+ * call's contents; the output region is cleared on every call.  Calls are
+ * serialised per device inside the process (a host lock held until the
+ * stream is finished); calls that overlap on one device in any other way,
+ * for instance work captured into a graph and replayed concurrently, race
+ * on the array.  Results equal sadmrg_sigma's (same kernels, same order).
+ * Errors: EINVAL (no prepared step, precision mode 1 or 2, or a step whose
+ * intermediates exceed the array: the message gives the bytes needed),
+ * EDEVICE. */
+int sadmrg_sigma_noalloc(sadmrg_ctx* ctx, const double* x, double* y);
+
 /* Diagonal of the effective Hamiltonian at the prepared step (same layout). */
 int sadmrg_heff_diagonal(sadmrg_ctx* ctx, double* d, int on_device);
 

@@ -58,6 +58,7 @@ def load_library(path: str | None = None):
         "sadmrg_sigma": (c_int, [c_vp, c_vp, c_vp, c_int]),
         "sadmrg_heff_diagonal": (c_int, [c_vp, c_vp, c_int]),
         "sadmrg_debug_guess": (c_int, [c_vp, c_vp, c_int]),
+        "sadmrg_sigma_noalloc": (c_int, [c_vp, c_vp, c_vp]),
         "sadmrg_debug_plan_stats": (c_int, [c_vp, P(ctypes.c_int64)]),
         "sadmrg_sigma_counters": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(ctypes.c_int64)]),
         "sadmrg_stats": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl), P(c_dbl), P(c_dbl)]),
@@ -244,6 +245,17 @@ class SaDMRG:
         y = np.zeros_like(xx)
         self._chk(self.lib.sadmrg_sigma(self.h, xx.ctypes.data_as(ctypes.c_void_p),
                                         y.ctypes.data_as(ctypes.c_void_p), 0))
+        return y
+
+    def sigma_noalloc(self, x, y=None):
+        """sadmrg_sigma_noalloc: x (and y) are torch CUDA float64 tensors of the
+        prepared step's length; the library allocates no device memory."""
+        if y is None:
+            import torch
+            y = torch.empty_like(x)
+        if not (getattr(x, "is_cuda", False) and getattr(y, "is_cuda", False)):
+            raise ValueError("sigma_noalloc takes device tensors")
+        self._chk(self.lib.sadmrg_sigma_noalloc(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr())))
         return y
 
     def heff_diagonal(self):

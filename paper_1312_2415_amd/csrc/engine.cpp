@@ -4284,6 +4284,7 @@ int sadmrg_create(sadmrg_ctx** out, int L, int group_order, const int* orb_irrep
     if (nd <= 0) sadmrg::fail(SADMRG_EDEVICE, "no HIP device available");
     if (device < 0 || device >= nd) sadmrg::fail(SADMRG_EINVAL, "device index out of range");
     sadmrg::dev_set_device(device);
+    sadmrg::scratch_init(device);
     c->e.device = device;
     c->e.pool = c->pool;
     c->e.P.L = L;
@@ -4630,6 +4631,98 @@ int sadmrg_debug_guess(sadmrg_ctx* ctx, double* out, int on_device) {
     else
       sadmrg::dev_d2h(out, S.in.p, (size_t)S.n * 8, E.st);
     sadmrg::dev_sync(E.st);
+    return 0;
+  });
+}
+
+int sadmrg_sigma_noalloc(sadmrg_ctx* ctx, const double* x, double* y) {
+  return guard(ctx, [&] {
+    using namespace sadmrg;
+    auto& E = ctx->e;
+    auto& S = E.step;
+    if (S.i < 0 || !S.X) fail(SADMRG_EINVAL, "no prepared step");
+    if (!x || !y) fail(SADMRG_EINVAL, "null vector");
+    if (E.prec != 0) fail(SADMRG_EINVAL, "the allocation-free sigma is FP64: set precision mode 0");
+    if (S.p2_pending) fail(SADMRG_EINVAL, "sigma plan incomplete");
+    char* base = (char*)scratch_ptr(E.device);
+    std::mutex* use = scratch_lock(E.device);
+    if (!base || !use) fail(SADMRG_EDEVICE, "static workspace not initialised on this device");
+    const GemmList::Plan* pl[2] = {&S.plan.p1, &S.plan.p2};
+    // regions of the static array, each 256-byte aligned: psi in, sigma out,
+    // the first pass's workspace, the partial tiles of both passes, then the
+    // launch records of both passes with their pointers moved into the array
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      const size_t at = off;
+      off += (bytes + 255) / 256 * 256;
+      return at;
+    };
+    const size_t o_in = take((size_t)S.n * 8), o_out = take((size_t)S.n * 8);
+    const size_t o_ws = take(S.plan.ws.n * 8);
+    const size_t o_part[2] = {take(pl[0]->part.n * 8), take(pl[1]->part.n * 8)};
+    size_t o_tiles[2], o_tasks[2], o_ws0[2], o_reds[2];
+    for (int q = 0; q < 2; ++q) {
+      o_tiles[q] = take(pl[q]->tiles.host.size() * sizeof(GTile));
+      o_tasks[q] = take(pl[q]->tasks.host.size() * sizeof(GTask));
+      o_ws0[q] = take(pl[q]->wstart.host.size() * sizeof(int));
+      o_reds[q] = take(pl[q]->reds.host.size() * sizeof(RTile));
+    }
+    if (off > scratch_bytes())
+      fail(SADMRG_EINVAL, "prepared step needs " + std::to_string(off) + " bytes of workspace; the allocation-free sigma holds at most " +
+                              std::to_string(scratch_bytes()));
+    struct Region {
+      const double* from;
+      size_t n;
+      size_t to;
+    };
+    const Region reg[] = {{S.in.p, (size_t)S.n, o_in},
+                          {S.out.p, (size_t)S.n, o_out},
+                          {S.plan.ws.p, S.plan.ws.n, o_ws},
+                          {pl[0]->part.p, pl[0]->part.n, o_part[0]},
+                          {pl[1]->part.p, pl[1]->part.n, o_part[1]}};
+    auto remap = [&](const double* p) -> double* {
+      if (!p) return nullptr;
+      for (const Region& r : reg)
+        if (r.from && p >= r.from && p < r.from + r.n) return (double*)(base + r.to) + (p - r.from);
+      return const_cast<double*>(p);  // operator stores: read in place
+    };
+    // the records, remapped, in one host image of the record regions
+    const size_t rec0 = o_tiles[0];
+    std::vector<char> img(off - rec0);
+    for (int q = 0; q < 2; ++q) {
+      GTile* tl = (GTile*)(img.data() + (o_tiles[q] - rec0));
+      for (size_t j = 0; j < pl[q]->tiles.host.size(); ++j) {
+        tl[j] = pl[q]->tiles.host[j];
+        tl[j].out = remap(tl[j].out);
+        tl[j].part = remap(tl[j].part);
+      }
+      GTask* tk = (GTask*)(img.data() + (o_tasks[q] - rec0));
+      for (size_t j = 0; j < pl[q]->tasks.host.size(); ++j) {
+        tk[j] = pl[q]->tasks.host[j];
+        tk[j].a = remap(tk[j].a);
+        tk[j].b = remap(tk[j].b);
+      }
+      if (!pl[q]->wstart.host.empty())
+        std::memcpy(img.data() + (o_ws0[q] - rec0), pl[q]->wstart.host.data(), pl[q]->wstart.host.size() * sizeof(int));
+      RTile* rd = (RTile*)(img.data() + (o_reds[q] - rec0));
+      for (size_t j = 0; j < pl[q]->reds.host.size(); ++j) {
+        rd[j] = pl[q]->reds.host[j];
+        rd[j].out = remap(rd[j].out);
+        rd[j].part = (const double*)remap(rd[j].part);
+      }
+    }
+    // one call at a time per device: the array keeps the last call's contents
+    std::lock_guard<std::mutex> lk(*use);
+    dev_h2d(base + rec0, img.data(), img.size(), E.st);
+    dev_d2d(base + o_in, x, (size_t)S.n * 8, E.st);
+    dev_zero(base + o_out, (size_t)S.n * 8, E.st);  // pass 2 accumulates into it
+    for (int q = 0; q < 2; ++q) {
+      launch_gemm((const GTile*)(base + o_tiles[q]), (const GTask*)(base + o_tasks[q]), (const int*)(base + o_ws0[q]),
+                  pl[q]->nwg, pl[q]->stream, pl[q]->tag, false, E.st);
+      launch_reduce((const RTile*)(base + o_reds[q]), pl[q]->nreds, false, E.st);
+    }
+    dev_d2d(y, base + o_out, (size_t)S.n * 8, E.st);
+    dev_sync(E.st);
     return 0;
   });
 }

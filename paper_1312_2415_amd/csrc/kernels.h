@@ -4,6 +4,7 @@
 #pragma once
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 
 namespace sadmrg {
 
@@ -47,6 +48,16 @@ void dev_event_wait(void* e);  // the host waits until the stream has passed e
 Stream dev_stream_create();
 void dev_stream_destroy(Stream s);
 void dev_stream_order(Stream a, Stream b);
+
+// Static per-device workspace of the allocation-free sigma entry point.
+// scratch_init(device) must run with that device current (context creation
+// does it); scratch_ptr returns the device address it found (null before),
+// scratch_lock a host mutex that serialises the entry point's calls on that
+// device, scratch_bytes the array's size.
+void scratch_init(int device);
+void* scratch_ptr(int device);
+std::mutex* scratch_lock(int device);
+size_t scratch_bytes();
 
 // Flags of a block triple product  out += coef * opA(A) * B * opC(C)  (the
 // host evaluates it as two grouped GEMMs): transpose A / C, identity A / C.

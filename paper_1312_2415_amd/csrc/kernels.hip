@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <iterator>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <unordered_map>
 
@@ -285,6 +286,43 @@ void dev_stream_order(Stream a, Stream b) {
   hip_ok(hipStreamWaitEvent((hipStream_t)a, e, 0), "hipStreamWaitEvent");
   (void)hipEventDestroy(e);
 }
+
+// ---------------------------------------------------------------------------
+// Static device workspace of the allocation-free sigma entry point
+// (sadmrg_sigma_noalloc): one copy per device, held until the process ends.
+// In host code the array's name is not a device address: scratch_init looks
+// the address up once per device, with that device current, and every later
+// use (kernel arguments, copies, fills) goes through the address it keeps.
+// ---------------------------------------------------------------------------
+static constexpr size_t SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;
+static std::map<int, std::unique_ptr<std::mutex>> g_scratch_use;
+
+void scratch_init(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr.count(device)) return;
+  int cur = -1;
+  hip_ok(hipGetDevice(&cur), "hipGetDevice");
+  if (cur != device) dev_fail("scratch_init: the device is not current");
+  void* p = nullptr;
+  hip_ok(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+  if (!p) dev_fail("hipGetSymbolAddress(scratch) returned a null address");
+  g_scratch_ptr[device] = p;
+  g_scratch_use[device] = std::make_unique<std::mutex>();
+}
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
+std::mutex* scratch_lock(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_use.find(device);
+  return it == g_scratch_use.end() ? nullptr : it->second.get();
+}
+size_t scratch_bytes() { return SCRATCH_BYTES; }
 
 namespace {
 
