@@ -23,8 +23,10 @@
  *   - Spins are passed doubled (twoS = 2S).  Point-group irreps are integers
  *     0..order-1 whose direct product is XOR (D2h in Cotton order
  *     Ag,B1g,B2g,B3g,Au,B1u,B2u,B3u; subgroups use the low bits).
- *   - Two-electron integrals are chemist (ij|kl), dense L^4, row-major,
- *     eightfold symmetric; the paper's physics-notation V_ijkl equals (ik|jl).
+ *   - Two-electron integrals are chemist (ij|kl), dense L^4, row-major, with
+ *     the symmetry of a real two-body operator, (ij|kl) = (kl|ij) = (ji|lk)
+ *     (real orbitals add (ij|kl) = (ji|kl): eightfold); the paper's
+ *     physics-notation V_ijkl equals (ik|jl).
  *   - Every call returns a status: 0 on success, 1 = converged-with-warning
  *     (Davidson hit its iteration cap), negative on error:
  *       SADMRG_EINVAL   bad argument / shape / call order
@@ -73,9 +75,10 @@ void sadmrg_destroy(sadmrg_ctx* ctx);
  * subsequent device work of this context. */
 int sadmrg_set_stream(sadmrg_ctx* ctx, void* hip_stream);
 
-/* Set E_const, one-body h[L*L] (row-major) and two-body eri[L^4] (chemist,
- * row-major).  The eightfold symmetry and point-group selection rules are
- * checked to within sym_tol (EINTEG on failure). */
+/* Set E_const, one-body h[L*L] (row-major, symmetric) and two-body eri[L^4]
+ * (chemist, row-major).  h = h^T, (ij|kl) = (kl|ij) = (ji|lk) and the
+ * point-group selection rules are checked to within sym_tol (EINTEG on
+ * failure). */
 int sadmrg_set_integrals(sadmrg_ctx* ctx, double e_const, const double* h, const double* eri, double sym_tol);
 
 /* Target symmetry sector: N electrons, total spin twoS/2, irrep (the paper's
@@ -217,26 +220,46 @@ int sadmrg_get_energy(sadmrg_ctx* ctx, double* e_min, double* e_last, double* wd
  * *n receives the count). */
 int sadmrg_get_trace(sadmrg_ctx* ctx, double* out, int* n);
 
-/* Spin-summed reduced density matrices of the current MPS (the paper's 2DM
- * section: Gamma^A_{ij;kl} = sum_{sigma tau} <a+_{i sigma} a+_{j tau}
- * a_{l tau} a_{k sigma}>, and the 1-RDM gamma_ij = sum_sigma <a+_{i sigma}
- * a_{j sigma}>), evaluated at the current two-site centre (after a sweep,
- * a micro-iteration or an import) as the derivative of the energy with
- * respect to the integrals: the energy E = <psi|H|psi> of the normalised
- * two-site object is differentiated in reverse mode through every
+/* Spin-summed reduced density matrices of the current MPS (the paper's
+ * calc2DM, section "CheMPS2 library", the DMRG object):
+ *   Gamma^A_{ij;kl} = sum_{s t} <a+_{i s} a+_{j t} a_{l t} a_{k s}>,
+ *   gamma_ij = sum_s <a+_{i s} a_{j s}> = sum_k Gamma^A_{ik;jk} / (N - 1),
+ * evaluated at the current two-site centre (after a sweep, a micro-iteration
+ * or an import) as the derivative of E = <psi|H|psi> (normalised two-site
+ * object) with respect to the integrals, in reverse mode through every
  * complementary-operator construction and renormalisation of both blocks.
- * rdm1[L*L] (row-major, may be NULL) and rdm2[L^4] (index order i,j,k,l, may
- * be NULL) are host arrays; rdm2 is symmetrised over the eightfold index
- * permutations of the integral it multiplies, i.e. Gamma_{ij;kl} is replaced
- * by (Gamma_{ij;kl} + Gamma_{kj;il}) / 2, which is exactly what the energy
- * E = E_const + sum h_ij gamma_ij + 1/2 sum (ik|jl) Gamma_{ij;kl} and its
- * integral derivatives use.  *energy (may be NULL) receives that E.
- * Errors: EINVAL (no two-site centre), ESYMM (no target), ENOMEM. */
+ * The blocking formulas keep each creator next to its own annihilator
+ * partner in every integral they read, so the derivative is taken over
+ * integrals with only the symmetry of a real two-body operator and Gamma^A
+ * comes out whole, not symmetrised over (ik|jl) = (ki|jl).
+ * rdm1[L*L] (row-major, may be NULL) and rdm2[L^4] (Gamma^A_{ij;kl} at
+ * [i][j][k][l], may be NULL) are host arrays; *energy (may be NULL) receives
+ * E = E_const + sum h_ij gamma_ij + 1/2 sum (ik|jl) Gamma^A_{ij;kl}.  Cost:
+ * one reverse pass over the whole chain.  Errors: EINVAL (no two-site
+ * centre), ESYMM (no target), ENOMEM. */
 int sadmrg_rdm(sadmrg_ctx* ctx, double* rdm1, double* rdm2, double* energy);
 
-/* <S^2> of the current MPS.  The spin-adapted MPS with singlet embedding is an
- * exact eigenstate of S^2 (section "Symmetry-adapted DMRG"), so this is
- * S(S+1) of the target. */
+/* All calc2DM outputs from one reverse pass (same definitions as sadmrg_rdm):
+ *   gamma_a[L^4] (may be NULL): Gamma^A; layout 0 = paper order,
+ *     gamma_a[i][j][k][l] = Gamma^A_{ij;kl}; layout 1 = chemist order,
+ *     gamma_a[p][q][r][s] = Gamma^A_{pr;qs}, so that E = E_const +
+ *     sum h_pq gamma_pq + 1/2 sum (pq|rs) gamma_a[p][q][r][s];
+ *   gamma_b[L^4] (may be NULL, paper order): Gamma^B_{ij;kl} = sum_{s t}
+ *     (-1)^(s-t) <a+_{i s} a+_{j t} a_{l t} a_{k s}> averaged over the 2S+1
+ *     members of the multiplet (the singlet-embedding spin is traced out; a
+ *     singlet has one member).  For that SU(2)-invariant average the spin
+ *     structure fixes Gamma^B_{ij;kl} = -(Gamma^A_{ij;kl} + 2 Gamma^A_{ij;lk})/3;
+ *   rdm1[L*L], *s2 = <S^2> = -N(N-4)/4 - 1/2 sum_ij Gamma^A_{ij;ji} and
+ *     *energy (each may be NULL).
+ * Errors: EINVAL (bad layout, no two-site centre), ESYMM, ENOMEM. */
+int sadmrg_calc2dm(sadmrg_ctx* ctx, double* gamma_a, double* gamma_b, int layout, double* rdm1, double* s2,
+                   double* energy);
+
+/* <S^2> of the current MPS, evaluated from the state: -N(N-4)/4 - 1/2
+ * sum_ij Gamma^A_{ij;ji} with Gamma^A from one reverse pass (sadmrg_rdm).
+ * The spin-adapted MPS is an exact spin eigenstate (section "Symmetry-adapted
+ * DMRG"), so this returns S(S+1) to rounding; it checks the density matrix.
+ * Errors: as sadmrg_rdm. */
 int sadmrg_get_s2(sadmrg_ctx* ctx, double* s2);
 
 /* ------------------------------------------------------------------------

@@ -641,6 +641,9 @@ def enlarge_right(P: Problem, Y: Block, E: RightEnl) -> Block:
     couple_right(o, SITE_B[2], get_Q(Y, P, 2, k, k), E, SQ3)
     out.ops[("H",)] = o
 
+    # S_x = sum W_{p x r s} b+_p E_rs: the outside index x is the partner of
+    # the creator p, so every coefficient below keeps x in the second slot
+    # next to its partner (this matters only when (pq|rs) != (qp|rs))
     for x in comp:
         gx = int(P.orb_irrep[x])
         o = new(1, 1, gx, True)
@@ -649,13 +652,13 @@ def enlarge_right(P: Problem, Y: Block, E: RightEnl) -> Block:
         couple_right(o, SITE_CDAG, get_Q(Y, P, 2, k, x), E, math.sqrt(1.5))
         couple_right(o, SITE_C, get_P(Y, P, 0, x, k), E, 1.0 / SQ2)
         couple_right(o, SITE_C, get_P(Y, P, 2, x, k), E, math.sqrt(1.5))
-        cs = cdag_combo(Y, P, {s: W[x, k, k, s] for s in Y.orbs})
+        cs = cdag_combo(Y, P, {s: W[k, x, k, s] for s in Y.orbs})
         if cs is not None:
             couple_right(o, SITE_A0, adjoint(cs), E, 1.0 / SQ2)
-        c0 = cdag_combo(Y, P, {r: W[x, k, r, k] / SQ2 - SQ2 * W[x, r, k, k] for r in Y.orbs})
+        c0 = cdag_combo(Y, P, {r: W[k, x, r, k] / SQ2 - SQ2 * W[r, x, k, k] for r in Y.orbs})
         if c0 is not None:
             couple_right(o, SITE_B[0], c0, E, 1.0)
-        c1 = cdag_combo(Y, P, {r: W[x, k, r, k] for r in Y.orbs})
+        c1 = cdag_combo(Y, P, {r: W[k, x, r, k] for r in Y.orbs})
         if c1 is not None:
             couple_right(o, SITE_B[2], c1, E, -math.sqrt(1.5))
         couple_right(o, SITE_CDAG_E, Ik, E, W[x, k, k, k])

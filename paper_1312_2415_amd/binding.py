@@ -75,6 +75,7 @@ def load_library(path: str | None = None):
         "sadmrg_set_precision": (c_int, [c_vp, c_int, c_dbl]),
         "sadmrg_rdm": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
         "sadmrg_get_s2": (c_int, [c_vp, P(c_dbl)]),
+        "sadmrg_calc2dm": (c_int, [c_vp, P(c_dbl), P(c_dbl), c_int, P(c_dbl), P(c_dbl), P(c_dbl)]),
         "sadmrg_debug_copy_probe": (c_int, [c_vp, ctypes.c_int64, c_int, P(c_dbl)]),
         "sadmrg_last_error": (ctypes.c_char_p, [c_vp]),
         "sadmrg_debug_coupling": (c_int, [c_int, P(c_int), P(c_dbl)]),
@@ -313,6 +314,17 @@ class SaDMRG:
         e = ctypes.c_double()
         self._chk(self.lib.sadmrg_rdm(self.h, _dptr(g1), _dptr(g2) if two_body else None, ctypes.byref(e)))
         return g1, g2, e.value
+
+    def calc2dm(self, layout: int = 0):
+        """The paper's calc2DM outputs from one reverse pass:
+        (Gamma^A [L]*4 in `layout` (0 paper, 1 chemist), Gamma^B (paper order,
+        multiplet average), gamma, <S^2>, E)."""
+        L = self.L
+        ga, gb, g1 = np.zeros((L,) * 4), np.zeros((L,) * 4), np.zeros((L, L))
+        s2, e = ctypes.c_double(), ctypes.c_double()
+        self._chk(self.lib.sadmrg_calc2dm(self.h, _dptr(ga), _dptr(gb), int(layout), _dptr(g1), ctypes.byref(s2),
+                                          ctypes.byref(e)))
+        return ga, gb, g1, s2.value, e.value
 
     def s2(self) -> float:
         v = ctypes.c_double()

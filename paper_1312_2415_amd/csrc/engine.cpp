@@ -1029,16 +1029,18 @@ static std::vector<Def> defs_right(const Problem& P, Store& Y, Combos& cb) {
     add_term(d, bk.getQ(2, k, x), so.CD, s32);
     add_term(d, bk.getP(0, x, k), so.C, 1.0 / s2);
     add_term(d, bk.getP(2, x, k), so.C, s32);
+    // S_x = sum W_{p x r s} b+_p E_rs: x is the partner of the creator p, so
+    // it stays in the second slot (needed when (pq|rs) != (qp|rs))
     reset();
-    for (int s : Y.orbs) coef[s] = P.wl(x, k, k, s);
+    for (int s : Y.orbs) coef[s] = P.wl(k, x, k, s);
     add_term(d, adjoint_expr(bk.cdag(coef), Y, cb.T), so.A0, 1.0 / s2);
     reset();
-    for (int r : Y.orbs) coef[r] = P.wl(x, k, r, k) * (1.0 / s2) + P.wl(x, r, k, k) * -s2;
+    for (int r : Y.orbs) coef[r] = P.wl(k, x, r, k) * (1.0 / s2) + P.wl(r, x, k, k) * -s2;
     add_term(d, bk.cdag(coef), so.B0, 1.0);
     reset();
-    for (int r : Y.orbs) coef[r] = P.wl(x, k, r, k);
+    for (int r : Y.orbs) coef[r] = P.wl(k, x, r, k);
     add_term(d, bk.cdag(coef), so.B1, -s32);
-    add_term_w(d, IDX, so.CDE, P.wl(x, k, k, k));
+    add_term_w(d, IDX, so.CDE, P.wl(k, x, k, k));
     defs.push_back(d);
   }
   std::vector<int> orbs;
@@ -2281,34 +2283,60 @@ struct Engine {
     return e;
   }
 
-  // Spin-summed 1-RDM gamma_pq = <E_pq> and 2-RDM Gamma_{ij;kl} =
-  // sum_{st} <a+_is a+_jt a_lt a_ks> (symmetrised over the eightfold
-  // permutations of the integral it multiplies) from d E / d W.
-  double rdms(double* rdm1, double* rdm2) {
+  // The paper's calc2DM outputs from d E / d W (section "CheMPS2 library",
+  // the DMRG object): gamma_pq = <E_pq>, Gamma^A_{ij;kl} = sum_{st}
+  // <a+_is a+_jt a_lt a_ks> and Gamma^B_{ij;kl} = sum_{st} (-1)^(s-t) (same).
+  // E is linear in the folded integrals W_pqrs = (pq|rs) + (h_pq d_rs + h_rs
+  // d_pq)/(N-1), and every blocking formula reads W with each creator next to
+  // its own annihilator partner, so the derivative holds for any W with the
+  // symmetry of a real two-body operator, (pq|rs) = (rs|pq) = (qp|sr); its
+  // average over those four images is D_pqrs = Gamma^A_{pr;qs} / 2, with no
+  // symmetrisation over (pq|rs) = (qp|rs).  Gamma^B is the average over the
+  // 2S+1 members of the multiplet (the singlet-embedding ghost is traced
+  // out): for an SU(2)-invariant two-body density the spin structure leaves
+  // Gamma^B_{ij;kl} = -(Gamma^A_{ij;kl} + 2 Gamma^A_{ij;lk}) / 3.
+  // layout 0: rdm2[i][j][k][l] = Gamma^A_{ij;kl}; layout 1 (chemist):
+  // rdm2[p][q][r][s] = Gamma^A_{pr;qs}, so E = E_c + sum h gamma + 1/2 sum
+  // (pq|rs) rdm2_pqrs.  <S^2> = -N(N-4)/4 - 1/2 sum_ij Gamma^A_{ij;ji}.
+  double rdms(double* rdm1, double* rdm2, int layout = 0, double* rdm2b = nullptr, double* s2 = nullptr) {
     std::vector<double> G;
     const double e = energy_gradient(G);
     const int L = P.L;
     auto ix = [L](int p, int q, int r, int s) { return (((size_t)p * L + q) * L + r) * L + s; };
-    std::vector<double> D((size_t)L * L * L * L);
+    std::vector<double> GA((size_t)L * L * L * L);  // Gamma^A_{pr;qs} at [p][r][q][s]
     for (int p = 0; p < L; ++p)
       for (int q = 0; q < L; ++q)
         for (int r = 0; r < L; ++r)
           for (int s = 0; s < L; ++s)
-            D[ix(p, q, r, s)] = (G[ix(p, q, r, s)] + G[ix(q, p, r, s)] + G[ix(p, q, s, r)] + G[ix(q, p, s, r)] +
-                                 G[ix(r, s, p, q)] + G[ix(s, r, p, q)] + G[ix(r, s, q, p)] + G[ix(s, r, q, p)]) /
-                                8.0;
-    if (rdm2)
-      for (int p = 0; p < L; ++p)
-        for (int q = 0; q < L; ++q)
-          for (int r = 0; r < L; ++r)
-            for (int s = 0; s < L; ++s) rdm2[ix(p, r, q, s)] = 2.0 * D[ix(p, q, r, s)];
-    if (rdm1)
+            GA[ix(p, r, q, s)] =
+                (G[ix(p, q, r, s)] + G[ix(r, s, p, q)] + G[ix(q, p, s, r)] + G[ix(s, r, q, p)]) / 2.0;
+    if (rdm2) {
+      if (layout == 0)
+        std::copy(GA.begin(), GA.end(), rdm2);
+      else
+        for (int p = 0; p < L; ++p)
+          for (int q = 0; q < L; ++q)
+            for (int r = 0; r < L; ++r)
+              for (int s = 0; s < L; ++s) rdm2[ix(p, q, r, s)] = GA[ix(p, r, q, s)];
+    }
+    if (rdm2b)
+      for (int i = 0; i < L; ++i)
+        for (int j = 0; j < L; ++j)
+          for (int k = 0; k < L; ++k)
+            for (int l = 0; l < L; ++l) rdm2b[ix(i, j, k, l)] = -(GA[ix(i, j, k, l)] + 2.0 * GA[ix(i, j, l, k)]) / 3.0;
+    if (rdm1)  // gamma_ik = sum_j Gamma^A_{ij;kj} / (N - 1)
       for (int p = 0; p < L; ++p)
         for (int q = 0; q < L; ++q) {
           double v = 0.0;
-          for (int r = 0; r < L; ++r) v += D[ix(p, q, r, r)];
-          rdm1[p * L + q] = 2.0 * v / (P.N - 1);
+          for (int j = 0; j < L; ++j) v += GA[ix(p, j, q, j)];
+          rdm1[p * L + q] = v / (P.N - 1);
         }
+    if (s2) {
+      double t = 0.0;
+      for (int i = 0; i < L; ++i)
+        for (int j = 0; j < L; ++j) t += GA[ix(i, j, j, i)];
+      *s2 = -0.25 * P.N * (P.N - 4) - 0.5 * t;
+    }
     return e + P.e_const;
   }
 
@@ -4345,9 +4373,8 @@ int sadmrg_set_integrals(sadmrg_ctx* ctx, double e_const, const double* h, const
         for (int r = 0; r < L; ++r)
           for (int s = 0; s < L; ++s) {
             const double v = E4(p, q, r, s);
-            if (std::abs(v - E4(q, p, r, s)) > sym_tol || std::abs(v - E4(p, q, s, r)) > sym_tol ||
-                std::abs(v - E4(r, s, p, q)) > sym_tol)
-              sadmrg::fail(SADMRG_EINTEG, "eri lacks eightfold symmetry");
+            if (std::abs(v - E4(r, s, p, q)) > sym_tol || std::abs(v - E4(q, p, s, r)) > sym_tol)
+              sadmrg::fail(SADMRG_EINTEG, "eri lacks the symmetry (pq|rs) = (rs|pq) = (qp|sr)");
             if ((P.orb[p] ^ P.orb[q] ^ P.orb[r] ^ P.orb[s]) != 0 && std::abs(v) > sym_tol)
               sadmrg::fail(SADMRG_EINTEG, "eri breaks the point-group symmetry");
           }
@@ -4827,12 +4854,23 @@ int sadmrg_rdm(sadmrg_ctx* ctx, double* rdm1, double* rdm2, double* energy) {
   });
 }
 
+int sadmrg_calc2dm(sadmrg_ctx* ctx, double* gamma_a, double* gamma_b, int layout, double* rdm1, double* s2,
+                   double* energy) {
+  return guard(ctx, [&] {
+    auto& E = ctx->e;
+    if (layout != 0 && layout != 1) sadmrg::fail(SADMRG_EINVAL, "layout must be 0 (paper) or 1 (chemist)");
+    if (E.P.N < 2) sadmrg::fail(SADMRG_ESYMM, "no target");
+    const double e = E.rdms(rdm1, gamma_a, layout, gamma_b, s2);
+    if (energy) *energy = e;
+    return 0;
+  });
+}
+
 int sadmrg_get_s2(sadmrg_ctx* ctx, double* s2) {
   return guard(ctx, [&] {
     if (!s2) sadmrg::fail(SADMRG_EINVAL, "null output");
-    if (ctx->e.P.N < 0) sadmrg::fail(SADMRG_ESYMM, "no target");
-    const double S = 0.5 * ctx->e.P.twoS;
-    *s2 = S * (S + 1.0);
+    if (ctx->e.P.N < 2) sadmrg::fail(SADMRG_ESYMM, "no target");
+    ctx->e.rdms(nullptr, nullptr, 0, nullptr, s2);
     return 0;
   });
 }

@@ -15,7 +15,7 @@ import pytest
 
 from oracle import sadmrg as sd
 from oracle.explicit import Expansion, Fock, rdms_of_state, state_vector
-from synth.integrals import make_integrals
+from synth.integrals import fourfold_eri, make_integrals
 
 pytestmark = pytest.mark.gpu
 
@@ -26,8 +26,10 @@ CASES = [(4, 4, 2, "C1", 0, 16), (5, 5, 1, "C2v", 1, 16), (6, 6, 0, "C1", 0, 6),
          (6, 6, 4, "D2h", 0, 10), (6, 7, 1, "C2v", 3, 7)]
 
 
-def _setup(L, N, twoS, group, irrep, D, seed=11):
+def _setup(L, N, twoS, group, irrep, D, seed=11, four=False):
     I = make_integrals(L, group, seed)
+    if four:  # only (pq|rs) = (rs|pq) = (qp|sr): probes each formula's integral orientation
+        I.eri = fourfold_eri(I, seed + 100)
     P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
     dm = sd.DMRG(P, D, seed=3)
     dm.build_boundaries()
@@ -42,9 +44,10 @@ def _gpu(L, group, I, N, twoS, irrep):
     return g
 
 
+@pytest.mark.parametrize("four", [False, True])
 @pytest.mark.parametrize("case", CASES)
-def test_gpu_sigma_equals_projected_hamiltonian(case):
-    I, P, dm = _setup(*case)
+def test_gpu_sigma_equals_projected_hamiltonian(case, four):
+    I, P, dm = _setup(*case, four=four)
     L, N, twoS, group, irrep, D = case
     F = Fock(L)
     H = F.hamiltonian(I.h, I.eri)
@@ -82,16 +85,20 @@ def test_gpu_rdms_equal_explicit_rdms_of_a_truncated_mps(case):
         dm.sweep(D)
     F = Fock(L)
     Psi = state_vector(Expansion(dm, F), dm)
-    g1, GA, GB, s2 = rdms_of_state(F, Psi)
-    e_ref = float(np.sum(Psi * (F.hamiltonian(I.h, I.eri) @ Psi)))
+    g1, GA, GB, s2_ref = rdms_of_state(F, Psi)
+    # <Psi|H|Psi> through the explicit RDMs (the identity is pinned on the CPU
+    # against the explicit Hamiltonian, which is slow to build at L = 8)
+    e_ref = I.e_const + np.einsum("ij,ij->", I.h, g1) + 0.5 * np.einsum("ijkl,ikjl->", GA, I.eri)
+    print(f"case {case}: explicit RDMs done", flush=True)
     g = _gpu(L, group, I, N, twoS, irrep)
     g.mps_import(sd.export_blob(dm))
-    r1, r2, e = g.rdm()
+    ga, gb, r1, s2, e = g.calc2dm()
     g.close()
     assert abs(e - e_ref) < 1e-10
     assert np.abs(r1 - g1).max() < 1e-10
-    sym = 0.5 * (GA + GA.transpose(2, 1, 0, 3))  # the energy-symmetrised Gamma^A
-    assert np.abs(r2 - sym).max() < 1e-10
+    assert np.abs(ga - GA).max() < 1e-10
+    assert np.abs(gb - GB).max() < 1e-10
+    assert abs(s2 - s2_ref) < 1e-10
 
 
 @pytest.mark.parametrize("case", [(6, 6, 0, "C1", 0), (6, 5, 1, "C2v", 1), (7, 8, 2, "D2h", 0)])

@@ -1,16 +1,18 @@
 """GPU RDMs: spin-summed 1- and 2-RDMs from the energy adjoint.
 
-Pinned by brute-force FCI where the bond dimension is complete, by central
-finite differences of the energy with respect to integral orbits on a
-truncated MPS, by the energy identity E = E_c + h.gamma + 1/2 (ik|jl) Gamma_ijkl,
+Pinned by brute-force FCI where the bond dimension is complete (gamma, the
+whole Gamma^A, the multiplet-averaged Gamma^B and <S^2>), by central finite
+differences of the energy with respect to integral orbits on a truncated MPS
+(eightfold orbits, and four-fold ones that see the part of Gamma^A odd under
+i <-> k), by the energy identity E = E_c + h.gamma + 1/2 (ik|jl) Gamma_ijkl,
 and by the partial-trace relation between gamma and Gamma.
 """
 import numpy as np
 import pytest
 
 from oracle import sadmrg as sd
-from oracle.fci import fci_solve, rdms, s2_from_gamma
-from synth.integrals import make_integrals
+from oracle.fci import fci_solve, rdm_b_multiplet, rdms, s2_from_gamma
+from synth.integrals import fourfold_eri, make_integrals
 
 pytestmark = pytest.mark.gpu
 
@@ -22,14 +24,6 @@ def _gpu(L, group, I, h=None, eri=None):
     g = SaDMRG(L, ORDER[group], I.orb_irrep, device=0)
     g.set_integrals(I.h if h is None else h, I.eri if eri is None else eri)
     return g
-
-
-def sym8(G):
-    """Gamma_{ij;kl} multiplies (ik|jl): average it over the eightfold images of (ik|jl)."""
-    D = np.einsum("ijkl->ikjl", G)
-    S = (D + D.transpose(1, 0, 2, 3) + D.transpose(0, 1, 3, 2) + D.transpose(1, 0, 3, 2) + D.transpose(2, 3, 0, 1)
-         + D.transpose(3, 2, 0, 1) + D.transpose(2, 3, 1, 0) + D.transpose(3, 2, 1, 0)) / 8.0
-    return np.einsum("pqrs->prqs", S)
 
 
 @pytest.mark.parametrize("case", [(6, 6, 0, "C1", 64), (8, 8, 0, "D2h", 128), (7, 5, 1, "C2v", 64),
@@ -49,8 +43,15 @@ def test_rdms_match_fci_at_complete_bond_dimension(case):
     fg1, fg2 = rdms(f, vecs[:, 0])
     assert abs(e - vals[0]) <= 1e-8
     assert np.abs(g1 - fg1).max() <= 1e-8
-    assert np.abs(g2 - sym8(fg2)).max() <= 1e-8
+    assert np.abs(g2 - fg2).max() <= 1e-8  # the whole Gamma^A, not a symmetrised part
     assert abs(g.s2() - s2_from_gamma(fg2, N)) <= 1e-8
+    assert abs(g.s2() - 0.25 * twoS * (twoS + 2)) <= 1e-8
+    ga, gb, c1, s2, e2 = g.calc2dm(layout=0)
+    assert np.abs(ga - fg2).max() <= 1e-8 and np.abs(c1 - fg1).max() <= 1e-8 and abs(e2 - e) <= 1e-10
+    assert np.abs(gb - rdm_b_multiplet(f, vecs[:, 0])).max() <= 1e-8
+    assert abs(s2 - 0.25 * twoS * (twoS + 2)) <= 1e-8
+    gc = g.calc2dm(layout=1)[0]  # chemist: gc[p][q][r][s] = Gamma^A_{pr;qs}
+    assert np.abs(gc - np.einsum("prqs->pqrs", fg2)).max() <= 1e-8
     g.close()
 
 
@@ -103,6 +104,15 @@ def test_rdm_is_the_integral_derivative_of_the_energy():
         dE = np.zeros_like(I.eri)
         for a, b, c, d in {(p, q, r, s), (q, p, r, s), (p, q, s, r), (q, p, s, r), (r, s, p, q), (s, r, p, q),
                            (r, s, q, p), (s, r, q, p)}:
+            dE[a, b, c, d] = 1.0
+        fd = (energy(I.h, I.eri + eps * dE) - energy(I.h, I.eri - eps * dE)) / (2 * eps)
+        an = 0.5 * np.einsum("ikjl,ijkl", dE, g2)
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+    for _ in range(6):  # four-fold orbits: (pq|rs) = (rs|pq) = (qp|sr) only, so the
+        # quotient sees the whole Gamma^A (including its part odd under i <-> k)
+        p, q, r, s = rng.integers(0, L, 4)
+        dE = np.zeros_like(I.eri)
+        for a, b, c, d in {(p, q, r, s), (r, s, p, q), (q, p, s, r), (s, r, q, p)}:
             dE[a, b, c, d] = 1.0
         fd = (energy(I.h, I.eri + eps * dE) - energy(I.h, I.eri - eps * dE)) / (2 * eps)
         an = 0.5 * np.einsum("ikjl,ijkl", dE, g2)
