@@ -71,6 +71,24 @@ int sadmrg_create(sadmrg_ctx** out, int L, int group_order, const int* orb_irrep
 /* Destroy a context and release all its device memory.  NULL is allowed. */
 void sadmrg_destroy(sadmrg_ctx* ctx);
 
+/* Device-memory hooks (for instance a framework's caching allocator).
+ * alloc_fn(bytes, device, user) returns a device block of at least `bytes`
+ * on `device`, or NULL when it cannot (the call then fails with ENOMEM after
+ * the library has given back the blocks it keeps cached); free_fn(ptr,
+ * bytes, device, user) takes back a block alloc_fn returned, with the same
+ * size.  Every device allocation of the context goes through them (the
+ * context caches freed blocks and hands them out again; the cache is
+ * returned through free_fn when memory runs short and at sadmrg_destroy).
+ * Blocks are used on the context's stream.  The callbacks may be called from
+ * host threads the library starts inside a call, so they must be
+ * thread-safe; they must not call back into the library.  Set them right
+ * after sadmrg_create, before the context allocates (EINVAL otherwise); NULL,
+ * NULL returns to hipMalloc / hipFree.  Errors: EINVAL (one callback without
+ * the other, or device memory already held). */
+typedef void* (*sadmrg_alloc_fn)(size_t bytes, int device, void* user);
+typedef void (*sadmrg_free_fn)(void* ptr, size_t bytes, int device, void* user);
+int sadmrg_set_allocator(sadmrg_ctx* ctx, sadmrg_alloc_fn alloc_fn, sadmrg_free_fn free_fn, void* user);
+
 /* Use `hip_stream` (a hipStream_t, may be NULL for the default stream) for all
  * subsequent device work of this context. */
 int sadmrg_set_stream(sadmrg_ctx* ctx, void* hip_stream);
@@ -211,6 +229,24 @@ int sadmrg_set_enlarge_cache(sadmrg_ctx* ctx, int on);
  * EINVAL. */
 int sadmrg_solve(sadmrg_ctx* ctx, int n, const int* D, const double* e_conv, const int* max_sweeps,
                  const double* noise, double* e_min);
+
+/* Discarded-weight extrapolation (section "Extrapolation"): the energies of
+ * a run with several D lie on E(D) = E0 + C1 w_disc(D) for small discarded
+ * weights.  n pairs (w[i] >= 0, e[i]) give the least-squares line; a pair
+ * with w = 0 is an exact energy at its D and is returned as E0 (the lowest of
+ * them) with C1 = 0; a single truncated pair gives its energy and C1 = 0.
+ * Host arithmetic only.  Errors: EINVAL (n < 1, null pointers, negative or
+ * non-finite values). */
+int sadmrg_extrapolate(int n, const double* w, const double* e, double* e0, double* c1);
+
+/* A convergence scheme run stage by stage (each stage as sadmrg_solve with
+ * one instruction), then the extrapolation above: E(D) of a stage is the
+ * lowest energy of its last macro-iteration and w(D) that macro-iteration's
+ * largest discarded weight.  points[3n] (may be NULL) receives (D, w, E) per
+ * stage; *e0, *c1 (may be NULL) the fit.  Returns 1 if some Davidson solve
+ * hit its iteration cap.  Errors: as sadmrg_solve. */
+int sadmrg_solve_extrapolated(sadmrg_ctx* ctx, int n, const int* D, const double* e_conv, const int* max_sweeps,
+                              const double* noise, double* points, double* e0, double* c1);
 
 /* Energies: lowest over all micro-iterations so far, last micro-iteration's,
  * and the largest discarded weight of the last macro-iteration. */

@@ -39,6 +39,7 @@ def load_library(path: str | None = None):
         "sadmrg_create": (c_int, [P(c_vp), c_int, c_int, P(c_int), c_int]),
         "sadmrg_destroy": (None, [c_vp]),
         "sadmrg_set_stream": (c_int, [c_vp, c_vp]),
+        "sadmrg_set_allocator": (c_int, [c_vp, c_vp, c_vp, c_vp]),
         "sadmrg_set_integrals": (c_int, [c_vp, c_dbl, P(c_dbl), P(c_dbl), c_dbl]),
         "sadmrg_set_target": (c_int, [c_vp, c_int, c_int, c_int]),
         "sadmrg_set_davidson": (c_int, [c_vp, c_dbl, c_int, c_int]),
@@ -48,6 +49,9 @@ def load_library(path: str | None = None):
         "sadmrg_batch_sweep": (c_int, [P(c_vp), c_int, P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_solve": (c_int, [c_vp, c_int, P(c_int), P(c_dbl), P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_get_energy": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
+        "sadmrg_extrapolate": (c_int, [c_int, P(c_dbl), P(c_dbl), P(c_dbl), P(c_dbl)]),
+        "sadmrg_solve_extrapolated": (c_int, [c_vp, c_int, P(c_int), P(c_dbl), P(c_int), P(c_dbl), P(c_dbl),
+                                              P(c_dbl), P(c_dbl)]),
         "sadmrg_get_trace": (c_int, [c_vp, P(c_dbl), P(c_int)]),
         "sadmrg_mps_import": (c_int, [c_vp, c_vp, c_sz]),
         "sadmrg_mps_export": (c_int, [c_vp, c_vp, P(c_sz)]),
@@ -129,6 +133,36 @@ class SaDMRG:
         return rc
 
     # ---- problem definition
+    ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p)
+    FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p)
+
+    def set_allocator(self, alloc, free):
+        """sadmrg_set_allocator with Python callables alloc(bytes, device) -> int
+        pointer (0 on failure) and free(ptr, bytes, device); None, None restores
+        hipMalloc.  The callables are kept alive with the solver."""
+        if alloc is None and free is None:
+            self._hooks = None
+            self._chk(self.lib.sadmrg_set_allocator(self.h, None, None, None))
+            return
+        a = self.ALLOC_FN(lambda n, dev, user: int(alloc(int(n), int(dev))) or None)
+        f = self.FREE_FN(lambda p, n, dev, user: free(int(p), int(n), int(dev)))
+        self._chk(self.lib.sadmrg_set_allocator(self.h, ctypes.cast(a, ctypes.c_void_p),
+                                                ctypes.cast(f, ctypes.c_void_p), None))
+        self._hooks = (a, f)
+
+    def use_torch_allocator(self):
+        """Route the context's device memory through torch's caching allocator
+        (torch.cuda.caching_allocator_alloc / _delete on the current stream)."""
+        import torch
+
+        def alloc(n, dev):
+            try:
+                return torch.cuda.caching_allocator_alloc(n, device=dev)
+            except RuntimeError:
+                return 0
+
+        self.set_allocator(alloc, lambda p, n, dev: torch.cuda.caching_allocator_delete(p))
+
     def set_stream(self, stream_handle: int):
         self._chk(self.lib.sadmrg_set_stream(self.h, ctypes.c_void_p(int(stream_handle))))
 
@@ -170,19 +204,19 @@ class SaDMRG:
 
     def solve_extrapolated(self, schedule):
         """The convergence scheme stage by stage with the discarded-weight
-        extrapolation of section "Extrapolation" (eq. extrapolSchemeEq: E(D) =
-        E_exact + C1 w_disc(D)): after each stage, E(D) is the lowest energy of
-        its last sweep and w_disc(D) the largest discarded weight of that sweep.
-        Returns (E0, C1, [(D, w_disc, E(D))]), E0 and C1 from the least-squares
-        line through the stages that truncated (w_disc > 0)."""
-        n_sweep = 2 * (self.L - 1)
-        points = []
-        for stage in schedule:
-            self.solve([stage])
-            w = self.energy()[2]
-            points.append((int(stage[0]), w, float(np.min(self.trace()[-n_sweep:]))))
-        e0, c1 = fit_discarded_weight([(w, e) for _, w, e in points])
-        return e0, c1, points
+        extrapolation (sadmrg_solve_extrapolated).  Returns (E0, C1,
+        [(D, w_disc, E(D))])."""
+        n = len(schedule)
+        D = (ctypes.c_int * n)(*[int(s[0]) for s in schedule])
+        ec = (ctypes.c_double * n)(*[float(s[1]) for s in schedule])
+        ms = (ctypes.c_int * n)(*[int(s[2]) for s in schedule])
+        nz = (ctypes.c_double * n)(*[float(s[3]) if len(s) > 3 else 0.0 for s in schedule])
+        pts = (ctypes.c_double * (3 * n))()
+        e0, c1 = ctypes.c_double(), ctypes.c_double()
+        self._chk(self.lib.sadmrg_solve_extrapolated(self.h, n, D, ec, ms, nz, pts, ctypes.byref(e0),
+                                                     ctypes.byref(c1)))
+        points = [(int(pts[3 * i]), pts[3 * i + 1], pts[3 * i + 2]) for i in range(n)]
+        return e0.value, c1.value, points
 
     def energy(self):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
@@ -364,24 +398,21 @@ class SaDMRG:
         self._chk(self.lib.sadmrg_stats_reset(self.h))
 
 
-def fit_discarded_weight(points):
-    """Least-squares line E = E0 + C1 w through (w_disc, E) pairs (section
-    "Extrapolation", eq. extrapolSchemeEq).  Pairs with w_disc = 0 are exact
-    energies at their D: if there is one, E0 is the lowest of them and C1 = 0;
-    a single truncated pair gives C1 = 0 and E0 = its energy.  Returns (E0, C1)."""
+def fit_discarded_weight(points, lib_path: str | None = None):
+    """E0, C1 of the line E = E0 + C1 w through (w_disc, E) pairs
+    (sadmrg_extrapolate: section "Extrapolation")."""
     pts = [(float(w), float(e)) for w, e in points]
     if not pts:
         raise ValueError("no (w_disc, E) pairs")
-    exact = [e for w, e in pts if w <= 0.0]
-    if exact:
-        return min(exact), 0.0
-    if len(pts) == 1:
-        return pts[0][1], 0.0
-    w = np.array([p[0] for p in pts])
-    e = np.array([p[1] for p in pts])
-    A = np.stack([np.ones_like(w), w], axis=1)
-    (e0, c1), *_ = np.linalg.lstsq(A, e, rcond=None)
-    return float(e0), float(c1)
+    lib = load_library(lib_path)
+    n = len(pts)
+    w = (ctypes.c_double * n)(*[p[0] for p in pts])
+    e = (ctypes.c_double * n)(*[p[1] for p in pts])
+    e0, c1 = ctypes.c_double(), ctypes.c_double()
+    rc = lib.sadmrg_extrapolate(n, w, e, ctypes.byref(e0), ctypes.byref(c1))
+    if rc != 0:
+        raise SadmrgError(rc, "bad (w, E) pairs")
+    return e0.value, c1.value
 
 
 def device_memory(device: int = 0, lib_path: str | None = None):

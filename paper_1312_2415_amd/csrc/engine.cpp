@@ -35,6 +35,7 @@ namespace sadmrg {
 
 void fail(int code, const std::string& msg) { throw Failure{code, msg}; }
 [[noreturn]] void dev_fail(const char* what) { throw Failure{-5, what}; }
+[[noreturn]] void dev_fail_nomem(const char* what) { throw Failure{-4, what}; }
 
 int Basis::find(const Sec& s) const {
   auto it = std::lower_bound(sec.begin(), sec.end(), s);
@@ -4251,6 +4252,50 @@ static void export_mps(Engine& E, std::vector<char>& out) {
   putT(E.cen.t);
 }
 
+// Discarded-weight extrapolation (section "Extrapolation"): the least-squares
+// line E = E0 + C1 w through the (w, E) pairs with w > 0; a pair with w = 0 is
+// an exact energy at its D and is returned as E0 (the lowest of them); one
+// truncated pair carries no slope.
+static void fit_line(int n, const double* w, const double* e, double* e0, double* c1) {
+  double best_exact = INFINITY;
+  int nt = 0;
+  double sw = 0.0, se = 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (!std::isfinite(w[i]) || !std::isfinite(e[i]) || w[i] < 0.0) fail(-1, "bad (w, E) pair");
+    if (w[i] == 0.0) {
+      best_exact = std::min(best_exact, e[i]);
+    } else {
+      ++nt;
+      sw += w[i];
+      se += e[i];
+    }
+  }
+  if (std::isfinite(best_exact)) {
+    *e0 = best_exact;
+    *c1 = 0.0;
+    return;
+  }
+  if (nt == 1) {
+    *e0 = se;
+    *c1 = 0.0;
+    return;
+  }
+  // centred normal equations of the two-parameter fit
+  const double mw = sw / nt, me = se / nt;
+  double sxx = 0.0, sxy = 0.0;
+  for (int i = 0; i < n; ++i) {
+    sxx += (w[i] - mw) * (w[i] - mw);
+    sxy += (w[i] - mw) * (e[i] - me);
+  }
+  if (!(sxx > 0.0)) {  // all weights equal: no slope can be fitted
+    *e0 = me;
+    *c1 = 0.0;
+    return;
+  }
+  *c1 = sxy / sxx;
+  *e0 = me - *c1 * mw;
+}
+
 }  // namespace sadmrg
 
 // ---------------------------------------------------------------------------
@@ -4340,6 +4385,16 @@ void sadmrg_destroy(sadmrg_ctx* ctx) {
     delete ctx;  // device blocks return to the pool
   }
   sadmrg::dev_pool_destroy(pool);
+}
+
+int sadmrg_set_allocator(sadmrg_ctx* ctx, sadmrg_alloc_fn alloc_fn, sadmrg_free_fn free_fn, void* user) {
+  return guard(ctx, [&] {
+    if ((alloc_fn == nullptr) != (free_fn == nullptr)) sadmrg::fail(SADMRG_EINVAL, "give both callbacks or neither");
+    sadmrg::dev_sync(ctx->e.st);
+    if (!sadmrg::dev_pool_set_allocator(ctx->pool, alloc_fn, free_fn, user, ctx->e.device))
+      sadmrg::fail(SADMRG_EINVAL, "the context already holds device memory: set the allocator right after creation");
+    return 0;
+  });
 }
 
 int sadmrg_set_stream(sadmrg_ctx* ctx, void* hip_stream) {
@@ -4530,6 +4585,50 @@ int sadmrg_solve(sadmrg_ctx* ctx, int n, const int* D, const double* e_conv, con
     }
     if (e_min) *e_min = E.emin;
     return E.warned ? SADMRG_WARN_NOT_CONVERGED : 0;
+  });
+}
+
+int sadmrg_extrapolate(int n, const double* w, const double* e, double* e0, double* c1) {
+  if (n < 1 || !w || !e || !e0 || !c1) return SADMRG_EINVAL;
+  try {
+    sadmrg::fit_line(n, w, e, e0, c1);
+  } catch (const sadmrg::Failure& f) {
+    return f.code;
+  }
+  return 0;
+}
+
+int sadmrg_solve_extrapolated(sadmrg_ctx* ctx, int n, const int* D, const double* e_conv, const int* max_sweeps,
+                              const double* noise, double* points, double* e0, double* c1) {
+  return guard(ctx, [&] {
+    if (n < 1 || !D || !e_conv || !max_sweeps) sadmrg::fail(SADMRG_EINVAL, "bad schedule");
+    auto& E = ctx->e;
+    std::vector<double> ws(n), es(n);
+    int warn = 0;
+    for (int i = 0; i < n; ++i) {
+      const double nz = noise ? noise[i] : 0.0;
+      const int rc = sadmrg_solve(ctx, 1, D + i, e_conv + i, max_sweeps + i, &nz, nullptr);
+      if (rc < 0) throw sadmrg::Failure{rc, ctx->err};
+      if (rc > 0) warn = rc;
+      // E(D): lowest energy of the stage's last macro-iteration; w(D): its
+      // largest discarded weight
+      const size_t per = 2 * (size_t)(E.P.L - 1);
+      const size_t nt = E.trace.size();
+      double lo = INFINITY;
+      for (size_t k = nt > per ? nt - per : 0; k < nt; ++k) lo = std::min(lo, E.trace[k]);
+      ws[i] = E.wdisc;
+      es[i] = lo;
+      if (points) {
+        points[3 * i] = D[i];
+        points[3 * i + 1] = ws[i];
+        points[3 * i + 2] = es[i];
+      }
+    }
+    double a = 0.0, b = 0.0;
+    sadmrg::fit_line(n, ws.data(), es.data(), &a, &b);
+    if (e0) *e0 = a;
+    if (c1) *c1 = b;
+    return warn;
   });
 }
 

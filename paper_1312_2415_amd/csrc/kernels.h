@@ -18,6 +18,12 @@ void dev_free(void* p);
 // Per-context cache of device blocks (see kernels.hip); bind returns the
 // previously bound pool.  Destroy only after the context's stream is idle.
 struct DevPool;
+// Caller-supplied allocator of a pool: alloc returns a device block of at
+// least `bytes` on `device` (null on failure), free returns one.
+using DevAllocFn = void* (*)(size_t bytes, int device, void* user);
+using DevFreeFn = void (*)(void* ptr, size_t bytes, int device, void* user);
+// false if the pool already owns blocks (they came from the other allocator)
+bool dev_pool_set_allocator(DevPool* pool, DevAllocFn a, DevFreeFn f, void* user, int device);
 DevPool* dev_pool_create();
 void dev_pool_destroy(DevPool* pool);
 DevPool* dev_pool_bind(DevPool* pool);

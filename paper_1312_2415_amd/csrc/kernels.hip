@@ -21,7 +21,8 @@
 
 namespace sadmrg {
 
-[[noreturn]] void dev_fail(const char* what);  // defined by the engine (throws)
+[[noreturn]] void dev_fail(const char* what);        // defined by the engine (throws)
+[[noreturn]] void dev_fail_nomem(const char* what);  // same, as an out-of-memory error
 
 static void hip_ok(hipError_t e, const char* what) {
   if (e != hipSuccess) {
@@ -46,7 +47,28 @@ struct DevPool {
   std::unordered_map<void*, size_t> owned;  // every block of this pool -> size class
   size_t cached_bytes = 0;
   std::mutex mu;  // host threads of one context may share the pool
+  // caller-supplied allocator (null: hipMalloc / hipFree)
+  DevAllocFn alloc_fn = nullptr;
+  DevFreeFn free_fn = nullptr;
+  void* user = nullptr;
+  int device = 0;
 };
+// a new block for `pool` (its allocator, else hipMalloc); null on failure
+static void* pool_raw_alloc(DevPool* pool, size_t bytes) {
+  if (pool && pool->alloc_fn) return pool->alloc_fn(bytes, pool->device, pool->user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+static void pool_raw_free(DevPool* pool, void* p, size_t bytes) {
+  if (pool && pool->free_fn)
+    pool->free_fn(p, bytes, pool->device, pool->user);
+  else
+    (void)hipFree(p);
+}
 static thread_local DevPool* tl_pool = nullptr;
 static constexpr size_t POOL_CACHE_MAX = (size_t)96 << 30;
 // Every live pool, so that an allocation that fails in one context can take
@@ -67,8 +89,18 @@ void dev_pool_destroy(DevPool* pool) {
     std::lock_guard<std::mutex> lk(g_pools_mu);
     g_pools.erase(std::remove(g_pools.begin(), g_pools.end(), pool), g_pools.end());
   }
-  for (auto& [p, sz] : pool->owned) (void)hipFree(p);
+  for (auto& [p, sz] : pool->owned) pool_raw_free(pool, p, sz);
   delete pool;
+}
+bool dev_pool_set_allocator(DevPool* pool, DevAllocFn a, DevFreeFn f, void* user, int device) {
+  if (!pool) return false;
+  std::lock_guard<std::mutex> lk(pool->mu);
+  if (!pool->owned.empty()) return false;  // blocks of the previous allocator are live
+  pool->alloc_fn = a;
+  pool->free_fn = f;
+  pool->user = user;
+  pool->device = device;
+  return true;
 }
 DevPool* dev_pool_bind(DevPool* pool) {
   DevPool* prev = tl_pool;
@@ -92,7 +124,7 @@ static void pool_trim(DevPool* pool, size_t keep) {
     auto it = std::prev(pool->cached.end());  // largest first
     pool->cached_bytes -= it->first;
     pool->owned.erase(it->second);
-    (void)hipFree(it->second);
+    pool_raw_free(pool, it->second, it->first);
     pool->cached.erase(it);
   }
 }
@@ -147,26 +179,20 @@ void* dev_alloc(size_t bytes) {
       if (lk.owns_lock()) lk.unlock();
       trim_other_pools(pool);
       if (pool) lk.lock();
-      if (!dev_room(bytes)) dev_fail("hipMalloc: out of device memory (the runtime's reserve is reached)");
+      if (!dev_room(bytes)) dev_fail_nomem("out of device memory (the runtime's reserve is reached)");
     }
   }
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess && pool && pool->cached_bytes) {  // give the cache back and retry
-    (void)hipGetLastError();
+  void* p = pool_raw_alloc(pool, bytes);
+  if (!p && pool && pool->cached_bytes) {  // give the cache back and retry
     pool_trim(pool, 0);
-    e = hipMalloc(&p, bytes);
+    p = pool_raw_alloc(pool, bytes);
   }
-  if (e != hipSuccess) {  // then the caches of the other contexts
-    (void)hipGetLastError();
+  if (!p) {  // then the caches of the other contexts
     if (lk.owns_lock()) lk.unlock();
-    if (trim_other_pools(pool) > 0) e = hipMalloc(&p, bytes);
+    if (trim_other_pools(pool) > 0) p = pool_raw_alloc(pool, bytes);
     if (pool) lk.lock();
   }
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    dev_fail("hipMalloc: out of device memory");
-  }
+  if (!p) dev_fail_nomem("device allocation failed: out of device memory");
   if (pool) pool->owned[p] = bytes;
   return p;
 }
