@@ -248,6 +248,65 @@ int sadmrg_extrapolate(int n, const double* w, const double* e, double* e0, doub
 int sadmrg_solve_extrapolated(sadmrg_ctx* ctx, int n, const int* D, const double* e_conv, const int* max_sweeps,
                               const double* noise, double* points, double* e0, double* c1);
 
+/* ------------------------------------------------------------------------
+ * DMRG-SCF (section "DMRG-SCF" of the library description): orbital
+ * optimisation of a complete-active-space wavefunction with this library's
+ * DMRG as the active-space solver, by the augmented-Hessian Newton-Raphson
+ * method with the exact Hessian.  Conventions: real orbitals, chemist
+ * integrals g_pqrs = (pq|rs); D_pq = <E_pq>, d_pqrs = <E_pq E_rs - d_qr
+ * E_ps> (= Gamma^A_{pr;qs}); E = e_nuc + sum h_pq D_pq + 1/2 sum g_pqrs
+ * d_pqrs; an orbital update is phi'_p = sum_q phi_q R_qp with R = exp(-K),
+ * K antisymmetric with parameters K_pq, p > q.  All host arithmetic.
+ * ------------------------------------------------------------------------ */
+/* h_out = R^T h R and eri_out_ijkl = sum_pqrs R_pi R_qj R_rk R_sl eri_pqrs
+ * (L x L and L^4, row-major; R orthogonal, column j = new orbital j).
+ * Errors: EINVAL, ENOMEM. */
+int sadmrg_rotate_integrals(int L, const double* R, const double* h, const double* eri, double* h_out,
+                            double* eri_out);
+/* R = exp(kappa) for an antisymmetric L x L kappa (EINVAL if it is not
+ * antisymmetric to 1e-12): Taylor series after scaling, repeated squaring,
+ * columns re-orthonormalised. */
+int sadmrg_rotation(int L, const double* kappa, double* R);
+/* Orbital derivatives of E with the RDMs D[L*L], d[L^4] held fixed:
+ * the generalised Fock matrix F_pq = sum_m D_pm h_qm + sum_mnt d_pmnt g_qmnt
+ * (fock[L*L], may be NULL), the gradient dE/dK_pq = 2 (F_pq - F_qp) for the
+ * npairs pairs (pairs[2a] = p > pairs[2a+1] = q) into grad[npairs], and, when
+ * hess is not NULL, the exact Hessian into hess[npairs^2]:
+ *   H_pq,rs = (1 - P_pq)(1 - P_rs) [2 D_pr h_qs - (F_pr + F_rp) d_qs + 2 Y_pqrs],
+ *   Y_pqrs = sum_mn [(d_pmrn + d_pmnr) g_qmsn + d_prmn g_qsmn].
+ * Errors: EINVAL (bad pair), ENOMEM. */
+int sadmrg_orbital_derivatives(int L, const double* h, const double* eri, const double* D, const double* d,
+                               int npairs, const int* pairs, double* grad, double* hess, double* fock);
+/* The DMRG-SCF loop.  ctx is an active-space context: created with one
+ * orbital per active orbital (in increasing full-space index order, with
+ * their irreps) and its target set to the active electrons (N - 2 n_core),
+ * spin and irrep; its Davidson and precision settings apply.  Full space:
+ * Lt orbitals with irreps orb_irrep[Lt] and classes cls[Lt] (0 core =
+ * doubly occupied, 1 active, 2 virtual), nuclear repulsion e_nuc, h[Lt^2],
+ * eri[Lt^4] in the starting orbitals.  Each iteration: rotate the integrals
+ * to the current orbitals; fold the core into the active Hamiltonian
+ * (E_core = e_nuc + sum_c 2 h_cc + sum_cc' [2 (cc|c'c') - (cc'|c'c)],
+ * h_tu + sum_c [2 (tu|cc) - (tc|cu)]); run the convergence scheme (n_sched
+ * instructions as sadmrg_solve; the previous iteration's MPS is the start);
+ * form gamma and Gamma^A (sadmrg_calc2dm) and the full-space D and d of the
+ * closed-shell core times the active state; stop if the norm of the gradient
+ * over the non-redundant rotations (p > q of different classes and the same
+ * irrep) is below grad_tol; else take the augmented-Hessian step (lowest
+ * eigenvector (v0, v) of [[0, g^T], [g, H]], x = v / v0, scaled to norm <=
+ * max_step) and update R <- R exp(-K(x)).
+ *   U[Lt*Lt] (may be NULL): in, the starting rotation (NULL: identity); out,
+ *     the final one (columns = optimised orbitals in the starting basis).
+ *   history[2*max_iter] (may be NULL): per iteration, the energy at that
+ *     iteration's orbitals and the gradient norm.
+ *   *n_iter, *energy (may be NULL): iterations run, last energy.
+ * The gradient of the last iteration is below grad_tol unless *n_iter ==
+ * max_iter.  Errors: EINVAL (arguments, active orbitals that do not match
+ * the context), ESYMM (no target on the context), and those of sadmrg_solve. */
+int sadmrg_dmrgscf(sadmrg_ctx* ctx, int Lt, const int* orb_irrep, const int* cls, double e_nuc, const double* h,
+                   const double* eri, int n_sched, const int* D, const double* e_conv, const int* max_sweeps,
+                   const double* noise, double grad_tol, int max_iter, double max_step, double* U,
+                   double* history, int* n_iter, double* energy);
+
 /* Energies: lowest over all micro-iterations so far, last micro-iteration's,
  * and the largest discarded weight of the last macro-iteration. */
 int sadmrg_get_energy(sadmrg_ctx* ctx, double* e_min, double* e_last, double* wdisc_max);

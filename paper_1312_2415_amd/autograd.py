@@ -61,26 +61,33 @@ def dmrg_energy(h, eri, solver, schedule, e_const=0.0, warm=True):
 
 def rotate_integrals(h, eri, kappa):
     """The integrals in the orbitals rotated by U = exp(kappa - kappa^T):
-    h' = U^T h U and (pq|rs)' = sum_ijkl U_ip U_jq U_kr U_ls (ij|kl), one
-    index at a time; differentiable in kappa (float64 tensors, one device)."""
-    u = torch.matrix_exp(kappa - kappa.transpose(0, 1))
-    L = h.shape[0]
-    h2 = u.transpose(0, 1) @ h @ u
-    v = eri
-    for axis in range(4):
-        w = torch.movedim(v, axis, 0).reshape(L, -1)
-        v = torch.movedim((u.transpose(0, 1) @ w).reshape(L, L, L, L), 0, axis)
-    return h2, v
+    h' = U^T h U and (pq|rs)' = sum_ijkl U_ip U_jq U_kr U_ls (ij|kl)
+    (sadmrg_rotation and sadmrg_rotate_integrals in the library; float64
+    tensors in, CPU tensors out)."""
+    from .binding import rotate_integrals as _rot, rotation
+    k = kappa.detach().to("cpu", torch.float64).numpy()
+    u = rotation(k - k.T)
+    h2, v2 = _rot(u, h.detach().to("cpu", torch.float64).numpy(), eri.detach().to("cpu", torch.float64).numpy())
+    return torch.from_numpy(h2), torch.from_numpy(v2)
 
 
 def orbital_gradient(h, eri, solver, schedule, e_const=0.0):
     """dE/dkappa at kappa = 0 for orbitals rotated by exp(kappa - kappa^T):
-    the orbital gradient that a DMRG-SCF step (section "DMRG-SCF") is built
-    from.  The chain rule runs through ``rotate_integrals`` and the energy's
-    adjoint (the RDMs); the solver is left at its re-converged MPS.  Returns
-    (E, gradient [L, L], antisymmetric)."""
-    kappa = torch.zeros_like(h, requires_grad=True)
-    h2, v2 = rotate_integrals(h, eri, kappa)
-    e = dmrg_energy(h2, v2, solver, schedule, e_const)
-    (g,) = torch.autograd.grad(e, kappa)
-    return e.detach(), g
+    the orbital gradient a DMRG-SCF step (section "DMRG-SCF") is built from.
+    The solver re-converges on (h, eri) (warm start), the library returns the
+    RDMs (sadmrg_calc2dm) and the orbital gradient 2 (F_pq - F_qp) from the
+    generalised Fock matrix (sadmrg_orbital_derivatives, every pair p > q).
+    Returns (E, gradient [L, L], antisymmetric)."""
+    from .binding import orbital_derivatives
+    e = dmrg_energy(h.detach(), eri.detach(), solver, schedule, e_const)
+    gchem, _, g1, _, _ = solver.calc2dm(layout=1)
+    L = h.shape[0]
+    pairs = [(p, q) for p in range(L) for q in range(p)]
+    g, _, _ = orbital_derivatives(h.detach().to("cpu", torch.float64).numpy(),
+                                  eri.detach().to("cpu", torch.float64).numpy(), g1, gchem, pairs, hessian=False)
+    # g_pq = dE/dK_pq for R = exp(-K); kappa - kappa^T = -K
+    G = np.zeros((L, L))
+    for (p, q), v in zip(pairs, g):
+        G[p, q] = -v
+        G[q, p] = v
+    return e.detach(), torch.from_numpy(G).to(h.device)

@@ -49,6 +49,13 @@ def load_library(path: str | None = None):
         "sadmrg_batch_sweep": (c_int, [P(c_vp), c_int, P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_solve": (c_int, [c_vp, c_int, P(c_int), P(c_dbl), P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_get_energy": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
+        "sadmrg_rotate_integrals": (c_int, [c_int, P(c_dbl), P(c_dbl), P(c_dbl), P(c_dbl), P(c_dbl)]),
+        "sadmrg_rotation": (c_int, [c_int, P(c_dbl), P(c_dbl)]),
+        "sadmrg_orbital_derivatives": (c_int, [c_int, P(c_dbl), P(c_dbl), P(c_dbl), P(c_dbl), c_int, P(c_int),
+                                               P(c_dbl), P(c_dbl), P(c_dbl)]),
+        "sadmrg_dmrgscf": (c_int, [c_vp, c_int, P(c_int), P(c_int), c_dbl, P(c_dbl), P(c_dbl), c_int, P(c_int),
+                                   P(c_dbl), P(c_int), P(c_dbl), c_dbl, c_int, c_dbl, P(c_dbl), P(c_dbl), P(c_int),
+                                   P(c_dbl)]),
         "sadmrg_extrapolate": (c_int, [c_int, P(c_dbl), P(c_dbl), P(c_dbl), P(c_dbl)]),
         "sadmrg_solve_extrapolated": (c_int, [c_vp, c_int, P(c_int), P(c_dbl), P(c_int), P(c_dbl), P(c_dbl),
                                               P(c_dbl), P(c_dbl)]),
@@ -217,6 +224,32 @@ class SaDMRG:
                                                      ctypes.byref(c1)))
         points = [(int(pts[3 * i]), pts[3 * i + 1], pts[3 * i + 2]) for i in range(n)]
         return e0.value, c1.value, points
+
+    def dmrgscf(self, orb_irrep, cls, h, eri, schedule, e_nuc=0.0, grad_tol=1e-6, max_iter=30, max_step=0.5,
+                U0=None):
+        """sadmrg_dmrgscf on this active-space solver.  Returns (E, U, history
+        [(E, |g|)], iterations)."""
+        Lt = len(cls)
+        irr = np.ascontiguousarray(orb_irrep, dtype=np.int32)
+        cl = np.ascontiguousarray(cls, dtype=np.int32)
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        eri = np.ascontiguousarray(eri, dtype=np.float64)
+        n = len(schedule)
+        D = (ctypes.c_int * n)(*[int(s[0]) for s in schedule])
+        ec = (ctypes.c_double * n)(*[float(s[1]) for s in schedule])
+        ms = (ctypes.c_int * n)(*[int(s[2]) for s in schedule])
+        nz = (ctypes.c_double * n)(*[float(s[3]) if len(s) > 3 else 0.0 for s in schedule])
+        U = np.eye(Lt) if U0 is None else np.array(U0, dtype=np.float64)
+        U = np.ascontiguousarray(U)
+        hist = np.zeros(2 * max_iter)
+        it, e = ctypes.c_int(), ctypes.c_double()
+        ip = ctypes.POINTER(ctypes.c_int)
+        self._chk(self.lib.sadmrg_dmrgscf(self.h, Lt, irr.ctypes.data_as(ip), cl.ctypes.data_as(ip), float(e_nuc),
+                                          _dptr(h), _dptr(eri), n, D, ec, ms, nz, float(grad_tol), int(max_iter),
+                                          float(max_step), _dptr(U), _dptr(hist), ctypes.byref(it),
+                                          ctypes.byref(e)))
+        k = it.value
+        return e.value, U, [(hist[2 * i], hist[2 * i + 1]) for i in range(k)], k
 
     def energy(self):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
@@ -413,6 +446,48 @@ def fit_discarded_weight(points, lib_path: str | None = None):
     if rc != 0:
         raise SadmrgError(rc, "bad (w, E) pairs")
     return e0.value, c1.value
+
+
+def rotate_integrals(R, h, eri, lib_path: str | None = None):
+    """(R^T h R, eri with R on every index) (sadmrg_rotate_integrals)."""
+    lib = load_library(lib_path)
+    R, h, eri = (np.ascontiguousarray(a, dtype=np.float64) for a in (R, h, eri))
+    L = h.shape[0]
+    h2, e2 = np.zeros_like(h), np.zeros_like(eri)
+    rc = lib.sadmrg_rotate_integrals(L, _dptr(R), _dptr(h), _dptr(eri), _dptr(h2), _dptr(e2))
+    if rc != 0:
+        raise SadmrgError(rc, "sadmrg_rotate_integrals failed")
+    return h2, e2
+
+
+def rotation(kappa, lib_path: str | None = None):
+    """exp(kappa) of an antisymmetric matrix (sadmrg_rotation)."""
+    lib = load_library(lib_path)
+    k = np.ascontiguousarray(kappa, dtype=np.float64)
+    R = np.zeros_like(k)
+    rc = lib.sadmrg_rotation(k.shape[0], _dptr(k), _dptr(R))
+    if rc != 0:
+        raise SadmrgError(rc, "sadmrg_rotation failed")
+    return R
+
+
+def orbital_derivatives(h, eri, D, d, pairs, hessian=True, lib_path: str | None = None):
+    """(gradient, Hessian or None, generalised Fock) of E over `pairs` with
+    the RDMs fixed (sadmrg_orbital_derivatives)."""
+    lib = load_library(lib_path)
+    h, eri, D, d = (np.ascontiguousarray(a, dtype=np.float64) for a in (h, eri, D, d))
+    L = h.shape[0]
+    n = len(pairs)
+    pr = np.ascontiguousarray(np.array(pairs, dtype=np.int32).reshape(-1))
+    g = np.zeros(max(n, 1))
+    H = np.zeros((n, n)) if hessian else None
+    F = np.zeros((L, L))
+    rc = lib.sadmrg_orbital_derivatives(L, _dptr(h), _dptr(eri), _dptr(D), _dptr(d), n,
+                                        pr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dptr(g),
+                                        _dptr(H) if hessian else None, _dptr(F))
+    if rc != 0:
+        raise SadmrgError(rc, "sadmrg_orbital_derivatives failed")
+    return g[:n], H, F
 
 
 def device_memory(device: int = 0, lib_path: str | None = None):

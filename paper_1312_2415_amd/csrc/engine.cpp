@@ -4632,6 +4632,201 @@ int sadmrg_solve_extrapolated(sadmrg_ctx* ctx, int n, const int* D, const double
   });
 }
 
+int sadmrg_rotate_integrals(int L, const double* R, const double* h, const double* eri, double* h_out,
+                            double* eri_out) {
+  if (L < 1 || !R || !h || !eri || !h_out || !eri_out) return SADMRG_EINVAL;
+  try {
+    sadmrg::rotate_integrals(L, R, h, eri, h_out, eri_out);
+  } catch (const std::bad_alloc&) {
+    return SADMRG_ENOMEM;
+  }
+  return 0;
+}
+
+int sadmrg_rotation(int L, const double* kappa, double* R) {
+  if (L < 1 || !kappa || !R) return SADMRG_EINVAL;
+  for (int p = 0; p < L; ++p)
+    for (int q = 0; q < L; ++q)
+      if (!std::isfinite(kappa[(size_t)p * L + q]) ||
+          std::abs(kappa[(size_t)p * L + q] + kappa[(size_t)q * L + p]) > 1e-12)
+        return SADMRG_EINVAL;
+  try {
+    sadmrg::expm_antisym(L, kappa, R);
+  } catch (const std::bad_alloc&) {
+    return SADMRG_ENOMEM;
+  }
+  return 0;
+}
+
+int sadmrg_orbital_derivatives(int L, const double* h, const double* eri, const double* D, const double* d,
+                               int npairs, const int* pairs, double* grad, double* hess, double* fock) {
+  if (L < 1 || !h || !eri || !D || !d || npairs < 0 || (npairs > 0 && (!pairs || !grad))) return SADMRG_EINVAL;
+  std::vector<std::pair<int, int>> pr;
+  for (int a = 0; a < npairs; ++a) {
+    const int p = pairs[2 * a], q = pairs[2 * a + 1];
+    if (p < 0 || p >= L || q < 0 || q >= L || p == q) return SADMRG_EINVAL;
+    pr.push_back({p, q});
+  }
+  std::vector<int> occ;  // orbitals where D or d is nonzero
+  const size_t L3 = (size_t)L * L * L;
+  for (int p = 0; p < L; ++p) {
+    bool nz = false;
+    for (int q = 0; q < L && !nz; ++q) nz = D[(size_t)p * L + q] != 0.0;
+    for (size_t r = 0; r < L3 && !nz; ++r) nz = d[(size_t)p * L3 + r] != 0.0;
+    if (nz) occ.push_back(p);
+  }
+  std::vector<double> g(std::max(npairs, 1));
+  try {
+    sadmrg::orbital_derivatives(L, h, eri, D, d, occ, pr, fock, npairs ? grad : g.data(), hess);
+  } catch (const std::bad_alloc&) {
+    return SADMRG_ENOMEM;
+  }
+  return 0;
+}
+
+int sadmrg_dmrgscf(sadmrg_ctx* ctx, int Lt, const int* orb_irrep, const int* cls, double e_nuc, const double* h,
+                   const double* eri, int n_sched, const int* D, const double* e_conv, const int* max_sweeps,
+                   const double* noise, double grad_tol, int max_iter, double max_step, double* U,
+                   double* history, int* n_iter, double* energy) {
+  return guard(ctx, [&] {
+    using namespace sadmrg;
+    auto& E = ctx->e;
+    if (Lt < 2 || !orb_irrep || !cls || !h || !eri || max_iter < 1 || !(grad_tol > 0.0) || !(max_step > 0.0))
+      fail(SADMRG_EINVAL, "bad DMRG-SCF arguments");
+    if (n_sched < 1 || !D || !e_conv || !max_sweeps) fail(SADMRG_EINVAL, "bad schedule");
+    std::vector<int> core, act;
+    for (int p = 0; p < Lt; ++p) {
+      if (cls[p] < 0 || cls[p] > 2) fail(SADMRG_EINVAL, "orbital class must be 0 (core), 1 (active) or 2 (virtual)");
+      if (orb_irrep[p] < 0 || orb_irrep[p] >= E.P.order) fail(SADMRG_EINVAL, "orbital irrep out of range");
+      if (cls[p] == 0) core.push_back(p);
+      if (cls[p] == 1) act.push_back(p);
+    }
+    const int La = (int)act.size();
+    if (La != E.P.L) fail(SADMRG_EINVAL, "the context must have one orbital per active orbital");
+    for (int t = 0; t < La; ++t)
+      if (orb_irrep[act[t]] != E.P.orb[t]) fail(SADMRG_EINVAL, "active orbital irreps differ from the context's");
+    if (E.P.N < 2) fail(SADMRG_ESYMM, "set the active-space target (N, 2S, irrep) on the context first");
+    std::vector<std::pair<int, int>> pairs;  // non-redundant rotations
+    for (int p = 0; p < Lt; ++p)
+      for (int q = 0; q < p; ++q)
+        if (cls[p] != cls[q] && orb_irrep[p] == orb_irrep[q]) pairs.push_back({p, q});
+    const size_t n2 = (size_t)Lt * Lt, n4 = n2 * n2;
+    std::vector<double> R(n2, 0.0), ht(n2), gt(n4), ha((size_t)La * La), ga((size_t)La * La * La * La);
+    if (U)
+      std::copy(U, U + n2, R.begin());
+    else
+      for (int p = 0; p < Lt; ++p) R[(size_t)p * Lt + p] = 1.0;
+    std::vector<double> g1((size_t)La * La), G2((size_t)La * La * La * La), Dm(n2), dm(n4);
+    auto gi = [&](int p, int q, int r, int s) { return gt[(((size_t)p * Lt + q) * Lt + r) * Lt + s]; };
+    double e = 0.0;
+    int it = 0;
+    for (; it < max_iter; ++it) {
+      rotate_integrals(Lt, R.data(), h, eri, ht.data(), gt.data());
+      // core energy and the active-space Hamiltonian in the core's field
+      double e_core = e_nuc;
+      for (int c : core) e_core += 2.0 * ht[(size_t)c * Lt + c];
+      for (int c : core)
+        for (int c2 : core) e_core += 2.0 * gi(c, c, c2, c2) - gi(c, c2, c2, c);
+      for (int t = 0; t < La; ++t)
+        for (int u = 0; u < La; ++u) {
+          double v = ht[(size_t)act[t] * Lt + act[u]];
+          for (int c : core) v += 2.0 * gi(act[t], act[u], c, c) - gi(act[t], c, c, act[u]);
+          ha[(size_t)t * La + u] = v;
+        }
+      for (int t = 0; t < La; ++t)
+        for (int u = 0; u < La; ++u)
+          for (int v = 0; v < La; ++v)
+            for (int w = 0; w < La; ++w) ga[(((size_t)t * La + u) * La + v) * La + w] = gi(act[t], act[u], act[v], act[w]);
+      // warm start: the converged MPS of the previous orbitals
+      std::vector<char> blob;
+      if (E.mps_ready) {
+        size_t nb = 0;
+        int rc = sadmrg_mps_export(ctx, nullptr, &nb);
+        if (rc == 0) {
+          blob.resize(nb);
+          rc = sadmrg_mps_export(ctx, blob.data(), &nb);
+        }
+        if (rc != 0) blob.clear();
+      }
+      int rc = sadmrg_set_integrals(ctx, e_core, ha.data(), ga.data(), 1e-9);
+      if (rc < 0) throw Failure{rc, ctx->err};
+      if (!blob.empty()) {
+        rc = sadmrg_mps_import(ctx, blob.data(), blob.size());
+        if (rc < 0) throw Failure{rc, ctx->err};
+      }
+      rc = sadmrg_solve(ctx, n_sched, D, e_conv, max_sweeps, noise, nullptr);
+      if (rc < 0) throw Failure{rc, ctx->err};
+      e = E.rdms(g1.data(), G2.data(), 1);  // chemist: G2[t][u][v][w] = d_tuvw
+      // full-space RDMs of (closed-shell core) x (active state)
+      std::fill(Dm.begin(), Dm.end(), 0.0);
+      std::fill(dm.begin(), dm.end(), 0.0);
+      auto DD = [&](int p, int q) -> double& { return Dm[(size_t)p * Lt + q]; };
+      auto dd = [&](int p, int q, int r, int s) -> double& { return dm[(((size_t)p * Lt + q) * Lt + r) * Lt + s]; };
+      for (int c : core) DD(c, c) = 2.0;
+      for (int t = 0; t < La; ++t)
+        for (int u = 0; u < La; ++u) DD(act[t], act[u]) = g1[(size_t)t * La + u];
+      for (int c : core)
+        for (int c2 : core) {
+          dd(c, c, c2, c2) += 4.0;
+          dd(c, c2, c2, c) -= 2.0;
+        }
+      for (int c : core)
+        for (int t = 0; t < La; ++t)
+          for (int u = 0; u < La; ++u) {
+            const double gtu = g1[(size_t)t * La + u];
+            dd(c, c, act[t], act[u]) += 2.0 * gtu;
+            dd(act[t], act[u], c, c) += 2.0 * gtu;
+            dd(c, act[u], act[t], c) -= gtu;
+            dd(act[t], c, c, act[u]) -= gtu;
+          }
+      for (int t = 0; t < La; ++t)
+        for (int u = 0; u < La; ++u)
+          for (int v = 0; v < La; ++v)
+            for (int w = 0; w < La; ++w)
+              dd(act[t], act[u], act[v], act[w]) = G2[(((size_t)t * La + u) * La + v) * La + w];
+      std::vector<int> occ(core);
+      occ.insert(occ.end(), act.begin(), act.end());
+      std::sort(occ.begin(), occ.end());
+      const int np = (int)pairs.size();
+      std::vector<double> grad(std::max(np, 1)), hess((size_t)np * np);
+      orbital_derivatives(Lt, ht.data(), gt.data(), Dm.data(), dm.data(), occ, pairs, nullptr, grad.data(),
+                          nullptr);
+      double gn = 0.0;
+      for (int a = 0; a < np; ++a) gn += grad[a] * grad[a];
+      gn = std::sqrt(gn);
+      if (history) {
+        history[2 * it] = e;
+        history[2 * it + 1] = gn;
+      }
+      if (gn < grad_tol || np == 0) {
+        ++it;
+        break;
+      }
+      orbital_derivatives(Lt, ht.data(), gt.data(), Dm.data(), dm.data(), occ, pairs, nullptr, grad.data(),
+                          hess.data());
+      grad.resize(np);
+      const std::vector<double> x = ah_step(grad, hess, max_step);
+      std::vector<double> K(n2, 0.0), Rs(n2), Rn(n2);
+      for (int a = 0; a < np; ++a) {  // R <- R exp(-kappa)
+        K[(size_t)pairs[a].first * Lt + pairs[a].second] = -x[a];
+        K[(size_t)pairs[a].second * Lt + pairs[a].first] = x[a];
+      }
+      expm_antisym(Lt, K.data(), Rs.data());
+      for (int p = 0; p < Lt; ++p)
+        for (int q = 0; q < Lt; ++q) {
+          double v = 0.0;
+          for (int k = 0; k < Lt; ++k) v += R[(size_t)p * Lt + k] * Rs[(size_t)k * Lt + q];
+          Rn[(size_t)p * Lt + q] = v;
+        }
+      R.swap(Rn);
+    }
+    if (U) std::copy(R.begin(), R.end(), U);
+    if (n_iter) *n_iter = std::min(it, max_iter);
+    if (energy) *energy = e;
+    return 0;
+  });
+}
+
 int sadmrg_get_energy(sadmrg_ctx* ctx, double* e_min, double* e_last, double* wdisc_max) {
   return guard(ctx, [&] {
     if (e_min) *e_min = ctx->e.emin;

@@ -29,6 +29,14 @@ double coupling_singlet(int tj, int tjp, int tk);
 double recouple_singlet(int ta, int ts, int tb);
 double adjoint_factor(int tj_bra, int tj_ket, int tk);
 
+// ---- DMRG-SCF host arithmetic (scf.cpp)
+void rotate_integrals(int L, const double* R, const double* h, const double* g, double* h2, double* g2);
+void expm_antisym(int L, const double* A, double* R);
+void orbital_derivatives(int L, const double* h, const double* g, const double* D, const double* d,
+                         const std::vector<int>& occ, const std::vector<std::pair<int, int>>& pairs, double* F,
+                         double* grad, double* hess);
+std::vector<double> ah_step(const std::vector<double>& grad, const std::vector<double>& hess, double max_step);
+
 // ---- symmetry sectors: (N left of the bond, 2j, irrep)
 struct Sec {
   int N, tj, G;
