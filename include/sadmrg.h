@@ -307,6 +307,24 @@ int sadmrg_dmrgscf(sadmrg_ctx* ctx, int Lt, const int* orb_irrep, const int* cls
                    const double* noise, double grad_tol, int max_iter, double max_step, double* U,
                    double* history, int* n_iter, double* energy);
 
+/* Excited states by projection (section "CheMPS2 library", the DMRG object:
+ * newExcitation).  sadmrg_push_excitation keeps the current MPS as the state
+ * Psi_k (normalised; it must have its two-site centre at the left end, as
+ * after a sweep or an import there) with weight eta > 0; every later solve
+ * of this context uses H_m = H_0 + sum_k eta_k |Psi_k><Psi_k|, which pushes
+ * the lower states up by eta_k and so targets the next state of the same
+ * (N, S, irrep) sector (eta must exceed the gap to it).  The current MPS is
+ * left as it is: start the next state with sadmrg_init_mps or
+ * sadmrg_mps_import.  On the two-site space the extra term is sum_k eta_k
+ * <phi_k|x> phi_k with phi_k the projection of Psi_k, built from overlap
+ * environments of the current and the stored MPS that follow the sweep;
+ * sadmrg_sigma and sadmrg_heff_diagonal include it, the density matrices
+ * (sadmrg_rdm, sadmrg_calc2dm) are those of the state for H_0.  At most 64
+ * states; sadmrg_set_target removes them, sadmrg_clear_excitations too.
+ * Errors: EINVAL (eta <= 0, centre not at the left end, too many states). */
+int sadmrg_push_excitation(sadmrg_ctx* ctx, double eta);
+int sadmrg_clear_excitations(sadmrg_ctx* ctx);
+
 /* Energies: lowest over all micro-iterations so far, last micro-iteration's,
  * and the largest discarded weight of the last macro-iteration. */
 int sadmrg_get_energy(sadmrg_ctx* ctx, double* e_min, double* e_last, double* wdisc_max);

@@ -961,6 +961,7 @@ class DMRG:
         self.n_pass = 0
         self.wd_prev = 0.0
         self.wd_pass = 0.0
+        self.lower = []  # LowerState objects (excited-state solves)
         self._init_mps()
 
     # ----- initial state: random right-canonical tensors (paper: random noise)
@@ -1040,7 +1041,15 @@ class DMRG:
         if np.linalg.norm(x0) == 0:
             x0 = np.ones_like(x0)
         dg = flatten(H.diagonal(shapes), secs)
-        mv = lambda v: flatten(H.apply(unflatten(v, shapes, secs)), secs)
+        phis = [(w.eta, flatten(project_lower(P, self, w, i, El, Er, secs), secs)) for w in self.lower]
+        for eta, f in phis:
+            dg = dg + eta * f * f
+
+        def mv(v):
+            y = flatten(H.apply(unflatten(v, shapes, secs)), secs)
+            for eta, f in phis:
+                y = y + eta * (f @ v) * f
+            return y
         th, x, its, conv = davidson(mv, dg, x0, self.dav_tol, self.dav_max_sub, self.dav_max_iter)
         e = th + P.e_const
         self.emin = min(self.emin, e)
@@ -1076,6 +1085,11 @@ class DMRG:
             C = {m: U[m] * s[m][None, :] for m in kept}
             self.center = (i - 1, move_center_left(P, C, self.U[i - 1], c, kept, self.dims[c - 1]))
         return e
+
+    def push_lower(self, other, eta):
+        """Project the state of `other` (a DMRG of the same problem, centre at
+        the left end) out of this one's solves with weight eta."""
+        self.lower.append(LowerState(other, eta))
 
     def sweep(self, D, noise=0.0):
         """One macro-iteration: right pass i = 0..L-2, left pass i = L-2..0.
@@ -1117,6 +1131,109 @@ class DMRG:
     # two-site wavefunction as (sectors, shapes, flat vector) at the current centre
     def current_psi(self):
         return self.center
+
+
+# ---------------------------------------------------------------------------
+# Excited states by projection (section "CheMPS2 library", the DMRG object):
+# after a state Psi_k is found it is pushed back with a weight eta_k > 0 and
+# the next solve uses H_m = H_0 + sum_k eta_k |Psi_k><Psi_k|.  On the current
+# two-site space the extra term is sum_k eta_k |phi_k><phi_k| with
+# phi_k = P_i Psi_k the projection of Psi_k onto that space.  Here Psi_k's
+# centre is first carried along the chain by exact decompositions (nothing
+# truncated), so that its two-site object psi_k(i) at every step is at hand
+# in its own left- and right-normalised bases; then
+#   phi_k(i) = (OL(i) (x) 1 (x) 1 (x) OR(i+2)) psi_k(i),
+# OL / OR the overlaps between the current and Psi_k's normalised left /
+# right block states, built afresh from the chain ends at every step.
+# ---------------------------------------------------------------------------
+class LowerState:
+    def __init__(self, dm, eta):
+        P = dm.P
+        i, psi = dm.center
+        if i != 0:
+            raise ValueError("push a lower state when its centre is at the left end")
+        self.eta = float(eta)
+        nrm = math.sqrt(sum(float(np.sum(x * x)) for x in psi.values()))
+        self.dimsR = [dict(d) for d in dm.dims]        # right-normalised bases
+        self.V = [None if v is None else {m: x.copy() for m, x in v.items()} for v in dm.V]
+        self.dimsL = [dict(dm.dims[0])] + [None] * P.L  # left-normalised bases
+        self.U = [None] * P.L
+        self.psi = [None] * (P.L - 1)
+        cur = {m: x / nrm for m, x in psi.items()}
+        for j in range(P.L - 1):
+            self.psi[j] = cur
+            if j == P.L - 2:
+                break
+            U, s, Vt, kept, _ = svd_truncate(cur, 10 ** 9)
+            self.U[j] = U
+            self.dimsL[j + 1] = kept
+            C = {m: s[m][:, None] * Vt[m] for m in kept}
+            cur = move_center_right(P, C, self.V[j + 2], j + 1, kept, self.dimsR[j + 2])
+
+
+def overlap_left(P, U_cur, dims_cur, U_k, dims_k, i):
+    """<current left states at bond i | Psi_k's left-normalised states>."""
+    O = {s: np.ones((1, 1)) for s in dims_cur[0]}
+    for c in range(i):
+        Ec, Ek = LeftEnl(P, c + 1, dims_cur[c]), LeftEnl(P, c + 1, dims_k[c])
+        new = {}
+        for m, Uc in U_cur[c].items():
+            if m not in U_k[c] or m not in Ec.pieces:
+                continue
+            acc = np.zeros((Uc.shape[1], U_k[c][m].shape[1]))
+            for (a, n) in Ec.pieces[m]:
+                if a not in O or (m, a, n) not in Ek.off:
+                    continue
+                oc, ok = Ec.off[(m, a, n)], Ek.off[(m, a, n)]
+                acc += Uc[oc:oc + dims_cur[c][a]].T @ O[a] @ U_k[c][m][ok:ok + dims_k[c][a]]
+            new[m] = acc
+        O = new
+    return O
+
+
+def overlap_right(P, V_cur, dims_cur, V_k, dims_k, b0):
+    """<current right states at bond b0 | Psi_k's right-normalised states>."""
+    O = {s: np.ones((1, 1)) for s in dims_cur[P.L]}
+    for c in range(P.L - 1, b0 - 1, -1):
+        Ec, Ek = RightEnl(P, c, dims_cur[c + 1]), RightEnl(P, c, dims_k[c + 1])
+        new = {}
+        for m, Vc in V_cur[c].items():
+            if m not in V_k[c] or m not in Ec.pieces:
+                continue
+            acc = np.zeros((Vc.shape[0], V_k[c][m].shape[0]))
+            for (n, b) in Ec.pieces[m]:
+                if b not in O or (m, n, b) not in Ek.off:
+                    continue
+                oc, ok = Ec.off[(m, n, b)], Ek.off[(m, n, b)]
+                acc += Vc[:, oc:oc + dims_cur[c + 1][b]] @ O[b] @ V_k[c][m][:, ok:ok + dims_k[c + 1][b]].T
+            new[m] = acc
+        O = new
+    return O
+
+
+def project_lower(P, dm, w: LowerState, i, El, Er, secs):
+    """phi = P_i Psi_k on the current two-site space of step i."""
+    OL = overlap_left(P, dm.U, dm.dims, w.U, w.dimsL, i)
+    OR = overlap_right(P, dm.V, dm.dims, w.V, w.dimsR, i + 2)
+    Elk, Erk = LeftEnl(P, i + 1, w.dimsL[i]), RightEnl(P, i + 1, w.dimsR[i + 2])
+    out = {}
+    for m in secs:
+        phi = np.zeros((El.dim[m], Er.dim[m]))
+        pk = w.psi[i].get(m)
+        if pk is not None and m in Elk.pieces and m in Erk.pieces:
+            for (a, n1) in El.pieces[m]:
+                if a not in OL or (m, a, n1) not in Elk.off:
+                    continue
+                rc, rk = El.off[(m, a, n1)], Elk.off[(m, a, n1)]
+                rows = OL[a] @ pk[rk:rk + w.dimsL[i][a]]
+                for (n2, b) in Er.pieces[m]:
+                    if b not in OR or (m, n2, b) not in Erk.off:
+                        continue
+                    cc, ck = Er.off[(m, n2, b)], Erk.off[(m, n2, b)]
+                    phi[rc:rc + dm.dims[i][a], cc:cc + dm.dims[i + 2][b]] += (
+                        rows[:, ck:ck + w.dimsR[i + 2][b]] @ OR[b].T)
+        out[m] = phi
+    return out
 
 
 NOISE_STREAM = 0x4E4F << 40

@@ -49,6 +49,8 @@ def load_library(path: str | None = None):
         "sadmrg_batch_sweep": (c_int, [P(c_vp), c_int, P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_solve": (c_int, [c_vp, c_int, P(c_int), P(c_dbl), P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_get_energy": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
+        "sadmrg_push_excitation": (c_int, [c_vp, c_dbl]),
+        "sadmrg_clear_excitations": (c_int, [c_vp]),
         "sadmrg_rotate_integrals": (c_int, [c_int, P(c_dbl), P(c_dbl), P(c_dbl), P(c_dbl), P(c_dbl)]),
         "sadmrg_rotation": (c_int, [c_int, P(c_dbl), P(c_dbl)]),
         "sadmrg_orbital_derivatives": (c_int, [c_int, P(c_dbl), P(c_dbl), P(c_dbl), P(c_dbl), c_int, P(c_int),
@@ -250,6 +252,13 @@ class SaDMRG:
                                           ctypes.byref(e)))
         k = it.value
         return e.value, U, [(hist[2 * i], hist[2 * i + 1]) for i in range(k)], k
+
+    def push_excitation(self, eta):
+        """Keep the current MPS as a lower state with weight eta (sadmrg_push_excitation)."""
+        self._chk(self.lib.sadmrg_push_excitation(self.h, float(eta)))
+
+    def clear_excitations(self):
+        self._chk(self.lib.sadmrg_clear_excitations(self.h))
 
     def energy(self):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -1561,6 +1561,8 @@ struct Step {
   double flops = 0.0, bytes = 0.0;
   int64_t ntasks = 0;
   std::vector<std::array<int, 5>> shapes;  // per tile task: rows, K1, K2, cols, flags
+  DBuf proj;                     // projection vectors of the lower states (excited-state solves)
+  int nproj = 0;
   int site = -1;                 // i of the sites (i, i+1), kept when i is reset
   uint64_t genX = 0, genY = 0;   // generations of the blocks X and Y were built from
 };
@@ -2237,7 +2239,7 @@ struct Engine {
     dpartial.ensure(256 * 64);
     launch_dots(step.in.p, n, 1, step.in.p, n, dsmall.p, dpartial.p, st);
     launch_normalize(step.in.p, dsmall.p, n, st);
-    sigma_fixed(false);
+    sigma_fixed(false, false);  // H_0: the density matrices of the state itself
     launch_dots(step.in.p, n, 1, step.out.p, n, dsmall.p + 1, dpartial.p, st);
     double e;
     dev_d2h(&e, dsmall.p + 1, 8, st);
@@ -2339,6 +2341,339 @@ struct Engine {
       *s2 = -0.25 * P.N * (P.N - 4) - 0.5 * t;
     }
     return e + P.e_const;
+  }
+
+  // ---- excited states by projection (section "CheMPS2 library", the DMRG
+  // object): after a state Psi_k is found it is pushed back with a weight
+  // eta_k > 0 and the next solve uses H_m = H_0 + sum_k eta_k |Psi_k><Psi_k|,
+  // which projects the lower states out of the target sector.  On the
+  // current two-site space at sites (i, i+1) the extra term is
+  //   sigma += sum_k eta_k <phi_k|x> phi_k,  phi_k = P_i Psi_k,
+  // with P_i the projector onto the space of the current left states at bond
+  // i, the two sites and the current right states at bond i+2.  Psi_k is kept
+  // as its left-end object C (bond 1) and right-normalised tensors V_k[1..];
+  // the overlaps are carried as environments updated with the sweep:
+  //   OR[b] = <current right states at bond b | Psi_k's right states>,
+  //   M[c]  = <current left states at bond c | Psi_k's part left of bond c>,
+  // and at step i, X_i = (M[i] V_k[i]) recoupled into the left-enlarged basis
+  // at bond i+1 (X_0 = C), phi_k = X_i V_k[i+1] OR[i+2]^T, M[i+1] = U[i]^T X_i.
+  struct Lower {
+    double eta = 0.0;
+    std::vector<Basis> dims;  // Psi_k's bond bases
+    Tensor C;                 // left-end object: bond-1 sectors, 1 x dims[1]
+    std::vector<Tensor> V;    // V[1..L-1], right-normalised
+    std::vector<Tensor> M;    // M[c], c = 1..L-1
+    std::vector<Tensor> OR;   // OR[b], b = 2..L
+    Tensor X;                 // X_i of the prepared step
+  };
+  std::vector<Lower> lower;
+  DBuf projc, projpart;  // scalars and partial sums of the projector dots
+
+  static void copy_meta(const Tensor& a, Tensor& b) {
+    b.rowsec = a.rowsec;
+    b.rows = a.rows;
+    b.cols = a.cols;
+  }
+  void copy_tensor(const Tensor& a, Tensor& b) {
+    copy_meta(a, b);
+    alloc_tensor(b);
+    int64_t tot = 0;
+    for (size_t j = 0; j < a.rows.size(); ++j) tot += (int64_t)a.rows[j] * a.cols[j];
+    if (tot) dev_d2d(b.data.p, a.data.p, (size_t)tot * 8, st);
+  }
+  void zero_tensor(Tensor& t) {
+    int64_t tot = 0;
+    for (size_t j = 0; j < t.rows.size(); ++j) tot += (int64_t)t.rows[j] * t.cols[j];
+    dev_zero(t.data.p, (size_t)std::max<int64_t>(tot, 1) * 8, st);
+  }
+  void run_triples(const std::vector<OutBlk>& outs, const std::vector<Triple>& trs) {
+    if (!trs.empty()) {
+      TwoPass tp;
+      build_two_pass(outs, trs, tp, st);
+      tp.run(st);
+    }
+    dev_sync(st);
+  }
+  // the step a centre of this kind leads to (as sadmrg_prepare_step)
+  int next_step() const {
+    switch (cen.kind) {
+      case C_TWO:
+      case C_T0:
+      case C_BOND_R:
+        return cen.pos;
+      case C_BOND_L:
+        return cen.pos - 2;
+      default:
+        fail(-1, "no centre");
+    }
+  }
+  // OR[c] = V[c] (1_site x OR[c+1]) V_k[c]^T over the right-enlarged pieces
+  void lower_or(Lower& w, int c) {
+    Tensor& o = w.OR[c];
+    o = Tensor();
+    for (size_t j = 0; j < dims[c].sec.size(); ++j) {
+      const int kj = w.dims[c].find(dims[c].sec[j]);
+      if (kj < 0 || V[c].find(dims[c].sec[j]) < 0 || w.V[c].find(dims[c].sec[j]) < 0) continue;
+      o.rowsec.sec.push_back(dims[c].sec[j]);
+      o.rowsec.dim.push_back(dims[c].dim[j]);
+      o.rows.push_back(dims[c].dim[j]);
+      o.cols.push_back(w.dims[c].dim[kj]);
+    }
+    alloc_tensor(o);
+    zero_tensor(o);
+    Enl ec = right_enl(P, c, dims[c + 1], nullptr), ek = right_enl(P, c, w.dims[c + 1], nullptr);
+    std::vector<OutBlk> outs;
+    std::vector<Triple> trs;
+    for (size_t j = 0; j < o.rowsec.sec.size(); ++j) {
+      const Sec& be = o.rowsec.sec[j];
+      const int vc = V[c].find(be), vk = w.V[c].find(be), pc = ec.find(be), pk = ek.find(be);
+      if (pc < 0 || pk < 0) continue;
+      outs.push_back({o.at((int)j), o.rows[j], o.cols[j], o.cols[j]});
+      for (const Piece& qc : ec.pieces[pc]) {
+        const Sec& b = dims[c + 1].sec[qc.sub];
+        const int ob = w.OR[c + 1].find(b);
+        if (ob < 0) continue;
+        for (const Piece& qk : ek.pieces[pk]) {
+          if (qk.n != qc.n || !(w.dims[c + 1].sec[qk.sub] == b)) continue;
+          Triple t{};
+          t.blk = (int)outs.size() - 1;
+          t.a = V[c].at(vc) + qc.off;
+          t.lda = V[c].cols[vc];
+          t.K1 = dims[c + 1].dim[qc.sub];
+          t.b = w.OR[c + 1].at(ob);
+          t.ldb = w.OR[c + 1].cols[ob];
+          t.K2 = w.dims[c + 1].dim[qk.sub];
+          t.c = w.V[c].at(vk) + qk.off;
+          t.ldc = w.V[c].cols[vk];
+          t.flags = TT_TRANS_C;
+          t.coef = 1.0;
+          trs.push_back(t);
+        }
+      }
+    }
+    run_triples(outs, trs);
+  }
+  // X_i: (M[i] V_k[i]) recoupled into the current left-enlarged basis at bond
+  // i+1 (columns: Psi_k's bond i+1); X_0 is the left-end object
+  void lower_x(Lower& w, int i) {
+    if (i == 0) {
+      copy_tensor(w.C, w.X);
+      return;
+    }
+    Enl el = left_enl(P, i + 1, dims[i], nullptr), ek = right_enl(P, i, w.dims[i + 1], nullptr);
+    Tensor& x = w.X;
+    x = Tensor();
+    for (size_t m = 0; m < el.sec.size(); ++m) {
+      const int kj = w.dims[i + 1].find(el.sec[m]);
+      if (kj < 0) continue;
+      x.rowsec.sec.push_back(el.sec[m]);
+      x.rowsec.dim.push_back(el.dim[m]);
+      x.rows.push_back(el.dim[m]);
+      x.cols.push_back(w.dims[i + 1].dim[kj]);
+    }
+    alloc_tensor(x);
+    zero_tensor(x);
+    std::vector<OutBlk> outs;
+    std::vector<Triple> trs;
+    const Tensor& M = w.M[i];
+    for (size_t ja = 0; ja < M.rowsec.sec.size(); ++ja) {
+      const Sec& a = M.rowsec.sec[ja];
+      const int va = w.V[i].find(a), ea = ek.find(a), ai = dims[i].find(a);
+      if (va < 0 || ea < 0 || ai < 0) continue;
+      for (const Piece& pc : ek.pieces[ea]) {
+        const Sec& be = w.dims[i + 1].sec[pc.sub];
+        const int xb = x.find(be), eb = el.find(be);
+        if (xb < 0 || eb < 0) continue;
+        int roff = -1;
+        for (const Piece& q : el.pieces[eb])
+          if (q.sub == ai && q.n == pc.n) roff = q.off;
+        if (roff < 0) continue;
+        outs.push_back({x.at(xb) + (int64_t)roff * x.cols[xb], M.rows[ja], x.cols[xb], x.cols[xb]});
+        Triple t{};
+        t.blk = (int)outs.size() - 1;
+        t.a = M.at((int)ja);
+        t.lda = M.cols[ja];
+        t.K1 = M.cols[ja];
+        t.b = w.V[i].at(va) + pc.off;
+        t.ldb = w.V[i].cols[va];
+        t.flags = TT_IDENT_C;
+        t.coef = recouple_singlet(a.tj, LOC_TJ[pc.n], be.tj);
+        trs.push_back(t);
+      }
+    }
+    run_triples(outs, trs);
+  }
+  // M[i+1] = U[i]^T X_i
+  void lower_m(Lower& w, int i) {
+    Tensor& o = w.M[i + 1];
+    o = Tensor();
+    for (size_t j = 0; j < U[i].rowsec.sec.size(); ++j) {
+      const int xj = w.X.find(U[i].rowsec.sec[j]);
+      if (xj < 0) continue;
+      o.rowsec.sec.push_back(U[i].rowsec.sec[j]);
+      o.rowsec.dim.push_back(U[i].cols[j]);
+      o.rows.push_back(U[i].cols[j]);
+      o.cols.push_back(w.X.cols[xj]);
+    }
+    alloc_tensor(o);
+    zero_tensor(o);
+    std::vector<OutBlk> outs;
+    std::vector<Triple> trs;
+    for (size_t j = 0; j < o.rowsec.sec.size(); ++j) {
+      const int uj = U[i].find(o.rowsec.sec[j]), xj = w.X.find(o.rowsec.sec[j]);
+      if (U[i].rows[uj] != w.X.rows[xj]) fail(-1, "internal: overlap environment shape mismatch");
+      outs.push_back({o.at((int)j), o.rows[j], o.cols[j], o.cols[j]});
+      Triple t{};
+      t.blk = (int)outs.size() - 1;
+      t.a = U[i].at(uj);
+      t.lda = U[i].cols[uj];
+      t.K1 = U[i].rows[uj];
+      t.b = w.X.at(xj);
+      t.ldb = w.X.cols[xj];
+      t.flags = TT_TRANS_A | TT_IDENT_C;
+      t.coef = 1.0;
+      trs.push_back(t);
+    }
+    run_triples(outs, trs);
+  }
+  // every environment for the step the centre leads to
+  void lower_rebuild() {
+    if (lower.empty() || !mps_ready) return;
+    const int L = P.L, i = next_step();
+    for (Lower& w : lower) {
+      w.M.clear();
+      w.M.resize(L + 1);
+      w.OR.clear();
+      w.OR.resize(L + 1);
+      Tensor& o = w.OR[L];  // boundary: one sector, <1|1>
+      o.rowsec = dims[L];
+      o.rows = {1};
+      o.cols = {1};
+      alloc_tensor(o);
+      const double one = 1.0;
+      dev_h2d(o.data.p, &one, 8, st);
+      for (int b = L - 1; b >= i + 2; --b) lower_or(w, b);
+      for (int c = 0; c < i; ++c) {
+        lower_x(w, c);
+        lower_m(w, c);
+      }
+    }
+  }
+  // snapshot of the current MPS (centre at the left end) as a lower state
+  void lower_push(double eta) {
+    if (!(eta > 0.0) || !std::isfinite(eta)) fail(-1, "eta must be positive");
+    if (!mps_ready || cen.kind != C_TWO || cen.pos != 0)
+      fail(-1, "push an excitation when the two-site centre is at the left end (after a sweep or an import there)");
+    if (lower.size() >= 64) fail(-1, "at most 64 lower states");
+    Lower w;
+    w.eta = eta;
+    w.dims = dims;
+    w.V.resize(P.L);
+    for (int k = 2; k < P.L; ++k) copy_tensor(V[k], w.V[k]);
+    // the left-end object: one row per sector of bond 1 (bond 0 is one
+    // state); row m = |row_m| (row_m / |row_m|): C holds the norms, V[1] the
+    // normalised rows, Psi_k normalised as a whole
+    const int ns = (int)cen.t.rows.size();
+    std::vector<double> nrm(ns, 0.0);
+    projc.ensure(64);
+    projpart.ensure(256 * 64);
+    for (int j = 0; j < ns; ++j) {
+      if (cen.t.rows[j] != 1) fail(-1, "internal: left-end object with more than one row per sector");
+      launch_dots(cen.t.at(j), cen.t.cols[j], 1, cen.t.at(j), cen.t.cols[j], projc.p, projpart.p, st);
+      dev_d2h(&nrm[j], projc.p, 8, st);
+    }
+    double tot = 0.0;
+    for (double v : nrm) tot += v;
+    if (!(tot > 0.0)) fail(-1, "the current MPS is zero");
+    Basis b1;
+    std::vector<int> src;
+    for (int j = 0; j < ns; ++j)
+      if (nrm[j] > 0.0) {
+        b1.sec.push_back(cen.t.rowsec.sec[j]);
+        b1.dim.push_back(1);
+        src.push_back(j);
+      }
+    w.dims[1] = b1;
+    Tensor& v1 = w.V[1];
+    v1.rowsec = b1;
+    w.C.rowsec = b1;
+    for (int j : src) {
+      v1.rows.push_back(1);
+      v1.cols.push_back(cen.t.cols[j]);
+      w.C.rows.push_back(1);
+      w.C.cols.push_back(1);
+    }
+    alloc_tensor(v1);
+    alloc_tensor(w.C);
+    std::vector<double> cv;
+    for (size_t q = 0; q < src.size(); ++q) {
+      const int j = src[q];
+      dev_d2d(v1.at((int)q), cen.t.at(j), (size_t)cen.t.cols[j] * 8, st);
+      launch_scal(v1.at((int)q), 1.0 / std::sqrt(nrm[j]), cen.t.cols[j], st);
+      cv.push_back(std::sqrt(nrm[j] / tot));
+    }
+    dev_h2d(w.C.data.p, cv.data(), cv.size() * 8, st);
+    lower.push_back(std::move(w));
+    step.i = -1;  // the next prepare adds the projector
+    lower_rebuild();
+  }
+  void lower_clear() {
+    lower.clear();
+    step.i = -1;
+  }
+  // phi_k of step i into step.proj (scaled by sqrt(eta_k)), added to the diagonal
+  void lower_phi(int i) {
+    const int K = (int)lower.size();
+    step.nproj = K;
+    if (!K) return;
+    step.proj.alloc((size_t)K * std::max<int64_t>(step.n, 1));
+    dev_zero(step.proj.p, (size_t)K * std::max<int64_t>(step.n, 1) * 8, st);
+    for (int k = 0; k < K; ++k) {
+      Lower& w = lower[k];
+      lower_x(w, i);
+      Enl ek = right_enl(P, i + 1, w.dims[i + 2], nullptr);
+      std::vector<OutBlk> outs;
+      std::vector<Triple> trs;
+      double* base = step.proj.p + (int64_t)k * step.n;
+      for (size_t m = 0; m < step.psi.sec.size(); ++m) {
+        const Sec& ms = step.psi.sec[m];
+        const int xm = w.X.find(ms), vm = w.V[i + 1].find(ms), em = ek.find(ms);
+        if (xm < 0 || vm < 0 || em < 0) continue;
+        for (const Piece& q : step.EY.pieces[m]) {
+          const Sec& b = dims[i + 2].sec[q.sub];
+          const int ob = w.OR[i + 2].find(b);
+          if (ob < 0) continue;
+          for (const Piece& qk : ek.pieces[em]) {
+            if (qk.n != q.n || !(w.dims[i + 2].sec[qk.sub] == b)) continue;
+            outs.push_back({base + step.off[m] + q.off, step.dx[m], dims[i + 2].dim[q.sub], step.dy[m]});
+            Triple t{};
+            t.blk = (int)outs.size() - 1;
+            t.a = w.X.at(xm);
+            t.lda = w.X.cols[xm];
+            t.K1 = w.X.cols[xm];
+            t.b = w.V[i + 1].at(vm) + qk.off;
+            t.ldb = w.V[i + 1].cols[vm];
+            t.K2 = w.dims[i + 2].dim[qk.sub];
+            t.c = w.OR[i + 2].at(ob);
+            t.ldc = w.OR[i + 2].cols[ob];
+            t.flags = TT_TRANS_C;
+            t.coef = std::sqrt(w.eta);
+            trs.push_back(t);
+          }
+        }
+      }
+      run_triples(outs, trs);
+    }
+    launch_add_squares(step.diag.p, step.proj.p, step.n, K, step.n, st);
+    dev_sync(st);
+  }
+  // y += sum_k (phi_k . x) phi_k (phi_k scaled by sqrt(eta_k)); x, y device vectors of the step
+  void add_projectors(const double* x, double* y) {
+    if (!step.nproj) return;
+    projc.ensure(64);
+    projpart.ensure(256 * 64);
+    launch_dots(step.proj.p, step.n, step.nproj, x, step.n, projc.p, projpart.p, st);
+    launch_combo_vec(step.proj.p, step.n, step.nproj, projc.p, 1.0, step.n, y, 1.0, st);
   }
 
   // ---- random initial MPS (section "DMRG" of the library description)
@@ -2448,6 +2783,7 @@ struct Engine {
     mps_ready = true;
     n_pass = 0;
     wd_prev = wd_pass = 0.0;
+    lower_rebuild();
   }
 
   // Build left blocks 0..i and right blocks L..i+2 from the stored tensors.
@@ -2525,6 +2861,7 @@ struct Engine {
     {
       PhaseTimer pt(t_phase[PH_DIAG]);
       build_diag();
+      lower_phi(i);
     }
     {
       PhaseTimer pt(t_phase[PH_GUESS]);
@@ -2952,8 +3289,15 @@ struct Engine {
 
   // ---- sigma on the prepared step: step.out = H_eff step.in (FP64, or with
   // FP32 operands and FP32 accumulation when f32)
-  void sigma_fixed(bool f32 = false) {
+  void sigma_fixed(bool f32 = false, bool proj = true) {
     if (step.p2_pending) fail(-1, "internal: sigma plan incomplete");
+    struct AddProj {  // the excited-state projectors, after the products
+      Engine& e;
+      bool on;
+      ~AddProj() noexcept(false) {
+        if (on && !std::uncaught_exceptions()) e.add_projectors(e.step.in.p, e.step.out.p);
+      }
+    } addp{*this, proj};
     if (f32) ensure_f32();
     const GemmList::Plan& p1 = f32 ? step.q1 : step.plan.p1;
     const GemmList::Plan& p2 = f32 ? step.q2 : step.plan.p2;
@@ -3015,6 +3359,7 @@ struct Engine {
   }
   void sigma_out(double* y, bool f32) {
     if (f32) launch_cvt_f2d(step.out.p, (const float*)step.out32.p, step.n, st);
+    add_projectors(step.in.p, step.out.p);
     dev_d2d(y, step.out.p, (size_t)step.n * 8, st);
   }
   // Pick the sigma plans' workgroups per CU by timing the prepared step:
@@ -3455,6 +3800,7 @@ struct Engine {
       dims[c] = sp.kept;
       U[i] = std::move(u);
       Lb[c] = renormalize(*step.X, U[i], dims[c], true);
+      for (Lower& w : lower) lower_m(w, i);
       cen.kind = C_BOND_R;
       cen.pos = c;
       cen.t = std::move(cc);
@@ -3490,6 +3836,7 @@ struct Engine {
       dims[c] = sp.kept;
       V[i + 1] = std::move(v);
       Rb[c] = renormalize(*step.Y, V[i + 1], dims[c], false);
+      for (Lower& w : lower) lower_or(w, c);
       cen.kind = C_BOND_L;
       cen.pos = c;
       cen.t = std::move(cc);
@@ -4222,6 +4569,7 @@ static void import_mps(Engine& E, const void* blob, size_t bytes) {
   E.mps_ready = true;
   E.n_pass = 0;
   E.wd_prev = E.wd_pass = 0.0;
+  E.lower_rebuild();
 }
 
 static void export_mps(Engine& E, std::vector<char>& out) {
@@ -4463,6 +4811,7 @@ int sadmrg_set_target(sadmrg_ctx* ctx, int N, int twoS, int irrep) {
     P.irrep = irrep;
     if (P.have_ints) P.fold();
     ctx->e.mps_ready = false;
+    ctx->e.lower_clear();  // lower states of another sector
     return 0;
   });
 }
@@ -4827,6 +5176,20 @@ int sadmrg_dmrgscf(sadmrg_ctx* ctx, int Lt, const int* orb_irrep, const int* cls
   });
 }
 
+int sadmrg_push_excitation(sadmrg_ctx* ctx, double eta) {
+  return guard(ctx, [&] {
+    ctx->e.lower_push(eta);
+    return 0;
+  });
+}
+
+int sadmrg_clear_excitations(sadmrg_ctx* ctx) {
+  return guard(ctx, [&] {
+    ctx->e.lower_clear();
+    return 0;
+  });
+}
+
 int sadmrg_get_energy(sadmrg_ctx* ctx, double* e_min, double* e_last, double* wdisc_max) {
   return guard(ctx, [&] {
     if (e_min) *e_min = ctx->e.emin;
@@ -4964,6 +5327,7 @@ int sadmrg_sigma_noalloc(sadmrg_ctx* ctx, const double* x, double* y) {
     if (S.i < 0 || !S.X) fail(SADMRG_EINVAL, "no prepared step");
     if (!x || !y) fail(SADMRG_EINVAL, "null vector");
     if (E.prec != 0) fail(SADMRG_EINVAL, "the allocation-free sigma is FP64: set precision mode 0");
+    if (!E.lower.empty()) fail(SADMRG_EINVAL, "the allocation-free sigma has no excited-state projectors");
     if (S.p2_pending) fail(SADMRG_EINVAL, "sigma plan incomplete");
     char* base = (char*)scratch_ptr(E.device);
     std::mutex* use = scratch_lock(E.device);

@@ -1844,4 +1844,22 @@ void launch_copy(double* dst, const double* src, int64_t n, Stream st) {
   check_launch("copy");
 }
 
+
+__global__ void add_squares_kernel(double* y, const double* V, int64_t ldv, int k, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v = y[i];
+    for (int j = 0; j < k; ++j) {
+      const double x = V[j * ldv + i];
+      v += x * x;
+    }
+    y[i] = v;
+  }
+}
+void launch_add_squares(double* y, const double* V, int64_t ldv, int k, int64_t n, Stream st) {
+  if (n <= 0 || k <= 0) return;
+  const int nb = (int)std::min<int64_t>(8192, (n + 255) / 256);
+  hipLaunchKernelGGL(add_squares_kernel, dim3(nb), dim3(256), 0, (hipStream_t)st, y, V, ldv, k, n);
+  check_launch("add_squares");
+}
+
 }  // namespace sadmrg
