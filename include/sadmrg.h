@@ -458,6 +458,21 @@ int sadmrg_debug_plan_stats(sadmrg_ctx* ctx, int64_t* out);
  * plus the input and output vectors) and the number of block products. */
 int sadmrg_sigma_counters(sadmrg_ctx* ctx, double* flops, double* bytes, int64_t* tasks);
 
+/* Method-work counter.  The enlarged operator blocks the sigma products
+ * multiply are dense (sector pair) blocks whose (sector, local state) piece
+ * pairs are partly structurally zero.  With the counter on (on = 1), each
+ * enlargement records its nonzero piece pairs and each prepared step counts
+ * the flops of its sigma products with those zero pieces skipped (each
+ * product in the cheaper of its two contraction orders); kept enlargements
+ * are not used meanwhile (they carry no piece lists), which slows the sweep,
+ * so turn it on for a counting sweep apart from timed ones.  Default off.
+ * sadmrg_stats_method returns, since the last sadmrg_stats_reset, the method
+ * flops and the performed flops (as sadmrg_stats) of the FP64 sigma calls on
+ * counted steps, and the prepared step's method flops (-1 if not counted).
+ * Errors: EINVAL. */
+int sadmrg_set_method_counter(sadmrg_ctx* ctx, int on);
+int sadmrg_stats_method(sadmrg_ctx* ctx, double* method_flops, double* performed_flops, double* step_method_flops);
+
 /* Accumulated timings and counts since the last reset: seconds in sigma
  * kernels, number of sigma calls, seconds of whole micro-iterations, sigma
  * flops, and seconds in renormalisation/enlargement kernels. */

@@ -1016,6 +1016,28 @@ class DMRG:
         E = RightEnl(P, 1, self.dims[2], keep=set(self.dims[1]))
         self.center = (0, {m: self._T0[m] @ self.V[1][m] for m in self._T0 if m in self.V[1]})
 
+    def build_blocks_at(self, i):
+        """Left blocks at bonds 0..i from U[0..i-1] and right blocks at bonds
+        L..i+2 from V[i+2..L-1] (for an MPS with its centre on (i, i+1))."""
+        P = self.P
+        L = P.L
+        lb = Block("L", 0, {(0, 0, 0): 1}, [])
+        lb.ops[("H",)] = zero_like(0, 0, 0, False)
+        for y in range(L):
+            lb.ops[("S", y)] = zero_like(1, 1, int(P.orb_irrep[y]), True)
+        self.Lblk[0] = lb
+        for c in range(1, i + 1):
+            E = LeftEnl(P, c, self.Lblk[c - 1].dims, keep=set(self.dims[c]))
+            self.Lblk[c] = renorm_left(enlarge_left(P, self.Lblk[c - 1], E), self.U[c - 1], self.dims[c])
+        rb = Block("R", L, {(P.N, P.twoS, P.irrep): 1}, [])
+        rb.ops[("H",)] = zero_like(0, 0, 0, False)
+        for x in range(L):
+            rb.ops[("S", x)] = zero_like(1, 1, int(P.orb_irrep[x]), True)
+        self.Rblk[L] = rb
+        for k in range(L - 1, i + 1, -1):
+            E = RightEnl(P, k, self.Rblk[k + 1].dims, keep=set(self.dims[k]))
+            self.Rblk[k] = renorm_right(enlarge_right(P, self.Rblk[k + 1], E), self.V[k], self.dims[k])
+
     # ----- one micro-iteration
     def enlarged(self, i):
         P = self.P
@@ -1237,6 +1259,36 @@ def project_lower(P, dm, w: LowerState, i, El, Er, secs):
 
 
 NOISE_STREAM = 0x4E4F << 40
+
+
+def random_mps_at(P: Problem, D: int, seed: int, i: int) -> "DMRG":
+    """A random MPS with its two-site centre on sites (i, i+1): the initial
+    right-normalised tensors V[i+2..L-1] of DMRG(P, D, seed), random
+    left-normalised tensors U[0..i-1] (orthonormal columns from the QR of
+    counter-generated entries) and a counter-generated two-site object.  No
+    blocks are built (build_blocks_at does that).  A deterministic input for
+    parity checks at a chosen step without any optimisation."""
+    dm = DMRG(P, D, seed=seed)
+    for c in range(i):
+        E = LeftEnl(P, c + 1, dm.dims[c], keep=set(dm.dims[c + 1]))
+        U, newd = {}, {}
+        for qi, m in enumerate(sorted(dm.dims[c + 1])):
+            if m not in E.dim:
+                continue
+            rows, k = E.dim[m], dm.dims[c + 1][m]
+            q, _ = np.linalg.qr(_mps_random(seed, (1 << 12) | c, qi, rows * k).reshape(rows, k))
+            r = min(rows, k)
+            U[m] = q[:, :r]
+            newd[m] = r
+        dm.U[c] = U
+        dm.dims[c + 1] = newd
+    El = LeftEnl(P, i + 1, dm.dims[i])
+    Er = RightEnl(P, i + 1, dm.dims[i + 2])
+    psi = {}
+    for qi, m in enumerate(sorted(set(El.dim) & set(Er.dim))):
+        psi[m] = _mps_random(seed, (1 << 13) | i, qi, El.dim[m] * Er.dim[m]).reshape(El.dim[m], Er.dim[m])
+    dm.center = (i, psi)
+    return dm
 
 
 def noise_values(seed, n_pass, i, n):

@@ -49,6 +49,8 @@ def load_library(path: str | None = None):
         "sadmrg_batch_sweep": (c_int, [P(c_vp), c_int, P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_solve": (c_int, [c_vp, c_int, P(c_int), P(c_dbl), P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_get_energy": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
+        "sadmrg_set_method_counter": (c_int, [c_vp, c_int]),
+        "sadmrg_stats_method": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
         "sadmrg_push_excitation": (c_int, [c_vp, c_dbl]),
         "sadmrg_clear_excitations": (c_int, [c_vp]),
         "sadmrg_rotate_integrals": (c_int, [c_int, P(c_dbl), P(c_dbl), P(c_dbl), P(c_dbl), P(c_dbl)]),
@@ -435,6 +437,16 @@ class SaDMRG:
         s = ctypes.c_double()
         self._chk(self.lib.sadmrg_debug_copy_probe(self.h, int(n), int(reps), ctypes.byref(s)))
         return s.value
+
+    def set_method_counter(self, on: bool):
+        self._chk(self.lib.sadmrg_set_method_counter(self.h, int(bool(on))))
+
+    def stats_method(self):
+        """(method flops, performed flops) of the counted FP64 sigma calls and
+        the prepared step's method flops (sadmrg_stats_method)."""
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._chk(self.lib.sadmrg_stats_method(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def stats_reset(self):
         self._chk(self.lib.sadmrg_stats_reset(self.h))

@@ -140,6 +140,7 @@ struct Problem {
   double e_const = 0.0;
   std::vector<double> h, eri, W;
   bool have_ints = false;
+  bool count_method = false;  // record nonzero piece pairs for the method-work counter
   int N = -1, twoS = 0, irrep = 0;
   double w(int p, int q, int r, int s) const { return W[(((size_t)p * L + q) * L + r) * L + s]; }
   // q^j_ab(r,s): 2 W_abrs - W_rbas (j = 0), W_rbas (j = 1)
@@ -381,6 +382,18 @@ struct Store {
   std::unordered_map<uint64_t, int> by_key;
   DBuf data;
   int64_t total = 0;
+  // structurally nonzero piece pairs of every block (kept only when the
+  // method-work counter is on): sorted by block start, then offsets
+  struct PieceRect {
+    int64_t bstart;
+    int roff, coff, rows, cols, ld;
+    bool operator<(const PieceRect& o) const {
+      return std::tie(bstart, roff, coff) < std::tie(o.bstart, o.roff, o.coff);
+    }
+    bool operator==(const PieceRect& o) const { return bstart == o.bstart && roff == o.roff && coff == o.coff; }
+  };
+  std::vector<PieceRect> pieces;
+  bool has_pieces = false;
 
   int layout(int tk, int dN, int dG) {
     auto key = std::make_tuple(tk, dN, dG);
@@ -640,6 +653,8 @@ static const int ENLARGE_HOST_THREADS = 16;
 
 struct Entry {
   int64_t dst;  // element offset in the enlarged store
+  int64_t bstart;  // element offset of the enlarged block it lies in
+  int roff, coff;  // its position in that block (a piece pair)
   int rows, cols, ld;
   GatherSrc src;
   const Term* term;  // the term that produced it (scale = term->coef * unit)
@@ -718,6 +733,9 @@ struct Materializer {
             const int cols_mk = E.dim[mk];
             Entry e;
             e.dst = Out.ops[outop].off + OL.eoff[blk] + (int64_t)offb * cols_mk + offk;
+            e.bstart = Out.ops[outop].off + OL.eoff[blk];
+            e.roff = offb;
+            e.coff = offk;
             e.rows = sub.dim[abra];
             e.cols = sub.dim[aket];
             e.ld = cols_mk;
@@ -730,6 +748,9 @@ struct Materializer {
               if (blk2 < 0) fail(-1, "internal: transpose block missing");
               Entry m;
               m.dst = Out.ops[outop].off + OL.eoff[blk2] + (int64_t)offk * E.dim[mb] + offb;
+              m.bstart = Out.ops[outop].off + OL.eoff[blk2];
+              m.roff = offk;
+              m.coff = offb;
               m.rows = sub.dim[aket];
               m.cols = sub.dim[abra];
               m.ld = E.dim[mb];
@@ -1143,6 +1164,16 @@ static void trace_enlarge(const Problem& P, Store& X, const Enl& E, bool left, S
   });
   size_t tot = 0;
   for (auto& v : per) tot += v.size();
+  if (P.count_method) {  // nonzero piece pairs of every enlarged block
+    std::vector<Store::PieceRect>& pr = out.pieces;
+    pr.clear();
+    pr.reserve(tot);
+    for (auto& v : per)
+      for (const Entry& e : v) pr.push_back({e.bstart, e.roff, e.coff, e.rows, e.cols, e.ld});
+    std::sort(pr.begin(), pr.end());
+    pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+    out.has_pieces = true;
+  }
   tr.mat.entries.clear();
   tr.mat.entries.reserve(tot);
   tr.mat.seg.assign(1, 0);
@@ -1160,6 +1191,23 @@ static std::unique_ptr<Store> enlarge(const Problem& P, Store& X, const Enl& E, 
   tr.out->allocate(st);
   tr.mat.run(*tr.out, st);
   if (n_entries) *n_entries += tr.mat.n_entries;
+  if (tr.out->has_pieces) {  // keep the piece pairs that hold a nonzero value
+    std::vector<Store::PieceRect>& pr = tr.out->pieces;
+    std::vector<RectDesc> rd;
+    rd.reserve(pr.size());
+    for (const auto& q : pr) rd.push_back({q.bstart + (int64_t)q.roff * q.ld + q.coff, q.rows, q.cols, q.ld});
+    DArr<RectDesc> d_rd;
+    d_rd.put(rd, st);
+    DBuf fl;
+    fl.alloc(pr.size() / 8 + 1);
+    launch_rects_nonzero(tr.out->data.p, d_rd.p, (int)rd.size(), (unsigned char*)fl.p, st);
+    std::vector<unsigned char> h(pr.size());
+    dev_d2h(h.data(), fl.p, h.size(), st);
+    size_t w = 0;
+    for (size_t q = 0; q < pr.size(); ++q)
+      if (h[q]) pr[w++] = pr[q];
+    pr.resize(w);
+  }
   dev_sync(st);  // scratch combinations are released on return
   return std::move(tr.out);
 }
@@ -1559,6 +1607,7 @@ struct Step {
   GemmList g2;
   bool p2_pending = false;
   double flops = 0.0, bytes = 0.0;
+  double method_flops = -1.0;  // with structurally zero piece pairs skipped (< 0: not counted)
   int64_t ntasks = 0;
   std::vector<std::array<int, 5>> shapes;  // per tile task: rows, K1, K2, cols, flags
   DBuf proj;                     // projection vectors of the lower states (excited-state solves)
@@ -1713,6 +1762,9 @@ struct Engine {
   double t_pass1 = 0, t_pass2 = 0, f_pass1 = 0, f_pass2 = 0, b_pass1 = 0, b_pass2 = 0;
   int64_t n_pass1 = 0, n_pass2 = 0;
   double t_sigma32 = 0, f_sigma32 = 0;
+  // the method-work counter: method flops and performed flops of the FP64
+  // sigma calls on steps where it was on
+  double f_method = 0, f_method_perf = 0;
   int64_t n_sigma32 = 0;
   // host wall seconds of the parts of a micro-iteration outside Davidson
   enum { PH_ENLARGE, PH_TASKS, PH_PLAN, PH_DIAG, PH_GUESS, PH_SVD, PH_RENORM, PH_N };
@@ -1756,6 +1808,7 @@ struct Engine {
   std::vector<EnlCache> cacheX, cacheY;
   std::vector<std::pair<int, int>> cache_fifo;  // (side 0 = X / 1 = Y, site), oldest first
   bool enl_cache_on = true;
+  bool enl_cache_on_saved = true;  // the setting while the method-work counter is on
 
   Engine() = default;
   Engine(const Engine&) = delete;
@@ -2915,6 +2968,60 @@ struct Engine {
     return ts;
   }
 
+  // Flops of the sigma products with the structurally zero piece pairs of
+  // the enlarged operator blocks skipped: a block of an enlarged operator
+  // holds (sector, local state) piece pairs, and only those a blocking term
+  // writes are nonzero.  For out += c op(A) B op(C), with nzA / nzC the
+  // nonzero areas of op(A) / op(C), Rnz the rows of op(A) that hold a
+  // nonzero piece and Cnz the columns of op(C): left first 2 nzA K2 + 2 Rnz
+  // nzC, right first 2 K1 nzC + 2 nzA Cnz, the cheaper of the two (the
+  // identity factors: one GEMM).
+  double method_flops(const std::vector<OutBlk>& outs, const std::vector<Triple>& trs) const {
+    const Store &X = *step.X, &Y = *step.Y;
+    struct Shape {
+      double area = 0.0;
+      int rows_nz = 0, cols_nz = 0;  // of the stored block
+    };
+    auto shape = [](const Store& S, const double* p, int rows, int cols) {
+      Shape sh;
+      const int64_t b0 = p - S.data.p;
+      Store::PieceRect key{b0, -1, -1, 0, 0};
+      auto it = std::lower_bound(S.pieces.begin(), S.pieces.end(), key);
+      std::vector<char> r(rows, 0), c(cols, 0);
+      for (; it != S.pieces.end() && it->bstart == b0; ++it) {
+        sh.area += (double)it->rows * it->cols;
+        for (int q = 0; q < it->rows; ++q) r[it->roff + q] = 1;
+        for (int q = 0; q < it->cols; ++q) c[it->coff + q] = 1;
+      }
+      for (char v : r) sh.rows_nz += v;
+      for (char v : c) sh.cols_nz += v;
+      return sh;
+    };
+    double f = 0.0;
+    for (const Triple& t : trs) {
+      const int R = outs[t.blk].rows, C = outs[t.blk].cols;
+      Shape a, c;
+      int aRnz = 0, cCnz = 0;
+      if (!(t.flags & TT_IDENT_A)) {  // op(A) is R x K1
+        const bool tr = t.flags & TT_TRANS_A;
+        a = shape(X, t.a, tr ? t.K1 : R, tr ? R : t.K1);
+        aRnz = tr ? a.cols_nz : a.rows_nz;
+      }
+      if (!(t.flags & TT_IDENT_C)) {  // op(C) is K2 x C
+        const bool tr = t.flags & TT_TRANS_C;
+        c = shape(Y, t.c, tr ? C : t.K2, tr ? t.K2 : C);
+        cCnz = tr ? c.rows_nz : c.cols_nz;
+      }
+      if (t.flags & TT_IDENT_C)
+        f += 2.0 * a.area * C;
+      else if (t.flags & TT_IDENT_A)
+        f += 2.0 * R * c.area;
+      else
+        f += std::min(2.0 * a.area * t.K2 + 2.0 * aRnz * c.area, 2.0 * t.K1 * c.area + 2.0 * a.area * cCnz);
+    }
+    return f;
+  }
+
   void build_sigma_tasks() {
     auto tt0 = std::chrono::steady_clock::now();
     Store &X = *step.X, &Y = *step.Y;
@@ -3039,6 +3146,7 @@ struct Engine {
     step.flops = step.plan.flops;
     step.bytes = bytes;
     step.ntasks = (int64_t)trs.size();
+    step.method_flops = (X.has_pieces && Y.has_pieces) ? method_flops(outs, trs) : -1.0;
     step.shapes.clear();
     for (auto& t : trs) step.shapes.push_back({outs[t.blk].rows, t.K1, t.K2, outs[t.blk].cols, t.flags});
   }
@@ -3327,6 +3435,10 @@ struct Engine {
       return;
     }
     t_sigma += t1 + t2 + t3;
+    if (step.method_flops >= 0.0) {
+      f_method += step.method_flops;
+      f_method_perf += step.flops;
+    }
     t_pass1 += t1;
     t_pass2 += t2;
     ++n_sigma;
@@ -5190,6 +5302,30 @@ int sadmrg_clear_excitations(sadmrg_ctx* ctx) {
   });
 }
 
+int sadmrg_set_method_counter(sadmrg_ctx* ctx, int on) {
+  return guard(ctx, [&] {
+    auto& E = ctx->e;
+    if (on && !E.P.count_method) {  // kept enlargements carry no piece lists
+      E.enl_cache_on_saved = E.enl_cache_on;
+      E.enl_cache_on = false;
+      E.clear_enl_cache();
+    }
+    if (!on && E.P.count_method) E.enl_cache_on = E.enl_cache_on_saved;
+    E.P.count_method = on != 0;
+    E.step.i = -1;
+    return 0;
+  });
+}
+
+int sadmrg_stats_method(sadmrg_ctx* ctx, double* method_flops, double* performed_flops, double* step_method_flops) {
+  return guard(ctx, [&] {
+    if (method_flops) *method_flops = ctx->e.f_method;
+    if (performed_flops) *performed_flops = ctx->e.f_method_perf;
+    if (step_method_flops) *step_method_flops = ctx->e.step.method_flops;
+    return 0;
+  });
+}
+
 int sadmrg_get_energy(sadmrg_ctx* ctx, double* e_min, double* e_last, double* wdisc_max) {
   return guard(ctx, [&] {
     if (e_min) *e_min = ctx->e.emin;
@@ -5592,6 +5728,7 @@ int sadmrg_stats_reset(sadmrg_ctx* ctx) {
     E.t_sigma32 = E.f_sigma32 = 0;
     E.n_sigma32 = 0;
     E.n_sigma = 0;
+    E.f_method = E.f_method_perf = 0;
     for (double& t : E.t_phase) t = 0.0;
     return 0;
   });

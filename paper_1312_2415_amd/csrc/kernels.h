@@ -262,6 +262,13 @@ void launch_scalars(const double* const* src, int n, double* dst, Stream st);
 void launch_fill_uniform(double* p, int64_t n, uint64_t seed, uint64_t stream, Stream st);
 // y[i] += a * x[i], i < n
 void launch_axpy(double* y, const double* x, double a, int64_t n, Stream st);
+// flag[r] = 1 if the (rows x cols, leading dim ld) sub-block at base + off
+// holds a nonzero value, else 0, r < n
+struct RectDesc {
+  int64_t off;
+  int rows, cols, ld;
+};
+void launch_rects_nonzero(const double* base, const RectDesc* rects, int n, unsigned char* flag, Stream st);
 // y[i] += sum_{j < k} V[j * ldv + i]^2, i < n
 void launch_add_squares(double* y, const double* V, int64_t ldv, int k, int64_t n, Stream st);
 // y[i] *= a, i < n

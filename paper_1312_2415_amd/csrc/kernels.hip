@@ -1862,4 +1862,28 @@ void launch_add_squares(double* y, const double* V, int64_t ldv, int k, int64_t 
   check_launch("add_squares");
 }
 
+
+__global__ void rects_nonzero_kernel(const double* base, const RectDesc* rects, int n, unsigned char* flag) {
+  const int r = blockIdx.x;
+  if (r >= n) return;
+  const RectDesc d = rects[r];
+  int any = 0;
+  const int64_t tot = (int64_t)d.rows * d.cols;
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int64_t rr = e / d.cols, cc = e % d.cols;
+    if (base[d.off + rr * d.ld + cc] != 0.0) any = 1;
+  }
+  __shared__ int hit;
+  if (threadIdx.x == 0) hit = 0;
+  __syncthreads();
+  if (any) atomicOr(&hit, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) flag[r] = (unsigned char)hit;
+}
+void launch_rects_nonzero(const double* base, const RectDesc* rects, int n, unsigned char* flag, Stream st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(rects_nonzero_kernel, dim3(n), dim3(256), 0, (hipStream_t)st, base, rects, n, flag);
+  check_launch("rects_nonzero");
+}
+
 }  // namespace sadmrg

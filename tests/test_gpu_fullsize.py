@@ -113,3 +113,36 @@ def test_l24_d500_sweeps_and_identities():
     assert np.abs(g1 - g1.T).max() <= 1e-12
     assert e >= es[-1] - 1e-6  # the final state's energy is not below the sweep minimum
     g.close()
+
+
+def test_config2_middle_step_sigma_matches_the_oracle_golden():
+    """L = 24, N = 12, D2h, D = 500 (the survey's oracle-GPU parity
+    configuration): sigma at the middle step on the same deterministic MPS
+    (oracle.sadmrg.random_mps_at, rebuilt here) against the oracle's values
+    stored by tests/golden/make_cfg2_sigma.py: 512 sampled entries, the norm
+    and a projection, within 1e-10 relative."""
+    import json
+    import os
+
+    from paper_1312_2415_amd import SaDMRG
+    from oracle import sadmrg as sd
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "cfg2_mid_sigma.json")))
+    I = make_integrals(gold["L"], "D2h", gold["seed_integrals"])
+    P = sd.Problem(I.h, I.eri, gold["N"], gold["twoS"], gold["irrep"], I.orb_irrep)
+    dm = sd.random_mps_at(P, gold["D"], gold["seed_mps"], gold["step"])
+    g = SaDMRG(gold["L"], 8, I.orb_irrep, device=0)
+    g.set_integrals(I.h, I.eri)
+    g.set_target(gold["N"], gold["twoS"], gold["irrep"])
+    g.mps_import(sd.export_blob(dm))
+    g.prepare_step()
+    desc, n = g.psi_layout()
+    assert n == gold["n"]
+    assert [list(map(int, d[:5])) for d in desc] == gold["sectors"]
+    x = np.random.default_rng(gold["x_seed"]).normal(size=n)
+    got = g.sigma(x)
+    g.close()
+    scale = gold["max_abs_sigma"]
+    assert np.abs(got[gold["index"]] - np.array(gold["value"])).max() <= 1e-10 * scale
+    assert abs(np.linalg.norm(got) - gold["sigma_norm"]) <= 1e-10 * gold["sigma_norm"]
+    r = np.random.default_rng(gold["r_seed"]).normal(size=n)
+    assert abs(r @ got - gold["r_dot_sigma"]) <= 1e-10 * gold["sigma_norm"] * np.sqrt(n)
