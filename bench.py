@@ -79,82 +79,114 @@ def stored_traffic(pass_name: str):
     return ent.get("fetch_bytes", 0.0) + ent.get("write_bytes", 0.0)
 
 
-def cpu_baseline(seconds: float, L: int, N: int, twoS: int, irrep: int, seed: int, D: int):
-    """The oracle's sigma rate on a bounded sample of the same workload.
+def sigma_flops_oracle(H):
+    """Flops of the oracle's H_eff application counted as the GPU path counts
+    them: dense enlarged-block triple products, each in the cheaper of its
+    two contraction orders (the oracle's own blocks are dense as well)."""
+    f = 0.0
+    for coef, Xo, Yo, hc in H.terms:
+        mult = 2.0 if hc else 1.0
+        if Yo is None:
+            for (mb, mk), M in Xo.blocks.items():
+                if mb in H.dy and mk in H.dy:
+                    f += 2.0 * M.shape[0] * M.shape[1] * H.dy[mk]
+            continue
+        if Xo is None:
+            for (mb, mk), M in Yo.blocks.items():
+                if mb in H.dx and mk in H.dx:
+                    f += 2.0 * H.dx[mk] * M.shape[1] * M.shape[0]
+            continue
+        for (mb, mk), MX in Xo.blocks.items():
+            if mb not in H.dy or mk not in H.dy or (mb, mk) not in Yo.blocks:
+                continue
+            R, K1, K2, C = H.dx[mb], H.dx[mk], H.dy[mk], H.dy[mb]
+            f += mult * min(2.0 * R * K2 * (K1 + C), 2.0 * K1 * C * (K2 + R))
+    return f
 
-    Sample: the oracle DMRG on the same integrals and target with bond
-    dimension D (boundary blocks built), then micro-iterations of the first
-    left-to-right pass until `seconds` of sigma time; flops are counted with the
-    GPU path's definition (dense enlarged-block triple products, each in the
-    cheaper of its two contraction orders).
-    """
-    import numpy as np
+
+def physical_cores():
+    """Physical cores of the host (lscpu), or None."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu", "-p=CORE,SOCKET"], capture_output=True, text=True, timeout=10).stdout
+        return len({line for line in out.splitlines() if line and not line.startswith("#")}) or None
+    except Exception:
+        return None
+
+
+def cpu_baseline(seconds: float, L: int, N: int, twoS: int, irrep: int, seed: int, D: int, step: int):
+    """The oracle and the GPU on the same sigma product: the middle step of
+    the headline shape (L orbitals, N electrons, D_SU(2) = D, D2h, the same
+    integrals), on the deterministic MPS oracle.sadmrg.random_mps_at(P, D, 3,
+    step) that both sides build (random left- and right-normalised tensors,
+    equal split of D over the sectors).  The oracle builds every block of the
+    chain (not timed), then applies H_eff until `seconds` of sigma time with
+    all of its BLAS threads, and once more on one thread; the GPU imports the
+    same MPS and times its sigma on the same step.  Flops: the GPU path's
+    definition, counted from the oracle's blocks."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import sadmrg as sd
+    from paper_1312_2415_amd import SaDMRG
     from synth.integrals import make_integrals
 
     I = make_integrals(L, "D2h", seed)
     P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
-    dm = sd.DMRG(P, D, seed=3)
-    dm.build_boundaries()
-    acc = {"t": 0.0, "f": 0.0, "n": 0}
-    orig_apply = sd.Heff.apply
-
-    def flops_of(H):
-        f = 0.0
-        for coef, Xo, Yo, hc in H.terms:
-            mult = 2.0 if hc else 1.0
-            if Yo is None:
-                for (mb, mk), M in Xo.blocks.items():
-                    if mb in H.dy and mk in H.dy:
-                        f += 2.0 * M.shape[0] * M.shape[1] * H.dy[mk]
-                continue
-            if Xo is None:
-                for (mb, mk), M in Yo.blocks.items():
-                    if mb in H.dx and mk in H.dx:
-                        f += 2.0 * H.dx[mk] * M.shape[1] * M.shape[0]
-                continue
-            for (mb, mk), MX in Xo.blocks.items():
-                if mb not in H.dy or mk not in H.dy or (mb, mk) not in Yo.blocks:
-                    continue
-                R, K1, K2, C = H.dx[mb], H.dx[mk], H.dy[mk], H.dy[mb]
-                # the cheaper contraction order, as the GPU path chooses it
-                f += mult * min(2.0 * R * K2 * (K1 + C), 2.0 * K1 * C * (K2 + R))
-        return f
-
-    def timed_apply(self, psi):
-        if not hasattr(self, "dx"):
-            self.dx = {m: v.shape[0] for m, v in psi.items()}
-            self.dy = {m: v.shape[1] for m, v in psi.items()}
-            self._f = flops_of(self)
+    t0 = time.perf_counter()
+    dm = sd.random_mps_at(P, D, 3, step)
+    dm.build_blocks_at(step)
+    El, Er, Xe, Ye, secs = dm.enlarged(step)
+    H = sd.Heff(P, Xe, Ye, secs)
+    shapes = {m: (El.dim[m], Er.dim[m]) for m in secs}
+    H.dx = {m: shapes[m][0] for m in secs}
+    H.dy = {m: shapes[m][1] for m in secs}
+    flops = sigma_flops_oracle(H)
+    t_setup = time.perf_counter() - t0
+    n = sum(a * b for a, b in shapes.values())
+    x = np.random.default_rng(7).normal(size=n)
+    psi = sd.unflatten(x, shapes, secs)
+    print(f"cpu baseline: oracle blocks of L={L} D={D} step {step} built in {t_setup:.0f}s, |psi| = {n}, "
+          f"{flops:.3e} flop per sigma", file=sys.stderr, flush=True)
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    calls, t_all = 0, 0.0
+    while calls < 1 or t_all < seconds:
         t = time.perf_counter()
-        out = orig_apply(self, psi)
-        acc["t"] += time.perf_counter() - t
-        acc["f"] += self._f
-        acc["n"] += 1
-        return out
-
-    sd.Heff.apply = timed_apply
-    steps = 0
+        y_ref = sd.flatten(H.apply(psi), secs)
+        t_all += time.perf_counter() - t
+        calls += 1
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        H.apply(psi)
+        t_one = time.perf_counter() - t
+    print(f"cpu baseline: {t_all / calls:.2f}s per sigma on {threads} threads, {t_one:.2f}s on one",
+          file=sys.stderr, flush=True)
+    g = SaDMRG(L, 8, I.orb_irrep, device=0)
     try:
-        for i in range(0, L - 2):
-            dm.micro(i, D, "right")
-            steps += 1
-            if acc["t"] >= seconds:
-                break
+        g.set_integrals(I.h, I.eri)
+        g.set_target(N, twoS, irrep)
+        g.mps_import(sd.export_blob(dm))
+        g.prepare_step()
+        y = g.sigma(x)
+        err = float(np.abs(y - y_ref).max() / np.abs(y_ref).max())
+        gflops, _, _ = g.sigma_counters()
+        g.stats_reset()
+        for _ in range(10):  # kernel time from the library's HIP events (host copies outside)
+            g.sigma(x)
+        st = g.stats()
+        t_gpu = st["t_sigma"] / max(st["n_sigma"], 1)
     finally:
-        sd.Heff.apply = orig_apply
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        cores = 1
-    rate = acc["f"] / max(acc["t"], 1e-12) / 1e12
-    return {"value": rate, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"oracle sigma on L={L} N={N} 2S={twoS} D2h, D={D}: {acc['n']} sigma calls over the first "
-                      f"{steps} micro-iterations of a left-to-right pass ({acc['t']:.1f} s of sigma time); "
-                      f"flops counted as for the GPU path", "sigma_calls": acc["n"],
-            "sigma_seconds": acc["t"]}
+        g.close()
+    rate = flops / (t_all / calls) / 1e12
+    return {"value": rate, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle sigma at the middle step (i={step}) of L={L} N={N} 2S={twoS} D2h D_SU(2)={D} "
+                      f"on oracle.sadmrg.random_mps_at(seed 3): {calls} call(s), {t_all:.1f}s of sigma time on "
+                      f"{threads} BLAS threads (block building {t_setup:.0f}s, not timed) and one call on one "
+                      f"thread; flops counted as for the GPU path",
+            "oracle_seconds_per_sigma": t_all / calls, "oracle_seconds_per_sigma_one_thread": t_one,
+            "oracle_tflops_one_thread": flops / t_one / 1e12, "physical_cores": physical_cores(),
+            "flops_per_sigma": flops, "gpu_flops_per_sigma": gflops, "psi_length": n,
+            "gpu_ms_per_sigma_same_step": 1e3 * t_gpu, "gpu_speedup_same_step": (t_all / calls) / t_gpu,
+            "gpu_vs_oracle_sigma_max_rel_diff": err}
 
 
 def batch_workload(n, seed):
@@ -230,103 +262,137 @@ def batch_bench(n, seed, prec, mixed_tol):
 ROOT_TARGETS = [(2 * s, ir) for s in (0, 1, 2) for ir in (0, 1, 2, 3)]  # (2S, irrep) of the twelve roots
 
 
-def roots_bench(k, L, N, D, seed, warm, dav_tol, mixed_tol, refine=1):
-    """Roots 0, 12/k, 2*12/k, ... of the twelve (one GPU's share when they are
-    dealt round-robin over 12/k GPUs) swept in lockstep (sadmrg_batch_sweep):
-    `warm` FP64 lockstep sweeps from random MPS, then one timed FP64 lockstep
-    sweep, the same sweep of each root on its own, and one timed mixed
-    lockstep sweep (FP32 sigma + FP64 refinement) from the same states."""
+def roots_bench(group, L, N, D, seed, warm, dav_tol, mixed_tol, refine=1):
+    """All twelve roots of the headline problem, in separate (S, irrep)
+    sectors (S in {0, 1, 2} times four irreps), swept on one GPU in
+    sequential lockstep groups of `group` (sadmrg_batch_sweep; a group fills
+    most of the 288 GB).  Per group: `warm` FP64 lockstep sweeps from random
+    MPS, one timed FP64 lockstep sweep, then from the same states one timed
+    FP32 and one timed BF16x3 lockstep sweep (FP64 refinement), with per-root
+    |dE| and RDM errors against the FP64 sweep; the first group also sweeps
+    its roots one after another in FP64 for the lockstep speedup."""
     from paper_1312_2415_amd import SaDMRG
     from paper_1312_2415_amd.binding import batch_sweep, device_memory
     from synth.integrals import make_integrals
-    if k < 1 or 12 % k:
-        raise ValueError("roots: k must divide 12")
-    targets = ROOT_TARGETS[::12 // k]
+    if group < 1 or 12 % group:
+        raise ValueError("roots: the group size must divide 12")
     I = make_integrals(L, "D2h", seed)
-    gs = []
-    try:
-        for j, (twoS, irrep) in enumerate(targets):
-            g = SaDMRG(L, 8, I.orb_irrep, device=0)
-            gs.append(g)
-            g.set_integrals(I.h, I.eri)
-            g.set_target(N, twoS, irrep)
-            g.set_seed(seed + 17 * j)
-            g.set_davidson(dav_tol, 32, 100)
-            g.init_mps(D)
-        for w in range(warm):
+    per, t64s, t32s, tb3s, fl64, tt64, fl32, tt32, flb3, ttb3 = [], [], [], [], 0, 0, 0, 0, 0, 0
+    tsep = t64_first = None
+    mem_used = 0.0
+    for g0 in range(0, 12, group):
+        targets = ROOT_TARGETS[g0:g0 + group]
+        gs = []
+        try:
+            for j, (twoS, irrep) in enumerate(targets):
+                g = SaDMRG(L, 8, I.orb_irrep, device=0)
+                gs.append(g)
+                g.set_integrals(I.h, I.eri)
+                g.set_target(N, twoS, irrep)
+                g.set_seed(seed + 17 * (g0 + j))
+                g.set_davidson(dav_tol, 32, 100)
+                g.init_mps(D)
+            for w in range(warm):
+                t = time.perf_counter()
+                batch_sweep(gs, D)
+                print(f"roots {targets}: warm-up lockstep sweep {w + 1}/{warm} {time.perf_counter() - t:.1f}s",
+                      file=sys.stderr, flush=True)
+            blobs = [g.mps_export() for g in gs]
+            n0 = [len(g.trace()) for g in gs]
             t = time.perf_counter()
-            batch_sweep(gs, D)
-            print(f"roots: warm-up lockstep sweep {w + 1}/{warm} {time.perf_counter() - t:.1f}s", file=sys.stderr,
-                  flush=True)
-        blobs = [g.mps_export() for g in gs]
-        n0 = [len(g.trace()) for g in gs]
-        t = time.perf_counter()
-        e64, st64, _ = batch_sweep(gs, D)
-        t64 = time.perf_counter() - t
-        free, total = device_memory(0)
-        tr64 = [np.array(g.trace()[n:]) for g, n in zip(gs, n0)]
-        print(f"roots: FP64 lockstep sweep {t64:.2f}s", file=sys.stderr, flush=True)
-        r64 = [g.rdm() for g in gs]
-        t = time.perf_counter()
-        for g, b in zip(gs, blobs):
-            g.mps_import(b)
-            g.sweep(D)
-        tsep = time.perf_counter() - t
-        print(f"roots: separate FP64 sweeps {tsep:.2f}s", file=sys.stderr, flush=True)
-        n1 = []
-        for g, b in zip(gs, blobs):
-            g.set_precision(1, mixed_tol)
-            g.set_refinement(refine)
-            g.mps_import(b)
-            n1.append(len(g.trace()))
-        t = time.perf_counter()
-        e32, st32, _ = batch_sweep(gs, D)
-        t32 = time.perf_counter() - t
-        tr32 = [np.array(g.trace()[n:]) for g, n in zip(gs, n1)]
-        print(f"roots: mixed lockstep sweep {t32:.2f}s", file=sys.stderr, flush=True)
-        r32 = [g.rdm() for g in gs]
-        per = []
-        for j, (twoS, irrep) in enumerate(targets):
-            same = len(tr32[j]) == len(tr64[j]) and len(tr64[j]) > 0
-            per.append({"twoS": twoS, "irrep": irrep, "energy_fp64": e64[j], "energy_mixed": e32[j],
-                        "abs_dE": abs(e32[j] - e64[j]),
-                        "max_abs_dE_per_micro_iteration": float(np.abs(tr32[j] - tr64[j]).max()) if same else None,
-                        "rdm_max_abs_error": {"gamma": float(np.abs(r32[j][0] - r64[j][0]).max()),
-                                              "Gamma": float(np.abs(r32[j][1] - r64[j][1]).max())}})
-        f64 = st64["flops_sigma"] / max(st64["t_sigma"], 1e-12) / 1e12
-        f32 = st32["flops_sigma32"] / max(st32["t_sigma32"], 1e-12) / 1e12
-        return {
-            "workload": f"roots of L={L} N={N} D2h D_SU(2)={D} (seed {seed}): (2S, irrep) in "
-                        f"{[list(t) for t in targets]}, the share of one GPU when the twelve roots "
-                        f"(S in {{0,1,2}} x irreps 0..3) are dealt round-robin to {12 // k} GPUs",
-            "roots": k, "warmup_lockstep_sweeps": warm, "fp64_refinement_steps": refine,
-            "s_per_lockstep_sweep_fp64": t64,
-            "s_per_separate_sweeps_fp64": tsep,
-            "s_per_lockstep_sweep_mixed": t32,
-            "speedup_mixed_lockstep_vs_fp64_lockstep": t64 / t32,
-            "speedup_mixed_lockstep_vs_fp64_separate": tsep / t32,
-            "sigma_tflops_fp64_lockstep": f64,
-            "sigma_roofline_frac_fp64": f64 / FP64_MFMA_PEAK,
-            "sigma_tflops_fp32_mixed": f32,
-            "sigma_roofline_frac_fp32": f32 / FP32_MFMA_PEAK,
-            "max_abs_dE": max(r["abs_dE"] for r in per),
-            "max_rdm_abs_error": max(max(r["rdm_max_abs_error"].values()) for r in per),
-            "device_memory_used_GiB": (total - free) / 2**30,
-            "per_root": per,
-        }
-    finally:
-        for g in gs:
-            g.close()
+            e64, st64, _ = batch_sweep(gs, D)
+            t64 = time.perf_counter() - t
+            free, total = device_memory(0)
+            mem_used = max(mem_used, (total - free) / 2**30)
+            tr64 = [np.array(g.trace()[n:]) for g, n in zip(gs, n0)]
+            r64 = [g.rdm() for g in gs]
+            print(f"roots {targets}: FP64 lockstep sweep {t64:.2f}s", file=sys.stderr, flush=True)
+            t64s.append(t64)
+            fl64 += st64["flops_sigma"]
+            tt64 += st64["t_sigma"]
+            if g0 == 0:
+                t = time.perf_counter()
+                for g, b in zip(gs, blobs):
+                    g.mps_import(b)
+                    g.sweep(D)
+                tsep = time.perf_counter() - t
+                t64_first = t64
+                print(f"roots {targets}: separate FP64 sweeps {tsep:.2f}s", file=sys.stderr, flush=True)
+            res = {}
+            for mode in (1, 2):
+                n1 = []
+                for g, b in zip(gs, blobs):
+                    g.set_precision(mode, mixed_tol)
+                    g.set_refinement(refine)
+                    g.mps_import(b)
+                    n1.append(len(g.trace()))
+                t = time.perf_counter()
+                em, stm, _ = batch_sweep(gs, D)
+                tm = time.perf_counter() - t
+                trm = [np.array(g.trace()[n:]) for g, n in zip(gs, n1)]
+                rm = [g.rdm() for g in gs]
+                res[mode] = (em, trm, rm, tm)
+                print(f"roots {targets}: {'FP32' if mode == 1 else 'BF16x3'} lockstep sweep {tm:.2f}s",
+                      file=sys.stderr, flush=True)
+                if mode == 1:
+                    t32s.append(tm)
+                    fl32 += stm["flops_sigma32"]
+                    tt32 += stm["t_sigma32"]
+                else:
+                    tb3s.append(tm)
+                    flb3 += stm["flops_sigma32"]
+                    ttb3 += stm["t_sigma32"]
+            for j, (twoS, irrep) in enumerate(targets):
+                rec = {"twoS": twoS, "irrep": irrep, "energy_fp64": e64[j]}
+                for mode, key in ((1, "fp32"), (2, "bf16x3")):
+                    em, trm, rm, _ = res[mode]
+                    same = len(trm[j]) == len(tr64[j]) and len(tr64[j]) > 0
+                    rec[key] = {"energy": em[j], "abs_dE": abs(em[j] - e64[j]),
+                                "max_abs_dE_per_micro_iteration":
+                                    float(np.abs(trm[j] - tr64[j]).max()) if same else None,
+                                "rdm_max_abs_error": {"gamma": float(np.abs(rm[j][0] - r64[j][0]).max()),
+                                                      "Gamma": float(np.abs(rm[j][1] - r64[j][1]).max())}}
+                per.append(rec)
+        finally:
+            for g in gs:
+                g.close()
+
+    def worst(key, f):
+        return max(f(r[key]) for r in per)
+
+    out = {
+        "workload": f"the twelve roots of L={L} N={N} D2h D_SU(2)={D} (seed {seed}): (2S, irrep) in "
+                    f"{[list(t) for t in ROOT_TARGETS]}, one GPU, lockstep groups of {group}",
+        "roots": 12, "group": group, "warmup_lockstep_sweeps": warm, "fp64_refinement_steps": refine,
+        "s_per_lockstep_sweep_fp64": t64s, "s_per_lockstep_sweep_fp32": t32s,
+        "s_per_lockstep_sweep_bf16x3": tb3s,
+        "s_all_twelve_fp64": sum(t64s), "s_all_twelve_fp32": sum(t32s), "s_all_twelve_bf16x3": sum(tb3s),
+        "speedup_fp32_vs_fp64": sum(t64s) / sum(t32s), "speedup_bf16x3_vs_fp64": sum(t64s) / sum(tb3s),
+        "first_group_s_separate_fp64": tsep, "first_group_lockstep_speedup_fp64": tsep / t64_first,
+        "sigma_tflops_fp64": fl64 / max(tt64, 1e-12) / 1e12,
+        "sigma_tflops_fp32": fl32 / max(tt32, 1e-12) / 1e12,
+        "sigma_tflops_bf16x3": flb3 / max(ttb3, 1e-12) / 1e12,
+        "device_memory_used_GiB": mem_used,
+        "max_abs_dE": {"fp32": worst("fp32", lambda r: r["abs_dE"]), "bf16x3": worst("bf16x3", lambda r: r["abs_dE"])},
+        "max_rdm_abs_error": {k: worst(k, lambda r: max(r["rdm_max_abs_error"].values()))
+                              for k in ("fp32", "bf16x3")},
+        "per_root": per,
+    }
+    out["target_met"] = {k: bool(out["max_abs_dE"][k] <= 1e-6 and out["max_rdm_abs_error"][k] <= 1e-5)
+                         for k in ("fp32", "bf16x3")}
+    return out
 
 
-def grad_bench(L, N, D, seed, warm, n_orbits, tau):
+def grad_bench(L, N, D, seed, warm, n_orbits, tau, n_dir=200):
     """Energy adjoint at the differentiation configuration (L orbitals, N
     electrons, singlet Ag, D2h): the spin-summed 1- and 2-RDM of the MPS after
     `warm` sweeps at D, as dE/dh and dE/d(ij|kl), against central differences
     of E = <psi|H|psi> for that same frozen MPS along symmetry-allowed integral
     orbits (every evaluation rebuilds all renormalised operators from the MPS
-    with the shifted integrals).  At fixed psi, E is linear in the integrals,
-    so the difference quotient is exact up to rounding."""
+    with the shifted integrals), and along one direction that moves `n_dir`
+    random symmetry-allowed entries (with their symmetry partners) at once.
+    At fixed psi, E is linear in the integrals, so the difference quotient is
+    exact up to rounding."""
     from paper_1312_2415_amd import SaDMRG
     from synth.integrals import make_integrals
     I = make_integrals(L, "D2h", seed)
@@ -381,8 +447,43 @@ def grad_bench(L, N, D, seed, warm, n_orbits, tau):
             fd = (es[0] - es[1]) / (2.0 * tau)
             rows.append({"entry": label, "adjoint": pred, "finite_difference": fd, "abs_diff": abs(fd - pred)})
             print(f"grad: {label} adjoint {pred:.10f} fd {fd:.10f}", file=sys.stderr, flush=True)
+        # one direction that moves n_dir random symmetry-allowed entries at
+        # once (each with its symmetry partners, random weights): the
+        # adjoint's contraction with it against one central difference
+        dh = np.zeros((L, L))
+        dv = np.zeros((L,) * 4)
+        picked = 0
+        while picked < n_dir:
+            w = float(rng.normal())
+            if rng.random() < 0.1:
+                p, q = (int(x) for x in rng.integers(0, L, 2))
+                if irr[p] != irr[q]:
+                    continue
+                dh[p, q] += w
+                if p != q:
+                    dh[q, p] += w
+            else:
+                i, j, kk, l = (int(x) for x in rng.integers(0, L, 4))
+                if irr[i] ^ irr[j] ^ irr[kk] ^ irr[l]:
+                    continue
+                for a, b, c, d in {(i, j, kk, l), (j, i, kk, l), (i, j, l, kk), (j, i, l, kk),
+                                   (kk, l, i, j), (l, kk, i, j), (kk, l, j, i), (l, kk, j, i)}:
+                    dv[a, b, c, d] += w
+            picked += 1
+        pred_dir = float(np.sum(g1 * dh)) + 0.5 * float(np.sum(dv_of * dv))
+        es = []
+        for sgn in (1.0, -1.0):
+            g.set_integrals(I.h + sgn * tau * dh, I.eri + sgn * tau * dv)
+            g.mps_import(blob)
+            es.append(g.rdm(two_body=False)[2])
+        fd_dir = (es[0] - es[1]) / (2.0 * tau)
+        print(f"grad: direction over {n_dir} entries: adjoint {pred_dir:.10f} fd {fd_dir:.10f}", file=sys.stderr,
+              flush=True)
         t_fd = time.perf_counter() - t_fd
         return {
+            "fd_direction": {"entries": n_dir, "adjoint": pred_dir, "finite_difference": fd_dir,
+                             "abs_diff": abs(fd_dir - pred_dir),
+                             "rel_diff": abs(fd_dir - pred_dir) / max(abs(pred_dir), 1e-300)},
             "workload": f"energy adjoint at L={L} N={N} 2S=0 D2h irrep Ag D_SU(2)={D}, seeded synthetic integrals "
                         f"(seed {seed}), MPS after {warm} sweeps from random",
             "seconds_sweeps": t_sweeps, "seconds_rdm": t_rdm, "energy": e0,
@@ -393,6 +494,85 @@ def grad_bench(L, N, D, seed, warm, n_orbits, tau):
         }
     finally:
         g.close()
+
+
+def dmrgscf_bench(L, N, D, seed, n_core, max_iter, sweeps, dav_tol):
+    """DMRG-SCF (section "DMRG-SCF", sadmrg_dmrgscf) on the differentiation
+    configuration's integrals: the first n_core orbitals doubly occupied and
+    optimised, the other L - n_core active with N - 2 n_core electrons (the
+    paper's DMRG-SCF(34o, 8e) partition of 36 orbitals), D_SU(2) = D;
+    `max_iter` augmented-Hessian iterations, each after `sweeps` sweeps from
+    the previous MPS."""
+    from paper_1312_2415_amd import SaDMRG
+    from synth.integrals import make_integrals
+    I = make_integrals(L, "D2h", seed)
+    cls = [0] * n_core + [1] * (L - n_core)
+    act = list(range(n_core, L))
+    g = SaDMRG(L - n_core, 8, np.asarray(I.orb_irrep)[act], device=0)
+    try:
+        g.set_target(N - 2 * n_core, 0, 0)
+        g.set_davidson(dav_tol, 32, 100)
+        t = time.perf_counter()
+        e, U, hist, it = g.dmrgscf(I.orb_irrep, cls, I.h, I.eri, [(D, 1e-8, sweeps)], grad_tol=1e-6,
+                                   max_iter=max_iter)
+        t = time.perf_counter() - t
+    finally:
+        g.close()
+    for k, (ek, gk) in enumerate(hist):
+        print(f"dmrgscf: iteration {k}: E {ek:.10f} |g| {gk:.3e}", file=sys.stderr, flush=True)
+    return {"workload": f"DMRG-SCF, L={L} orbitals ({n_core} core, {L - n_core} active, {N - 2 * n_core} active "
+                        f"electrons), singlet Ag, D2h, D_SU(2)={D}, seeded synthetic integrals (seed {seed}), "
+                        f"{sweeps} sweep(s) per iteration",
+            "iterations": it, "seconds": t, "seconds_per_iteration": t / max(it, 1), "energy": e,
+            "history": [{"energy": ek, "gradient_norm": gk} for ek, gk in hist],
+            "orbital_orthonormality_error": float(np.abs(U.T @ U - np.eye(L)).max())}
+
+
+TABLE1 = [(200, 1e-8, 2, 0.03), (200, 1e-8, 3, 0.0), (500, 1e-8, 2, 0.03), (500, 1e-8, 5, 0.0),
+          (1000, 1e-8, 2, 0.03), (1000, 1e-8, 5, 0.0), (1500, 1e-8, 2, 0.03), (1500, 1e-8, 5, 0.0),
+          (2000, 1e-8, 2, 0.03), (2000, 1e-8, 5, 0.0), (2500, 1e-8, 2, 0.03), (2500, 1e-8, 12, 0.0)]
+
+
+def scheme_bench(L, N, twoS, irrep, seed, dav_tol):
+    """The paper's convergence scheme for its carbon-dimer runs (section
+    "Convergence scheme", Table 1: D 200 -> 2500, noise 0.03 then 0, E_conv
+    1e-8, at most 47 sweeps) on the headline problem, stage by stage
+    (sadmrg_solve_extrapolated), and the discarded-weight extrapolation
+    (section "Extrapolation") through the noise-free stages."""
+    from paper_1312_2415_amd import SaDMRG
+    from paper_1312_2415_amd.binding import fit_discarded_weight
+    from synth.integrals import make_integrals
+    I = make_integrals(L, "D2h", seed)
+    g = SaDMRG(L, 8, I.orb_irrep, device=0)
+    try:
+        g.set_integrals(I.h, I.eri)
+        g.set_target(N, twoS, irrep)
+        g.set_davidson(dav_tol, 32, 100)
+        g.set_seed(seed)
+        t = time.perf_counter()
+        stages = []
+        for k, ins in enumerate(TABLE1):
+            n0 = len(g.trace())
+            ts = time.perf_counter()
+            e0, c1, pts = g.solve_extrapolated([ins])
+            ts = time.perf_counter() - ts
+            n_sw = (len(g.trace()) - n0) // (2 * (L - 1))
+            stages.append({"D": ins[0], "noise": ins[3], "max_sweeps": ins[2], "sweeps": n_sw, "seconds": ts,
+                           "w_disc": pts[0][1], "energy_last_sweep": pts[0][2]})
+            print(f"scheme stage {k}: D={ins[0]} noise={ins[3]} {n_sw} sweeps {ts:.1f}s E={pts[0][2]:.10f} "
+                  f"w={pts[0][1]:.3e}", file=sys.stderr, flush=True)
+        t = time.perf_counter() - t
+        e_min = g.energy()[0]
+    finally:
+        g.close()
+    clean = [(st["w_disc"], st["energy_last_sweep"]) for st in stages if st["noise"] == 0.0]
+    e0, c1 = fit_discarded_weight(clean)
+    return {"workload": f"Table 1 convergence scheme on L={L} N={N} 2S={twoS} D2h irrep {irrep}, seeded synthetic "
+                        f"integrals (seed {seed})",
+            "seconds": t, "sweeps": sum(st["sweeps"] for st in stages), "energy_min": e_min,
+            "extrapolated_energy": e0, "extrapolation_slope": c1, "stages": stages,
+            "paper_context": "about 8 h per carbon-dimer geometry for this scheme on 16 Sandy Bridge cores "
+                             "(cc-pVDZ integrals, not available here)"}
 
 
 def main():
@@ -407,29 +587,39 @@ def main():
     ap.add_argument("--D", type=int, default=2500)
     ap.add_argument("--copy-probe-mib", type=int, default=1024,
                     help="size of the reference streaming copy (HBM counter scale); 0 = skip")
+    ap.add_argument("--gemm-probe", type=int, default=4096,
+                    help="independent 64x256x64 products of the reference GEMM (counter scale); 0 = skip")
     ap.add_argument("--seed", type=int, default=1003)
     ap.add_argument("--dav-tol", type=float, default=1e-7)
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--cpu-D", type=int, default=60)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-tol", type=float, default=1e-5)
+    ap.add_argument("--mixed-steps", type=int, default=4, help="sweeps of each mixed-precision record (at most "
+                                                               "--steps)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-rdm", action="store_true")
+    ap.add_argument("--no-method-count", action="store_true")
     ap.add_argument("--batch-n", type=int, default=64, help="independent problems of the lockstep batch; 0 = skip")
     ap.add_argument("--batch-seed", type=int, default=4)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--only-batch", action="store_true", help="run only the lockstep batch record")
-    ap.add_argument("--roots", type=int, default=3, help="roots of the headline problem swept in lockstep "
+    ap.add_argument("--roots", type=int, default=3, help="lockstep group size of the twelve-root record "
                                                          "(a divisor of 12; 0 = skip)")
     ap.add_argument("--roots-warmup", type=int, default=2)
     ap.add_argument("--refine", type=int, default=1, help="FP64 Davidson steps after the reduced-precision phase")
     ap.add_argument("--only-roots", action="store_true", help="run only the roots record")
-    ap.add_argument("--grad", type=int, default=4, help="integral orbits checked by finite differences in the "
-                                                        "energy-adjoint record at --grad-L orbitals (0 = skip)")
+    ap.add_argument("--grad", type=int, default=4, help="integral orbits checked one by one by finite differences "
+                                                        "in the energy-adjoint record at --grad-L orbitals (0 = skip)")
+    ap.add_argument("--grad-dir", type=int, default=200, help="entries of the one multi-entry difference direction")
     ap.add_argument("--grad-L", type=int, default=36)
     ap.add_argument("--grad-warmup", type=int, default=3)
     ap.add_argument("--grad-tau", type=float, default=1e-5)
     ap.add_argument("--only-grad", action="store_true", help="run only the energy-adjoint record")
+    ap.add_argument("--scf-iter", type=int, default=2, help="DMRG-SCF iterations of the dmrgscf record (0 = skip)")
+    ap.add_argument("--scf-D", type=int, default=1000)
+    ap.add_argument("--scf-core", type=int, default=2)
+    ap.add_argument("--only-dmrgscf", action="store_true")
+    ap.add_argument("--only-scheme", action="store_true", help="run only the Table 1 convergence-scheme record")
     ap.add_argument("--gpc", default="", help="fixed sigma launch shape 'pass1,pass2' (workgroups per CU) "
                                                "instead of autotuning")
     args = ap.parse_args()
@@ -442,7 +632,7 @@ def main():
 
     if args.only_grad:
         print(json.dumps({"grad": grad_bench(args.grad_L, args.N, args.D, args.seed, args.grad_warmup,
-                                             max(args.grad, 1), args.grad_tau)}), flush=True)
+                                             max(args.grad, 1), args.grad_tau, args.grad_dir)}), flush=True)
         return
     if args.only_roots:
         print(json.dumps({"roots": roots_bench(args.roots, args.L, args.N, args.D, args.seed, args.roots_warmup,
@@ -450,6 +640,14 @@ def main():
         return
     if args.only_batch:  # the lockstep batch record alone (for profiling it)
         print(json.dumps({"batch": batch_bench(max(args.batch_n, 1), args.batch_seed, 1, args.mixed_tol)}),
+              flush=True)
+        return
+    if args.only_dmrgscf:
+        print(json.dumps({"dmrgscf": dmrgscf_bench(args.grad_L, args.N, args.scf_D, args.seed, args.scf_core,
+                                                   max(args.scf_iter, 1), 2, args.dav_tol)}), flush=True)
+        return
+    if args.only_scheme:
+        print(json.dumps({"scheme": scheme_bench(args.L, args.N, args.twoS, args.irrep, args.seed, args.dav_tol)}),
               flush=True)
         return
 
@@ -469,6 +667,14 @@ def main():
         copy_gbps = 16.0 * n / sec / 1e9
         print(f"copy probe {args.copy_probe_mib} MiB: {1e3 * sec:.3f} ms/launch, {copy_gbps:.0f} GB/s", file=sys.stderr,
               flush=True)
+    gemm_probe = None
+    if args.gemm_probe > 0:
+        sec, byt = g.gemm_probe(args.gemm_probe, 256, 5)
+        gemm_probe = {"products": args.gemm_probe, "K": 256, "bytes_per_launch": byt, "ms_per_launch": 1e3 * sec,
+                      "GBps": byt / sec / 1e9,
+                      "kernel": "gemm_tile_kernel<double, 0>, the first dispatches of the run (5 launches)"}
+        print(f"gemm probe {args.gemm_probe} products: {1e3 * sec:.3f} ms/launch, {byt / sec / 1e9:.0f} GB/s",
+              file=sys.stderr, flush=True)
     g.init_mps(args.D)
     for w in range(args.warmup):
         t = time.time()
@@ -491,8 +697,8 @@ def main():
         tune = {"step": L // 2 - 1, "chosen_gpc_pass1_pass2": list(chosen),
                 "candidates_ms_per_sigma": {f"{a},{b}": ms for (a, b), ms in table}}
         print(f"autotune: pass-1/pass-2 workgroups per CU {chosen}", file=sys.stderr, flush=True)
-    import numpy as np
     g.stats_reset()
+    n_before = len(g.trace())
     t0 = time.perf_counter()
     energies = []
     for k in range(args.steps):
@@ -506,6 +712,7 @@ def main():
     mem_free, mem_total = device_memory(0)
     st = g.stats()
     trace64 = g.trace()
+    per_sweep = 2 * (L - 1)
     sec_per_sweep = (t1 - t0) / args.steps
     sigma_tflops = st["flops_sigma"] / max(st["t_sigma"], 1e-12) / 1e12
     avg_sigma_ms = 1e3 * st["t_sigma"] / max(st["n_sigma"], 1)
@@ -516,7 +723,20 @@ def main():
     flops_per_launch = ps["flops"] / nl
     bytes_per_launch = ps["bytes"] / nl
     launch_ms = 1e3 * ps["t"] / nl
-    achieved = flops_per_launch / max(launch_ms, 1e-12) / 1e9
+    achieved_tf = flops_per_launch / max(launch_ms, 1e-12) / 1e9
+    achieved_gbs = bytes_per_launch / max(launch_ms, 1e-12) / 1e6
+    ai = flops_per_launch / max(bytes_per_launch, 1.0)
+    ridge = FP64_MFMA_PEAK / (HBM_PEAK / 1000.0)  # flop per byte where the two roofs meet
+    if ai < ridge:
+        roof = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK, "unit": "GB/s",
+                "frac": achieved_gbs / HBM_PEAK}
+    else:
+        roof = {"bound": "mfma", "achieved": achieved_tf, "peak": FP64_MFMA_PEAK, "unit": "TFLOP/s",
+                "frac": achieved_tf / FP64_MFMA_PEAK}
+    roof.update({"traffic": stored_traffic(dom), "kernel": PASS_KERNEL[dom], "flops_per_launch": flops_per_launch,
+                 "algorithmic_bytes_per_launch": bytes_per_launch, "arithmetic_intensity": ai,
+                 "ridge_flop_per_byte": ridge, "launch_ms_avg": launch_ms, "launches": ps["launches"],
+                 "mfma_tflops": achieved_tf, "mfma_frac": achieved_tf / FP64_MFMA_PEAK})
     line = {
         "metric": METRIC,
         "value": sigma_tflops,
@@ -542,34 +762,54 @@ def main():
         "wdisc_max": wd,
         "sigma_passes": {k: {"ms_per_launch": 1e3 * st[k]["t"] / max(st[k]["launches"], 1),
                              "tflops": st[k]["flops"] / max(st[k]["t"], 1e-12) / 1e12,
+                             "GBps_algorithmic": st[k]["bytes"] / max(st[k]["t"], 1e-12) / 1e9,
+                             "arithmetic_intensity": st[k]["flops"] / max(st[k]["bytes"], 1.0),
                              "share_of_sigma_time": st[k]["t"] / max(st["t_sigma"], 1e-12)}
                          for k in ("pass1", "pass2")},
         "copy_probe_GBps": copy_gbps,
+        "gemm_probe": gemm_probe,
         "autotune": tune,
         "host_phase_seconds_per_sweep": {k: v / args.steps for k, v in st["phases"].items()},
         "davidson_sigma_seconds_per_sweep": st["t_sigma"] / args.steps,
         "max_enlarged_bytes": st["max_enlarged_bytes"],
         "device_memory_used_GiB_after_timed_sweeps": (mem_total - mem_free) / 2**30,
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_MFMA_PEAK, "traffic": stored_traffic(dom),
-                     "kernel": PASS_KERNEL[dom], "flops_per_launch": flops_per_launch,
-                     "algorithmic_bytes_per_launch": bytes_per_launch, "launch_ms_avg": launch_ms,
-                     "launches": ps["launches"]},
+        "roofline": roof,
     }
     rdm64 = None
     if not args.no_rdm:  # spin-summed 1- and 2-RDM of the final FP64 MPS (energy adjoint)
         tr0 = time.perf_counter()
-        g1, g2, e_rdm = g.rdm()
+        ga, gb, g1, s2, e_rdm = g.calc2dm()
         t_rdm = time.perf_counter() - tr0
-        rdm64 = (g1, g2)
-        e_id = I.e_const + float(np.einsum("pq,pq", I.h, g1)) + 0.5 * float(np.einsum("ikjl,ijkl", I.eri, g2))
+        rdm64 = (g1, ga)
+        e_id = I.e_const + float(np.einsum("pq,pq", I.h, g1)) + 0.5 * float(np.einsum("ikjl,ijkl", I.eri, ga))
         line["rdm"] = {"seconds": t_rdm, "energy": e_rdm, "energy_identity_error": abs(e_id - e_rdm),
-                       "trace_gamma": float(np.trace(g1))}
-        print(f"rdm {t_rdm:.1f}s E={e_rdm:.10f} identity error {abs(e_id - e_rdm):.2e}", file=sys.stderr, flush=True)
+                       "trace_gamma": float(np.trace(g1)), "s2": s2,
+                       "s2_error": abs(s2 - 0.25 * args.twoS * (args.twoS + 2))}
+        print(f"rdm {t_rdm:.1f}s E={e_rdm:.10f} identity error {abs(e_id - e_rdm):.2e} <S^2> {s2:.2e}",
+              file=sys.stderr, flush=True)
+    if not args.no_method_count:
+        # one more FP64 sweep with the method-work counter on (not timed): the
+        # share of the performed sigma flops that multiply structurally
+        # nonzero piece pairs of the enlarged operators
+        g.set_method_counter(True)
+        g.stats_reset()
+        tm = time.perf_counter()
+        g.sweep(args.D)
+        tm = time.perf_counter() - tm
+        mf, pf, _ = g.stats_method()
+        g.set_method_counter(False)
+        ratio = pf / max(mf, 1.0)
+        line["method_work"] = {"performed_over_method_flops": ratio,
+                               "sigma_method_tflops": sigma_tflops / ratio,
+                               "counting_sweep_seconds": tm}
+        roof["method_mfma_tflops"] = achieved_tf / ratio
+        roof["method_mfma_frac"] = achieved_tf / ratio / FP64_MFMA_PEAK
+        print(f"method work: performed / method flops {ratio:.3f}", file=sys.stderr, flush=True)
     if not args.no_mixed:
-        # the same timed sweeps from the same state with reduced-precision
+        # the first sweeps again from the same state with reduced-precision
         # sigma in Davidson (FP32, then BF16x3) and an FP64 refinement step
-        n_done = len(trace64)
+        nmix = max(1, min(args.steps, args.mixed_steps))
+        ref_trace = trace64[n_before:n_before + nmix * per_sweep]
         for mode, key, desc in (
                 (1, "mixed", "FP32 sigma (FP32 operators, FP32 accumulation) in Davidson"),
                 (2, "mixed_bf16x3", "BF16x3 sigma (hi*hi + hi*lo + lo*hi of BF16 splits of the FP32 operators, "
@@ -578,22 +818,21 @@ def main():
             g.set_refinement(args.refine)
             g.mps_import(start)
             g.stats_reset()
+            n_done = len(g.trace())
             tm0 = time.perf_counter()
             emix = []
-            for k in range(args.steps):
+            for k in range(nmix):
                 ts = time.perf_counter()
                 e, _ = g.sweep(args.D)
                 emix.append(e)
-                print(f"{key} sweep {k + 1}/{args.steps} D={args.D} E={e:.10f} {time.perf_counter() - ts:.1f}s",
+                print(f"{key} sweep {k + 1}/{nmix} D={args.D} E={e:.10f} {time.perf_counter() - ts:.1f}s",
                       file=sys.stderr, flush=True)
             tm1 = time.perf_counter()
             sm = g.stats()
-            tracem = g.trace()
-            nt = len(tracem) - n_done  # micro-iterations of these sweeps
-            d_micro = float(max(abs(a - b) for a, b in zip(trace64[len(trace64) - nt:], tracem[n_done:]))) \
-                if nt > 0 else None
-            n_done = len(tracem)
-            sec_mixed = (tm1 - tm0) / args.steps
+            tracem = g.trace()[n_done:n_done + len(ref_trace)]
+            d_micro = float(np.abs(np.array(tracem) - np.array(ref_trace)).max()) \
+                if len(tracem) == len(ref_trace) and len(ref_trace) else None
+            sec_mixed = (tm1 - tm0) / nmix
             peak = FP32_MFMA_PEAK if mode == 1 else BF16_MFMA_PEAK / 3
             tf = sm["fp32"]["flops"] / max(sm["fp32"]["t"], 1e-12) / 1e12
             rec = {
@@ -602,6 +841,7 @@ def main():
                                     "and give its energy",
                 "mixed_tol": args.mixed_tol,
                 "fp64_refinement_steps": args.refine,
+                "sweeps": nmix,
                 "s_per_sweep": sec_mixed,
                 "speedup_s_per_sweep": sec_per_sweep / sec_mixed,
                 "sigma_reduced_tflops": tf,
@@ -609,13 +849,13 @@ def main():
                 "sigma_reduced_peak_tflops": peak,
                 "sigma_reduced_calls": sm["fp32"]["calls"],
                 "sigma_fp64_calls": sm["n_sigma"],
-                "sigma_seconds_per_sweep": (sm["fp32"]["t"] + sm["t_sigma"]) / args.steps,
+                "sigma_seconds_per_sweep": (sm["fp32"]["t"] + sm["t_sigma"]) / nmix,
                 "sigma_seconds_per_sweep_fp64_path": st["t_sigma"] / args.steps,
                 "energy_last_sweep": emix[-1],
-                "abs_dE_last_sweep_vs_fp64": abs(emix[-1] - energies[-1]),
+                "abs_dE_last_sweep_vs_fp64": abs(emix[-1] - energies[nmix - 1]),
                 "max_abs_dE_per_micro_iteration_vs_fp64": d_micro,
             }
-            if rdm64 is not None:
+            if rdm64 is not None and nmix == args.steps:
                 m1, m2, _ = g.rdm()
                 rec["rdm_max_abs_error_vs_fp64"] = {"gamma": float(np.abs(m1 - rdm64[0]).max()),
                                                     "Gamma": float(np.abs(m2 - rdm64[1]).max())}
@@ -623,21 +863,28 @@ def main():
     g.close()
     if args.batch_n > 0:
         line["batch"] = batch_bench(args.batch_n, args.batch_seed, 1, args.mixed_tol)
-    # the extra records run last, the one that fills device memory most at the
-    # end; after a failed record no further GPU work is started
-    if args.grad > 0:
+    # the extra records run last; after a failed record no further GPU work
+    # that fills the device is started
+    failed = False
+    for key, run in (("grad", lambda: grad_bench(args.grad_L, N, args.D, args.seed, args.grad_warmup, args.grad,
+                                                 args.grad_tau, args.grad_dir) if args.grad > 0 else None),
+                     ("dmrgscf", lambda: dmrgscf_bench(args.grad_L, N, args.scf_D, args.seed, args.scf_core,
+                                                       args.scf_iter, 2, args.dav_tol) if args.scf_iter > 0 else None),
+                     ("roots", lambda: roots_bench(args.roots, L, N, args.D, args.seed, args.roots_warmup,
+                                                   args.dav_tol, args.mixed_tol, args.refine)
+                      if args.roots > 0 else None)):
+        if failed:
+            break
         try:
-            line["grad"] = grad_bench(args.grad_L, N, args.D, args.seed, args.grad_warmup, args.grad, args.grad_tau)
+            rec = run()
+            if rec is not None:
+                line[key] = rec
         except Exception as ex:  # the headline record stands on its own
-            line["grad"] = {"error": f"{type(ex).__name__}: {ex}"}
-    if args.roots > 0 and "error" not in line.get("grad", {}):
-        try:
-            line["roots"] = roots_bench(args.roots, L, N, args.D, args.seed, args.roots_warmup, args.dav_tol,
-                                        args.mixed_tol, args.refine)
-        except Exception as ex:
-            line["roots"] = {"error": f"{type(ex).__name__}: {ex}"}
+            line[key] = {"error": f"{type(ex).__name__}: {ex}"}
+            failed = True
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, L, N, args.twoS, args.irrep, args.seed, args.cpu_D)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, L, N, args.twoS, args.irrep, args.seed, args.D,
+                                            L // 2 - 1)
     print(json.dumps(line), flush=True)
 
 

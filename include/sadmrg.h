@@ -510,6 +510,15 @@ int sadmrg_stats_mixed(sadmrg_ctx* ctx, double* t_sigma32, int64_t* n_sigma32, d
  * (n or reps not positive), ENOMEM, EDEVICE. */
 int sadmrg_debug_copy_probe(sadmrg_ctx* ctx, int64_t n, int reps, double* seconds);
 
+/* Reference GEMM for HBM byte counters: nprod independent products
+ * c_q = a_q b_q (64 x K times K x 64, every operand its own array, so each
+ * is read once and each result written once) through the sigma pass-1
+ * kernel (one 64 x 64 tile per workgroup), `reps` launches; *seconds gets
+ * the mean kernel time per launch, *bytes the exact traffic per launch
+ * (8 (2 * 64 K + 64 * 64) nprod).  Allocates and frees its arrays.  Errors:
+ * EINVAL (sizes), ENOMEM, EDEVICE. */
+int sadmrg_debug_gemm_probe(sadmrg_ctx* ctx, int nprod, int K, int reps, double* seconds, double* bytes);
+
 /* Description of the last failure (static until the next call on ctx). */
 const char* sadmrg_last_error(const sadmrg_ctx* ctx);
 

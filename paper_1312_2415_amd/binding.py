@@ -49,6 +49,7 @@ def load_library(path: str | None = None):
         "sadmrg_batch_sweep": (c_int, [P(c_vp), c_int, P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_solve": (c_int, [c_vp, c_int, P(c_int), P(c_dbl), P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_get_energy": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
+        "sadmrg_debug_gemm_probe": (c_int, [c_vp, c_int, c_int, c_int, P(c_dbl), P(c_dbl)]),
         "sadmrg_set_method_counter": (c_int, [c_vp, c_int]),
         "sadmrg_stats_method": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
         "sadmrg_push_excitation": (c_int, [c_vp, c_dbl]),
@@ -447,6 +448,13 @@ class SaDMRG:
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         self._chk(self.lib.sadmrg_stats_method(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
+
+    def gemm_probe(self, nprod: int, K: int, reps: int = 5):
+        """(seconds per launch, exact bytes per launch) of the reference GEMM."""
+        s, b = ctypes.c_double(), ctypes.c_double()
+        self._chk(self.lib.sadmrg_debug_gemm_probe(self.h, int(nprod), int(K), int(reps), ctypes.byref(s),
+                                                   ctypes.byref(b)))
+        return s.value, b.value
 
     def stats_reset(self):
         self._chk(self.lib.sadmrg_stats_reset(self.h))

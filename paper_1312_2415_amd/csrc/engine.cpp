@@ -5719,6 +5719,41 @@ int sadmrg_debug_copy_probe(sadmrg_ctx* ctx, int64_t n, int reps, double* second
   });
 }
 
+int sadmrg_debug_gemm_probe(sadmrg_ctx* ctx, int nprod, int K, int reps, double* seconds, double* bytes) {
+  return guard(ctx, [&] {
+    using namespace sadmrg;
+    if (nprod <= 0 || K <= 0 || K > 4096 || reps <= 0) fail(SADMRG_EINVAL, "gemm probe: bad sizes");
+    const int64_t per = (int64_t)64 * K;  // one 64 x K panel
+    DBuf a, b, c;
+    a.alloc((size_t)nprod * per);
+    b.alloc((size_t)nprod * per);
+    c.alloc((size_t)nprod * 64 * 64);
+    launch_fill_uniform(a.p, (int64_t)nprod * per, 3, 4, ctx->e.st);
+    launch_fill_uniform(b.p, (int64_t)nprod * per, 5, 6, ctx->e.st);
+    GemmList gl;
+    for (int q = 0; q < nprod; ++q) {  // c_q = a_q (64 x K) * b_q (K x 64), operands of their own
+      const int blk = gl.add_block(c.p + (int64_t)q * 4096, 64, 64, 64, 1);
+      gl.add(blk, 64, 64, GTask{a.p + q * per, b.p + q * per, K, 64, K, 0, 1.0});
+    }
+    GemmList::Plan pl;
+    gl.plan(pl, ctx->e.st, 0);
+    pl.tag = 0;  // the sigma pass-1 kernel
+    double t = 0.0;
+    for (int r = 0; r < reps; ++r) {
+      void* e0 = dev_event_record(ctx->e.st);
+      launch_gemm(pl.tiles.p, pl.tasks.p, pl.wstart.p, pl.nwg, pl.stream, pl.tag, false, ctx->e.st);
+      void* e1 = dev_event_record(ctx->e.st);
+      t += dev_event_elapsed(e0, e1);
+      dev_event_free(e0);
+      dev_event_free(e1);
+    }
+    dev_sync(ctx->e.st);
+    if (seconds) *seconds = t / reps;
+    if (bytes) *bytes = 8.0 * ((double)nprod * 2 * per + (double)nprod * 4096);
+    return 0;
+  });
+}
+
 int sadmrg_stats_reset(sadmrg_ctx* ctx) {
   return guard(ctx, [&] {
     auto& E = ctx->e;

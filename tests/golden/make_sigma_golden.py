@@ -1,9 +1,12 @@
-"""Writes tests/golden/cfg2_mid_sigma.json: the oracle's sigma at the middle
-step of the L = 24, N = 12, singlet Ag, D2h (orbital irreps i mod 8),
-D_SU(2) = 500 configuration (synthetic integrals, seed 1002).
+"""Writes the oracle's sigma at the middle step of two configurations:
 
-The MPS is oracle.sadmrg.random_mps_at(P, 500, seed=3, i=11): deterministic
-random left- and right-normalised tensors with the centre on sites (11, 12),
+* cfg2_mid_sigma.json: L = 24, N = 12, singlet Ag, D2h (orbital irreps
+  i mod 8), D_SU(2) = 500, integral seed 1002, step 11;
+* headline_mid_sigma.json: L = 28, N = 12, singlet Ag, D2h, D_SU(2) = 2500,
+  integral seed 1003 (the benchmark's problem), step 13.
+
+The MPS is oracle.sadmrg.random_mps_at(P, D, seed=3, i=step): deterministic
+random left- and right-normalised tensors with the centre on sites (i, i+1),
 so that the same MPS can be rebuilt anywhere without optimisation.  Every
 left and right block is built by the oracle (complementary operators,
 renormalisation), then sigma = H_eff x for x ~ N(0, 1) from
@@ -11,7 +14,7 @@ numpy.random.default_rng(2024) over the step's flat layout.  Stored: the
 layout, |sigma|, <r, sigma> for r from default_rng(2025), and 512 entries at
 indices drawn from default_rng(2026).  Calls only oracle/ and synth/.
 
-    python tests/golden/make_cfg2_sigma.py
+    python tests/golden/make_sigma_golden.py            (both, about 2 min)
 """
 import json
 import os
@@ -26,10 +29,11 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 from oracle import sadmrg as sd  # noqa: E402
 from synth.integrals import make_integrals  # noqa: E402
 
-L, N, TWOS, IRREP, D, SEED_INT, SEED_MPS, STEP = 24, 12, 0, 0, 500, 1002, 3, 11
+CONFIGS = {"cfg2_mid_sigma.json": (24, 12, 0, 0, 500, 1002, 3, 11),
+           "headline_mid_sigma.json": (28, 12, 0, 0, 2500, 1003, 3, 13)}
 
 
-def main():
+def make(name, L, N, TWOS, IRREP, D, SEED_INT, SEED_MPS, STEP):
     t0 = time.time()
     I = make_integrals(L, "D2h", SEED_INT)
     P = sd.Problem(I.h, I.eri, N, TWOS, IRREP, I.orb_irrep)
@@ -54,10 +58,13 @@ def main():
         "index": [int(k) for k in idx], "value": [float(sig[k]) for k in idx],
         "oracle_seconds": time.time() - t0,
     }
-    with open(os.path.join(HERE, "cfg2_mid_sigma.json"), "w") as f:
+    with open(os.path.join(HERE, name), "w") as f:
         json.dump(out, f)
-    print(f"n = {n}, |sigma| = {out['sigma_norm']:.12e}, {out['oracle_seconds']:.0f} s")
+    print(f"{name}: n = {n}, |sigma| = {out['sigma_norm']:.12e}, {out['oracle_seconds']:.0f} s")
 
 
 if __name__ == "__main__":
-    main()
+    for name, cfg in CONFIGS.items():
+        if len(sys.argv) > 1 and name not in sys.argv[1:]:
+            continue
+        make(name, *cfg)

@@ -13,6 +13,10 @@ benchmark times:
 The plain FP64 configuration L = 24, N = 12, singlet Ag, D2h, D_SU(2) = 500,
 six sweeps: sweep minima do not rise, a larger bond dimension does not raise
 the energy, and the same symmetry, diagonal and RDM identities hold.
+
+Both configurations are also compared with the oracle itself at their
+middle step: sigma on a deterministic random MPS against stored oracle
+values (tests/golden/make_sigma_golden.py).
 """
 import numpy as np
 import pytest
@@ -115,18 +119,19 @@ def test_l24_d500_sweeps_and_identities():
     g.close()
 
 
-def test_config2_middle_step_sigma_matches_the_oracle_golden():
-    """L = 24, N = 12, D2h, D = 500 (the survey's oracle-GPU parity
-    configuration): sigma at the middle step on the same deterministic MPS
-    (oracle.sadmrg.random_mps_at, rebuilt here) against the oracle's values
-    stored by tests/golden/make_cfg2_sigma.py: 512 sampled entries, the norm
-    and a projection, within 1e-10 relative."""
+@pytest.mark.parametrize("name", ["cfg2_mid_sigma.json", "headline_mid_sigma.json"])
+def test_middle_step_sigma_matches_the_oracle_golden(name):
+    """L = 24, N = 12, D2h, D = 500 (the oracle-GPU parity configuration)
+    and the headline L = 28, N = 12, D2h, D = 2500: sigma at the middle step
+    on the same deterministic MPS (oracle.sadmrg.random_mps_at, rebuilt here)
+    against the oracle's values stored by tests/golden/make_sigma_golden.py:
+    512 sampled entries, the norm and a projection, within 1e-10 relative."""
     import json
     import os
 
     from paper_1312_2415_amd import SaDMRG
     from oracle import sadmrg as sd
-    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "cfg2_mid_sigma.json")))
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", name)))
     I = make_integrals(gold["L"], "D2h", gold["seed_integrals"])
     P = sd.Problem(I.h, I.eri, gold["N"], gold["twoS"], gold["irrep"], I.orb_irrep)
     dm = sd.random_mps_at(P, gold["D"], gold["seed_mps"], gold["step"])
