@@ -622,6 +622,8 @@ def main():
     ap.add_argument("--only-scheme", action="store_true", help="run only the Table 1 convergence-scheme record")
     ap.add_argument("--gpc", default="", help="fixed sigma launch shape 'pass1,pass2' (workgroups per CU) "
                                                "instead of autotuning")
+    ap.add_argument("--xcd", default="", help="XCD-grouped workgroup order of the sigma passes 'pass1,pass2' "
+                                               "(0/1 each)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -675,6 +677,10 @@ def main():
                       "kernel": "gemm_tile_kernel<double, 0>, the first dispatches of the run (5 launches)"}
         print(f"gemm probe {args.gemm_probe} products: {1e3 * sec:.3f} ms/launch, {byt / sec / 1e9:.0f} GB/s",
               file=sys.stderr, flush=True)
+    xcd = None
+    if args.xcd:
+        xcd = [int(v) for v in args.xcd.split(",")]
+        g.set_xcd_order(*xcd)
     g.init_mps(args.D)
     for w in range(args.warmup):
         t = time.time()
@@ -769,6 +775,7 @@ def main():
         "copy_probe_GBps": copy_gbps,
         "gemm_probe": gemm_probe,
         "autotune": tune,
+        "xcd_order_pass1_pass2": xcd,
         "host_phase_seconds_per_sweep": {k: v / args.steps for k, v in st["phases"].items()},
         "davidson_sigma_seconds_per_sweep": st["t_sigma"] / args.steps,
         "max_enlarged_bytes": st["max_enlarged_bytes"],

@@ -204,6 +204,15 @@ int sadmrg_autotune(sadmrg_ctx* ctx, int reps, int* gpc1, int* gpc2, double* tab
  * Takes effect from the next prepared step.  Errors: EINVAL. */
 int sadmrg_set_launch_shape(sadmrg_ctx* ctx, int gpc1, int gpc2);
 
+/* Workgroup order of the two sigma GEMM passes (1 = on, 0 = off, per pass).
+ * The dispatcher deals the workgroups of a launch to the device's eight XCDs
+ * in turn, and each XCD has its own L2 cache.  With the order on, the tiles
+ * (or tile ranges) are split into eight contiguous parts and part x runs on
+ * XCD x, so the tiles of one product, which read the same operand panels,
+ * run on one XCD close in time.  Results do not depend on it.  Takes effect
+ * from the next prepared step.  Errors: EINVAL. */
+int sadmrg_set_xcd_order(sadmrg_ctx* ctx, int pass1, int pass2);
+
 /* Free and total bytes of device memory on a device (the library's cached
  * blocks count as used).  Errors: EINVAL, EDEVICE. */
 int sadmrg_device_memory(int device, size_t* free_bytes, size_t* total_bytes);

@@ -49,6 +49,7 @@ def load_library(path: str | None = None):
         "sadmrg_batch_sweep": (c_int, [P(c_vp), c_int, P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_solve": (c_int, [c_vp, c_int, P(c_int), P(c_dbl), P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_get_energy": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
+        "sadmrg_set_xcd_order": (c_int, [c_vp, c_int, c_int]),
         "sadmrg_debug_gemm_probe": (c_int, [c_vp, c_int, c_int, c_int, P(c_dbl), P(c_dbl)]),
         "sadmrg_set_method_counter": (c_int, [c_vp, c_int]),
         "sadmrg_stats_method": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
@@ -420,6 +421,10 @@ class SaDMRG:
 
     def set_launch_shape(self, gpc1: int, gpc2: int):
         self._chk(self.lib.sadmrg_set_launch_shape(self.h, int(gpc1), int(gpc2)))
+
+    def set_xcd_order(self, pass1: bool, pass2: bool):
+        """XCD-grouped workgroup order of the two sigma passes (sadmrg_set_xcd_order)."""
+        self._chk(self.lib.sadmrg_set_xcd_order(self.h, int(bool(pass1)), int(bool(pass2))))
 
     def set_enlarge_cache(self, on: bool):
         self._chk(self.lib.sadmrg_set_enlarge_cache(self.h, int(bool(on))))

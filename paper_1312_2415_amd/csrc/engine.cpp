@@ -1230,6 +1230,9 @@ struct GemmList {
   std::vector<GTile> tiles;
   std::vector<Item> items;
 
+  double flops = 0.0;  // 2 m n k of every task added
+  double bytes = 0.0;  // each operand of every product, once
+
   int add_block(double* out, int rows, int cols, int ld, int mode) {
     const int first = (int)tiles.size();
     for (int r0 = 0; r0 < rows; r0 += TS)
@@ -1249,6 +1252,7 @@ struct GemmList {
     if (reach(!(base.flags & GT_TRANS_A), base.lda, base.K) >= lim ||
         reach((base.flags & GT_TRANS_B) != 0, base.ldb, base.K) >= lim)
       fail(-4, "block product too large for the grouped GEMM kernel");
+    bytes += 8.0 * ((double)rows * base.K + (double)base.K * cols);
     const int ntc = (cols + TS - 1) / TS;
     for (int r0 = 0, tr = 0; r0 < rows; r0 += TS, ++tr)
       for (int c0 = 0, tc = 0; c0 < cols; c0 += TS, ++tc) {
@@ -1257,6 +1261,7 @@ struct GemmList {
         t.b += (t.flags & GT_TRANS_B) ? (int64_t)c0 * t.ldb : (int64_t)c0;
         const double w = 2.0 * std::min(TS, rows - r0) * std::min(TS, cols - c0) * t.K;
         items.push_back({first + tr * ntc + tc, t, w});
+        flops += w;
       }
   }
 
@@ -1269,8 +1274,9 @@ struct GemmList {
     int ntiles = 0, nwg = 0, nreds = 0;
     bool stream = false, f32 = false;
     int tag = 2;
+    int xcd = 0;  // XCD count for the workgroup order (0: dispatch order)
     void run(Stream st, bool bf3 = false) const {
-      launch_gemm(tiles.p, tasks.p, wstart.p, nwg, stream, tag, f32, st, f32 && bf3);
+      launch_gemm(tiles.p, tasks.p, wstart.p, nwg, stream, tag, f32, st, f32 && bf3, xcd);
       launch_reduce(reds.p, nreds, f32, st);
     }
   };
@@ -1439,6 +1445,13 @@ struct OutBlk {
 #ifndef GEMM_GPC_PASS2
 #define GEMM_GPC_PASS2 64
 #endif
+#ifndef GEMM_XCD_PASS1
+#define GEMM_XCD_PASS1 0
+#endif
+#ifndef GEMM_XCD_PASS2
+#define GEMM_XCD_PASS2 0
+#endif
+static constexpr int MI355X_XCDS = 8;  // XCDs of the device (256 CUs, 32 per XCD)
 
 struct TwoPass {
   GemmList::Plan p1, p2;
@@ -1459,7 +1472,7 @@ struct TwoPass {
 // planning it (a batch plans it with the cost target of the whole batch).
 static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Triple>& tr, TwoPass& tp, Stream st,
                            bool sigma = false, GemmList* keep2 = nullptr, int gpc1 = GEMM_GPC_PASS1,
-                           int gpc2 = GEMM_GPC_PASS2) {
+                           int gpc2 = GEMM_GPC_PASS2, int xcd1 = 0, int xcd2 = 0) {
   // Contraction order of every full product out[R x C] += c opA(A)[R x K1]
   // B'[K1 x K2] opC(C)[K2 x C] (B' = B or its transpose): left first (T =
   // opA(A) B' in the workspace, then out += c T opC(C): 2 R K2 (K1 + C)
@@ -1479,39 +1492,17 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
       ws += right[i] ? (int64_t)x.K1 * outs[x.blk].cols : (int64_t)outs[x.blk].rows * x.K2;
     }
   tp.ws.alloc((size_t)std::max<int64_t>(ws, 1));
-  // counters
-  double fl = 0.0, f1 = 0.0, by1 = 0.0, by2 = 0.0;
-  for (const OutBlk& o : outs) by2 += 8.0 * (double)o.rows * o.cols;
-  for (size_t i = 0; i < tr.size(); ++i) {
-    const Triple& x = tr[i];
-    const int R = outs[x.blk].rows, Cc = outs[x.blk].cols;
-    if (x.flags & TT_IDENT_C) {
-      fl += 2.0 * R * x.K1 * Cc;
-      by2 += 8.0 * ((double)R * x.K1 + (double)x.K1 * Cc);
-    } else if (x.flags & TT_IDENT_A) {
-      fl += 2.0 * R * x.K2 * Cc;
-      by2 += 8.0 * ((double)R * x.K2 + (double)x.K2 * Cc);
-    } else if (right[i]) {
-      fl += 2.0 * x.K1 * x.K2 * Cc + 2.0 * R * x.K1 * Cc;
-      f1 += 2.0 * x.K1 * x.K2 * Cc;
-      by1 += 8.0 * ((double)x.K1 * x.K2 + (double)x.K2 * Cc + (double)x.K1 * Cc);
-      by2 += 8.0 * ((double)R * x.K1 + (double)x.K1 * Cc);
-    } else {
-      fl += 2.0 * R * x.K1 * x.K2 + 2.0 * R * x.K2 * Cc;
-      f1 += 2.0 * R * x.K1 * x.K2;
-      by1 += 8.0 * ((double)R * x.K1 + (double)x.K1 * x.K2 + (double)R * x.K2);
-      by2 += 8.0 * ((double)R * x.K2 + (double)x.K2 * Cc);
-    }
-  }
-  tp.bytes1 = by1;
-  tp.bytes2 = by2;
-  tp.flops = fl;
-  tp.flops1 = f1;
-  tp.flops2 = fl - f1;
+  // output bytes: pass 1 writes every workspace slot once, pass 2 adds to
+  // every output block once; operand bytes and flops are counted per task
+  double wsb = 0.0, outb = 0.0;
+  for (const OutBlk& o : outs) outb += 8.0 * (double)o.rows * o.cols;
+  for (size_t i = 0; i < tr.size(); ++i)
+    if (slot[i] >= 0) wsb += 8.0 * (right[i] ? (double)tr[i].K1 * outs[tr[i].blk].cols : (double)outs[tr[i].blk].rows * tr[i].K2);
   tp.p1.tag = sigma ? 0 : 2;
   tp.p2.tag = sigma ? 1 : 2;
   tp.nprod = (int64_t)tr.size();
   const int tag1 = tp.p1.tag, tag2 = tp.p2.tag;
+  double g1f = 0.0, g1b = 0.0, g2f = 0.0, g2b = 0.0;
   // the two passes' product lists and plans are independent: built on two
   // host threads (pass 1: the T = op(A) B' or U = B' op(C) products into
   // workspace slots; pass 2: the accumulation into the output blocks)
@@ -1533,6 +1524,8 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
           g1.add(b1, R, x.K2, GTask{x.a, x.b, x.lda, x.ldb, x.K1, trA | (trB ? GT_TRANS_B : 0), 1.0});
         }
       }
+      g1f = g1.flops;
+      g1b = g1.bytes;
       g1.plan(tp.p1, st, gpc1);
     } else {
       GemmList g2;
@@ -1554,14 +1547,23 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
         else
           g2.add(first[x.blk], R, Cc, GTask{tp.ws.p + slot[i], x.c, x.K2, x.ldc, x.K2, trC, x.coef});
       }
+      g2f = g2.flops;
+      g2b = g2.bytes;
       if (keep2)
         *keep2 = std::move(g2);
       else
         g2.plan(tp.p2, st, gpc2);
     }
   });
+  tp.flops1 = g1f;
+  tp.flops2 = g2f;
+  tp.flops = g1f + g2f;
+  tp.bytes1 = g1b + wsb;
+  tp.bytes2 = g2b + outb;
   tp.p1.tag = tag1;
   tp.p2.tag = tag2;
+  tp.p1.xcd = xcd1;
+  tp.p2.xcd = xcd2;
 }
 
 // ---------------------------------------------------------------------------
@@ -1793,6 +1795,9 @@ struct Engine {
   // workgroups per CU of the sigma plans (0 = one tile per workgroup), set by
   // sadmrg_autotune
   int gpc1 = GEMM_GPC_PASS1, gpc2 = GEMM_GPC_PASS2;
+  // XCD-grouped workgroup order of the two sigma passes (0: dispatch order,
+  // else the XCD count), set by sadmrg_set_xcd_order
+  int xcd1 = GEMM_XCD_PASS1, xcd2 = GEMM_XCD_PASS2;
   // Enlarged blocks kept from the previous pass (section "Sweeping"): while
   // a left-to-right pass renews the left blocks, the right blocks are the
   // ones the previous right-to-left pass built, so the enlargement of the
@@ -3140,7 +3145,7 @@ struct Engine {
     bytes += 16.0 * step.n;
     t_phase[PH_TASKS] += std::chrono::duration<double>(std::chrono::steady_clock::now() - tt0).count();
     PhaseTimer pt(t_phase[PH_PLAN]);
-    build_two_pass(outs, trs, step.plan, st, true, defer_p2 ? &step.g2 : nullptr, gpc1, gpc2);
+    build_two_pass(outs, trs, step.plan, st, true, defer_p2 ? &step.g2 : nullptr, gpc1, gpc2, xcd1, xcd2);
     step.p2_pending = defer_p2;
     step.trs = trs;
     step.flops = step.plan.flops;
@@ -3388,6 +3393,7 @@ struct Engine {
       b.nreds = a.nreds;
       b.stream = a.stream;
       b.tag = a.tag;
+      b.xcd = a.xcd;
       b.f32 = true;
     };
     mirror(S.plan.p1, S.q1);
@@ -3420,7 +3426,7 @@ struct Engine {
     const bool bf3 = f32 && prec == 2;
     p1.run(st, bf3);
     void* e2 = dev_event_record(st);
-    launch_gemm(p2.tiles.p, p2.tasks.p, p2.wstart.p, p2.nwg, p2.stream, p2.tag, p2.f32, st, bf3);
+    launch_gemm(p2.tiles.p, p2.tasks.p, p2.wstart.p, p2.nwg, p2.stream, p2.tag, p2.f32, st, bf3, p2.xcd);
     void* e3 = dev_event_record(st);
     launch_reduce(p2.reds.p, p2.nreds, p2.f32, st);
     if (f32) launch_cvt_f2d(step.out.p, (const float*)step.out32.p, step.n, st);
@@ -3498,7 +3504,7 @@ struct Engine {
     for (int c = 0; c < TUNE_N; ++c) {
       const int g1 = TUNE_G1[c / 6], g2 = TUNE_G2[c % 6];
       TwoPass tp;
-      build_two_pass(outs, step.trs, tp, st, true, nullptr, g1, g2);
+      build_two_pass(outs, step.trs, tp, st, true, nullptr, g1, g2, xcd1, xcd2);
       std::swap(tp, step.plan);
       sigma_fixed(false);  // warm-up
       const double t0 = t_sigma;
@@ -3518,7 +3524,7 @@ struct Engine {
     gpc1 = TUNE_G1[best / 6];
     gpc2 = TUNE_G2[best % 6];
     TwoPass tp;
-    build_two_pass(outs, step.trs, tp, st, true, nullptr, gpc1, gpc2);
+    build_two_pass(outs, step.trs, tp, st, true, nullptr, gpc1, gpc2, xcd1, xcd2);
     std::swap(tp, step.plan);
     step.flops = step.plan.flops;
     step.f32_ready = false;
@@ -5539,7 +5545,7 @@ int sadmrg_sigma_noalloc(sadmrg_ctx* ctx, const double* x, double* y) {
     dev_zero(base + o_out, (size_t)S.n * 8, E.st);  // pass 2 accumulates into it
     for (int q = 0; q < 2; ++q) {
       launch_gemm((const GTile*)(base + o_tiles[q]), (const GTask*)(base + o_tasks[q]), (const int*)(base + o_ws0[q]),
-                  pl[q]->nwg, pl[q]->stream, pl[q]->tag, false, E.st);
+                  pl[q]->nwg, pl[q]->stream, pl[q]->tag, false, E.st, false, pl[q]->xcd);
       launch_reduce((const RTile*)(base + o_reds[q]), pl[q]->nreds, false, E.st);
     }
     dev_d2d(y, base + o_out, (size_t)S.n * 8, E.st);
@@ -5765,6 +5771,15 @@ int sadmrg_stats_reset(sadmrg_ctx* ctx) {
     E.n_sigma = 0;
     E.f_method = E.f_method_perf = 0;
     for (double& t : E.t_phase) t = 0.0;
+    return 0;
+  });
+}
+
+int sadmrg_set_xcd_order(sadmrg_ctx* ctx, int pass1, int pass2) {
+  return guard(ctx, [&] {
+    ctx->e.xcd1 = pass1 ? sadmrg::MI355X_XCDS : 0;
+    ctx->e.xcd2 = pass2 ? sadmrg::MI355X_XCDS : 0;
+    ctx->e.step.i = -1;  // re-plan on the next step
     return 0;
   });
 }

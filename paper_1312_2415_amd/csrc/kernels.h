@@ -162,8 +162,11 @@ struct GTask {
 // pointers keep their double* type and are reinterpreted).
 // bf3 (with f32): BF16x3 products on the FP32 data (hi*hi + hi*lo + lo*hi of
 // the BF16 splits, FP32 accumulation).
+// nx > 1: workgroups are ordered so that consecutive tiles (or ranges) run
+// on one of nx XCDs (the dispatcher deals workgroups to the XCDs in turn);
+// results do not depend on it.
 void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag, bool f32,
-                 Stream st, bool bf3 = false);
+                 Stream st, bool bf3 = false, int nx = 0);
 // Number of compute units of the current device.
 int dev_cu_count();
 void launch_reduce(const RTile* reds, int nred, bool f32, Stream st);

@@ -646,6 +646,19 @@ __device__ inline void g_write(const GOut& tile, const typename GT<T>::Acc (&acc
   }
 }
 
+// Workgroup order across the XCDs.  The dispatcher hands consecutive
+// workgroups of a launch to the XCDs in turn (workgroup b to XCD b mod nx),
+// and each XCD has its own L2.  With nx > 1 workgroup b takes item
+// start(x) + b / nx with x = b mod nx, where XCD x owns the contiguous items
+// [start(x), start(x+1)) of an even split: consecutive items (the tiles of
+// one product, which share operand panels) then run on one XCD, close in
+// time.  A bijection of [0, n) for any n.
+__device__ __forceinline__ unsigned xcd_item(unsigned b, unsigned n, int nx) {
+  if (nx <= 1) return b;
+  const unsigned q = n / (unsigned)nx, r = n % (unsigned)nx, x = b % (unsigned)nx, j = b / (unsigned)nx;
+  return x * q + min(x, r) + j;
+}
+
 // One tile per workgroup (blockIdx.x = tile), no state carried between tiles:
 // the hardware dispatcher balances short, independent tiles best.
 // TAG only separates the symbols of the launch sites for profiling:
@@ -728,14 +741,14 @@ __device__ __forceinline__ void gemm_tile_body(const GTile* __restrict__ tiles, 
 
 template <typename T, int TAG>
 __global__ __launch_bounds__(256, 4) void gemm_tile_kernel(const GTile* __restrict__ tiles,
-                                                           const GTask* __restrict__ tasks) {
-  gemm_tile_body<T>(tiles, tasks, blockIdx.x);
+                                                           const GTask* __restrict__ tasks, int nx) {
+  gemm_tile_body<T>(tiles, tasks, xcd_item(blockIdx.x, gridDim.x, nx));
 }
 // the same with BF16x3 products on FP32 data
 template <int TAG>
 __global__ __launch_bounds__(256, 4) void gemm_tile_bf3_kernel(const GTile* __restrict__ tiles,
-                                                               const GTask* __restrict__ tasks) {
-  gemm_tile_body<float, true>(tiles, tasks, blockIdx.x);
+                                                               const GTask* __restrict__ tasks, int nx) {
+  gemm_tile_body<float, true>(tiles, tasks, xcd_item(blockIdx.x, gridDim.x, nx));
 }
 
 // Workgroup g streams the tiles [wstart[g], wstart[g+1]).
@@ -856,14 +869,14 @@ __device__ __forceinline__ void gemm_stream_body(const GTile* __restrict__ tiles
 template <typename T, int TAG>
 __global__ __launch_bounds__(256, 3) void gemm_stream_kernel(const GTile* __restrict__ tiles,
                                                              const GTask* __restrict__ tasks,
-                                                             const int* __restrict__ wstart) {
-  gemm_stream_body<T>(tiles, tasks, wstart, blockIdx.x);
+                                                             const int* __restrict__ wstart, int nx) {
+  gemm_stream_body<T>(tiles, tasks, wstart, xcd_item(blockIdx.x, gridDim.x, nx));
 }
 template <int TAG>
 __global__ __launch_bounds__(256, 3) void gemm_stream_bf3_kernel(const GTile* __restrict__ tiles,
                                                                  const GTask* __restrict__ tasks,
-                                                                 const int* __restrict__ wstart) {
-  gemm_stream_body<float, true>(tiles, tasks, wstart, blockIdx.x);
+                                                                 const int* __restrict__ wstart, int nx) {
+  gemm_stream_body<float, true>(tiles, tasks, wstart, xcd_item(blockIdx.x, gridDim.x, nx));
 }
 
 // Several plans in one launch (independent problems batched together): plan s
@@ -931,51 +944,51 @@ __global__ __launch_bounds__(256, 3) void gemm_stream_seg_bf3_kernel(const GSeg*
 
 template <typename T>
 static void launch_gemm_t(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag,
-                          hipStream_t hs) {
+                          hipStream_t hs, int nx) {
   if (stream) {
     if (tag == 0)
-      hipLaunchKernelGGL((gemm_stream_kernel<T, 0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+      hipLaunchKernelGGL((gemm_stream_kernel<T, 0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx);
     else if (tag == 1)
-      hipLaunchKernelGGL((gemm_stream_kernel<T, 1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+      hipLaunchKernelGGL((gemm_stream_kernel<T, 1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx);
     else
-      hipLaunchKernelGGL((gemm_stream_kernel<T, 2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+      hipLaunchKernelGGL((gemm_stream_kernel<T, 2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx);
   } else {
     if (tag == 0)
-      hipLaunchKernelGGL((gemm_tile_kernel<T, 0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+      hipLaunchKernelGGL((gemm_tile_kernel<T, 0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx);
     else if (tag == 1)
-      hipLaunchKernelGGL((gemm_tile_kernel<T, 1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+      hipLaunchKernelGGL((gemm_tile_kernel<T, 1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx);
     else
-      hipLaunchKernelGGL((gemm_tile_kernel<T, 2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+      hipLaunchKernelGGL((gemm_tile_kernel<T, 2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx);
   }
 }
 static void launch_gemm_bf3(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag,
-                            hipStream_t hs) {
+                            hipStream_t hs, int nx) {
   if (stream) {
     if (tag == 0)
-      hipLaunchKernelGGL((gemm_stream_bf3_kernel<0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+      hipLaunchKernelGGL((gemm_stream_bf3_kernel<0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx);
     else if (tag == 1)
-      hipLaunchKernelGGL((gemm_stream_bf3_kernel<1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+      hipLaunchKernelGGL((gemm_stream_bf3_kernel<1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx);
     else
-      hipLaunchKernelGGL((gemm_stream_bf3_kernel<2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart);
+      hipLaunchKernelGGL((gemm_stream_bf3_kernel<2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx);
   } else {
     if (tag == 0)
-      hipLaunchKernelGGL((gemm_tile_bf3_kernel<0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+      hipLaunchKernelGGL((gemm_tile_bf3_kernel<0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx);
     else if (tag == 1)
-      hipLaunchKernelGGL((gemm_tile_bf3_kernel<1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+      hipLaunchKernelGGL((gemm_tile_bf3_kernel<1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx);
     else
-      hipLaunchKernelGGL((gemm_tile_bf3_kernel<2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks);
+      hipLaunchKernelGGL((gemm_tile_bf3_kernel<2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx);
   }
 }
 
 void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag, bool f32,
-                 Stream st, bool bf3) {
+                 Stream st, bool bf3, int nx) {
   if (nwg <= 0) return;
   if (f32 && bf3)
-    launch_gemm_bf3(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st);
+    launch_gemm_bf3(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st, nx);
   else if (f32)
-    launch_gemm_t<float>(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st);
+    launch_gemm_t<float>(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st, nx);
   else
-    launch_gemm_t<double>(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st);
+    launch_gemm_t<double>(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st, nx);
   check_launch("gemm");
 }
 

@@ -357,3 +357,32 @@ def test_sigma_matches_oracle_on_wide_blocks():
     assert widest > 128
     assert orders == {"left", "right"}
     assert cuts > 0
+
+
+def test_xcd_order_gives_identical_sigma():
+    """The XCD-grouped workgroup order only changes which workgroup runs
+    which tile: sigma is bit for bit the same, and on the oracle's."""
+    L, N, twoS, group, irrep, D = 10, 10, 0, "C1", 0, 120
+    I = make_integrals(L, group, 11)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    for i in range(4):
+        dm.micro(i, D, "right")
+    g = _gpu(L, group, I)
+    g.set_target(N, twoS, irrep)
+    g.mps_import(sd.export_blob(dm))
+    g.prepare_step()
+    _, n = g.psi_layout()
+    x = np.random.default_rng(5).normal(size=n)
+    y0 = g.sigma(x)
+    for p1, p2 in ((1, 0), (0, 1), (1, 1)):
+        g.set_xcd_order(p1, p2)
+        g.prepare_step()
+        assert np.array_equal(g.sigma(x), y0)
+    El, Er, Xe, Ye, secs = dm.enlarged(4)
+    shapes = {m: (El.dim[m], Er.dim[m]) for m in secs}
+    ref = sd.flatten(sd.Heff(P, Xe, Ye, secs).apply(sd.unflatten(x, shapes, secs)), secs)
+    assert np.abs(y0 - ref).max() <= 1e-10 * np.abs(ref).max()
+    g.close()
+
