@@ -202,9 +202,11 @@ def batch_workload(n, seed):
     return specs
 
 
-def batch_bench(n, seed, prec, mixed_tol):
+def batch_bench(n, seed, prec, mixed_tol, graph=4):
     """One lockstep sweep of n problems (sadmrg_batch_sweep) against the same
-    problems swept one after another from the same states."""
+    problems swept one after another from the same states, and (graph > 0)
+    the same lockstep sweep again with the Davidson iterations replayed from
+    a recorded HIP graph, `graph` replays per host check."""
     from paper_1312_2415_amd import SaDMRG
     from paper_1312_2415_amd.binding import batch_sweep
     from synth.integrals import make_integrals
@@ -232,6 +234,29 @@ def batch_bench(n, seed, prec, mixed_tol):
     eb, st, _ = batch_sweep(gs, Ds)
     t_batch = time.perf_counter() - t0
     print(f"batch of {n}: lockstep sweep {t_batch:.2f}s", file=sys.stderr, flush=True)
+    rec = None
+    if graph > 0:
+        for g, b in zip(gs, blobs):
+            g.mps_import(b)
+            g.set_davidson_graph(graph)
+            g.stats_reset()
+        t0 = time.perf_counter()
+        eg, stg, _ = batch_sweep(gs, Ds)
+        t_graph = time.perf_counter() - t0
+        sg = [g.stats_graph() for g in gs]
+        rec = {"replays_per_host_check": graph, "s_per_lockstep_sweep": t_graph,
+               "speedup_vs_host_driven_lockstep": t_batch / t_graph,
+               "speedup_vs_separate_sweeps": None,
+               "recordings": int(sum(x["records"] for x in sg)),
+               "replayed_segment_seconds": float(sum(x["seconds"] for x in sg)),
+               "recording_host_seconds": float(sum(x["record_seconds"] for x in sg)),
+               "sigma_products_in_replays": int(sum(x["sigma_calls"] for x in sg)),
+               "host_phase_wall_seconds": stg["wall"],
+               "max_abs_dE_vs_host_driven_lockstep": float(max(abs(a - b) for a, b in zip(eg, eb)))}
+        print(f"batch of {n}: lockstep sweep with recorded Davidson iterations {t_graph:.2f}s", file=sys.stderr,
+              flush=True)
+        for g in gs:
+            g.set_davidson_graph(0)
     for g, b in zip(gs, blobs):
         g.mps_import(b)
     t0 = time.perf_counter()
@@ -242,6 +267,8 @@ def batch_bench(n, seed, prec, mixed_tol):
         g.close()
     t_sh = st["t_sigma"] + st["t_sigma32"]
     f_sh = st["flops_sigma"] + st["flops_sigma32"]
+    if rec is not None:
+        rec["speedup_vs_separate_sweeps"] = t_sep / rec["s_per_lockstep_sweep"]
     return {
         "workload": "independent problems, L uniform 10..20, N = L/2 rounded to even, S in {0,1}, "
                     "D_SU(2) uniform 128..1024, D2h round-robin orbital irreps, own integral seed each",
@@ -255,6 +282,7 @@ def batch_bench(n, seed, prec, mixed_tol):
         "shared_sigma_launches": st["n_sigma"] + st["n_sigma32"],
         "host_phase_wall_seconds": st["wall"],
         "max_abs_dE_lockstep_vs_separate": float(max(abs(a - b) for a, b in zip(eb, es))),
+        "recorded_davidson": rec,
         "L": [sp["L"] for sp in specs], "D": Ds,
     }
 
@@ -262,7 +290,7 @@ def batch_bench(n, seed, prec, mixed_tol):
 ROOT_TARGETS = [(2 * s, ir) for s in (0, 1, 2) for ir in (0, 1, 2, 3)]  # (2S, irrep) of the twelve roots
 
 
-def roots_bench(group, L, N, D, seed, warm, dav_tol, mixed_tol, refine=1):
+def roots_bench(group, L, N, D, seed, warm, dav_tol, mixed_tol, refine=1, refine_tol=0.0):
     """All twelve roots of the headline problem, in separate (S, irrep)
     sectors (S in {0, 1, 2} times four irreps), swept on one GPU in
     sequential lockstep groups of `group` (sadmrg_batch_sweep; a group fills
@@ -324,6 +352,7 @@ def roots_bench(group, L, N, D, seed, warm, dav_tol, mixed_tol, refine=1):
                 for g, b in zip(gs, blobs):
                     g.set_precision(mode, mixed_tol)
                     g.set_refinement(refine)
+                    g.set_refinement_tol(refine_tol)
                     g.mps_import(b)
                     n1.append(len(g.trace()))
                 t = time.perf_counter()
@@ -364,6 +393,7 @@ def roots_bench(group, L, N, D, seed, warm, dav_tol, mixed_tol, refine=1):
         "workload": f"the twelve roots of L={L} N={N} D2h D_SU(2)={D} (seed {seed}): (2S, irrep) in "
                     f"{[list(t) for t in ROOT_TARGETS]}, one GPU, lockstep groups of {group}",
         "roots": 12, "group": group, "warmup_lockstep_sweeps": warm, "fp64_refinement_steps": refine,
+        "fp64_refinement_residual_target": refine_tol,
         "s_per_lockstep_sweep_fp64": t64s, "s_per_lockstep_sweep_fp32": t32s,
         "s_per_lockstep_sweep_bf16x3": tb3s,
         "s_all_twelve_fp64": sum(t64s), "s_all_twelve_fp32": sum(t32s), "s_all_twelve_bf16x3": sum(tb3s),
@@ -603,11 +633,15 @@ def main():
     ap.add_argument("--batch-seed", type=int, default=4)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--only-batch", action="store_true", help="run only the lockstep batch record")
+    ap.add_argument("--graph", type=int, default=4, help="replays per host check of the recorded Davidson "
+                                                          "iterations in the batch record (0 = skip)")
     ap.add_argument("--roots", type=int, default=3, help="lockstep group size of the twelve-root record "
                                                          "(a divisor of 12; 0 = skip)")
     ap.add_argument("--roots-warmup", type=int, default=2)
     ap.add_argument("--refine", type=int, default=1, help="FP64 Davidson steps after the reduced-precision phase")
     ap.add_argument("--only-roots", action="store_true", help="run only the roots record")
+    ap.add_argument("--refine-tol", type=float, default=0.0, help="FP64 residual norm that ends the refinement "
+                                                                   "early (0 = always --refine steps)")
     ap.add_argument("--grad", type=int, default=4, help="integral orbits checked one by one by finite differences "
                                                         "in the energy-adjoint record at --grad-L orbitals (0 = skip)")
     ap.add_argument("--grad-dir", type=int, default=200, help="entries of the one multi-entry difference direction")
@@ -638,10 +672,11 @@ def main():
         return
     if args.only_roots:
         print(json.dumps({"roots": roots_bench(args.roots, args.L, args.N, args.D, args.seed, args.roots_warmup,
-                                               args.dav_tol, args.mixed_tol, args.refine)}), flush=True)
+                                               args.dav_tol, args.mixed_tol, args.refine, args.refine_tol)}),
+              flush=True)
         return
     if args.only_batch:  # the lockstep batch record alone (for profiling it)
-        print(json.dumps({"batch": batch_bench(max(args.batch_n, 1), args.batch_seed, 1, args.mixed_tol)}),
+        print(json.dumps({"batch": batch_bench(max(args.batch_n, 1), args.batch_seed, 1, args.mixed_tol, args.graph)}),
               flush=True)
         return
     if args.only_dmrgscf:
@@ -823,6 +858,7 @@ def main():
                                     "FP32 accumulation) in Davidson")):
             g.set_precision(mode, args.mixed_tol)
             g.set_refinement(args.refine)
+            g.set_refinement_tol(args.refine_tol)
             g.mps_import(start)
             g.stats_reset()
             n_done = len(g.trace())
@@ -848,6 +884,7 @@ def main():
                                     "and give its energy",
                 "mixed_tol": args.mixed_tol,
                 "fp64_refinement_steps": args.refine,
+                "fp64_refinement_residual_target": args.refine_tol,
                 "sweeps": nmix,
                 "s_per_sweep": sec_mixed,
                 "speedup_s_per_sweep": sec_per_sweep / sec_mixed,
@@ -869,7 +906,7 @@ def main():
             line[key] = rec
     g.close()
     if args.batch_n > 0:
-        line["batch"] = batch_bench(args.batch_n, args.batch_seed, 1, args.mixed_tol)
+        line["batch"] = batch_bench(args.batch_n, args.batch_seed, 1, args.mixed_tol, args.graph)
     # the extra records run last; after a failed record no further GPU work
     # that fills the device is started
     failed = False
@@ -878,7 +915,7 @@ def main():
                      ("dmrgscf", lambda: dmrgscf_bench(args.grad_L, N, args.scf_D, args.seed, args.scf_core,
                                                        args.scf_iter, 2, args.dav_tol) if args.scf_iter > 0 else None),
                      ("roots", lambda: roots_bench(args.roots, L, N, args.D, args.seed, args.roots_warmup,
-                                                   args.dav_tol, args.mixed_tol, args.refine)
+                                                   args.dav_tol, args.mixed_tol, args.refine, args.refine_tol)
                       if args.roots > 0 else None)):
         if failed:
             break

@@ -137,6 +137,39 @@ int sadmrg_set_precision(sadmrg_ctx* ctx, int mode, double mixed_tol);
  * early when a step cannot move the vector.  Contexts swept together by
  * sadmrg_batch_sweep must share it.  Errors: EINVAL. */
 int sadmrg_set_refinement(sadmrg_ctx* ctx, int steps);
+/* Davidson iterations replayed from a recorded launch sequence (section "The
+ * effective Hamiltonian equation": the iterative eigensolver of every
+ * micro-iteration).  replays = 0 (default): the host drives every
+ * iteration.  replays > 0: after the first sigma product, one whole
+ * iteration of every solve of the call (the lockstep solves of
+ * sadmrg_batch_sweep included) -- Ritz pair, residual, convergence test,
+ * preconditioned and orthogonalised correction, restart of a full subspace,
+ * sigma product of the new vector and its row of the projected matrix -- is
+ * recorded once per micro-iteration as a HIP graph that reads each solve's
+ * subspace size and flags from device memory, and replayed `replays` times
+ * between two host checks of those flags; a finished solve's kernels (its
+ * GEMM passes included) return at once.  Results are those of the
+ * host-driven iterations.  Not used on the legacy default stream (a null
+ * stream set by sadmrg_set_stream) or for one-element problems.  Contexts
+ * swept together by sadmrg_batch_sweep must share it.  Errors: EINVAL
+ * (replays outside 0..64). */
+int sadmrg_set_davidson_graph(sadmrg_ctx* ctx, int replays);
+/* Counters of the recorded iterations since sadmrg_stats_reset: seconds of
+ * the replayed segments (sigma products and every other step of them), host
+ * seconds spent recording and instantiating the sequences (a batch's times
+ * are split evenly over its contexts), the sigma flops and sigma products
+ * inside the replays, replays and recordings.  Pointers may be NULL. */
+int sadmrg_stats_graph(sadmrg_ctx* ctx, double* seconds, double* record_seconds, double* sigma_flops,
+                       int64_t* sigma_calls, int64_t* replays, int64_t* records);
+
+/* Residual target of that refinement (default 0: always the set number of
+ * steps).  With tol > 0, steps after the first run only while the FP64
+ * residual norm |H x - theta x| of the refined vector is above tol, up to
+ * the number set by sadmrg_set_refinement; a reduced-precision phase that
+ * stopped on its rounding floor (BF16x3 products) then gets the FP64 steps it
+ * needs to reach the residual an FP64 solve would have.  Contexts swept
+ * together by sadmrg_batch_sweep must share it.  Errors: EINVAL. */
+int sadmrg_set_refinement_tol(sadmrg_ctx* ctx, double tol);
 
 /* Seed of the counter-based generator used for the random initial MPS. */
 int sadmrg_set_seed(sadmrg_ctx* ctx, uint64_t seed);

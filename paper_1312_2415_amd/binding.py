@@ -89,6 +89,10 @@ def load_library(path: str | None = None):
         "sadmrg_stats_passes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_mixed": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl)]),
         "sadmrg_set_refinement": (c_int, [c_vp, c_int]),
+        "sadmrg_set_davidson_graph": (c_int, [c_vp, c_int]),
+        "sadmrg_stats_graph": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl), P(ctypes.c_int64), P(ctypes.c_int64),
+                                       P(ctypes.c_int64)]),
+        "sadmrg_set_refinement_tol": (c_int, [c_vp, c_dbl]),
         "sadmrg_set_precision": (c_int, [c_vp, c_int, c_dbl]),
         "sadmrg_rdm": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
         "sadmrg_get_s2": (c_int, [c_vp, P(c_dbl)]),
@@ -433,6 +437,24 @@ class SaDMRG:
         """0: FP64 sigma; 1 / 2: FP32 / BF16x3 sigma in Davidson, then one FP64
         Davidson step per micro-iteration (sadmrg_set_precision)."""
         self._chk(self.lib.sadmrg_set_precision(self.h, int(mode), float(mixed_tol)))
+
+    def set_davidson_graph(self, replays: int):
+        """Davidson iterations replayed from a recorded HIP graph, `replays`
+        per host check; 0 = host-driven (sadmrg_set_davidson_graph)."""
+        self._chk(self.lib.sadmrg_set_davidson_graph(self.h, int(replays)))
+
+    def stats_graph(self):
+        """Counters of the recorded Davidson iterations (sadmrg_stats_graph)."""
+        t, tr, f = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        n, r, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._chk(self.lib.sadmrg_stats_graph(self.h, ctypes.byref(t), ctypes.byref(tr), ctypes.byref(f),
+                                              ctypes.byref(n), ctypes.byref(r), ctypes.byref(c)))
+        return {"seconds": t.value, "record_seconds": tr.value, "sigma_flops": f.value, "sigma_calls": n.value,
+                "replays": r.value, "records": c.value}
+
+    def set_refinement_tol(self, tol: float):
+        """Residual target of the FP64 refinement (sadmrg_set_refinement_tol)."""
+        self._chk(self.lib.sadmrg_set_refinement_tol(self.h, float(tol)))
 
     def set_refinement(self, steps: int):
         """FP64 Davidson steps after the reduced-precision phase (modes 1, 2)."""

@@ -1785,7 +1785,16 @@ struct Engine {
   int prec = 0;             // 0: FP64 sigma; 1 / 2: FP32 / BF16x3 sigma in Davidson + FP64 refinement
   double mixed_tol = 1e-5;  // Davidson tolerance of the FP32 phase
   int refine_steps = 1;     // FP64 Davidson steps after the FP32 phase
+  double refine_tol = 0.0;  // > 0: refinement steps stop once the FP64 residual norm is below it
   int64_t n_sigma = 0;
+  // Davidson iterations replayed from a recorded launch sequence (0: the
+  // host drives every iteration; k > 0: k replays between host checks)
+  int dav_graph = 0;
+  double t_dgraph = 0.0;  // seconds of the replayed segments (sigma and the rest)
+  double t_dgraph_rec = 0.0;  // host seconds spent recording and instantiating
+  Stream cap_stream = nullptr;  // recording stream when the work runs on the default stream
+  double f_dgraph = 0.0;  // sigma flops inside them
+  int64_t n_dgraph_sigma = 0, n_dgraph_replay = 0, n_dgraph_record = 0;
   // Davidson work buffers
   DBuf dV, dW, dHs, dsmall, dpartial, dx_, dax, dr, dt;
   double* hpin = nullptr;   // page-locked scalars read back after a stream sync
@@ -1822,6 +1831,7 @@ struct Engine {
     clear_enl_cache();
     stage.reset();
     host_free_pinned(hpin);
+    dev_stream_destroy(cap_stream);
   }
 
   void drop_cache_entry(EnlCache& c) {
@@ -3462,6 +3472,35 @@ struct Engine {
     sigma_fixed(f32);
     dev_d2d(y, step.out.p, (size_t)step.n * 8, st);
   }
+  // The launches of sigma_fixed (step.in to step.out) with no host wait, no
+  // allocation and no timing events, for a recorded sequence; the GEMM
+  // passes do nothing while *gate != 0.  record_prepare() first makes the
+  // buffers it uses.
+  void record_prepare(bool f32) {
+    if (step.p2_pending) fail(-1, "internal: sigma plan incomplete");
+    if (f32) ensure_f32();
+    if (step.nproj) {
+      projc.ensure(64);
+      projpart.ensure(256 * 64);
+    }
+  }
+  void sigma_record(bool f32, const int* gate) {
+    const GemmList::Plan& p1 = f32 ? step.q1 : step.plan.p1;
+    const GemmList::Plan& p2 = f32 ? step.q2 : step.plan.p2;
+    if (f32) {
+      launch_cvt_d2f((float*)step.in32.p, step.in.p, step.n, st);
+      dev_zero(step.out32.p, step.out32.n * 8, st);
+    } else {
+      dev_zero(step.out.p, (size_t)std::max<int64_t>(step.n, 1) * 8, st);
+    }
+    const bool bf3 = f32 && prec == 2;
+    launch_gemm(p1.tiles.p, p1.tasks.p, p1.wstart.p, p1.nwg, p1.stream, p1.tag, p1.f32, st, f32 && bf3, p1.xcd, gate);
+    launch_reduce(p1.reds.p, p1.nreds, p1.f32, st, gate);
+    launch_gemm(p2.tiles.p, p2.tasks.p, p2.wstart.p, p2.nwg, p2.stream, p2.tag, p2.f32, st, bf3, p2.xcd, gate);
+    launch_reduce(p2.reds.p, p2.nreds, p2.f32, st, gate);
+    if (f32) launch_cvt_f2d(step.out.p, (const float*)step.out32.p, step.n, st);
+    add_projectors(step.in.p, step.out.p);
+  }
   // the parts of sigma_vec around the two GEMM passes, for a launch shared
   // with other engines (same operations in the same order)
   void sigma_in(const double* x, bool f32) {
@@ -3755,6 +3794,7 @@ struct Engine {
   void refine_dir(const double* x) {
     const int64_t n = step.n;
     launch_residual(dr.p, x, dav_evals(), n, dt.p, st);
+    if (refine_tol > 0.0) launch_dots(dt.p, n, 1, dt.p, n, dav_nrm(), dpartial.p, st);  // |r|^2 of x
     launch_precond(dt.p, step.diag.p, dav_evals(), n, dt.p, st);
     for (int pass = 0; pass < 2; ++pass) {
       launch_dots(x, n, 1, dt.p, n, dav_coef(), dpartial.p, st);
@@ -3802,11 +3842,18 @@ struct Engine {
     if (moved) *moved = true;
     return lam;
   }
+  // the residual norm of the vector refine_dir last worked on (synchronises)
+  double refine_residual() {
+    double r2 = 0.0;
+    dev_d2h(&r2, dav_nrm(), 8, st);
+    return std::sqrt(std::max(0.0, r2));
+  }
   double refine64(double* x) {
     sigma_vec(x, dr.p, false);
-    double th = 0.0;
+    double th = NAN;
     for (int k = 0; k < refine_steps; ++k) {
       refine_dir(x);
+      if (refine_tol > 0.0 && k > 0 && refine_residual() <= refine_tol) break;
       sigma_vec(dt.p, dax.p, false);
       refine_dots(x);
       dev_sync(st);
@@ -4095,6 +4142,30 @@ struct BatchLaunch {
   // around the GEMM passes as job lists)
   void sigma(const std::vector<Engine*>& E, const std::vector<const double*>& x, const std::vector<double*>& y,
              bool use32);
+
+  // The shared sigma of step.in into step.out of every engine as launches
+  // with no host work, for a recorded sequence: descriptors and job lists
+  // are uploaded once (prepare), then launched (record) as often as needed;
+  // gates[e]: engine e's GEMM workgroups do nothing while *gates[e] != 0.
+  // The arrays live in the staging area sg (valid until its next reset).
+  struct Rec {
+    const GSeg *s1 = nullptr, *s2 = nullptr, *sr = nullptr;
+    const int *b1 = nullptr, *b2 = nullptr, *br = nullptr;
+    const EwJob *pre = nullptr, *post = nullptr;
+    int ns1 = 0, ns2 = 0, nsr = 0, npre = 0, npost = 0;
+    int nw1 = 0, nw2 = 0, nr = 0;
+    bool stream2 = true, use32 = false, bf3 = false;
+    int64_t maxn = 0;
+  };
+  void record_prepare(Rec& r, const std::vector<Engine*>& E, bool use32, const std::vector<const int*>& gates,
+                      Staging& sg);
+  void record(const Rec& r) const {
+    launch_ew_batch(r.pre, r.npre, r.maxn, st);
+    launch_gemm_seg(r.s1, r.b1, r.ns1, r.nw1, false, r.use32, st, r.bf3);
+    launch_gemm_seg(r.s2, r.b2, r.ns2, r.nw2, r.stream2, r.use32, st, r.bf3);
+    launch_reduce_seg(r.sr, r.br, r.nsr, r.nr, r.use32, st);
+    launch_ew_batch(r.post, r.npost, r.maxn, st);
+  }
 };
 
 // host threads for the per-engine parts of a batched micro-iteration
@@ -4194,6 +4265,60 @@ void BatchLaunch::sigma(const std::vector<Engine*>& E, const std::vector<const d
   ew.run(stage, st);
 }
 
+void BatchLaunch::record_prepare(Rec& r, const std::vector<Engine*>& E, bool use32,
+                                 const std::vector<const int*>& gates, Staging& sg) {
+  std::vector<GSeg> s1, s2, sr;
+  std::vector<int> b1, b2, br;
+  std::vector<EwJob> pre, post;
+  r = Rec();
+  r.use32 = use32;
+  r.bf3 = use32 && !E.empty() && E[0]->prec == 2;
+  for (size_t k = 0; k < E.size(); ++k) {
+    Engine& e = *E[k];
+    {
+      PoolBind b(e.pool);
+      e.record_prepare(use32);
+    }
+    const Step& S = e.step;
+    const GemmList::Plan& p1 = use32 ? S.q1 : S.plan.p1;
+    const GemmList::Plan& p2 = use32 ? S.q2 : S.plan.p2;
+    if (p1.stream || p1.nreds != 0) fail(-1, "internal: first pass must be one tile per workgroup");
+    r.stream2 = p2.stream;
+    if (p1.nwg > 0) {
+      s1.push_back({p1.tiles.p, p1.tasks.p, nullptr, nullptr, gates[k]});
+      b1.push_back(r.nw1);
+      r.nw1 += p1.nwg;
+    }
+    if (p2.nwg > 0) {
+      s2.push_back({p2.tiles.p, p2.tasks.p, p2.wstart.p, nullptr, gates[k]});
+      b2.push_back(r.nw2);
+      r.nw2 += p2.nwg;
+    }
+    if (p2.nreds > 0) {
+      sr.push_back({nullptr, nullptr, nullptr, p2.reds.p, gates[k]});
+      br.push_back(r.nr);
+      r.nr += p2.nreds;
+    }
+    const int64_t n = S.n;
+    r.maxn = std::max(r.maxn, std::max<int64_t>(n, (int64_t)S.out32.n));
+    if (use32) {
+      pre.push_back({S.in.p, nullptr, nullptr, S.in32.p, n, EW_D2F});
+      pre.push_back({nullptr, nullptr, nullptr, S.out32.p, (int64_t)S.out32.n, EW_ZERO});
+      post.push_back({S.out32.p, nullptr, nullptr, S.out.p, n, EW_F2D});
+    } else {
+      pre.push_back({nullptr, nullptr, nullptr, S.out.p, std::max<int64_t>(n, 1), EW_ZERO});
+    }
+  }
+  r.s1 = sg.up(s1), r.ns1 = (int)s1.size();
+  r.s2 = sg.up(s2), r.ns2 = (int)s2.size();
+  r.sr = sg.up(sr), r.nsr = (int)sr.size();
+  r.b1 = sg.up(b1);
+  r.b2 = sg.up(b2);
+  r.br = sg.up(br);
+  r.pre = sg.up(pre), r.npre = (int)pre.size();
+  r.post = sg.up(post), r.npost = (int)post.size();
+}
+
 // Davidson solves of engines that share one stream, in lockstep.  Every
 // stage is one launch over all solves that take part in it (the helpers'
 // job-list forms, each job with the arithmetic of the single-solve kernel),
@@ -4290,8 +4415,184 @@ static void davidson_lockstep(const std::vector<Engine*>& E, std::vector<DavStat
   for (size_t k : all) ew.add(EW_NORMALIZE, nullptr, nullptr, E[k]->dav_nrm(), E[k]->dV.p, N(k));
   ew.run(sg, st);
   sigma_round(all);
-
   std::vector<size_t> act, cont, fin, next;
+
+  // Recorded iterations: one iteration of every solve (Ritz pair, residual,
+  // convergence test, correction, restart, sigma, new row) is recorded once
+  // as a fixed launch sequence that reads each solve's state from device
+  // memory, and replayed dav_graph times between two host checks; the host
+  // only finishes the solves that the replays marked done.  The arithmetic
+  // is that of the host-driven loop below, step for step.
+  bool graph = E[0]->dav_graph > 0;
+  for (size_t k : all) graph = graph && N(k) > 1 && D[k].f32 == D[0].f32;
+  if (graph) {
+    const int seg = E[0]->dav_graph;
+    const bool use32 = D[0].f32;
+    PoolBind pb(sg.pool);
+    std::vector<DGState> hs(ne);
+    int msmax = 1;
+    int64_t nmax = 1;
+    for (size_t k : all) {
+      hs[k] = DGState{D[k].k, D[k].it, 0, 0, 0, 0, 0, 0, INFINITY, 0.0};
+      msmax = std::max(msmax, D[k].ms);
+      nmax = std::max(nmax, N(k));
+    }
+    // the state and job arrays stay in the staging area until the final sync
+    DGState* const dst = const_cast<DGState*>(sg.up(hs));
+    std::vector<DGJob> hj(ne);
+    std::vector<const int*> gates(ne);
+    for (size_t k : all) {
+      Engine& g = *E[k];
+      gates[k] = &dst[k].done;
+      hj[k] = DGJob{dst + k, g.dV.p, g.dW.p, g.dHs.p, g.dav_evals(), g.dav_evecs(), g.dav_coef(), g.dav_nrm(),
+                    g.dav_nrm2(), g.dx_.p, g.dax.p, g.dr.p, g.dt.p, g.dpartial.p, g.step.diag.p, g.step.in.p,
+                    g.step.out.p, N(k), D[k].ms, g.dav_max_iter, use32 ? 1 : 0, 0, D[k].tol, D[k].eps};
+    }
+    const DGJob* const J = sg.up(hj);
+    const bool shared = bl && ne > 1;
+    BatchLaunch::Rec rec;
+    if (shared) {
+      bl->record_prepare(rec, E, use32, gates, sg);
+    } else {
+      for (size_t k : all) {
+        PoolBind b(E[k]->pool);
+        E[k]->record_prepare(use32);
+      }
+    }
+    const int nj = (int)ne;
+    const int C = DG_GATE_COLLAPSE, R = DG_GATE_RESTART;
+    // The legacy default stream cannot be recorded: the sequence is then
+    // recorded on a stream of its own (recording runs nothing) and replayed
+    // on the default stream.  The engines (and the shared launch) record on
+    // that stream while the recording lasts.
+    struct Capture {  // ends an interrupted recording, restores the streams, frees the graph
+      Stream st, rs = nullptr;
+      const std::vector<Engine*>& E;
+      BatchLaunch* bl;
+      bool open = false, swapped = false;
+      void* ex = nullptr;
+      Capture(Stream s, const std::vector<Engine*>& e, BatchLaunch* b) : st(s), E(e), bl(b) {}
+      void begin() {
+        rs = st;
+        if (!st) {
+          if (!E[0]->cap_stream) E[0]->cap_stream = dev_stream_create();
+          rs = E[0]->cap_stream;
+          for (Engine* e : E) e->st = rs;
+          if (bl) bl->st = rs;
+          swapped = true;
+        }
+        dev_capture_begin(rs);
+        open = true;
+      }
+      void restore() {
+        if (!swapped) return;
+        for (Engine* e : E) e->st = st;
+        if (bl) bl->st = st;
+        swapped = false;
+      }
+      void end() {
+        open = false;
+        ex = dev_capture_end(rs);
+        restore();
+      }
+      ~Capture() {
+        if (open) dev_capture_abort(rs);
+        restore();
+        dev_graph_free(ex);
+      }
+    } cap(st, E, bl);
+    const auto tr0 = std::chrono::steady_clock::now();
+    cap.begin();
+    {
+      const Stream st = cap.rs;  // the recording stream, for the launches of this block
+      launch_dg_scalar(J, nj, DG_TOP, st);
+      launch_dg_syev(J, nj, st);
+      launch_dg_combo(J, nj, DGC_RITZ_X, 0, nmax, st);
+      launch_dg_combo(J, nj, DGC_RITZ_AX, 0, nmax, st);
+      launch_dg_ew(J, nj, DGE_RESIDUAL, 0, nmax, st);
+      launch_dg_dots(J, nj, DGD_RR, 0, 1, st);
+      launch_dg_scalar(J, nj, DG_CHECK, st);
+      launch_dg_ew(J, nj, DGE_PRECOND, 0, nmax, st);
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_dg_dots(J, nj, DGD_VT, 0, msmax, st);
+        launch_dg_combo(J, nj, DGC_ORTH, 0, nmax, st);
+      }
+      launch_dg_dots(J, nj, DGD_TT, 0, 1, st);
+      launch_dg_scalar(J, nj, DG_COLLAPSE, st);
+      launch_dg_ew(J, nj, DGE_COPY_RT, C, nmax, st);  // the residual itself instead
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_dg_dots(J, nj, DGD_VT, C, msmax, st);
+        launch_dg_combo(J, nj, DGC_ORTH, C, nmax, st);
+      }
+      launch_dg_dots(J, nj, DGD_TT, C, 1, st);
+      launch_dg_scalar(J, nj, DG_COLLAPSE2, st);
+      launch_dg_ew(J, nj, DGE_NORMALIZE_T, 0, nmax, st);
+      launch_dg_scalar(J, nj, DG_RESTART_FLAG, st);
+      launch_dg_ew(J, nj, DGE_RESTART_COPY, R, nmax, st);  // V_0 = x, W_0 = Ax
+      launch_dg_dots(J, nj, DGD_V0W0, R, 1, st);
+      launch_dg_dots(J, nj, DGD_V0T, R, 1, st);
+      launch_dg_combo(J, nj, DGC_ORTH0, R, nmax, st);
+      launch_dg_dots(J, nj, DGD_TT, R, 1, st);
+      launch_dg_ew(J, nj, DGE_NORMALIZE_T, R, nmax, st);
+      launch_dg_scalar(J, nj, DG_RESTART_K, st);
+      launch_dg_ew(J, nj, DGE_APPEND, 0, nmax, st);
+      launch_dg_ew(J, nj, DGE_LOAD, 0, nmax, st);
+      if (shared)
+        bl->record(rec);
+      else
+        for (size_t k : all) E[k]->sigma_record(use32, gates[k]);
+      launch_dg_ew(J, nj, DGE_STORE, 0, nmax, st);
+      launch_dg_dots(J, nj, DGD_ROW, 0, msmax, st);
+      launch_dg_scalar(J, nj, DG_ADVANCE, st);
+    }
+    cap.end();
+    void* const ex = cap.ex;
+    const double trec = std::chrono::duration<double>(std::chrono::steady_clock::now() - tr0).count();
+    for (size_t k : all) {
+      ++E[k]->n_dgraph_record;
+      E[k]->t_dgraph_rec += trec / (double)ne;
+    }
+    std::vector<DGState> prev = hs;
+    while (true) {
+      void* e0 = dev_event_record(st);
+      for (int r = 0; r < seg; ++r) dev_graph_launch(ex, st);
+      void* e1 = dev_event_record(st);
+      sc.clear();
+      for (size_t k : all) sc.push_back(E[k]->dav_evals());
+      sg.fetch(sc);
+      dev_d2h(hs.data(), dst, ne * sizeof(DGState), st);  // waits for the stream
+      const double tseg = dev_event_elapsed(e0, e1);
+      dev_event_free(e0);
+      dev_event_free(e1);
+      std::vector<double> th(sg.shost, sg.shost + ne);
+      fin.clear();
+      bool live = false;
+      for (size_t k : all) {
+        Engine& g = *E[k];
+        const int nsig = hs[k].it - prev[k].it;
+        g.t_dgraph += tseg / (double)ne;
+        g.n_dgraph_replay += seg;
+        g.n_dgraph_sigma += nsig;
+        g.f_dgraph += nsig * g.step.flops;
+        if (D[k].done) continue;
+        if (hs[k].done) {
+          D[k].theta = th[k];
+          D[k].k = hs[k].k;
+          D[k].it = hs[k].state == 2 ? g.dav_max_iter : hs[k].it;
+          D[k].conv = hs[k].state != 2;
+          fin.push_back(k);
+        } else {
+          live = true;
+        }
+      }
+      finish(fin);
+      prev = hs;
+      if (!live) break;
+    }
+    sync();
+    return;
+  }
+
   while (true) {
     act.clear();
     fin.clear();
@@ -4527,6 +4828,7 @@ static bool batch_sweep(const std::vector<Engine*>& E, const std::vector<int>& D
       }
       shared_sigma(xs, ys);
       const int steps = E[0]->refine_steps;
+      const double rtol = E[0]->refine_tol;
       std::vector<char> live(na, 1);  // still refining (a step that could not move x ends it)
       for (int k = 0; k < steps; ++k) {
         std::vector<Engine*> ek;
@@ -4536,6 +4838,20 @@ static bool batch_sweep(const std::vector<Engine*>& E, const std::vector<int>& D
           if (!live[j]) continue;
           PoolBind b(ea[j]->pool);
           ea[j]->refine_dir(xb[j].p);
+        }
+        if (rtol > 0.0 && k > 0) {  // residual norms of the refined vectors: done below rtol
+          std::vector<const double*> rn;
+          std::vector<size_t> idx;
+          for (size_t j = 0; j < na; ++j)
+            if (live[j]) rn.push_back(ea[j]->dav_nrm()), idx.push_back(j);
+          bl.stage.fetch(rn);
+          dev_sync(bl.st);
+          for (size_t q = 0; q < idx.size(); ++q)
+            if (std::sqrt(std::max(0.0, bl.stage.shost[q])) <= rtol) live[idx[q]] = 0;
+          bl.stage.reset();
+        }
+        for (size_t j = 0; j < na; ++j) {
+          if (!live[j]) continue;
           ek.push_back(ea[j]);
           tk.push_back(ts[j]);
           wk.push_back(ws[j]);
@@ -4989,8 +5305,9 @@ int sadmrg_batch_sweep(sadmrg_ctx* const* ctxs, int n, const int* D, double* e_m
     if (D[k] < 1) return fail_all(SADMRG_EINVAL, "D must be positive");
     if (e.device != e0.device || e.st != e0.st)
       return fail_all(SADMRG_EINVAL, "batched contexts must share one device and one stream");
-    if (e.prec != e0.prec || e.refine_steps != e0.refine_steps)
-      return fail_all(SADMRG_EINVAL, "batched contexts must share one precision mode and refinement");
+    if (e.prec != e0.prec || e.refine_steps != e0.refine_steps || e.refine_tol != e0.refine_tol ||
+        e.dav_graph != e0.dav_graph)
+      return fail_all(SADMRG_EINVAL, "batched contexts must share one precision mode, refinement and recording");
   }
   try {
     std::vector<sadmrg::Engine*> E;
@@ -5694,6 +6011,36 @@ int sadmrg_set_refinement(sadmrg_ctx* ctx, int steps) {
   });
 }
 
+int sadmrg_set_davidson_graph(sadmrg_ctx* ctx, int replays) {
+  return guard(ctx, [&] {
+    if (replays < 0 || replays > 64) sadmrg::fail(SADMRG_EINVAL, "replays must be in 0..64");
+    ctx->e.dav_graph = replays;
+    return 0;
+  });
+}
+
+int sadmrg_stats_graph(sadmrg_ctx* ctx, double* seconds, double* record_seconds, double* sigma_flops,
+                       int64_t* sigma_calls, int64_t* replays, int64_t* records) {
+  return guard(ctx, [&] {
+    const auto& E = ctx->e;
+    if (seconds) *seconds = E.t_dgraph;
+    if (record_seconds) *record_seconds = E.t_dgraph_rec;
+    if (sigma_flops) *sigma_flops = E.f_dgraph;
+    if (sigma_calls) *sigma_calls = E.n_dgraph_sigma;
+    if (replays) *replays = E.n_dgraph_replay;
+    if (records) *records = E.n_dgraph_record;
+    return 0;
+  });
+}
+
+int sadmrg_set_refinement_tol(sadmrg_ctx* ctx, double tol) {
+  return guard(ctx, [&] {
+    if (!(tol >= 0.0) || !std::isfinite(tol)) sadmrg::fail(SADMRG_EINVAL, "refinement tolerance must be >= 0");
+    ctx->e.refine_tol = tol;
+    return 0;
+  });
+}
+
 int sadmrg_stats_mixed(sadmrg_ctx* ctx, double* t_sigma32, int64_t* n_sigma32, double* flops_sigma32) {
   return guard(ctx, [&] {
     if (t_sigma32) *t_sigma32 = ctx->e.t_sigma32;
@@ -5770,6 +6117,8 @@ int sadmrg_stats_reset(sadmrg_ctx* ctx) {
     E.n_sigma32 = 0;
     E.n_sigma = 0;
     E.f_method = E.f_method_perf = 0;
+    E.t_dgraph = E.f_dgraph = E.t_dgraph_rec = 0;
+    E.n_dgraph_sigma = E.n_dgraph_replay = E.n_dgraph_record = 0;
     for (double& t : E.t_phase) t = 0.0;
     return 0;
   });

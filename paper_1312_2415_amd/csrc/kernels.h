@@ -165,11 +165,12 @@ struct GTask {
 // nx > 1: workgroups are ordered so that consecutive tiles (or ranges) run
 // on one of nx XCDs (the dispatcher deals workgroups to the XCDs in turn);
 // results do not depend on it.
+// gate (device int, optional): the launch does nothing while *gate != 0
 void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag, bool f32,
-                 Stream st, bool bf3 = false, int nx = 0);
+                 Stream st, bool bf3 = false, int nx = 0, const int* gate = nullptr);
 // Number of compute units of the current device.
 int dev_cu_count();
-void launch_reduce(const RTile* reds, int nred, bool f32, Stream st);
+void launch_reduce(const RTile* reds, int nred, bool f32, Stream st, const int* gate = nullptr);
 // Several independent plans in one launch: plan s owns the workgroups
 // [base[s], base[s+1]) of the grid (base ascending from 0, nwg in total) and
 // reads its own records: tiles + tasks (+ wstart when stream) for the GEMM,
@@ -179,6 +180,7 @@ struct GSeg {
   const GTask* tasks;
   const int* wstart;
   const RTile* reds;
+  const int* gate;  // optional: the plan's workgroups do nothing while *gate != 0
 };
 void launch_gemm_seg(const GSeg* segs, const int* base, int nseg, int nwg, bool stream, bool f32, Stream st,
                      bool bf3 = false);
@@ -259,6 +261,68 @@ struct SyevJob {
   int k, ld;
 };
 void launch_syev_batch(const SyevJob* jobs, int njobs, Stream st);
+// ---- Davidson iterations as one fixed launch sequence (recorded once into a
+// graph and replayed).  Each solve keeps its subspace size and flags in
+// device memory; the kernels read them, so the same sequence serves every
+// iteration, and a finished solve's kernels return at once.  Every kernel
+// does exactly the arithmetic of the job-list helpers above.
+struct DGState {
+  int k;         // vectors in the subspace
+  int it;        // iteration number
+  int done;      // nonzero: the solve has finished
+  int state;     // 1 converged, 2 out of iterations, 3 residual vanished
+  int collapse;  // the preconditioned residual vanished: the residual is tried
+  int restart;   // the subspace is full: restart from the Ritz vector
+  int stall;     // reduced-precision floor: iterations without 10 % progress
+  int pad;
+  double rbest;  // best residual norm near the reduced-precision floor
+  double pad2;
+};
+struct DGJob {
+  DGState* s;
+  double* V;  // ms vectors of length n (ld n)
+  double* W;  // their sigma images
+  double* Hs;  // projected matrix, lower triangle, ld ms
+  double* evals;
+  double* evecs;
+  double* coef;
+  double* nrm;   // |r|^2
+  double* nrm2;  // |t|^2
+  double* x;
+  double* ax;
+  double* r;
+  double* t;
+  double* part;  // 256 * ms partial sums
+  const double* diag;
+  double* in;         // the sigma input of the problem
+  const double* out;  // and its output
+  int64_t n;
+  int ms, max_it, f32, pad;
+  double tol, eps;
+};
+// scalar steps (one thread per solve)
+enum : int { DG_TOP = 0, DG_CHECK, DG_COLLAPSE, DG_COLLAPSE2, DG_RESTART_FLAG, DG_RESTART_K, DG_ADVANCE };
+// inner products
+enum : int { DGD_ROW = 0, DGD_RR, DGD_VT, DGD_TT, DGD_V0W0, DGD_V0T };
+// element-wise steps
+enum : int { DGE_PRECOND = 0, DGE_COPY_RT, DGE_NORMALIZE_T, DGE_RESTART_COPY, DGE_APPEND, DGE_LOAD, DGE_STORE,
+             DGE_RESIDUAL };
+// linear combinations
+enum : int { DGC_RITZ_X = 0, DGC_RITZ_AX, DGC_ORTH, DGC_ORTH0 };
+// extra condition of a step: none, the collapse flag, the restart flag
+enum : int { DG_GATE_NONE = 0, DG_GATE_COLLAPSE, DG_GATE_RESTART };
+void launch_dg_scalar(const DGJob* jobs, int njobs, int which, Stream st);
+void launch_dg_dots(const DGJob* jobs, int njobs, int which, int gate, int max_k, Stream st);
+void launch_dg_ew(const DGJob* jobs, int njobs, int which, int gate, int64_t max_n, Stream st);
+void launch_dg_combo(const DGJob* jobs, int njobs, int which, int gate, int64_t max_n, Stream st);
+void launch_dg_syev(const DGJob* jobs, int njobs, Stream st);
+// Stream capture into a graph and its replay
+void dev_capture_begin(Stream st);
+void* dev_capture_end(Stream st);  // instantiated graph
+void dev_capture_abort(Stream st);  // ends a recording and drops it
+void dev_graph_launch(void* exec, Stream st);
+void dev_graph_free(void* exec);
+
 // dst[i] = *src[i], i < n (src: device array of device pointers)
 void launch_scalars(const double* const* src, int n, double* dst, Stream st);
 // uniform [-1,1) numbers from the SplitMix64 counter generator

@@ -739,15 +739,21 @@ __device__ __forceinline__ void gemm_tile_body(const GTile* __restrict__ tiles, 
   if (active) g_write<T>(g_out(tile), acc, r0, li, lk);
 }
 
+// gate: when given and nonzero the launch does nothing (a finished solve in a
+// recorded Davidson sequence)
 template <typename T, int TAG>
 __global__ __launch_bounds__(256, 4) void gemm_tile_kernel(const GTile* __restrict__ tiles,
-                                                           const GTask* __restrict__ tasks, int nx) {
+                                                           const GTask* __restrict__ tasks, int nx,
+                                                           const int* __restrict__ gate) {
+  if (gate && *gate) return;
   gemm_tile_body<T>(tiles, tasks, xcd_item(blockIdx.x, gridDim.x, nx));
 }
 // the same with BF16x3 products on FP32 data
 template <int TAG>
 __global__ __launch_bounds__(256, 4) void gemm_tile_bf3_kernel(const GTile* __restrict__ tiles,
-                                                               const GTask* __restrict__ tasks, int nx) {
+                                                               const GTask* __restrict__ tasks, int nx,
+                                                               const int* __restrict__ gate) {
+  if (gate && *gate) return;
   gemm_tile_body<float, true>(tiles, tasks, xcd_item(blockIdx.x, gridDim.x, nx));
 }
 
@@ -869,13 +875,17 @@ __device__ __forceinline__ void gemm_stream_body(const GTile* __restrict__ tiles
 template <typename T, int TAG>
 __global__ __launch_bounds__(256, 3) void gemm_stream_kernel(const GTile* __restrict__ tiles,
                                                              const GTask* __restrict__ tasks,
-                                                             const int* __restrict__ wstart, int nx) {
+                                                             const int* __restrict__ wstart, int nx,
+                                                             const int* __restrict__ gate) {
+  if (gate && *gate) return;
   gemm_stream_body<T>(tiles, tasks, wstart, xcd_item(blockIdx.x, gridDim.x, nx));
 }
 template <int TAG>
 __global__ __launch_bounds__(256, 3) void gemm_stream_bf3_kernel(const GTile* __restrict__ tiles,
                                                                  const GTask* __restrict__ tasks,
-                                                                 const int* __restrict__ wstart, int nx) {
+                                                                 const int* __restrict__ wstart, int nx,
+                                                                 const int* __restrict__ gate) {
+  if (gate && *gate) return;
   gemm_stream_body<float, true>(tiles, tasks, wstart, xcd_item(blockIdx.x, gridDim.x, nx));
 }
 
@@ -903,6 +913,7 @@ struct GSegDev {
   const G_GLOBAL GTask* tasks;
   const G_GLOBAL int* wstart;
   const G_GLOBAL RTile* reds;
+  const G_GLOBAL int* gate;
 };
 static_assert(sizeof(GSegDev) == sizeof(GSeg), "descriptor layout");
 
@@ -911,6 +922,7 @@ __device__ __forceinline__ void gemm_tile_seg_body(const GSeg* __restrict__ segs
                                                                const int* __restrict__ base, int nseg) {
   const int s = seg_find(base, nseg, blockIdx.x);
   const GSegDev* const d = (const GSegDev*)segs;
+  if (d[s].gate && *d[s].gate) return;
   gemm_tile_body<T, BF3>((const GTile*)d[s].tiles, (const GTask*)d[s].tasks, blockIdx.x - base[s]);
 }
 
@@ -919,6 +931,7 @@ __device__ __forceinline__ void gemm_stream_seg_body(const GSeg* __restrict__ se
                                                                  const int* __restrict__ base, int nseg) {
   const int s = seg_find(base, nseg, blockIdx.x);
   const GSegDev* const d = (const GSegDev*)segs;
+  if (d[s].gate && *d[s].gate) return;
   gemm_stream_body<T, BF3>((const GTile*)d[s].tiles, (const GTask*)d[s].tasks, (const int*)d[s].wstart,
                       blockIdx.x - base[s]);
 }
@@ -944,51 +957,51 @@ __global__ __launch_bounds__(256, 3) void gemm_stream_seg_bf3_kernel(const GSeg*
 
 template <typename T>
 static void launch_gemm_t(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag,
-                          hipStream_t hs, int nx) {
+                          hipStream_t hs, int nx, const int* gate) {
   if (stream) {
     if (tag == 0)
-      hipLaunchKernelGGL((gemm_stream_kernel<T, 0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx);
+      hipLaunchKernelGGL((gemm_stream_kernel<T, 0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx, gate);
     else if (tag == 1)
-      hipLaunchKernelGGL((gemm_stream_kernel<T, 1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx);
+      hipLaunchKernelGGL((gemm_stream_kernel<T, 1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx, gate);
     else
-      hipLaunchKernelGGL((gemm_stream_kernel<T, 2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx);
+      hipLaunchKernelGGL((gemm_stream_kernel<T, 2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx, gate);
   } else {
     if (tag == 0)
-      hipLaunchKernelGGL((gemm_tile_kernel<T, 0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx);
+      hipLaunchKernelGGL((gemm_tile_kernel<T, 0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx, gate);
     else if (tag == 1)
-      hipLaunchKernelGGL((gemm_tile_kernel<T, 1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx);
+      hipLaunchKernelGGL((gemm_tile_kernel<T, 1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx, gate);
     else
-      hipLaunchKernelGGL((gemm_tile_kernel<T, 2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx);
+      hipLaunchKernelGGL((gemm_tile_kernel<T, 2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx, gate);
   }
 }
 static void launch_gemm_bf3(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag,
-                            hipStream_t hs, int nx) {
+                            hipStream_t hs, int nx, const int* gate) {
   if (stream) {
     if (tag == 0)
-      hipLaunchKernelGGL((gemm_stream_bf3_kernel<0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx);
+      hipLaunchKernelGGL((gemm_stream_bf3_kernel<0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx, gate);
     else if (tag == 1)
-      hipLaunchKernelGGL((gemm_stream_bf3_kernel<1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx);
+      hipLaunchKernelGGL((gemm_stream_bf3_kernel<1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx, gate);
     else
-      hipLaunchKernelGGL((gemm_stream_bf3_kernel<2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx);
+      hipLaunchKernelGGL((gemm_stream_bf3_kernel<2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, wstart, nx, gate);
   } else {
     if (tag == 0)
-      hipLaunchKernelGGL((gemm_tile_bf3_kernel<0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx);
+      hipLaunchKernelGGL((gemm_tile_bf3_kernel<0>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx, gate);
     else if (tag == 1)
-      hipLaunchKernelGGL((gemm_tile_bf3_kernel<1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx);
+      hipLaunchKernelGGL((gemm_tile_bf3_kernel<1>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx, gate);
     else
-      hipLaunchKernelGGL((gemm_tile_bf3_kernel<2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx);
+      hipLaunchKernelGGL((gemm_tile_bf3_kernel<2>), dim3(nwg), dim3(256), 0, hs, tiles, tasks, nx, gate);
   }
 }
 
 void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int tag, bool f32,
-                 Stream st, bool bf3, int nx) {
+                 Stream st, bool bf3, int nx, const int* gate) {
   if (nwg <= 0) return;
   if (f32 && bf3)
-    launch_gemm_bf3(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st, nx);
+    launch_gemm_bf3(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st, nx, gate);
   else if (f32)
-    launch_gemm_t<float>(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st, nx);
+    launch_gemm_t<float>(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st, nx, gate);
   else
-    launch_gemm_t<double>(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st, nx);
+    launch_gemm_t<double>(tiles, tasks, wstart, nwg, stream, tag, (hipStream_t)st, nx, gate);
   check_launch("gemm");
 }
 
@@ -1048,22 +1061,25 @@ __device__ __forceinline__ void reduce_body(const RTile* __restrict__ reds, cons
   }
 }
 template <typename T>
-__global__ __launch_bounds__(256) void reduce_kernel(const RTile* __restrict__ reds) {
+__global__ __launch_bounds__(256) void reduce_kernel(const RTile* __restrict__ reds, const int* __restrict__ gate) {
+  if (gate && *gate) return;
   reduce_body<T>(reds, blockIdx.x);
 }
 template <typename T>
 __global__ __launch_bounds__(256) void reduce_seg_kernel(const GSeg* __restrict__ segs, const int* __restrict__ base,
                                                          int nseg) {
   const int s = seg_find(base, nseg, blockIdx.x);
-  reduce_body<T>((const RTile*)((const GSegDev*)segs)[s].reds, blockIdx.x - base[s]);
+  const GSegDev* const d = (const GSegDev*)segs;
+  if (d[s].gate && *d[s].gate) return;
+  reduce_body<T>((const RTile*)d[s].reds, blockIdx.x - base[s]);
 }
 
-void launch_reduce(const RTile* reds, int nred, bool f32, Stream st) {
+void launch_reduce(const RTile* reds, int nred, bool f32, Stream st, const int* gate) {
   if (nred <= 0) return;
   if (f32)
-    hipLaunchKernelGGL(reduce_kernel<float>, dim3(nred), dim3(256), 0, (hipStream_t)st, reds);
+    hipLaunchKernelGGL(reduce_kernel<float>, dim3(nred), dim3(256), 0, (hipStream_t)st, reds, gate);
   else
-    hipLaunchKernelGGL(reduce_kernel<double>, dim3(nred), dim3(256), 0, (hipStream_t)st, reds);
+    hipLaunchKernelGGL(reduce_kernel<double>, dim3(nred), dim3(256), 0, (hipStream_t)st, reds, gate);
   check_launch("reduce");
 }
 
@@ -1760,6 +1776,298 @@ void launch_syev_batch(const SyevJob* jobs, int njobs, Stream st) {
   if (njobs <= 0) return;
   hipLaunchKernelGGL(syev_batch_kernel, dim3(njobs), dim3(64), 0, (hipStream_t)st, jobs);
   check_launch("syev_batch");
+}
+
+// ---------------------------------------------------------------------------
+// Davidson iterations as a fixed launch sequence.  Each kernel reads the
+// solve's subspace size and flags from its DGState and runs only while the
+// solve is live (and, for the collapse and restart branches, while their
+// flag is set); its arithmetic is that of the corresponding job-list helper.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool dg_live(const DGJob& j, int gate) {
+  const DGState* s = j.s;
+  if (s->done) return false;
+  if (gate == DG_GATE_COLLAPSE) return s->collapse != 0;
+  if (gate == DG_GATE_RESTART) return s->restart != 0;
+  return true;
+}
+
+__global__ void dg_scalar_kernel(const DGJob* __restrict__ jobs, int njobs, int which) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= njobs) return;
+  const DGJob j = jobs[q];
+  DGState* s = j.s;
+  if (s->done) return;
+  switch (which) {
+    case DG_TOP:  // out of iterations: the previous Ritz vector is the result
+      if (s->it > j.max_it) {
+        s->state = 2;
+        s->done = 1;
+      }
+      break;
+    case DG_CHECK: {
+      const double th = j.evals[0];
+      const double rn = sqrt(fmax(0.0, j.nrm[0]));
+      if (rn <= j.tol) {
+        s->state = 1;
+        s->done = 1;
+      } else if (j.f32 && rn < 100.0 * j.eps * fmax(1.0, fabs(th))) {
+        // the reduced-precision floor: stop when four iterations gain < 10 %
+        if (rn < 0.9 * s->rbest) {
+          s->rbest = rn;
+          s->stall = 0;
+        } else if (++s->stall >= 4) {
+          s->state = 1;
+          s->done = 1;
+        }
+      }
+      break;
+    }
+    case DG_COLLAPSE:
+      s->collapse = !(j.nrm2[0] > 1e-28);
+      break;
+    case DG_COLLAPSE2:
+      if (s->collapse && !(j.nrm2[0] > 1e-28)) {
+        s->state = 3;
+        s->done = 1;
+      }
+      s->collapse = 0;
+      break;
+    case DG_RESTART_FLAG:
+      s->restart = s->k >= j.ms;
+      break;
+    case DG_RESTART_K:
+      if (s->restart) s->k = 1;
+      s->restart = 0;
+      break;
+    case DG_ADVANCE:
+      s->k += 1;
+      s->it += 1;
+      break;
+    default:
+      break;
+  }
+}
+
+void launch_dg_scalar(const DGJob* jobs, int njobs, int which, Stream st) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(dg_scalar_kernel, dim3((njobs + 63) / 64), dim3(64), 0, (hipStream_t)st, jobs, njobs, which);
+  check_launch("dg_scalar");
+}
+
+// the operands of an inner-product step: out[j] = V_j . x, j < cnt
+__device__ __forceinline__ void dg_dot_args(const DGJob& jb, int which, const double*& V, const double*& x,
+                                            double*& out, int& cnt) {
+  const int k = jb.s->k;
+  switch (which) {
+    case DGD_ROW:  // row k of the projected matrix: V_j . W_k, j <= k
+      V = jb.V, x = jb.W + (int64_t)k * jb.n, out = jb.Hs + (int64_t)k * jb.ms, cnt = k + 1;
+      break;
+    case DGD_RR:
+      V = jb.r, x = jb.r, out = jb.nrm, cnt = 1;
+      break;
+    case DGD_VT:
+      V = jb.V, x = jb.t, out = jb.coef, cnt = k;
+      break;
+    case DGD_TT:
+      V = jb.t, x = jb.t, out = jb.nrm2, cnt = 1;
+      break;
+    case DGD_V0W0:
+      V = jb.V, x = jb.W, out = jb.Hs, cnt = 1;
+      break;
+    default:  // DGD_V0T
+      V = jb.V, x = jb.t, out = jb.coef, cnt = 1;
+      break;
+  }
+}
+
+// One workgroup per (chunk, solve) takes the vectors j < cnt in turn (the
+// count is only known on the device); each partial sum is formed exactly as
+// by the job-list helper.
+__global__ __launch_bounds__(RB) void dg_dots_stage1(const DGJob* __restrict__ jobs, int which, int gate) {
+  const DGJob jb = jobs[blockIdx.y];
+  if (!dg_live(jb, gate)) return;
+  const double *V, *x;
+  double* out;
+  int cnt;
+  dg_dot_args(jb, which, V, x, out, cnt);
+  const int64_t n = jb.n;
+  const int64_t chunk = (n + RCH - 1) / RCH;
+  const int64_t b = blockIdx.x * chunk, e = min(n, b + chunk);
+  __shared__ double red[RB / 64];
+  for (int j = 0; j < cnt; ++j) {
+    const double* v = V + j * n;
+    double s = 0;
+    for (int64_t i = b + threadIdx.x; i < e; i += RB) s += v[i] * x[i];
+    s = wave_sum(s);
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0;
+      for (int w = 0; w < RB / 64; ++w) t += red[w];
+      jb.part[(int64_t)j * RCH + blockIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void dg_dots_stage2(const DGJob* __restrict__ jobs, int which, int gate) {
+  const DGJob jb = jobs[blockIdx.y];
+  if (!dg_live(jb, gate)) return;
+  const double *V, *x;
+  double* out;
+  int cnt;
+  dg_dot_args(jb, which, V, x, out, cnt);
+  const int j = blockIdx.x;
+  if (j >= cnt) return;
+  double s = 0;
+  for (int i = threadIdx.x; i < RCH; i += 64) s += jb.part[(int64_t)j * RCH + i];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+void launch_dg_dots(const DGJob* jobs, int njobs, int which, int gate, int max_k, Stream st) {
+  if (njobs <= 0 || max_k <= 0) return;
+  hipLaunchKernelGGL(dg_dots_stage1, dim3(RCH, njobs), dim3(RB), 0, (hipStream_t)st, jobs, which, gate);
+  hipLaunchKernelGGL(dg_dots_stage2, dim3(max_k, njobs), dim3(64), 0, (hipStream_t)st, jobs, which, gate);
+  check_launch("dg_dots");
+}
+
+__global__ void dg_ew_kernel(const DGJob* __restrict__ jobs, int which, int gate) {
+  const DGJob jb = jobs[blockIdx.y];
+  if (!dg_live(jb, gate)) return;
+  const int64_t n = jb.n;
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, step = (int64_t)gridDim.x * blockDim.x;
+  const int k = jb.s->k;
+  switch (which) {
+    case DGE_PRECOND: {
+      const double th = jb.evals[0];
+      for (int64_t i = i0; i < n; i += step) {
+        double d = th - jb.diag[i];
+        if (fabs(d) < 1e-12) d = d < 0 ? -1e-12 : 1e-12;
+        jb.t[i] = jb.r[i] / d;
+      }
+      break;
+    }
+    case DGE_RESIDUAL: {
+      const double th = jb.evals[0];
+      for (int64_t i = i0; i < n; i += step) jb.r[i] = jb.ax[i] - th * jb.x[i];
+      break;
+    }
+    case DGE_COPY_RT:
+      for (int64_t i = i0; i < n; i += step) jb.t[i] = jb.r[i];
+      break;
+    case DGE_NORMALIZE_T: {
+      const double f = 1.0 / sqrt(jb.nrm2[0]);
+      for (int64_t i = i0; i < n; i += step) jb.t[i] *= f;
+      break;
+    }
+    case DGE_RESTART_COPY:
+      for (int64_t i = i0; i < n; i += step) {
+        jb.V[i] = jb.x[i];
+        jb.W[i] = jb.ax[i];
+      }
+      break;
+    case DGE_APPEND: {
+      double* v = jb.V + (int64_t)k * n;
+      for (int64_t i = i0; i < n; i += step) v[i] = jb.t[i];
+      break;
+    }
+    case DGE_LOAD: {
+      const double* v = jb.V + (int64_t)k * n;
+      for (int64_t i = i0; i < n; i += step) jb.in[i] = v[i];
+      break;
+    }
+    case DGE_STORE: {
+      double* w = jb.W + (int64_t)k * n;
+      for (int64_t i = i0; i < n; i += step) w[i] = jb.out[i];
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+void launch_dg_ew(const DGJob* jobs, int njobs, int which, int gate, int64_t max_n, Stream st) {
+  if (njobs <= 0) return;
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (max_n + 255) / 256));
+  hipLaunchKernelGGL(dg_ew_kernel, dim3(nb, njobs), dim3(256), 0, (hipStream_t)st, jobs, which, gate);
+  check_launch("dg_ew");
+}
+
+// y = beta y + alpha sum_{j < cnt} coef[j] V_j with the combo helper's arithmetic
+__global__ void dg_combo_kernel(const DGJob* __restrict__ jobs, int which, int gate) {
+  const DGJob jb = jobs[blockIdx.y];
+  if (!dg_live(jb, gate)) return;
+  const double* V;
+  const double* coef;
+  double* y;
+  int cnt;
+  double alpha, beta;
+  const int k = jb.s->k;
+  switch (which) {
+    case DGC_RITZ_X:
+      V = jb.V, coef = jb.evecs, y = jb.x, cnt = k, alpha = 1.0, beta = 0.0;
+      break;
+    case DGC_RITZ_AX:
+      V = jb.W, coef = jb.evecs, y = jb.ax, cnt = k, alpha = 1.0, beta = 0.0;
+      break;
+    case DGC_ORTH:
+      V = jb.V, coef = jb.coef, y = jb.t, cnt = k, alpha = -1.0, beta = 1.0;
+      break;
+    default:  // DGC_ORTH0
+      V = jb.V, coef = jb.coef, y = jb.t, cnt = 1, alpha = -1.0, beta = 1.0;
+      break;
+  }
+  const int64_t n = jb.n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0;
+    for (int j = 0; j < cnt; ++j) s += coef[j] * V[j * n + i];
+    y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + alpha * s;
+  }
+}
+
+void launch_dg_combo(const DGJob* jobs, int njobs, int which, int gate, int64_t max_n, Stream st) {
+  if (njobs <= 0) return;
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (max_n + 255) / 256));
+  hipLaunchKernelGGL(dg_combo_kernel, dim3(nb, njobs), dim3(256), 0, (hipStream_t)st, jobs, which, gate);
+  check_launch("dg_combo");
+}
+
+__global__ __launch_bounds__(64) void dg_syev_kernel(const DGJob* __restrict__ jobs) {
+  const DGJob jb = jobs[blockIdx.x];
+  if (jb.s->done) return;
+  syev_body(jb.Hs, jb.s->k, jb.ms, jb.evals, jb.evecs);
+}
+
+void launch_dg_syev(const DGJob* jobs, int njobs, Stream st) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(dg_syev_kernel, dim3(njobs), dim3(64), 0, (hipStream_t)st, jobs);
+  check_launch("dg_syev");
+}
+
+void dev_capture_begin(Stream st) {
+  hip_ok(hipStreamBeginCapture((hipStream_t)st, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+}
+void* dev_capture_end(Stream st) {
+  hipGraph_t g = nullptr;
+  hip_ok(hipStreamEndCapture((hipStream_t)st, &g), "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  hip_ok(e, "hipGraphInstantiate");
+  return (void*)ex;
+}
+void dev_capture_abort(Stream st) {
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture((hipStream_t)st, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+}
+void dev_graph_launch(void* exec, Stream st) {
+  hip_ok(hipGraphLaunch((hipGraphExec_t)exec, (hipStream_t)st), "hipGraphLaunch");
+}
+void dev_graph_free(void* exec) {
+  if (exec) (void)hipGraphExecDestroy((hipGraphExec_t)exec);
 }
 
 __global__ void scalars_kernel(const double* const* __restrict__ src, int n, double* __restrict__ dst) {

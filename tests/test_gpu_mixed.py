@@ -129,6 +129,49 @@ def test_fp64_refinement_steps():
     assert 2.0 < calls[3] <= 4.0
 
 
+def test_refinement_residual_target():
+    """With a residual target, FP64 refinement steps after the first run only
+    while the refined vector's FP64 residual is above it: BF16x3 Davidson
+    (which stops on its rounding floor) then gets the steps it needs, its
+    sweeps land closer to the FP64 oracle's than with a single step, and a
+    loose target never costs more FP64 sigma than the fixed step count."""
+    from paper_1312_2415_amd.binding import SadmrgError
+    L, N, twoS, group, irrep, D, nsw, seed = 10, 6, 2, "D2h", 0, 24, 2, 5
+    I = make_integrals(L, group, seed)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    blob = sd.export_blob(dm)
+    for _ in range(nsw):
+        dm.sweep(D)
+    ref = np.array(dm.stats.energies)
+    err, calls = {}, {}
+    for steps, tol in ((1, 0.0), (6, 1e-8), (6, 1.0)):
+        g = _gpu(L, group, I)
+        g.set_target(N, twoS, irrep)
+        g.set_davidson(1e-9, 32, 200)
+        g.set_precision(2, 1e-5)
+        g.set_refinement(steps)
+        g.set_refinement_tol(tol)
+        g.mps_import(blob)
+        g.stats_reset()
+        for s in range(nsw):
+            print(f"refinement {steps} target {tol} sweep {s}", flush=True)
+            g.sweep(D)
+        got = g.trace()
+        assert len(got) == len(ref)
+        err[tol] = float(np.abs(got - ref).max())
+        calls[tol] = g.stats()["n_sigma"] / len(got)
+        with pytest.raises(SadmrgError):
+            g.set_refinement_tol(-1.0)
+        g.close()
+    print(f"max |dE| per micro-iteration: {err}; FP64 sigma per micro-iteration: {calls}", flush=True)
+    assert err[1e-8] <= 1e-7
+    assert err[1e-8] <= err[0.0]
+    assert abs(calls[1.0] - 2.0) <= 1e-12  # the first step only
+    assert calls[1e-8] > 2.0
+
+
 def test_bf16x3_sigma_within_its_rounding_of_oracle():
     """Mode 2: BF16x3 products (hi*hi + hi*lo + lo*hi of the BF16 splits,
     FP32 accumulation).  The sigma stays within a few hundred times the
