@@ -638,10 +638,11 @@ def main():
     ap.add_argument("--roots", type=int, default=3, help="lockstep group size of the twelve-root record "
                                                          "(a divisor of 12; 0 = skip)")
     ap.add_argument("--roots-warmup", type=int, default=2)
-    ap.add_argument("--refine", type=int, default=1, help="FP64 Davidson steps after the reduced-precision phase")
+    ap.add_argument("--refine", type=int, default=4, help="FP64 Davidson steps after the reduced-precision phase "
+                                                          "(at most, with --refine-tol)")
     ap.add_argument("--only-roots", action="store_true", help="run only the roots record")
-    ap.add_argument("--refine-tol", type=float, default=0.0, help="FP64 residual norm that ends the refinement "
-                                                                   "early (0 = always --refine steps)")
+    ap.add_argument("--refine-tol", type=float, default=1e-6, help="FP64 residual norm that ends the refinement "
+                                                                    "early (0 = always --refine steps)")
     ap.add_argument("--grad", type=int, default=4, help="integral orbits checked one by one by finite differences "
                                                         "in the energy-adjoint record at --grad-L orbitals (0 = skip)")
     ap.add_argument("--grad-dir", type=int, default=200, help="entries of the one multi-entry difference direction")
@@ -742,13 +743,21 @@ def main():
     n_before = len(g.trace())
     t0 = time.perf_counter()
     energies = []
+    # the FP64 state after as many sweeps as the mixed records run, for their
+    # RDM comparison (its export is excluded from the timed window)
+    nmix_ref = max(1, min(args.steps, args.mixed_steps))
+    blob_nmix, t_export = None, 0.0
     for k in range(args.steps):
         ts = time.perf_counter()
         e, _ = g.sweep(args.D)
         energies.append(e)
         print(f"timed sweep {k + 1}/{args.steps} D={args.D} E={e:.10f} {time.perf_counter() - ts:.1f}s",
               file=sys.stderr, flush=True)
-    t1 = time.perf_counter()
+        if k + 1 == nmix_ref and not args.no_mixed and not args.no_rdm:
+            tx = time.perf_counter()
+            blob_nmix = g.mps_export()
+            t_export += time.perf_counter() - tx
+    t1 = time.perf_counter() - t_export
     from paper_1312_2415_amd.binding import device_memory
     mem_free, mem_total = device_memory(0)
     st = g.stats()
@@ -850,7 +859,12 @@ def main():
     if not args.no_mixed:
         # the first sweeps again from the same state with reduced-precision
         # sigma in Davidson (FP32, then BF16x3) and an FP64 refinement step
-        nmix = max(1, min(args.steps, args.mixed_steps))
+        nmix = nmix_ref
+        rdm_nmix = None  # the FP64 RDMs after the same number of sweeps
+        if blob_nmix is not None:
+            g.mps_import(blob_nmix)
+            r1, r2, _ = g.rdm()
+            rdm_nmix = (r1, r2)
         ref_trace = trace64[n_before:n_before + nmix * per_sweep]
         for mode, key, desc in (
                 (1, "mixed", "FP32 sigma (FP32 operators, FP32 accumulation) in Davidson"),
@@ -899,11 +913,39 @@ def main():
                 "abs_dE_last_sweep_vs_fp64": abs(emix[-1] - energies[nmix - 1]),
                 "max_abs_dE_per_micro_iteration_vs_fp64": d_micro,
             }
-            if rdm64 is not None and nmix == args.steps:
+            if rdm_nmix is not None:
                 m1, m2, _ = g.rdm()
-                rec["rdm_max_abs_error_vs_fp64"] = {"gamma": float(np.abs(m1 - rdm64[0]).max()),
-                                                    "Gamma": float(np.abs(m2 - rdm64[1]).max())}
+                rec["rdm_max_abs_error_vs_fp64"] = {"gamma": float(np.abs(m1 - rdm_nmix[0]).max()),
+                                                    "Gamma": float(np.abs(m2 - rdm_nmix[1]).max())}
             line[key] = rec
+    if args.graph > 0:
+        # the first timed FP64 sweeps again from the same state with the
+        # Davidson iterations replayed from a recorded HIP graph
+        nrec = max(1, min(args.steps, 2))
+        g.set_precision(0, args.mixed_tol)
+        g.set_davidson_graph(args.graph)
+        g.mps_import(start)
+        g.stats_reset()
+        n_done = len(g.trace())
+        tg0 = time.perf_counter()
+        for k in range(nrec):
+            ts = time.perf_counter()
+            e, _ = g.sweep(args.D)
+            print(f"recorded-Davidson sweep {k + 1}/{nrec} D={args.D} E={e:.10f} {time.perf_counter() - ts:.1f}s",
+                  file=sys.stderr, flush=True)
+        tg1 = time.perf_counter()
+        sgr = g.stats_graph()
+        trg = np.array(g.trace()[n_done:n_done + nrec * per_sweep])
+        ref = np.array(trace64[n_before:n_before + nrec * per_sweep])
+        line["recorded_davidson"] = {
+            "replays_per_host_check": args.graph, "sweeps": nrec,
+            "s_per_sweep": (tg1 - tg0) / nrec, "speedup_vs_host_driven": sec_per_sweep / ((tg1 - tg0) / nrec),
+            "replayed_segment_seconds_per_sweep": sgr["seconds"] / nrec,
+            "recording_host_seconds_per_sweep": sgr["record_seconds"] / nrec,
+            "sigma_products_in_replays": sgr["sigma_calls"], "recordings": sgr["records"],
+            "trace_identical_to_host_driven": bool(len(trg) == len(ref) and np.array_equal(trg, ref)),
+        }
+        g.set_davidson_graph(0)
     g.close()
     if args.batch_n > 0:
         line["batch"] = batch_bench(args.batch_n, args.batch_seed, 1, args.mixed_tol, args.graph)
