@@ -413,7 +413,7 @@ def roots_bench(group, L, N, D, seed, warm, dav_tol, mixed_tol, refine=1, refine
     return out
 
 
-def grad_bench(L, N, D, seed, warm, n_orbits, tau, n_dir=200):
+def grad_bench(L, N, D, seed, warm, n_orbits, tau, n_dir=200, ckpt=6):
     """Energy adjoint at the differentiation configuration (L orbitals, N
     electrons, singlet Ag, D2h): the spin-summed 1- and 2-RDM of the MPS after
     `warm` sweeps at D, as dE/dh and dE/d(ij|kl), against central differences
@@ -510,7 +510,31 @@ def grad_bench(L, N, D, seed, warm, n_orbits, tau, n_dir=200):
         print(f"grad: direction over {n_dir} entries: adjoint {pred_dir:.10f} fd {fd_dir:.10f}", file=sys.stderr,
               flush=True)
         t_fd = time.perf_counter() - t_fd
+        # the adjoint again with renormalised operators recomputed instead of
+        # stored (blocks kept every `ckpt` bonds), on the original integrals
+        ck = None
+        if ckpt > 0:
+            full_blocks = g.stats_blocks()
+            g.set_integrals(I.h, I.eri)
+            g.set_block_checkpoints(ckpt)
+            g.stats_reset()
+            t = time.perf_counter()
+            g.mps_import(blob)
+            t_imp = time.perf_counter() - t
+            t = time.perf_counter()
+            c1, c2, ec = g.rdm()
+            t_ck = time.perf_counter() - t
+            sb = g.stats_blocks()
+            ck = {"interval": ckpt, "seconds_import": t_imp, "seconds_rdm": t_ck,
+                  "block_bytes_max": sb["max_bytes"], "block_bytes_max_all_stored": full_blocks["max_bytes"],
+                  "blocks_rebuilt_in_rdm": sb["rebuilt"], "rebuild_seconds": sb["seconds"],
+                  "max_abs_diff_gamma": float(np.abs(c1 - g1).max()),
+                  "max_abs_diff_Gamma": float(np.abs(c2 - g2).max()), "abs_diff_energy": abs(ec - e0)}
+            print(f"grad: checkpoints every {ckpt} bonds: rdm {t_ck:.1f}s, block bytes "
+                  f"{sb['max_bytes'] / 2**30:.1f} GiB against {full_blocks['max_bytes'] / 2**30:.1f} GiB, "
+                  f"|dGamma| {ck['max_abs_diff_Gamma']:.1e}", file=sys.stderr, flush=True)
         return {
+            "operator_recomputation": ck,
             "fd_direction": {"entries": n_dir, "adjoint": pred_dir, "finite_difference": fd_dir,
                              "abs_diff": abs(fd_dir - pred_dir),
                              "rel_diff": abs(fd_dir - pred_dir) / max(abs(pred_dir), 1e-300)},
@@ -649,6 +673,8 @@ def main():
     ap.add_argument("--grad-L", type=int, default=36)
     ap.add_argument("--grad-warmup", type=int, default=3)
     ap.add_argument("--grad-tau", type=float, default=1e-5)
+    ap.add_argument("--ckpt", type=int, default=6, help="block checkpoint interval of the operator-recomputation "
+                                                        "leg of the grad record (0 = skip)")
     ap.add_argument("--only-grad", action="store_true", help="run only the energy-adjoint record")
     ap.add_argument("--scf-iter", type=int, default=2, help="DMRG-SCF iterations of the dmrgscf record (0 = skip)")
     ap.add_argument("--scf-D", type=int, default=1000)
@@ -669,7 +695,8 @@ def main():
 
     if args.only_grad:
         print(json.dumps({"grad": grad_bench(args.grad_L, args.N, args.D, args.seed, args.grad_warmup,
-                                             max(args.grad, 1), args.grad_tau, args.grad_dir)}), flush=True)
+                                             max(args.grad, 1), args.grad_tau, args.grad_dir, args.ckpt)}),
+              flush=True)
         return
     if args.only_roots:
         print(json.dumps({"roots": roots_bench(args.roots, args.L, args.N, args.D, args.seed, args.roots_warmup,
@@ -953,7 +980,7 @@ def main():
     # that fills the device is started
     failed = False
     for key, run in (("grad", lambda: grad_bench(args.grad_L, N, args.D, args.seed, args.grad_warmup, args.grad,
-                                                 args.grad_tau, args.grad_dir) if args.grad > 0 else None),
+                                                 args.grad_tau, args.grad_dir, args.ckpt) if args.grad > 0 else None),
                      ("dmrgscf", lambda: dmrgscf_bench(args.grad_L, N, args.scf_D, args.seed, args.scf_core,
                                                        args.scf_iter, 2, args.dav_tol) if args.scf_iter > 0 else None),
                      ("roots", lambda: roots_bench(args.roots, L, N, args.D, args.seed, args.roots_warmup,

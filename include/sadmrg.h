@@ -137,6 +137,24 @@ int sadmrg_set_precision(sadmrg_ctx* ctx, int mode, double mixed_tol);
  * early when a step cannot move the vector.  Contexts swept together by
  * sadmrg_batch_sweep must share it.  Errors: EINVAL. */
 int sadmrg_set_refinement(sadmrg_ctx* ctx, int steps);
+/* Renormalised operators recomputed instead of stored (section
+ * "Sweeping": a sweep needs the blocks on both sides of the current two
+ * sites; the paper keeps them on disk).  interval = 0 (default): every
+ * left and right block stays in device memory.  interval > 0: only the
+ * blocks at bonds 0, L and multiples of `interval` are kept; any other block
+ * is rebuilt from the nearest kept block and the MPS tensors (enlargement
+ * and renormalisation) when a step or the energy adjoint needs it, kept
+ * while the sweep works through that stretch, and dropped once it has
+ * passed, so that about 2 L / interval + interval blocks are held instead
+ * of L + 1.  Turns the kept enlargements off (sadmrg_set_enlarge_cache).
+ * Results equal those with every block stored up to rounding.  Errors:
+ * EINVAL (interval < 0). */
+int sadmrg_set_block_checkpoints(sadmrg_ctx* ctx, int interval);
+/* Block statistics since sadmrg_stats_reset: blocks rebuilt, host seconds
+ * spent rebuilding them, the largest device bytes the blocks held at once,
+ * and the number of blocks held now.  Pointers may be NULL. */
+int sadmrg_stats_blocks(sadmrg_ctx* ctx, int64_t* rebuilt, double* seconds, double* max_bytes, int* held);
+
 /* Davidson iterations replayed from a recorded launch sequence (section "The
  * effective Hamiltonian equation": the iterative eigensolver of every
  * micro-iteration).  replays = 0 (default): the host drives every

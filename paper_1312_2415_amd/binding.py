@@ -89,6 +89,8 @@ def load_library(path: str | None = None):
         "sadmrg_stats_passes": (c_int, [c_vp, P(c_dbl), P(c_dbl)]),
         "sadmrg_stats_mixed": (c_int, [c_vp, P(c_dbl), P(ctypes.c_int64), P(c_dbl)]),
         "sadmrg_set_refinement": (c_int, [c_vp, c_int]),
+        "sadmrg_set_block_checkpoints": (c_int, [c_vp, c_int]),
+        "sadmrg_stats_blocks": (c_int, [c_vp, P(ctypes.c_int64), P(c_dbl), P(c_dbl), P(c_int)]),
         "sadmrg_set_davidson_graph": (c_int, [c_vp, c_int]),
         "sadmrg_stats_graph": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl), P(ctypes.c_int64), P(ctypes.c_int64),
                                        P(ctypes.c_int64)]),
@@ -437,6 +439,18 @@ class SaDMRG:
         """0: FP64 sigma; 1 / 2: FP32 / BF16x3 sigma in Davidson, then one FP64
         Davidson step per micro-iteration (sadmrg_set_precision)."""
         self._chk(self.lib.sadmrg_set_precision(self.h, int(mode), float(mixed_tol)))
+
+    def set_block_checkpoints(self, interval: int):
+        """Keep renormalised blocks only every `interval` bonds and rebuild the
+        others when needed (sadmrg_set_block_checkpoints); 0 keeps all."""
+        self._chk(self.lib.sadmrg_set_block_checkpoints(self.h, int(interval)))
+
+    def stats_blocks(self):
+        """(blocks rebuilt, rebuild seconds, largest block bytes held, blocks held now)."""
+        n, t, b, h = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        self._chk(self.lib.sadmrg_stats_blocks(self.h, ctypes.byref(n), ctypes.byref(t), ctypes.byref(b),
+                                               ctypes.byref(h)))
+        return {"rebuilt": n.value, "seconds": t.value, "max_bytes": b.value, "held": h.value}
 
     def set_davidson_graph(self, replays: int):
         """Davidson iterations replayed from a recorded HIP graph, `replays`

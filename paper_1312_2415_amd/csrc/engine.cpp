@@ -1752,6 +1752,13 @@ struct Engine {
   std::vector<std::map<Sec, long long>> caps;
   std::vector<Basis> dims;  // bond dimensions (kept)
   std::vector<std::unique_ptr<Store>> Lb, Rb;
+  // Renormalised blocks kept only at every ckpt-th bond (0: every bond):
+  // the others are rebuilt from the nearest kept block and the MPS tensors
+  // when a step needs them, and dropped again when the sweep has passed.
+  int ckpt = 0;
+  int64_t n_rebuilt = 0;    // blocks rebuilt since the statistics were reset
+  double t_rebuilt = 0.0;   // host wall seconds of those rebuilds
+  double block_bytes_max = 0.0;  // largest device bytes held by the blocks at once
   std::vector<Tensor> U, V;  // left tensors U[i]: bond i+1 sectors (dimX x k); right V[i]: bond i (k x dimY)
   Center cen;
   Step step;
@@ -2313,9 +2320,12 @@ struct Engine {
     dev_d2h(&e, dsmall.p + 1, 8, st);
     G.assign((size_t)P.L * P.L * P.L * P.L, 0.0);
     seed_adjoints();
+    // With checkpoints the walks rebuild the dropped blocks from the kept
+    // ones below (left) or above (right) and drop each block again once its
+    // adjoint has been passed on.
     {  // left blocks: bond i down to 0
       EnlargeTrace tr;
-      trace_enlarge(P, *Lb[i], step.EX, true, st, tr);
+      trace_enlarge(P, lblock(i), step.EX, true, st, tr);
       if (tr.out->total != step.X->total) fail(-1, "internal: enlarged store mismatch in the adjoint");
       tr.out->adj = std::move(step.X->adj);
       for (int k = i;; --k) {
@@ -2324,17 +2334,19 @@ struct Engine {
         if (k == 0) break;
         EnlargeTrace prev;
         std::set<Sec> keep(dims[k].sec.begin(), dims[k].sec.end());
-        Enl E = left_enl(P, k, Lb[k - 1]->basis, &keep);
-        trace_enlarge(P, *Lb[k - 1], E, true, st, prev);
+        Store& Lp = lblock(k - 1);
+        Enl E = left_enl(P, k, Lp.basis, &keep);
+        trace_enlarge(P, Lp, E, true, st, prev);
         renorm_backward(*Lb[k], *prev.out, U[k - 1], true);
         Lb[k]->adj.release();
+        if (k < i && !kept_bond(k)) Lb[k].reset();
         tr = std::move(prev);
       }
       Lb[0]->adj.release();
     }
     {  // right blocks: bond i+2 up to L
       EnlargeTrace tr;
-      trace_enlarge(P, *Rb[i + 2], step.EY, false, st, tr);
+      trace_enlarge(P, rblock(i + 2), step.EY, false, st, tr);
       if (tr.out->total != step.Y->total) fail(-1, "internal: enlarged store mismatch in the adjoint");
       tr.out->adj = std::move(step.Y->adj);
       for (int k = i + 2;; ++k) {
@@ -2343,10 +2355,12 @@ struct Engine {
         if (k == P.L) break;
         EnlargeTrace prev;
         std::set<Sec> keep(dims[k].sec.begin(), dims[k].sec.end());
-        Enl E = right_enl(P, k, Rb[k + 1]->basis, &keep);
-        trace_enlarge(P, *Rb[k + 1], E, false, st, prev);
+        Store& Rp = rblock(k + 1);
+        Enl E = right_enl(P, k, Rp.basis, &keep);
+        trace_enlarge(P, Rp, E, false, st, prev);
         renorm_backward(*Rb[k], *prev.out, V[k], false);
         Rb[k]->adj.release();
+        if (k > i + 2 && !kept_bond(k)) Rb[k].reset();
         tr = std::move(prev);
       }
       Rb[P.L]->adj.release();
@@ -2863,20 +2877,98 @@ struct Engine {
     Lb.resize(P.L + 1);
     Rb.resize(P.L + 1);
     Lb[0] = left_boundary();
-    for (int k = 0; k < i; ++k) {
-      std::set<Sec> keep(dims[k + 1].sec.begin(), dims[k + 1].sec.end());
-      Enl E = left_enl(P, k + 1, Lb[k]->basis, &keep);
-      auto Xe = enlarge(P, *Lb[k], E, true, st, nullptr);
-      Lb[k + 1] = renormalize(*Xe, U[k], dims[k + 1], true);
+    for (int k = 0; k < i; ++k) {  // the block below each new one is dropped unless kept
+      build_left(k);
+      if (!keep_left(k, i)) Lb[k].reset();
     }
     Rb[P.L] = right_boundary();
     for (int k = P.L - 1; k >= i + 2; --k) {
-      std::set<Sec> keep(dims[k].sec.begin(), dims[k].sec.end());
-      Enl E = right_enl(P, k, Rb[k + 1]->basis, &keep);
-      auto Ye = enlarge(P, *Rb[k + 1], E, false, st, nullptr);
-      Rb[k] = renormalize(*Ye, V[k], dims[k], false);
+      build_right(k);
+      if (!keep_right(k + 1, i)) Rb[k + 1].reset();
     }
+    note_block_bytes();
     step.i = -1;
+  }
+  // left block at bond k+1 from the block at bond k and the tensor U[k]
+  // (enlargement by site k, then renormalisation)
+  void build_left(int k) {
+    std::set<Sec> keep(dims[k + 1].sec.begin(), dims[k + 1].sec.end());
+    Enl E = left_enl(P, k + 1, Lb[k]->basis, &keep);
+    auto Xe = enlarge(P, *Lb[k], E, true, st, nullptr);
+    Lb[k + 1] = renormalize(*Xe, U[k], dims[k + 1], true);
+  }
+  // right block at bond k from the block at bond k+1 and the tensor V[k]
+  void build_right(int k) {
+    std::set<Sec> keep(dims[k].sec.begin(), dims[k].sec.end());
+    Enl E = right_enl(P, k, Rb[k + 1]->basis, &keep);
+    auto Ye = enlarge(P, *Rb[k + 1], E, false, st, nullptr);
+    Rb[k] = renormalize(*Ye, V[k], dims[k], false);
+  }
+  bool kept_bond(int b) const { return ckpt <= 0 || b == 0 || b == P.L || b % ckpt == 0; }
+  // The left block at bond b, rebuilt upwards from the nearest block below
+  // it when it was dropped (the blocks in between are rebuilt too and kept:
+  // a right-to-left pass needs them next).
+  Store& lblock(int b) {
+    if (!Lb[b]) {
+      const auto t0 = std::chrono::steady_clock::now();
+      int c = b - 1;
+      while (!Lb[c]) --c;  // Lb[0] is always kept
+      for (int k = c; k < b; ++k)
+        if (!Lb[k + 1]) {
+          build_left(k);
+          ++n_rebuilt;
+        }
+      t_rebuilt += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      note_block_bytes();
+    }
+    return *Lb[b];
+  }
+  // The right block at bond b, rebuilt downwards from the nearest block above.
+  Store& rblock(int b) {
+    if (!Rb[b]) {
+      const auto t0 = std::chrono::steady_clock::now();
+      int c = b + 1;
+      while (!Rb[c]) ++c;  // Rb[L] is always kept
+      for (int k = c - 1; k >= b; --k)
+        if (!Rb[k]) {
+          build_right(k);
+          ++n_rebuilt;
+        }
+      t_rebuilt += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      note_block_bytes();
+    }
+    return *Rb[b];
+  }
+  // With checkpoints, keep around step i only the blocks a sweep through i
+  // may need next: left bonds (cl, i+1] with cl the last kept bond below i,
+  // right bonds [i+1, cr) with cr the first kept bond above i+2, and every
+  // kept bond.
+  bool keep_left(int k, int i) const {
+    if (kept_bond(k)) return true;
+    int cl = std::max(0, i - 1);
+    while (cl > 0 && !kept_bond(cl)) --cl;
+    return k > cl && k <= i + 1;
+  }
+  bool keep_right(int k, int i) const {
+    if (kept_bond(k)) return true;
+    int cr = std::min(P.L, i + 3);
+    while (cr < P.L && !kept_bond(cr)) ++cr;
+    return k >= i + 1 && k < cr;
+  }
+  void drop_blocks(int i) {
+    if (ckpt <= 0) return;
+    for (int k = 1; k < P.L; ++k) {
+      if (Lb[k] && !keep_left(k, i)) Lb[k].reset();
+      if (Rb[k] && !keep_right(k, i)) Rb[k].reset();
+    }
+  }
+  void note_block_bytes() {
+    double b = 0.0;
+    for (auto& x : Lb)
+      if (x) b += 8.0 * x->total;
+    for (auto& x : Rb)
+      if (x) b += 8.0 * x->total;
+    block_bytes_max = std::max(block_bytes_max, b);
   }
 
   // ---- prepare the two-site step at sites (i, i+1)
@@ -2887,8 +2979,8 @@ struct Engine {
     }
     auto t0 = std::chrono::steady_clock::now();
     const int c = i + 1;
-    Store& Lk = *Lb[i];
-    Store& Rk = *Rb[i + 2];
+    Store& Lk = lblock(i);
+    Store& Rk = rblock(i + 2);
     Enl el0 = left_enl(P, c, Lk.basis, nullptr), er0 = right_enl(P, c, Rk.basis, nullptr);
     std::set<Sec> keep;
     for (auto& s : el0.sec)
@@ -2911,6 +3003,7 @@ struct Engine {
       step.Y = cache_take(1, i, Rk, step.EY);
       if (!step.Y) step.Y = enlarge(P, Rk, step.EY, false, st, &ne);
     }
+    drop_blocks(i);
     // psi layout
     step.psi.sec = step.EX.sec;
     step.n = 0;
@@ -3965,6 +4058,7 @@ struct Engine {
       dims[c] = sp.kept;
       U[i] = std::move(u);
       Lb[c] = renormalize(*step.X, U[i], dims[c], true);
+      note_block_bytes();
       for (Lower& w : lower) lower_m(w, i);
       cen.kind = C_BOND_R;
       cen.pos = c;
@@ -4001,6 +4095,7 @@ struct Engine {
       dims[c] = sp.kept;
       V[i + 1] = std::move(v);
       Rb[c] = renormalize(*step.Y, V[i + 1], dims[c], false);
+      note_block_bytes();
       for (Lower& w : lower) lower_or(w, c);
       cen.kind = C_BOND_L;
       cen.pos = c;
@@ -6011,6 +6106,39 @@ int sadmrg_set_refinement(sadmrg_ctx* ctx, int steps) {
   });
 }
 
+int sadmrg_set_block_checkpoints(sadmrg_ctx* ctx, int interval) {
+  return guard(ctx, [&] {
+    auto& E = ctx->e;
+    if (interval < 0) sadmrg::fail(SADMRG_EINVAL, "checkpoint interval must be >= 0");
+    E.ckpt = interval;
+    if (interval > 0 && E.enl_cache_on) {  // the kept enlargements would hold what the checkpoints save
+      E.enl_cache_on = false;
+      E.clear_enl_cache();
+    }
+    if (E.mps_ready && interval > 0) {
+      const int i = E.step.i >= 0 ? E.step.i : (E.cen.pos >= 0 ? std::min(E.cen.pos, E.P.L - 2) : 0);
+      E.drop_blocks(std::max(0, i));
+    }
+    return 0;
+  });
+}
+
+int sadmrg_stats_blocks(sadmrg_ctx* ctx, int64_t* rebuilt, double* seconds, double* max_bytes, int* held) {
+  return guard(ctx, [&] {
+    const auto& E = ctx->e;
+    if (rebuilt) *rebuilt = E.n_rebuilt;
+    if (seconds) *seconds = E.t_rebuilt;
+    if (max_bytes) *max_bytes = E.block_bytes_max;
+    if (held) {
+      int n = 0;
+      for (auto& x : E.Lb) n += x ? 1 : 0;
+      for (auto& x : E.Rb) n += x ? 1 : 0;
+      *held = n;
+    }
+    return 0;
+  });
+}
+
 int sadmrg_set_davidson_graph(sadmrg_ctx* ctx, int replays) {
   return guard(ctx, [&] {
     if (replays < 0 || replays > 64) sadmrg::fail(SADMRG_EINVAL, "replays must be in 0..64");
@@ -6118,6 +6246,8 @@ int sadmrg_stats_reset(sadmrg_ctx* ctx) {
     E.n_sigma = 0;
     E.f_method = E.f_method_perf = 0;
     E.t_dgraph = E.f_dgraph = E.t_dgraph_rec = 0;
+    E.n_rebuilt = 0;
+    E.t_rebuilt = E.block_bytes_max = 0;
     E.n_dgraph_sigma = E.n_dgraph_replay = E.n_dgraph_record = 0;
     for (double& t : E.t_phase) t = 0.0;
     return 0;
