@@ -651,6 +651,7 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=4, help="sweeps of each mixed-precision record (at most "
                                                                "--steps)")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-renorm32", action="store_true", help="skip the FP32-renormalisation mixed record")
     ap.add_argument("--no-rdm", action="store_true")
     ap.add_argument("--no-method-count", action="store_true")
     ap.add_argument("--batch-n", type=int, default=64, help="independent problems of the lockstep batch; 0 = skip")
@@ -683,6 +684,8 @@ def main():
     ap.add_argument("--only-scheme", action="store_true", help="run only the Table 1 convergence-scheme record")
     ap.add_argument("--gpc", default="", help="fixed sigma launch shape 'pass1,pass2' (workgroups per CU) "
                                                "instead of autotuning")
+    ap.add_argument("--order", type=int, default=0, help="contraction order of the sigma products: 0 fewer flops, "
+                                                          "1 fewer bytes streamed")
     ap.add_argument("--xcd", default="", help="XCD-grouped workgroup order of the sigma passes 'pass1,pass2' "
                                                "(0/1 each)")
     args = ap.parse_args()
@@ -744,6 +747,7 @@ def main():
     if args.xcd:
         xcd = [int(v) for v in args.xcd.split(",")]
         g.set_xcd_order(*xcd)
+    g.set_contraction_order(args.order)
     g.init_mps(args.D)
     for w in range(args.warmup):
         t = time.time()
@@ -847,6 +851,7 @@ def main():
         "gemm_probe": gemm_probe,
         "autotune": tune,
         "xcd_order_pass1_pass2": xcd,
+        "contraction_order": "fewer bytes streamed" if args.order == 1 else "fewer flops",
         "host_phase_seconds_per_sweep": {k: v / args.steps for k, v in st["phases"].items()},
         "davidson_sigma_seconds_per_sweep": st["t_sigma"] / args.steps,
         "max_enlarged_bytes": st["max_enlarged_bytes"],
@@ -893,10 +898,15 @@ def main():
             r1, r2, _ = g.rdm()
             rdm_nmix = (r1, r2)
         ref_trace = trace64[n_before:n_before + nmix * per_sweep]
-        for mode, key, desc in (
-                (1, "mixed", "FP32 sigma (FP32 operators, FP32 accumulation) in Davidson"),
+        for mode, key, desc, rprec in (
+                (1, "mixed", "FP32 sigma (FP32 operators, FP32 accumulation) in Davidson", 0),
                 (2, "mixed_bf16x3", "BF16x3 sigma (hi*hi + hi*lo + lo*hi of BF16 splits of the FP32 operators, "
-                                    "FP32 accumulation) in Davidson")):
+                                    "FP32 accumulation) in Davidson", 0),
+                (1, "mixed_fp32_renorm", "FP32 sigma in Davidson and FP32 renormalisation products (the new "
+                                         "blocks stored in FP64 but carrying FP32 rounding)", 1)):
+            if rprec and args.no_renorm32:
+                continue
+            g.set_renorm_precision(rprec)
             g.set_precision(mode, args.mixed_tol)
             g.set_refinement(args.refine)
             g.set_refinement_tol(args.refine_tol)
@@ -920,12 +930,13 @@ def main():
             peak = FP32_MFMA_PEAK if mode == 1 else BF16_MFMA_PEAK / 3
             tf = sm["fp32"]["flops"] / max(sm["fp32"]["t"], 1e-12) / 1e12
             rec = {
-                "precision": desc + f"; FP64 Davidson algebra, SVD, renormalisation; {args.refine} FP64 Davidson "
-                                    f"step(s) ({args.refine + 1} FP64 sigma) refine each micro-iteration's vector "
-                                    "and give its energy",
+                "precision": desc + f"; FP64 Davidson algebra and SVD{'' if rprec else ', FP64 renormalisation'}; "
+                                    f"up to {args.refine} FP64 Davidson step(s) (until the FP64 residual is "
+                                    f"<= {args.refine_tol:g}) refine each micro-iteration's vector and give its energy",
                 "mixed_tol": args.mixed_tol,
                 "fp64_refinement_steps": args.refine,
                 "fp64_refinement_residual_target": args.refine_tol,
+                "renormalisation": "FP32" if rprec else "FP64",
                 "sweeps": nmix,
                 "s_per_sweep": sec_mixed,
                 "speedup_s_per_sweep": sec_per_sweep / sec_mixed,
@@ -945,6 +956,7 @@ def main():
                 rec["rdm_max_abs_error_vs_fp64"] = {"gamma": float(np.abs(m1 - rdm_nmix[0]).max()),
                                                     "Gamma": float(np.abs(m2 - rdm_nmix[1]).max())}
             line[key] = rec
+        g.set_renorm_precision(0)
     if args.graph > 0:
         # the first timed FP64 sweeps again from the same state with the
         # Davidson iterations replayed from a recorded HIP graph

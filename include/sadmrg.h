@@ -180,6 +180,16 @@ int sadmrg_set_davidson_graph(sadmrg_ctx* ctx, int replays);
 int sadmrg_stats_graph(sadmrg_ctx* ctx, double* seconds, double* record_seconds, double* sigma_flops,
                        int64_t* sigma_calls, int64_t* replays, int64_t* records);
 
+/* Precision of the renormalisation products (section "Sweeping": the new
+ * block's operators U^T O U after every decomposition).  mode 0 (default):
+ * FP64.  mode 1: FP32 copies of the enlarged operators (the sigma's FP32
+ * copies when the step has them) and of the tensor, FP32 products and
+ * accumulation, the new block stored in FP64.  mode 2: BF16x3 products on
+ * those FP32 copies.  The rounding stays in the renormalised operators for
+ * every later step and sweep.  Contexts swept together by
+ * sadmrg_batch_sweep must share it.  Errors: EINVAL. */
+int sadmrg_set_renorm_precision(sadmrg_ctx* ctx, int mode);
+
 /* Residual target of that refinement (default 0: always the set number of
  * steps).  With tol > 0, steps after the first run only while the FP64
  * residual norm |H x - theta x| of the refined vector is above tol, up to
@@ -254,6 +264,15 @@ int sadmrg_autotune(sadmrg_ctx* ctx, int reps, int* gpc1, int* gpc2, double* tab
  * the accumulating pass, 0 = one output tile per workgroup, at most 64.
  * Takes effect from the next prepared step.  Errors: EINVAL. */
 int sadmrg_set_launch_shape(sadmrg_ctx* ctx, int gpc1, int gpc2);
+
+/* How each sigma product out += c op(A) psi op(C) picks its contraction
+ * order (left first: T = op(A) psi, then T op(C); right first: U = psi
+ * op(C), then op(A) U).  mode 0 (default): fewer flops.  mode 1: fewer bytes
+ * streamed from memory when every 64-wide output tile reads its panels of
+ * op(A), op(C) and the intermediate (the psi block stays in the caches),
+ * flops deciding ties.  Results differ only by rounding.  Takes effect from
+ * the next prepared step.  Errors: EINVAL. */
+int sadmrg_set_contraction_order(sadmrg_ctx* ctx, int mode);
 
 /* Workgroup order of the two sigma GEMM passes (1 = on, 0 = off, per pass).
  * The dispatcher deals the workgroups of a launch to the device's eight XCDs

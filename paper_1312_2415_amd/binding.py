@@ -49,6 +49,7 @@ def load_library(path: str | None = None):
         "sadmrg_batch_sweep": (c_int, [P(c_vp), c_int, P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_solve": (c_int, [c_vp, c_int, P(c_int), P(c_dbl), P(c_int), P(c_dbl), P(c_dbl)]),
         "sadmrg_get_energy": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
+        "sadmrg_set_contraction_order": (c_int, [c_vp, c_int]),
         "sadmrg_set_xcd_order": (c_int, [c_vp, c_int, c_int]),
         "sadmrg_debug_gemm_probe": (c_int, [c_vp, c_int, c_int, c_int, P(c_dbl), P(c_dbl)]),
         "sadmrg_set_method_counter": (c_int, [c_vp, c_int]),
@@ -94,6 +95,7 @@ def load_library(path: str | None = None):
         "sadmrg_set_davidson_graph": (c_int, [c_vp, c_int]),
         "sadmrg_stats_graph": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl), P(ctypes.c_int64), P(ctypes.c_int64),
                                        P(ctypes.c_int64)]),
+        "sadmrg_set_renorm_precision": (c_int, [c_vp, c_int]),
         "sadmrg_set_refinement_tol": (c_int, [c_vp, c_dbl]),
         "sadmrg_set_precision": (c_int, [c_vp, c_int, c_dbl]),
         "sadmrg_rdm": (c_int, [c_vp, P(c_dbl), P(c_dbl), P(c_dbl)]),
@@ -428,6 +430,11 @@ class SaDMRG:
     def set_launch_shape(self, gpc1: int, gpc2: int):
         self._chk(self.lib.sadmrg_set_launch_shape(self.h, int(gpc1), int(gpc2)))
 
+    def set_contraction_order(self, mode: int):
+        """0: each sigma product in the order with fewer flops; 1: fewer bytes
+        streamed (sadmrg_set_contraction_order)."""
+        self._chk(self.lib.sadmrg_set_contraction_order(self.h, int(mode)))
+
     def set_xcd_order(self, pass1: bool, pass2: bool):
         """XCD-grouped workgroup order of the two sigma passes (sadmrg_set_xcd_order)."""
         self._chk(self.lib.sadmrg_set_xcd_order(self.h, int(bool(pass1)), int(bool(pass2))))
@@ -465,6 +472,10 @@ class SaDMRG:
                                               ctypes.byref(n), ctypes.byref(r), ctypes.byref(c)))
         return {"seconds": t.value, "record_seconds": tr.value, "sigma_flops": f.value, "sigma_calls": n.value,
                 "replays": r.value, "records": c.value}
+
+    def set_renorm_precision(self, mode: int):
+        """0 FP64, 1 FP32, 2 BF16x3 renormalisation products (sadmrg_set_renorm_precision)."""
+        self._chk(self.lib.sadmrg_set_renorm_precision(self.h, int(mode)))
 
     def set_refinement_tol(self, tol: float):
         """Residual target of the FP64 refinement (sadmrg_set_refinement_tol)."""

@@ -1470,9 +1470,23 @@ struct TwoPass {
 
 // keep2: hand the accumulating pass's product list to the caller instead of
 // planning it (a batch plans it with the cost target of the whole batch).
+// Operand bytes a product streams from memory in each contraction order when
+// every 64-wide output tile reads its panels of the two large factors
+// (op(A), op(C) and the intermediate; the psi block is small and stays in the
+// caches): left first, op(A) once per column tile of T, T and op(C) once per
+// column / row tile of the output; right first, op(C) once per row tile of
+// U, op(A) and U once per column / row tile of the output.
+static void product_traffic(double R, double K1, double K2, double C, double& left, double& right) {
+  auto tiles = [](double x) { return std::ceil(x / 64.0); };
+  left = 8.0 * (R * K1 * tiles(K2) + R * K2 + R * K2 * tiles(C) + K2 * C * tiles(R));
+  right = 8.0 * (K2 * C * tiles(K1) + K1 * C + R * K1 * tiles(C) + K1 * C * tiles(R));
+}
+
+// order: 0 = each product in the order with fewer flops; 1 = the order that
+// streams fewer bytes (product_traffic), flops deciding ties.
 static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Triple>& tr, TwoPass& tp, Stream st,
                            bool sigma = false, GemmList* keep2 = nullptr, int gpc1 = GEMM_GPC_PASS1,
-                           int gpc2 = GEMM_GPC_PASS2, int xcd1 = 0, int xcd2 = 0) {
+                           int gpc2 = GEMM_GPC_PASS2, int xcd1 = 0, int xcd2 = 0, int order = 0) {
   // Contraction order of every full product out[R x C] += c opA(A)[R x K1]
   // B'[K1 x K2] opC(C)[K2 x C] (B' = B or its transpose): left first (T =
   // opA(A) B' in the workspace, then out += c T opC(C): 2 R K2 (K1 + C)
@@ -1487,7 +1501,14 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
     if (!(tr[i].flags & (TT_IDENT_A | TT_IDENT_C))) {
       const Triple& x = tr[i];
       const double R = outs[x.blk].rows, Cc = outs[x.blk].cols;
-      right[i] = (double)x.K1 * Cc * (x.K2 + R) < R * x.K2 * (x.K1 + Cc);
+      const double fr = (double)x.K1 * Cc * (x.K2 + R), fl = R * x.K2 * (x.K1 + Cc);
+      if (order == 1) {
+        double bl, br;
+        product_traffic(R, x.K1, x.K2, Cc, bl, br);
+        right[i] = br < bl || (br == bl && fr < fl);
+      } else {
+        right[i] = fr < fl;
+      }
       slot[i] = ws;
       ws += right[i] ? (int64_t)x.K1 * outs[x.blk].cols : (int64_t)outs[x.blk].rows * x.K2;
     }
@@ -1564,6 +1585,48 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
   tp.p2.tag = tag2;
   tp.p1.xcd = xcd1;
   tp.p2.xcd = xcd2;
+}
+
+// A plan's records with every pointer moved from an FP64 buffer to its FP32
+// mirror (same element offsets): the FP32 form of the same products.
+struct PlanRegion {
+  const double* b64;
+  size_t n;
+  float* b32;
+};
+static void mirror_plan(const GemmList::Plan& a, GemmList::Plan& b, const PlanRegion* reg, int nreg, Stream st) {
+  auto remap = [&](const double* p) -> double* {
+    if (!p) return nullptr;
+    for (int r = 0; r < nreg; ++r)
+      if (reg[r].b64 && p >= reg[r].b64 && p < reg[r].b64 + reg[r].n) return (double*)(reg[r].b32 + (p - reg[r].b64));
+    fail(-5, "internal: product operand outside the known buffers");
+  };
+  std::vector<GTile> tl = a.tiles.host;
+  for (GTile& t : tl) {
+    t.out = remap(t.out);
+    t.part = remap(t.part);
+  }
+  std::vector<GTask> tk = a.tasks.host;
+  for (GTask& t : tk) {
+    t.a = remap(t.a);
+    t.b = remap(t.b);
+  }
+  std::vector<RTile> rd = a.reds.host;
+  for (RTile& r : rd) {
+    r.out = remap(r.out);
+    r.part = remap(r.part);
+  }
+  b.tiles.put(tl, st);
+  b.tasks.put(tk, st);
+  b.wstart.put(a.wstart.host, st);
+  b.reds.put(rd, st);
+  b.ntiles = a.ntiles;
+  b.nwg = a.nwg;
+  b.nreds = a.nreds;
+  b.stream = a.stream;
+  b.tag = a.tag;
+  b.xcd = a.xcd;
+  b.f32 = true;
 }
 
 // ---------------------------------------------------------------------------
@@ -1792,6 +1855,7 @@ struct Engine {
   int prec = 0;             // 0: FP64 sigma; 1 / 2: FP32 / BF16x3 sigma in Davidson + FP64 refinement
   double mixed_tol = 1e-5;  // Davidson tolerance of the FP32 phase
   int refine_steps = 1;     // FP64 Davidson steps after the FP32 phase
+  int renorm_prec = 0;      // renormalisation products: 0 FP64, 1 FP32, 2 BF16x3
   double refine_tol = 0.0;  // > 0: refinement steps stop once the FP64 residual norm is below it
   int64_t n_sigma = 0;
   // Davidson iterations replayed from a recorded launch sequence (0: the
@@ -1814,6 +1878,9 @@ struct Engine {
   // XCD-grouped workgroup order of the two sigma passes (0: dispatch order,
   // else the XCD count), set by sadmrg_set_xcd_order
   int xcd1 = GEMM_XCD_PASS1, xcd2 = GEMM_XCD_PASS2;
+  // contraction order of the sigma products (0: fewer flops, 1: fewer bytes
+  // streamed), set by sadmrg_set_contraction_order
+  int corder = 0;
   // Enlarged blocks kept from the previous pass (section "Sweeping"): while
   // a left-to-right pass renews the left blocks, the right blocks are the
   // ones the previous right-to-left pass built, so the enlargement of the
@@ -1951,7 +2018,8 @@ struct Engine {
   }
 
   // ---- renormalisation: left O' = U^T O U, right O' = V O V^T
-  std::unique_ptr<Store> renormalize(const Store& E, const Tensor& T, const Basis& nb, bool left) {
+  std::unique_ptr<Store> renormalize(const Store& E, const Tensor& T, const Basis& nb, bool left,
+                                     const float* E32 = nullptr, int prec32 = 0) {
     auto out = std::make_unique<Store>();
     out->side = E.side;
     out->bond = E.bond;
@@ -1993,7 +2061,40 @@ struct Engine {
     }
     TwoPass tp;
     build_two_pass(outs, trs, tp, st);
-    tp.run(st);
+    if (prec32 == 0) {
+      tp.run(st);
+    } else {
+      // The same products in reduced precision: FP32 copies of the enlarged
+      // store (the sigma mirror when given), of the tensor, of the output,
+      // workspace and partial tiles; FP32 (prec32 1) or BF16x3 (2) products
+      // with FP32 accumulation; the new block converted back to FP64.
+      DBuf e32, t32, o32, w32, q1p, q2p;
+      auto fbuf = [](DBuf& b, int64_t count) { b.alloc((size_t)std::max<int64_t>((count + 1) / 2, 1)); };
+      if (!E32) {
+        fbuf(e32, E.total);
+        launch_cvt_d2f((float*)e32.p, E.data.p, E.total, st);
+        E32 = (const float*)e32.p;
+      }
+      fbuf(t32, (int64_t)T.data.n);
+      launch_cvt_d2f((float*)t32.p, T.data.p, (int64_t)T.data.n, st);
+      fbuf(o32, out->total);
+      dev_zero(o32.p, o32.n * 8, st);
+      fbuf(w32, (int64_t)tp.ws.n);
+      fbuf(q1p, (int64_t)tp.p1.part.n);
+      fbuf(q2p, (int64_t)tp.p2.part.n);
+      const PlanRegion reg[] = {{E.data.p, (size_t)E.total, (float*)E32},
+                                {T.data.p, T.data.n, (float*)t32.p},
+                                {out->data.p, (size_t)out->total, (float*)o32.p},
+                                {tp.ws.p, tp.ws.n, (float*)w32.p},
+                                {tp.p1.part.p, tp.p1.part.n, (float*)q1p.p},
+                                {tp.p2.part.p, tp.p2.part.n, (float*)q2p.p}};
+      GemmList::Plan q1, q2;
+      mirror_plan(tp.p1, q1, reg, 6, st);
+      mirror_plan(tp.p2, q2, reg, 6, st);
+      q1.run(st, prec32 == 2);
+      q2.run(st, prec32 == 2);
+      launch_cvt_f2d(out->data.p, (const float*)o32.p, out->total, st);
+    }
     dev_sync(st);
     return out;
   }
@@ -3248,7 +3349,8 @@ struct Engine {
     bytes += 16.0 * step.n;
     t_phase[PH_TASKS] += std::chrono::duration<double>(std::chrono::steady_clock::now() - tt0).count();
     PhaseTimer pt(t_phase[PH_PLAN]);
-    build_two_pass(outs, trs, step.plan, st, true, defer_p2 ? &step.g2 : nullptr, gpc1, gpc2, xcd1, xcd2);
+    build_two_pass(outs, trs, step.plan, st, true, defer_p2 ? &step.g2 : nullptr, gpc1, gpc2, xcd1, xcd2,
+                   corder);
     step.p2_pending = defer_p2;
     step.trs = trs;
     step.flops = step.plan.flops;
@@ -3453,54 +3555,15 @@ struct Engine {
     alloc_f32(S.p2part32, (int64_t)S.plan.p2.part.n);
     launch_cvt_d2f((float*)S.x32.p, X.data.p, X.total, st);
     launch_cvt_d2f((float*)S.y32.p, Y.data.p, Y.total, st);
-    struct Region {
-      const double* b64;
-      size_t n;
-      float* b32;
-    };
-    const Region reg[] = {{X.data.p, (size_t)X.total, (float*)S.x32.p},
-                          {Y.data.p, (size_t)Y.total, (float*)S.y32.p},
-                          {S.in.p, (size_t)S.n, (float*)S.in32.p},
-                          {S.out.p, (size_t)S.n, (float*)S.out32.p},
-                          {S.plan.ws.p, S.plan.ws.n, (float*)S.ws32.p},
-                          {S.plan.p1.part.p, S.plan.p1.part.n, (float*)S.p1part32.p},
-                          {S.plan.p2.part.p, S.plan.p2.part.n, (float*)S.p2part32.p}};
-    auto remap = [&](const double* p) -> double* {
-      if (!p) return nullptr;
-      for (const Region& r : reg)
-        if (r.b64 && p >= r.b64 && p < r.b64 + r.n) return (double*)(r.b32 + (p - r.b64));
-      fail(-5, "internal: sigma operand outside the known buffers");
-    };
-    auto mirror = [&](const GemmList::Plan& a, GemmList::Plan& b) {
-      std::vector<GTile> tl = a.tiles.host;
-      for (GTile& t : tl) {
-        t.out = remap(t.out);
-        t.part = remap(t.part);
-      }
-      std::vector<GTask> tk = a.tasks.host;
-      for (GTask& t : tk) {
-        t.a = remap(t.a);
-        t.b = remap(t.b);
-      }
-      std::vector<RTile> rd = a.reds.host;
-      for (RTile& r : rd) {
-        r.out = remap(r.out);
-        r.part = remap(r.part);
-      }
-      b.tiles.put(tl, st);
-      b.tasks.put(tk, st);
-      b.wstart.put(a.wstart.host, st);
-      b.reds.put(rd, st);
-      b.ntiles = a.ntiles;
-      b.nwg = a.nwg;
-      b.nreds = a.nreds;
-      b.stream = a.stream;
-      b.tag = a.tag;
-      b.xcd = a.xcd;
-      b.f32 = true;
-    };
-    mirror(S.plan.p1, S.q1);
-    mirror(S.plan.p2, S.q2);
+    const PlanRegion reg[] = {{X.data.p, (size_t)X.total, (float*)S.x32.p},
+                              {Y.data.p, (size_t)Y.total, (float*)S.y32.p},
+                              {S.in.p, (size_t)S.n, (float*)S.in32.p},
+                              {S.out.p, (size_t)S.n, (float*)S.out32.p},
+                              {S.plan.ws.p, S.plan.ws.n, (float*)S.ws32.p},
+                              {S.plan.p1.part.p, S.plan.p1.part.n, (float*)S.p1part32.p},
+                              {S.plan.p2.part.p, S.plan.p2.part.n, (float*)S.p2part32.p}};
+    mirror_plan(S.plan.p1, S.q1, reg, 7, st);
+    mirror_plan(S.plan.p2, S.q2, reg, 7, st);
     S.f32_ready = true;
   }
 
@@ -3636,7 +3699,7 @@ struct Engine {
     for (int c = 0; c < TUNE_N; ++c) {
       const int g1 = TUNE_G1[c / 6], g2 = TUNE_G2[c % 6];
       TwoPass tp;
-      build_two_pass(outs, step.trs, tp, st, true, nullptr, g1, g2, xcd1, xcd2);
+      build_two_pass(outs, step.trs, tp, st, true, nullptr, g1, g2, xcd1, xcd2, corder);
       std::swap(tp, step.plan);
       sigma_fixed(false);  // warm-up
       const double t0 = t_sigma;
@@ -3656,7 +3719,7 @@ struct Engine {
     gpc1 = TUNE_G1[best / 6];
     gpc2 = TUNE_G2[best % 6];
     TwoPass tp;
-    build_two_pass(outs, step.trs, tp, st, true, nullptr, gpc1, gpc2, xcd1, xcd2);
+    build_two_pass(outs, step.trs, tp, st, true, nullptr, gpc1, gpc2, xcd1, xcd2, corder);
     std::swap(tp, step.plan);
     step.flops = step.plan.flops;
     step.f32_ready = false;
@@ -4057,7 +4120,8 @@ struct Engine {
         launch_scale_rows(cc.at(j), cc.rows[j], cc.cols[j], cc.cols[j], sp.sbuf.p + sp.so[sp.ms[j]], st);
       dims[c] = sp.kept;
       U[i] = std::move(u);
-      Lb[c] = renormalize(*step.X, U[i], dims[c], true);
+      Lb[c] = renormalize(*step.X, U[i], dims[c], true, step.f32_ready ? (const float*)step.x32.p : nullptr,
+                          renorm_prec);
       note_block_bytes();
       for (Lower& w : lower) lower_m(w, i);
       cen.kind = C_BOND_R;
@@ -4094,7 +4158,8 @@ struct Engine {
         launch_scale_cols(cc.at(j), cc.rows[j], cc.cols[j], cc.cols[j], sp.sbuf.p + sp.so[sp.ms[j]], st);
       dims[c] = sp.kept;
       V[i + 1] = std::move(v);
-      Rb[c] = renormalize(*step.Y, V[i + 1], dims[c], false);
+      Rb[c] = renormalize(*step.Y, V[i + 1], dims[c], false, step.f32_ready ? (const float*)step.y32.p : nullptr,
+                          renorm_prec);
       note_block_bytes();
       for (Lower& w : lower) lower_or(w, c);
       cen.kind = C_BOND_L;
@@ -5401,7 +5466,7 @@ int sadmrg_batch_sweep(sadmrg_ctx* const* ctxs, int n, const int* D, double* e_m
     if (e.device != e0.device || e.st != e0.st)
       return fail_all(SADMRG_EINVAL, "batched contexts must share one device and one stream");
     if (e.prec != e0.prec || e.refine_steps != e0.refine_steps || e.refine_tol != e0.refine_tol ||
-        e.dav_graph != e0.dav_graph)
+        e.dav_graph != e0.dav_graph || e.renorm_prec != e0.renorm_prec)
       return fail_all(SADMRG_EINVAL, "batched contexts must share one precision mode, refinement and recording");
   }
   try {
@@ -6161,6 +6226,14 @@ int sadmrg_stats_graph(sadmrg_ctx* ctx, double* seconds, double* record_seconds,
   });
 }
 
+int sadmrg_set_renorm_precision(sadmrg_ctx* ctx, int mode) {
+  return guard(ctx, [&] {
+    if (mode < 0 || mode > 2) sadmrg::fail(SADMRG_EINVAL, "renormalisation precision must be 0, 1 or 2");
+    ctx->e.renorm_prec = mode;
+    return 0;
+  });
+}
+
 int sadmrg_set_refinement_tol(sadmrg_ctx* ctx, double tol) {
   return guard(ctx, [&] {
     if (!(tol >= 0.0) || !std::isfinite(tol)) sadmrg::fail(SADMRG_EINVAL, "refinement tolerance must be >= 0");
@@ -6250,6 +6323,15 @@ int sadmrg_stats_reset(sadmrg_ctx* ctx) {
     E.t_rebuilt = E.block_bytes_max = 0;
     E.n_dgraph_sigma = E.n_dgraph_replay = E.n_dgraph_record = 0;
     for (double& t : E.t_phase) t = 0.0;
+    return 0;
+  });
+}
+
+int sadmrg_set_contraction_order(sadmrg_ctx* ctx, int mode) {
+  return guard(ctx, [&] {
+    if (mode != 0 && mode != 1) sadmrg::fail(SADMRG_EINVAL, "contraction order mode must be 0 or 1");
+    ctx->e.corder = mode;
+    ctx->e.step.i = -1;  // re-plan on the next step
     return 0;
   });
 }

@@ -172,6 +172,49 @@ def test_refinement_residual_target():
     assert calls[1e-8] > 2.0
 
 
+@pytest.mark.parametrize("mode,tol", [(1, 1e-5), (2, 1e-3)])
+def test_reduced_precision_renormalisation(mode, tol):
+    """Renormalisation products in FP32 (mode 1) or BF16x3 (mode 2): the
+    new blocks carry that rounding into every later step, so the sweep
+    energies move away from the FP64 oracle's by an amount of the order of
+    the products' rounding and stay within `tol` of them (with FP64 sigma,
+    and with FP32 sigma in Davidson as well)."""
+    from paper_1312_2415_amd.binding import SadmrgError
+    L, N, twoS, group, irrep, D, nsw, seed = 10, 6, 2, "D2h", 0, 24, 2, 5
+    I = make_integrals(L, group, seed)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    blob = sd.export_blob(dm)
+    for _ in range(nsw):
+        dm.sweep(D)
+    ref = np.array(dm.stats.energies)
+    for sigma_prec in (0, 1):
+        g = _gpu(L, group, I)
+        g.set_target(N, twoS, irrep)
+        g.set_davidson(1e-9, 32, 200)
+        if sigma_prec:
+            g.set_precision(sigma_prec, 1e-5)
+            g.set_refinement(4)
+            g.set_refinement_tol(1e-7)
+        g.set_renorm_precision(mode)
+        g.mps_import(blob)
+        for s in range(nsw):
+            print(f"renormalisation mode {mode} sigma {sigma_prec} sweep {s}", flush=True)
+            g.sweep(D)
+        got = g.trace()
+        assert len(got) == len(ref)
+        err = np.abs(got[-(L - 1):] - ref[-(L - 1):]).max()
+        print(f"max |dE| of the final pass {err:.2e}", flush=True)
+        assert err <= tol
+        assert abs(g.energy()[0] - dm.emin) <= tol
+        if sigma_prec == 0:
+            assert np.abs(got - ref).max() > 1e-12  # the reduced products really ran
+        with pytest.raises(SadmrgError):
+            g.set_renorm_precision(3)
+        g.close()
+
+
 def test_bf16x3_sigma_within_its_rounding_of_oracle():
     """Mode 2: BF16x3 products (hi*hi + hi*lo + lo*hi of the BF16 splits,
     FP32 accumulation).  The sigma stays within a few hundred times the

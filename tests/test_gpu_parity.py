@@ -386,3 +386,43 @@ def test_xcd_order_gives_identical_sigma():
     assert np.abs(y0 - ref).max() <= 1e-10 * np.abs(ref).max()
     g.close()
 
+
+
+def test_traffic_order_keeps_sigma_on_the_oracle():
+    """Contraction orders picked by the bytes a product streams
+    (sadmrg_set_contraction_order(1)) instead of its flops: sigma stays on
+    the oracle's at every step of the wide-block case, some products change
+    order, and the flops never drop below the minimum-flop plan's."""
+    L, N, twoS, group, irrep, D = 10, 10, 0, "C1", 0, 256
+    I = make_integrals(L, group, 11)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    g = _gpu(L, group, I)
+    g.set_target(N, twoS, irrep)
+    changed = 0.0
+    for i in range(L - 1):
+        print(f"traffic order step {i}", flush=True)
+        g.mps_import(sd.export_blob(dm))
+        g.set_contraction_order(0)
+        g.prepare_step()
+        f0 = g.sigma_counters()[0]
+        g.set_contraction_order(1)
+        g.prepare_step()
+        f1 = g.sigma_counters()[0]
+        assert f1 >= f0 * (1 - 1e-12)
+        changed += f1 - f0
+        desc, n = g.psi_layout()
+        El, Er, Xe, Ye, secs = dm.enlarged(i)
+        He = sd.Heff(P, Xe, Ye, secs)
+        shapes = {m: (El.dim[m], Er.dim[m]) for m in secs}
+        x = np.random.default_rng(700 + i).normal(size=n)
+        ref = sd.flatten(He.apply(sd.unflatten(x, shapes, secs)), secs)
+        assert np.abs(g.sigma(x) - ref).max() <= 1e-10 * np.abs(ref).max()
+        if i < L - 2:
+            dm.micro(i, D, "right")
+    assert changed > 0.0
+    from paper_1312_2415_amd.binding import SadmrgError
+    with pytest.raises(SadmrgError):
+        g.set_contraction_order(2)
+    g.close()
