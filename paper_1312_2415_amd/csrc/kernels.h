@@ -15,6 +15,12 @@ using Stream = void*;  // hipStream_t
 // ---------------------------------------------------------------------------
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
+// The raw calls under the pools (pool.cpp): a new device block or null, its
+// release, and the free / total bytes of the current device (false when the
+// runtime cannot tell).
+void* dev_raw_alloc(size_t bytes);
+void dev_raw_free(void* p);
+bool dev_raw_meminfo(size_t* free_bytes, size_t* total_bytes);
 // Per-context cache of device blocks (see kernels.hip); bind returns the
 // previously bound pool.  Destroy only after the context's stream is idle.
 struct DevPool;

@@ -1,0 +1,128 @@
+// Runs the engine's host code through the C ABI on the CPU device emulation
+// (kernels_emu.cpp), in the pattern of the batched sweeps: several contexts
+// advanced in lockstep by sadmrg_batch_sweep, whose per-problem preparation
+// and update run on the library's host worker threads, in FP64 and in mixed
+// precision, with checkpointed blocks, followed by separate sweeps and the
+// energy adjoint.  Built with -fsanitize=thread or -fsanitize=address by
+// tests/test_cpu_emulation.py; prints one summary line and returns nonzero on
+// an error or an inconsistent result.
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/sadmrg.h"
+
+namespace {
+
+uint64_t mix(uint64_t x) {  // SplitMix64 finaliser
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+double gauss(uint64_t& s) {  // Box-Muller on two counter draws
+  const double u1 = ((mix(++s) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  const double u2 = ((mix(++s) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+}
+
+// h_ii = -2 + 3i/(L-1), small symmetric off-diagonal h; (ij|kl) = sum_P B_ij B_kl
+void integrals(int L, uint64_t seed, std::vector<double>& h, std::vector<double>& eri) {
+  uint64_t s = seed * 1000003ull;
+  h.assign((size_t)L * L, 0.0);
+  for (int i = 0; i < L; ++i) {
+    h[(size_t)i * L + i] = -2.0 + 3.0 * i / (L - 1);
+    for (int j = 0; j < i; ++j) h[(size_t)i * L + j] = h[(size_t)j * L + i] = 0.02 * gauss(s);
+  }
+  eri.assign((size_t)L * L * L * L, 0.0);
+  std::vector<double> B((size_t)L * L);
+  for (int P = 0; P < 2 * L; ++P) {
+    for (int i = 0; i < L; ++i)
+      for (int j = 0; j <= i; ++j) B[(size_t)i * L + j] = B[(size_t)j * L + i] = 0.3 / std::sqrt(1.0 + i - j) * gauss(s);
+    for (size_t a = 0; a < (size_t)L * L; ++a)
+      for (size_t b = 0; b < (size_t)L * L; ++b) eri[a * L * L + b] += B[a] * B[b];
+  }
+}
+
+struct Spec {
+  int L, N, twoS, D;
+};
+
+bool ok(sadmrg_ctx* c, int rc, const char* what) {
+  if (rc < 0) {
+    std::printf("FAIL %s: %d %s\n", what, rc, c ? sadmrg_last_error(c) : "");
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+int main() {
+  const std::vector<Spec> specs = {{6, 6, 0, 16}, {7, 6, 2, 20}, {8, 8, 0, 24}, {6, 4, 0, 12}, {7, 8, 2, 20}};
+  const int n = (int)specs.size();
+  std::vector<sadmrg_ctx*> ctx(n, nullptr), twin(n, nullptr);
+  std::vector<int> Ds;
+  auto make = [&](int k, sadmrg_ctx** out) -> bool {
+    const Spec& s = specs[k];
+    std::vector<int> irr(s.L, 0);
+    if (!ok(nullptr, sadmrg_create(out, s.L, 1, irr.data(), 0), "create")) return false;
+    std::vector<double> h, eri;
+    integrals(s.L, 11 + k, h, eri);
+    return ok(*out, sadmrg_set_integrals(*out, 0.0, h.data(), eri.data(), 1e-10), "integrals") &&
+           ok(*out, sadmrg_set_target(*out, s.N, s.twoS, 0), "target") &&
+           ok(*out, sadmrg_set_davidson(*out, 1e-8, 16, 80), "davidson") &&
+           ok(*out, sadmrg_set_seed(*out, 5 + k), "seed");
+  };
+  for (int k = 0; k < n; ++k) {
+    if (!make(k, &ctx[k]) || !make(k, &twin[k])) return 1;
+    if (!ok(ctx[k], sadmrg_init_mps(ctx[k], specs[k].D), "init")) return 1;
+    Ds.push_back(specs[k].D);
+  }
+  std::vector<double> e(n), st(16);
+  // FP64 lockstep sweeps (worker threads prepare and update the problems)
+  for (int s = 0; s < 2; ++s)
+    if (!ok(ctx[0], sadmrg_batch_sweep(ctx.data(), n, Ds.data(), e.data(), st.data()), "batch sweep")) return 1;
+  // the same next sweep in lockstep and one problem at a time must agree
+  std::vector<std::vector<char>> blobs(n);
+  for (int k = 0; k < n; ++k) {
+    size_t bytes = 0;
+    if (!ok(ctx[k], sadmrg_mps_export(ctx[k], nullptr, &bytes), "export size")) return 1;
+    blobs[k].resize(bytes);
+    if (!ok(ctx[k], sadmrg_mps_export(ctx[k], blobs[k].data(), &bytes), "export")) return 1;
+    if (!ok(twin[k], sadmrg_mps_import(twin[k], blobs[k].data(), bytes), "import")) return 1;
+  }
+  if (!ok(ctx[0], sadmrg_batch_sweep(ctx.data(), n, Ds.data(), e.data(), st.data()), "batch sweep")) return 1;
+  double worst = 0.0;
+  for (int k = 0; k < n; ++k) {
+    double es = 0.0;
+    if (!ok(twin[k], sadmrg_sweep(twin[k], Ds[k], &es), "sweep")) return 1;
+    worst = std::fmax(worst, std::fabs(es - e[k]));
+  }
+  // mixed precision and checkpointed blocks in lockstep
+  for (int k = 0; k < n; ++k) {
+    if (!ok(ctx[k], sadmrg_set_precision(ctx[k], 1, 1e-5), "precision")) return 1;
+    if (!ok(ctx[k], sadmrg_set_block_checkpoints(ctx[k], 2), "checkpoints")) return 1;
+  }
+  if (!ok(ctx[0], sadmrg_batch_sweep(ctx.data(), n, Ds.data(), e.data(), st.data()), "mixed batch sweep")) return 1;
+  // the energy adjoint of each problem
+  for (int k = 0; k < n; ++k) {
+    const int L = specs[k].L;
+    std::vector<double> g1((size_t)L * L), g2((size_t)L * L * L * L);
+    double er = 0.0;
+    if (!ok(ctx[k], sadmrg_rdm(ctx[k], g1.data(), g2.data(), &er), "rdm")) return 1;
+    double tr = 0.0;
+    for (int i = 0; i < L; ++i) tr += g1[(size_t)i * L + i];
+    if (std::fabs(tr - specs[k].N) > 1e-8) {
+      std::printf("FAIL trace of the 1-RDM %g against N = %d\n", tr, specs[k].N);
+      return 1;
+    }
+  }
+  for (int k = 0; k < n; ++k) {
+    sadmrg_destroy(ctx[k]);
+    sadmrg_destroy(twin[k]);
+  }
+  std::printf("emulated batch: %d problems, lockstep vs separate max |dE| %.3e\n", n, worst);
+  return worst <= 1e-8 ? 0 : 2;
+}
