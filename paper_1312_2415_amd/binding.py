@@ -31,6 +31,14 @@ def load_library(path: str | None = None):
         return _LIB
     if not os.path.exists(path):
         raise RuntimeError(f"libsadmrg not built: {path} is missing (build it with python -m paper_1312_2415_amd.build)")
+    # torch's wheel ships its own HIP runtime under the same soname as the
+    # system one the library links; whichever is loaded first serves the whole
+    # process.  Loading torch first gives the library the runtime that owns
+    # torch's device tensors and streams (and keeps torch usable afterwards).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     c_int, c_dbl, c_vp, c_sz = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
     P = ctypes.POINTER
