@@ -24,6 +24,7 @@
 #include <chrono>
 #include <exception>
 #include <mutex>
+#include <functional>
 #include <thread>
 #include <climits>
 #include <cmath>
@@ -651,6 +652,44 @@ static void parallel_for(size_t n, int threads, F&& fn) {
 // host threads for the per-operator parts of an enlargement
 static const int ENLARGE_HOST_THREADS = 16;
 
+// fn on a host thread of its own (bound to the caller's device and
+// device-memory pool) while the caller goes on, when `on`; otherwise fn runs
+// in join().  join() (or the destructor, which swallows the error of an
+// unwinding caller) waits for it and rethrows its exception.
+struct Overlap {
+  std::function<void()> fn;
+  std::thread th;
+  std::exception_ptr err;
+  bool done = false;
+  Overlap(bool on, std::function<void()> f) : fn(std::move(f)) {
+    if (!on) return;
+    DevPool* const mem = dev_pool_current();
+    const int device = dev_get_device();
+    th = std::thread([this, mem, device] {
+      dev_pool_bind(mem);
+      try {
+        dev_set_device(device);
+        fn();
+      } catch (...) {
+        err = std::current_exception();
+      }
+    });
+  }
+  void join() {
+    if (done) return;
+    done = true;
+    if (th.joinable()) {
+      th.join();
+      if (err) std::rethrow_exception(err);
+    } else {
+      fn();
+    }
+  }
+  ~Overlap() {
+    if (th.joinable()) th.join();
+  }
+};
+
 struct Entry {
   int64_t dst;  // element offset in the enlarged store
   int64_t bstart;  // element offset of the enlarged block it lies in
@@ -764,32 +803,52 @@ struct Materializer {
   }
 
   void run(Store& Out, Stream st) {
-    std::vector<size_t> idx(entries.size());
-    std::iota(idx.begin(), idx.end(), 0);
     // group equal destinations, keeping the emission order inside a group
-    // (the order of the summands), one operator's segment at a time
+    // (the order of the summands), one operator's segment at a time on host
+    // threads; the segments' lists are then laid end to end
     if (seg.size() < 2) seg = {0, entries.size()};
-    parallel_for(seg.size() - 1, ENLARGE_HOST_THREADS, [&](size_t i) {
-      std::stable_sort(idx.begin() + seg[i], idx.begin() + seg[i + 1],
-                       [&](size_t a, size_t b) { return entries[a].dst < entries[b].dst; });
-    });
-    std::vector<GatherDst> dsts;
-    std::vector<GatherSrc> srcs;
-    srcs.reserve(entries.size());
-    for (size_t i = 0; i < idx.size();) {
-      const Entry& e0 = entries[idx[i]];
-      GatherDst d{Out.data.p + e0.dst, e0.rows, e0.cols, e0.ld, (int)srcs.size(), 0};
-      size_t j = i;
-      while (j < idx.size() && entries[idx[j]].dst == e0.dst) {
-        const Entry& e = entries[idx[j]];
-        if (e.rows != e0.rows || e.cols != e0.cols) fail(-1, "internal: overlapping sub-blocks of different shape");
-        srcs.push_back(e.src);
-        ++j;
+    const size_t nseg = seg.size() - 1;
+    std::vector<std::vector<GatherDst>> sd(nseg);
+    std::vector<std::vector<GatherSrc>> ss(nseg);
+    parallel_for(nseg, ENLARGE_HOST_THREADS, [&](size_t i) {
+      const size_t a = seg[i], n = seg[i + 1] - seg[i];
+      std::vector<std::pair<int64_t, uint32_t>> key(n);  // (destination, emission order)
+      for (size_t k = 0; k < n; ++k) key[k] = {entries[a + k].dst, (uint32_t)k};
+      std::sort(key.begin(), key.end());
+      std::vector<GatherDst>& dl = sd[i];
+      std::vector<GatherSrc>& sl = ss[i];
+      sl.reserve(n);
+      for (size_t k = 0; k < n;) {
+        const Entry& e0 = entries[a + key[k].second];
+        GatherDst d{Out.data.p + e0.dst, e0.rows, e0.cols, e0.ld, (int)sl.size(), 0};
+        size_t j = k;
+        for (; j < n && key[j].first == e0.dst; ++j) {
+          const Entry& e = entries[a + key[j].second];
+          if (e.rows != e0.rows || e.cols != e0.cols) fail(-1, "internal: overlapping sub-blocks of different shape");
+          sl.push_back(e.src);
+        }
+        d.s1 = (int)sl.size();
+        dl.push_back(d);
+        k = j;
       }
-      d.s1 = (int)srcs.size();
-      dsts.push_back(d);
-      i = j;
+    });
+    std::vector<size_t> od(nseg + 1, 0), os(nseg + 1, 0);
+    for (size_t i = 0; i < nseg; ++i) {
+      od[i + 1] = od[i] + sd[i].size();
+      os[i + 1] = os[i] + ss[i].size();
     }
+    if (os[nseg] > (size_t)INT32_MAX) fail(-4, "enlargement with more than 2^31 gather sources");
+    std::vector<GatherDst> dsts(od[nseg]);
+    std::vector<GatherSrc> srcs(os[nseg]);
+    parallel_for(nseg, ENLARGE_HOST_THREADS, [&](size_t i) {
+      for (size_t k = 0; k < sd[i].size(); ++k) {
+        GatherDst d = sd[i][k];
+        d.s0 += (int)os[i];
+        d.s1 += (int)os[i];
+        dsts[od[i] + k] = d;
+      }
+      std::copy(ss[i].begin(), ss[i].end(), srcs.begin() + (ptrdiff_t)os[i]);
+    });
     d_dst.put(dsts, st);
     d_src.put(srcs, st);
     launch_gather(d_dst.p, (int)dsts.size(), d_src.p, st);
@@ -1130,11 +1189,14 @@ static std::vector<Def> defs_right(const Problem& P, Store& Y, Combos& cb) {
 struct EnlargeTrace {
   Combos cb;
   std::vector<Def> defs;
+  std::vector<int> opidx;  // operator of out for every definition
   std::unique_ptr<Store> out;
   Materializer mat;
 };
 
-static void trace_enlarge(const Problem& P, Store& X, const Enl& E, bool left, Stream st, EnlargeTrace& tr) {
+// First part of an enlargement: the operator definitions, the combination
+// scratch (its kernel enqueued on st) and the enlarged store's layouts.
+static void trace_layouts(const Problem& P, Store& X, const Enl& E, bool left, Stream st, EnlargeTrace& tr) {
   tr.cb.T.side = X.side;
   tr.cb.T.bond = X.bond;
   tr.cb.T.basis = X.basis;
@@ -1151,8 +1213,14 @@ static void trace_enlarge(const Problem& P, Store& X, const Enl& E, bool left, S
     out.orbs.insert(out.orbs.begin(), X.bond - 1);
   out.basis.sec = E.sec;
   out.basis.dim = E.dim;
-  std::vector<int> opidx;
-  for (auto& d : tr.defs) opidx.push_back(out.add(d.key, d.tk, d.dN, d.dG, d.odd));
+  tr.opidx.clear();
+  for (auto& d : tr.defs) tr.opidx.push_back(out.add(d.key, d.tk, d.dN, d.dG, d.odd));
+}
+
+// Second part (host only, reads the stores' layouts): the gather entries of
+// every operator of the enlarged store `out` (the one trace_layouts built).
+static void trace_entries(const Problem& P, const Store& X, const Enl& E, bool left, EnlargeTrace& tr, Store& out) {
+  const std::vector<int>& opidx = tr.opidx;
   // the operators' entries are independent: emitted on host threads, then
   // concatenated in operator order (the serial emission order)
   std::vector<std::vector<Entry>> per(tr.defs.size());
@@ -1174,13 +1242,43 @@ static void trace_enlarge(const Problem& P, Store& X, const Enl& E, bool left, S
     pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
     out.has_pieces = true;
   }
-  tr.mat.entries.clear();
-  tr.mat.entries.reserve(tot);
   tr.mat.seg.assign(1, 0);
-  for (auto& v : per) {
-    tr.mat.entries.insert(tr.mat.entries.end(), v.begin(), v.end());
-    tr.mat.seg.push_back(tr.mat.entries.size());
+  for (auto& v : per) tr.mat.seg.push_back(tr.mat.seg.back() + v.size());
+  tr.mat.entries.resize(tot);
+  parallel_for(per.size(), ENLARGE_HOST_THREADS, [&](size_t i) {
+    std::copy(per[i].begin(), per[i].end(), tr.mat.entries.begin() + (ptrdiff_t)tr.mat.seg[i]);
+  });
+}
+
+static void trace_enlarge(const Problem& P, Store& X, const Enl& E, bool left, Stream st, EnlargeTrace& tr) {
+  trace_layouts(P, X, E, left, st, tr);
+  trace_entries(P, X, E, left, tr, *tr.out);
+}
+
+// Last part: the gather of the traced entries into `out` (allocated), then
+// the nonzero piece pairs when the method counter is on; waits for the
+// stream (the scratch combinations are released with the trace).
+static void enlarge_finish(EnlargeTrace& tr, Store& out, Stream st, int64_t* n_entries) {
+  tr.mat.run(out, st);
+  if (n_entries) *n_entries += tr.mat.n_entries;
+  if (out.has_pieces) {  // keep the piece pairs that hold a nonzero value
+    std::vector<Store::PieceRect>& pr = out.pieces;
+    std::vector<RectDesc> rd;
+    rd.reserve(pr.size());
+    for (const auto& q : pr) rd.push_back({q.bstart + (int64_t)q.roff * q.ld + q.coff, q.rows, q.cols, q.ld});
+    DArr<RectDesc> d_rd;
+    d_rd.put(rd, st);
+    DBuf fl;
+    fl.alloc(pr.size() / 8 + 1);
+    launch_rects_nonzero(out.data.p, d_rd.p, (int)rd.size(), (unsigned char*)fl.p, st);
+    std::vector<unsigned char> h(pr.size());
+    dev_d2h(h.data(), fl.p, h.size(), st);
+    size_t w = 0;
+    for (size_t q = 0; q < pr.size(); ++q)
+      if (h[q]) pr[w++] = pr[q];
+    pr.resize(w);
   }
+  dev_sync(st);
 }
 
 // Enlarge a block by one site: combinations, then materialisation.
@@ -1189,26 +1287,7 @@ static std::unique_ptr<Store> enlarge(const Problem& P, Store& X, const Enl& E, 
   EnlargeTrace tr;
   trace_enlarge(P, X, E, left, st, tr);
   tr.out->allocate(st);
-  tr.mat.run(*tr.out, st);
-  if (n_entries) *n_entries += tr.mat.n_entries;
-  if (tr.out->has_pieces) {  // keep the piece pairs that hold a nonzero value
-    std::vector<Store::PieceRect>& pr = tr.out->pieces;
-    std::vector<RectDesc> rd;
-    rd.reserve(pr.size());
-    for (const auto& q : pr) rd.push_back({q.bstart + (int64_t)q.roff * q.ld + q.coff, q.rows, q.cols, q.ld});
-    DArr<RectDesc> d_rd;
-    d_rd.put(rd, st);
-    DBuf fl;
-    fl.alloc(pr.size() / 8 + 1);
-    launch_rects_nonzero(tr.out->data.p, d_rd.p, (int)rd.size(), (unsigned char*)fl.p, st);
-    std::vector<unsigned char> h(pr.size());
-    dev_d2h(h.data(), fl.p, h.size(), st);
-    size_t w = 0;
-    for (size_t q = 0; q < pr.size(); ++q)
-      if (h[q]) pr[w++] = pr[q];
-    pr.resize(w);
-  }
-  dev_sync(st);  // scratch combinations are released on return
+  enlarge_finish(tr, *tr.out, st, n_entries);
   return std::move(tr.out);
 }
 
@@ -3097,14 +3176,29 @@ struct Engine {
     step.genX = Lk.gen;
     step.genY = Rk.gen;
     int64_t ne = 0;
+    // An enlargement built here is traced in two parts: its layouts (and
+    // device memory) first, so that the sigma products can be planned from
+    // them on a host thread while this one emits and gathers the enlarged
+    // operators' entries.
+    EnlargeTrace trX, trY;
+    bool freshX = false, freshY = false;
     {
       PhaseTimer pt(t_phase[PH_ENLARGE]);
       step.X = cache_take(0, i, Lk, step.EX);
-      if (!step.X) step.X = enlarge(P, Lk, step.EX, true, st, &ne);
+      if (!step.X) {
+        trace_layouts(P, Lk, step.EX, true, st, trX);
+        step.X = std::move(trX.out);
+        step.X->allocate(st);
+        freshX = true;
+      }
       step.Y = cache_take(1, i, Rk, step.EY);
-      if (!step.Y) step.Y = enlarge(P, Rk, step.EY, false, st, &ne);
+      if (!step.Y) {
+        trace_layouts(P, Rk, step.EY, false, st, trY);
+        step.Y = std::move(trY.out);
+        step.Y->allocate(st);
+        freshY = true;
+      }
     }
-    drop_blocks(i);
     // psi layout
     step.psi.sec = step.EX.sec;
     step.n = 0;
@@ -3118,7 +3212,22 @@ struct Engine {
     step.in.alloc((size_t)std::max<int64_t>(step.n, 1));
     step.out.alloc((size_t)std::max<int64_t>(step.n, 1));
     step.diag.alloc((size_t)std::max<int64_t>(step.n, 1));
-    build_sigma_tasks();
+    {
+      // the planner reads the stores' layouts only; the method counter's
+      // piece lists are written by the entries part, so it runs in order
+      Overlap planner(!tl_in_pool && (freshX || freshY) && !P.count_method, [this] { build_sigma_tasks(); });
+      PhaseTimer pt(t_phase[PH_ENLARGE]);
+      if (freshX) {
+        trace_entries(P, Lk, step.EX, true, trX, *step.X);
+        enlarge_finish(trX, *step.X, st, &ne);
+      }
+      if (freshY) {
+        trace_entries(P, Rk, step.EY, false, trY, *step.Y);
+        enlarge_finish(trY, *step.Y, st, &ne);
+      }
+      planner.join();
+    }
+    drop_blocks(i);
     max_enl_bytes = std::max(max_enl_bytes, 8.0 * (double)(step.X->total + step.Y->total));
     {
       PhaseTimer pt(t_phase[PH_DIAG]);
