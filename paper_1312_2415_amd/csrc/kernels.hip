@@ -1076,25 +1076,84 @@ __device__ inline double wave_sum(double v) {
 // Works on the tall orientation M (m x n, m >= n): columns are rotated until
 // mutually orthogonal; M V = U S.  Column pairs are visited in round-robin
 // (tournament) order, so n/2 disjoint pairs are processed concurrently: a
-// group of SVD_G lanes per pair, 64 / SVD_G pairs per wavefront at a time
-// (their loads in flight together).
+// group of G lanes per pair, G chosen per matrix so that a round's pairs
+// are all in flight at once where they fit (G = 8 from 65 pairs up, 16, 32,
+// 64 for fewer); a round is then a single pass of dependent memory accesses
+// instead of several.
 // ---------------------------------------------------------------------------
 #ifndef SVD_WAVES_N
 #define SVD_WAVES_N 16
 #endif
-#ifndef SVD_GROUP_N
-#define SVD_GROUP_N 32
-#endif
 constexpr int SVD_WAVES = SVD_WAVES_N;
-constexpr int SVD_G = SVD_GROUP_N;                   // lanes per column pair
-constexpr int SVD_PAIRS = SVD_WAVES * (64 / SVD_G);  // pairs processed at once
-static_assert(SVD_G == 16 || SVD_G == 32 || SVD_G == 64, "pair group size");
 
-// Sum over the SVD_G lanes of a group (butterfly: every lane of the group
-// ends with the same value, bit for bit).
+// Sum over the G lanes of a group (butterfly: every lane of the group ends
+// with the same value, bit for bit).
+template <int G>
 __device__ inline double group_sum(double v) {
-  for (int o = SVD_G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, SVD_G);
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
   return v;
+}
+
+// Jacobi sweeps over the columns of M (m x n) and V (n x n), column j
+// contiguous, until a sweep rotates no pair of columns that both hold more
+// than 1e-13 of the matrix norm (fro2 = squared Frobenius norm), at most 60
+// sweeps.  Pairs of smaller columns are still rotated, but do not keep the
+// sweeps going: in a rank-deficient matrix they are rounding noise whose
+// relative inner products never settle, and the decomposition replaces them
+// (vanishing singular values) anyway.
+template <int G>
+__device__ void svd_sweeps(double* M, double* V, int m, int n, double fro2) {
+  constexpr int PAIRS = SVD_WAVES * (64 / G);  // pairs processed at once
+  const int tid = threadIdx.x;
+  const int gl = tid % G, grp = tid / G;  // lane within its pair group, group index
+  __shared__ int s_rot;
+  const int np = (n % 2) ? n + 1 : n;  // tournament with a dummy when n is odd
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int round = 0; round < np - 1; ++round) {
+      // pairs (p, q) of the round-robin schedule: position 0 fixed, others rotate
+      for (int pr = grp; pr < np / 2; pr += PAIRS) {
+        // circle method: slot 0 fixed, slots 1..np-1 rotate; pair (slot pr, slot np-1-pr)
+        const int a = (pr == 0) ? 0 : ((pr - 1 + round) % (np - 1)) + 1;
+        const int b = ((np - 2 - pr + round) % (np - 1)) + 1;
+        const int p = min(a, b), q = max(a, b);
+        if (q >= n || p == q) continue;
+        double* mp = M + (int64_t)p * m;
+        double* mq = M + (int64_t)q * m;
+        double al = 0, be = 0, ga = 0;
+        for (int i = gl; i < m; i += G) {
+          const double x = mp[i], y = mq[i];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+        al = group_sum<G>(al);
+        be = group_sum<G>(be);
+        ga = group_sum<G>(ga);
+        if (fabs(ga) <= 1e-15 * sqrt(al * be) || ga == 0.0) continue;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+        for (int i = gl; i < m; i += G) {
+          const double x = mp[i], y = mq[i];
+          mp[i] = cs * x - sn * y;
+          mq[i] = sn * x + cs * y;
+        }
+        double* vp = V + (int64_t)p * n;
+        double* vq = V + (int64_t)q * n;
+        for (int i = gl; i < n; i += G) {
+          const double x = vp[i], y = vq[i];
+          vp[i] = cs * x - sn * y;
+          vq[i] = sn * x + cs * y;
+        }
+        if (gl == 0 && al > 1e-26 * fro2 && be > 1e-26 * fro2) s_rot = 1;
+      }
+      __syncthreads();
+    }
+    if (s_rot == 0) break;
+    __syncthreads();
+  }
 }
 
 __global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __restrict__ jobs) {
@@ -1106,7 +1165,6 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __res
   double* V = M + (int64_t)m * n;          // n x n, column j contiguous
   double* nrm = V + (int64_t)n * n;        // n
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
-  const int gl = tid % SVD_G, grp = tid / SVD_G;  // lane within its pair group, group index
   const int nth = blockDim.x;
   const double* A = jb.a;
   // load (column-major working copy of the tall orientation)
@@ -1115,56 +1173,26 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __res
     M[e] = tall ? A[(int64_t)i * jb.lda + j] : A[(int64_t)j * jb.lda + i];
   }
   for (int e = tid; e < n * n; e += nth) V[e] = (e / n == e % n) ? 1.0 : 0.0;
-  __syncthreads();
-
-  __shared__ int s_rot;
-  const int np = (n % 2) ? n + 1 : n;  // tournament with a dummy when n is odd
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    if (tid == 0) s_rot = 0;
-    __syncthreads();
-    for (int round = 0; round < np - 1; ++round) {
-      // pairs (p, q) of the round-robin schedule: position 0 fixed, others rotate
-      for (int pr = grp; pr < np / 2; pr += SVD_PAIRS) {
-        // circle method: slot 0 fixed, slots 1..np-1 rotate; pair (slot pr, slot np-1-pr)
-        const int a = (pr == 0) ? 0 : ((pr - 1 + round) % (np - 1)) + 1;
-        const int b = ((np - 2 - pr + round) % (np - 1)) + 1;
-        const int p = min(a, b), q = max(a, b);
-        if (q >= n || p == q) continue;
-        double* mp = M + (int64_t)p * m;
-        double* mq = M + (int64_t)q * m;
-        double al = 0, be = 0, ga = 0;
-        for (int i = gl; i < m; i += SVD_G) {
-          const double x = mp[i], y = mq[i];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
-        }
-        al = group_sum(al);
-        be = group_sum(be);
-        ga = group_sum(ga);
-        if (fabs(ga) <= 1e-15 * sqrt(al * be) || ga == 0.0) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-        for (int i = gl; i < m; i += SVD_G) {
-          const double x = mp[i], y = mq[i];
-          mp[i] = cs * x - sn * y;
-          mq[i] = sn * x + cs * y;
-        }
-        double* vp = V + (int64_t)p * n;
-        double* vq = V + (int64_t)q * n;
-        for (int i = gl; i < n; i += SVD_G) {
-          const double x = vp[i], y = vq[i];
-          vp[i] = cs * x - sn * y;
-          vq[i] = sn * x + cs * y;
-        }
-        if (gl == 0) s_rot = 1;
-      }
-      __syncthreads();
-    }
-    if (s_rot == 0) break;
-    __syncthreads();
+  __shared__ double s_fro[SVD_WAVES];
+  {
+    double f = 0;
+    for (int e = tid; e < m * n; e += nth) f += M[e] * M[e];
+    f = wave_sum(f);
+    if (lane == 0) s_fro[wv] = f;
   }
+  __syncthreads();
+  double fro2 = 0;
+  for (int w = 0; w < SVD_WAVES; ++w) fro2 += s_fro[w];
+
+  const int half = (n + 1) / 2;  // pairs per round
+  if (half <= SVD_WAVES)
+    svd_sweeps<64>(M, V, m, n, fro2);
+  else if (half <= 2 * SVD_WAVES)
+    svd_sweeps<32>(M, V, m, n, fro2);
+  else if (half <= 4 * SVD_WAVES)
+    svd_sweeps<16>(M, V, m, n, fro2);
+  else
+    svd_sweeps<8>(M, V, m, n, fro2);
   // column norms
   for (int j = wv; j < n; j += SVD_WAVES) {
     double s = 0;
@@ -1189,43 +1217,50 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __res
   double* VT = jb.vt;
   const double smax = nrm[s_ord[0]];
   for (int k = tid; k < n; k += nth) S[k] = nrm[s_ord[k]];
-  // long-side factor, with Gram-Schmidt completion of vanishing columns (serial, rare)
-  for (int k = 0; k < n; ++k) {
-    const int j = s_ord[k];
-    const double s = nrm[j];
-    const bool tiny = !(s > 1e-13 * smax) || s == 0.0;
-    // destination column k of the long-side factor
-    auto put = [&](int i, double v) {
-      if (tall)
-        U[(int64_t)i * n + k] = v;
-      else
-        VT[(int64_t)k * jb.cols + i] = v;
-    };
-    auto get = [&](int i, int kk) -> double { return tall ? U[(int64_t)i * n + kk] : VT[(int64_t)kk * jb.cols + i]; };
-    if (!tiny) {
-      for (int i = tid; i < m; i += nth) put(i, M[(int64_t)j * m + i] / s);
-      __syncthreads();
-      continue;
-    }
-    // completion: try unit vectors e_t until one survives orthogonalisation
-    for (int tt = 0; tt < m; ++tt) {
-      for (int i = tid; i < m; i += nth) put(i, i == tt ? 1.0 : 0.0);
+  // long-side factor: column k is M's column s_ord[k] / s while s is not
+  // vanishing (the columns are sorted, so those are a prefix) ...
+  auto put = [&](int i, int k, double v) {
+    if (tall)
+      U[(int64_t)i * n + k] = v;
+    else
+      VT[(int64_t)k * jb.cols + i] = v;
+  };
+  auto get = [&](int i, int k) -> double { return tall ? U[(int64_t)i * n + k] : VT[(int64_t)k * jb.cols + i]; };
+  int kt = 0;
+  while (kt < n && nrm[s_ord[kt]] > 1e-13 * smax && nrm[s_ord[kt]] != 0.0) ++kt;
+  for (int e = tid; e < kt * m; e += nth) {
+    const int k = e / m, i = e % m;
+    put(i, k, M[(int64_t)s_ord[k] * m + i] / nrm[s_ord[k]]);
+  }
+  __syncthreads();
+  // ... and the vanishing ones complete the set: column k from the unit
+  // vector e_t (t = k, k+1, ... mod m) orthogonalised twice against every
+  // earlier column at once (classical Gram-Schmidt: the inner products one
+  // wave per column, then one update pass), kept once the squared norm left
+  // exceeds half the average share (m - k) / m of the complement, which the
+  // best unit vector always reaches
+  __shared__ double s_d[1024];
+  __shared__ double s_red2[SVD_WAVES];
+  for (int k = kt; k < n; ++k) {
+    for (int a = 0; a < m; ++a) {
+      const int tt = (k + a) % m;
+      for (int i = tid; i < m; i += nth) put(i, k, i == tt ? 1.0 : 0.0);
       __syncthreads();
       for (int pass = 0; pass < 2; ++pass) {
-        for (int kk = 0; kk < k; ++kk) {
-          __shared__ double s_red[SVD_WAVES];
+        for (int kk = wv; kk < k; kk += SVD_WAVES) {
           double d = 0;
-          for (int i = tid; i < m; i += nth) d += get(i, kk) * get(i, k);
+          for (int i = lane; i < m; i += 64) d += get(i, kk) * get(i, k);
           d = wave_sum(d);
-          if (lane == 0) s_red[wv] = d;
-          __syncthreads();
-          double dd = 0;
-          for (int w = 0; w < SVD_WAVES; ++w) dd += s_red[w];
-          for (int i = tid; i < m; i += nth) put(i, get(i, k) - dd * get(i, kk));
-          __syncthreads();
+          if (lane == 0) s_d[kk] = d;
         }
+        __syncthreads();
+        for (int i = tid; i < m; i += nth) {
+          double v = get(i, k);
+          for (int kk = 0; kk < k; ++kk) v -= s_d[kk] * get(i, kk);
+          put(i, k, v);
+        }
+        __syncthreads();
       }
-      __shared__ double s_red2[SVD_WAVES];
       double d = 0;
       for (int i = tid; i < m; i += nth) d += get(i, k) * get(i, k);
       d = wave_sum(d);
@@ -1234,9 +1269,9 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __res
       double nn = 0;
       for (int w = 0; w < SVD_WAVES; ++w) nn += s_red2[w];
       __syncthreads();
-      if (nn > 0.25) {
+      if (nn > 0.5 * (double)(m - k) / (double)m) {
         const double inv = 1.0 / sqrt(nn);
-        for (int i = tid; i < m; i += nth) put(i, get(i, k) * inv);
+        for (int i = tid; i < m; i += nth) put(i, k, get(i, k) * inv);
         __syncthreads();
         break;
       }

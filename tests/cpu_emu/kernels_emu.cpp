@@ -279,6 +279,8 @@ static void svd_one(const SvdJob& jb) {
   for (int j = 0; j < n; ++j)
     for (int i = 0; i < m; ++i) M[(size_t)j * m + i] = tall ? jb.a[(int64_t)i * jb.lda + j] : jb.a[(int64_t)j * jb.lda + i];
   for (int j = 0; j < n; ++j) V[(size_t)j * n + j] = 1.0;
+  double fro2 = 0.0;  // sweeps end when no pair of columns above 1e-13 of the norm rotates
+  for (double x : M) fro2 += x * x;
   for (int sweep = 0; sweep < 60; ++sweep) {
     bool rot = false;
     for (int p = 0; p < n; ++p)
@@ -307,7 +309,7 @@ static void svd_one(const SvdJob& jb) {
           vp[i] = cs * x - sn * y;
           vq[i] = sn * x + cs * y;
         }
-        rot = true;
+        if (al > 1e-26 * fro2 && be > 1e-26 * fro2) rot = true;
       }
     if (!rot) break;
   }
@@ -335,17 +337,22 @@ static void svd_one(const SvdJob& jb) {
       for (int i = 0; i < m; ++i) put(i, k, M[(size_t)j * m + i] / s);
       continue;
     }
-    for (int tt = 0; tt < m; ++tt) {  // Gram-Schmidt completion with unit vectors
+    for (int a = 0; a < m; ++a) {  // completion with unit vectors e_t, t = k, k+1, ... mod m
+      const int tt = (k + a) % m;
       for (int i = 0; i < m; ++i) put(i, k, i == tt ? 1.0 : 0.0);
-      for (int pass = 0; pass < 2; ++pass)
-        for (int kk = 0; kk < k; ++kk) {
-          double d = 0;
-          for (int i = 0; i < m; ++i) d += get(i, kk) * get(i, k);
-          for (int i = 0; i < m; ++i) put(i, k, get(i, k) - d * get(i, kk));
+      for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+        std::vector<double> d(k, 0.0);
+        for (int kk = 0; kk < k; ++kk)
+          for (int i = 0; i < m; ++i) d[kk] += get(i, kk) * get(i, k);
+        for (int i = 0; i < m; ++i) {
+          double v = get(i, k);
+          for (int kk = 0; kk < k; ++kk) v -= d[kk] * get(i, kk);
+          put(i, k, v);
         }
+      }
       double nn = 0;
       for (int i = 0; i < m; ++i) nn += get(i, k) * get(i, k);
-      if (nn > 0.25) {
+      if (nn > 0.5 * (double)(m - k) / (double)m) {
         for (int i = 0; i < m; ++i) put(i, k, get(i, k) / std::sqrt(nn));
         break;
       }
