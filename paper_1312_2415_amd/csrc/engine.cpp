@@ -3977,7 +3977,50 @@ struct Engine {
     }
     DArr<SvdJob> dj;
     dj.put(jobs, st);
-    launch_svd(dj.p, (int)jobs.size(), maxs, st);
+    // matrices with 64 or more singular values are orthogonalised by block
+    // rounds (a workgroup per pair of column blocks, sweeps repeated until
+    // converged), the others in one workgroup each
+    std::vector<SvdJob> small, big;
+    std::vector<int> pbase{0};
+    int maxs_small = 1, maxs_big = 1, rounds = 0;
+    for (const SvdJob& jb : jobs) {
+      const int r = std::min(jb.rows, jb.cols);
+      if (r >= 64 && svd_block_fits(jb.rows, jb.cols)) {
+        big.push_back(jb);
+        pbase.push_back(pbase.back() + svd_block_pairs(jb.rows, jb.cols));
+        rounds = std::max(rounds, svd_block_rounds(jb.rows, jb.cols));
+        maxs_big = std::max(maxs_big, r);
+      } else {
+        small.push_back(jb);
+        maxs_small = std::max(maxs_small, r);
+      }
+    }
+    (void)maxs;
+    DArr<SvdJob> dsmall, dbig;
+    DArr<int> dpb, dfl;
+    if (!small.empty()) {
+      dsmall.put(small, st);
+      launch_svd(dsmall.p, (int)small.size(), maxs_small, st, 0);
+    }
+    if (!big.empty()) {
+      const int nb = (int)big.size();
+      dbig.put(big, st);
+      dpb.put(pbase, st);
+      // two flag arrays: the sweep's and the previous one's (a job whose
+      // previous sweep rotated nothing significant is skipped)
+      std::vector<int> fl(2 * nb, 1);
+      dfl.put(fl, st);
+      launch_svd(dbig.p, nb, maxs_big, st, 1);
+      for (int sweep = 0; sweep < 60; ++sweep) {
+        const int* act = dfl.p + nb * (sweep % 2);
+        int* cur = dfl.p + nb * ((sweep + 1) % 2);
+        dev_zero(cur, sizeof(int) * nb, st);
+        for (int r = 0; r < rounds; ++r) launch_svd_block(dbig.p, dpb.p, nb, pbase.back(), r, act, cur, st);
+        dev_d2h(fl.data(), cur, sizeof(int) * nb, st);
+        if (std::none_of(fl.begin(), fl.begin() + nb, [](int f) { return f != 0; })) break;
+      }
+      launch_svd(dbig.p, nb, maxs_big, st, 2);
+    }
     launch_svd_signs(dj.p, (int)jobs.size(), st);
     std::vector<double> s(nsv);
     dev_d2h(s.data(), sp.sbuf.p, (size_t)nsv * 8, st);

@@ -203,7 +203,22 @@ void launch_cvt_f2d(double* dst, const float* src, int64_t n, Stream st);
 void launch_gather(const GatherDst* dsts, int ndst, const GatherSrc* srcs, Stream st);
 void launch_combo(const ComboOut* outs, int nout, const ComboIn* ins, int64_t max_nnz, Stream st);
 void launch_diag(const DiagSec* secs, int nsec, const DiagTask* tasks, Stream st);
-void launch_svd(const SvdJob* jobs, int njobs, int max_short, Stream st);
+// phase 0: the whole decomposition in one workgroup per job; 1: only the
+// working copy for the block rounds; 2: only the outputs of a working copy
+// the block rounds have orthogonalised.
+void launch_svd(const SvdJob* jobs, int njobs, int max_short, Stream st, int phase = 0);
+// Block rounds of the one-sided Jacobi sweep for larger jobs (after phase 1,
+// before phase 2): job k owns workgroups [pair_base[k], pair_base[k+1]) (its
+// svd_block_pairs), npairs in total, pair_base ascending from 0; round r of
+// a sweep (svd_block_rounds of them for a job; later rounds leave it alone);
+// flags[k] is set when the round rotated a significant pair of job k; jobs
+// with active[k] == 0 are skipped.  A job fits when svd_block_fits (its
+// blocks' columns of M and V in LDS).
+bool svd_block_fits(int rows, int cols);
+int svd_block_pairs(int rows, int cols);
+int svd_block_rounds(int rows, int cols);
+void launch_svd_block(const SvdJob* jobs, const int* pair_base, int njobs, int npairs, int round,
+                      const int* active, int* flags, Stream st);
 // Sign convention of singular vectors: for every column a of U (rows x r,
 // leading dimension r) the entry of largest magnitude (lowest row among ties)
 // is made positive; row a of Vt (r x cols, leading dimension cols) follows.

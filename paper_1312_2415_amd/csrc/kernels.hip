@@ -1156,7 +1156,10 @@ __device__ void svd_sweeps(double* M, double* V, int m, int n, double fro2) {
   }
 }
 
-__global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __restrict__ jobs) {
+// phase 0: the whole decomposition; 1: only the working copy (M, V = 1, and
+// the squared norm of A in the norm slot, for svd_block_kernel); 2: only the
+// outputs of a working copy the block rounds have orthogonalised.
+__global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __restrict__ jobs, int phase) {
   const SvdJob jb = jobs[blockIdx.x];
   const bool tall = jb.rows >= jb.cols;
   const int m = tall ? jb.rows : jb.cols;  // long side
@@ -1167,32 +1170,39 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __res
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int nth = blockDim.x;
   const double* A = jb.a;
-  // load (column-major working copy of the tall orientation)
-  for (int e = tid; e < m * n; e += nth) {
-    const int j = e / m, i = e % m;  // column j, row i of the tall matrix
-    M[e] = tall ? A[(int64_t)i * jb.lda + j] : A[(int64_t)j * jb.lda + i];
-  }
-  for (int e = tid; e < n * n; e += nth) V[e] = (e / n == e % n) ? 1.0 : 0.0;
-  __shared__ double s_fro[SVD_WAVES];
-  {
-    double f = 0;
-    for (int e = tid; e < m * n; e += nth) f += M[e] * M[e];
-    f = wave_sum(f);
-    if (lane == 0) s_fro[wv] = f;
+  if (phase != 2) {
+    // load (column-major working copy of the tall orientation)
+    for (int e = tid; e < m * n; e += nth) {
+      const int j = e / m, i = e % m;  // column j, row i of the tall matrix
+      M[e] = tall ? A[(int64_t)i * jb.lda + j] : A[(int64_t)j * jb.lda + i];
+    }
+    for (int e = tid; e < n * n; e += nth) V[e] = (e / n == e % n) ? 1.0 : 0.0;
+    __shared__ double s_fro[SVD_WAVES];
+    {
+      double f = 0;
+      for (int e = tid; e < m * n; e += nth) f += M[e] * M[e];
+      f = wave_sum(f);
+      if (lane == 0) s_fro[wv] = f;
+    }
+    __syncthreads();
+    double fro2 = 0;
+    for (int w = 0; w < SVD_WAVES; ++w) fro2 += s_fro[w];
+    if (phase == 1) {
+      if (tid == 0) nrm[0] = fro2;
+      return;
+    }
+
+    const int half = (n + 1) / 2;  // pairs per round
+    if (half <= SVD_WAVES)
+      svd_sweeps<64>(M, V, m, n, fro2);
+    else if (half <= 2 * SVD_WAVES)
+      svd_sweeps<32>(M, V, m, n, fro2);
+    else if (half <= 4 * SVD_WAVES)
+      svd_sweeps<16>(M, V, m, n, fro2);
+    else
+      svd_sweeps<8>(M, V, m, n, fro2);
   }
   __syncthreads();
-  double fro2 = 0;
-  for (int w = 0; w < SVD_WAVES; ++w) fro2 += s_fro[w];
-
-  const int half = (n + 1) / 2;  // pairs per round
-  if (half <= SVD_WAVES)
-    svd_sweeps<64>(M, V, m, n, fro2);
-  else if (half <= 2 * SVD_WAVES)
-    svd_sweeps<32>(M, V, m, n, fro2);
-  else if (half <= 4 * SVD_WAVES)
-    svd_sweeps<16>(M, V, m, n, fro2);
-  else
-    svd_sweeps<8>(M, V, m, n, fro2);
   // column norms
   for (int j = wv; j < n; j += SVD_WAVES) {
     double s = 0;
@@ -1288,11 +1298,148 @@ __global__ __launch_bounds__(64 * SVD_WAVES) void svd_kernel(const SvdJob* __res
   }
 }
 
-void launch_svd(const SvdJob* jobs, int njobs, int max_short, Stream st) {
+void launch_svd(const SvdJob* jobs, int njobs, int max_short, Stream st, int phase) {
   if (njobs <= 0) return;
   if (max_short > 1024) dev_fail("svd: sector matrix too large (short side > 1024)");
-  hipLaunchKernelGGL(svd_kernel, dim3(njobs), dim3(64 * SVD_WAVES), 0, (hipStream_t)st, jobs);
+  if (phase < 0 || phase > 2) dev_fail("svd: phase must be 0, 1 or 2");
+  hipLaunchKernelGGL(svd_kernel, dim3(njobs), dim3(64 * SVD_WAVES), 0, (hipStream_t)st, jobs, phase);
   check_launch("svd");
+}
+
+// ---------------------------------------------------------------------------
+// Block one-sided Jacobi for the larger sector matrices: the working copy's
+// columns are cut into blocks of SVB_W; in round r of a sweep the blocks are
+// paired by the same round-robin schedule as single columns, and every pair
+// of blocks is a workgroup of its own, so a matrix is worked on by many
+// compute units at once.  A workgroup loads the pair's columns of M and V
+// into LDS, runs one sweep of the single-column method over them (one wave
+// per column pair, all in LDS) and writes them back; the memory traffic per
+// rotation falls by the width of a block and the rounds of a sweep by its
+// square.  flags[job] is set when a pair of columns that both hold more than
+// 1e-13 of the matrix norm was rotated (the convergence test of the
+// single-workgroup sweeps), so the host repeats sweeps until no flag is set;
+// a job whose previous sweep set no flag (active[k] == 0) is left alone.
+// ---------------------------------------------------------------------------
+constexpr int SVB_W = 16;                 // columns per block
+constexpr int SVB_LDS = 2 * SVB_W * 600;  // doubles of LDS: the pair's columns of M and V, m + n <= 600
+__global__ __launch_bounds__(1024) void svd_block_kernel(const SvdJob* __restrict__ jobs,
+                                                         const int* __restrict__ pair_base, int njobs, int round,
+                                                         const int* __restrict__ active, int* __restrict__ flags) {
+  __shared__ double sMV[SVB_LDS];
+  __shared__ int s_flag;
+  // job of this workgroup: the last k with pair_base[k] <= blockIdx.x
+  int k = 0;
+  {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (pair_base[mid] <= (int)blockIdx.x)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    k = lo;
+  }
+  if (!active[k]) return;  // converged in an earlier sweep
+  const SvdJob jb = jobs[k];
+  const bool tall = jb.rows >= jb.cols;
+  const int m = tall ? jb.rows : jb.cols, n = tall ? jb.cols : jb.rows;
+  double* M = jb.work;
+  double* V = M + (int64_t)m * n;
+  const double fro2 = V[(int64_t)n * n];  // phase 1 left it in the norm slot
+  const int nblk = (n + SVB_W - 1) / SVB_W, npb = nblk + (nblk & 1);
+  if (round >= npb - 1) return;
+  const int pr = (int)blockIdx.x - pair_base[k];
+  const int ba = (pr == 0) ? 0 : ((pr - 1 + round) % (npb - 1)) + 1;
+  const int bb = ((npb - 2 - pr + round) % (npb - 1)) + 1;
+  // local columns: block ba then block bb (a block at or past nblk is empty)
+  const int a0 = ba * SVB_W, a1 = ba < nblk ? min(a0 + SVB_W, n) : a0;
+  const int b0 = bb * SVB_W, b1 = bb < nblk ? min(b0 + SVB_W, n) : b0;
+  const int na = a1 - a0, nc = na + (b1 - b0);
+  if (nc < 2) return;
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
+  double* sM = sMV;               // local column c at c * m
+  double* sV = sMV + 2 * SVB_W * m;  // local column c at c * n
+  auto gcol = [&](int c) { return c < na ? a0 + c : b0 + (c - na); };
+  for (int e = tid; e < nc * m; e += 1024) {
+    const int c = e / m, i = e % m;
+    sM[e] = M[(int64_t)gcol(c) * m + i];
+  }
+  for (int e = tid; e < nc * n; e += 1024) {
+    const int c = e / n, i = e % n;
+    sV[e] = V[(int64_t)gcol(c) * n + i];
+  }
+  if (tid == 0) s_flag = 0;
+  __syncthreads();
+  const double tol = fmax(1e-15, (double)m * 2.220446049250313e-16);
+  const int npl = nc + (nc & 1);
+  for (int r = 0; r < npl - 1; ++r) {
+    // wave wv takes local pair wv of round r (npl / 2 <= SVB_W pairs, 16 waves)
+    if (wv < npl / 2) {
+      const int la = (wv == 0) ? 0 : ((wv - 1 + r) % (npl - 1)) + 1;
+      const int lb = ((npl - 2 - wv + r) % (npl - 1)) + 1;
+      const int p = min(la, lb), q = max(la, lb);
+      if (q < nc && p != q) {
+        double* mp = sM + p * m;
+        double* mq = sM + q * m;
+        double al = 0, be = 0, ga = 0;
+        for (int i = lane; i < m; i += 64) {
+          const double x = mp[i], y = mq[i];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (!(fabs(ga) <= tol * sqrt(al * be) || ga == 0.0)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          for (int i = lane; i < m; i += 64) {
+            const double x = mp[i], y = mq[i];
+            mp[i] = cs * x - sn * y;
+            mq[i] = sn * x + cs * y;
+          }
+          double* vp = sV + p * n;
+          double* vq = sV + q * n;
+          for (int i = lane; i < n; i += 64) {
+            const double x = vp[i], y = vq[i];
+            vp[i] = cs * x - sn * y;
+            vq[i] = sn * x + cs * y;
+          }
+          if (lane == 0 && al > 1e-26 * fro2 && be > 1e-26 * fro2) s_flag = 1;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nc * m; e += 1024) {
+    const int c = e / m, i = e % m;
+    M[(int64_t)gcol(c) * m + i] = sM[e];
+  }
+  for (int e = tid; e < nc * n; e += 1024) {
+    const int c = e / n, i = e % n;
+    V[(int64_t)gcol(c) * n + i] = sV[e];
+  }
+  if (tid == 0 && s_flag) flags[k] = 1;
+}
+
+bool svd_block_fits(int rows, int cols) { return rows + cols <= SVB_LDS / (2 * SVB_W); }
+int svd_block_pairs(int rows, int cols) {
+  const int nblk = (min(rows, cols) + SVB_W - 1) / SVB_W;
+  return (nblk + (nblk & 1)) / 2;
+}
+int svd_block_rounds(int rows, int cols) {
+  const int nblk = (min(rows, cols) + SVB_W - 1) / SVB_W;
+  return nblk + (nblk & 1) - 1;
+}
+void launch_svd_block(const SvdJob* jobs, const int* pair_base, int njobs, int npairs, int round,
+                      const int* active, int* flags, Stream st) {
+  if (njobs <= 0 || npairs <= 0) return;
+  hipLaunchKernelGGL(svd_block_kernel, dim3(npairs), dim3(1024), 0, (hipStream_t)st, jobs, pair_base, njobs, round,
+                     active, flags);
+  check_launch("svd_block");
 }
 
 __global__ __launch_bounds__(256) void svd_signs_kernel(const SvdJob* __restrict__ jobs) {

@@ -367,9 +367,21 @@ static void svd_one(const SvdJob& jb) {
         jb.u[(int64_t)i * n + k] = v;
     }
 }
-void launch_svd(const SvdJob* jobs, int njobs, int, Stream) {
+void launch_svd(const SvdJob* jobs, int njobs, int, Stream, int phase) {
+  // the block rounds are not emulated: phase 2 decomposes from A directly
+  if (phase == 1) return;
   for (int j = 0; j < njobs; ++j) svd_one(jobs[j]);
 }
+bool svd_block_fits(int rows, int cols) { return rows + cols <= 600; }
+int svd_block_pairs(int rows, int cols) {
+  const int nblk = (std::min(rows, cols) + 15) / 16;
+  return (nblk + (nblk & 1)) / 2;
+}
+int svd_block_rounds(int rows, int cols) {
+  const int nblk = (std::min(rows, cols) + 15) / 16;
+  return nblk + (nblk & 1) - 1;
+}
+void launch_svd_block(const SvdJob*, const int*, int, int, int, const int*, int*, Stream) {}
 void launch_svd_signs(const SvdJob* jobs, int njobs, Stream) {
   for (int q = 0; q < njobs; ++q) {
     const SvdJob& j = jobs[q];
