@@ -5,6 +5,8 @@ sigma vectors and the effective-Hamiltonian diagonal element by element
 (relative 1e-10), and per-micro-iteration energies of whole sweeps (1e-8 E_h),
 plus exactness against brute-force FCI where the bond dimension is complete.
 """
+import copy
+
 import numpy as np
 import pytest
 
@@ -425,4 +427,41 @@ def test_traffic_order_keeps_sigma_on_the_oracle():
     from paper_1312_2415_amd.binding import SadmrgError
     with pytest.raises(SadmrgError):
         g.set_contraction_order(2)
+    g.close()
+
+
+def test_decomposition_of_wide_sectors_keeps_sweeps_on_the_oracle():
+    """The wide-block case (C1, L = 10, D = 256: sector matrices with more than
+    64 singular values, decomposed by block Jacobi): from the oracle's state
+    at every step, two GPU micro-iterations against the oracle's two; the
+    second one's energy depends on the first one's decomposition, truncation
+    and renormalisation (1e-8 E_h), and the kept sector dimensions agree."""
+    L, N, twoS, group, irrep, D = 10, 10, 0, "C1", 0, 256
+    I = make_integrals(L, group, 11)
+    P = sd.Problem(I.h, I.eri, N, twoS, irrep, I.orb_irrep)
+    dm = sd.DMRG(P, D, seed=3)
+    dm.build_boundaries()
+    g = _gpu(L, group, I)
+    g.set_target(N, twoS, irrep)
+    g.set_davidson(1e-9, 32, 200)
+    widest = 0
+    for i in range(L - 3):
+        print(f"wide decomposition step {i}", flush=True)
+        g.mps_import(sd.export_blob(dm))
+        g.prepare_step()
+        desc, _ = g.psi_layout()
+        widest = max(widest, int(np.minimum(desc[:, 3], desc[:, 4]).max()))
+        e_gpu = [g.advance(D, 1)]
+        g.prepare_step()
+        desc1, _ = g.psi_layout()
+        e_gpu.append(g.advance(D, 1))
+        e_ora = [dm.micro(i, D, "right")]
+        after = copy.deepcopy(dm)  # the start of step i + 1
+        El, Er, _, _, secs = dm.enlarged(i + 1)
+        assert sorted((int(r[3]), int(r[4])) for r in desc1) == sorted((El.dim[m], Er.dim[m]) for m in secs)
+        e_ora.append(dm.micro(i + 1, D, "right"))
+        assert abs(e_gpu[0] - e_ora[0]) <= 1e-8
+        assert abs(e_gpu[1] - e_ora[1]) <= 1e-8
+        dm = after
+    assert widest >= 64
     g.close()
