@@ -666,7 +666,7 @@ def main():
     ap.add_argument("--refine", type=int, default=4, help="FP64 Davidson steps after the reduced-precision phase "
                                                           "(at most, with --refine-tol)")
     ap.add_argument("--only-roots", action="store_true", help="run only the roots record")
-    ap.add_argument("--refine-tol", type=float, default=1e-6, help="FP64 residual norm that ends the refinement "
+    ap.add_argument("--refine-tol", type=float, default=5e-7, help="FP64 residual norm that ends the refinement "
                                                                     "early (0 = always --refine steps)")
     ap.add_argument("--grad", type=int, default=4, help="integral orbits checked one by one by finite differences "
                                                         "in the energy-adjoint record at --grad-L orbitals (0 = skip)")
