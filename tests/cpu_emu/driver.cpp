@@ -3,15 +3,25 @@
 // advanced in lockstep by sadmrg_batch_sweep, whose per-problem preparation
 // and update run on the library's host worker threads, in FP64 and in mixed
 // precision, with checkpointed blocks, followed by separate sweeps and the
-// energy adjoint.  Built with -fsanitize=thread or -fsanitize=address by
+// energy adjoint; then (unless --no-block is given) the block-Jacobi
+// decomposition of a larger problem's wide sectors against the one-workgroup
+// decomposition.  Built with -fsanitize=thread or -fsanitize=address by
 // tests/test_cpu_emulation.py; prints one summary line and returns nonzero on
 // an error or an inconsistent result.
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <string>
 #include <vector>
 
 #include "../../include/sadmrg.h"
+
+namespace sadmrg {  // switches of the emulated device layer (kernels_emu.cpp)
+extern std::atomic<long> emu_svd_block_pairs_run;
+extern std::atomic<bool> emu_svd_block_off;
+}  // namespace sadmrg
 
 namespace {
 
@@ -59,13 +69,13 @@ bool ok(sadmrg_ctx* c, int rc, const char* what) {
 
 }  // namespace
 
-int main() {
+int main(int argc, char** argv) {
+  const bool block = !(argc > 1 && std::string(argv[1]) == "--no-block");
   const std::vector<Spec> specs = {{6, 6, 0, 16}, {7, 6, 2, 20}, {8, 8, 0, 24}, {6, 4, 0, 12}, {7, 8, 2, 20}};
   const int n = (int)specs.size();
   std::vector<sadmrg_ctx*> ctx(n, nullptr), twin(n, nullptr);
   std::vector<int> Ds;
-  auto make = [&](int k, sadmrg_ctx** out) -> bool {
-    const Spec& s = specs[k];
+  auto make_spec = [&](const Spec& s, int k, sadmrg_ctx** out) -> bool {
     std::vector<int> irr(s.L, 0);
     if (!ok(nullptr, sadmrg_create(out, s.L, 1, irr.data(), 0), "create")) return false;
     std::vector<double> h, eri;
@@ -75,6 +85,7 @@ int main() {
            ok(*out, sadmrg_set_davidson(*out, 1e-8, 16, 80), "davidson") &&
            ok(*out, sadmrg_set_seed(*out, 5 + k), "seed");
   };
+  auto make = [&](int k, sadmrg_ctx** out) -> bool { return make_spec(specs[k], k, out); };
   for (int k = 0; k < n; ++k) {
     if (!make(k, &ctx[k]) || !make(k, &twin[k])) return 1;
     if (!ok(ctx[k], sadmrg_init_mps(ctx[k], specs[k].D), "init")) return 1;
@@ -123,6 +134,45 @@ int main() {
     sadmrg_destroy(ctx[k]);
     sadmrg_destroy(twin[k]);
   }
-  std::printf("emulated batch: %d problems, lockstep vs separate max |dE| %.3e\n", n, worst);
-  return worst <= 1e-8 ? 0 : 2;
+  // the decomposition of sectors with 64 or more singular values (the first
+  // six steps of a larger problem after one sweep of short Davidson solves):
+  // the block path and the one-workgroup path give the same micro-iterations
+  double svd_diff = 0.0;
+  long block_pairs = 0;
+  if (block) {
+    const Spec big = {10, 10, 0, 200};
+    sadmrg_ctx *w = nullptr, *w2 = nullptr;
+    double ew = 0.0;
+    if (!make_spec(big, 7, &w) || !make_spec(big, 7, &w2)) return 1;
+    for (sadmrg_ctx* c : {w, w2})
+      if (!ok(c, sadmrg_set_davidson(c, 1e-8, 8, 2), "davidson")) return 1;
+    if (!ok(w, sadmrg_init_mps(w, big.D), "init") || !ok(w, sadmrg_sweep(w, big.D, &ew), "sweep")) return 1;
+    size_t bytes = 0;
+    if (!ok(w, sadmrg_mps_export(w, nullptr, &bytes), "export size")) return 1;
+    std::vector<char> blob(bytes);
+    if (!ok(w, sadmrg_mps_export(w, blob.data(), &bytes), "export") ||
+        !ok(w2, sadmrg_mps_import(w2, blob.data(), bytes), "import") ||
+        !ok(w, sadmrg_mps_import(w, blob.data(), bytes), "import"))
+      return 1;
+    sadmrg::emu_svd_block_off = true;
+    if (!ok(w2, sadmrg_advance(w2, big.D, 6, &ew), "advance")) return 1;
+    sadmrg::emu_svd_block_off = false;
+    const long before = sadmrg::emu_svd_block_pairs_run;
+    if (!ok(w, sadmrg_advance(w, big.D, 6, &ew), "advance")) return 1;
+    block_pairs = sadmrg::emu_svd_block_pairs_run - before;
+    int n1 = 0, n2 = 0;
+    sadmrg_get_trace(w, nullptr, &n1);
+    sadmrg_get_trace(w2, nullptr, &n2);
+    std::vector<double> t1(std::max(n1, 1)), t2(std::max(n2, 1));
+    sadmrg_get_trace(w, t1.data(), &n1);
+    sadmrg_get_trace(w2, t2.data(), &n2);
+    for (int q = 1; q <= 6; ++q)
+      svd_diff = std::fmax(svd_diff, q <= n1 && q <= n2 ? std::fabs(t1[n1 - q] - t2[n2 - q]) : 1.0);
+    sadmrg_destroy(w2);
+    sadmrg_destroy(w);
+  }
+  std::printf("emulated batch: %d problems, lockstep vs separate max |dE| %.3e; block decomposition: %ld block "
+              "pairs, against one workgroup |dE| %.3e\n",
+              n, worst, block_pairs, svd_diff);
+  return worst <= 1e-8 && (!block || block_pairs > 0) && svd_diff <= 1e-9 ? 0 : 2;
 }

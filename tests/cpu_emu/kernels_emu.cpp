@@ -272,47 +272,70 @@ void launch_diag(const DiagSec* secs, int nsec, const DiagTask* tasks, Stream) {
 }
 
 // ---- SVD (one-sided Jacobi, the layout of SvdJob) ----------------------------------
-static void svd_one(const SvdJob& jb) {
-  const bool tall = jb.rows >= jb.cols;
-  const int m = tall ? jb.rows : jb.cols, n = tall ? jb.cols : jb.rows;
-  std::vector<double> M((size_t)m * n), V((size_t)n * n, 0.0), nrm(n);
-  for (int j = 0; j < n; ++j)
-    for (int i = 0; i < m; ++i) M[(size_t)j * m + i] = tall ? jb.a[(int64_t)i * jb.lda + j] : jb.a[(int64_t)j * jb.lda + i];
-  for (int j = 0; j < n; ++j) V[(size_t)j * n + j] = 1.0;
-  double fro2 = 0.0;  // sweeps end when no pair of columns above 1e-13 of the norm rotates
-  for (double x : M) fro2 += x * x;
+// The working copy lives in the job's work buffer as on the device: M (m x n,
+// column j at j*m), V (n x n, column j at j*n), then the norm slot (n).
+struct SvdView {
+  bool tall;
+  int m, n;
+  double *M, *V, *nrm;
+  explicit SvdView(const SvdJob& jb)
+      : tall(jb.rows >= jb.cols), m(tall ? jb.rows : jb.cols), n(tall ? jb.cols : jb.rows), M(jb.work),
+        V(jb.work + (size_t)m * n), nrm(jb.work + (size_t)m * n + (size_t)n * n) {}
+};
+// one Jacobi rotation of columns p, q of M (and V); returns true when the
+// pair was rotated and both columns hold more than 1e-13 of the norm
+static bool svd_rotate(double* mp, double* mq, double* vp, double* vq, int m, int n, double tol, double fro2) {
+  double al = 0, be = 0, ga = 0;
+  for (int i = 0; i < m; ++i) {
+    al += mp[i] * mp[i];
+    be += mq[i] * mq[i];
+    ga += mp[i] * mq[i];
+  }
+  if (std::fabs(ga) <= tol * std::sqrt(al * be) || ga == 0.0) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+  const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+  for (int i = 0; i < m; ++i) {
+    const double x = mp[i], y = mq[i];
+    mp[i] = cs * x - sn * y;
+    mq[i] = sn * x + cs * y;
+  }
+  for (int i = 0; i < n; ++i) {
+    const double x = vp[i], y = vq[i];
+    vp[i] = cs * x - sn * y;
+    vq[i] = sn * x + cs * y;
+  }
+  return al > 1e-26 * fro2 && be > 1e-26 * fro2;
+}
+static void svd_load(const SvdJob& jb) {
+  SvdView w(jb);
+  for (int j = 0; j < w.n; ++j)
+    for (int i = 0; i < w.m; ++i)
+      w.M[(size_t)j * w.m + i] = w.tall ? jb.a[(int64_t)i * jb.lda + j] : jb.a[(int64_t)j * jb.lda + i];
+  for (size_t e = 0; e < (size_t)w.n * w.n; ++e) w.V[e] = (e / w.n == e % w.n) ? 1.0 : 0.0;
+  double fro2 = 0.0;
+  for (size_t e = 0; e < (size_t)w.m * w.n; ++e) fro2 += w.M[e] * w.M[e];
+  w.nrm[0] = fro2;
+}
+static void svd_sweeps_serial(const SvdJob& jb) {
+  SvdView w(jb);
+  const double fro2 = w.nrm[0];
   for (int sweep = 0; sweep < 60; ++sweep) {
     bool rot = false;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        double* mp = &M[(size_t)p * m];
-        double* mq = &M[(size_t)q * m];
-        double al = 0, be = 0, ga = 0;
-        for (int i = 0; i < m; ++i) {
-          al += mp[i] * mp[i];
-          be += mq[i] * mq[i];
-          ga += mp[i] * mq[i];
-        }
-        if (std::fabs(ga) <= 1e-15 * std::sqrt(al * be) || ga == 0.0) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
-        for (int i = 0; i < m; ++i) {
-          const double x = mp[i], y = mq[i];
-          mp[i] = cs * x - sn * y;
-          mq[i] = sn * x + cs * y;
-        }
-        double* vp = &V[(size_t)p * n];
-        double* vq = &V[(size_t)q * n];
-        for (int i = 0; i < n; ++i) {
-          const double x = vp[i], y = vq[i];
-          vp[i] = cs * x - sn * y;
-          vq[i] = sn * x + cs * y;
-        }
-        if (al > 1e-26 * fro2 && be > 1e-26 * fro2) rot = true;
-      }
+    for (int p = 0; p < w.n; ++p)
+      for (int q = p + 1; q < w.n; ++q)
+        rot |= svd_rotate(w.M + (size_t)p * w.m, w.M + (size_t)q * w.m, w.V + (size_t)p * w.n, w.V + (size_t)q * w.n,
+                          w.m, w.n, 1e-15, fro2);
     if (!rot) break;
   }
+}
+static void svd_output(const SvdJob& jb) {
+  SvdView w(jb);
+  const int m = w.m, n = w.n;
+  const bool tall = w.tall;
+  const double* M = w.M;
+  const double* V = w.V;
+  std::vector<double> nrm(n);
   for (int j = 0; j < n; ++j) {
     double s = 0;
     for (int i = 0; i < m; ++i) s += M[(size_t)j * m + i] * M[(size_t)j * m + i];
@@ -368,20 +391,61 @@ static void svd_one(const SvdJob& jb) {
     }
 }
 void launch_svd(const SvdJob* jobs, int njobs, int, Stream, int phase) {
-  // the block rounds are not emulated: phase 2 decomposes from A directly
-  if (phase == 1) return;
-  for (int j = 0; j < njobs; ++j) svd_one(jobs[j]);
+  for (int j = 0; j < njobs; ++j) {
+    if (phase != 2) svd_load(jobs[j]);
+    if (phase == 0) svd_sweeps_serial(jobs[j]);
+    if (phase != 1) svd_output(jobs[j]);
+  }
 }
-bool svd_block_fits(int rows, int cols) { return rows + cols <= 600; }
+// Block rounds as the device runs them: workgroup b takes block pair b -
+// pair_base[k] of job k; the pairs of one round touch disjoint columns, so
+// running them one after another is the same computation.
+static constexpr int EMU_SVB_W = 16;
+std::atomic<long> emu_svd_block_pairs_run{0};  // block pairs processed (read by the test driver)
+std::atomic<bool> emu_svd_block_off{false};    // the test driver's switch to the one-workgroup path
+bool svd_block_fits(int rows, int cols) { return !emu_svd_block_off && rows + cols <= 600; }
 int svd_block_pairs(int rows, int cols) {
-  const int nblk = (std::min(rows, cols) + 15) / 16;
+  const int nblk = (std::min(rows, cols) + EMU_SVB_W - 1) / EMU_SVB_W;
   return (nblk + (nblk & 1)) / 2;
 }
 int svd_block_rounds(int rows, int cols) {
-  const int nblk = (std::min(rows, cols) + 15) / 16;
+  const int nblk = (std::min(rows, cols) + EMU_SVB_W - 1) / EMU_SVB_W;
   return nblk + (nblk & 1) - 1;
 }
-void launch_svd_block(const SvdJob*, const int*, int, int, int, const int*, int*, Stream) {}
+void launch_svd_block(const SvdJob* jobs, const int* pair_base, int njobs, int npairs, int round, const int* active,
+                      int* flags, Stream) {
+  for (int b = 0; b < npairs; ++b) {
+    int k = 0;
+    while (k + 1 < njobs && pair_base[k + 1] <= b) ++k;
+    if (!active[k]) continue;
+    SvdView w(jobs[k]);
+    const int nblk = (w.n + EMU_SVB_W - 1) / EMU_SVB_W, npb = nblk + (nblk & 1);
+    if (round >= npb - 1) continue;
+    const int pr = b - pair_base[k];
+    const int ba = (pr == 0) ? 0 : ((pr - 1 + round) % (npb - 1)) + 1;
+    const int bb = ((npb - 2 - pr + round) % (npb - 1)) + 1;
+    std::vector<int> cols;
+    for (int blk : {ba, bb})
+      if (blk < nblk)
+        for (int c = blk * EMU_SVB_W; c < std::min((blk + 1) * EMU_SVB_W, w.n); ++c) cols.push_back(c);
+    const int nc = (int)cols.size();
+    if (nc < 2) continue;
+    ++emu_svd_block_pairs_run;
+    const double tol = std::fmax(1e-15, w.m * 2.220446049250313e-16);
+    const int npl = nc + (nc & 1);
+    bool sig = false;
+    for (int r = 0; r < npl - 1; ++r)
+      for (int wv = 0; wv < npl / 2; ++wv) {
+        const int la = (wv == 0) ? 0 : ((wv - 1 + r) % (npl - 1)) + 1;
+        const int lb = ((npl - 2 - wv + r) % (npl - 1)) + 1;
+        const int p = std::min(la, lb), q = std::max(la, lb);
+        if (q >= nc || p == q) continue;
+        sig |= svd_rotate(w.M + (size_t)cols[p] * w.m, w.M + (size_t)cols[q] * w.m, w.V + (size_t)cols[p] * w.n,
+                          w.V + (size_t)cols[q] * w.n, w.m, w.n, tol, w.nrm[0]);
+      }
+    if (sig) flags[k] = 1;
+  }
+}
 void launch_svd_signs(const SvdJob* jobs, int njobs, Stream) {
   for (int q = 0; q < njobs; ++q) {
     const SvdJob& j = jobs[q];
