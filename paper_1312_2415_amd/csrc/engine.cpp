@@ -701,10 +701,11 @@ struct Entry {
 };
 
 struct Materializer {
-  std::vector<Entry> entries;
-  // entries[seg[i], seg[i+1]) write operator i of the enlarged store (each
-  // operator has its own region, so equal destinations stay in one segment)
-  std::vector<size_t> seg;
+  std::vector<Entry> entries;  // what emit_op appends to
+  // parts[i]: the entries that write operator i of the enlarged store, in
+  // emission order (each operator has its own region, so equal destinations
+  // stay in one part)
+  std::vector<std::vector<Entry>> parts;
 
   void emit_op(const Problem& P, const Store& X, const Store& T, const Enl& E, Store& Out, int outop,
                const Term& term, bool left, bool mirror) {
@@ -804,57 +805,50 @@ struct Materializer {
 
   void run(Store& Out, Stream st) {
     // group equal destinations, keeping the emission order inside a group
-    // (the order of the summands), one operator's segment at a time on host
-    // threads; the segments' lists are then laid end to end
-    if (seg.size() < 2) seg = {0, entries.size()};
-    const size_t nseg = seg.size() - 1;
+    // (the order of the summands), one operator's part at a time on host
+    // threads; every entry is one gather source, so each part's sources go
+    // straight to their place in the final list (the destinations, fewer and
+    // known only after grouping, are laid end to end afterwards)
+    const size_t nseg = parts.size();
+    std::vector<size_t> os(nseg + 1, 0);
+    for (size_t i = 0; i < nseg; ++i) os[i + 1] = os[i] + parts[i].size();
+    if (os[nseg] > (size_t)INT32_MAX) fail(-4, "enlargement with more than 2^31 gather sources");
+    std::vector<GatherSrc> srcs(os[nseg]);
     std::vector<std::vector<GatherDst>> sd(nseg);
-    std::vector<std::vector<GatherSrc>> ss(nseg);
     parallel_for(nseg, ENLARGE_HOST_THREADS, [&](size_t i) {
-      const size_t a = seg[i], n = seg[i + 1] - seg[i];
+      const std::vector<Entry>& pe = parts[i];
+      const size_t n = pe.size();
       std::vector<std::pair<int64_t, uint32_t>> key(n);  // (destination, emission order)
-      for (size_t k = 0; k < n; ++k) key[k] = {entries[a + k].dst, (uint32_t)k};
+      for (size_t k = 0; k < n; ++k) key[k] = {pe[k].dst, (uint32_t)k};
       std::sort(key.begin(), key.end());
       std::vector<GatherDst>& dl = sd[i];
-      std::vector<GatherSrc>& sl = ss[i];
-      sl.reserve(n);
+      GatherSrc* const sl = srcs.data() + os[i];
+      size_t ns = 0;
       for (size_t k = 0; k < n;) {
-        const Entry& e0 = entries[a + key[k].second];
-        GatherDst d{Out.data.p + e0.dst, e0.rows, e0.cols, e0.ld, (int)sl.size(), 0};
+        const Entry& e0 = pe[key[k].second];
+        GatherDst d{Out.data.p + e0.dst, e0.rows, e0.cols, e0.ld, (int)(os[i] + ns), 0};
         size_t j = k;
         for (; j < n && key[j].first == e0.dst; ++j) {
-          const Entry& e = entries[a + key[j].second];
+          const Entry& e = pe[key[j].second];
           if (e.rows != e0.rows || e.cols != e0.cols) fail(-1, "internal: overlapping sub-blocks of different shape");
-          sl.push_back(e.src);
+          sl[ns++] = e.src;
         }
-        d.s1 = (int)sl.size();
+        d.s1 = (int)(os[i] + ns);
         dl.push_back(d);
         k = j;
       }
     });
-    std::vector<size_t> od(nseg + 1, 0), os(nseg + 1, 0);
-    for (size_t i = 0; i < nseg; ++i) {
-      od[i + 1] = od[i] + sd[i].size();
-      os[i + 1] = os[i] + ss[i].size();
-    }
-    if (os[nseg] > (size_t)INT32_MAX) fail(-4, "enlargement with more than 2^31 gather sources");
+    std::vector<size_t> od(nseg + 1, 0);
+    for (size_t i = 0; i < nseg; ++i) od[i + 1] = od[i] + sd[i].size();
     std::vector<GatherDst> dsts(od[nseg]);
-    std::vector<GatherSrc> srcs(os[nseg]);
-    parallel_for(nseg, ENLARGE_HOST_THREADS, [&](size_t i) {
-      for (size_t k = 0; k < sd[i].size(); ++k) {
-        GatherDst d = sd[i][k];
-        d.s0 += (int)os[i];
-        d.s1 += (int)os[i];
-        dsts[od[i] + k] = d;
-      }
-      std::copy(ss[i].begin(), ss[i].end(), srcs.begin() + (ptrdiff_t)os[i]);
-    });
-    d_dst.put(dsts, st);
-    d_src.put(srcs, st);
-    launch_gather(d_dst.p, (int)dsts.size(), d_src.p, st);
-    n_entries = (int64_t)entries.size();
-    entries.clear();
-    seg.clear();
+    parallel_for(nseg, ENLARGE_HOST_THREADS,
+                 [&](size_t i) { std::copy(sd[i].begin(), sd[i].end(), dsts.begin() + (ptrdiff_t)od[i]); });
+    n_entries = (int64_t)os[nseg];
+    parts.clear();
+    const int ndst = (int)dsts.size();
+    d_dst.put(std::move(dsts), st);
+    d_src.put(std::move(srcs), st);
+    launch_gather(d_dst.p, ndst, d_src.p, st);
   }
   DArr<GatherDst> d_dst;
   DArr<GatherSrc> d_src;
@@ -1221,8 +1215,8 @@ static void trace_layouts(const Problem& P, Store& X, const Enl& E, bool left, S
 // every operator of the enlarged store `out` (the one trace_layouts built).
 static void trace_entries(const Problem& P, const Store& X, const Enl& E, bool left, EnlargeTrace& tr, Store& out) {
   const std::vector<int>& opidx = tr.opidx;
-  // the operators' entries are independent: emitted on host threads, then
-  // concatenated in operator order (the serial emission order)
+  // the operators' entries are independent: emitted on host threads, one
+  // list per operator (in operator order they are the serial emission order)
   std::vector<std::vector<Entry>> per(tr.defs.size());
   parallel_for(tr.defs.size(), ENLARGE_HOST_THREADS, [&](size_t i) {
     Materializer m;
@@ -1230,9 +1224,9 @@ static void trace_entries(const Problem& P, const Store& X, const Enl& E, bool l
     for (auto& t : tr.defs[i].sym) m.emit_op(P, X, tr.cb.T, E, out, opidx[i], t, left, true);
     per[i] = std::move(m.entries);
   });
-  size_t tot = 0;
-  for (auto& v : per) tot += v.size();
   if (P.count_method) {  // nonzero piece pairs of every enlarged block
+    size_t tot = 0;
+    for (auto& v : per) tot += v.size();
     std::vector<Store::PieceRect>& pr = out.pieces;
     pr.clear();
     pr.reserve(tot);
@@ -1242,12 +1236,7 @@ static void trace_entries(const Problem& P, const Store& X, const Enl& E, bool l
     pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
     out.has_pieces = true;
   }
-  tr.mat.seg.assign(1, 0);
-  for (auto& v : per) tr.mat.seg.push_back(tr.mat.seg.back() + v.size());
-  tr.mat.entries.resize(tot);
-  parallel_for(per.size(), ENLARGE_HOST_THREADS, [&](size_t i) {
-    std::copy(per[i].begin(), per[i].end(), tr.mat.entries.begin() + (ptrdiff_t)tr.mat.seg[i]);
-  });
+  tr.mat.parts = std::move(per);
 }
 
 static void trace_enlarge(const Problem& P, Store& X, const Enl& E, bool left, Stream st, EnlargeTrace& tr) {
@@ -1382,9 +1371,17 @@ struct GemmList {
   // tile i owns flat[cnt[i], cnt[i+1])
   void grouped(std::vector<int>& cnt, std::vector<GTask>& flat) const {
     cnt.assign(tiles.size() + 1, 0);
-    for (auto& t : items) cnt[t.tile + 1]++;
+    bool sorted = true;  // items added tile by tile (every first pass) keep their order as they are
+    for (size_t k = 0; k < items.size(); ++k) {
+      cnt[items[k].tile + 1]++;
+      sorted = sorted && (k == 0 || items[k - 1].tile <= items[k].tile);
+    }
     for (size_t i = 0; i < tiles.size(); ++i) cnt[i + 1] += cnt[i];
     flat.resize(items.size());
+    if (sorted) {
+      for (size_t k = 0; k < items.size(); ++k) flat[k] = items[k].t;
+      return;
+    }
     std::vector<int> pos(cnt.begin(), cnt.end() - 1);
     for (auto& t : items) flat[pos[t.tile]++] = t.t;
   }
@@ -1413,9 +1410,9 @@ struct GemmList {
     std::vector<int> cnt;
     std::vector<GTask> flat;
     grouped(cnt, flat);
-    std::vector<double> cost(flat.size());
+    std::vector<double> cost(gpc > 0 ? flat.size() : 0);  // estimates: only ranges of tiles need them
     double total = 0.0;
-    for (size_t i = 0; i < tiles.size(); ++i) {
+    for (size_t i = 0; i < tiles.size() && gpc > 0; ++i) {
       if (cnt[i] == cnt[i + 1] && tiles[i].mode == 0) continue;
       total += TILE_COST;
       for (int t = cnt[i]; t < cnt[i + 1]; ++t) total += (cost[t] = task_cost(flat[t].K, tiles[i].cols));
@@ -1426,6 +1423,9 @@ struct GemmList {
     std::vector<GTile> chunks;
     std::vector<int> owner;  // source tile of every chunk
     std::vector<int> ws{0};
+    chunks.reserve(tiles.size());
+    owner.reserve(tiles.size());
+    if (gpc <= 0) ws.reserve(tiles.size() + 1);
     double acc = 0.0;
     auto emit = [&](size_t i, int t0, int t1) {
       GTile c = tiles[i];
@@ -1490,14 +1490,14 @@ struct GemmList {
     for (size_t j = 0; j < chunks.size(); ++j) chunks[j].part = poff[j] >= 0 ? pl.part.p + poff[j] : nullptr;
     for (size_t j = 0, r = 0; j < chunks.size(); ++j)
       if (poff[j] >= 0 && (j == 0 || owner[j - 1] != owner[j])) reds[r++].part = chunks[j].part;
-    pl.tiles.put(chunks, st);
-    pl.tasks.put(flat, st);
-    pl.wstart.put(ws, st);
-    pl.reds.put(reds, st);
     pl.ntiles = (int)chunks.size();
     pl.nwg = (int)ws.size() - 1;
     pl.stream = gpc > 0;
     pl.nreds = (int)reds.size();
+    pl.tiles.put(std::move(chunks), st);
+    pl.tasks.put(std::move(flat), st);
+    pl.wstart.put(std::move(ws), st);
+    pl.reds.put(std::move(reds), st);
   }
 };
 
@@ -1606,9 +1606,15 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
   // the two passes' product lists and plans are independent: built on two
   // host threads (pass 1: the T = op(A) B' or U = B' op(C) products into
   // workspace slots; pass 2: the accumulation into the output blocks)
+  auto ntiles = [](int64_t r, int64_t c) { return ((r + GemmList::TS - 1) / GemmList::TS) * ((c + GemmList::TS - 1) / GemmList::TS); };
   parallel_for(2, 2, [&](size_t which) {
     if (which == 0) {
       GemmList g1;
+      int64_t n1 = 0;  // tiles of the workspace slots, one task each
+      for (size_t i = 0; i < tr.size(); ++i)
+        if (slot[i] >= 0) n1 += right[i] ? ntiles(tr[i].K1, outs[tr[i].blk].cols) : ntiles(outs[tr[i].blk].rows, tr[i].K2);
+      g1.tiles.reserve((size_t)n1);
+      g1.items.reserve((size_t)n1);
       for (size_t i = 0; i < tr.size(); ++i) {
         const Triple& x = tr[i];
         if (x.flags & (TT_IDENT_A | TT_IDENT_C)) continue;
@@ -1629,6 +1635,9 @@ static void build_two_pass(const std::vector<OutBlk>& outs, const std::vector<Tr
       g1.plan(tp.p1, st, gpc1);
     } else {
       GemmList g2;
+      int64_t n2 = 0;  // one task per product and output tile
+      for (size_t i = 0; i < tr.size(); ++i) n2 += ntiles(outs[tr[i].blk].rows, outs[tr[i].blk].cols);
+      g2.items.reserve((size_t)n2);
       std::vector<int> first(outs.size());
       for (size_t b = 0; b < outs.size(); ++b)
         first[b] = g2.add_block(outs[b].out, outs[b].rows, outs[b].cols, outs[b].ld, 0);
@@ -2332,30 +2341,31 @@ struct Engine {
     std::vector<Grp> groups;
     std::vector<TraceJob> jobs;
     std::vector<const Entry*> jent;
-    for (const Entry& en : tr.mat.entries) {
-      double* dsub = Out.adj.p + en.dst;
-      if (en.src.kind == GS_IDENT) {  // identity on the block: the coefficient may be an integral
-        if (en.term->wl.n > 0) {
-          jobs.push_back({dsub, en.rows, en.ld});
-          jent.push_back(&en);
+    for (const std::vector<Entry>& part : tr.mat.parts)
+      for (const Entry& en : part) {
+        double* dsub = Out.adj.p + en.dst;
+        if (en.src.kind == GS_IDENT) {  // identity on the block: the coefficient may be an integral
+          if (en.term->wl.n > 0) {
+            jobs.push_back({dsub, en.rows, en.ld});
+            jent.push_back(&en);
+          }
+          continue;
         }
-        continue;
+        const double* s = en.src.src;
+        double* sadj = X.owns(s) ? X.adj_of(s) : (T.owns(s) ? T.adj_of(s) : nullptr);
+        if (!sadj) fail(-1, "internal: materialisation source outside the block and its combinations");
+        const bool trn = en.src.kind == GS_TRANS;
+        auto it = gid.find(sadj);
+        int g;
+        if (it == gid.end()) {
+          g = (int)groups.size();
+          gid[sadj] = g;
+          groups.push_back({sadj, trn ? en.cols : en.rows, trn ? en.rows : en.cols, en.src.ld, {}});
+        } else {
+          g = it->second;
+        }
+        groups[g].src.push_back({dsub, en.ld, en.src.kind, en.src.scale});
       }
-      const double* s = en.src.src;
-      double* sadj = X.owns(s) ? X.adj_of(s) : (T.owns(s) ? T.adj_of(s) : nullptr);
-      if (!sadj) fail(-1, "internal: materialisation source outside the block and its combinations");
-      const bool trn = en.src.kind == GS_TRANS;
-      auto it = gid.find(sadj);
-      int g;
-      if (it == gid.end()) {
-        g = (int)groups.size();
-        gid[sadj] = g;
-        groups.push_back({sadj, trn ? en.cols : en.rows, trn ? en.rows : en.cols, en.src.ld, {}});
-      } else {
-        g = it->second;
-      }
-      groups[g].src.push_back({dsub, en.ld, en.src.kind, en.src.scale});
-    }
     {
       std::vector<GatherDst> dsts;
       std::vector<GatherSrc> srcs;
@@ -3461,13 +3471,14 @@ struct Engine {
     build_two_pass(outs, trs, step.plan, st, true, defer_p2 ? &step.g2 : nullptr, gpc1, gpc2, xcd1, xcd2,
                    corder);
     step.p2_pending = defer_p2;
-    step.trs = trs;
     step.flops = step.plan.flops;
     step.bytes = bytes;
     step.ntasks = (int64_t)trs.size();
     step.method_flops = (X.has_pieces && Y.has_pieces) ? method_flops(outs, trs) : -1.0;
     step.shapes.clear();
+    step.shapes.reserve(trs.size());
     for (auto& t : trs) step.shapes.push_back({outs[t.blk].rows, t.K1, t.K2, outs[t.blk].cols, t.flags});
+    step.trs = std::move(trs);
   }
 
   void build_diag() {

@@ -116,14 +116,25 @@ struct DArr {
     if (p) dev_free(p);
   }
   void put(const std::vector<T>& v, Stream st) {
-    if (v.size() > cap) {
-      if (p) dev_free(p);
-      cap = v.size() + v.size() / 4 + 16;
-      p = (T*)dev_alloc(cap * sizeof(T));
-    }
-    n = v.size();
+    reserve(v.size());
     host = v;
     dev_h2d(p, host.data(), host.size() * sizeof(T), st);
+  }
+  // the same, taking the host copy over from the caller instead of copying it
+  void put(std::vector<T>&& v, Stream st) {
+    reserve(v.size());
+    host = std::move(v);
+    dev_h2d(p, host.data(), host.size() * sizeof(T), st);
+  }
+
+ private:
+  void reserve(size_t count) {
+    if (count > cap) {
+      if (p) dev_free(p);
+      cap = count + count / 4 + 16;
+      p = (T*)dev_alloc(cap * sizeof(T));
+    }
+    n = count;
   }
 };
 

@@ -883,14 +883,18 @@ int dev_cu_count() {
 
 // Ordered sum of a tile's partial results: eight interleaved accumulators
 // keep loads in flight; the combination order is fixed, so results are
-// reproducible run to run.
+// reproducible run to run.  A tile (at most 64 x 64) is shared by
+// REDUCE_SPLIT workgroups, each summing every REDUCE_SPLIT-th run of 256
+// elements.
+constexpr int REDUCE_SPLIT = 4;
 template <typename T>
 __device__ __forceinline__ void reduce_body(const RTile* __restrict__ reds, const unsigned bid) {
   const RTile t = reds[bid];
   const T* const part = (const T*)t.part;
   T* const out = (T*)t.out;
   const int n = t.rows * t.cols;
-  for (int e = threadIdx.x; e < n; e += 256) {
+  // blockIdx.y takes every gridDim.y-th run of 256 elements of the tile
+  for (int e = blockIdx.y * 256 + threadIdx.x; e < n; e += 256 * gridDim.y) {
     T v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const T* p = part + e;
     int q = 0;
@@ -920,18 +924,20 @@ __global__ __launch_bounds__(256) void reduce_seg_kernel(const GSeg* __restrict_
 void launch_reduce(const RTile* reds, int nred, bool f32, Stream st, const int* gate) {
   if (nred <= 0) return;
   if (f32)
-    hipLaunchKernelGGL(reduce_kernel<float>, dim3(nred), dim3(256), 0, (hipStream_t)st, reds, gate);
+    hipLaunchKernelGGL(reduce_kernel<float>, dim3(nred, REDUCE_SPLIT), dim3(256), 0, (hipStream_t)st, reds, gate);
   else
-    hipLaunchKernelGGL(reduce_kernel<double>, dim3(nred), dim3(256), 0, (hipStream_t)st, reds, gate);
+    hipLaunchKernelGGL(reduce_kernel<double>, dim3(nred, REDUCE_SPLIT), dim3(256), 0, (hipStream_t)st, reds, gate);
   check_launch("reduce");
 }
 
 void launch_reduce_seg(const GSeg* segs, const int* base, int nseg, int nred, bool f32, Stream st) {
   if (nred <= 0 || nseg <= 0) return;
   if (f32)
-    hipLaunchKernelGGL(reduce_seg_kernel<float>, dim3(nred), dim3(256), 0, (hipStream_t)st, segs, base, nseg);
+    hipLaunchKernelGGL(reduce_seg_kernel<float>, dim3(nred, REDUCE_SPLIT), dim3(256), 0, (hipStream_t)st, segs, base,
+                       nseg);
   else
-    hipLaunchKernelGGL(reduce_seg_kernel<double>, dim3(nred), dim3(256), 0, (hipStream_t)st, segs, base, nseg);
+    hipLaunchKernelGGL(reduce_seg_kernel<double>, dim3(nred, REDUCE_SPLIT), dim3(256), 0, (hipStream_t)st, segs, base,
+                       nseg);
   check_launch("reduce_seg");
 }
 
@@ -1583,9 +1589,12 @@ void launch_normalize(double* y, const double* nrm2, int64_t n, Stream st) {
   hipLaunchKernelGGL(normalize_kernel, dim3(nb), dim3(256), 0, (hipStream_t)st, y, nrm2, n);
 }
 
-// Cyclic Jacobi eigen-decomposition of a small symmetric matrix, one wavefront.
-// Round-robin ordering: k/2 disjoint rotations per round.
+// Cyclic Jacobi eigen-decomposition of a small symmetric matrix, one
+// workgroup of SYEV_T threads.  Round-robin ordering: k/2 disjoint rotations
+// per round, whose row and column updates are spread over all threads (each
+// element's arithmetic does not depend on the thread count).
 constexpr int SYEV_MAX = 64;
+constexpr int SYEV_T = 256;
 
 __device__ __forceinline__ void syev_body(const double* __restrict__ H, const int k, const int ld,
                                           double* __restrict__ evals, double* __restrict__ evecs) {
@@ -1595,7 +1604,7 @@ __device__ __forceinline__ void syev_body(const double* __restrict__ H, const in
   __shared__ int rp[SYEV_MAX / 2], rq[SYEV_MAX / 2];
   __shared__ int s_any;
   const int lane = threadIdx.x;
-  for (int e = lane; e < k * k; e += 64) {
+  for (int e = lane; e < k * k; e += SYEV_T) {
     const int i = e / k, j = e % k;
     a[i][j] = (i >= j) ? H[i * ld + j] : H[j * ld + i];  // lower triangle is authoritative
     v[i][j] = (i == j) ? 1.0 : 0.0;
@@ -1631,7 +1640,7 @@ __device__ __forceinline__ void syev_body(const double* __restrict__ H, const in
       }
       __syncthreads();
       // rows: a <- J^T a
-      for (int e = lane; e < (np / 2) * k; e += 64) {
+      for (int e = lane; e < (np / 2) * k; e += SYEV_T) {
         const int pr = e / k, j = e % k;
         const int p = rp[pr], q = rq[pr];
         if (p < 0) continue;
@@ -1642,7 +1651,7 @@ __device__ __forceinline__ void syev_body(const double* __restrict__ H, const in
       }
       __syncthreads();
       // cols: a <- a J ; v <- v J
-      for (int e = lane; e < (np / 2) * k; e += 64) {
+      for (int e = lane; e < (np / 2) * k; e += SYEV_T) {
         const int pr = e / k, i = e % k;
         const int p = rp[pr], q = rq[pr];
         if (p < 0) continue;
@@ -1661,26 +1670,26 @@ __device__ __forceinline__ void syev_body(const double* __restrict__ H, const in
   }
   // sort ascending (selection by rank)
   __shared__ int ord[SYEV_MAX];
-  for (int j = lane; j < k; j += 64) {
+  for (int j = lane; j < k; j += SYEV_T) {
     int rank = 0;
     for (int i = 0; i < k; ++i) rank += (a[i][i] < a[j][j]) || (a[i][i] == a[j][j] && i < j);
     ord[rank] = j;
   }
   __syncthreads();
-  for (int j = lane; j < k; j += 64) evals[j] = a[ord[j]][ord[j]];
-  for (int e = lane; e < k * k; e += 64) {
+  for (int j = lane; j < k; j += SYEV_T) evals[j] = a[ord[j]][ord[j]];
+  for (int e = lane; e < k * k; e += SYEV_T) {
     const int j = e / k, i = e % k;
     evecs[j * k + i] = v[i][ord[j]];  // eigenvector j contiguous
   }
 }
 
-__global__ __launch_bounds__(64) void syev_kernel(const double* __restrict__ H, int k, int ld,
+__global__ __launch_bounds__(SYEV_T) void syev_kernel(const double* __restrict__ H, int k, int ld,
                                                   double* __restrict__ evals, double* __restrict__ evecs) {
   syev_body(H, k, ld, evals, evecs);
 }
 
 void launch_syev_small(const double* H, int k, int ld, double* evals, double* evecs, Stream st) {
-  hipLaunchKernelGGL(syev_kernel, dim3(1), dim3(64), 0, (hipStream_t)st, H, k, ld, evals, evecs);
+  hipLaunchKernelGGL(syev_kernel, dim3(1), dim3(SYEV_T), 0, (hipStream_t)st, H, k, ld, evals, evecs);
 }
 
 // ---------------------------------------------------------------------------
@@ -1792,14 +1801,14 @@ void launch_ew_batch(const EwJob* jobs, int njobs, int64_t max_n, Stream st) {
   check_launch("ew_batch");
 }
 
-__global__ __launch_bounds__(64) void syev_batch_kernel(const SyevJob* __restrict__ jobs) {
+__global__ __launch_bounds__(SYEV_T) void syev_batch_kernel(const SyevJob* __restrict__ jobs) {
   const SyevJob jb = jobs[blockIdx.x];
   syev_body(jb.H, jb.k, jb.ld, jb.evals, jb.evecs);
 }
 
 void launch_syev_batch(const SyevJob* jobs, int njobs, Stream st) {
   if (njobs <= 0) return;
-  hipLaunchKernelGGL(syev_batch_kernel, dim3(njobs), dim3(64), 0, (hipStream_t)st, jobs);
+  hipLaunchKernelGGL(syev_batch_kernel, dim3(njobs), dim3(SYEV_T), 0, (hipStream_t)st, jobs);
   check_launch("syev_batch");
 }
 
@@ -2059,7 +2068,7 @@ void launch_dg_combo(const DGJob* jobs, int njobs, int which, int gate, int64_t 
   check_launch("dg_combo");
 }
 
-__global__ __launch_bounds__(64) void dg_syev_kernel(const DGJob* __restrict__ jobs) {
+__global__ __launch_bounds__(SYEV_T) void dg_syev_kernel(const DGJob* __restrict__ jobs) {
   const DGJob jb = jobs[blockIdx.x];
   if (jb.s->done) return;
   syev_body(jb.Hs, jb.s->k, jb.ms, jb.evals, jb.evecs);
@@ -2067,7 +2076,7 @@ __global__ __launch_bounds__(64) void dg_syev_kernel(const DGJob* __restrict__ j
 
 void launch_dg_syev(const DGJob* jobs, int njobs, Stream st) {
   if (njobs <= 0) return;
-  hipLaunchKernelGGL(dg_syev_kernel, dim3(njobs), dim3(64), 0, (hipStream_t)st, jobs);
+  hipLaunchKernelGGL(dg_syev_kernel, dim3(njobs), dim3(SYEV_T), 0, (hipStream_t)st, jobs);
   check_launch("dg_syev");
 }
 
