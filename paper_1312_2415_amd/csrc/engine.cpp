@@ -397,9 +397,17 @@ struct Store {
   bool has_pieces = false;
 
   int layout(int tk, int dN, int dG) {
-    auto key = std::make_tuple(tk, dN, dG);
-    auto it = lay_of.find(key);
+    auto it = lay_of.find(std::make_tuple(tk, dN, dG));
     if (it != lay_of.end()) return it->second;
+    return insert_layout(make_layout(tk, dN, dG));
+  }
+  int insert_layout(std::unique_ptr<Layout> L) {
+    lay_of[std::make_tuple(L->tk, L->dN, L->dG)] = (int)lays.size();
+    lays.push_back(std::move(L));
+    return (int)lays.size() - 1;
+  }
+  // the blocks of the class (tk, dN, dG) over this basis
+  std::unique_ptr<Layout> make_layout(int tk, int dN, int dG) const {
     auto L = std::make_unique<Layout>();
     L->tk = tk, L->dN = dN, L->dG = dG;
     const int ns = (int)basis.sec.size();
@@ -416,9 +424,7 @@ struct Store {
         L->eoff.push_back(L->nnz);
         L->nnz += (int64_t)basis.dim[b] * basis.dim[k];
       }
-    lays.push_back(std::move(L));
-    lay_of[key] = (int)lays.size() - 1;
-    return (int)lays.size() - 1;
+    return L;
   }
   int add(uint64_t key, int tk, int dN, int dG, bool odd) {
     const int l = layout(tk, dN, dG);
@@ -1207,6 +1213,19 @@ static void trace_layouts(const Problem& P, Store& X, const Enl& E, bool left, S
     out.orbs.insert(out.orbs.begin(), X.bond - 1);
   out.basis.sec = E.sec;
   out.basis.dim = E.dim;
+  // the layouts of the operator classes, built on host threads and taken in
+  // order of first use
+  std::vector<std::tuple<int, int, int>> cls;
+  {
+    std::set<std::tuple<int, int, int>> seen;
+    for (auto& d : tr.defs)
+      if (seen.insert(std::make_tuple(d.tk, d.dN, d.dG)).second) cls.push_back(std::make_tuple(d.tk, d.dN, d.dG));
+  }
+  std::vector<std::unique_ptr<Layout>> built(cls.size());
+  parallel_for(cls.size(), ENLARGE_HOST_THREADS, [&](size_t i) {
+    built[i] = out.make_layout(std::get<0>(cls[i]), std::get<1>(cls[i]), std::get<2>(cls[i]));
+  });
+  for (auto& L : built) out.insert_layout(std::move(L));
   tr.opidx.clear();
   for (auto& d : tr.defs) tr.opidx.push_back(out.add(d.key, d.tk, d.dN, d.dG, d.odd));
 }
