@@ -2132,27 +2132,48 @@ struct Engine {
     out->bond = E.bond;
     out->orbs = E.orbs;
     out->basis = nb;
+    // the class layouts over the new basis, built on host threads in order of
+    // first use, then the operators in the enlarged store's order
+    {
+      std::vector<int> cls;  // enlarged-store layouts in order of first use
+      std::vector<char> seen(E.lays.size(), 0);
+      for (auto& o : E.ops)
+        if (!seen[(size_t)o.lay]) seen[(size_t)o.lay] = 1, cls.push_back(o.lay);
+      std::vector<std::unique_ptr<Layout>> built(cls.size());
+      parallel_for(cls.size(), ENLARGE_HOST_THREADS, [&](size_t q) {
+        const Layout& L = *E.lays[(size_t)cls[q]];
+        built[q] = out->make_layout(L.tk, L.dN, L.dG);
+      });
+      for (auto& L : built) out->insert_layout(std::move(L));
+    }
     for (auto& o : E.ops) {
       const Layout& L = *E.lays[o.lay];
       out->add(o.key, L.tk, L.dN, L.dG, o.odd);
     }
     out->allocate(st);
-    std::vector<OutBlk> outs;
-    std::vector<Triple> trs;
-    for (size_t i = 0; i < out->ops.size(); ++i) {
+    // every new sector's index in the enlarged basis and in the tensor
+    const int nsec = (int)nb.sec.size();
+    std::vector<int> emap((size_t)nsec), tmap((size_t)nsec);
+    for (int j = 0; j < nsec; ++j) {
+      emap[(size_t)j] = E.basis.find(nb.sec[(size_t)j]);
+      tmap[(size_t)j] = T.find(nb.sec[(size_t)j]);
+    }
+    // the products of every operator (independent: built on host threads),
+    // then laid end to end in operator order
+    std::vector<std::vector<std::pair<OutBlk, Triple>>> per(out->ops.size());
+    parallel_for(out->ops.size(), ENLARGE_HOST_THREADS, [&](size_t i) {
       const Layout& NL = out->lay((int)i);
       const Layout& EL = E.lay((int)i);
+      std::vector<std::pair<OutBlk, Triple>>& pr = per[i];
       for (size_t b = 0; b < NL.bra.size(); ++b) {
-        const Sec &sb = nb.sec[NL.bra[b]], &sk = nb.sec[NL.ket[b]];
-        const int eb = E.basis.find(sb), ek = E.basis.find(sk);
-        const int tb = T.find(sb), tkk = T.find(sk);
+        const int eb = emap[(size_t)NL.bra[b]], ek = emap[(size_t)NL.ket[b]];
+        const int tb = tmap[(size_t)NL.bra[b]], tkk = tmap[(size_t)NL.ket[b]];
         if (eb < 0 || ek < 0 || tb < 0 || tkk < 0) fail(-1, "internal: renormalisation sector missing");
         const int eblk = EL.find(eb, ek);
         if (eblk < 0) continue;
         const int rows = nb.dim[NL.bra[b]], cols = nb.dim[NL.ket[b]];
-        outs.push_back({out->ptr((int)i, (int)b), rows, cols, cols});
+        const OutBlk ob{out->ptr((int)i, (int)b), rows, cols, cols};
         Triple t{};
-        t.blk = (int)outs.size() - 1;
         t.b = E.ptr((int)i, eblk);
         t.ldb = E.basis.dim[ek];
         t.coef = 1.0;
@@ -2163,9 +2184,22 @@ struct Engine {
         t.ldc = T.cols[tkk];
         t.K2 = E.basis.dim[ek];
         t.flags = left ? TT_TRANS_A : TT_TRANS_C;  // left: U^T O U ; right: V O V^T
-        trs.push_back(t);
+        pr.push_back({ob, t});
       }
-    }
+    });
+    size_t np = 0;
+    for (auto& v : per) np += v.size();
+    std::vector<OutBlk> outs;
+    std::vector<Triple> trs;
+    outs.reserve(np);
+    trs.reserve(np);
+    for (auto& v : per)
+      for (auto& [ob, t] : v) {
+        outs.push_back(ob);
+        trs.push_back(t);
+        trs.back().blk = (int)outs.size() - 1;
+      }
+    per.clear();
     TwoPass tp;
     build_two_pass(outs, trs, tp, st);
     if (prec32 == 0) {
