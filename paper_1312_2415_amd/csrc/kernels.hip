@@ -1318,10 +1318,12 @@ void launch_svd(const SvdJob* jobs, int njobs, int max_short, Stream st, int pha
 // paired by the same round-robin schedule as single columns, and every pair
 // of blocks is a workgroup of its own, so a matrix is worked on by many
 // compute units at once.  A workgroup loads the pair's columns of M and V
-// into LDS, runs one sweep of the single-column method over them (one wave
-// per column pair, all in LDS) and writes them back; the memory traffic per
-// rotation falls by the width of a block and the rounds of a sweep by its
-// square.  flags[job] is set when a pair of columns that both hold more than
+// into LDS, rotates pairs of them (one wave per column pair, all in LDS) and
+// writes them back: in round 0, where every block is visited once, one sweep
+// of the single-column method over all columns of the two blocks; in the
+// later rounds only the pairs across the two blocks, so every pair of
+// columns is visited once per sweep.  The memory traffic per rotation falls
+// by the width of a block and the rounds of a sweep by its square.  flags[job] is set when a pair of columns that both hold more than
 // 1e-13 of the matrix norm was rotated (the convergence test of the
 // single-workgroup sweeps), so the host repeats sweeps until no flag is set;
 // a job whose previous sweep set no flag (active[k] == 0) is left alone.
@@ -1362,7 +1364,8 @@ __global__ __launch_bounds__(1024) void svd_block_kernel(const SvdJob* __restric
   const int a0 = ba * SVB_W, a1 = ba < nblk ? min(a0 + SVB_W, n) : a0;
   const int b0 = bb * SVB_W, b1 = bb < nblk ? min(b0 + SVB_W, n) : b0;
   const int na = a1 - a0, nc = na + (b1 - b0);
-  if (nc < 2) return;
+  const bool cross = round > 0;  // only the pairs across the two blocks
+  if (nc < 2 || (cross && (na == 0 || na == nc))) return;
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   double* sM = sMV;               // local column c at c * m
   double* sV = sMV + 2 * SVB_W * m;  // local column c at c * n
@@ -1379,43 +1382,51 @@ __global__ __launch_bounds__(1024) void svd_block_kernel(const SvdJob* __restric
   __syncthreads();
   const double tol = fmax(1e-15, (double)m * 2.220446049250313e-16);
   const int npl = nc + (nc & 1);
-  for (int r = 0; r < npl - 1; ++r) {
-    // wave wv takes local pair wv of round r (npl / 2 <= SVB_W pairs, 16 waves)
-    if (wv < npl / 2) {
+  const int nr = cross ? SVB_W : npl - 1;
+  for (int r = 0; r < nr; ++r) {
+    // wave wv takes local pair wv of round r (at most SVB_W pairs, 16 waves):
+    // across the blocks column wv of the first with column (wv + r) mod SVB_W
+    // of the second, else the round-robin pair of all columns
+    int p = 0, q = 0;
+    if (cross) {
+      p = wv;
+      q = na + (wv + r) % SVB_W;
+    } else if (wv < npl / 2) {
       const int la = (wv == 0) ? 0 : ((wv - 1 + r) % (npl - 1)) + 1;
       const int lb = ((npl - 2 - wv + r) % (npl - 1)) + 1;
-      const int p = min(la, lb), q = max(la, lb);
-      if (q < nc && p != q) {
-        double* mp = sM + p * m;
-        double* mq = sM + q * m;
-        double al = 0, be = 0, ga = 0;
+      p = min(la, lb);
+      q = max(la, lb);
+    }
+    if (q < nc && p != q && p < (cross ? na : nc)) {
+      double* mp = sM + p * m;
+      double* mq = sM + q * m;
+      double al = 0, be = 0, ga = 0;
+      for (int i = lane; i < m; i += 64) {
+        const double x = mp[i], y = mq[i];
+        al += x * x;
+        be += y * y;
+        ga += x * y;
+      }
+      al = wave_sum(al);
+      be = wave_sum(be);
+      ga = wave_sum(ga);
+      if (!(fabs(ga) <= tol * sqrt(al * be) || ga == 0.0)) {
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
         for (int i = lane; i < m; i += 64) {
           const double x = mp[i], y = mq[i];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
+          mp[i] = cs * x - sn * y;
+          mq[i] = sn * x + cs * y;
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (!(fabs(ga) <= tol * sqrt(al * be) || ga == 0.0)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          for (int i = lane; i < m; i += 64) {
-            const double x = mp[i], y = mq[i];
-            mp[i] = cs * x - sn * y;
-            mq[i] = sn * x + cs * y;
-          }
-          double* vp = sV + p * n;
-          double* vq = sV + q * n;
-          for (int i = lane; i < n; i += 64) {
-            const double x = vp[i], y = vq[i];
-            vp[i] = cs * x - sn * y;
-            vq[i] = sn * x + cs * y;
-          }
-          if (lane == 0 && al > 1e-26 * fro2 && be > 1e-26 * fro2) s_flag = 1;
+        double* vp = sV + p * n;
+        double* vq = sV + q * n;
+        for (int i = lane; i < n; i += 64) {
+          const double x = vp[i], y = vq[i];
+          vp[i] = cs * x - sn * y;
+          vq[i] = sn * x + cs * y;
         }
+        if (lane == 0 && al > 1e-26 * fro2 && be > 1e-26 * fro2) s_flag = 1;
       }
     }
     __syncthreads();

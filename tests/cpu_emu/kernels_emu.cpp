@@ -402,6 +402,7 @@ void launch_svd(const SvdJob* jobs, int njobs, int, Stream, int phase) {
 // running them one after another is the same computation.
 static constexpr int EMU_SVB_W = 16;
 std::atomic<long> emu_svd_block_pairs_run{0};  // block pairs processed (read by the test driver)
+std::atomic<long> emu_svd_rotations{0};        // column pairs tried by the block rounds
 std::atomic<bool> emu_svd_block_off{false};    // the test driver's switch to the one-workgroup path
 bool svd_block_fits(int rows, int cols) { return !emu_svd_block_off && rows + cols <= 600; }
 int svd_block_pairs(int rows, int cols) {
@@ -429,20 +430,34 @@ void launch_svd_block(const SvdJob* jobs, const int* pair_base, int njobs, int n
       if (blk < nblk)
         for (int c = blk * EMU_SVB_W; c < std::min((blk + 1) * EMU_SVB_W, w.n); ++c) cols.push_back(c);
     const int nc = (int)cols.size();
-    if (nc < 2) continue;
+    const int na = ba < nblk ? std::min((ba + 1) * EMU_SVB_W, w.n) - ba * EMU_SVB_W : 0;
+    const bool cross = round > 0;  // later rounds: only the pairs across the two blocks
+    if (nc < 2 || (cross && (na == 0 || na == nc))) continue;
     ++emu_svd_block_pairs_run;
     const double tol = std::fmax(1e-15, w.m * 2.220446049250313e-16);
     const int npl = nc + (nc & 1);
     bool sig = false;
-    for (int r = 0; r < npl - 1; ++r)
-      for (int wv = 0; wv < npl / 2; ++wv) {
-        const int la = (wv == 0) ? 0 : ((wv - 1 + r) % (npl - 1)) + 1;
-        const int lb = ((npl - 2 - wv + r) % (npl - 1)) + 1;
-        const int p = std::min(la, lb), q = std::max(la, lb);
-        if (q >= nc || p == q) continue;
-        sig |= svd_rotate(w.M + (size_t)cols[p] * w.m, w.M + (size_t)cols[q] * w.m, w.V + (size_t)cols[p] * w.n,
-                          w.V + (size_t)cols[q] * w.n, w.m, w.n, tol, w.nrm[0]);
-      }
+    auto rot = [&](int p, int q) {
+      ++emu_svd_rotations;
+      sig |= svd_rotate(w.M + (size_t)cols[p] * w.m, w.M + (size_t)cols[q] * w.m, w.V + (size_t)cols[p] * w.n,
+                        w.V + (size_t)cols[q] * w.n, w.m, w.n, tol, w.nrm[0]);
+    };
+    if (cross) {
+      for (int r = 0; r < EMU_SVB_W; ++r)
+        for (int wv = 0; wv < EMU_SVB_W; ++wv) {
+          const int p = wv, q = na + (wv + r) % EMU_SVB_W;
+          if (p < na && q < nc) rot(p, q);
+        }
+    } else {
+      for (int r = 0; r < npl - 1; ++r)
+        for (int wv = 0; wv < npl / 2; ++wv) {
+          const int la = (wv == 0) ? 0 : ((wv - 1 + r) % (npl - 1)) + 1;
+          const int lb = ((npl - 2 - wv + r) % (npl - 1)) + 1;
+          const int p = std::min(la, lb), q = std::max(la, lb);
+          if (q >= nc || p == q) continue;
+          rot(p, q);
+        }
+    }
     if (sig) flags[k] = 1;
   }
 }
