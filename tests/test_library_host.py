@@ -93,3 +93,14 @@ def test_discarded_weight_fit():
     assert binding.fit_discarded_weight([(1e-3, -1.0)]) == (-1.0, 0.0)
     with pytest.raises(ValueError):
         binding.fit_discarded_weight([])
+
+
+def test_bench_runs_on_one_gpu_only():
+    """bench.py measures one GPU: a request for more exits with a message before any GPU work."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+    assert r.stdout.strip() == ""  # no JSON line
