@@ -22,10 +22,12 @@
 #include <array>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <exception>
 #include <mutex>
 #include <functional>
 #include <thread>
+#include <type_traits>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -605,18 +607,12 @@ struct Combos {
 // Reduced elements via coupling_product (9j) and the fermion sign of the
 // factor that is moved past the other one's electrons.
 // ---------------------------------------------------------------------------
-// fn(j) for j < n on up to `threads` host threads (the calling one
-// included); the first exception is rethrown after all have stopped.  A
-// call from inside a worker runs serially (no nested pools).  Workers use
-// the caller's device and device-memory pool.
 static thread_local bool tl_in_pool = false;
+
+// Threads started for one loop and joined at its end (the loop of a host
+// thread that finds the persistent workers below taken by another one).
 template <class F>
-static void parallel_for(size_t n, int threads, F&& fn) {
-  const int nt = tl_in_pool ? 1 : (int)std::min<size_t>(n, (size_t)std::max(1, threads));
-  if (nt <= 1) {
-    for (size_t j = 0; j < n; ++j) fn(j);
-    return;
-  }
+static void parallel_for_spawned(size_t n, int nt, F& fn) {
   std::atomic<size_t> next{0};
   std::atomic<bool> stop{false};
   std::exception_ptr first;
@@ -653,6 +649,134 @@ static void parallel_for(size_t n, int threads, F&& fn) {
   work();
   for (auto& t : pool) t.join();
   if (first) std::rethrow_exception(first);
+}
+
+// Persistent host workers: started on first use and kept for the process,
+// they take one loop at a time beside the thread that posts it, each bound
+// to that thread's device and device-memory pool for the loop.  Starting
+// threads for every loop (a few hundred loops per sweep) cost as much as
+// some of the loops themselves.
+struct HostWorkers {
+  static constexpr int N = 15;  // workers beside the posting thread
+  std::mutex mu;
+  std::condition_variable cv_job, cv_done;
+  std::vector<std::thread> th;
+  bool busy = false, quit = false;
+  uint64_t gen = 0;  // loops posted
+  int want = 0, finished = 0;
+  void (*call)(void*, size_t) = nullptr;
+  void* ctx = nullptr;
+  size_t n = 0;
+  std::atomic<size_t> next{0};
+  std::atomic<bool> stop{false};
+  std::exception_ptr first;
+  DevPool* mem = nullptr;
+  int device = 0;
+
+  ~HostWorkers() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      quit = true;
+    }
+    cv_job.notify_all();
+    for (auto& x : th) x.join();
+  }
+  void failed(std::exception_ptr e) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!first) first = e;
+    stop = true;
+  }
+  // the loop body, on the posting thread and on every worker taking part
+  void work() {
+    const bool was = tl_in_pool;
+    tl_in_pool = true;
+    for (size_t j; !stop.load() && (j = next.fetch_add(1)) < n;) {
+      try {
+        call(ctx, j);
+      } catch (...) {
+        failed(std::current_exception());
+      }
+    }
+    tl_in_pool = was;
+  }
+  void loop(int id) {
+    uint64_t seen = 0;
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+      cv_job.wait(lk, [&] { return quit || (gen != seen && id < want); });
+      if (quit) return;
+      seen = gen;
+      DevPool* const m = mem;
+      const int dev = device;
+      lk.unlock();
+      DevPool* const prev = dev_pool_bind(m);
+      try {
+        dev_set_device(dev);
+      } catch (...) {
+        failed(std::current_exception());
+      }
+      work();
+      dev_pool_bind(prev);
+      lk.lock();
+      if (++finished == want) cv_done.notify_all();
+    }
+  }
+};
+
+static HostWorkers& host_workers() {
+  static HostWorkers w;
+  return w;
+}
+
+// fn(j) for j < n on up to `threads` host threads (the calling one
+// included); the first exception is rethrown after all have stopped.  A
+// call from inside a worker runs serially (no nested loops).  Workers use
+// the caller's device and device-memory pool.
+template <class F>
+static void parallel_for(size_t n, int threads, F&& fn) {
+  const int nt = tl_in_pool ? 1 : (int)std::min<size_t>(n, (size_t)std::max(1, threads));
+  if (nt <= 1) {
+    for (size_t j = 0; j < n; ++j) fn(j);
+    return;
+  }
+  typedef std::remove_reference_t<F> Fn;
+  DevPool* const mem = dev_pool_current();
+  const int device = dev_get_device();
+  HostWorkers& W = host_workers();
+  std::unique_lock<std::mutex> lk(W.mu);
+  if (W.busy) {  // another host thread's loop holds the workers
+    lk.unlock();
+    parallel_for_spawned(n, nt, fn);
+    return;
+  }
+  while ((int)W.th.size() < HostWorkers::N) {
+    const int id = (int)W.th.size();
+    W.th.emplace_back([&W, id] { W.loop(id); });
+  }
+  W.busy = true;
+  W.call = [](void* c, size_t j) { (*static_cast<Fn*>(c))(j); };
+  W.ctx = const_cast<void*>(static_cast<const void*>(&fn));
+  W.n = n;
+  W.next = 0;
+  W.stop = false;
+  W.first = nullptr;
+  W.want = std::min(nt - 1, HostWorkers::N);
+  W.finished = 0;
+  W.mem = mem;
+  W.device = device;
+  ++W.gen;
+  lk.unlock();
+  W.cv_job.notify_all();
+  W.work();
+  lk.lock();
+  W.cv_done.wait(lk, [&] { return W.finished == W.want; });
+  const std::exception_ptr e = W.first;
+  W.first = nullptr;
+  W.call = nullptr;
+  W.ctx = nullptr;
+  W.busy = false;
+  lk.unlock();
+  if (e) std::rethrow_exception(e);
 }
 
 // host threads for the per-operator parts of an enlargement
