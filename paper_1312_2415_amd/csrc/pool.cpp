@@ -169,18 +169,28 @@ void* dev_alloc(size_t bytes) {
   if (pool) pool->owned[p] = bytes;
   return p;
 }
+// a block that `pool` owns goes back to its cache (false: not this pool's)
+static bool pool_take_back(DevPool* pool, void* p) {
+  std::lock_guard<std::mutex> lk(pool->mu);
+  auto it = pool->owned.find(p);
+  if (it == pool->owned.end()) return false;
+  pool->cached.emplace(it->second, p);
+  pool->cached_bytes += it->second;
+  if (pool->cached_bytes > POOL_CACHE_MAX) pool_trim(pool, POOL_CACHE_MAX / 2);
+  return true;
+}
 void dev_free(void* p) {
   if (!p) return;
   DevPool* pool = tl_pool;
-  if (pool) {
-    std::lock_guard<std::mutex> lk(pool->mu);
-    auto it = pool->owned.find(p);
-    if (it != pool->owned.end()) {
-      pool->cached.emplace(it->second, p);
-      pool->cached_bytes += it->second;
-      if (pool->cached_bytes > POOL_CACHE_MAX) pool_trim(pool, POOL_CACHE_MAX / 2);
-      return;
-    }
+  if (pool && pool_take_back(pool, p)) return;
+  {
+    // a block of another context's pool, freed on a thread bound to another
+    // pool or none (a batch's buffers released while an error unwinds): back
+    // to the pool that owns it, which would otherwise free it a second time
+    // when it is destroyed
+    std::lock_guard<std::mutex> reg(g_pools_mu);
+    for (DevPool* q : g_pools)
+      if (q != pool && pool_take_back(q, p)) return;
   }
   dev_raw_free(p);
 }

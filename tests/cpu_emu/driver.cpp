@@ -3,7 +3,8 @@
 // advanced in lockstep by sadmrg_batch_sweep, whose per-problem preparation
 // and update run on the library's host worker threads, in FP64 and in mixed
 // precision, with checkpointed blocks, followed by separate sweeps and the
-// energy adjoint; then (unless --no-block is given) the block-Jacobi
+// energy adjoint, and an injected device failure inside the worker threads
+// that must come back as an error; then (unless --no-block is given) the block-Jacobi
 // decomposition of a larger problem's wide sectors against the one-workgroup
 // decomposition.  Built with -fsanitize=thread or -fsanitize=address by
 // tests/test_cpu_emulation.py; prints one summary line and returns nonzero on
@@ -21,6 +22,7 @@
 namespace sadmrg {  // switches of the emulated device layer (kernels_emu.cpp)
 extern std::atomic<long> emu_svd_block_pairs_run;
 extern std::atomic<bool> emu_svd_block_off;
+extern std::atomic<int> emu_fail_gathers;
 }  // namespace sadmrg
 
 namespace {
@@ -130,6 +132,22 @@ int main(int argc, char** argv) {
       return 1;
     }
   }
+  // a failure inside the batch's worker threads (an injected gather error)
+  // comes back as an error of the call, and the next calls work: fresh MPS,
+  // a lockstep sweep and a separate one
+  sadmrg::emu_fail_gathers = 1;
+  const int rc_fail = sadmrg_batch_sweep(ctx.data(), n, Ds.data(), e.data(), st.data());
+  const bool injected = sadmrg::emu_fail_gathers.load() <= 0;
+  sadmrg::emu_fail_gathers = 0;
+  if (rc_fail >= 0 || !injected) {
+    std::printf("FAIL injected gather failure: rc %d, injected %d\n", rc_fail, (int)injected);
+    return 1;
+  }
+  for (int k = 0; k < n; ++k)
+    if (!ok(ctx[k], sadmrg_init_mps(ctx[k], Ds[k]), "init after failure")) return 1;
+  if (!ok(ctx[0], sadmrg_batch_sweep(ctx.data(), n, Ds.data(), e.data(), st.data()), "batch sweep after failure") ||
+      !ok(ctx[1], sadmrg_sweep(ctx[1], Ds[1], &e[1]), "sweep after failure"))
+    return 1;
   for (int k = 0; k < n; ++k) {
     sadmrg_destroy(ctx[k]);
     sadmrg_destroy(twin[k]);

@@ -227,7 +227,9 @@ void launch_cvt_d2f(float* dst, const double* src, int64_t n, Stream) {
 void launch_cvt_f2d(double* dst, const float* src, int64_t n, Stream) {
   for (int64_t i = 0; i < n; ++i) dst[i] = (double)src[i];
 }
+std::atomic<int> emu_fail_gathers{0};  // the test driver's injected failures: the next n gathers fail
 void launch_gather(const GatherDst* dsts, int ndst, const GatherSrc* srcs, Stream) {
+  if (emu_fail_gathers.load() > 0 && emu_fail_gathers.fetch_sub(1) > 0) dev_fail("emulation: injected gather failure");
   for (int i = 0; i < ndst; ++i) {
     const GatherDst& d = dsts[i];
     for (int r = 0; r < d.rows; ++r)

@@ -8,7 +8,11 @@ the Python binding.  The driver (tests/cpu_emu/driver.cpp) runs the batched
 sweep pattern -- five contexts in lockstep, whose preparation and update run
 on the library's host worker threads, in FP64, then mixed precision with
 checkpointed blocks, then separate sweeps and the energy adjoint -- and
-checks that lockstep and separate sweeps agree; the AddressSanitizer run then
+checks that lockstep and separate sweeps agree, then injects a device error
+inside the batch's worker threads, which must come back as an error of the
+call and leave the contexts usable (and their memory pools consistent: a
+buffer released while the error unwinds once went back to no pool and was
+freed twice); the AddressSanitizer run then
 compares the block-Jacobi decomposition of wide sectors with the
 one-workgroup decomposition over six micro-iterations of a larger problem
 (serial emulated kernels, left out of the slower ThreadSanitizer run).  Both
