@@ -1924,6 +1924,26 @@ static int64_t enl_cache_budget() {
 static const uint64_t NOISE_STREAM = (uint64_t)0x4E4F << 40;
 
 // binds a device-memory pool to the calling thread for one scope
+// A timing event recorded on a stream, freed on every way out of its scope
+// (an error between two events leaves none behind).
+struct Event {
+  void* p = nullptr;
+  explicit Event(Stream st) : p(dev_event_record(st)) {}
+  Event(const Event&) = delete;
+  Event& operator=(const Event&) = delete;
+  ~Event() {
+    if (p) try {
+        dev_event_free(p);
+      } catch (...) {
+      }
+  }
+  void* release() {
+    void* q = p;
+    p = nullptr;
+    return q;
+  }
+};
+
 struct PoolBind {
   DevPool* prev;
   explicit PoolBind(DevPool* p) : prev(p ? dev_pool_bind(p) : nullptr), set(p != nullptr) {}
@@ -3878,25 +3898,24 @@ struct Engine {
     if (f32) ensure_f32();
     const GemmList::Plan& p1 = f32 ? step.q1 : step.plan.p1;
     const GemmList::Plan& p2 = f32 ? step.q2 : step.plan.p2;
-    void* e0 = dev_event_record(st);
+    const Event e0(st);
     if (f32) {
       launch_cvt_d2f((float*)step.in32.p, step.in.p, step.n, st);
       dev_zero(step.out32.p, step.out32.n * 8, st);  // whole mirror (n floats, rounded up)
     } else {
       dev_zero(step.out.p, (size_t)std::max<int64_t>(step.n, 1) * 8, st);
     }
-    void* e1 = dev_event_record(st);
+    const Event e1(st);
     const bool bf3 = f32 && prec == 2;
     p1.run(st, bf3);
-    void* e2 = dev_event_record(st);
+    const Event e2(st);
     launch_gemm(p2.tiles.p, p2.tasks.p, p2.wstart.p, p2.nwg, p2.stream, p2.tag, p2.f32, st, bf3, p2.xcd);
-    void* e3 = dev_event_record(st);
+    const Event e3(st);
     launch_reduce(p2.reds.p, p2.nreds, p2.f32, st);
     if (f32) launch_cvt_f2d(step.out.p, (const float*)step.out32.p, step.n, st);
-    void* e4 = dev_event_record(st);
-    const double t0 = dev_event_elapsed(e0, e1), t1 = dev_event_elapsed(e1, e2), t2 = dev_event_elapsed(e2, e3),
-                 t3 = dev_event_elapsed(e3, e4);
-    for (void* ev : {e0, e1, e2, e3, e4}) dev_event_free(ev);
+    const Event e4(st);
+    const double t0 = dev_event_elapsed(e0.p, e1.p), t1 = dev_event_elapsed(e1.p, e2.p),
+                 t2 = dev_event_elapsed(e2.p, e3.p), t3 = dev_event_elapsed(e3.p, e4.p);
     if (f32) {
       t_sigma32 += t0 + t1 + t2 + t3;
       f_sigma32 += step.flops;
@@ -4627,13 +4646,15 @@ struct BatchLaunch {
     const int* e1 = stage.up(b1);
     const int* e2 = stage.up(b2);
     const int* er = stage.up(br);
-    void* t0 = dev_event_record(st);
+    Event t0(st);
     const bool bf3 = use32 && !E.empty() && E[0]->prec == 2;
     launch_gemm_seg(d1, e1, (int)s1.size(), nw1, false, use32, st, bf3);
     launch_gemm_seg(d2, e2, (int)s2.size(), nw2, stream2, use32, st, bf3);
     launch_reduce_seg(dr, er, (int)sr.size(), nr, use32, st);
-    void* t1 = dev_event_record(st);
-    (use32 ? ev32 : ev64).push_back({t0, t1});
+    Event t1(st);
+    (use32 ? ev32 : ev64).push_back({t0.p, t1.p});
+    t0.release();
+    t1.release();
     (use32 ? f32 : f64) += fl;
     ++(use32 ? n32 : n64);
   }
@@ -5054,16 +5075,14 @@ static void davidson_lockstep(const std::vector<Engine*>& E, std::vector<DavStat
     }
     std::vector<DGState> prev = hs;
     while (true) {
-      void* e0 = dev_event_record(st);
+      const Event e0(st);
       for (int r = 0; r < seg; ++r) dev_graph_launch(ex, st);
-      void* e1 = dev_event_record(st);
+      const Event e1(st);
       sc.clear();
       for (size_t k : all) sc.push_back(E[k]->dav_evals());
       sg.fetch(sc);
       dev_d2h(hs.data(), dst, ne * sizeof(DGState), st);  // waits for the stream
-      const double tseg = dev_event_elapsed(e0, e1);
-      dev_event_free(e0);
-      dev_event_free(e1);
+      const double tseg = dev_event_elapsed(e0.p, e1.p);
       std::vector<double> th(sg.shost, sg.shost + ne);
       fin.clear();
       bool live = false;
@@ -6600,12 +6619,10 @@ int sadmrg_debug_copy_probe(sadmrg_ctx* ctx, int64_t n, int reps, double* second
     sadmrg::launch_fill_uniform(a.p, n, 1, 2, ctx->e.st);
     double t = 0.0;
     for (int r = 0; r < reps; ++r) {
-      void* e0 = sadmrg::dev_event_record(ctx->e.st);
+      const sadmrg::Event e0(ctx->e.st);
       sadmrg::launch_copy(b.p, a.p, n, ctx->e.st);
-      void* e1 = sadmrg::dev_event_record(ctx->e.st);
-      t += sadmrg::dev_event_elapsed(e0, e1);
-      sadmrg::dev_event_free(e0);
-      sadmrg::dev_event_free(e1);
+      const sadmrg::Event e1(ctx->e.st);
+      t += sadmrg::dev_event_elapsed(e0.p, e1.p);
     }
     sadmrg::dev_sync(ctx->e.st);
     if (seconds) *seconds = t / reps;
@@ -6634,12 +6651,10 @@ int sadmrg_debug_gemm_probe(sadmrg_ctx* ctx, int nprod, int K, int reps, double*
     pl.tag = 0;  // the sigma pass-1 kernel
     double t = 0.0;
     for (int r = 0; r < reps; ++r) {
-      void* e0 = dev_event_record(ctx->e.st);
+      const Event e0(ctx->e.st);
       launch_gemm(pl.tiles.p, pl.tasks.p, pl.wstart.p, pl.nwg, pl.stream, pl.tag, false, ctx->e.st);
-      void* e1 = dev_event_record(ctx->e.st);
-      t += dev_event_elapsed(e0, e1);
-      dev_event_free(e0);
-      dev_event_free(e1);
+      const Event e1(ctx->e.st);
+      t += dev_event_elapsed(e0.p, e1.p);
     }
     dev_sync(ctx->e.st);
     if (seconds) *seconds = t / reps;

@@ -3,8 +3,9 @@
 // advanced in lockstep by sadmrg_batch_sweep, whose per-problem preparation
 // and update run on the library's host worker threads, in FP64 and in mixed
 // precision, with checkpointed blocks, followed by separate sweeps and the
-// energy adjoint, and an injected device failure inside the worker threads
-// that must come back as an error; then (unless --no-block is given) the block-Jacobi
+// energy adjoint, and injected device failures (in the worker threads, beside
+// the planning thread, in shared and single sigma launches) that must come
+// back as errors; then (unless --no-block is given) the block-Jacobi
 // decomposition of a larger problem's wide sectors against the one-workgroup
 // decomposition.  Built with -fsanitize=thread or -fsanitize=address by
 // tests/test_cpu_emulation.py; prints one summary line and returns nonzero on
@@ -23,6 +24,7 @@ namespace sadmrg {  // switches of the emulated device layer (kernels_emu.cpp)
 extern std::atomic<long> emu_svd_block_pairs_run;
 extern std::atomic<bool> emu_svd_block_off;
 extern std::atomic<int> emu_fail_gathers;
+extern std::atomic<int> emu_fail_gemms;
 }  // namespace sadmrg
 
 namespace {
@@ -132,22 +134,38 @@ int main(int argc, char** argv) {
       return 1;
     }
   }
-  // a failure inside the batch's worker threads (an injected gather error)
-  // comes back as an error of the call, and the next calls work: fresh MPS,
-  // a lockstep sweep and a separate one
-  sadmrg::emu_fail_gathers = 1;
-  const int rc_fail = sadmrg_batch_sweep(ctx.data(), n, Ds.data(), e.data(), st.data());
-  const bool injected = sadmrg::emu_fail_gathers.load() <= 0;
-  sadmrg::emu_fail_gathers = 0;
-  if (rc_fail >= 0 || !injected) {
-    std::printf("FAIL injected gather failure: rc %d, injected %d\n", rc_fail, (int)injected);
-    return 1;
+  // injected device errors -- a gather inside the batch's worker threads or
+  // a plain sweep (beside its planning thread), a GEMM launch of a shared
+  // sigma or of one context's -- come back as errors of the call, and the
+  // contexts work again from a fresh MPS (a lockstep sweep and a separate one)
+  struct Inject {
+    std::atomic<int>* counter;
+    int nth;  // the launch that fails, counted from the start of the call
+    bool batch;
+    const char* what;
+  };
+  const Inject injects[] = {{&sadmrg::emu_fail_gathers, 1, true, "gather in a batch"},
+                            {&sadmrg::emu_fail_gathers, 5, false, "gather in a sweep"},
+                            {&sadmrg::emu_fail_gemms, 40, true, "GEMM in a batch"},
+                            {&sadmrg::emu_fail_gemms, 25, false, "GEMM in a sweep"}};
+  for (const Inject& q : injects) {
+    for (int k = 0; k < n; ++k)
+      if (!ok(ctx[k], sadmrg_init_mps(ctx[k], Ds[k]), "init before injection")) return 1;
+    *q.counter = q.nth;
+    const int rc_fail = q.batch ? sadmrg_batch_sweep(ctx.data(), n, Ds.data(), e.data(), st.data())
+                                : sadmrg_sweep(ctx[0], Ds[0], &e[0]);
+    const bool injected = q.counter->load() <= 0;
+    *q.counter = 0;
+    if (rc_fail >= 0 || !injected) {
+      std::printf("FAIL injected %s: rc %d, injected %d\n", q.what, rc_fail, (int)injected);
+      return 1;
+    }
+    for (int k = 0; k < n; ++k)
+      if (!ok(ctx[k], sadmrg_init_mps(ctx[k], Ds[k]), "init after failure")) return 1;
+    if (!ok(ctx[0], sadmrg_batch_sweep(ctx.data(), n, Ds.data(), e.data(), st.data()), "batch sweep after failure") ||
+        !ok(ctx[1], sadmrg_sweep(ctx[1], Ds[1], &e[1]), "sweep after failure"))
+      return 1;
   }
-  for (int k = 0; k < n; ++k)
-    if (!ok(ctx[k], sadmrg_init_mps(ctx[k], Ds[k]), "init after failure")) return 1;
-  if (!ok(ctx[0], sadmrg_batch_sweep(ctx.data(), n, Ds.data(), e.data(), st.data()), "batch sweep after failure") ||
-      !ok(ctx[1], sadmrg_sweep(ctx[1], Ds[1], &e[1]), "sweep after failure"))
-    return 1;
   for (int k = 0; k < n; ++k) {
     sadmrg_destroy(ctx[k]);
     sadmrg_destroy(twin[k]);

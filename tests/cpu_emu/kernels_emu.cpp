@@ -174,8 +174,10 @@ static void plan_run(const GTile* tiles, const GTask* tasks, const int* wstart, 
       tile_run<double>(tiles[i], tasks);
   }
 }
+std::atomic<int> emu_fail_gemms{0};  // the test driver's injected failure: GEMM launch number n from now fails
 void launch_gemm(const GTile* tiles, const GTask* tasks, const int* wstart, int nwg, bool stream, int, bool f32,
                  Stream, bool, int, const int* gate) {
+  if (emu_fail_gemms.load() > 0 && emu_fail_gemms.fetch_sub(1) == 1) dev_fail("emulation: injected GEMM failure");
   if (nwg <= 0 || (gate && *gate)) return;
   plan_run(tiles, tasks, wstart, nwg, stream, f32);
 }
@@ -200,6 +202,7 @@ void launch_reduce(const RTile* reds, int nred, bool f32, Stream, const int* gat
   }
 }
 void launch_gemm_seg(const GSeg* segs, const int* base, int nseg, int nwg, bool stream, bool f32, Stream, bool) {
+  if (emu_fail_gemms.load() > 0 && emu_fail_gemms.fetch_sub(1) == 1) dev_fail("emulation: injected GEMM failure");
   for (int s = 0; s < nseg; ++s) {
     if (segs[s].gate && *segs[s].gate) continue;
     const int n = (s + 1 < nseg ? base[s + 1] : nwg) - base[s];
@@ -227,9 +230,9 @@ void launch_cvt_d2f(float* dst, const double* src, int64_t n, Stream) {
 void launch_cvt_f2d(double* dst, const float* src, int64_t n, Stream) {
   for (int64_t i = 0; i < n; ++i) dst[i] = (double)src[i];
 }
-std::atomic<int> emu_fail_gathers{0};  // the test driver's injected failures: the next n gathers fail
+std::atomic<int> emu_fail_gathers{0};  // the test driver's injected failure: gather number n from now fails
 void launch_gather(const GatherDst* dsts, int ndst, const GatherSrc* srcs, Stream) {
-  if (emu_fail_gathers.load() > 0 && emu_fail_gathers.fetch_sub(1) > 0) dev_fail("emulation: injected gather failure");
+  if (emu_fail_gathers.load() > 0 && emu_fail_gathers.fetch_sub(1) == 1) dev_fail("emulation: injected gather failure");
   for (int i = 0; i < ndst; ++i) {
     const GatherDst& d = dsts[i];
     for (int r = 0; r < d.rows; ++r)
