@@ -3,11 +3,11 @@
 // advanced in lockstep by sadmrg_batch_sweep, whose per-problem preparation
 // and update run on the library's host worker threads, in FP64 and in mixed
 // precision, with checkpointed blocks, followed by separate sweeps and the
-// energy adjoint, and injected device failures (in the worker threads, beside
-// the planning thread, in shared and single sigma launches) that must come
-// back as errors; then (unless --no-block is given) the block-Jacobi
-// decomposition of a larger problem's wide sectors against the one-workgroup
-// decomposition.  Built with -fsanitize=thread or -fsanitize=address by
+// energy adjoint, and (unless --no-inject is given) injected device failures
+// (in the worker threads, beside the planning thread, in shared and single
+// sigma launches) that must come back as errors; then (unless --no-block is
+// given) the block-Jacobi decomposition of a larger problem's wide sectors
+// against the one-workgroup decomposition.  Built with -fsanitize=thread or -fsanitize=address by
 // tests/test_cpu_emulation.py; prints one summary line and returns nonzero on
 // an error or an inconsistent result.
 #include <algorithm>
@@ -74,7 +74,11 @@ bool ok(sadmrg_ctx* c, int rc, const char* what) {
 }  // namespace
 
 int main(int argc, char** argv) {
-  const bool block = !(argc > 1 && std::string(argv[1]) == "--no-block");
+  bool block = true, inject = true;
+  for (int a = 1; a < argc; ++a) {
+    block = block && std::string(argv[a]) != "--no-block";
+    inject = inject && std::string(argv[a]) != "--no-inject";
+  }
   const std::vector<Spec> specs = {{6, 6, 0, 16}, {7, 6, 2, 20}, {8, 8, 0, 24}, {6, 4, 0, 12}, {7, 8, 2, 20}};
   const int n = (int)specs.size();
   std::vector<sadmrg_ctx*> ctx(n, nullptr), twin(n, nullptr);
@@ -144,11 +148,11 @@ int main(int argc, char** argv) {
     bool batch;
     const char* what;
   };
-  const Inject injects[] = {{&sadmrg::emu_fail_gathers, 1, true, "gather in a batch"},
-                            {&sadmrg::emu_fail_gathers, 5, false, "gather in a sweep"},
-                            {&sadmrg::emu_fail_gemms, 40, true, "GEMM in a batch"},
-                            {&sadmrg::emu_fail_gemms, 25, false, "GEMM in a sweep"}};
-  for (const Inject& q : injects) {
+  const std::vector<Inject> injects = {{&sadmrg::emu_fail_gathers, 1, true, "gather in a batch"},
+                                      {&sadmrg::emu_fail_gathers, 5, false, "gather in a sweep"},
+                                      {&sadmrg::emu_fail_gemms, 40, true, "GEMM in a batch"},
+                                      {&sadmrg::emu_fail_gemms, 25, false, "GEMM in a sweep"}};
+  for (const Inject& q : inject ? injects : std::vector<Inject>()) {
     for (int k = 0; k < n; ++k)
       if (!ok(ctx[k], sadmrg_init_mps(ctx[k], Ds[k]), "init before injection")) return 1;
     *q.counter = q.nth;

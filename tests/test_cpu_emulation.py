@@ -8,15 +8,15 @@ the Python binding.  The driver (tests/cpu_emu/driver.cpp) runs the batched
 sweep pattern -- five contexts in lockstep, whose preparation and update run
 on the library's host worker threads, in FP64, then mixed precision with
 checkpointed blocks, then separate sweeps and the energy adjoint -- and
-checks that lockstep and separate sweeps agree, then injects a device error
-inside the batch's worker threads, which must come back as an error of the
-call and leave the contexts usable (and their memory pools consistent: a
-buffer released while the error unwinds once went back to no pool and was
-freed twice); the AddressSanitizer run then
+checks that lockstep and separate sweeps agree.  The AddressSanitizer run
+then injects device errors (a gather and a GEMM launch, in a batch and in a
+single sweep), each of which must come back as an error of the call and
+leave the contexts and their memory pools usable (a buffer released while
+such an error unwound once went back to no pool and was freed twice), and
 compares the block-Jacobi decomposition of wide sectors with the
-one-workgroup decomposition over six micro-iterations of a larger problem
-(serial emulated kernels, left out of the slower ThreadSanitizer run).  Both
-sanitizer runs must end cleanly with no report.
+one-workgroup decomposition over six micro-iterations of a larger problem;
+both are left out of the slower ThreadSanitizer run.  Both sanitizer runs
+must end cleanly with no report.
 """
 import os
 import shutil
@@ -31,7 +31,8 @@ SOURCES = [os.path.join(CSRC, f) for f in ("engine.cpp", "su2.cpp", "scf.cpp", "
     os.path.join(HERE, "cpu_emu", "kernels_emu.cpp"), os.path.join(HERE, "cpu_emu", "driver.cpp")]
 OUT = os.path.join(ROOT, "_build_emu")
 VARIANTS = {
-    "tsan": (["-fsanitize=thread"], {"TSAN_OPTIONS": "halt_on_error=1"}, "ThreadSanitizer", ["--no-block"]),
+    "tsan": (["-fsanitize=thread"], {"TSAN_OPTIONS": "halt_on_error=1"}, "ThreadSanitizer",
+             ["--no-block", "--no-inject"]),
     "asan": (["-fsanitize=address", "-fno-omit-frame-pointer"], {"ASAN_OPTIONS": "detect_leaks=1"},
              "Sanitizer", []),
 }
