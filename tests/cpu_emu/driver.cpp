@@ -170,6 +170,30 @@ int main(int argc, char** argv) {
         !ok(ctx[1], sadmrg_sweep(ctx[1], Ds[1], &e[1]), "sweep after failure"))
       return 1;
   }
+  // misuse of the C ABI is refused with EINVAL and leaves the context usable
+  if (inject) {
+    sadmrg_ctx* u = nullptr;
+    if (!make(0, &u)) return 1;
+    std::vector<char> junk(64, 7);
+    size_t jb = 0;
+    const int D0 = specs[0].D;
+    const int rcs[] = {sadmrg_sweep(u, D0, &e[0]),               // no MPS yet
+                       sadmrg_init_mps(u, 0),                    // D < 1
+                       sadmrg_set_target(u, -2, 0, 0),           // N < 0
+                       sadmrg_set_precision(u, 7, 1e-5),         // no such mode
+                       sadmrg_mps_import(u, junk.data(), junk.size()),  // not an MPS blob
+                       sadmrg_mps_export(u, nullptr, &jb),       // no two-site centre
+                       sadmrg_batch_sweep(nullptr, 1, &D0, nullptr, nullptr)};
+    for (int rc : rcs)
+      if (rc >= 0) {
+        std::printf("FAIL misuse accepted (rc %d)\n", rc);
+        return 1;
+      }
+    double eu = 0.0;
+    if (!ok(u, sadmrg_init_mps(u, D0), "init after misuse") || !ok(u, sadmrg_sweep(u, D0, &eu), "sweep after misuse"))
+      return 1;
+    sadmrg_destroy(u);
+  }
   for (int k = 0; k < n; ++k) {
     sadmrg_destroy(ctx[k]);
     sadmrg_destroy(twin[k]);
